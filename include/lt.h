@@ -1,0 +1,186 @@
+/*
+ * lt.h -- C-ABI of the MI355X (gfx950) *_L-product tensor-completion library.
+ *
+ * Operations follow Bentbib, Elalj, El Hachimi, Jbilou, Ratnani, "Generalized
+ * L-product for high order tensors with applications using GPU computations"
+ * (arXiv 2202.02870):
+ *   lt_lproduct      A *_L B                       (Section 3.2, Alg. 2)
+ *   lt_lsvd          *_L-SVD  A = U *_L S *_L V^T  (Section 3.2 theorem, Alg. 3)
+ *   lt_svt_prox      D_tau(A), the prox of tau ||.||_* (Theorem 23, Alg. 4)
+ *   lt_complete_pga  completion by PGA             (Section 4, eqs. (48)-(53), Alg. 5)
+ *
+ * Tensors.  A tensor of order N (2 <= N <= LT_MAX_ORDER) with dims I1..IN is a
+ * float32 array in column-major (first-index-fastest) order over
+ * (i1, i2, i3, ..., iN).  Frontal slice p -- the paper's representative matrix
+ * X^p of eq. (3.5), p the column-major index of (i3, ..., iN) -- therefore
+ * starts at element p*I1*I2 and is an I1 x I2 column-major matrix with leading
+ * dimension I1.  (A C-contiguous array of shape (IN, ..., I3, I2, I1) has this
+ * layout.)  The transform L multiplies mode i (i = 3..N) by the matrix M_i
+ * selected by lt_desc.kind[i-1] (Section 3.2: L(A) = A x_3 M_3 ... x_N M_N).
+ *
+ * Memory and streams.  Every tensor pointer argument is a DEVICE pointer owned
+ * by the caller; the library never frees or retains it.  `ws` is a device
+ * workspace of at least lt_workspace_bytes(...) bytes, owned by the caller.
+ * No call allocates device memory.  All calls are asynchronous on the handle's
+ * stream unless stated otherwise; results are ready once that stream is
+ * synchronised.  A handle must not be used from two threads at once.
+ *
+ * Errors.  Every function returns an int status: 0 on success, a negative
+ * LT_ERR_* code on failure (nothing has been launched, outputs untouched unless
+ * stated), a positive LT_WARN_* code when results were produced with a caveat.
+ * lt_last_error(h) returns a message for the last failure on that handle.  No
+ * C++ exception crosses this interface.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LT_MAX_ORDER 8
+
+/* ---- status codes ------------------------------------------------------ */
+#define LT_OK 0
+#define LT_ERR_ARG (-1)          /* null pointer, bad enum or parameter value */
+#define LT_ERR_SHAPE (-2)        /* dims inconsistent or beyond a kernel's limits */
+#define LT_ERR_UNSUPPORTED (-3)  /* valid request this GPU library does not run */
+#define LT_ERR_NONFINITE (-4)    /* NaN or Inf found in an input that is checked */
+#define LT_ERR_HIP (-5)          /* a HIP runtime call failed */
+#define LT_ERR_WORKSPACE (-6)    /* ws is NULL or smaller than lt_workspace_bytes */
+#define LT_WARN_MAXSWEEPS 1      /* some slice SVD stopped at max_sweeps */
+#define LT_WARN_NOT_CONVERGED 2  /* PGA reached max_iter with tol > 0 unmet */
+
+/* ---- transform kinds (one per trailing mode) ----------------------------- */
+typedef enum {
+  LT_DCT = 0,       /* orthonormal DCT-II C_n (Section 2; the transform of TNN-PGA-C) */
+  LT_DFT = 1,       /* Fourier matrix F_n (Section 2); complex -- not run on the GPU */
+  LT_IDENTITY = 2,  /* M_i = I (mode i not transformed) */
+  LT_CUSTOM = 3     /* caller-given invertible M_i (e.g. the c-product W^{-1} C (I+Z)) */
+} lt_mode_kind;
+
+/* Transform precision of the L / L^{-1} GEMMs. */
+typedef enum {
+  LT_PREC_F32 = 0,     /* FP32 MFMA, FP32 accumulate */
+  LT_PREC_BF16X3 = 1   /* BF16 MFMA on hi/lo splits of both operands
+                          (hi*hi + hi*lo + lo*hi), FP32 accumulate */
+} lt_precision;
+
+/* Operations, for lt_workspace_bytes. */
+typedef enum { LT_OP_LPRODUCT = 0, LT_OP_LSVD = 1, LT_OP_SVT = 2, LT_OP_PGA = 3 } lt_op;
+
+/* Tensor shape and transform.  Host struct, read during the call only. */
+typedef struct {
+  int32_t order;                        /* N, 2..LT_MAX_ORDER (N = 2: one slice, no transform) */
+  int32_t kind[LT_MAX_ORDER];           /* kind[i-1] is the lt_mode_kind of mode i, i = 3..N */
+  int64_t dims[LT_MAX_ORDER];           /* dims[i-1] = I_i >= 1 */
+  const double* custom[LT_MAX_ORDER];   /* HOST pointer, row-major I_i x I_i matrix, read when
+                                           kind[i-1] == LT_CUSTOM; must be invertible */
+} lt_desc;
+
+/* One-sided Jacobi SVD options (Alg. 3 / Alg. 4 per-slice SVD). */
+typedef struct {
+  double jacobi_tol;    /* a column pair is rotated while |a_i.a_j| > tol ||a_i|| ||a_j||;
+                           <= 0 selects 1e-6 */
+  int32_t max_sweeps;   /* sweep limit per slice; <= 0 selects 40 */
+  int32_t precision;    /* lt_precision of the transform GEMMs */
+} lt_svd_opts;
+
+/* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
+ * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */
+typedef struct {
+  double mu0;             /* threshold of the first iteration, > 0 */
+  double nu;              /* continuation factor, 0 < nu <= 1: mu_{k+1} = max(nu mu_k, mu_bar) */
+  double mu_bar;          /* threshold floor, 0 < mu_bar <= mu0 */
+  double tol;             /* stop when ||Y^k - X^{k+1}||_F / ||X^{k+1}||_F <= tol; <= 0: never */
+  int32_t max_iter;       /* iteration limit, >= 1 */
+  int32_t check_every;    /* the stopping test syncs the host every this many iterations (>= 1) */
+  int32_t gate_until_floor; /* nonzero: the test may stop the run only once mu_k == mu_bar */
+  int32_t fixed_mu;       /* nonzero: every iteration thresholds at mu0 */
+  lt_svd_opts svd;
+} lt_pga_params;
+
+typedef struct {
+  int32_t iters;          /* iterations performed */
+  int32_t converged;      /* 1 if the stopping rule fired */
+  int32_t max_sweeps_hit; /* number of slice SVDs that stopped at max_sweeps */
+  int32_t reserved;
+  double last_crit;       /* last evaluated stopping ratio (inf if X = 0; NaN if never evaluated) */
+  int64_t total_sweeps;   /* Jacobi sweeps summed over all slices and iterations */
+  int64_t total_slices;   /* slice SVDs performed (iters x P) */
+  int64_t total_rotations; /* column-pair rotations applied, summed likewise */
+} lt_pga_report;
+
+/* Kernel timing, recorded with HIP events on the handle's stream around every
+ * kernel launch of the classes below while profiling is on. */
+#define LT_PROF_FORWARD 0   /* L: transform GEMM (with the fused momentum/mask step in PGA) */
+#define LT_PROF_JACOBI 1    /* per-slice one-sided Jacobi SVD + threshold */
+#define LT_PROF_REBUILD 2   /* rank-r rebuild of the thresholded slices */
+#define LT_PROF_INVERSE 3   /* L^{-1}: transform GEMM (with the fused stopping norms in PGA) */
+#define LT_PROF_OTHER 4     /* small reductions, transform-matrix builds, face-wise products */
+#define LT_PROF_NCLASS 5
+typedef struct {
+  int64_t calls[LT_PROF_NCLASS];
+  double ms[LT_PROF_NCLASS];   /* summed event-to-event durations */
+  int64_t dropped;             /* launches not timed because the event pool was full */
+} lt_profile;
+
+typedef struct lt_handle lt_handle;
+
+/* Create a handle bound to the current HIP device and `stream` (a hipStream_t;
+ * NULL = the legacy default stream).  Allocates only host memory. */
+int lt_create(lt_handle** h, void* stream);
+int lt_destroy(lt_handle* h);
+int lt_set_stream(lt_handle* h, void* stream);
+const char* lt_last_error(const lt_handle* h);
+const char* lt_status_string(int status);
+
+/* Start recording kernel durations on this handle (allocates HIP events the
+ * first time; call outside graph capture).  lt_profile_end synchronises the
+ * stream, returns the totals since lt_profile_begin and stops recording. */
+int lt_profile_begin(lt_handle* h);
+int lt_profile_end(lt_handle* h, lt_profile* out);
+
+/* Bytes of device workspace an operation needs.  `b` is read only for
+ * LT_OP_LPRODUCT.  Returns 0 if the descriptor is invalid. */
+size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precision);
+
+/* C = A *_L B (Alg. 2).  a: I1 x l x I3..IN, b: l x I2 x I3..IN (same trailing
+ * dims and kinds), C: I1 x I2 x I3..IN.  Transform precision: `precision`. */
+int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b,
+                const float* B, float* C, int precision, void* ws, size_t ws_bytes);
+
+/* *_L-SVD (Alg. 3), economy size: with n = min(I1, I2),
+ *   U: I1 x n x I3..IN, S: n x n x I3..IN, V: I2 x n x I3..IN,
+ * such that A = U *_L S *_L V^T.  Transform-domain singular values of every
+ * slice are sorted in descending order.  transform_domain != 0 returns L(U),
+ * L(S), L(V) (the per-slice factors) instead.  sigma (may be NULL): P x n
+ * float array of transform-domain singular values, slice-major. */
+int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
+            float* V, float* sigma, int transform_domain, const lt_svd_opts* opts,
+            void* ws, size_t ws_bytes);
+
+/* D = D_tau(A) (Alg. 4): every slice of L(A) has its singular values
+ * soft-thresholded by tau >= 0, then L^{-1}.  rank_out (device, P int32, may
+ * be NULL): per slice, the number of singular values above tau.  sweeps_out
+ * (device, P int32, may be NULL): Jacobi sweeps used per slice.  D may alias A. */
+int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
+                int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts,
+                void* ws, size_t ws_bytes);
+
+/* Completion by PGA (Alg. 5) from X^0 = X^1 = 0.  M: observed tensor; mask:
+ * uint8 per entry, nonzero = observed (the set Omega of eq. (48)); X: output,
+ * the last iterate.  Checks M on Omega for NaN/Inf (LT_ERR_NONFINITE).
+ * Synchronises the host with the stream when tol > 0 (every check_every
+ * iterations) and at the end (to fill rep).  rep may be NULL. */
+int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_t* mask,
+                    const lt_pga_params* p, float* X, lt_pga_report* rep,
+                    void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LT_H */

@@ -1,0 +1,784 @@
+// Host runtime of liblt.so: the C-ABI declared in include/lt.h.
+//
+// Every operation is a short sequence of kernel launches on the handle's
+// stream; the only host work is argument checking, workspace carving, building
+// the data-independent PGA schedule (Alg. 5: t_k and mu_k), and, for custom
+// mode matrices, their FP64 inversion before upload.
+#include "lt_internal.h"
+#include "../../include/lt.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+struct lt_handle {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int max_lds = 65536;
+  std::string err;
+  double* pinned = nullptr;   // small host staging for readbacks (16 doubles)
+  // kernel timing (lt_profile_begin / lt_profile_end)
+  bool prof_on = false;
+  std::vector<hipEvent_t> events;          // pool, used in start/stop pairs
+  size_t ev_next = 0;
+  std::vector<std::pair<int, size_t>> recs;  // (class, index of the start event)
+  int64_t dropped = 0;
+};
+
+namespace {
+
+constexpr int kMaxP = 4096;
+constexpr size_t kEventPool = 8192;
+
+// Records a HIP event pair around the launches made during its lifetime.
+struct ProfScope {
+  lt_handle* h;
+  int cls;
+  long long idx = -1;
+  ProfScope(lt_handle* hh, int c) : h(hh), cls(c) {
+    if (!h->prof_on) return;
+    if (h->ev_next + 2 > h->events.size()) {
+      ++h->dropped;
+      return;
+    }
+    idx = (long long)h->ev_next;
+    h->ev_next += 2;
+    (void)hipEventRecord(h->events[idx], h->stream);
+  }
+  ~ProfScope() {
+    if (idx < 0) return;
+    (void)hipEventRecord(h->events[idx + 1], h->stream);
+    h->recs.emplace_back(cls, (size_t)idx);
+  }
+};
+
+int fail(lt_handle* h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(h, expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((h), LT_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+struct Shape {
+  int order = 0;
+  long long I1 = 0, I2 = 0, P = 1, N = 0, nel = 0;
+  int nmodes = 0;
+  int n[LT_MAX_ORDER] = {0};
+  int kind[LT_MAX_ORDER] = {0};
+  const double* custom[LT_MAX_ORDER] = {nullptr};
+  bool any_custom = false;
+};
+
+int parse(lt_handle* h, const lt_desc* d, Shape* s) {
+  if (!d) return fail(h, LT_ERR_ARG, "descriptor is NULL");
+  if (d->order < 2 || d->order > LT_MAX_ORDER)
+    return fail(h, LT_ERR_SHAPE, "order %d outside 2..%d", d->order, LT_MAX_ORDER);
+  s->order = d->order;
+  for (int i = 0; i < d->order; ++i)
+    if (d->dims[i] < 1 || d->dims[i] > (1LL << 30))
+      return fail(h, LT_ERR_SHAPE, "dims[%d] = %lld out of range", i, (long long)d->dims[i]);
+  s->I1 = d->dims[0];
+  s->I2 = d->dims[1];
+  s->P = 1;
+  s->nmodes = d->order - 2;
+  for (int i = 2; i < d->order; ++i) {
+    const int k = d->kind[i];
+    if (k == LT_DFT)
+      return fail(h, LT_ERR_UNSUPPORTED, "mode %d: the DFT (complex slices) is not run on the GPU", i + 1);
+    if (k != LT_DCT && k != LT_IDENTITY && k != LT_CUSTOM)
+      return fail(h, LT_ERR_ARG, "mode %d: unknown kind %d", i + 1, k);
+    if (k == LT_CUSTOM && !d->custom[i])
+      return fail(h, LT_ERR_ARG, "mode %d: LT_CUSTOM without a matrix", i + 1);
+    s->n[i - 2] = (int)d->dims[i];
+    s->kind[i - 2] = k;
+    s->custom[i - 2] = d->custom[i];
+    s->any_custom |= (k == LT_CUSTOM);
+    s->P *= d->dims[i];
+    if (s->P > kMaxP) return fail(h, LT_ERR_SHAPE, "more than %d frontal slices", kMaxP);
+  }
+  s->N = s->I1 * s->I2;
+  s->nel = s->N * s->P;
+  return LT_OK;
+}
+
+// ---- workspace carving -------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct TransformWs {
+  float* K = nullptr;
+  float* Kinv = nullptr;
+  uint16_t *Khi = nullptr, *Klo = nullptr, *Kihi = nullptr, *Kilo = nullptr;
+  double* custom = nullptr;   // per custom mode: M then M^{-1}
+};
+
+void carve_transform(Carver& c, const Shape& s, int precision, TransformWs* t) {
+  const size_t P2 = (size_t)s.P * s.P;
+  t->K = c.take<float>(P2);
+  t->Kinv = c.take<float>(P2);
+  if (precision == LT_PREC_BF16X3) {
+    t->Khi = c.take<uint16_t>(P2);
+    t->Klo = c.take<uint16_t>(P2);
+    t->Kihi = c.take<uint16_t>(P2);
+    t->Kilo = c.take<uint16_t>(P2);
+  }
+  size_t nc = 0;
+  for (int i = 0; i < s.nmodes; ++i)
+    if (s.kind[i] == LT_CUSTOM) nc += 2 * (size_t)s.n[i] * s.n[i];
+  if (nc) t->custom = c.take<double>(nc);
+}
+
+// Gauss-Jordan inverse with partial pivoting, FP64, row-major n x n.
+bool invert(const double* M, int n, std::vector<double>& inv) {
+  std::vector<double> a(M, M + (size_t)n * n);
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(a[(size_t)r * n + col]) > fabs(a[(size_t)piv * n + col])) piv = r;
+    if (a[(size_t)piv * n + col] == 0.0) return false;
+    if (piv != col)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[(size_t)piv * n + k], a[(size_t)col * n + k]);
+        std::swap(inv[(size_t)piv * n + k], inv[(size_t)col * n + k]);
+      }
+    const double d = a[(size_t)col * n + col];
+    for (int k = 0; k < n; ++k) {
+      a[(size_t)col * n + k] /= d;
+      inv[(size_t)col * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[(size_t)r * n + col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[(size_t)r * n + k] -= f * a[(size_t)col * n + k];
+        inv[(size_t)r * n + k] -= f * inv[(size_t)col * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+int build_transform(lt_handle* h, const Shape& s, int precision, const TransformWs& t) {
+  lt::KronDesc fwd{}, inv{};
+  fwd.nmodes = inv.nmodes = s.nmodes;
+  double* dst = t.custom;
+  for (int i = 0; i < s.nmodes; ++i) {
+    fwd.n[i] = inv.n[i] = s.n[i];
+    fwd.kind[i] = inv.kind[i] = s.kind[i];
+    if (s.kind[i] == LT_CUSTOM) {
+      const int n = s.n[i];
+      std::vector<double> Mi;
+      if (!invert(s.custom[i], n, Mi))
+        return fail(h, LT_ERR_ARG, "mode %d: custom matrix is singular", i + 3);
+      const size_t bytes = (size_t)n * n * sizeof(double);
+      HIP_TRY(h, hipMemcpyAsync(dst, s.custom[i], bytes, hipMemcpyHostToDevice, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(dst + (size_t)n * n, Mi.data(), bytes, hipMemcpyHostToDevice,
+                                h->stream));
+      // the pageable source must stay valid until the copy has been consumed
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+      fwd.custom[i] = dst;
+      inv.custom[i] = dst + (size_t)n * n;
+      dst += 2 * (size_t)n * n;
+    }
+  }
+  ProfScope ps(h, LT_PROF_OTHER);
+  HIP_TRY(h, lt::launch_build_kron(fwd, (int)s.P, 0, t.K, t.Khi, t.Klo, h->stream));
+  HIP_TRY(h, lt::launch_build_kron(inv, (int)s.P, 1, t.Kinv, t.Kihi, t.Kilo, h->stream));
+  (void)precision;
+  return LT_OK;
+}
+
+lt::GemmArgs gemm_plain(const TransformWs& t, bool inverse, int P, long long N, const float* in,
+                        float* out) {
+  lt::GemmArgs g{};
+  g.K = inverse ? t.Kinv : t.K;
+  g.Khi = inverse ? t.Kihi : t.Khi;
+  g.Klo = inverse ? t.Kilo : t.Klo;
+  g.P = P;
+  g.N = N;
+  g.B = in;
+  g.out = out;
+  return g;
+}
+
+int gemm(lt_handle* h, const lt::GemmArgs& g, int prec, int pro, int epi, int cls,
+         int* n_partials = nullptr) {
+  ProfScope ps(h, cls);
+  HIP_TRY(h, lt::launch_transform_gemm(g, prec, pro, epi, h->stream, n_partials));
+  return LT_OK;
+}
+
+void resolve_opts(const lt_svd_opts* o, double* tol, int* max_sweeps, int* prec) {
+  *tol = (o && o->jacobi_tol > 0) ? o->jacobi_tol : 1e-6;
+  *max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
+  *prec = o ? o->precision : LT_PREC_F32;
+}
+
+int check_prec(lt_handle* h, int prec) {
+  if (prec != LT_PREC_F32 && prec != LT_PREC_BF16X3)
+    return fail(h, LT_ERR_ARG, "unknown precision %d", prec);
+  return LT_OK;
+}
+
+int jacobi_config(lt_handle* h, const Shape& s, lt::JacobiConfig* cfg) {
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
+  const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  const char* env = getenv("LT_JACOBI_G");
+  const int forceG = env ? atoi(env) : 0;
+  if (lt::jacobi_pick_config(m, n, h->max_lds, cfg, forceG) != 0)
+    return fail(h, LT_ERR_SHAPE,
+                "slice %lld x %lld exceeds the register-resident Jacobi kernel "
+                "(needs ceil(n/2)*G <= 1024 and ceil(m/G) <= 32)",
+                (long long)s.I1, (long long)s.I2);
+  return LT_OK;
+}
+
+struct SvtWs {
+  TransformWs t;
+  float* Gh = nullptr;
+  float* Bk = nullptr;
+  int32_t* rank = nullptr;
+  int32_t* sweeps = nullptr;
+};
+
+void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
+  carve_transform(c, s, prec, &w->t);
+  w->Gh = c.take<float>((size_t)s.nel);
+  w->Bk = c.take<float>((size_t)s.nel);
+  w->rank = c.take<int32_t>((size_t)s.P);
+  w->sweeps = c.take<int32_t>((size_t)s.P);
+}
+
+struct PgaWs {
+  SvtWs svt;
+  float* Xb = nullptr;
+  double* partials = nullptr;
+  double* norms = nullptr;
+  unsigned long long* sweep_total = nullptr;
+  unsigned long long* rot_total = nullptr;
+  unsigned int* maxsweep_hits = nullptr;
+  unsigned int* nonfinite = nullptr;
+};
+
+long long n_partials(const Shape& s) {
+  return ((s.N + 63) / 64) * ((s.P + 63) / 64);
+}
+
+void carve_pga(Carver& c, const Shape& s, int prec, PgaWs* w) {
+  carve_svt(c, s, prec, &w->svt);
+  w->Xb = c.take<float>((size_t)s.nel);
+  w->partials = c.take<double>(2 * (size_t)n_partials(s));
+  w->norms = c.take<double>(2);
+  w->sweep_total = c.take<unsigned long long>(1);
+  w->rot_total = c.take<unsigned long long>(1);
+  w->maxsweep_hits = c.take<unsigned int>(1);
+  w->nonfinite = c.take<unsigned int>(1);
+}
+
+struct LprodWs {
+  TransformWs t;
+  float *Ah = nullptr, *Bh = nullptr, *Ch = nullptr;
+};
+
+struct LsvdWs {
+  TransformWs t;
+  float* Ah = nullptr;
+  float* cols = nullptr;
+  double* sigma = nullptr;
+  float *Uh = nullptr, *Sh = nullptr, *Vh = nullptr;
+  int32_t* sweeps = nullptr;
+};
+
+void carve_lsvd(Carver& c, const Shape& s, int prec, LsvdWs* w) {
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  carve_transform(c, s, prec, &w->t);
+  w->Ah = c.take<float>((size_t)s.nel);
+  w->cols = c.take<float>((size_t)s.nel);
+  w->sigma = c.take<double>((size_t)(s.P * n));
+  w->Uh = c.take<float>((size_t)(s.P * s.I1 * n));
+  w->Sh = c.take<float>((size_t)(s.P * n * n));
+  w->Vh = c.take<float>((size_t)(s.P * s.I2 * n));
+  w->sweeps = c.take<int32_t>((size_t)s.P);
+}
+
+int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
+  if (!ws) return fail(h, LT_ERR_WORKSPACE, "workspace is NULL");
+  if (have < need)
+    return fail(h, LT_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", have, need);
+  return LT_OK;
+}
+
+int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtWs& w,
+                   double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
+                   unsigned long long* sweep_total, unsigned long long* rot_total,
+                   unsigned int* hits) {
+  lt::JacobiConfig cfg;
+  int rc = jacobi_config(h, s, &cfg);
+  if (rc) return rc;
+  lt::JacobiArgs j{};
+  j.src = Gh;
+  j.slice_stride = s.N;
+  j.I1 = (int)s.I1;
+  j.I2 = (int)s.I2;
+  j.nslices = (int)s.P;
+  j.tau = tau;
+  j.tol = tol;
+  j.max_sweeps = max_sweeps;
+  j.mode = 0;
+  j.bk = w.Bk;
+  j.rank = rank;
+  j.sweeps = sweeps;
+  j.sweep_total = sweep_total;
+  j.rot_total = rot_total;
+  j.maxsweep_hits = hits;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+  }
+  lt::RebuildArgs r{};
+  r.W = Gh;
+  r.D = Dh;
+  r.bk = w.Bk;
+  r.rank = rank;
+  r.slice_stride = s.N;
+  r.I1 = (int)s.I1;
+  r.I2 = (int)s.I2;
+  r.nslices = (int)s.P;
+  {
+    ProfScope ps(h, LT_PROF_REBUILD);
+    HIP_TRY(h, lt::launch_rebuild(r, h->stream));
+  }
+  return LT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lt_status_string(int status) {
+  switch (status) {
+    case LT_OK: return "ok";
+    case LT_ERR_ARG: return "invalid argument";
+    case LT_ERR_SHAPE: return "invalid or unsupported shape";
+    case LT_ERR_UNSUPPORTED: return "unsupported on this library";
+    case LT_ERR_NONFINITE: return "non-finite input";
+    case LT_ERR_HIP: return "HIP runtime error";
+    case LT_ERR_WORKSPACE: return "workspace missing or too small";
+    case LT_WARN_MAXSWEEPS: return "warning: Jacobi sweep limit reached";
+    case LT_WARN_NOT_CONVERGED: return "warning: PGA iteration limit reached";
+    default: return "unknown status";
+  }
+}
+
+int lt_create(lt_handle** out, void* stream) {
+  if (!out) return LT_ERR_ARG;
+  lt_handle* h = new (std::nothrow) lt_handle();
+  if (!h) return LT_ERR_ARG;
+  h->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return LT_ERR_HIP;
+  }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) ==
+          hipSuccess &&
+      lds > 0)
+    h->max_lds = lds;
+  if (hipHostMalloc((void**)&h->pinned, 16 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete h;
+    return LT_ERR_HIP;
+  }
+  *out = h;
+  return LT_OK;
+}
+
+int lt_destroy(lt_handle* h) {
+  if (!h) return LT_ERR_ARG;
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return LT_OK;
+}
+
+int lt_set_stream(lt_handle* h, void* stream) {
+  if (!h) return LT_ERR_ARG;
+  h->stream = static_cast<hipStream_t>(stream);
+  return LT_OK;
+}
+
+const char* lt_last_error(const lt_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+int lt_profile_begin(lt_handle* h) {
+  if (!h) return LT_ERR_ARG;
+  if (h->events.empty()) {
+    h->events.resize(kEventPool);
+    for (size_t i = 0; i < kEventPool; ++i)
+      if (hipEventCreate(&h->events[i]) != hipSuccess) {
+        h->events.resize(i);
+        return fail(h, LT_ERR_HIP, "hipEventCreate failed");
+      }
+  }
+  h->ev_next = 0;
+  h->recs.clear();
+  h->dropped = 0;
+  h->prof_on = true;
+  return LT_OK;
+}
+
+int lt_profile_end(lt_handle* h, lt_profile* out) {
+  if (!h || !out) return LT_ERR_ARG;
+  h->prof_on = false;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  memset(out, 0, sizeof(*out));
+  for (const auto& r : h->recs) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->events[r.second], h->events[r.second + 1]));
+    out->calls[r.first] += 1;
+    out->ms[r.first] += ms;
+  }
+  out->dropped = h->dropped;
+  h->recs.clear();
+  h->ev_next = 0;
+  return LT_OK;
+}
+
+size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precision) {
+  Shape s;
+  if (parse(nullptr, a, &s) != LT_OK) return 0;
+  if (precision != LT_PREC_F32 && precision != LT_PREC_BF16X3) return 0;
+  Carver c(nullptr);
+  switch (op) {
+    case LT_OP_SVT: {
+      SvtWs w;
+      carve_svt(c, s, precision, &w);
+      break;
+    }
+    case LT_OP_PGA: {
+      PgaWs w;
+      carve_pga(c, s, precision, &w);
+      break;
+    }
+    case LT_OP_LPRODUCT: {
+      Shape sb;
+      if (!b || parse(nullptr, b, &sb) != LT_OK) return 0;
+      LprodWs w;
+      carve_transform(c, s, precision, &w.t);
+      w.Ah = c.take<float>((size_t)s.nel);
+      w.Bh = c.take<float>((size_t)sb.nel);
+      w.Ch = c.take<float>((size_t)(s.I1 * sb.I2 * s.P));
+      break;
+    }
+    case LT_OP_LSVD: {
+      LsvdWs w;
+      carve_lsvd(c, s, precision, &w);
+      break;
+    }
+    default: return 0;
+  }
+  return c.off + 256;
+}
+
+int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
+                int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts, void* ws,
+                size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!A || !D) return fail(h, LT_ERR_ARG, "A or D is NULL");
+  if (!(tau >= 0.0) || !isfinite(tau)) return fail(h, LT_ERR_ARG, "tau must be finite and >= 0");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  lt::JacobiConfig probe;
+  if ((rc = jacobi_config(h, s, &probe))) return rc;
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_SVT, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  SvtWs w;
+  carve_svt(c, s, prec, &w);
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  if ((rc = gemm(h, gemm_plain(w.t, false, (int)s.P, s.N, A, w.Gh), prec, lt::PRO_PLAIN,
+                 lt::EPI_PLAIN, LT_PROF_FORWARD)))
+    return rc;
+  rc = run_jacobi_svt(h, s, w.Gh, w.Gh, w, tau, tol, max_sweeps, rank_out ? rank_out : w.rank,
+                      sweeps_out ? sweeps_out : w.sweeps, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Gh, D), prec, lt::PRO_PLAIN,
+              lt::EPI_PLAIN, LT_PROF_INVERSE);
+}
+
+int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b,
+                const float* B, float* C, int precision, void* ws, size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape sa, sb;
+  int rc = parse(h, a, &sa);
+  if (rc) return rc;
+  if ((rc = parse(h, b, &sb))) return rc;
+  if (!A || !B || !C) return fail(h, LT_ERR_ARG, "A, B or C is NULL");
+  if ((rc = check_prec(h, precision))) return rc;
+  if (sa.order != sb.order || sa.I2 != sb.I1)
+    return fail(h, LT_ERR_SHAPE, "inner dimensions differ (%lld vs %lld)", sa.I2, sb.I1);
+  for (int i = 2; i < sa.order; ++i)
+    if (a->dims[i] != b->dims[i] || a->kind[i] != b->kind[i] ||
+        (a->kind[i] == LT_CUSTOM && a->custom[i] != b->custom[i]))
+      return fail(h, LT_ERR_SHAPE, "mode %d differs between A and B", i + 1);
+  const size_t need = lt_workspace_bytes(a, b, LT_OP_LPRODUCT, precision);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LprodWs w;
+  carve_transform(c, sa, precision, &w.t);
+  w.Ah = c.take<float>((size_t)sa.nel);
+  w.Bh = c.take<float>((size_t)sb.nel);
+  w.Ch = c.take<float>((size_t)(sa.I1 * sb.I2 * sa.P));
+  if ((rc = build_transform(h, sa, precision, w.t))) return rc;
+  const int P = (int)sa.P;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, sa.N, A, w.Ah), precision, lt::PRO_PLAIN,
+                 lt::EPI_PLAIN, LT_PROF_FORWARD)))
+    return rc;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, sb.N, B, w.Bh), precision, lt::PRO_PLAIN,
+                 lt::EPI_PLAIN, LT_PROF_FORWARD)))
+    return rc;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_facewise(w.Ah, w.Bh, w.Ch, (int)sa.I1, (int)sa.I2, (int)sb.I2, P,
+                                   h->stream));
+  }
+  return gemm(h, gemm_plain(w.t, true, P, sa.I1 * sb.I2, w.Ch, C), precision, lt::PRO_PLAIN,
+              lt::EPI_PLAIN, LT_PROF_INVERSE);
+}
+
+int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, float* V,
+            float* sigma, int transform_domain, const lt_svd_opts* opts, void* ws,
+            size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!A || !U || !S || !V) return fail(h, LT_ERR_ARG, "A, U, S or V is NULL");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  lt::JacobiConfig cfg;
+  if ((rc = jacobi_config(h, s, &cfg))) return rc;
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  if (n > 256) return fail(h, LT_ERR_SHAPE, "lsvd supports min(I1, I2) <= 256");
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdWs w;
+  carve_lsvd(c, s, prec, &w);
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  const int P = (int)s.P;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_FORWARD)))
+    return rc;
+  lt::JacobiArgs j{};
+  j.src = w.Ah;
+  j.slice_stride = s.N;
+  j.I1 = (int)s.I1;
+  j.I2 = (int)s.I2;
+  j.nslices = P;
+  j.tau = 0.0;
+  j.tol = tol;
+  j.max_sweeps = max_sweeps;
+  j.mode = 1;
+  j.bk = w.cols;
+  j.rank = nullptr;
+  j.sweeps = w.sweeps;
+  j.sigma = w.sigma;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+  }
+  lt::LsvdArgs f{};
+  f.W = w.Ah;
+  f.cols = w.cols;
+  f.sigma = w.sigma;
+  f.slice_stride = s.N;
+  f.I1 = (int)s.I1;
+  f.I2 = (int)s.I2;
+  f.nslices = P;
+  f.U = transform_domain ? U : w.Uh;
+  f.S = transform_domain ? S : w.Sh;
+  f.V = transform_domain ? V : w.Vh;
+  f.sig_out = sigma;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_lsvd_finalize(f, h->stream));
+  }
+  if (!transform_domain) {
+    if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * n, w.Uh, U), prec, lt::PRO_PLAIN,
+                   lt::EPI_PLAIN, LT_PROF_INVERSE)))
+      return rc;
+    if ((rc = gemm(h, gemm_plain(w.t, true, P, n * n, w.Sh, S), prec, lt::PRO_PLAIN,
+                   lt::EPI_PLAIN, LT_PROF_INVERSE)))
+      return rc;
+    if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I2 * n, w.Vh, V), prec, lt::PRO_PLAIN,
+                   lt::EPI_PLAIN, LT_PROF_INVERSE)))
+      return rc;
+  }
+  return LT_OK;
+}
+
+int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_t* mask,
+                    const lt_pga_params* p, float* X, lt_pga_report* rep, void* ws,
+                    size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!M || !mask || !X || !p) return fail(h, LT_ERR_ARG, "M, mask, X or params is NULL");
+  if (!(p->mu0 > 0) || !(p->nu > 0 && p->nu <= 1) || !(p->mu_bar > 0 && p->mu_bar <= p->mu0) ||
+      p->max_iter < 1 || !isfinite(p->mu0))
+    return fail(h, LT_ERR_ARG, "invalid PGA parameters (need mu0 > 0, 0 < nu <= 1, "
+                               "0 < mu_bar <= mu0, max_iter >= 1)");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(&p->svd, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  lt::JacobiConfig probe;
+  if ((rc = jacobi_config(h, s, &probe))) return rc;
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_PGA, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  PgaWs w;
+  carve_pga(c, s, prec, &w);
+  hipStream_t st = h->stream;
+
+  // NaN / Inf among the observed entries: one host sync before any iteration
+  HIP_TRY(h, hipMemsetAsync(w.nonfinite, 0, sizeof(unsigned int) * 1, st));
+  HIP_TRY(h, lt::launch_count_nonfinite(M, mask, s.nel, w.nonfinite, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned, w.nonfinite, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  if (*reinterpret_cast<unsigned int*>(h->pinned) != 0)
+    return fail(h, LT_ERR_NONFINITE, "%u non-finite observed entries in M",
+                *reinterpret_cast<unsigned int*>(h->pinned));
+
+  if ((rc = build_transform(h, s, prec, w.svt.t))) return rc;
+  const size_t bytes = (size_t)s.nel * sizeof(float);
+  float* Xcur = X;        // X^k
+  float* Xprev = w.Xb;    // X^{k-1}
+  HIP_TRY(h, hipMemsetAsync(Xcur, 0, bytes, st));
+  HIP_TRY(h, hipMemsetAsync(Xprev, 0, bytes, st));
+  HIP_TRY(h, hipMemsetAsync(w.sweep_total, 0, sizeof(unsigned long long), st));
+  HIP_TRY(h, hipMemsetAsync(w.rot_total, 0, sizeof(unsigned long long), st));
+  HIP_TRY(h, hipMemsetAsync(w.maxsweep_hits, 0, sizeof(unsigned int), st));
+
+  const int check_every = p->check_every > 0 ? p->check_every : 1;
+  double t_prev = 1.0, t = 1.0, mu = p->mu0;   // t_0 = t_1 = 1, mu_1 = mu0
+  int iters = 0;
+  bool converged = false;
+  double crit = NAN;
+  for (int k = 0; k < p->max_iter; ++k) {
+    const double beta = (t_prev - 1.0) / t;   // eq. (52)
+    const double mu_k = p->fixed_mu ? p->mu0 : mu;
+
+    lt::GemmArgs f = gemm_plain(w.svt.t, false, (int)s.P, s.N, nullptr, w.svt.Gh);
+    f.X = Xcur;
+    f.Xp = Xprev;
+    f.M = M;
+    f.mask = mask;
+    f.beta = (float)beta;
+    if ((rc = gemm(h, f, prec, lt::PRO_PGA, lt::EPI_PLAIN, LT_PROF_FORWARD))) return rc;
+    rc = run_jacobi_svt(h, s, w.svt.Gh, w.svt.Gh, w.svt, mu_k, tol, max_sweeps, w.svt.rank,
+                        w.svt.sweeps, w.sweep_total, w.rot_total, w.maxsweep_hits);
+    if (rc) return rc;
+    lt::GemmArgs b = gemm_plain(w.svt.t, true, (int)s.P, s.N, w.svt.Gh, Xprev);
+    b.X = Xcur;
+    b.Xp = Xprev;
+    b.beta = (float)beta;
+    b.partials = w.partials;
+    int np = 0;
+    if ((rc = gemm(h, b, prec, lt::PRO_PLAIN, lt::EPI_PGA, LT_PROF_INVERSE, &np))) return rc;
+    {
+      ProfScope ps(h, LT_PROF_OTHER);
+      HIP_TRY(h, lt::launch_reduce_partials(w.partials, np, w.norms, st));
+    }
+    float* tmp = Xcur;   // X^{k+1} now lives in the old X^{k-1} buffer
+    Xcur = Xprev;
+    Xprev = tmp;
+    iters = k + 1;
+
+    t_prev = t;
+    t = (1.0 + sqrt(4.0 * t * t + 1.0)) / 2.0;
+    const bool at_floor = p->fixed_mu || mu_k <= p->mu_bar;
+    mu = fmax(p->nu * mu, p->mu_bar);
+
+    if (p->tol > 0 && (iters % check_every == 0 || iters == p->max_iter)) {
+      HIP_TRY(h, hipMemcpyAsync(h->pinned, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(h, hipStreamSynchronize(st));
+      const double num = h->pinned[0], den = h->pinned[1];
+      crit = den > 0 ? sqrt(num) / sqrt(den) : INFINITY;   // 0/0 counts as not converged
+      if (crit <= p->tol && (at_floor || !p->gate_until_floor)) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  if (Xcur != X) HIP_TRY(h, hipMemcpyAsync(X, Xcur, bytes, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned + 2, w.sweep_total, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned + 3, w.maxsweep_hits, sizeof(unsigned int),
+                            hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned + 4, w.rot_total, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  const double num = h->pinned[0], den = h->pinned[1];
+  crit = den > 0 ? sqrt(num) / sqrt(den) : INFINITY;
+  unsigned long long sweeps_total;
+  memcpy(&sweeps_total, h->pinned + 2, sizeof(sweeps_total));
+  unsigned int hits;
+  memcpy(&hits, h->pinned + 3, sizeof(hits));
+  unsigned long long rots;
+  memcpy(&rots, h->pinned + 4, sizeof(rots));
+  if (rep) {
+    rep->iters = iters;
+    rep->converged = converged ? 1 : 0;
+    rep->max_sweeps_hit = (int32_t)hits;
+    rep->reserved = 0;
+    rep->last_crit = crit;
+    rep->total_sweeps = (int64_t)sweeps_total;
+    rep->total_slices = (int64_t)iters * s.P;
+    rep->total_rotations = (int64_t)rots;
+  }
+  if (p->tol > 0 && !converged) return LT_WARN_NOT_CONVERGED;
+  if (hits) return LT_WARN_MAXSWEEPS;
+  return LT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP sources of liblt.so (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ---- bf16 helpers (round to nearest even; inputs here are finite) ---------
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float v) {
+  union { float f; uint32_t u; } x;
+  x.f = v;
+  uint32_t u = x.u;
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t h) {
+  union { float f; uint32_t u; } x;
+  x.u = ((uint32_t)h) << 16;
+  return x.f;
+}
+
+// ---- transform GEMM: out[q, e] = sum_p K[q, p] in[p, e] ----------------------
+// Rows are transform-domain slice indices (q, p < P); columns are the I1*I2
+// entries of a slice (e < N).  in/out are row-major P x N (ld = N), which is
+// exactly the tensor layout (slice p starts at p*N).
+enum ProMode { PRO_PLAIN = 0, PRO_PGA = 1 };
+enum EpiMode { EPI_PLAIN = 0, EPI_PGA = 1 };
+
+struct GemmArgs {
+  const float* K;          // P x P row-major (FP32 path)
+  const uint16_t* Khi;     // bf16 split of the same matrix (BF16X3 path)
+  const uint16_t* Klo;
+  int P;
+  long long N;
+  // prologue: PRO_PLAIN reads B; PRO_PGA builds G = mask ? M : X + beta (X - Xp)
+  const float* B;
+  const float* X;
+  const float* Xp;
+  const float* M;
+  const uint8_t* mask;
+  float beta;
+  // epilogue: EPI_PLAIN stores out; EPI_PGA also forms Y = X + beta (X - Xp) at
+  // the output position and accumulates ||Y - out||^2, ||out||^2 per workgroup
+  float* out;
+  double* partials;        // [gridDim.x * gridDim.y][2]
+};
+
+hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int epi,
+                                 hipStream_t s, int* n_partials);
+
+// Build the Kronecker transform K = M_N (x) ... (x) M_3 (P x P, row-major) and
+// optionally its bf16 hi/lo split.  Per mode: kind (0 DCT, 2 identity, 3 custom),
+// size, and for custom a device pointer to the row-major matrix (double).
+// inverse != 0 builds (x) M_i^{-1} (for DCT: transposes; custom matrices must
+// then already be the inverses).
+struct KronDesc {
+  int nmodes;
+  int n[8];
+  int kind[8];
+  const double* custom[8];
+};
+hipError_t launch_build_kron(const KronDesc& d, int P, int inverse, float* K,
+                             uint16_t* Khi, uint16_t* Klo, hipStream_t s);
+
+hipError_t launch_reduce_partials(const double* partials, int n, double* out2,
+                                  hipStream_t s);
+
+// C^p = A^p B^p for p < P; A^p: I1 x L (ld I1), B^p: L x I2 (ld L), C^p: I1 x I2.
+hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L,
+                           int I2, int P, hipStream_t s);
+
+// count of non-finite values among entries with mask != 0 (mask may be null)
+hipError_t launch_count_nonfinite(const float* X, const uint8_t* mask, long long n,
+                                  unsigned int* count, hipStream_t s);
+
+// ---- one-sided Jacobi SVT ----------------------------------------------------
+// Per slice (one workgroup each), working matrix W = slice (I1 >= I2) or
+// slice^T (I1 < I2), m = max(I1, I2) rows, n = min(I1, I2) columns.
+struct JacobiArgs {
+  const float* src;        // slices, slice s at src + s * slice_stride
+  long long slice_stride;
+  int I1, I2;
+  int nslices;
+  double tau;              // SVT threshold (svt mode)
+  double tol;              // rotate while |a.b| > tol |a||b|
+  int max_sweeps;
+  int mode;                // 0: SVT (write kept, scaled columns); 1: all columns + norms
+  float* bk;               // out, slice s at bk + s * slice_stride: m x r columns (ld m)
+  int32_t* rank;           // out [nslices] (svt mode: r; lsvd mode: n)
+  int32_t* sweeps;         // out [nslices]
+  double* sigma;           // lsvd mode: out [nslices][n] column norms (unsorted)
+  unsigned long long* sweep_total;  // optional: atomic sum of sweeps
+  unsigned long long* rot_total;    // optional: atomic sum of rotations
+  unsigned int* maxsweep_hits;      // optional: atomic count of slices at max_sweeps
+};
+
+struct JacobiConfig {
+  int G;        // lanes per column pair
+  int R;        // rows per lane (register-resident)
+  int threads;  // workgroup size
+  int nbuf;     // LDS exchange buffers (2: one barrier pair per round; 1: two)
+  size_t lds;   // dynamic LDS bytes
+};
+
+// Pick a kernel configuration for an m x n working matrix (0 on success).
+int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G);
+hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& cfg, hipStream_t s);
+
+// D (slice orientation) = rebuild from kept columns: D_W = Bk Bk^T W
+struct RebuildArgs {
+  const float* W;          // transform-domain slices (the Jacobi input)
+  float* D;                // output slices (may equal W)
+  const float* bk;
+  const int32_t* rank;
+  long long slice_stride;
+  int I1, I2, nslices;
+};
+hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s);
+
+// lsvd finalisation: sort, normalise, V = W^T U diag(1/sigma), write factors
+struct LsvdArgs {
+  const float* W;          // transform-domain slices
+  const float* cols;       // Jacobi final columns (m x n per slice, ld m)
+  const double* sigma;     // [nslices][n]
+  long long slice_stride;
+  int I1, I2, nslices;
+  float* U;                // I1 x n per slice (slice stride I1*n)
+  float* S;                // n x n per slice
+  float* V;                // I2 x n per slice
+  float* sig_out;          // optional [nslices][n]
+};
+hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s);
+
+}  // namespace lt

@@ -1,0 +1,594 @@
+// Per-slice SVD by one-sided (Hestenes) Jacobi and the singular value
+// soft-threshold of Alg. 4 / the prox of Theorem 23, batched over frontal
+// slices: one workgroup per slice.
+//
+// Working matrix: W = slice (I1 >= I2) or slice^T (I1 < I2), m x n with
+// m = max(I1, I2) rows and n = min(I1, I2) columns.  Columns of W are rotated
+// in pairs until every pair is orthogonal to within `tol`; the final columns
+// are u_i sigma_i with sigma_i their norms (W J = U Sigma, J orthogonal).
+//
+// Layout in the workgroup: pair slot g (0 <= g < ceil(n/2)) is held by a group
+// of G lanes; each lane keeps R consecutive rows of the slot's two columns in
+// registers (FP32).  Dot products, column norms and rotation angles are FP64.
+// The pair schedule is the round-robin (circle) tournament: position 0 is
+// fixed and every other column advances one position per round, so one sweep
+// of 2*ceil(n/2) - 1 rounds meets every column pair exactly once.  Columns move
+// between groups through LDS.
+//
+// SVT output: with g_i = 1 - tau / sigma_i for sigma_i > tau, the result of
+// Alg. 4 in working orientation is D_W = sum_i g_i u_i u_i^T W (because
+// u_i^T W = sigma_i v_i^T), so the kernel writes only the kept columns
+// sqrt(g_i) u_i (compacted, deterministic order) and their count; the rebuild
+// kernel forms D_W = Bk (Bk^T W) from the untouched input.
+#include "lt_internal.h"
+
+#include <math.h>
+
+namespace lt {
+
+namespace {
+
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+// FP64 dot product of two FP32 register columns (FP32 x FP32 products are exact
+// in FP64).  The scheduling barriers keep the compiler from converting the whole
+// column to FP64 ahead of use, which would hold 4 extra VGPRs per row.
+template <int R>
+__device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; r += 4) {
+    d0 = fma((double)x[r], (double)y[r], d0);
+    d1 = fma((double)x[r + 1], (double)y[r + 1], d1);
+    d0 = fma((double)x[r + 2], (double)y[r + 2], d0);
+    d1 = fma((double)x[r + 3], (double)y[r + 3], d1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return d0 + d1;
+}
+
+template <int R>
+__device__ inline void put_col(float* buf, int ldw, int idx, int row0, const float (&v)[R]) {
+  float4* p = reinterpret_cast<float4*>(buf + (size_t)idx * ldw + row0);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) p[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+template <int R>
+__device__ inline void get_col(const float* buf, int ldw, int idx, int row0, float (&v)[R]) {
+  const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw + row0);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    const float4 t = p[q];
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+
+template <int R>
+__device__ inline void store_col(float* col, int row0, int m, bool full, const float (&v)[R],
+                                 float sc) {
+  if (full) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) col[row0 + r] = v[r] * sc;
+  } else {
+    for (int r = 0; r < R; ++r)
+      if (row0 + r < m) col[row0 + r] = v[r] * sc;
+  }
+}
+
+template <int G, int R>
+__global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int s = blockIdx.x;
+  const int I1 = a.I1, I2 = a.I2;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int npairs = (n + 1) >> 1;
+  const int last = npairs - 1;
+  const int nb1 = npairs + 1;   // columns per exchange buffer (index 0: parked column)
+  const int tid = threadIdx.x;
+  const int g = tid / G, l = tid - (tid / G) * G;
+  const bool active = g < npairs;
+  const int row0 = l * R;
+  const float* __restrict__ A = a.src + (long long)s * a.slice_stride;
+
+  float* bufA = reinterpret_cast<float*>(smem);
+  float* bufB = (nbuf == 2) ? bufA + (size_t)nb1 * ldw : bufA;
+  double* nrmA = reinterpret_cast<double*>(bufA + (size_t)nbuf * nb1 * ldw);
+  double* nrmB = (nbuf == 2) ? nrmA + nb1 : nrmA;
+  int* idA = reinterpret_cast<int*>(nrmA + (size_t)nbuf * nb1);
+  int* idB = (nbuf == 2) ? idA + nb1 : idA;
+  // ctl[0], ctl[1]: rotation counters of even / odd sweeps; ctl[2]: kept total;
+  // ctl[3 + g]: per-slot output offsets
+  int* ctl = idA + (size_t)nbuf * nb1;
+
+  // ---- load: slot g holds columns g (top) and 2*npairs - 1 - g (bottom) ----
+  float av[R], bv[R];
+  int ida = g, idb = 2 * npairs - 1 - g;
+  {
+    // clamp every address into the slice and scale what is out of range by 0,
+    // so that the loads carry no control flow
+    const float fa = (active && ida < n) ? 1.f : 0.f, fb = (active && idb < n) ? 1.f : 0.f;
+    const int ca = ida < n ? ida : n - 1, cb = idb < n ? idb : n - 1;
+    if (trans) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = row0 + r;
+        const int rr = row < m ? row : m - 1;
+        const float f = row < m ? 1.f : 0.f;
+        av[r] = A[(long long)rr * I1 + ca] * (fa * f);
+        bv[r] = A[(long long)rr * I1 + cb] * (fb * f);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = row0 + r;
+        const int rr = row < m ? row : m - 1;
+        const float f = row < m ? 1.f : 0.f;
+        av[r] = A[(long long)ca * I1 + rr] * (fa * f);
+        bv[r] = A[(long long)cb * I1 + rr] * (fb * f);
+      }
+    }
+  }
+  if (tid == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+  }
+  __syncthreads();
+
+  const double tol = a.tol;
+  const int nrounds = 2 * npairs - 1;
+  double na = 0.0, nb = 0.0;
+  int sweep = 0;
+  bool converged = false;
+  long long rotations = 0;
+  // single-exit loop (max_sweeps >= 1): the columns stay in one register set
+  for (;;) {
+    na = group_sum<G>(dot64<R>(av, av));
+    nb = group_sum<G>(dot64<R>(bv, bv));
+    int my_rot = 0;
+    for (int round = 0; round < nrounds; ++round) {
+      const double d = group_sum<G>(dot64<R>(av, bv));
+      const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
+      if (active && d != 0.0 && fabs(d) > tol * sqrt(pa * pb)) {
+        // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]
+        const double zeta = (pb - pa) / (2.0 * d);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const float cf = (float)c, sf = (float)(c * t);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float x = av[r], y = bv[r];
+          av[r] = cf * x - sf * y;
+          bv[r] = sf * x + cf * y;
+        }
+        na = pa - t * d;
+        nb = pb + t * d;
+        my_rot += (l == 0);
+      }
+      if (npairs > 1) {
+        // phase 1: new tops (and park the last slot's bottom)
+        const int park = (nbuf == 2 && (round & 1)) ? 1 : 0;  // alternate park buffer
+        float* pbuf = park ? bufB : bufA;
+        double* pnrm = park ? nrmB : nrmA;
+        int* pid = park ? idB : idA;
+        if (active) {
+          if (g == 0) {
+            put_col<R>(bufA, ldw, 1, row0, bv);
+            if (l == 0) { nrmA[1] = nb; idA[1] = idb; }
+          } else if (g < last) {
+            put_col<R>(bufA, ldw, g + 1, row0, av);
+            if (l == 0) { nrmA[g + 1] = na; idA[g + 1] = ida; }
+          } else {
+            put_col<R>(pbuf, ldw, 0, row0, bv);
+            if (l == 0) { pnrm[0] = nb; pid[0] = idb; }
+          }
+        }
+        __syncthreads();
+        if (active && g >= 1) {
+          if (g == last) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) bv[r] = av[r];
+            nb = na;
+            idb = ida;
+          }
+          get_col<R>(bufA, ldw, g, row0, av);
+          na = nrmA[g];
+          ida = idA[g];
+        }
+        if (nbuf == 1) __syncthreads();
+        // phase 2: new bottoms
+        if (active && g >= 1 && g <= last - 1) {
+          put_col<R>(bufB, ldw, g, row0, bv);
+          if (l == 0) { nrmB[g] = nb; idB[g] = idb; }
+        }
+        __syncthreads();
+        if (active && g <= last - 1) {
+          if (g <= last - 2) {
+            get_col<R>(bufB, ldw, g + 1, row0, bv);
+            nb = nrmB[g + 1];
+            idb = idB[g + 1];
+          } else {
+            get_col<R>(pbuf, ldw, 0, row0, bv);
+            nb = pnrm[0];
+            idb = pid[0];
+          }
+        }
+        if (nbuf == 1) __syncthreads();
+      }
+    }
+    // the counter of the next sweep is cleared before the barrier that precedes
+    // any of its increments
+    if (my_rot) atomicAdd(&ctl[sweep & 1], my_rot);
+    __syncthreads();
+    const int total = ctl[sweep & 1];
+    if (tid == 0) ctl[(sweep + 1) & 1] = 0;
+    __syncthreads();
+    ++sweep;
+    rotations += total;
+    converged = (total == 0);
+    if (converged || sweep >= a.max_sweeps) break;
+  }
+
+  // ---- output -------------------------------------------------------------
+  na = group_sum<G>(dot64<R>(av, av));
+  nb = group_sum<G>(dot64<R>(bv, bv));
+  const double sa = sqrt(na), sb = sqrt(nb);
+  bool ka, kb;
+  if (a.mode == 0) {
+    ka = active && ida < n && sa > a.tau;
+    kb = active && idb < n && sb > a.tau;
+  } else {
+    ka = active && ida < n;
+    kb = active && idb < n;
+  }
+  __syncthreads();
+  if (active && l == 0) ctl[3 + g] = (int)ka + (int)kb;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int i = 0; i < npairs; ++i) {
+      const int c = ctl[3 + i];
+      ctl[3 + i] = acc;
+      acc += c;
+    }
+    ctl[2] = acc;
+  }
+  __syncthreads();
+  float* out = a.bk + (long long)s * a.slice_stride;
+  const bool full = row0 + R <= m;   // every row of this lane is inside the matrix
+  if (a.mode == 0) {
+    int j = active ? ctl[3 + g] : 0;
+    if (ka) {
+      const float sc = (float)(sqrt(1.0 - a.tau / sa) / sa);
+      store_col<R>(out + (long long)j * m, row0, m, full, av, sc);
+      ++j;
+    }
+    if (kb) {
+      const float sc = (float)(sqrt(1.0 - a.tau / sb) / sb);
+      store_col<R>(out + (long long)j * m, row0, m, full, bv, sc);
+    }
+  } else {
+    // all columns, at their original column index, plus their norms
+    if (ka) {
+      store_col<R>(out + (long long)ida * m, row0, m, full, av, 1.f);
+      if (l == 0) a.sigma[(long long)s * n + ida] = sa;
+    }
+    if (kb) {
+      store_col<R>(out + (long long)idb * m, row0, m, full, bv, 1.f);
+      if (l == 0) a.sigma[(long long)s * n + idb] = sb;
+    }
+  }
+  if (tid == 0) {
+    if (a.rank) a.rank[s] = ctl[2];
+    if (a.sweeps) a.sweeps[s] = sweep;
+    if (a.sweep_total) atomicAdd(a.sweep_total, (unsigned long long)sweep);
+    if (a.rot_total) atomicAdd(a.rot_total, (unsigned long long)rotations);
+    if (!converged && a.maxsweep_hits) atomicAdd(a.maxsweep_hits, 1u);
+  }
+}
+
+// ---- rebuild D_W = Bk (Bk^T W) ------------------------------------------------
+constexpr int RB_TN = 16;   // working columns per workgroup
+constexpr int RB_TK = 32;   // rows per LDS chunk
+constexpr int RB_RMAX = 256;
+
+__device__ inline float w_at(const float* W, bool trans, int I1, int row, int col) {
+  return trans ? W[(long long)row * I1 + col] : W[(long long)col * I1 + row];
+}
+
+__global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
+  __shared__ float Ws[RB_TK][RB_TN + 1];
+  __shared__ float Bs[RB_TK][RB_RMAX + 1];
+  __shared__ float Z[RB_RMAX][RB_TN + 1];
+  const int s = blockIdx.y;
+  const int I1 = a.I1, I2 = a.I2;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int j0 = blockIdx.x * RB_TN;
+  if (j0 >= n) return;
+  const int r = a.rank[s];
+  const int nq = (r + 15) >> 4;
+  const int rpad = nq << 4;
+  const float* W = a.W + (long long)s * a.slice_stride;
+  float* D = a.D + (long long)s * a.slice_stride;
+  const float* Bk = a.bk + (long long)s * a.slice_stride;
+  const int tid = threadIdx.x;
+  const int jj = tid & 15, hi = tid >> 4;
+
+  // phase A: Z[i][jj] = sum_k Bk[k][i] W[k][j0 + jj]
+  float zacc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) zacc[q] = 0.f;
+  if (r > 0) {
+    for (int k0 = 0; k0 < m; k0 += RB_TK) {
+      for (int idx = tid; idx < RB_TK * RB_TN; idx += 256) {
+        int kk, c;
+        if (trans) { c = idx % RB_TN; kk = idx / RB_TN; } else { kk = idx % RB_TK; c = idx / RB_TK; }
+        const int row = k0 + kk, col = j0 + c;
+        Ws[kk][c] = (row < m && col < n) ? w_at(W, trans, I1, row, col) : 0.f;
+      }
+      for (int idx = tid; idx < RB_TK * rpad; idx += 256) {
+        const int kk = idx % RB_TK, i = idx / RB_TK;
+        const int row = k0 + kk;
+        Bs[kk][i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < RB_TK; ++kk) {
+        const float w = Ws[kk][jj];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < nq) zacc[q] = fmaf(Bs[kk][hi + 16 * q], w, zacc[q]);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q < nq) Z[hi + 16 * q][jj] = zacc[q];
+  __syncthreads();
+
+  // phase B: D_W[k][j0 + jj] = sum_i Bk[k][i] Z[i][jj]
+  for (int k0 = 0; k0 < m; k0 += RB_TK) {
+    for (int idx = tid; idx < RB_TK * rpad; idx += 256) {
+      const int kk = idx % RB_TK, i = idx / RB_TK;
+      const int row = k0 + kk;
+      Bs[kk][i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = hi + 16 * h;
+      float acc = 0.f;
+      for (int i = 0; i < r; ++i) acc = fmaf(Bs[kk][i], Z[i][jj], acc);
+      const int row = k0 + kk, col = j0 + jj;
+      if (row < m && col < n) {
+        if (trans) D[(long long)row * I1 + col] = acc;
+        else D[(long long)col * I1 + row] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- lsvd: sort, normalise, V = W^T U / sigma, complete deficient columns ----
+constexpr int LS_NMAX = 256;
+
+__global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
+  __shared__ int perm[LS_NMAX];
+  __shared__ double sg[LS_NMAX];
+  __shared__ double red[256];
+  __shared__ int flag;
+  const int s = blockIdx.x;
+  const int I1 = a.I1, I2 = a.I2;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int tid = threadIdx.x;
+  const double* sig = a.sigma + (long long)s * n;
+  for (int i = tid; i < n; i += 256) {
+    const double si = sig[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = sig[j];
+      rk += (sj > si) || (sj == si && j < i);
+    }
+    perm[rk] = i;
+  }
+  __syncthreads();
+  for (int k = tid; k < n; k += 256) sg[k] = sig[perm[k]];
+  __syncthreads();
+  const double smax = n > 0 ? sg[0] : 0.0;
+  const double cut = smax * 1e-6;
+  const float* W = a.W + (long long)s * a.slice_stride;
+  const float* cols = a.cols + (long long)s * a.slice_stride;
+  // Uw (m x n) and Vw (n x n) live in the output factors:
+  //   I1 >= I2: U = Uw (I1 x n), V = Vw (I2 x n);  I1 < I2: U = Vw (I1 x n), V = Uw (I2 x n).
+  float* Uw = trans ? a.V + (long long)s * I2 * n : a.U + (long long)s * I1 * n;
+  float* Vw = trans ? a.U + (long long)s * I1 * n : a.V + (long long)s * I2 * n;
+  for (int idx = tid; idx < m * n; idx += 256) {
+    const int k = idx / m, row = idx - k * m;
+    const double sk = sg[k];
+    Uw[(long long)k * m + row] = sk > cut ? (float)((double)cols[(long long)perm[k] * m + row] / sk) : 0.f;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int k = idx / n, j = idx - k * n;
+    const double sk = sg[k];
+    double acc = 0.0;
+    if (sk > cut) {
+      for (int row = 0; row < m; ++row)
+        acc += (double)w_at(W, trans, I1, row, j) * (double)Uw[(long long)k * m + row];
+      acc /= sk;
+    }
+    Vw[(long long)k * n + j] = (float)acc;
+  }
+  __syncthreads();
+  // complete the columns of deficient singular values by Gram-Schmidt against
+  // the canonical basis (two passes), keeping both factors orthonormal
+  for (int pass = 0; pass < 2; ++pass) {
+    float* Q = pass == 0 ? Uw : Vw;
+    const int len = pass == 0 ? m : n;
+    for (int k = 0; k < n; ++k) {
+      if (sg[k] > cut) continue;
+      for (int cand = 0; cand < len; ++cand) {
+        for (int row = tid; row < len; row += 256) Q[(long long)k * len + row] = (row == cand) ? 1.f : 0.f;
+        __syncthreads();
+        for (int rep = 0; rep < 2; ++rep) {
+          for (int j = 0; j < n; ++j) {
+            if (j == k || (sg[j] <= cut && j > k)) continue;
+            double part = 0.0;
+            for (int row = tid; row < len; row += 256)
+              part += (double)Q[(long long)j * len + row] * (double)Q[(long long)k * len + row];
+            red[tid] = part;
+            __syncthreads();
+            for (int o = 128; o >= 1; o >>= 1) {
+              if (tid < o) red[tid] += red[tid + o];
+              __syncthreads();
+            }
+            const double c = red[0];
+            __syncthreads();
+            for (int row = tid; row < len; row += 256)
+              Q[(long long)k * len + row] -= (float)(c * (double)Q[(long long)j * len + row]);
+            __syncthreads();
+          }
+        }
+        double part = 0.0;
+        for (int row = tid; row < len; row += 256) {
+          const double v = Q[(long long)k * len + row];
+          part += v * v;
+        }
+        red[tid] = part;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+          if (tid < o) red[tid] += red[tid + o];
+          __syncthreads();
+        }
+        const double nrm = sqrt(red[0]);
+        if (tid == 0) flag = nrm > 0.5;
+        __syncthreads();
+        if (flag) {
+          for (int row = tid; row < len; row += 256)
+            Q[(long long)k * len + row] = (float)((double)Q[(long long)k * len + row] / nrm);
+          __syncthreads();
+          break;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  float* S = a.S + (long long)s * n * n;
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int k = idx / n, j = idx - k * n;
+    S[idx] = (j == k) ? (float)sg[k] : 0.f;
+  }
+  if (a.sig_out)
+    for (int k = tid; k < n; k += 256) a.sig_out[(long long)s * n + k] = (float)sg[k];
+}
+
+template <int G, int R>
+hipError_t launch_one(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
+  const int ldw = G * R + 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<G, R>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_jacobi<G, R>), dim3(a.nslices), dim3(c.threads), c.lds, s, a, c.nbuf, ldw);
+  return hipGetLastError();
+}
+
+template <int G>
+hipError_t launch_g(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
+  switch (c.R) {
+    case 4: return launch_one<G, 4>(a, c, s);
+    case 8: return launch_one<G, 8>(a, c, s);
+    case 12: return launch_one<G, 12>(a, c, s);
+    case 16: return launch_one<G, 16>(a, c, s);
+    case 20: return launch_one<G, 20>(a, c, s);
+    case 24: return launch_one<G, 24>(a, c, s);
+    case 28: return launch_one<G, 28>(a, c, s);
+    case 32: return launch_one<G, 32>(a, c, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t jacobi_lds_bytes(int npairs, int ldw, int nbuf) {
+  const size_t nb1 = (size_t)npairs + 1;
+  return (size_t)nbuf * nb1 * ldw * sizeof(float) + (size_t)nbuf * nb1 * sizeof(double) +
+         (size_t)nbuf * nb1 * sizeof(int) + ((size_t)npairs + 4) * sizeof(int);
+}
+
+}  // namespace
+
+int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G) {
+  // n <= 256 also bounds the kept-column count of the rebuild kernel's LDS arrays
+  if (m < 1 || n < 1 || m < n || n > RB_RMAX) return -1;
+  const int npairs = (n + 1) / 2;
+  const int Gs[5] = {64, 32, 16, 8, 4};
+  int bestG = 0;
+  int fallbackG = 0;
+  for (int i = 0; i < 5; ++i) {
+    const int G = Gs[i];
+    if (force_G && G != force_G) continue;
+    const int threads = ((npairs * G + 63) / 64) * 64;
+    int R = (m + G - 1) / G;
+    R = ((R + 3) / 4) * 4;
+    if (threads > 1024 || R > 32) continue;
+    const int ldw = G * R + 4;
+    if (jacobi_lds_bytes(npairs, ldw, 1) > (size_t)max_lds) continue;
+    if (R >= 8 && !bestG) bestG = G;
+    fallbackG = G;   // ends as the smallest feasible G
+  }
+  const int G = bestG ? bestG : fallbackG;
+  if (!G) return -1;
+  int R = (m + G - 1) / G;
+  R = ((R + 3) / 4) * 4;
+  cfg->G = G;
+  cfg->R = R;
+  cfg->threads = ((npairs * G + 63) / 64) * 64;
+  const int ldw = G * R + 4;
+  if (jacobi_lds_bytes(npairs, ldw, 2) <= (size_t)max_lds) {
+    cfg->nbuf = 2;
+  } else {
+    cfg->nbuf = 1;
+  }
+  cfg->lds = jacobi_lds_bytes(npairs, ldw, cfg->nbuf);
+  return 0;
+}
+
+hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  switch (c.G) {
+    case 4: return launch_g<4>(a, c, s);
+    case 8: return launch_g<8>(a, c, s);
+    case 16: return launch_g<16>(a, c, s);
+    case 32: return launch_g<32>(a, c, s);
+    case 64: return launch_g<64>(a, c, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
+  hipLaunchKernelGGL(k_rebuild, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lsvd_finalize, dim3(a.nslices), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lt

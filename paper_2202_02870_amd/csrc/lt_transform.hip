@@ -1,0 +1,336 @@
+// Transform-domain kernels: the invertible transform L as one GEMM with the
+// Kronecker matrix K = M_N (x) ... (x) M_3 (Section 3.2: L(A) = A x_3 M_3 ...
+// x_N M_N; with the Vec slice order of eq. (3.5), L(A)^q = sum_p K[q,p] A^p),
+// the masked momentum step of eqs. (51)-(52) fused into the forward GEMM's
+// operand load, and the stopping-rule norms of Section 5 fused into the
+// inverse GEMM's store.
+#include "lt_internal.h"
+
+#include <math.h>
+
+namespace lt {
+
+namespace {
+
+constexpr int TQ = 64;   // output rows (transform-domain slices) per workgroup
+constexpr int TE = 64;   // output columns (slice entries) per workgroup
+constexpr int TPK = 32;  // contraction chunk staged in LDS
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic workgroup sum of two doubles (256 threads), result in thread 0.
+__device__ inline void block_sum2(double& s1, double& s2) {
+  __shared__ double red[2][4];
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = s1; red[1][w] = s2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s1 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    s2 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+template <int PRO>
+__device__ inline float load_operand(const GemmArgs& a, long long g) {
+  if (PRO == PRO_PLAIN) return a.B[g];
+  const float x = a.X[g];
+  const float y = x + a.beta * (x - a.Xp[g]);          // eq. (52)
+  return a.mask[g] ? a.M[g] : y;                        // eq. (51), step 1/l_f = 1
+}
+
+template <int EPI>
+__device__ inline void store_result(const GemmArgs& a, long long g, float o, double& s1,
+                                    double& s2) {
+  if (EPI == EPI_PGA) {
+    const float x = a.X[g];
+    const float y = x + a.beta * (x - a.Xp[g]);
+    const double d = (double)y - (double)o;
+    s1 += d * d;
+    s2 += (double)o * (double)o;
+  }
+  a.out[g] = o;
+}
+
+// FP32 MFMA (v_mfma_f32_16x16x4_f32).  Workgroup = 4 waves; tile 64 x 64;
+// wave w owns output rows 16w..16w+15 and four 16-column sub-tiles.
+// Operand lane layout of the 16x16x4 instruction: A[i][k] at lane i + 16k,
+// B[k][j] at lane j + 16k, D[i][j] in element i%4 of lane j + 16(i/4).
+template <int PRO, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
+  __shared__ float Ks[TQ][TPK + 1];
+  __shared__ float Bs[TPK][TE + 4];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const long long e0 = (long long)blockIdx.x * TE;
+  const int q0 = blockIdx.y * TQ;
+  const int P = a.P;
+  const long long N = a.N;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int p0 = 0; p0 < P; p0 += TPK) {
+    for (int idx = tid; idx < TQ * TPK; idx += 256) {
+      const int i = idx / TPK, k = idx - i * TPK;
+      const int q = q0 + i, p = p0 + k;
+      Ks[i][k] = (q < P && p < P) ? a.K[(long long)q * P + p] : 0.f;
+    }
+    for (int idx = tid; idx < TPK * TE; idx += 256) {
+      const int k = idx / TE, j = idx - k * TE;
+      const int p = p0 + k;
+      const long long e = e0 + j;
+      Bs[k][j] = (p < P && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TPK; kk += 4) {
+      const float av = Ks[16 * w + (l & 15)][kk + (l >> 4)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float bv = Bs[kk + (l >> 4)][16 * t + (l & 15)];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 16 * w + 4 * (l >> 4) + v;
+      const long long e = e0 + 16 * t + (l & 15);
+      if (q < P && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
+    }
+  }
+  if (EPI == EPI_PGA) {
+    block_sum2(s1, s2);
+    if (threadIdx.x == 0) {
+      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+      a.partials[2 * b] = s1;
+      a.partials[2 * b + 1] = s2;
+    }
+  }
+}
+
+// BF16 MFMA (v_mfma_f32_16x16x32_bf16) on hi/lo splits: K ~ Kh + Kl and
+// in ~ Bh + Bl, product Kh Bh + Kh Bl + Kl Bh with FP32 accumulation.
+// Lane layout of the 16x16x32 instruction: A[i][8c..8c+7] at lane i + 16c,
+// B[8c..8c+7][j] at lane j + 16c, D as for the FP32 instruction.
+template <int PRO, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs a) {
+  constexpr int KP = TPK + 8;  // row pitch in halves (80 B: keeps 16-B alignment)
+  __shared__ __attribute__((aligned(16))) uint16_t Kh[TQ][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Kl[TQ][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[TE][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[TE][KP];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const long long e0 = (long long)blockIdx.x * TE;
+  const int q0 = blockIdx.y * TQ;
+  const int P = a.P;
+  const long long N = a.N;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int p0 = 0; p0 < P; p0 += TPK) {
+    for (int idx = tid; idx < TQ * TPK; idx += 256) {
+      const int i = idx / TPK, k = idx - i * TPK;
+      const int q = q0 + i, p = p0 + k;
+      const bool in = (q < P && p < P);
+      Kh[i][k] = in ? a.Khi[(long long)q * P + p] : (uint16_t)0;
+      Kl[i][k] = in ? a.Klo[(long long)q * P + p] : (uint16_t)0;
+    }
+    for (int idx = tid; idx < TPK * TE; idx += 256) {
+      const int k = idx / TE, j = idx - k * TE;
+      const int p = p0 + k;
+      const long long e = e0 + j;
+      const float v = (p < P && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
+      const uint16_t h = f32_to_bf16_bits(v);
+      Bh[j][k] = h;
+      Bl[j][k] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
+    }
+    __syncthreads();
+    const int c = l >> 4;
+    const uint4 ah = *reinterpret_cast<const uint4*>(&Kh[16 * w + (l & 15)][8 * c]);
+    const uint4 al = *reinterpret_cast<const uint4*>(&Kl[16 * w + (l & 15)][8 * c]);
+    const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah);
+    const bf16x8 Al = __builtin_bit_cast(bf16x8, al);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint4 bh = *reinterpret_cast<const uint4*>(&Bh[16 * t + (l & 15)][8 * c]);
+      const uint4 bl = *reinterpret_cast<const uint4*>(&Bl[16 * t + (l & 15)][8 * c]);
+      const bf16x8 Bhv = __builtin_bit_cast(bf16x8, bh);
+      const bf16x8 Blv = __builtin_bit_cast(bf16x8, bl);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Blv, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bhv, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bhv, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = q0 + 16 * w + 4 * (l >> 4) + v;
+      const long long e = e0 + 16 * t + (l & 15);
+      if (q < P && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
+    }
+  }
+  if (EPI == EPI_PGA) {
+    block_sum2(s1, s2);
+    if (threadIdx.x == 0) {
+      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+      a.partials[2 * b] = s1;
+      a.partials[2 * b + 1] = s2;
+    }
+  }
+}
+
+// Entry (r, c) of the mode matrix: orthonormal DCT-II
+// sqrt((2 - delta_{r,0}) / n) cos(r (2c + 1) pi / (2n)) (0-based indices).
+__device__ inline double dct_entry(int r, int c, int n) {
+  const double s = sqrt((r == 0 ? 1.0 : 2.0) / (double)n);
+  return s * cos((double)r * (double)(2 * c + 1) * M_PI / (2.0 * (double)n));
+}
+
+__global__ void k_build_kron(KronDesc d, int P, int inverse, float* K, uint16_t* Khi,
+                             uint16_t* Klo) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)P * P) return;
+  int rq = (int)(idx / P), rp = (int)(idx % P);
+  double v = 1.0;
+  for (int m = 0; m < d.nmodes; ++m) {
+    const int n = d.n[m];
+    const int j = rq % n, k = rp % n;
+    rq /= n;
+    rp /= n;
+    double e;
+    if (d.kind[m] == 0) {
+      e = inverse ? dct_entry(k, j, n) : dct_entry(j, k, n);   // C^{-1} = C^T
+    } else if (d.kind[m] == 2) {
+      e = (j == k) ? 1.0 : 0.0;
+    } else {
+      e = d.custom[m][(long long)j * n + k];
+    }
+    v *= e;
+  }
+  const float f = (float)v;
+  K[idx] = f;
+  if (Khi) {
+    const uint16_t h = f32_to_bf16_bits(f);
+    Khi[idx] = h;
+    Klo[idx] = f32_to_bf16_bits(f - bf16_bits_to_f32(h));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n, double* out) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    s1 += p[2 * i];
+    s2 += p[2 * i + 1];
+  }
+  block_sum2(s1, s2);
+  if (threadIdx.x == 0) {
+    out[0] = s1;
+    out[1] = s2;
+  }
+}
+
+// Face-wise product (Section 3.1 definition): one 16x16 output tile of one slice
+// per workgroup, contraction staged through LDS in chunks of 16.
+__global__ __launch_bounds__(256) void k_facewise(const float* A, const float* B, float* C,
+                                                  int I1, int L, int I2) {
+  __shared__ float As[16][17];
+  __shared__ float Bs[16][17];
+  const int p = blockIdx.z;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + ti, j = blockIdx.y * 16 + tj;
+  const float* Ap = A + (long long)p * I1 * L;
+  const float* Bp = B + (long long)p * L * I2;
+  float acc = 0.f;
+  for (int k0 = 0; k0 < L; k0 += 16) {
+    // A tile: rows i (ti), cols k0 + tj ; B tile: rows k0 + ti, cols j (tj)
+    const int ka = k0 + tj, kb = k0 + ti;
+    As[ti][tj] = (i < I1 && ka < L) ? Ap[(long long)ka * I1 + i] : 0.f;
+    Bs[ti][tj] = (kb < L && j < I2) ? Bp[(long long)j * L + kb] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = fmaf(As[ti][k], Bs[k][tj], acc);
+    __syncthreads();
+  }
+  if (i < I1 && j < I2) C[(long long)p * I1 * I2 + (long long)j * I1 + i] = acc;
+}
+
+__global__ void k_count_nonfinite(const float* X, const uint8_t* mask, long long n,
+                                  unsigned int* count) {
+  unsigned int c = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (mask && !mask[i]) continue;
+    if (!isfinite(X[i])) ++c;
+  }
+  if (c) atomicAdd(count, c);
+}
+
+}  // namespace
+
+hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int epi,
+                                 hipStream_t s, int* n_partials) {
+  if (a.P <= 0 || a.N <= 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((a.N + TE - 1) / TE), (unsigned)((a.P + TQ - 1) / TQ));
+  if (n_partials) *n_partials = (int)(grid.x * grid.y);
+  const int key = (precision ? 4 : 0) | (pro << 1) | epi;
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_gemm_f32<0, 0>), grid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_gemm_f32<0, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_gemm_f32<1, 0>), grid, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_gemm_f32<1, 1>), grid, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_gemm_bf16x3<0, 0>), grid, dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_gemm_bf16x3<0, 1>), grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_gemm_bf16x3<1, 0>), grid, dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_gemm_bf16x3<1, 1>), grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_kron(const KronDesc& d, int P, int inverse, float* K, uint16_t* Khi,
+                             uint16_t* Klo, hipStream_t s) {
+  const long long n = (long long)P * P;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_build_kron, dim3(blocks), dim3(256), 0, s, d, P, inverse, K, Khi, Klo);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partials, int n, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L, int I2,
+                           int P, hipStream_t s) {
+  dim3 grid((I1 + 15) / 16, (I2 + 15) / 16, P);
+  hipLaunchKernelGGL(k_facewise, grid, dim3(256), 0, s, A, B, C, I1, L, I2);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* X, const uint8_t* mask, long long n,
+                                  unsigned int* count, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, X, mask, n,
+                     count);
+  return hipGetLastError();
+}
+
+}  // namespace lt

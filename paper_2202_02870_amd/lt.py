@@ -1,0 +1,311 @@
+"""Thin ctypes binding of liblt.so (include/lt.h).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of liblt.so.  PyTorch provides device memory (tensors) and the stream
+(torch.cuda.current_stream()).  Importing this module raises ImportError when
+the built library is missing; there is no fallback.
+
+Tensor convention: a tensor of logical shape (I1, I2, I3, ..., IN) is a float32
+CUDA tensor in column-major (Fortran) order, i.e. strides (1, I1, I1*I2, ...).
+`to_device` / `to_host` convert from and to NumPy arrays of that shape.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LT_LIBRARY", os.path.join(_HERE, "liblt.so"))
+if not os.path.exists(LIB_PATH):
+    raise ImportError("liblt.so not built (%s); run python -m paper_2202_02870_amd.build" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_ORDER = 8
+OK = 0
+ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1, -2, -3, -4, -5, -6
+WARN_MAXSWEEPS, WARN_NOT_CONVERGED = 1, 2
+KIND = {"dct": 0, "dft": 1, "identity": 2, "custom": 3}
+PREC = {"f32": 0, "bf16x3": 1}
+OP = {"lproduct": 0, "lsvd": 1, "svt": 2, "pga": 3}
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("kind", ctypes.c_int32 * MAX_ORDER),
+                ("dims", ctypes.c_int64 * MAX_ORDER), ("custom", ctypes.c_void_p * MAX_ORDER)]
+
+
+class SvdOpts(ctypes.Structure):
+    _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class PgaParams(ctypes.Structure):
+    _fields_ = [("mu0", ctypes.c_double), ("nu", ctypes.c_double), ("mu_bar", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("gate_until_floor", ctypes.c_int32),
+                ("fixed_mu", ctypes.c_int32), ("svd", SvdOpts)]
+
+
+class PgaReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("max_sweeps_hit", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("last_crit", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
+                ("total_slices", ctypes.c_int64), ("total_rotations", ctypes.c_int64)]
+
+
+PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other")
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5), ("dropped", ctypes.c_int64)]
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "lt_create": (ctypes.c_int, [ctypes.POINTER(_vp), _vp]),
+    "lt_destroy": (ctypes.c_int, [_vp]),
+    "lt_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "lt_last_error": (ctypes.c_char_p, [_vp]),
+    "lt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "lt_profile_begin": (ctypes.c_int, [_vp]),
+    "lt_profile_end": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
+    "lt_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Desc), ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_int]),
+    "lt_lproduct": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.POINTER(Desc), _vp, _vp,
+                                   ctypes.c_int, _vp, ctypes.c_size_t]),
+    "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                               ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_svt_prox": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
+                                   ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_complete_pga": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, ctypes.POINTER(PgaParams),
+                                       _vp, ctypes.POINTER(PgaReport), _vp, ctypes.c_size_t]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class LtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_lib.lt_status_string(status).decode(), status, msg))
+        self.status = status
+
+
+_handles = {}
+
+
+def _handle():
+    dev = torch.cuda.current_device()
+    h = _handles.get(dev)
+    if h is None:
+        h = _vp()
+        st = _lib.lt_create(ctypes.byref(h), _vp(torch.cuda.current_stream().cuda_stream))
+        if st != OK:
+            raise LtError(st, "lt_create failed")
+        _handles[dev] = h
+    _lib.lt_set_stream(h, _vp(torch.cuda.current_stream().cuda_stream))
+    return h
+
+
+def _check(h, st, allow_warn=True):
+    if st < 0 or (st > 0 and not allow_warn):
+        raise LtError(st, _lib.lt_last_error(h).decode())
+    return st
+
+
+def make_desc(shape, kinds=None):
+    """lt_desc for a tensor of shape (I1, I2, I3, ..., IN); kinds per trailing
+    mode: 'dct' | 'identity' | 'dft' | a NumPy (Ii x Ii) matrix (custom).  The
+    returned object keeps custom matrices alive."""
+    shape = tuple(int(s) for s in shape)
+    if kinds is None:
+        kinds = ("dct",) * (len(shape) - 2)
+    if len(kinds) != len(shape) - 2:
+        raise ValueError("one kind per trailing mode")
+    d = Desc()
+    d.order = len(shape)
+    keep = []
+    for i, s in enumerate(shape):
+        d.dims[i] = s
+    for i, k in enumerate(kinds):
+        if isinstance(k, np.ndarray):
+            m = np.ascontiguousarray(k, dtype=np.float64)
+            keep.append(m)
+            d.kind[i + 2] = KIND["custom"]
+            d.custom[i + 2] = m.ctypes.data
+        else:
+            d.kind[i + 2] = KIND[k]
+    d._keep = keep
+    return d
+
+
+def fortran_empty(shape, dtype=torch.float32, device="cuda"):
+    strides = []
+    acc = 1
+    for s in shape:
+        strides.append(acc)
+        acc *= int(s)
+    return torch.empty_strided(tuple(int(s) for s in shape), tuple(strides), dtype=dtype, device=device)
+
+
+def is_fortran(t):
+    acc = 1
+    for s, st in zip(t.shape, t.stride()):
+        if s > 1 and st != acc:
+            return False
+        acc *= s
+    return True
+
+
+def to_device(a, dtype=torch.float32):
+    a = np.asarray(a)
+    t = fortran_empty(a.shape, dtype=dtype)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)).to(dtype))
+    return t
+
+
+def to_host(t):
+    return t.detach().cpu().numpy()
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp()
+
+
+def _check_tensor(t, shape, dtype=torch.float32, name="tensor"):
+    if not t.is_cuda or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not is_fortran(t):
+        raise ValueError("%s must be a column-major %s CUDA tensor of shape %s" % (name, dtype, tuple(shape)))
+
+
+def workspace_bytes(shape, kinds=None, op="svt", precision="f32", shape_b=None, kinds_b=None):
+    da = make_desc(shape, kinds)
+    db = make_desc(shape_b, kinds_b if kinds_b is not None else kinds) if shape_b is not None else None
+    n = _lib.lt_workspace_bytes(ctypes.byref(da), ctypes.byref(db) if db is not None else None,
+                                OP[op], PREC[precision])
+    if n == 0:
+        raise ValueError("invalid descriptor")
+    return int(n)
+
+
+def _workspace(nbytes, ws):
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small")
+        return ws
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32"):
+    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision])
+
+
+def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None):
+    """D_tau(A) (Alg. 4).  Returns (D, rank[P] int32, sweeps[P] int32)."""
+    shape = tuple(A.shape)
+    _check_tensor(A, shape, name="A")
+    d = make_desc(shape, kinds)
+    P = int(np.prod(shape[2:])) if len(shape) > 2 else 1
+    D = out if out is not None else fortran_empty(shape)
+    _check_tensor(D, shape, name="D")
+    rank = torch.empty(P, dtype=torch.int32, device="cuda")
+    sweeps = torch.empty(P, dtype=torch.int32, device="cuda")
+    nb = workspace_bytes(shape, kinds, "svt", precision)
+    w = _workspace(nb, ws)
+    h = _handle()
+    o = svd_opts(jacobi_tol, max_sweeps, precision)
+    st = _lib.lt_svt_prox(h, ctypes.byref(d), _ptr(A), float(tau), _ptr(D), _ptr(rank), _ptr(sweeps),
+                          ctypes.byref(o), _ptr(w), nb)
+    _check(h, st)
+    return D, rank, sweeps
+
+
+def lproduct(A, B, kinds=None, precision="f32", out=None, ws=None):
+    """A *_L B (Alg. 2)."""
+    sa, sb = tuple(A.shape), tuple(B.shape)
+    _check_tensor(A, sa, name="A")
+    _check_tensor(B, sb, name="B")
+    da, db = make_desc(sa, kinds), make_desc(sb, kinds)
+    sc = (sa[0], sb[1]) + sa[2:]
+    C = out if out is not None else fortran_empty(sc)
+    _check_tensor(C, sc, name="C")
+    nb = workspace_bytes(sa, kinds, "lproduct", precision, shape_b=sb)
+    w = _workspace(nb, ws)
+    h = _handle()
+    st = _lib.lt_lproduct(h, ctypes.byref(da), _ptr(A), ctypes.byref(db), _ptr(B), _ptr(C),
+                          PREC[precision], _ptr(w), nb)
+    _check(h, st)
+    return C
+
+
+def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, precision="f32", ws=None):
+    """Economy *_L-SVD (Alg. 3): returns (U, S, V, sigma) with U: I1 x n x ...,
+    S: n x n x ..., V: I2 x n x ..., sigma: P x n (transform domain, descending)."""
+    shape = tuple(A.shape)
+    _check_tensor(A, shape, name="A")
+    d = make_desc(shape, kinds)
+    I1, I2 = shape[0], shape[1]
+    n = min(I1, I2)
+    tr = shape[2:]
+    P = int(np.prod(tr)) if tr else 1
+    U = fortran_empty((I1, n) + tr)
+    S = fortran_empty((n, n) + tr)
+    V = fortran_empty((I2, n) + tr)
+    sig = torch.empty((P, n), dtype=torch.float32, device="cuda")
+    nb = workspace_bytes(shape, kinds, "lsvd", precision)
+    w = _workspace(nb, ws)
+    h = _handle()
+    o = svd_opts(jacobi_tol, max_sweeps, precision)
+    st = _lib.lt_lsvd(h, ctypes.byref(d), _ptr(A), _ptr(U), _ptr(S), _ptr(V), _ptr(sig),
+                      1 if transform_domain else 0, ctypes.byref(o), _ptr(w), nb)
+    _check(h, st)
+    return U, S, V, sig
+
+
+def pga_params(mu0, nu=0.9, mu_bar=None, tol=0.0, max_iter=100, check_every=10,
+               gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32"):
+    if mu_bar is None:
+        mu_bar = 1e-4 * mu0
+    return PgaParams(float(mu0), float(nu), float(mu_bar), float(tol), int(max_iter), int(check_every),
+                     1 if gate_until_floor else 0, 1 if fixed_mu else 0,
+                     svd_opts(jacobi_tol, max_sweeps, precision))
+
+
+def complete_pga(M, mask, params, kinds=None, out=None, ws=None):
+    """Completion by PGA (Alg. 5).  mask: uint8 CUDA tensor (same layout).
+    Returns (X, report dict, status)."""
+    shape = tuple(M.shape)
+    _check_tensor(M, shape, name="M")
+    _check_tensor(mask, shape, dtype=torch.uint8, name="mask")
+    d = make_desc(shape, kinds)
+    prec = {v: k for k, v in PREC.items()}[params.svd.precision]
+    X = out if out is not None else fortran_empty(shape)
+    _check_tensor(X, shape, name="X")
+    nb = workspace_bytes(shape, kinds, "pga", prec)
+    w = _workspace(nb, ws)
+    h = _handle()
+    rep = PgaReport()
+    st = _lib.lt_complete_pga(h, ctypes.byref(d), _ptr(M), _ptr(mask), ctypes.byref(params), _ptr(X),
+                              ctypes.byref(rep), _ptr(w), nb)
+    _check(h, st)
+    report = dict(iters=rep.iters, converged=bool(rep.converged), max_sweeps_hit=rep.max_sweeps_hit,
+                  last_crit=rep.last_crit, total_sweeps=rep.total_sweeps, total_slices=rep.total_slices,
+                  total_rotations=rep.total_rotations)
+    return X, report, st
+
+
+def profile_begin():
+    """Start timing every kernel launch of this device's handle (HIP events on
+    the current stream)."""
+    h = _handle()
+    _check(h, _lib.lt_profile_begin(h))
+
+
+def profile_end():
+    """Stop timing; returns {class: (calls, total_ms)} and the dropped count."""
+    h = _handle()
+    pr = Profile()
+    _check(h, _lib.lt_profile_end(h, ctypes.byref(pr)))
+    return {c: (int(pr.calls[i]), float(pr.ms[i])) for i, c in enumerate(PROF_CLASSES)}, int(pr.dropped)

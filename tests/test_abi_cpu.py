@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library: it builds, loads, exports every
+symbol include/lt.h declares, and its host-only logic (descriptor validation,
+workspace sizing, status strings) behaves; no device call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lt.h")
+LIB = os.path.join(ROOT, "paper_2202_02870_amd", "liblt.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2202_02870_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_operations():
+    names = declared_functions()
+    for op in ("lt_lproduct", "lt_lsvd", "lt_svt_prox", "lt_complete_pga", "lt_workspace_bytes",
+               "lt_create", "lt_destroy"):
+        assert op in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2202_02870_amd import lt
+    assert set(declared_functions()) == set(lt.EXPORTED)
+
+
+def test_status_strings(lib):
+    lib.lt_status_string.restype = ctypes.c_char_p
+    assert lib.lt_status_string(0) == b"ok"
+    assert b"unsupported" in lib.lt_status_string(-3)
+    assert b"non-finite" in lib.lt_status_string(-4)
+
+
+def test_workspace_sizes_host_only():
+    from paper_2202_02870_amd import lt
+    n_svt = lt.workspace_bytes((144, 176, 3, 50), None, "svt")
+    n_pga = lt.workspace_bytes((144, 176, 3, 50), None, "pga")
+    nel = 144 * 176 * 150
+    assert n_svt >= 2 * nel * 4 and n_pga >= 3 * nel * 4 and n_pga > n_svt
+    assert lt.workspace_bytes((144, 176, 3, 50), None, "pga", "bf16x3") > n_pga
+    assert lt.workspace_bytes((8, 3, 5), None, "lproduct", shape_b=(3, 7, 5)) > 0
+    assert lt.workspace_bytes((16, 12, 4), None, "lsvd") > 0
+    with pytest.raises(ValueError):          # DFT slices are complex: rejected
+        lt.workspace_bytes((8, 8, 4), ("dft",), "svt")
+    with pytest.raises(ValueError):          # zero-sized mode
+        lt.workspace_bytes((8, 0, 4), None, "svt")
+
+
+def test_descriptor_layout_matches_c():
+    from paper_2202_02870_amd import lt
+    assert ctypes.sizeof(lt.Desc) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 8
+    assert ctypes.sizeof(lt.SvdOpts) == 16
+    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 16
+    assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(lt.Profile) == 5 * 8 + 5 * 8 + 8

@@ -1,0 +1,261 @@
+"""GPU parity: every operation of the HIP library against the FP64 oracle on the
+same seeded inputs (the GPU gets float32 casts).  Tolerances: FP32 paths 1e-4
+relative Frobenius error (the completion target), individual kernels tighter;
+BF16x3-transform paths 1e-2."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_2202_02870_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_02870_amd import lt as _lt
+    return _lt
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a, np.float64) - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- lproduct --
+
+@pytest.mark.parametrize("sa,sb,kinds", [
+    ((8, 3, 5), (3, 7, 5), ("dct",)),
+    ((33, 17, 3, 50), (17, 70, 3, 50), ("dct", "dct")),      # P = 150: ragged 64-row tiles
+    ((20, 9, 4, 3), (9, 11, 4, 3), ("dct", "identity")),
+    ((6, 5, 7), (5, 4, 7), ("cprod",)),                        # the c-product transform
+    ((12, 12), (12, 12), ()),                                  # order 2: one slice
+])
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-6), ("bf16x3", 1e-4)])
+def test_lproduct(lt, sa, sb, kinds, precision, tol):
+    say("lproduct", sa, sb, kinds, precision)
+    rng = np.random.default_rng(100)
+    A = rng.standard_normal(sa)
+    B = rng.standard_normal(sb)
+    mats = o.mats_for(sa, list(kinds))
+    ck = tuple(mats[i] if k == "cprod" else k for i, k in enumerate(kinds))   # custom matrix
+    C = lt.lproduct(lt.to_device(A), lt.to_device(B), ck, precision=precision)
+    ref = o.lproduct(A, B, mats)
+    assert rel(lt.to_host(C), ref) < tol
+
+
+# --------------------------------------------------------------------- SVT --
+
+SVT_SHAPES = [
+    ((32, 32, 8), ("dct",)),
+    ((17, 33, 5), ("dct",)),            # I1 < I2 (transposed working matrix), odd n
+    ((48, 40, 3, 4), ("dct", "dct")),
+    ((144, 176, 3, 2), ("dct", "dct")),
+    ((256, 256, 3), ("dct",)),          # 32 rows per lane, one LDS exchange buffer
+    ((200, 5, 4), ("dct",)),            # tall and skinny
+    ((1, 1, 5, 3), ("dct", "dct")),     # scalar tensors: soft thresholding
+    ((96, 64, 2, 3), ("identity", "dct")),
+    ((7, 9), ()),
+]
+
+
+@pytest.mark.parametrize("shape,kinds", SVT_SHAPES)
+def test_svt_prox(lt, shape, kinds):
+    say("svt", shape, kinds)
+    rng = np.random.default_rng(101)
+    r = max(1, min(shape[0], shape[1]) // 4)
+    mats = o.mats_for(shape, list(kinds))
+    # low L-rank plus noise: a spectrum with a gap, like the completion iterates
+    A = o.lproduct(rng.standard_normal((shape[0], r) + shape[2:]),
+                   rng.standard_normal((r, shape[1]) + shape[2:]), mats)
+    A = A + 0.05 * rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    for tau in (0.0, float(np.quantile(s, 0.7)), float(s.max()) * 1.01):
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds)
+        ref = o.svt(A, tau, mats)
+        err = rel(lt.to_host(D), ref) if np.linalg.norm(ref) > 0 else float(np.abs(lt.to_host(D)).max())
+        say("  tau", tau, "err", err, "sweeps", lt.to_host(sweeps).max())
+        assert err < 2e-5
+        # ranks: exact except where a singular value sits within rounding of tau
+        rk = lt.to_host(rank)
+        ref_rk = o.svt_ranks(A, tau, mats)
+        near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
+        assert np.all(np.abs(rk - ref_rk) <= near)
+
+
+def test_svt_in_place_and_deterministic(lt):
+    rng = np.random.default_rng(102)
+    A = rng.standard_normal((40, 30, 6))
+    mats = o.mats_for(A.shape, ["dct"])
+    tau = float(np.median(o.singular_values(A, mats)))
+    a1 = lt.to_device(A)
+    D1, _, _ = lt.svt_prox(a1, tau)
+    D2, _, _ = lt.svt_prox(a1, tau)
+    assert np.array_equal(lt.to_host(D1), lt.to_host(D2))      # run-to-run bitwise
+    a2 = lt.to_device(A)
+    lt.svt_prox(a2, tau, out=a2)                                 # D aliases A
+    assert np.array_equal(lt.to_host(a2), lt.to_host(D1))
+
+
+# -------------------------------------------------------------------- lsvd --
+
+@pytest.mark.parametrize("shape,kinds", [((12, 9, 5), ("dct",)), ((9, 14, 3, 2), ("dct", "dct")),
+                                         ((64, 64, 4), ("dct",))])
+def test_lsvd_invariants(lt, shape, kinds):
+    say("lsvd", shape)
+    rng = np.random.default_rng(103)
+    A = rng.standard_normal(shape)
+    mats = o.mats_for(shape, list(kinds))
+    U, S, V, sig = lt.lsvd(lt.to_device(A), kinds)
+    U, S, V, sig = (lt.to_host(x).astype(np.float64) for x in (U, S, V, sig))
+    R = o.lproduct(o.lproduct(U, S, mats), o.ttranspose(V, mats), mats)
+    assert rel(R, A) < 2e-5
+    assert np.abs(sig - o.singular_values(A, mats)).max() < 2e-5 * o.singular_values(A, mats).max()
+    for Q in (U, V):
+        Qh = o.slices(o.transform(Q, mats))
+        for q in Qh:
+            assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 2e-5
+
+
+def test_lsvd_rank_deficient_completes_basis(lt):
+    rng = np.random.default_rng(104)
+    mats = o.mats_for((10, 8, 3), ["dct"])
+    A = o.lproduct(rng.standard_normal((10, 2, 3)), rng.standard_normal((2, 8, 3)), mats)
+    U, S, V, sig = lt.lsvd(lt.to_device(A))
+    U, S, V = (lt.to_host(x).astype(np.float64) for x in (U, S, V))
+    R = o.lproduct(o.lproduct(U, S, mats), o.ttranspose(V, mats), mats)
+    assert rel(R, A) < 2e-5
+    for Q in (U, V):
+        for q in o.slices(o.transform(Q, mats)):
+            assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 1e-4
+
+
+# --------------------------------------------------------- completion (PGA) --
+
+def _run_pga(lt, p, iters, precision="f32", tol=0.0, check_every=10):
+    s = p.schedule
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=tol, max_iter=iters,
+                           check_every=check_every, fixed_mu="fixed_mu" in s, precision=precision)
+    X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, dtype=__import__("torch").uint8),
+                                 params, p.kinds)
+    return lt.to_host(X).astype(np.float64), rep, st
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_pga(p, iters, tol=0.0):
+    key = (p.name, p.shape, iters, tol)
+    if key in _ORACLE_CACHE:
+        return _ORACLE_CACHE[key]
+    _ORACLE_CACHE[key] = _oracle_pga_run(p, iters, tol)
+    return _ORACLE_CACHE[key]
+
+
+def _oracle_pga_run(p, iters, tol):
+    s = p.schedule
+    mats = o.mats_for(p.shape, list(p.kinds))
+    X, info = o.complete_pga(p.M, p.mask, mats, mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"],
+                             tol=tol, max_iter=iters, fixed_mu=s.get("fixed_mu"))
+    return X, info
+
+
+def test_pga_config0_full(lt):
+    """Order-3 32x32x8 plain completion, 100 iterations, fixed threshold."""
+    p = wl.config0()
+    say("pga config0")
+    X, rep, st = _run_pga(lt, p, 100)
+    Xo, _ = _oracle_pga(p, 100)
+    err = rel(X, Xo)
+    say("  err vs oracle", err, "rse truth", o.rse(X, p.X_true), rep)
+    assert err < 1e-4
+    assert rep["iters"] == 100 and rep["total_slices"] == 800
+    assert o.rse(X, p.X_true) < 0.05
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("bf16x3", 1e-2)])
+def test_pga_video_reduced(lt, precision, tol):
+    """Video-shaped 144x176x3x4 (the 144x176 slices of the video workload, fewer
+    frames), 200 iterations of the continuation schedule."""
+    p = wl.config1(trailing=(3, 4))
+    say("pga video reduced", precision)
+    X, rep, st = _run_pga(lt, p, 200, precision)
+    Xo, _ = _oracle_pga(p, 200)
+    err = rel(X, Xo)
+    say("  err vs oracle", err, "rse truth", o.rse(X, p.X_true), "mean sweeps",
+        rep["total_sweeps"] / rep["total_slices"])
+    assert err < tol
+
+
+def test_pga_video_full_size_first_iterations(lt):
+    """Full 144x176x3x50 video workload in the benchmark's launch configuration,
+    first 4 iterations against the oracle (the oracle's cost bounds the count)."""
+    p = wl.config1()
+    say("pga video full size, 4 iterations")
+    X, rep, st = _run_pga(lt, p, 4)
+    Xo, _ = _oracle_pga(p, 4)
+    err = rel(X, Xo)
+    say("  err vs oracle", err)
+    assert err < 1e-5
+
+
+def test_pga_stopping_rule(lt):
+    p = wl.make_problem((24, 20, 3, 2), 2, 0.6, seed=7)
+    p.schedule = dict(wl.pga_schedule_params(p.M, p.mask))
+    X, rep, st = _run_pga(lt, p, 300, tol=1e-4, check_every=1)
+    Xo, info = _oracle_pga(p, 300, tol=1e-4)
+    say("stopping rule", rep, info)
+    assert rep["converged"] and info["converged"]
+    assert abs(rep["iters"] - info["iters"]) <= 1
+    assert rel(X, Xo) < 1e-3
+
+
+def test_pga_degenerate_masks(lt):
+    import torch
+    rng = np.random.default_rng(105)
+    M = rng.standard_normal((9, 7, 4))
+    ones = np.ones(M.shape, np.uint8)
+    params = lt.pga_params(mu0=0.5, max_iter=1, fixed_mu=True)
+    X, rep, st = lt.complete_pga(lt.to_device(M), lt.to_device(ones, torch.uint8), params)
+    assert rel(lt.to_host(X), o.svt(M, 0.5, o.mats_for(M.shape, ["dct"]))) < 2e-5
+    zeros = np.zeros(M.shape, np.uint8)
+    params = lt.pga_params(mu0=0.5, max_iter=5)
+    X, rep, st = lt.complete_pga(lt.to_device(M), lt.to_device(zeros, torch.uint8), params)
+    assert np.abs(lt.to_host(X)).max() == 0.0
+    assert rep["last_crit"] == np.inf
+
+
+# ------------------------------------------------------------ error paths --
+
+def test_error_paths(lt):
+    import torch
+    A = lt.to_device(np.ones((8, 8, 4)))
+    with pytest.raises(ValueError):
+        lt.svt_prox(A, 0.1, ("dft",))                # workspace query rejects the DFT
+    M = np.ones((8, 8, 4))
+    M[1, 2, 3] = np.nan
+    mask = np.ones(M.shape, np.uint8)
+    with pytest.raises(lt.LtError) as e:
+        lt.complete_pga(lt.to_device(M), lt.to_device(mask, torch.uint8), lt.pga_params(mu0=1.0, max_iter=2))
+    assert e.value.status == lt.ERR_NONFINITE
+    mask[1, 2, 3] = 0                                 # an unobserved NaN is never used
+    X, rep, st = lt.complete_pga(lt.to_device(M), lt.to_device(mask, torch.uint8),
+                                 lt.pga_params(mu0=1.0, max_iter=2))
+    assert np.isfinite(lt.to_host(X)).all()
+    with pytest.raises(ValueError):
+        lt.svt_prox(A, 0.1, ws=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(lt.LtError) as e:              # 2048 x 2048 slices exceed the kernel
+        lt.svt_prox(lt.fortran_empty((2048, 2048)), 0.1)
+    assert e.value.status == lt.ERR_SHAPE
+    with pytest.raises(lt.LtError) as e:
+        lt.svt_prox(A, -1.0)
+    assert e.value.status == lt.ERR_ARG
