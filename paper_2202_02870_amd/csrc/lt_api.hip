@@ -595,7 +595,9 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
   lt::JacobiConfig cfg;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
-  if (n > 256) return fail(h, LT_ERR_SHAPE, "lsvd supports min(I1, I2) <= 256");
+  const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
+  if (n > 256 || mrows > 2048)
+    return fail(h, LT_ERR_SHAPE, "lsvd supports min(I1, I2) <= 256 and max(I1, I2) <= 2048");
   const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
   if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
   Carver c(ws);

@@ -8,8 +8,11 @@
 // are u_i sigma_i with sigma_i their norms (W J = U Sigma, J orthogonal).
 //
 // Layout in the workgroup: pair slot g (0 <= g < ceil(n/2)) is held by a group
-// of G lanes; each lane keeps R consecutive rows of the slot's two columns in
-// registers (FP32).  Dot products, column norms and rotation angles are FP64.
+// of G lanes; each lane keeps R rows of the slot's two columns in registers
+// (FP32), as R/4 chunks of 4 consecutive rows interleaved across the group
+// (chunk c of a column belongs to lane c mod G), so a group moves a column
+// through LDS as contiguous 16-byte pieces.  Dot products, column norms and
+// rotation angles are FP64.
 // The pair schedule is the round-robin (circle) tournament: position 0 is
 // fixed and every other column advances one position per round, so one sweep
 // of 2*ceil(n/2) - 1 rounds meets every column pair exactly once.  Columns move
@@ -28,16 +31,43 @@ namespace lt {
 
 namespace {
 
+// Sum over the G lanes of a group; every lane gets the bitwise-same result.
+// Steps within 8 lanes use DPP (quad permutations, half-row mirror), wider
+// steps use cross-lane shuffles.
+__device__ inline double dpp_add(double v, int ctrl_sel) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int plo, phi;
+  switch (ctrl_sel) {
+    case 0:   // lane ^ 1
+      plo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+      phi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:   // lane ^ 2
+      plo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+      phi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    default:  // mirror within each half row of 8 lanes (pairs quad 0 with quad 1)
+      plo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+      phi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+      break;
+  }
+  return v + __hiloint2double(phi, plo);
+}
+
 template <int G>
 __device__ inline double group_sum(double v) {
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, G);
+  v = dpp_add(v, 0);
+  if (G >= 4) v = dpp_add(v, 1);
+  if (G >= 8) v = dpp_add(v, 2);
+  if (G >= 16) v += __shfl_xor(v, 8, 64);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
 // FP64 dot product of two FP32 register columns (FP32 x FP32 products are exact
-// in FP64).  The scheduling barriers keep the compiler from converting the whole
-// column to FP64 ahead of use, which would hold 4 extra VGPRs per row.
+// in FP64).  The scheduling barriers keep the compiler from converting a whole
+// column to FP64 ahead of use.
 template <int R>
 __device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
   double d0 = 0.0, d1 = 0.0;
@@ -52,19 +82,36 @@ __device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
   return d0 + d1;
 }
 
-template <int R>
-__device__ inline void put_col(float* buf, int ldw, int idx, int row0, const float (&v)[R]) {
-  float4* p = reinterpret_cast<float4*>(buf + (size_t)idx * ldw + row0);
-#pragma unroll
-  for (int q = 0; q < R / 4; ++q) p[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+// Hardware reciprocal / reciprocal square root (FP64) refined by one Newton
+// step; the rotation is applied in FP32, so ~1e-15 relative is far below what
+// the result can resolve, and the IEEE-exact division sequence is not needed.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);   // y (1.5 - 0.5 x y^2)
 }
 
-template <int R>
-__device__ inline void get_col(const float* buf, int ldw, int idx, int row0, float (&v)[R]) {
-  const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw + row0);
+// Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
+// 4 (l + G q) .. 4 (l + G q) + 3.
+template <int G, int R>
+__device__ inline void put_col(float* buf, int ldw, int idx, int l, const float (&v)[R]) {
+  float4* p = reinterpret_cast<float4*>(buf + (size_t)idx * ldw);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q)
+    p[l + G * q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+template <int G, int R>
+__device__ inline void get_col(const float* buf, int ldw, int idx, int l, float (&v)[R]) {
+  const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    const float4 t = p[q];
+    const float4 t = p[l + G * q];
     v[4 * q] = t.x;
     v[4 * q + 1] = t.y;
     v[4 * q + 2] = t.z;
@@ -72,20 +119,19 @@ __device__ inline void get_col(const float* buf, int ldw, int idx, int row0, flo
   }
 }
 
-template <int R>
-__device__ inline void store_col(float* col, int row0, int m, bool full, const float (&v)[R],
-                                 float sc) {
-  if (full) {
+template <int G, int R>
+__device__ inline void store_col(float* col, int l, int m, const float (&v)[R], float sc) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) col[row0 + r] = v[r] * sc;
-  } else {
-    for (int r = 0; r < R; ++r)
-      if (row0 + r < m) col[row0 + r] = v[r] * sc;
+  for (int q = 0; q < R / 4; ++q) {
+    const int row = 4 * (l + G * q);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (row + j < m) col[row + j] = v[4 * q + j] * sc;
   }
 }
 
-template <int G, int R>
-__global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int s = blockIdx.x;
   const int I1 = a.I1, I2 = a.I2;
@@ -98,7 +144,6 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
   const int tid = threadIdx.x;
   const int g = tid / G, l = tid - (tid / G) * G;
   const bool active = g < npairs;
-  const int row0 = l * R;
   const float* __restrict__ A = a.src + (long long)s * a.slice_stride;
 
   float* bufA = reinterpret_cast<float*>(smem);
@@ -119,23 +164,17 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
     // so that the loads carry no control flow
     const float fa = (active && ida < n) ? 1.f : 0.f, fb = (active && idb < n) ? 1.f : 0.f;
     const int ca = ida < n ? ida : n - 1, cb = idb < n ? idb : n - 1;
-    if (trans) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int row = row0 + r;
+    for (int q = 0; q < R / 4; ++q) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 4 * (l + G * q) + j;
         const int rr = row < m ? row : m - 1;
         const float f = row < m ? 1.f : 0.f;
-        av[r] = A[(long long)rr * I1 + ca] * (fa * f);
-        bv[r] = A[(long long)rr * I1 + cb] * (fb * f);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int row = row0 + r;
-        const int rr = row < m ? row : m - 1;
-        const float f = row < m ? 1.f : 0.f;
-        av[r] = A[(long long)ca * I1 + rr] * (fa * f);
-        bv[r] = A[(long long)cb * I1 + rr] * (fb * f);
+        const long long oa = trans ? (long long)rr * I1 + ca : (long long)ca * I1 + rr;
+        const long long ob = trans ? (long long)rr * I1 + cb : (long long)cb * I1 + rr;
+        av[4 * q + j] = A[oa] * (fa * f);
+        bv[4 * q + j] = A[ob] * (fb * f);
       }
     }
   }
@@ -160,10 +199,13 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
       const double d = group_sum<G>(dot64<R>(av, bv));
       const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
       if (active && d != 0.0 && fabs(d) > tol * sqrt(pa * pb)) {
-        // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]
-        const double zeta = (pb - pa) / (2.0 * d);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
+        // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
+        // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+        const double zeta = (pb - pa) * (0.5 * rcp64(d));
+        const double z2 = fma(zeta, zeta, 1.0);
+        const double q = fabs(zeta) + z2 * rsq64(z2);
+        const double t = copysign(rcp64(q), zeta == 0.0 ? 1.0 : zeta);
+        const double c = rsq64(fma(t, t, 1.0));
         const float cf = (float)c, sf = (float)(c * t);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -183,13 +225,13 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
         int* pid = park ? idB : idA;
         if (active) {
           if (g == 0) {
-            put_col<R>(bufA, ldw, 1, row0, bv);
+            put_col<G, R>(bufA, ldw, 1, l, bv);
             if (l == 0) { nrmA[1] = nb; idA[1] = idb; }
           } else if (g < last) {
-            put_col<R>(bufA, ldw, g + 1, row0, av);
+            put_col<G, R>(bufA, ldw, g + 1, l, av);
             if (l == 0) { nrmA[g + 1] = na; idA[g + 1] = ida; }
           } else {
-            put_col<R>(pbuf, ldw, 0, row0, bv);
+            put_col<G, R>(pbuf, ldw, 0, l, bv);
             if (l == 0) { pnrm[0] = nb; pid[0] = idb; }
           }
         }
@@ -201,24 +243,24 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
             nb = na;
             idb = ida;
           }
-          get_col<R>(bufA, ldw, g, row0, av);
+          get_col<G, R>(bufA, ldw, g, l, av);
           na = nrmA[g];
           ida = idA[g];
         }
         if (nbuf == 1) __syncthreads();
         // phase 2: new bottoms
         if (active && g >= 1 && g <= last - 1) {
-          put_col<R>(bufB, ldw, g, row0, bv);
+          put_col<G, R>(bufB, ldw, g, l, bv);
           if (l == 0) { nrmB[g] = nb; idB[g] = idb; }
         }
         __syncthreads();
         if (active && g <= last - 1) {
           if (g <= last - 2) {
-            get_col<R>(bufB, ldw, g + 1, row0, bv);
+            get_col<G, R>(bufB, ldw, g + 1, l, bv);
             nb = nrmB[g + 1];
             idb = idB[g + 1];
           } else {
-            get_col<R>(pbuf, ldw, 0, row0, bv);
+            get_col<G, R>(pbuf, ldw, 0, l, bv);
             nb = pnrm[0];
             idb = pid[0];
           }
@@ -265,26 +307,25 @@ __global__ __launch_bounds__(1024) void k_jacobi(JacobiArgs a, int nbuf, int ldw
   }
   __syncthreads();
   float* out = a.bk + (long long)s * a.slice_stride;
-  const bool full = row0 + R <= m;   // every row of this lane is inside the matrix
   if (a.mode == 0) {
     int j = active ? ctl[3 + g] : 0;
     if (ka) {
       const float sc = (float)(sqrt(1.0 - a.tau / sa) / sa);
-      store_col<R>(out + (long long)j * m, row0, m, full, av, sc);
+      store_col<G, R>(out + (long long)j * m, l, m, av, sc);
       ++j;
     }
     if (kb) {
       const float sc = (float)(sqrt(1.0 - a.tau / sb) / sb);
-      store_col<R>(out + (long long)j * m, row0, m, full, bv, sc);
+      store_col<G, R>(out + (long long)j * m, l, m, bv, sc);
     }
   } else {
     // all columns, at their original column index, plus their norms
     if (ka) {
-      store_col<R>(out + (long long)ida * m, row0, m, full, av, 1.f);
+      store_col<G, R>(out + (long long)ida * m, l, m, av, 1.f);
       if (l == 0) a.sigma[(long long)s * n + ida] = sa;
     }
     if (kb) {
-      store_col<R>(out + (long long)idb * m, row0, m, full, bv, 1.f);
+      store_col<G, R>(out + (long long)idb * m, l, m, bv, 1.f);
       if (l == 0) a.sigma[(long long)s * n + idb] = sb;
     }
   }
@@ -381,14 +422,69 @@ __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
   }
 }
 
-// ---- lsvd: sort, normalise, V = W^T U / sigma, complete deficient columns ----
+// ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
 constexpr int LS_NMAX = 256;
+constexpr int LS_MMAX = 2048;
+
+__device__ inline double block_sum256(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Orthonormalise the n columns of Q (len x n, ld len) in order by classical
+// Gram-Schmidt with one re-orthogonalisation pass.  Column k is replaced by a
+// canonical basis vector (the first that survives the projection) when ok[k]
+// is false or when it is numerically dependent on the columns before it.
+__device__ void cgs2_columns(float* Q, int len, int n, const int* ok, double* v, double* c,
+                             double* red) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < n; ++k) {
+    for (int cand = -1; cand < len; ++cand) {
+      if (cand < 0 && !ok[k]) continue;
+      for (int row = tid; row < len; row += 256)
+        v[row] = cand < 0 ? (double)Q[(long long)k * len + row] : (row == cand ? 1.0 : 0.0);
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int j = tid; j < k; j += 256) {
+          double acc = 0.0;
+          for (int row = 0; row < len; ++row) acc += (double)Q[(long long)j * len + row] * v[row];
+          c[j] = acc;
+        }
+        __syncthreads();
+        for (int row = tid; row < len; row += 256) {
+          double acc = v[row];
+          for (int j = 0; j < k; ++j) acc -= c[j] * (double)Q[(long long)j * len + row];
+          v[row] = acc;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int row = tid; row < len; row += 256) part += v[row] * v[row];
+      const double nrm = sqrt(block_sum256(part, red));
+      if (nrm > 0.5) {   // existing columns start at norm ~1; candidates at 1
+        for (int row = tid; row < len; row += 256) Q[(long long)k * len + row] = (float)(v[row] / nrm);
+        __syncthreads();
+        break;
+      }
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
   __shared__ int perm[LS_NMAX];
+  __shared__ int ok[LS_NMAX];
   __shared__ double sg[LS_NMAX];
+  __shared__ double cbuf[LS_NMAX];
+  __shared__ double vbuf[LS_MMAX];
   __shared__ double red[256];
-  __shared__ int flag;
   const int s = blockIdx.x;
   const int I1 = a.I1, I2 = a.I2;
   const bool trans = I1 < I2;
@@ -410,12 +506,14 @@ __global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
   __syncthreads();
   const double smax = n > 0 ? sg[0] : 0.0;
   const double cut = smax * 1e-6;
+  for (int k = tid; k < n; k += 256) ok[k] = sg[k] > cut;
   const float* W = a.W + (long long)s * a.slice_stride;
   const float* cols = a.cols + (long long)s * a.slice_stride;
   // Uw (m x n) and Vw (n x n) live in the output factors:
   //   I1 >= I2: U = Uw (I1 x n), V = Vw (I2 x n);  I1 < I2: U = Vw (I1 x n), V = Uw (I2 x n).
   float* Uw = trans ? a.V + (long long)s * I2 * n : a.U + (long long)s * I1 * n;
   float* Vw = trans ? a.U + (long long)s * I1 * n : a.V + (long long)s * I2 * n;
+  __syncthreads();
   for (int idx = tid; idx < m * n; idx += 256) {
     const int k = idx / m, row = idx - k * m;
     const double sk = sg[k];
@@ -434,59 +532,10 @@ __global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
     Vw[(long long)k * n + j] = (float)acc;
   }
   __syncthreads();
-  // complete the columns of deficient singular values by Gram-Schmidt against
-  // the canonical basis (two passes), keeping both factors orthonormal
-  for (int pass = 0; pass < 2; ++pass) {
-    float* Q = pass == 0 ? Uw : Vw;
-    const int len = pass == 0 ? m : n;
-    for (int k = 0; k < n; ++k) {
-      if (sg[k] > cut) continue;
-      for (int cand = 0; cand < len; ++cand) {
-        for (int row = tid; row < len; row += 256) Q[(long long)k * len + row] = (row == cand) ? 1.f : 0.f;
-        __syncthreads();
-        for (int rep = 0; rep < 2; ++rep) {
-          for (int j = 0; j < n; ++j) {
-            if (j == k || (sg[j] <= cut && j > k)) continue;
-            double part = 0.0;
-            for (int row = tid; row < len; row += 256)
-              part += (double)Q[(long long)j * len + row] * (double)Q[(long long)k * len + row];
-            red[tid] = part;
-            __syncthreads();
-            for (int o = 128; o >= 1; o >>= 1) {
-              if (tid < o) red[tid] += red[tid + o];
-              __syncthreads();
-            }
-            const double c = red[0];
-            __syncthreads();
-            for (int row = tid; row < len; row += 256)
-              Q[(long long)k * len + row] -= (float)(c * (double)Q[(long long)j * len + row]);
-            __syncthreads();
-          }
-        }
-        double part = 0.0;
-        for (int row = tid; row < len; row += 256) {
-          const double v = Q[(long long)k * len + row];
-          part += v * v;
-        }
-        red[tid] = part;
-        __syncthreads();
-        for (int o = 128; o >= 1; o >>= 1) {
-          if (tid < o) red[tid] += red[tid + o];
-          __syncthreads();
-        }
-        const double nrm = sqrt(red[0]);
-        if (tid == 0) flag = nrm > 0.5;
-        __syncthreads();
-        if (flag) {
-          for (int row = tid; row < len; row += 256)
-            Q[(long long)k * len + row] = (float)((double)Q[(long long)k * len + row] / nrm);
-          __syncthreads();
-          break;
-        }
-        __syncthreads();
-      }
-    }
-  }
+  // W^T u / sigma loses orthogonality like eps sigma_max / sigma; re-orthogonalising
+  // in decreasing-sigma order changes U S V^T by at most ~eps sigma_max
+  cgs2_columns(Uw, m, n, ok, vbuf, cbuf, red);
+  cgs2_columns(Vw, n, n, ok, vbuf, cbuf, red);
   float* S = a.S + (long long)s * n * n;
   for (int idx = tid; idx < n * n; idx += 256) {
     const int k = idx / n, j = idx - k * n;
@@ -496,27 +545,35 @@ __global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
     for (int k = tid; k < n; k += 256) a.sig_out[(long long)s * n + k] = (float)sg[k];
 }
 
-template <int G, int R>
+template <int G, int R, int LB>
 hipError_t launch_one(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
   const int ldw = G * R + 4;
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<G, R>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<G, R, LB>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_jacobi<G, R>), dim3(a.nslices), dim3(c.threads), c.lds, s, a, c.nbuf, ldw);
+  hipLaunchKernelGGL((k_jacobi<G, R, LB>), dim3(a.nslices), dim3(c.threads), c.lds, s, a, c.nbuf,
+                     ldw);
   return hipGetLastError();
+}
+
+template <int G, int R>
+hipError_t launch_gr(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
+  // workgroups of <= 768 lanes run at most 3 waves per SIMD: 168 VGPRs per lane
+  if (c.threads <= 768) return launch_one<G, R, 768>(a, c, s);
+  return launch_one<G, R, 1024>(a, c, s);
 }
 
 template <int G>
 hipError_t launch_g(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
   switch (c.R) {
-    case 4: return launch_one<G, 4>(a, c, s);
-    case 8: return launch_one<G, 8>(a, c, s);
-    case 12: return launch_one<G, 12>(a, c, s);
-    case 16: return launch_one<G, 16>(a, c, s);
-    case 20: return launch_one<G, 20>(a, c, s);
-    case 24: return launch_one<G, 24>(a, c, s);
-    case 28: return launch_one<G, 28>(a, c, s);
-    case 32: return launch_one<G, 32>(a, c, s);
+    case 4: return launch_gr<G, 4>(a, c, s);
+    case 8: return launch_gr<G, 8>(a, c, s);
+    case 12: return launch_gr<G, 12>(a, c, s);
+    case 16: return launch_gr<G, 16>(a, c, s);
+    case 20: return launch_gr<G, 20>(a, c, s);
+    case 24: return launch_gr<G, 24>(a, c, s);
+    case 28: return launch_gr<G, 28>(a, c, s);
+    case 32: return launch_gr<G, 32>(a, c, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -198,14 +198,17 @@ def test_pga_video_reduced(lt, precision, tol):
 
 def test_pga_video_full_size_first_iterations(lt):
     """Full 144x176x3x50 video workload in the benchmark's launch configuration,
-    first 4 iterations against the oracle (the oracle's cost bounds the count)."""
+    first 30 iterations against the oracle (the oracle's cost bounds the count;
+    the iterate is 0 for the first ~20 iterations, while mu_k exceeds every
+    singular value, so fewer would compare zeros)."""
     p = wl.config1()
-    say("pga video full size, 4 iterations")
-    X, rep, st = _run_pga(lt, p, 4)
-    Xo, _ = _oracle_pga(p, 4)
+    say("pga video full size, 30 iterations")
+    X, rep, st = _run_pga(lt, p, 30)
+    Xo, _ = _oracle_pga(p, 30)
+    assert np.linalg.norm(Xo) > 0.1 * np.linalg.norm(p.X_true)
     err = rel(X, Xo)
-    say("  err vs oracle", err)
-    assert err < 1e-5
+    say("  err vs oracle", err, "rank-carrying iterate norm", np.linalg.norm(Xo))
+    assert err < 1e-4
 
 
 def test_pga_stopping_rule(lt):
