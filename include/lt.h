@@ -180,6 +180,53 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
                     const lt_pga_params* p, float* X, lt_pga_report* rep,
                     void* ws, size_t ws_bytes);
 
+/* ---- batched completion engine ------------------------------------------
+ * Many independent completion problems (Alg. 5 each, possibly of different
+ * shapes and orders) advance together: one tick runs one PGA iteration of every
+ * unfinished problem with a fixed sequence of six launches -- tick start,
+ * forward L of all problems (one grouped GEMM launch), the one-sided Jacobi SVT
+ * of every frontal slice of every problem (one launch over a longest-first work
+ * list; small slices of one problem are packed several per workgroup), the
+ * rank-r rebuild (one launch), inverse L with the stopping norms (one grouped
+ * launch), tick end (stopping rule evaluated on the device).  A problem's whole
+ * state (iterates, scalars, counters) lives in its own workspace, so problems
+ * can join or leave between ticks by building a new batch. */
+typedef struct {
+  const lt_desc* desc;   /* shape and transform (host, read during lt_problem_init) */
+  const float* M;        /* device, observed tensor */
+  const uint8_t* mask;   /* device, 1 byte per entry, nonzero = observed */
+  float* X;              /* device, the iterate; holds the result once finished */
+  lt_pga_params params;  /* Alg. 5 parameters; svd.precision selects the transform */
+  void* ws;              /* device workspace of lt_problem_workspace_bytes(desc, &params) */
+  size_t ws_bytes;
+} lt_problem;
+
+size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p);
+
+/* Validate, check M on the mask for NaN/Inf (synchronises), build the
+ * transforms and the schedule, zero the iterates (X^0 = X^1 = 0). */
+int lt_problem_init(lt_handle* h, const lt_problem* p);
+
+/* Synchronise the handle's stream and read a problem's progress.  done is 0
+ * while running, 1 when the stopping rule fired, 2 at max_iter.  Once done, the
+ * last iterate is in p->X (copied there by this call if needed). */
+int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int32_t* done);
+
+typedef struct lt_batch lt_batch;
+
+/* Device bytes for the batch's work tables. */
+size_t lt_batch_workspace_bytes(int n, const lt_problem* probs);
+
+/* Build the work tables of n initialised problems (all with the same
+ * svd.precision, jacobi_tol and max_sweeps).  use_graph != 0 captures one tick
+ * as a HIP graph on first use and replays it.  bws: device workspace of
+ * lt_batch_workspace_bytes bytes (caller-owned, must outlive the batch). */
+int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, size_t bws_bytes,
+                    int use_graph, lt_batch** out);
+/* Enqueue `ticks` ticks on the handle's stream (asynchronous). */
+int lt_batch_step(lt_batch* b, int ticks);
+int lt_batch_destroy(lt_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cstddef>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,7 +43,7 @@ struct ProfScope {
   int cls;
   long long idx = -1;
   ProfScope(lt_handle* hh, int c) : h(hh), cls(c) {
-    if (!h->prof_on) return;
+    if (!h || !h->prof_on) return;
     if (h->ev_next + 2 > h->events.size()) {
       ++h->dropped;
       return;
@@ -381,7 +383,155 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   return LT_OK;
 }
 
+
+// ---- batch engine: per-problem workspace ------------------------------------
+struct ProblemWs {
+  lt::ProbDev* st = nullptr;
+  TransformWs t;
+  float* Xb = nullptr;
+  float* Gh = nullptr;
+  float* Bk = nullptr;
+  int32_t* rank = nullptr;
+  int32_t* sweeps = nullptr;
+  double* betas = nullptr;
+  double* mus = nullptr;
+  double* partials = nullptr;
+  unsigned int* scratch = nullptr;
+  int n_partials = 0;
+};
+
+void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, ProblemWs* w) {
+  w->st = c.take<lt::ProbDev>(1);
+  carve_transform(c, s, prec, &w->t);
+  w->Xb = c.take<float>((size_t)s.nel);
+  w->Gh = c.take<float>((size_t)s.nel);
+  w->Bk = c.take<float>((size_t)s.nel);
+  w->rank = c.take<int32_t>((size_t)s.P);
+  w->sweeps = c.take<int32_t>((size_t)s.P);
+  w->betas = c.take<double>((size_t)max_iter);
+  w->mus = c.take<double>((size_t)max_iter);
+  w->n_partials = (int)n_partials(s);
+  w->partials = c.take<double>(2 * (size_t)w->n_partials);
+  w->scratch = c.take<unsigned int>(4);
+}
+
+int check_pga_params(lt_handle* h, const lt_pga_params* p) {
+  if (!p) return fail(h, LT_ERR_ARG, "params is NULL");
+  if (!(p->mu0 > 0) || !(p->nu > 0 && p->nu <= 1) || !(p->mu_bar > 0 && p->mu_bar <= p->mu0) ||
+      p->max_iter < 1 || !isfinite(p->mu0))
+    return fail(h, LT_ERR_ARG, "invalid PGA parameters (need mu0 > 0, 0 < nu <= 1, "
+                               "0 < mu_bar <= mu0, max_iter >= 1)");
+  return LT_OK;
+}
+
+// Alg. 5 scalars that depend on no data: beta_k = (t_{k-1} - 1) / t_k with
+// t_0 = t_1 = 1, t_{k+1} = (1 + sqrt(4 t_k^2 + 1)) / 2; mu_1 = mu0,
+// mu_{k+1} = max(nu mu_k, mu_bar) (or mu0 throughout when fixed_mu).
+void pga_schedule(const lt_pga_params* p, std::vector<double>& betas, std::vector<double>& mus) {
+  betas.resize(p->max_iter);
+  mus.resize(p->max_iter);
+  double t_prev = 1.0, t = 1.0, mu = p->mu0;
+  for (int k = 0; k < p->max_iter; ++k) {
+    betas[k] = (t_prev - 1.0) / t;
+    mus[k] = p->fixed_mu ? p->mu0 : mu;
+    t_prev = t;
+    t = (1.0 + sqrt(4.0 * t * t + 1.0)) / 2.0;
+    mu = fmax(p->nu * mu, p->mu_bar);
+  }
+}
+
+struct BatchTables {
+  std::vector<lt::ProbDev*> ptrs;
+  std::vector<lt::GemmTile> gemm;
+  std::vector<lt::SvtItem> items;
+  std::vector<lt::RebuildTile> rebuild;
+  lt::JacobiBatchConfig cfg{};
+  int prec = 0, max_sweeps = 40;
+  double tol = 1e-6;
+  size_t rebuild_slices = 0;   // total frontal slices of the batch
+};
+
+int build_tables(lt_handle* h, int n, const lt_problem* probs, BatchTables* T) {
+  if (n <= 0 || !probs) return fail(h, LT_ERR_ARG, "empty batch");
+  std::vector<Shape> shapes(n);
+  std::vector<int> ms(n), ns(n), nsub(n), qeff(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = parse(h, probs[i].desc, &shapes[i]);
+    if (rc) return rc;
+    double tol;
+    int max_sweeps, prec;
+    resolve_opts(&probs[i].params.svd, &tol, &max_sweeps, &prec);
+    if (i == 0) {
+      T->tol = tol;
+      T->max_sweeps = max_sweeps;
+      T->prec = prec;
+    } else if (tol != T->tol || max_sweeps != T->max_sweeps || prec != T->prec) {
+      return fail(h, LT_ERR_ARG, "problems of one batch must share precision and Jacobi options");
+    }
+    ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
+    ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
+  }
+  const char* env = getenv("LT_JACOBI_G");
+  if (lt::jacobi_batch_config(ms.data(), ns.data(), n, h->max_lds, env ? atoi(env) : 0, &T->cfg,
+                              nsub.data(), qeff.data()) != 0)
+    return fail(h, LT_ERR_SHAPE, "a slice shape of the batch exceeds the register-resident Jacobi kernel");
+  T->ptrs.resize(n);
+  std::vector<std::pair<double, lt::SvtItem>> costed;
+  for (int i = 0; i < n; ++i) {
+    Carver c(probs[i].ws);
+    ProblemWs w;
+    carve_problem(c, shapes[i], T->prec, probs[i].params.max_iter, &w);
+    T->ptrs[i] = w.st;
+    const Shape& s = shapes[i];
+    const int ntx = (int)((s.N + 63) / 64), nty = (int)((s.P + 63) / 64);
+    for (int ty = 0; ty < nty; ++ty)
+      for (int tx = 0; tx < ntx; ++tx) T->gemm.push_back(lt::GemmTile{i, tx, ty, ty * ntx + tx});
+    const int rounds = 2 * ((ns[i] + 1) / 2) - 1;
+    for (int s0 = 0; s0 < (int)s.P; s0 += nsub[i]) {
+      const int k = (int)(s.P - s0) < nsub[i] ? (int)(s.P - s0) : nsub[i];
+      costed.push_back({(double)rounds * qeff[i], lt::SvtItem{i, s0, k, qeff[i]}});
+    }
+    for (int sl = 0; sl < (int)s.P; ++sl)
+      for (int j0 = 0; j0 < ns[i]; j0 += 16) T->rebuild.push_back(lt::RebuildTile{i, sl, j0, 0});
+    T->rebuild_slices += (size_t)s.P;
+  }
+  // longest first, ties by problem then slice (deterministic)
+  std::stable_sort(costed.begin(), costed.end(),
+                   [](const std::pair<double, lt::SvtItem>& a, const std::pair<double, lt::SvtItem>& b) {
+                     return a.first > b.first;
+                   });
+  for (auto& c : costed) T->items.push_back(c.second);
+  return LT_OK;
+}
+
+struct BatchWs {
+  lt::ProbDev** ptrs = nullptr;
+  lt::GemmTile* gemm = nullptr;
+  lt::SvtItem* items = nullptr;
+  lt::RebuildTile* rebuild = nullptr;
+};
+
+// The item count depends on how many slices a workgroup packs (device LDS);
+// the table is sized for one item per slice so the size does not.
+void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
+  w->ptrs = c.take<lt::ProbDev*>(T.ptrs.size());
+  w->gemm = c.take<lt::GemmTile>(T.gemm.size());
+  w->items = c.take<lt::SvtItem>(T.rebuild_slices);
+  w->rebuild = c.take<lt::RebuildTile>(T.rebuild.size());
+}
+
 }  // namespace
+
+struct lt_batch {
+  lt_handle* h = nullptr;
+  int n = 0;
+  BatchTables T;
+  BatchWs w;
+  int use_graph = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -780,6 +930,259 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   }
   if (p->tol > 0 && !converged) return LT_WARN_NOT_CONVERGED;
   if (hits) return LT_WARN_MAXSWEEPS;
+  return LT_OK;
+}
+
+size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
+  Shape s;
+  if (parse(nullptr, a, &s) != LT_OK || !p || p->max_iter < 1) return 0;
+  if (p->svd.precision != LT_PREC_F32 && p->svd.precision != LT_PREC_BF16X3) return 0;
+  Carver c(nullptr);
+  ProblemWs w;
+  carve_problem(c, s, p->svd.precision, p->max_iter, &w);
+  return c.off + 256;
+}
+
+int lt_problem_init(lt_handle* h, const lt_problem* p) {
+  if (!h || !p) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, p->desc, &s);
+  if (rc) return rc;
+  if (!p->M || !p->mask || !p->X) return fail(h, LT_ERR_ARG, "M, mask or X is NULL");
+  if ((rc = check_pga_params(h, &p->params))) return rc;
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  {
+    const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+    lt::JacobiBatchConfig cfg;
+    int ns, qe;
+    if (lt::jacobi_batch_config(&m, &n, 1, h->max_lds, 0, &cfg, &ns, &qe) != 0)
+      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the register-resident Jacobi kernel",
+                  s.I1, s.I2);
+  }
+  const size_t need = lt_problem_workspace_bytes(p->desc, &p->params);
+  if ((rc = check_ws(h, p->ws, p->ws_bytes, need))) return rc;
+  Carver c(p->ws);
+  ProblemWs w;
+  carve_problem(c, s, prec, p->params.max_iter, &w);
+  hipStream_t st = h->stream;
+  HIP_TRY(h, lt::launch_fill_zero(w.scratch, 16, st));
+  HIP_TRY(h, lt::launch_count_nonfinite(p->M, p->mask, s.nel, w.scratch, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned, w.scratch, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  if (*reinterpret_cast<unsigned int*>(h->pinned) != 0)
+    return fail(h, LT_ERR_NONFINITE, "%u non-finite observed entries in M",
+                *reinterpret_cast<unsigned int*>(h->pinned));
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  std::vector<double> betas, mus;
+  pga_schedule(&p->params, betas, mus);
+  HIP_TRY(h, hipMemcpyAsync(w.betas, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(w.mus, mus.data(), mus.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(h, lt::launch_fill_zero(p->X, (size_t)s.nel * sizeof(float), st));
+  HIP_TRY(h, lt::launch_fill_zero(w.Xb, (size_t)s.nel * sizeof(float), st));
+  lt::ProbDev d{};
+  d.I1 = (int)s.I1;
+  d.I2 = (int)s.I2;
+  d.P = (int)s.P;
+  d.N = s.N;
+  d.nel = s.nel;
+  d.M = p->M;
+  d.mask = p->mask;
+  d.Xa = p->X;
+  d.Xb = w.Xb;
+  d.Gh = w.Gh;
+  d.Bk = w.Bk;
+  d.rank = w.rank;
+  d.sweeps = w.sweeps;
+  d.K = w.t.K;
+  d.Kinv = w.t.Kinv;
+  d.Khi = w.t.Khi;
+  d.Klo = w.t.Klo;
+  d.Kihi = w.t.Kihi;
+  d.Kilo = w.t.Kilo;
+  d.betas = w.betas;
+  d.mus = w.mus;
+  d.partials = w.partials;
+  d.n_partials = w.n_partials;
+  d.max_iter = p->params.max_iter;
+  d.tol = p->params.tol;
+  d.mu_bar = p->params.fixed_mu ? p->params.mu0 : p->params.mu_bar;
+  d.gate_until_floor = p->params.gate_until_floor;
+  d.enabled = 1;
+  d.crit = NAN;
+  HIP_TRY(h, hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipStreamSynchronize(st));   // host vectors and d go out of scope
+  return LT_OK;
+}
+
+int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int32_t* done) {
+  if (!h || !p) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, p->desc, &s);
+  if (rc) return rc;
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
+  Carver c(p->ws);
+  ProblemWs w;
+  carve_problem(c, s, prec, p->params.max_iter, &w);
+  lt::ProbDev d;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(&d, w.st, sizeof(d), hipMemcpyDeviceToHost));
+  if (d.done && d.parity) {
+    // the last iterate is in the second buffer: move it to X and record that
+    HIP_TRY(h, hipMemcpyAsync(p->X, w.Xb, (size_t)s.nel * sizeof(float), hipMemcpyDeviceToDevice,
+                              h->stream));
+    int zero = 0;
+    HIP_TRY(h, hipMemcpyAsync(reinterpret_cast<char*>(w.st) + offsetof(lt::ProbDev, parity), &zero,
+                              sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  if (done) *done = d.done;
+  if (rep) {
+    rep->iters = d.iter;
+    rep->converged = d.done == 1;
+    rep->max_sweeps_hit = (int32_t)d.maxsweep_hits;
+    rep->reserved = 0;
+    rep->last_crit = d.iter > 0 ? d.crit : NAN;
+    rep->total_sweeps = (int64_t)d.sweep_total;
+    rep->total_slices = (int64_t)d.iter * s.P;
+    rep->total_rotations = (int64_t)d.rot_total;
+  }
+  return LT_OK;
+}
+
+size_t lt_batch_workspace_bytes(int n, const lt_problem* probs) {
+  lt_handle tmp;
+  tmp.max_lds = 163840;
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    tmp.max_lds = lds;
+  BatchTables T;
+  if (build_tables(&tmp, n, probs, &T) != LT_OK) return 0;
+  Carver c(nullptr);
+  BatchWs w;
+  carve_batch(c, T, &w);
+  return c.off + 256;
+}
+
+int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, size_t bws_bytes,
+                    int use_graph, lt_batch** out) {
+  if (!h || !out) return LT_ERR_ARG;
+  lt_batch* b = new (std::nothrow) lt_batch();
+  if (!b) return LT_ERR_ARG;
+  b->h = h;
+  b->n = n;
+  b->use_graph = use_graph;
+  int rc = build_tables(h, n, probs, &b->T);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  Carver c0(nullptr);
+  BatchWs tmp;
+  carve_batch(c0, b->T, &tmp);
+  if ((rc = check_ws(h, bws, bws_bytes, c0.off + 256))) {
+    delete b;
+    return rc;
+  }
+  Carver c(bws);
+  carve_batch(c, b->T, &b->w);
+  hipStream_t st = h->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  hipError_t e = up(b->w.ptrs, b->T.ptrs.data(), b->T.ptrs.size() * sizeof(lt::ProbDev*));
+  if (e == hipSuccess) e = up(b->w.gemm, b->T.gemm.data(), b->T.gemm.size() * sizeof(lt::GemmTile));
+  if (e == hipSuccess) e = up(b->w.items, b->T.items.data(), b->T.items.size() * sizeof(lt::SvtItem));
+  if (e == hipSuccess)
+    e = up(b->w.rebuild, b->T.rebuild.data(), b->T.rebuild.size() * sizeof(lt::RebuildTile));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(h, LT_ERR_HIP, "batch setup failed: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return LT_OK;
+}
+
+static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
+  lt_handle* h = b->h;
+  const int n = b->n;
+  const BatchTables& T = b->T;
+  hipError_t e;
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_OTHER);
+    if ((e = lt::launch_batch_begin(b->w.ptrs, n, s)) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_FORWARD);
+    if ((e = lt::launch_gemm_grouped(b->w.ptrs, b->w.gemm, (int)T.gemm.size(), T.prec, 0, s)) != hipSuccess)
+      return e;
+  }
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
+    if ((e = lt::launch_jacobi_items(b->w.ptrs, b->w.items, (int)T.items.size(), T.cfg, T.tol,
+                                     T.max_sweeps, s)) != hipSuccess)
+      return e;
+  }
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_REBUILD);
+    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild, (int)T.rebuild.size(), s)) != hipSuccess)
+      return e;
+  }
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_INVERSE);
+    if ((e = lt::launch_gemm_grouped(b->w.ptrs, b->w.gemm, (int)T.gemm.size(), T.prec, 1, s)) != hipSuccess)
+      return e;
+  }
+  {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_OTHER);
+    if ((e = lt::launch_batch_end(b->w.ptrs, n, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int lt_batch_step(lt_batch* b, int ticks) {
+  if (!b || ticks < 0) return LT_ERR_ARG;
+  lt_handle* h = b->h;
+  if (!b->use_graph) {
+    for (int t = 0; t < ticks; ++t) {
+      hipError_t e = enqueue_tick(b, h->stream, true);
+      if (e != hipSuccess) return fail(h, LT_ERR_HIP, "tick launch failed: %s", hipGetErrorString(e));
+    }
+    return LT_OK;
+  }
+  if (!b->exec) {
+    HIP_TRY(h, hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = enqueue_tick(b, b->cap, false);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(h, LT_ERR_HIP, "tick capture failed: %s / %s", hipGetErrorString(e),
+                  hipGetErrorString(e2));
+    }
+    b->graph = g;
+    HIP_TRY(h, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  for (int t = 0; t < ticks; ++t) {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, hipGraphLaunch(b->exec, h->stream));
+  }
+  return LT_OK;
+}
+
+int lt_batch_destroy(lt_batch* b) {
+  if (!b) return LT_ERR_ARG;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
   return LT_OK;
 }
 

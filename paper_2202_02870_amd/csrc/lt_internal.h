@@ -88,6 +88,7 @@ struct JacobiArgs {
   double tau;              // SVT threshold (svt mode)
   double tol;              // rotate while |a.b| > tol |a||b|
   int max_sweeps;
+  int qeff;                // 4-row chunks per lane that carry rows (set by launch_jacobi)
   int mode;                // 0: SVT (write kept, scaled columns); 1: all columns + norms
   float* bk;               // out, slice s at bk + s * slice_stride: m x r columns (ld m)
   int32_t* rank;           // out [nslices] (svt mode: r; lsvd mode: n)
@@ -134,5 +135,59 @@ struct LsvdArgs {
   float* sig_out;          // optional [nslices][n]
 };
 hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s);
+
+// ---- batched completion engine (many problems, one tick = one PGA iteration) --
+// Device-resident state of one problem.  Static fields are written once at
+// initialisation; the dynamic fields advance on the device every tick.
+struct ProbDev {
+  int I1, I2, P, pad0;
+  long long N, nel;
+  const float* M;
+  const uint8_t* mask;
+  float* Xa;                 // iterate buffers: X^k is in Xa when parity == 0
+  float* Xb;
+  float* Gh;                 // transform-domain slices (thresholded in place)
+  float* Bk;                 // kept columns of the Jacobi SVT
+  int32_t* rank;
+  int32_t* sweeps;
+  const float* K;            // forward / inverse Kronecker transforms (FP32)
+  const float* Kinv;
+  const uint16_t *Khi, *Klo, *Kihi, *Kilo;   // bf16 splits
+  const double* betas;       // [max_iter] momentum weights beta_k (eq. (52))
+  const double* mus;         // [max_iter] thresholds mu_k
+  double* partials;          // [n_partials][2] norms of the inverse GEMM tiles
+  int n_partials;
+  int max_iter;
+  double tol, mu_bar;
+  int gate_until_floor, enabled;
+  // dynamic
+  int iter, parity, done, active;   // done: 1 converged, 2 iteration limit
+  double beta, tau, num, den, crit;
+  unsigned long long sweep_total, rot_total;
+  unsigned int maxsweep_hits, pad1;
+};
+
+struct GemmTile { int prob, tx, ty, part; };          // one 64x64 output tile
+struct SvtItem { int prob, slice0, nsub, qeff; };    // nsub same-shape slices, qeff row chunks
+struct RebuildTile { int prob, slice, j0, pad; };    // 16 working columns of one slice
+
+hipError_t launch_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles, int ntiles, int precision,
+                               int inverse, hipStream_t s);
+hipError_t launch_batch_begin(ProbDev* const* probs, int nprob, hipStream_t s);
+hipError_t launch_batch_end(ProbDev* const* probs, int nprob, hipStream_t s);
+hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+struct JacobiBatchConfig {
+  int G, RMAX, threads, nbuf;
+  size_t lds;   // per workgroup (max over items)
+};
+// Choose a kernel for a batch of slices shapes (m_i x n_i) and each item's pack
+// size; returns 0 on success.
+int jacobi_batch_config(const int* m, const int* n, int count, int max_lds, int force_G,
+                        JacobiBatchConfig* cfg, int* nsub_out, int* qeff_out);
+hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int nitems,
+                               const JacobiBatchConfig& cfg, double tol, int max_sweeps,
+                               hipStream_t s);
 
 }  // namespace lt

@@ -66,17 +66,20 @@ __device__ inline double group_sum(double v) {
 }
 
 // FP64 dot product of two FP32 register columns (FP32 x FP32 products are exact
-// in FP64).  The scheduling barriers keep the compiler from converting a whole
-// column to FP64 ahead of use.
+// in FP64), over the first qeff 4-row chunks.  The scheduling barriers keep the
+// compiler from converting a whole column to FP64 ahead of use.
 template <int R>
-__device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
+__device__ inline double dot64(const float (&x)[R], const float (&y)[R], int qeff) {
   double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-  for (int r = 0; r < R; r += 4) {
-    d0 = fma((double)x[r], (double)y[r], d0);
-    d1 = fma((double)x[r + 1], (double)y[r + 1], d1);
-    d0 = fma((double)x[r + 2], (double)y[r + 2], d0);
-    d1 = fma((double)x[r + 3], (double)y[r + 3], d1);
+  for (int q = 0; q < R / 4; ++q) {
+    if (q < qeff) {
+      const int r = 4 * q;
+      d0 = fma((double)x[r], (double)y[r], d0);
+      d1 = fma((double)x[r + 1], (double)y[r + 1], d1);
+      d0 = fma((double)x[r + 2], (double)y[r + 2], d0);
+      d1 = fma((double)x[r + 3], (double)y[r + 3], d1);
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   return d0 + d1;
@@ -97,64 +100,99 @@ __device__ inline double rsq64(double x) {
 }
 
 // Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
-// 4 (l + G q) .. 4 (l + G q) + 3.
+// 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows.
 template <int G, int R>
-__device__ inline void put_col(float* buf, int ldw, int idx, int l, const float (&v)[R]) {
+__device__ inline void put_col(float* buf, int ldw, int idx, int l, const float (&v)[R], int qeff) {
   float4* p = reinterpret_cast<float4*>(buf + (size_t)idx * ldw);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q)
-    p[l + G * q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    if (q < qeff) p[l + G * q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 
 template <int G, int R>
-__device__ inline void get_col(const float* buf, int ldw, int idx, int l, float (&v)[R]) {
+__device__ inline void get_col(const float* buf, int ldw, int idx, int l, float (&v)[R], int qeff) {
   const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    const float4 t = p[l + G * q];
-    v[4 * q] = t.x;
-    v[4 * q + 1] = t.y;
-    v[4 * q + 2] = t.z;
-    v[4 * q + 3] = t.w;
+    if (q < qeff) {
+      const float4 t = p[l + G * q];
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    }
   }
 }
 
 template <int G, int R>
-__device__ inline void store_col(float* col, int l, int m, const float (&v)[R], float sc) {
+__device__ inline void store_col(float* col, int l, int m, const float (&v)[R], float sc, int qeff) {
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    const int row = 4 * (l + G * q);
+    if (q < qeff) {
+      const int row = 4 * (l + G * q);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (row + j < m) col[row + j] = v[4 * q + j] * sc;
+      for (int j = 0; j < 4; ++j)
+        if (row + j < m) col[row + j] = v[4 * q + j] * sc;
+    }
   }
 }
 
-template <int G, int R, int LB>
-__global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int s = blockIdx.x;
-  const int I1 = a.I1, I2 = a.I2;
+// Per-slice LDS region: two (or one) exchange buffers of npairs+1 columns,
+// their norms and column ids, and the slice's control words.
+__host__ __device__ inline size_t slice_lds_bytes(int npairs, int ldw, int nbuf) {
+  const size_t nb1 = (size_t)npairs + 1;
+  size_t b = (size_t)nbuf * nb1 * ldw * sizeof(float) + (size_t)nbuf * nb1 * sizeof(double) +
+             (size_t)nbuf * nb1 * sizeof(int) + ((size_t)npairs + 4) * sizeof(int);
+  return (b + 15) & ~size_t(15);
+}
+constexpr size_t kWgCtlBytes = 16;   // workgroup-wide rotation counters
+
+// One workgroup's work: nsub slices of identical shape (I1 x I2), slice q at
+// src + q * stride; outputs likewise.
+struct Job {
+  const float* src;
+  float* out;
+  int32_t* rank;
+  int32_t* sweeps;
+  double* sigma;
+  long long stride;
+  int I1, I2, nsub, qeff, mode;
+  double tau;
+  unsigned long long* sweep_total;
+  unsigned long long* rot_total;
+  unsigned int* hits;
+};
+
+template <int G, int R>
+__device__ void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf, int ldw,
+                            unsigned char* smem) {
+  const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
   const int n = trans ? I1 : I2;
   const int npairs = (n + 1) >> 1;
   const int last = npairs - 1;
   const int nb1 = npairs + 1;   // columns per exchange buffer (index 0: parked column)
+  const int tps = npairs * G;   // lanes per slice
   const int tid = threadIdx.x;
-  const int g = tid / G, l = tid - (tid / G) * G;
-  const bool active = g < npairs;
-  const float* __restrict__ A = a.src + (long long)s * a.slice_stride;
-
-  float* bufA = reinterpret_cast<float*>(smem);
+  const int sub = tid / tps;
+  const int t2 = tid - sub * tps;
+  const int g = t2 / G, l = t2 - (t2 / G) * G;
+  const bool active = sub < jb.nsub;
+  const int subr = active ? sub : 0;   // idle lanes point at slice 0's region, never write
+  const size_t sbytes = slice_lds_bytes(npairs, ldw, nbuf);
+  int* wg_ctl = reinterpret_cast<int*>(smem);
+  unsigned char* base = smem + kWgCtlBytes + (size_t)subr * sbytes;
+  float* bufA = reinterpret_cast<float*>(base);
   float* bufB = (nbuf == 2) ? bufA + (size_t)nb1 * ldw : bufA;
   double* nrmA = reinterpret_cast<double*>(bufA + (size_t)nbuf * nb1 * ldw);
   double* nrmB = (nbuf == 2) ? nrmA + nb1 : nrmA;
   int* idA = reinterpret_cast<int*>(nrmA + (size_t)nbuf * nb1);
   int* idB = (nbuf == 2) ? idA + nb1 : idA;
-  // ctl[0], ctl[1]: rotation counters of even / odd sweeps; ctl[2]: kept total;
-  // ctl[3 + g]: per-slot output offsets
+  // ctl[0], ctl[1]: the slice's rotation counters of even / odd sweeps;
+  // ctl[2]: kept total; ctl[3 + g]: per-slot output offsets
   int* ctl = idA + (size_t)nbuf * nb1;
+  const float* __restrict__ A = jb.src + (long long)subr * jb.stride;
 
   // ---- load: slot g holds columns g (top) and 2*npairs - 1 - g (bottom) ----
   float av[R], bv[R];
@@ -170,7 +208,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
       for (int j = 0; j < 4; ++j) {
         const int row = 4 * (l + G * q) + j;
         const int rr = row < m ? row : m - 1;
-        const float f = row < m ? 1.f : 0.f;
+        const float f = (row < m && q < qeff) ? 1.f : 0.f;
         const long long oa = trans ? (long long)rr * I1 + ca : (long long)ca * I1 + rr;
         const long long ob = trans ? (long long)rr * I1 + cb : (long long)cb * I1 + rr;
         av[4 * q + j] = A[oa] * (fa * f);
@@ -178,43 +216,54 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
       }
     }
   }
-  if (tid == 0) {
+  if (active && t2 == 0) {
     ctl[0] = 0;
     ctl[1] = 0;
   }
+  if (tid == 0) {
+    wg_ctl[0] = 0;
+    wg_ctl[1] = 0;
+  }
   __syncthreads();
 
-  const double tol = a.tol;
   const int nrounds = 2 * npairs - 1;
   double na = 0.0, nb = 0.0;
   int sweep = 0;
+  int my_sweeps = 0;            // sweeps this slice needed (first sweep without rotations)
   bool converged = false;
   long long rotations = 0;
   // single-exit loop (max_sweeps >= 1): the columns stay in one register set
   for (;;) {
-    na = group_sum<G>(dot64<R>(av, av));
-    nb = group_sum<G>(dot64<R>(bv, bv));
+    na = group_sum<G>(dot64<R>(av, av, qeff));
+    nb = group_sum<G>(dot64<R>(bv, bv, qeff));
     int my_rot = 0;
     for (int round = 0; round < nrounds; ++round) {
-      const double d = group_sum<G>(dot64<R>(av, bv));
+      const double d = group_sum<G>(dot64<R>(av, bv, qeff));
       const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
-      if (active && d != 0.0 && fabs(d) > tol * sqrt(pa * pb)) {
+      // a slice that has converged stays frozen while the rest of its pack
+      // finishes, so its result does not depend on what it is packed with
+      if (active && !converged && d != 0.0 && fabs(d) > tol * sqrt(pa * pb)) {
         // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
         // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+        // every multiply-add is written as an explicit fma: the rounding must
+        // not depend on how the compiler contracts a particular instantiation
         const double zeta = (pb - pa) * (0.5 * rcp64(d));
         const double z2 = fma(zeta, zeta, 1.0);
-        const double q = fabs(zeta) + z2 * rsq64(z2);
+        const double q = fma(z2, rsq64(z2), fabs(zeta));
         const double t = copysign(rcp64(q), zeta == 0.0 ? 1.0 : zeta);
         const double c = rsq64(fma(t, t, 1.0));
         const float cf = (float)c, sf = (float)(c * t);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const float x = av[r], y = bv[r];
-          av[r] = cf * x - sf * y;
-          bv[r] = sf * x + cf * y;
+          if (r < 4 * qeff) {
+            const float x = av[r], y = bv[r];
+            const float sy = sf * y, sx = sf * x;
+            av[r] = fmaf(cf, x, -sy);
+            bv[r] = fmaf(cf, y, sx);
+          }
         }
-        na = pa - t * d;
-        nb = pb + t * d;
+        na = fma(-t, d, pa);
+        nb = fma(t, d, pb);
         my_rot += (l == 0);
       }
       if (npairs > 1) {
@@ -225,13 +274,13 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
         int* pid = park ? idB : idA;
         if (active) {
           if (g == 0) {
-            put_col<G, R>(bufA, ldw, 1, l, bv);
+            put_col<G, R>(bufA, ldw, 1, l, bv, qeff);
             if (l == 0) { nrmA[1] = nb; idA[1] = idb; }
           } else if (g < last) {
-            put_col<G, R>(bufA, ldw, g + 1, l, av);
+            put_col<G, R>(bufA, ldw, g + 1, l, av, qeff);
             if (l == 0) { nrmA[g + 1] = na; idA[g + 1] = ida; }
           } else {
-            put_col<G, R>(pbuf, ldw, 0, l, bv);
+            put_col<G, R>(pbuf, ldw, 0, l, bv, qeff);
             if (l == 0) { pnrm[0] = nb; pid[0] = idb; }
           }
         }
@@ -243,24 +292,24 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
             nb = na;
             idb = ida;
           }
-          get_col<G, R>(bufA, ldw, g, l, av);
+          get_col<G, R>(bufA, ldw, g, l, av, qeff);
           na = nrmA[g];
           ida = idA[g];
         }
         if (nbuf == 1) __syncthreads();
         // phase 2: new bottoms
         if (active && g >= 1 && g <= last - 1) {
-          put_col<G, R>(bufB, ldw, g, l, bv);
+          put_col<G, R>(bufB, ldw, g, l, bv, qeff);
           if (l == 0) { nrmB[g] = nb; idB[g] = idb; }
         }
         __syncthreads();
         if (active && g <= last - 1) {
           if (g <= last - 2) {
-            get_col<G, R>(bufB, ldw, g + 1, l, bv);
+            get_col<G, R>(bufB, ldw, g + 1, l, bv, qeff);
             nb = nrmB[g + 1];
             idb = idB[g + 1];
           } else {
-            get_col<G, R>(pbuf, ldw, 0, l, bv);
+            get_col<G, R>(pbuf, ldw, 0, l, bv, qeff);
             nb = pnrm[0];
             idb = pid[0];
           }
@@ -268,27 +317,35 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
         if (nbuf == 1) __syncthreads();
       }
     }
-    // the counter of the next sweep is cleared before the barrier that precedes
-    // any of its increments
-    if (my_rot) atomicAdd(&ctl[sweep & 1], my_rot);
+    // counters of the next sweep are cleared before the barrier that precedes
+    // any of their increments
+    if (my_rot) {
+      atomicAdd(&ctl[sweep & 1], my_rot);
+      atomicAdd(&wg_ctl[sweep & 1], my_rot);
+    }
     __syncthreads();
-    const int total = ctl[sweep & 1];
-    if (tid == 0) ctl[(sweep + 1) & 1] = 0;
+    const int mine = ctl[sweep & 1];
+    const int any = wg_ctl[sweep & 1];
+    if (active && t2 == 0) ctl[(sweep + 1) & 1] = 0;
+    if (tid == 0) wg_ctl[(sweep + 1) & 1] = 0;
     __syncthreads();
     ++sweep;
-    rotations += total;
-    converged = (total == 0);
-    if (converged || sweep >= a.max_sweeps) break;
+    if (!converged) {
+      rotations += mine;
+      my_sweeps = sweep;
+      converged = (mine == 0);
+    }
+    if (any == 0 || sweep >= max_sweeps) break;
   }
 
   // ---- output -------------------------------------------------------------
-  na = group_sum<G>(dot64<R>(av, av));
-  nb = group_sum<G>(dot64<R>(bv, bv));
+  na = group_sum<G>(dot64<R>(av, av, qeff));
+  nb = group_sum<G>(dot64<R>(bv, bv, qeff));
   const double sa = sqrt(na), sb = sqrt(nb);
   bool ka, kb;
-  if (a.mode == 0) {
-    ka = active && ida < n && sa > a.tau;
-    kb = active && idb < n && sb > a.tau;
+  if (jb.mode == 0) {
+    ka = active && ida < n && sa > jb.tau;
+    kb = active && idb < n && sb > jb.tau;
   } else {
     ka = active && ida < n;
     kb = active && idb < n;
@@ -296,7 +353,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
   __syncthreads();
   if (active && l == 0) ctl[3 + g] = (int)ka + (int)kb;
   __syncthreads();
-  if (tid == 0) {
+  if (active && t2 == 0) {
     int acc = 0;
     for (int i = 0; i < npairs; ++i) {
       const int c = ctl[3 + i];
@@ -306,36 +363,90 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
     ctl[2] = acc;
   }
   __syncthreads();
-  float* out = a.bk + (long long)s * a.slice_stride;
-  if (a.mode == 0) {
+  float* out = jb.out + (long long)subr * jb.stride;
+  if (jb.mode == 0) {
     int j = active ? ctl[3 + g] : 0;
     if (ka) {
-      const float sc = (float)(sqrt(1.0 - a.tau / sa) / sa);
-      store_col<G, R>(out + (long long)j * m, l, m, av, sc);
+      const float sc = (float)(sqrt(1.0 - jb.tau / sa) / sa);
+      store_col<G, R>(out + (long long)j * m, l, m, av, sc, qeff);
       ++j;
     }
     if (kb) {
-      const float sc = (float)(sqrt(1.0 - a.tau / sb) / sb);
-      store_col<G, R>(out + (long long)j * m, l, m, bv, sc);
+      const float sc = (float)(sqrt(1.0 - jb.tau / sb) / sb);
+      store_col<G, R>(out + (long long)j * m, l, m, bv, sc, qeff);
     }
   } else {
     // all columns, at their original column index, plus their norms
     if (ka) {
-      store_col<G, R>(out + (long long)ida * m, l, m, av, 1.f);
-      if (l == 0) a.sigma[(long long)s * n + ida] = sa;
+      store_col<G, R>(out + (long long)ida * m, l, m, av, 1.f, qeff);
+      if (l == 0) jb.sigma[(long long)subr * n + ida] = sa;
     }
     if (kb) {
-      store_col<G, R>(out + (long long)idb * m, l, m, bv, 1.f);
-      if (l == 0) a.sigma[(long long)s * n + idb] = sb;
+      store_col<G, R>(out + (long long)idb * m, l, m, bv, 1.f, qeff);
+      if (l == 0) jb.sigma[(long long)subr * n + idb] = sb;
     }
   }
-  if (tid == 0) {
-    if (a.rank) a.rank[s] = ctl[2];
-    if (a.sweeps) a.sweeps[s] = sweep;
-    if (a.sweep_total) atomicAdd(a.sweep_total, (unsigned long long)sweep);
-    if (a.rot_total) atomicAdd(a.rot_total, (unsigned long long)rotations);
-    if (!converged && a.maxsweep_hits) atomicAdd(a.maxsweep_hits, 1u);
+  if (active && t2 == 0) {
+    if (jb.rank) jb.rank[sub] = ctl[2];
+    if (jb.sweeps) jb.sweeps[sub] = my_sweeps;
+    if (jb.sweep_total) atomicAdd(jb.sweep_total, (unsigned long long)my_sweeps);
+    if (jb.rot_total) atomicAdd(jb.rot_total, (unsigned long long)rotations);
+    if (!converged && jb.hits) atomicAdd(jb.hits, 1u);
   }
+}
+
+// One slice per workgroup (single problem).
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int s = blockIdx.x;
+  Job jb;
+  jb.src = a.src + (long long)s * a.slice_stride;
+  jb.out = a.bk + (long long)s * a.slice_stride;
+  jb.rank = a.rank ? a.rank + s : nullptr;
+  jb.sweeps = a.sweeps ? a.sweeps + s : nullptr;
+  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  jb.sigma = a.sigma ? a.sigma + (long long)s * n : nullptr;
+  jb.stride = a.slice_stride;
+  jb.I1 = a.I1;
+  jb.I2 = a.I2;
+  jb.nsub = 1;
+  jb.qeff = a.qeff;   // a run-time bound keeps the register allocation tighter
+  jb.mode = a.mode;
+  jb.tau = a.tau;
+  jb.sweep_total = a.sweep_total;
+  jb.rot_total = a.rot_total;
+  jb.hits = a.maxsweep_hits;
+  jacobi_body<G, R>(jb, a.tol, a.max_sweeps, nbuf, ldw, smem);
+}
+
+// Batch: one workgroup per item (nsub same-shape slices of one problem),
+// items ordered longest-first by the host; the threshold is the problem's
+// current mu_k from its device state.
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, const SvtItem* items,
+                                                    double tol, int max_sweeps, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const SvtItem it = items[blockIdx.x];
+  ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  Job jb;
+  jb.src = pd->Gh + (long long)it.slice0 * pd->N;
+  jb.out = pd->Bk + (long long)it.slice0 * pd->N;
+  jb.rank = pd->rank + it.slice0;
+  jb.sweeps = pd->sweeps + it.slice0;
+  jb.sigma = nullptr;
+  jb.stride = pd->N;
+  jb.I1 = pd->I1;
+  jb.I2 = pd->I2;
+  jb.nsub = it.nsub;
+  jb.qeff = it.qeff;
+  jb.mode = 0;
+  jb.tau = pd->tau;
+  jb.sweep_total = &pd->sweep_total;
+  jb.rot_total = &pd->rot_total;
+  jb.hits = &pd->maxsweep_hits;
+  jacobi_body<G, R>(jb, tol, max_sweeps, nbuf, ldw, smem);
 }
 
 // ---- rebuild D_W = Bk (Bk^T W) ------------------------------------------------
@@ -347,23 +458,18 @@ __device__ inline float w_at(const float* W, bool trans, int I1, int row, int co
   return trans ? W[(long long)row * I1 + col] : W[(long long)col * I1 + row];
 }
 
-__global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
+// Working columns j0 .. j0+15 of one slice: Z = Bk^T W(:, j0..) (r x 16), then
+// D_W(:, j0..) = Bk Z.  W and D may alias: the tile is read in full before any
+// of it is written, and no other workgroup touches these entries.
+__device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0) {
   __shared__ float Ws[RB_TK][RB_TN + 1];
   __shared__ float Bs[RB_TK][RB_RMAX + 1];
   __shared__ float Z[RB_RMAX][RB_TN + 1];
-  const int s = blockIdx.y;
-  const int I1 = a.I1, I2 = a.I2;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
   const int n = trans ? I1 : I2;
-  const int j0 = blockIdx.x * RB_TN;
-  if (j0 >= n) return;
-  const int r = a.rank[s];
   const int nq = (r + 15) >> 4;
   const int rpad = nq << 4;
-  const float* W = a.W + (long long)s * a.slice_stride;
-  float* D = a.D + (long long)s * a.slice_stride;
-  const float* Bk = a.bk + (long long)s * a.slice_stride;
   const int tid = threadIdx.x;
   const int jj = tid & 15, hi = tid >> 4;
 
@@ -420,6 +526,23 @@ __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
+  const int s = blockIdx.y;
+  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  const int j0 = blockIdx.x * RB_TN;
+  if (j0 >= n) return;
+  const long long off = (long long)s * a.slice_stride;
+  rebuild_body(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0);
+}
+
+__global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles) {
+  const RebuildTile t = tiles[blockIdx.x];
+  const ProbDev* pd = probs[t.prob];
+  if (!pd->active) return;
+  const long long off = (long long)t.slice * pd->N;
+  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
@@ -578,10 +701,41 @@ hipError_t launch_g(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
   }
 }
 
+template <int G, int R, int LB>
+hipError_t launch_items_one(ProbDev* const* probs, const SvtItem* items, int nitems,
+                            const JacobiBatchConfig& c, double tol, int max_sweeps, hipStream_t s) {
+  const int ldw = G * R + 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_items<G, R, LB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_jacobi_items<G, R, LB>), dim3(nitems), dim3(c.threads), c.lds, s, probs,
+                     items, tol, max_sweeps, c.nbuf, ldw);
+  return hipGetLastError();
+}
+
+template <int G>
+hipError_t launch_items_g(ProbDev* const* probs, const SvtItem* items, int nitems,
+                          const JacobiBatchConfig& c, double tol, int max_sweeps, hipStream_t s) {
+#define LT_ITEMS_CASE(RR)                                                                  \
+  case RR:                                                                                 \
+    return c.threads <= 768 ? launch_items_one<G, RR, 768>(probs, items, nitems, c, tol, max_sweeps, s) \
+                            : launch_items_one<G, RR, 1024>(probs, items, nitems, c, tol, max_sweeps, s);
+  switch (c.RMAX) {
+    LT_ITEMS_CASE(4)
+    LT_ITEMS_CASE(8)
+    LT_ITEMS_CASE(12)
+    LT_ITEMS_CASE(16)
+    LT_ITEMS_CASE(20)
+    LT_ITEMS_CASE(24)
+    LT_ITEMS_CASE(28)
+    LT_ITEMS_CASE(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef LT_ITEMS_CASE
+}
+
 size_t jacobi_lds_bytes(int npairs, int ldw, int nbuf) {
-  const size_t nb1 = (size_t)npairs + 1;
-  return (size_t)nbuf * nb1 * ldw * sizeof(float) + (size_t)nbuf * nb1 * sizeof(double) +
-         (size_t)nbuf * nb1 * sizeof(int) + ((size_t)npairs + 4) * sizeof(int);
+  return kWgCtlBytes + slice_lds_bytes(npairs, ldw, nbuf);
 }
 
 }  // namespace
@@ -622,8 +776,10 @@ int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G
   return 0;
 }
 
-hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
-  if (a.nslices <= 0) return hipSuccess;
+hipError_t launch_jacobi(const JacobiArgs& a0, const JacobiConfig& c, hipStream_t s) {
+  if (a0.nslices <= 0) return hipSuccess;
+  JacobiArgs a = a0;
+  a.qeff = c.R / 4;
   switch (c.G) {
     case 4: return launch_g<4>(a, c, s);
     case 8: return launch_g<8>(a, c, s);
@@ -632,6 +788,77 @@ hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& c, hipStream_t
     case 64: return launch_g<64>(a, c, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+int jacobi_batch_config(const int* m, const int* n, int count, int max_lds, int force_G,
+                        JacobiBatchConfig* cfg, int* nsub_out, int* qeff_out) {
+  if (count <= 0) return -1;
+  const int Gs[5] = {8, 16, 4, 32, 64};
+  for (int gi = 0; gi < 5; ++gi) {
+    const int G = Gs[gi];
+    if (force_G && G != force_G) continue;
+    int RMAX = 0, T = 0;
+    bool ok = true;
+    for (int i = 0; i < count && ok; ++i) {
+      if (m[i] < n[i] || n[i] < 1 || n[i] > RB_RMAX) { ok = false; break; }
+      const int npairs = (n[i] + 1) / 2;
+      int R = (m[i] + G - 1) / G;
+      R = ((R + 3) / 4) * 4;
+      const int t = ((npairs * G + 63) / 64) * 64;
+      if (R > 32 || t > 1024) ok = false;
+      RMAX = R > RMAX ? R : RMAX;
+      T = t > T ? t : T;
+    }
+    if (!ok) continue;
+    const int ldw = G * RMAX + 4;
+    int nbuf = 2;
+    for (int i = 0; i < count; ++i)
+      if (jacobi_lds_bytes((n[i] + 1) / 2, ldw, 2) > (size_t)max_lds) nbuf = 1;
+    size_t lds = 0;
+    for (int i = 0; i < count && ok; ++i) {
+      const int npairs = (n[i] + 1) / 2;
+      const size_t sb = slice_lds_bytes(npairs, ldw, nbuf);
+      if (kWgCtlBytes + sb > (size_t)max_lds) { ok = false; break; }
+      int nsub = T / (npairs * G);
+      const int fit = (int)(((size_t)max_lds - kWgCtlBytes) / sb);
+      if (nsub > fit) nsub = fit;
+      if (nsub < 1) nsub = 1;
+      int R = (m[i] + G - 1) / G;
+      R = ((R + 3) / 4) * 4;
+      nsub_out[i] = nsub;
+      qeff_out[i] = R / 4;
+      const size_t need = kWgCtlBytes + (size_t)nsub * sb;
+      lds = need > lds ? need : lds;
+    }
+    if (!ok) continue;
+    cfg->G = G;
+    cfg->RMAX = RMAX;
+    cfg->threads = T;
+    cfg->nbuf = nbuf;
+    cfg->lds = lds;
+    return 0;
+  }
+  return -1;
+}
+
+hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int nitems,
+                               const JacobiBatchConfig& c, double tol, int max_sweeps,
+                               hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  switch (c.G) {
+    case 4: return launch_items_g<4>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 8: return launch_items_g<8>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 16: return launch_items_g<16>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 32: return launch_items_g<32>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 64: return launch_items_g<64>(probs, items, nitems, c, tol, max_sweeps, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rebuild_tiles, dim3(ntiles), dim3(256), 0, s, probs, tiles);
+  return hipGetLastError();
 }
 
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {

@@ -62,12 +62,12 @@ __device__ inline void store_result(const GemmArgs& a, long long g, float o, dou
 // Operand lane layout of the 16x16x4 instruction: A[i][k] at lane i + 16k,
 // B[k][j] at lane j + 16k, D[i][j] in element i%4 of lane j + 16(i/4).
 template <int PRO, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
+__device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
   __shared__ float Ks[TQ][TPK + 1];
   __shared__ float Bs[TPK][TE + 4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const long long e0 = (long long)blockIdx.x * TE;
-  const int q0 = blockIdx.y * TQ;
+  const long long e0 = (long long)tx * TE;
+  const int q0 = ty * TQ;
   const int P = a.P;
   const long long N = a.N;
   f32x4 acc[4];
@@ -112,11 +112,16 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
   if (EPI == EPI_PGA) {
     block_sum2(s1, s2);
     if (threadIdx.x == 0) {
-      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-      a.partials[2 * b] = s1;
-      a.partials[2 * b + 1] = s2;
+      part[0] = s1;
+      part[1] = s2;
     }
   }
+}
+
+template <int PRO, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
+  gemm_f32_tile<PRO, EPI>(a, blockIdx.x, blockIdx.y,
+                          a.partials + 2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // BF16 MFMA (v_mfma_f32_16x16x32_bf16) on hi/lo splits: K ~ Kh + Kl and
@@ -124,15 +129,15 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 // Lane layout of the 16x16x32 instruction: A[i][8c..8c+7] at lane i + 16c,
 // B[8c..8c+7][j] at lane j + 16c, D as for the FP32 instruction.
 template <int PRO, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs a) {
+__device__ void gemm_bf16x3_tile(const GemmArgs& a, int tx, int ty, double* part) {
   constexpr int KP = TPK + 8;  // row pitch in halves (80 B: keeps 16-B alignment)
   __shared__ __attribute__((aligned(16))) uint16_t Kh[TQ][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Kl[TQ][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[TE][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Bl[TE][KP];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const long long e0 = (long long)blockIdx.x * TE;
-  const int q0 = blockIdx.y * TQ;
+  const long long e0 = (long long)tx * TE;
+  const int q0 = ty * TQ;
   const int P = a.P;
   const long long N = a.N;
   f32x4 acc[4];
@@ -188,11 +193,96 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs a) {
   if (EPI == EPI_PGA) {
     block_sum2(s1, s2);
     if (threadIdx.x == 0) {
-      const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-      a.partials[2 * b] = s1;
-      a.partials[2 * b + 1] = s2;
+      part[0] = s1;
+      part[1] = s2;
     }
   }
+}
+
+template <int PRO, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(GemmArgs a) {
+  gemm_bf16x3_tile<PRO, EPI>(a, blockIdx.x, blockIdx.y,
+                             a.partials + 2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Grouped transform GEMMs of a batch: one workgroup per (problem, tile).  The
+// forward pass builds G from the problem's current iterates (parity) and writes
+// the transform-domain slices; the inverse pass writes X^{k+1} over X^{k-1} and
+// the per-tile stopping norms.
+template <int PREC, int INV>
+__global__ __launch_bounds__(256) void k_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles) {
+  const GemmTile t = tiles[blockIdx.x];
+  const ProbDev* pd = probs[t.prob];
+  if (!pd->active) return;
+  GemmArgs a{};
+  a.P = pd->P;
+  a.N = pd->N;
+  a.K = INV ? pd->Kinv : pd->K;
+  a.Khi = INV ? pd->Kihi : pd->Khi;
+  a.Klo = INV ? pd->Kilo : pd->Klo;
+  float* cur = pd->parity ? pd->Xb : pd->Xa;
+  float* prev = pd->parity ? pd->Xa : pd->Xb;
+  a.X = cur;
+  a.Xp = prev;
+  a.beta = (float)pd->beta;
+  if constexpr (!INV) {
+    a.M = pd->M;
+    a.mask = pd->mask;
+    a.out = pd->Gh;
+    if constexpr (PREC != 0) gemm_bf16x3_tile<PRO_PGA, EPI_PLAIN>(a, t.tx, t.ty, nullptr);
+    else gemm_f32_tile<PRO_PGA, EPI_PLAIN>(a, t.tx, t.ty, nullptr);
+  } else {
+    a.B = pd->Gh;
+    a.out = prev;
+    double* part = pd->partials + 2 * (long long)t.part;
+    if constexpr (PREC != 0) gemm_bf16x3_tile<PRO_PLAIN, EPI_PGA>(a, t.tx, t.ty, part);
+    else gemm_f32_tile<PRO_PLAIN, EPI_PGA>(a, t.tx, t.ty, part);
+  }
+}
+
+// Start of a tick: problems that are enabled and not finished take part and
+// load this iteration's scalars (Alg. 5: beta_k of eq. (52), threshold mu_k).
+__global__ void k_batch_begin(ProbDev* const* probs, int nprob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nprob) return;
+  ProbDev* p = probs[i];
+  const int act = p->enabled && !p->done && p->iter < p->max_iter;
+  p->active = act;
+  if (act) {
+    p->beta = p->betas[p->iter];
+    p->tau = p->mus[p->iter];
+  }
+}
+
+// End of a tick: stopping ratio ||Y - X^{k+1}|| / ||X^{k+1}|| from the tile
+// partials (fixed summation order), iteration count, iterate parity, and the
+// stopping rule (gated until mu_k reaches mu_bar when requested).
+__global__ __launch_bounds__(256) void k_batch_end(ProbDev* const* probs, int nprob) {
+  ProbDev* p = probs[blockIdx.x];
+  if (!p->active) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < p->n_partials; i += 256) {
+    s1 += p->partials[2 * i];
+    s2 += p->partials[2 * i + 1];
+  }
+  block_sum2(s1, s2);
+  if (threadIdx.x == 0) {
+    const double crit = s2 > 0.0 ? sqrt(s1) / sqrt(s2) : INFINITY;
+    const bool at_floor = p->mus[p->iter] <= p->mu_bar;
+    p->num = s1;
+    p->den = s2;
+    p->crit = crit;
+    p->iter += 1;
+    p->parity ^= 1;
+    if (p->tol > 0.0 && crit <= p->tol && (at_floor || !p->gate_until_floor)) p->done = 1;
+    else if (p->iter >= p->max_iter) p->done = 2;
+  }
+}
+
+__global__ void k_fill_zero(uint32_t* p, long long nwords) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 // Entry (r, c) of the mode matrix: orthonormal DCT-II
@@ -282,6 +372,40 @@ __global__ void k_count_nonfinite(const float* X, const uint8_t* mask, long long
 }
 
 }  // namespace
+
+hipError_t launch_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles, int ntiles, int precision,
+                               int inverse, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const int key = (precision ? 2 : 0) | (inverse ? 1 : 0);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_gemm_grouped<0, 0>), dim3(ntiles), dim3(256), 0, s, probs, tiles); break;
+    case 1: hipLaunchKernelGGL((k_gemm_grouped<0, 1>), dim3(ntiles), dim3(256), 0, s, probs, tiles); break;
+    case 2: hipLaunchKernelGGL((k_gemm_grouped<1, 0>), dim3(ntiles), dim3(256), 0, s, probs, tiles); break;
+    default: hipLaunchKernelGGL((k_gemm_grouped<1, 1>), dim3(ntiles), dim3(256), 0, s, probs, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(ProbDev* const* probs, int nprob, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_begin, dim3((nprob + 63) / 64), dim3(64), 0, s, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_end(ProbDev* const* probs, int nprob, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_end, dim3(nprob), dim3(256), 0, s, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long nw = (long long)(bytes / 4);
+  if (nw <= 0) return hipSuccess;
+  long long blocks = (nw + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, nw);
+  return hipGetLastError();
+}
 
 hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int epi,
                                  hipStream_t s, int* n_partials) {

@@ -54,6 +54,12 @@ class PgaReport(ctypes.Structure):
                 ("total_slices", ctypes.c_int64), ("total_rotations", ctypes.c_int64)]
 
 
+class ProblemC(ctypes.Structure):
+    _fields_ = [("desc", ctypes.POINTER(Desc)), ("M", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("params", PgaParams), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other")
 
 
@@ -79,6 +85,15 @@ _sig = {
                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_complete_pga": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, ctypes.POINTER(PgaParams),
                                        _vp, ctypes.POINTER(PgaReport), _vp, ctypes.c_size_t]),
+    "lt_problem_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Desc), ctypes.POINTER(PgaParams)]),
+    "lt_problem_init": (ctypes.c_int, [_vp, ctypes.POINTER(ProblemC)]),
+    "lt_problem_status": (ctypes.c_int, [_vp, ctypes.POINTER(ProblemC), ctypes.POINTER(PgaReport),
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "lt_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(ProblemC)]),
+    "lt_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ProblemC), _vp, ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.POINTER(_vp)]),
+    "lt_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lt_batch_destroy": (ctypes.c_int, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -309,3 +324,88 @@ def profile_end():
     pr = Profile()
     _check(h, _lib.lt_profile_end(h, ctypes.byref(pr)))
     return {c: (int(pr.calls[i]), float(pr.ms[i])) for i, c in enumerate(PROF_CLASSES)}, int(pr.dropped)
+
+
+# ---------------------------------------------------------------------------
+# Batched completion engine
+# ---------------------------------------------------------------------------
+
+
+def _report(rep):
+    return dict(iters=rep.iters, converged=bool(rep.converged), max_sweeps_hit=rep.max_sweeps_hit,
+                last_crit=rep.last_crit, total_sweeps=rep.total_sweeps, total_slices=rep.total_slices,
+                total_rotations=rep.total_rotations)
+
+
+class Problem:
+    """One completion problem of the batch engine: owns its device iterate,
+    workspace and descriptor.  M and mask are column-major CUDA tensors (float32,
+    uint8) that must stay alive while the problem runs."""
+
+    def __init__(self, M, mask, params, kinds=None, out=None):
+        shape = tuple(M.shape)
+        _check_tensor(M, shape, name="M")
+        _check_tensor(mask, shape, dtype=torch.uint8, name="mask")
+        self.shape = shape
+        self.desc = make_desc(shape, kinds)
+        self.params = params
+        self.M, self.mask = M, mask
+        self.X = out if out is not None else fortran_empty(shape)
+        _check_tensor(self.X, shape, name="X")
+        nb = _lib.lt_problem_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(params))
+        if nb == 0:
+            raise ValueError("invalid problem")
+        self.ws_bytes = int(nb)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.c = ProblemC(ctypes.pointer(self.desc), _ptr(M), _ptr(mask), _ptr(self.X), params,
+                          _ptr(self.ws), self.ws_bytes)
+        h = _handle()
+        _check(h, _lib.lt_problem_init(h, ctypes.byref(self.c)))
+
+    @property
+    def nbytes(self):
+        """Device bytes this problem holds (M, mask, X and workspace)."""
+        n = int(np.prod(self.shape))
+        return 4 * n + n + 4 * n + self.ws_bytes
+
+    def status(self):
+        """(report, done) -- synchronises; once done the result is in self.X."""
+        h = _handle()
+        rep = PgaReport()
+        done = ctypes.c_int32()
+        _check(h, _lib.lt_problem_status(h, ctypes.byref(self.c), ctypes.byref(rep), ctypes.byref(done)))
+        return _report(rep), int(done.value)
+
+
+class Batch:
+    """Work tables of a set of initialised problems; step(k) enqueues k ticks
+    (one PGA iteration of every unfinished problem per tick)."""
+
+    def __init__(self, problems, use_graph=True):
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (ProblemC * n)(*[p.c for p in self.problems])
+        self._arr = arr
+        nb = _lib.lt_batch_workspace_bytes(n, arr)
+        if nb == 0:
+            raise ValueError("invalid batch")
+        self.ws = torch.empty(int(nb), dtype=torch.uint8, device="cuda")
+        h = _handle()
+        self.b = _vp()
+        _check(h, _lib.lt_batch_create(h, n, arr, _ptr(self.ws), int(nb), 1 if use_graph else 0,
+                                       ctypes.byref(self.b)))
+
+    def step(self, ticks=1):
+        h = _handle()
+        _check(h, _lib.lt_batch_step(self.b, int(ticks)))
+
+    def close(self):
+        if self.b:
+            _lib.lt_batch_destroy(self.b)
+            self.b = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
