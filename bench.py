@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=30,
                     help="oracle iterations timed on the host (bounded CPU sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanes", default="auto",
+                    help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -195,8 +197,13 @@ def bench_mix(args, torch, lt, wl):
         M = lt.to_device(p.M)
         mask = lt.to_device(p.mask, dtype=torch.uint8)
         dev.append((p, M, mask, params))
+    lanes, tune_ms = args.lanes, None
+    if lanes == "auto":
+        from paper_2202_02870_amd import autotune
+        lanes, tune_ms = autotune.tune([p.shape for p in probs])
+    lanes = int(lanes)
     gps = [lt.Problem(M, mask, params, p.kinds) for (p, M, mask, params) in dev]
-    batch = lt.Batch(gps, use_graph=True)
+    batch = lt.Batch(gps, use_graph=True, jacobi_lanes=lanes)
     if args.warmup > 0:
         batch.step(args.warmup)
     torch.cuda.synchronize()
@@ -209,7 +216,7 @@ def bench_mix(args, torch, lt, wl):
     batch.close()
     # eager ticks with per-kernel events (same work, no graph) for the kernel split
     gps2 = [lt.Problem(M, mask, params, p.kinds) for (p, M, mask, params) in dev]
-    b2 = lt.Batch(gps2, use_graph=False)
+    b2 = lt.Batch(gps2, use_graph=False, jacobi_lanes=lanes)
     b2.step(args.warmup)
     lt.profile_begin()
     b2.step(min(args.steps, 20))
@@ -247,6 +254,9 @@ def bench_mix(args, torch, lt, wl):
         "batched_over_per_request": round(value * total_slices / per_req_slices, 3),
         "mean_sweeps": round(sum(r["total_sweeps"] for r in reps) / max(sum(r["total_slices"] for r in reps), 1), 3),
         "kernel_ms_20_eager_ticks": {k2: round(v[1], 3) for k2, v in prof.items()},
+        "jacobi_lanes": lanes if lanes else "built-in",
+        "autotune_jacobi_ms_per_tick": ({str(g): round(t, 4) for g, t in sorted(tune_ms.items())}
+                                        if tune_ms else None),
     }
     print(json.dumps(line), flush=True)
 

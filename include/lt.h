@@ -219,10 +219,13 @@ size_t lt_batch_workspace_bytes(int n, const lt_problem* probs);
 
 /* Build the work tables of n initialised problems (all with the same
  * svd.precision, jacobi_tol and max_sweeps).  use_graph != 0 captures one tick
- * as a HIP graph on first use and replays it.  bws: device workspace of
- * lt_batch_workspace_bytes bytes (caller-owned, must outlive the batch). */
+ * as a HIP graph on first use and replays it.  jacobi_lanes selects the lanes
+ * per column pair of the Jacobi kernel (4, 8, 16, 32 or 64; 0 = built-in
+ * choice), e.g. from an autotuning run; LT_ERR_SHAPE if it cannot hold every
+ * slice of the batch.  bws: device workspace of lt_batch_workspace_bytes bytes
+ * (caller-owned, must outlive the batch). */
 int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, size_t bws_bytes,
-                    int use_graph, lt_batch** out);
+                    int use_graph, int jacobi_lanes, lt_batch** out);
 /* Enqueue `ticks` ticks on the handle's stream (asynchronous). */
 int lt_batch_step(lt_batch* b, int ticks);
 int lt_batch_destroy(lt_batch* b);

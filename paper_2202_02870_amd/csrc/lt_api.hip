@@ -451,7 +451,7 @@ struct BatchTables {
   size_t rebuild_slices = 0;   // total frontal slices of the batch
 };
 
-int build_tables(lt_handle* h, int n, const lt_problem* probs, BatchTables* T) {
+int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, BatchTables* T) {
   if (n <= 0 || !probs) return fail(h, LT_ERR_ARG, "empty batch");
   std::vector<Shape> shapes(n);
   std::vector<int> ms(n), ns(n), nsub(n), qeff(n);
@@ -471,8 +471,11 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, BatchTables* T) {
     ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
     ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
   }
-  const char* env = getenv("LT_JACOBI_G");
-  if (lt::jacobi_batch_config(ms.data(), ns.data(), n, h->max_lds, env ? atoi(env) : 0, &T->cfg,
+  if (force_G == 0) {
+    const char* env = getenv("LT_JACOBI_G");
+    force_G = env ? atoi(env) : 0;
+  }
+  if (lt::jacobi_batch_config(ms.data(), ns.data(), n, h->max_lds, force_G, &T->cfg,
                               nsub.data(), qeff.data()) != 0)
     return fail(h, LT_ERR_SHAPE, "a slice shape of the batch exceeds the register-resident Jacobi kernel");
   T->ptrs.resize(n);
@@ -1062,7 +1065,7 @@ size_t lt_batch_workspace_bytes(int n, const lt_problem* probs) {
       hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     tmp.max_lds = lds;
   BatchTables T;
-  if (build_tables(&tmp, n, probs, &T) != LT_OK) return 0;
+  if (build_tables(&tmp, n, probs, 0, &T) != LT_OK) return 0;
   Carver c(nullptr);
   BatchWs w;
   carve_batch(c, T, &w);
@@ -1070,14 +1073,19 @@ size_t lt_batch_workspace_bytes(int n, const lt_problem* probs) {
 }
 
 int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, size_t bws_bytes,
-                    int use_graph, lt_batch** out) {
+                    int use_graph, int jacobi_lanes, lt_batch** out) {
   if (!h || !out) return LT_ERR_ARG;
   lt_batch* b = new (std::nothrow) lt_batch();
   if (!b) return LT_ERR_ARG;
   b->h = h;
   b->n = n;
   b->use_graph = use_graph;
-  int rc = build_tables(h, n, probs, &b->T);
+  if (jacobi_lanes != 0 && jacobi_lanes != 4 && jacobi_lanes != 8 && jacobi_lanes != 16 &&
+      jacobi_lanes != 32 && jacobi_lanes != 64) {
+    delete b;
+    return fail(h, LT_ERR_ARG, "jacobi_lanes must be 0, 4, 8, 16, 32 or 64");
+  }
+  int rc = build_tables(h, n, probs, jacobi_lanes, &b->T);
   if (rc) {
     delete b;
     return rc;

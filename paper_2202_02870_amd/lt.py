@@ -91,7 +91,7 @@ _sig = {
                                          ctypes.POINTER(ctypes.c_int32)]),
     "lt_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(ProblemC)]),
     "lt_batch_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ProblemC), _vp, ctypes.c_size_t,
-                                       ctypes.c_int, ctypes.POINTER(_vp)]),
+                                       ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
     "lt_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lt_batch_destroy": (ctypes.c_int, [_vp]),
 }
@@ -359,6 +359,10 @@ class Problem:
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
         self.c = ProblemC(ctypes.pointer(self.desc), _ptr(M), _ptr(mask), _ptr(self.X), params,
                           _ptr(self.ws), self.ws_bytes)
+        self.reset()
+
+    def reset(self):
+        """(Re)initialise: X^0 = X^1 = 0, iteration 0."""
         h = _handle()
         _check(h, _lib.lt_problem_init(h, ctypes.byref(self.c)))
 
@@ -381,9 +385,15 @@ class Batch:
     """Work tables of a set of initialised problems; step(k) enqueues k ticks
     (one PGA iteration of every unfinished problem per tick)."""
 
-    def __init__(self, problems, use_graph=True):
+    def __init__(self, problems, use_graph=True, jacobi_lanes=0):
+        """jacobi_lanes: lanes per column pair of the Jacobi kernel (0 = built-in
+        choice, "auto" = timed choice of paper_2202_02870_amd.autotune)."""
         self.problems = list(problems)
         n = len(self.problems)
+        if jacobi_lanes == "auto":
+            from . import autotune
+            jacobi_lanes, _ = autotune.tune([p.shape for p in self.problems])
+        self.jacobi_lanes = int(jacobi_lanes)
         arr = (ProblemC * n)(*[p.c for p in self.problems])
         self._arr = arr
         nb = _lib.lt_batch_workspace_bytes(n, arr)
@@ -393,7 +403,7 @@ class Batch:
         h = _handle()
         self.b = _vp()
         _check(h, _lib.lt_batch_create(h, n, arr, _ptr(self.ws), int(nb), 1 if use_graph else 0,
-                                       ctypes.byref(self.b)))
+                                       int(jacobi_lanes), ctypes.byref(self.b)))
 
     def step(self, ticks=1):
         h = _handle()

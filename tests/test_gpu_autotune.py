@@ -1,0 +1,93 @@
+"""GPU tests of the Jacobi autotuner: every candidate lane count gives the same
+completion (to FP32 rounding) and matches the FP64 oracle, the tuned choice is
+the fastest measured candidate and is cached per shape signature, and a lane
+count that cannot hold a slice is refused."""
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_2202_02870_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_02870_amd import lt as _lt
+    return _lt
+
+
+SHAPES = [((32, 48, 3), 3, 0.5), ((96, 64, 8), 4, 0.35), ((33, 17, 5), 2, 0.6), ((128, 128, 3, 2), 6, 0.3)]
+
+
+def _problems(lt, iters, seed0=800):
+    import torch
+    out = []
+    for i, (shape, r, f) in enumerate(SHAPES):
+        p = wl.make_problem(shape, r, f, seed=seed0 + i)
+        s = wl.pga_schedule_params(p.M, p.mask)
+        prm = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
+        out.append((p, s, lt.Problem(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), prm, p.kinds)))
+    return out
+
+
+def test_tune_picks_fastest_and_caches(lt):
+    from paper_2202_02870_amd import autotune
+    shapes = [s for s, _, _ in SHAPES]
+    best, ms = autotune.tune(shapes)
+    print("timings", ms, "best", best, flush=True)
+    assert len(ms) >= 2 and all(t > 0 for t in ms.values())
+    assert best == min(ms, key=ms.get)
+    best2, ms2 = autotune.tune(list(reversed(shapes)))      # same signature: cached
+    assert best2 == best and ms2 == ms
+
+
+def test_every_lane_count_gives_the_same_completion(lt):
+    from paper_2202_02870_amd import autotune
+    _, ms = autotune.tune([s for s, _, _ in SHAPES])       # the feasible lane counts
+    assert len(ms) >= 2
+    iters = 30
+    ref = None
+    for G in sorted(ms):
+        ps = _problems(lt, iters)
+        b = lt.Batch([gp for _, _, gp in ps], jacobi_lanes=G)
+        b.step(iters)
+        b.close()
+        Xs = [lt.to_host(gp.X).astype(np.float64) for _, _, gp in ps]
+        if ref is None:
+            ref = Xs
+            for (p, s, gp), X in zip(ps, Xs):
+                Xo, _ = o.complete_pga(p.M, p.mask, o.mats_for(p.shape, list(p.kinds)), mu0=s["mu0"],
+                                       nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
+                assert np.linalg.norm(Xo) > 0
+                assert np.linalg.norm(X - Xo) / np.linalg.norm(Xo) < 1e-4
+        else:
+            for X, R in zip(Xs, ref):
+                assert np.linalg.norm(X - R) / np.linalg.norm(R) < 2e-5, G
+
+
+def test_auto_batch_runs(lt):
+    iters = 5
+    ps = _problems(lt, iters, seed0=900)
+    b = lt.Batch([gp for _, _, gp in ps], jacobi_lanes="auto")
+    assert b.jacobi_lanes in (4, 8, 16, 32, 64)
+    b.step(iters)
+    b.close()
+    for _, _, gp in ps:
+        rep, done = gp.status()
+        assert done == 2 and rep["iters"] == iters
+
+
+def test_infeasible_lane_count_is_refused(lt):
+    import torch
+    p = wl.make_problem((256, 200, 2), 3, 0.5, seed=5)
+    s = wl.pga_schedule_params(p.M, p.mask)
+    gp = lt.Problem(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8),
+                    lt.pga_params(mu0=s["mu0"], mu_bar=s["mu_bar"], max_iter=3), p.kinds)
+    with pytest.raises(lt.LtError):
+        lt.Batch([gp], jacobi_lanes=4)            # 256 rows over 4 lanes: 64 rows per lane > 32
+    with pytest.raises(lt.LtError):
+        lt.Batch([gp], jacobi_lanes=12)
