@@ -11,12 +11,21 @@
 // of G lanes; each lane keeps R rows of the slot's two columns in registers
 // (FP32), as R/4 chunks of 4 consecutive rows interleaved across the group
 // (chunk c of a column belongs to lane c mod G), so a group moves a column
-// through LDS as contiguous 16-byte pieces.  Dot products, column norms and
-// rotation angles are FP64.
-// The pair schedule is the round-robin (circle) tournament: position 0 is
-// fixed and every other column advances one position per round, so one sweep
-// of 2*ceil(n/2) - 1 rounds meets every column pair exactly once.  Columns move
-// between groups through LDS.
+// through LDS as contiguous 16-byte pieces.  Column norms and rotation angles
+// are FP64; the pair dot products are FP64, or FP32 within a lane and FP64
+// across the group when the tolerance is 1e-6 or looser.
+//
+// Pair schedule (one sweep meets every column pair exactly once, in
+// 2*ceil(n/2) - 1 rounds).  The ceil(n/2) slots form one range of c slots; while
+// c is even the range runs a ring phase: tops stay, bottoms shift one slot along
+// the range after each of its c rounds, so every top meets every bottom; then one
+// swap (the first half's bottoms trade places with the second half's tops) turns
+// the range into two ranges of c/2 slots, one holding the former tops and one the
+// former bottoms, and each continues the same way.  A range of odd size c finishes
+// with the round-robin (circle) tournament over its 2c columns (2c - 1 rounds).
+// A ring round moves one column per slot through LDS where the circle moves two;
+// the ordering is a reordering of the cyclic Jacobi sweep, not of the arithmetic
+// of a rotation.
 //
 // SVT output: with g_i = 1 - tau / sigma_i for sigma_i > tau, the result of
 // Alg. 4 in working orientation is D_W = sum_i g_i u_i u_i^T W (because
@@ -85,6 +94,25 @@ __device__ inline double dot64(const float (&x)[R], const float (&y)[R], int qef
   return d0 + d1;
 }
 
+// The same dot product with FP32 products and two FP32 accumulators per lane
+// (interleaved rows), returned in FP64 for the group sum: relative error about
+// (rows per lane) * 2^-24 of sum |x_i y_i|, below a 1e-6 orthogonality test.
+template <int R>
+__device__ inline double dot32x(const float (&x)[R], const float (&y)[R], int qeff) {
+  float d0 = 0.f, d1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    if (q < qeff) {
+      const int r = 4 * q;
+      d0 = fmaf(x[r], y[r], d0);
+      d1 = fmaf(x[r + 1], y[r + 1], d1);
+      d0 = fmaf(x[r + 2], y[r + 2], d0);
+      d1 = fmaf(x[r + 3], y[r + 3], d1);
+    }
+  }
+  return (double)d0 + (double)d1;
+}
+
 // Hardware reciprocal / reciprocal square root (FP64) refined by one Newton
 // step; the rotation is applied in FP32, so ~1e-15 relative is far below what
 // the result can resolve, and the IEEE-exact division sequence is not needed.
@@ -100,17 +128,46 @@ __device__ inline double rsq64(double x) {
 }
 
 // Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
-// 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows.
+// 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows.  An
+// LDS column slot is ldw = G R + 4 floats: the rows, then 16 bytes of metadata
+// (an FP64 value and an int: the column's norm and id while sweeping, the
+// output scale and destination when writing out), moved with the column.
 template <int G, int R>
-__device__ inline void put_col(float* buf, int ldw, int idx, int l, const float (&v)[R], int qeff) {
-  float4* p = reinterpret_cast<float4*>(buf + (size_t)idx * ldw);
+__device__ inline void put_col(float* buf, int ldw, int idx, int l, const float (&v)[R], int qeff,
+                               double meta_d, int meta_i) {
+  float* col = buf + (size_t)idx * ldw;
+  float4* p = reinterpret_cast<float4*>(col);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q)
     if (q < qeff) p[l + G * q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  if (l == 0)
+    *reinterpret_cast<float4*>(col + ldw - 4) =
+        make_float4(__int_as_float(__double2loint(meta_d)), __int_as_float(__double2hiint(meta_d)),
+                    __int_as_float(meta_i), 0.f);
 }
 
 template <int G, int R>
-__device__ inline void get_col(const float* buf, int ldw, int idx, int l, float (&v)[R], int qeff) {
+__device__ inline void get_col(const float* buf, int ldw, int idx, int l, float (&v)[R], int qeff,
+                               double& meta_d, int& meta_i) {
+  const float* col = buf + (size_t)idx * ldw;
+  const float4* p = reinterpret_cast<const float4*>(col);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    if (q < qeff) {
+      const float4 t = p[l + G * q];
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    }
+  }
+  const float4 m = *reinterpret_cast<const float4*>(col + ldw - 4);
+  meta_d = __hiloint2double(__float_as_int(m.y), __float_as_int(m.x));
+  meta_i = __float_as_int(m.z);
+}
+
+template <int G, int R>
+__device__ inline void get_rows(const float* buf, int ldw, int idx, int l, float (&v)[R], int qeff) {
   const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
@@ -124,25 +181,59 @@ __device__ inline void get_col(const float* buf, int ldw, int idx, int l, float 
   }
 }
 
-template <int G, int R>
-__device__ inline void store_col(float* col, int l, int m, const float (&v)[R], float sc, int qeff) {
-#pragma unroll
-  for (int q = 0; q < R / 4; ++q) {
-    if (q < qeff) {
-      const int row = 4 * (l + G * q);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (row + j < m) col[row + j] = v[4 * q + j] * sc;
+// Stage one half of the working columns (half 0: column p, half 1: column
+// 2*npairs - 1 - p, for p < npairs) into LDS column p, rows 0 .. mpad - 1, with
+// zeros beyond the slice.  The lanes of the slice cooperate; reads are
+// coalesced along the slice's contiguous dimension.
+__device__ inline void stage_in(const float* __restrict__ A, float* buf, int ldw, bool trans, int I1,
+                                int m, int n, int npairs, int mpad, int half, int t2, int tps) {
+  const int total = npairs * mpad;
+  if (!trans) {
+    for (int e = t2; e < total; e += tps) {   // W(row, col) = A[col * I1 + row]
+      const int p = e / mpad, row = e - p * mpad;
+      const int col = half ? 2 * npairs - 1 - p : p;
+      buf[(size_t)p * ldw + row] = (row < m && col < n) ? A[(long long)col * I1 + row] : 0.f;
+    }
+  } else {
+    for (int e = t2; e < total; e += tps) {   // W(row, col) = A[row * I1 + col]
+      const int row = e / npairs, p = e - row * npairs;
+      const int col = half ? 2 * npairs - 1 - p : p;
+      buf[(size_t)p * ldw + row] = (row < m && col < n) ? A[(long long)row * I1 + col] : 0.f;
     }
   }
 }
 
-// Per-slice LDS region: two (or one) exchange buffers of npairs+1 columns,
-// their norms and column ids, and the slice's control words.
+// Write LDS column p (rows 0 .. m-1), scaled by its metadata value, to the
+// output column its metadata int names (none when negative).  Coalesced along
+// the rows.
+__device__ inline void stage_out(float* __restrict__ out, const float* buf, int ldw, int m, int npairs,
+                                 int t2, int tps) {
+  const int total = npairs * m;
+  for (int e = t2; e < total; e += tps) {
+    const int p = e / m, row = e - p * m;
+    const float* col = buf + (size_t)p * ldw;
+    const int d = __float_as_int(col[ldw - 2]);
+    if (d >= 0) {
+      const double sc = __hiloint2double(__float_as_int(col[ldw - 3]), __float_as_int(col[ldw - 4]));
+      out[(long long)d * m + row] = col[row] * (float)sc;
+    }
+  }
+}
+
+// Exchange positions of one buffer: the ring phases use one per slot; the
+// circle phase of the odd-sized ranges uses c + 1 per range of c slots (one
+// extra for the bottom of the range's first slot).
+__host__ __device__ inline int exch_positions(int npairs) {
+  int c = npairs;
+  while (c > 1 && (c & 1) == 0) c >>= 1;
+  return c > 1 ? npairs + npairs / c : npairs;
+}
+
+// Per-slice LDS region: two (or one) exchange buffers of exch_positions
+// columns (rows + metadata) and the slice's control words.
 __host__ __device__ inline size_t slice_lds_bytes(int npairs, int ldw, int nbuf) {
-  const size_t nb1 = (size_t)npairs + 1;
-  size_t b = (size_t)nbuf * nb1 * ldw * sizeof(float) + (size_t)nbuf * nb1 * sizeof(double) +
-             (size_t)nbuf * nb1 * sizeof(int) + ((size_t)npairs + 4) * sizeof(int);
+  const size_t np = (size_t)exch_positions(npairs);
+  size_t b = (size_t)nbuf * np * ldw * sizeof(float) + ((size_t)npairs + 4) * sizeof(int);
   return (b + 15) & ~size_t(15);
 }
 constexpr size_t kWgCtlBytes = 16;   // workgroup-wide rotation counters
@@ -164,15 +255,14 @@ struct Job {
 };
 
 template <int G, int R>
-__device__ void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf, int ldw,
+__device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf, int ldw,
                             unsigned char* smem) {
   const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
   const int n = trans ? I1 : I2;
   const int npairs = (n + 1) >> 1;
-  const int last = npairs - 1;
-  const int nb1 = npairs + 1;   // columns per exchange buffer (index 0: parked column)
+  const int npos = exch_positions(npairs);   // columns per exchange buffer
   const int tps = npairs * G;   // lanes per slice
   const int tid = threadIdx.x;
   const int sub = tid / tps;
@@ -184,38 +274,23 @@ __device__ void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf,
   int* wg_ctl = reinterpret_cast<int*>(smem);
   unsigned char* base = smem + kWgCtlBytes + (size_t)subr * sbytes;
   float* bufA = reinterpret_cast<float*>(base);
-  float* bufB = (nbuf == 2) ? bufA + (size_t)nb1 * ldw : bufA;
-  double* nrmA = reinterpret_cast<double*>(bufA + (size_t)nbuf * nb1 * ldw);
-  double* nrmB = (nbuf == 2) ? nrmA + nb1 : nrmA;
-  int* idA = reinterpret_cast<int*>(nrmA + (size_t)nbuf * nb1);
-  int* idB = (nbuf == 2) ? idA + nb1 : idA;
+  float* bufB = (nbuf == 2) ? bufA + (size_t)npos * ldw : bufA;
   // ctl[0], ctl[1]: the slice's rotation counters of even / odd sweeps;
   // ctl[2]: kept total; ctl[3 + g]: per-slot output offsets
-  int* ctl = idA + (size_t)nbuf * nb1;
+  int* ctl = reinterpret_cast<int*>(bufA + (size_t)nbuf * npos * ldw);
   const float* __restrict__ A = jb.src + (long long)subr * jb.stride;
 
   // ---- load: slot g holds columns g (top) and 2*npairs - 1 - g (bottom) ----
   float av[R], bv[R];
   int ida = g, idb = 2 * npairs - 1 - g;
-  {
-    // clamp every address into the slice and scale what is out of range by 0,
-    // so that the loads carry no control flow
-    const float fa = (active && ida < n) ? 1.f : 0.f, fb = (active && idb < n) ? 1.f : 0.f;
-    const int ca = ida < n ? ida : n - 1, cb = idb < n ? idb : n - 1;
-#pragma unroll
-    for (int q = 0; q < R / 4; ++q) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = 4 * (l + G * q) + j;
-        const int rr = row < m ? row : m - 1;
-        const float f = (row < m && q < qeff) ? 1.f : 0.f;
-        const long long oa = trans ? (long long)rr * I1 + ca : (long long)ca * I1 + rr;
-        const long long ob = trans ? (long long)rr * I1 + cb : (long long)cb * I1 + rr;
-        av[4 * q + j] = A[oa] * (fa * f);
-        bv[4 * q + j] = A[ob] * (fb * f);
-      }
-    }
-  }
+  const int mpad = 4 * G * qeff;   // rows a lane group holds per column (>= m)
+  if (active) stage_in(A, bufA, ldw, trans, I1, m, n, npairs, mpad, 0, t2, tps);
+  __syncthreads();
+  if (active) get_rows<G, R>(bufA, ldw, g, l, av, qeff);
+  __syncthreads();
+  if (active) stage_in(A, bufA, ldw, trans, I1, m, n, npairs, mpad, 1, t2, tps);
+  __syncthreads();
+  if (active) get_rows<G, R>(bufA, ldw, g, l, bv, qeff);
   if (active && t2 == 0) {
     ctl[0] = 0;
     ctl[1] = 0;
@@ -226,95 +301,111 @@ __device__ void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf,
   }
   __syncthreads();
 
-  const int nrounds = 2 * npairs - 1;
   double na = 0.0, nb = 0.0;
   int sweep = 0;
   int my_sweeps = 0;            // sweeps this slice needed (first sweep without rotations)
   bool converged = false;
   long long rotations = 0;
+  // Per-lane FP32 partial dot products (FP64 sum over the group) when the
+  // tolerance is above what FP32 rounding of the products could fake; FP64
+  // products otherwise.
+  const bool dot32 = tol >= 1e-6;
   // single-exit loop (max_sweeps >= 1): the columns stay in one register set
   for (;;) {
     na = group_sum<G>(dot64<R>(av, av, qeff));
     nb = group_sum<G>(dot64<R>(bv, bv, qeff));
     int my_rot = 0;
-    for (int round = 0; round < nrounds; ++round) {
-      const double d = group_sum<G>(dot64<R>(av, bv, qeff));
-      const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
-      // a slice that has converged stays frozen while the rest of its pack
-      // finishes, so its result does not depend on what it is packed with
-      if (active && !converged && d != 0.0 && fabs(d) > tol * sqrt(pa * pb)) {
-        // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
-        // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
-        // every multiply-add is written as an explicit fma: the rounding must
-        // not depend on how the compiler contracts a particular instantiation
-        const double zeta = (pb - pa) * (0.5 * rcp64(d));
-        const double z2 = fma(zeta, zeta, 1.0);
-        const double q = fma(z2, rsq64(z2), fabs(zeta));
-        const double t = copysign(rcp64(q), zeta == 0.0 ? 1.0 : zeta);
-        const double c = rsq64(fma(t, t, 1.0));
-        const float cf = (float)c, sf = (float)(c * t);
+    // a converged slice stays frozen in place (no rotations, no moves) while
+    // the rest of its pack finishes, so its result and column order do not
+    // depend on what it is packed with
+    const bool moving = active && !converged;
+    // phase state: ranges of c slots; ring phase while c is even, circle
+    // tournament once c is odd; r counts the rounds of the current phase
+    int c = npairs;
+    bool ring = (c & 1) == 0;
+    int s0 = 0, i = g, r = 0;
+    const int nrounds = 2 * npairs - 1;
+    for (int k = 0; k < nrounds; ++k) {
+      // one rotation of the slot's pair (av, bv)
+      if (moving) {
+        const double d = group_sum<G>(dot32 ? dot32x<R>(av, bv, qeff) : dot64<R>(av, bv, qeff));
+        const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
+        if (d != 0.0 && d * d > tol * tol * (pa * pb)) {   // |d| > tol sqrt(pa pb)
+          // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
+          // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+          // every multiply-add is written as an explicit fma: the rounding must
+          // not depend on how the compiler contracts a particular instantiation
+          const double zeta = (pb - pa) * (0.5 * rcp64(d));
+          const double z2 = fma(zeta, zeta, 1.0);
+          const double q = fma(z2, rsq64(z2), fabs(zeta));
+          const double t = copysign(rcp64(q), zeta == 0.0 ? 1.0 : zeta);
+          const double cs = rsq64(fma(t, t, 1.0));
+          const float cf = (float)cs, sf = (float)(cs * t);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (r < 4 * qeff) {
-            const float x = av[r], y = bv[r];
-            const float sy = sf * y, sx = sf * x;
-            av[r] = fmaf(cf, x, -sy);
-            bv[r] = fmaf(cf, y, sx);
+          for (int e = 0; e < R; ++e) {
+            if (e < 4 * qeff) {
+              const float x = av[e], y = bv[e];
+              const float sy = sf * y, sx = sf * x;
+              av[e] = fmaf(cf, x, -sy);
+              bv[e] = fmaf(cf, y, sx);
+            }
           }
+          na = fma(-t, d, pa);
+          nb = fma(t, d, pb);
+          my_rot += (l == 0);
         }
-        na = fma(-t, d, pa);
-        nb = fma(t, d, pb);
-        my_rot += (l == 0);
       }
-      if (npairs > 1) {
-        // phase 1: new tops (and park the last slot's bottom)
-        const int park = (nbuf == 2 && (round & 1)) ? 1 : 0;  // alternate park buffer
-        float* pbuf = park ? bufB : bufA;
-        double* pnrm = park ? nrmB : nrmA;
-        int* pid = park ? idB : idA;
-        if (active) {
-          if (g == 0) {
-            put_col<G, R>(bufA, ldw, 1, l, bv, qeff);
-            if (l == 0) { nrmA[1] = nb; idA[1] = idb; }
-          } else if (g < last) {
-            put_col<G, R>(bufA, ldw, g + 1, l, av, qeff);
-            if (l == 0) { nrmA[g + 1] = na; idA[g + 1] = ida; }
-          } else {
-            put_col<G, R>(pbuf, ldw, 0, l, bv, qeff);
-            if (l == 0) { pnrm[0] = nb; pid[0] = idb; }
-          }
+      if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
+      if (ring && r + 1 < c) {
+        // ring: bottoms move one slot down the range (double-buffered: one barrier)
+        const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+        float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
+        if (moving) put_col<G, R>(buf, ldw, g, l, bv, qeff, nb, idb);
+        __syncthreads();
+        if (moving) get_col<G, R>(buf, ldw, nxt, l, bv, qeff, nb, idb);
+        if (nbuf == 1) __syncthreads();
+        ++r;
+      } else if (ring) {
+        // end of a ring phase: the first half's bottoms and the second half's
+        // tops trade places, leaving two ranges of c/2 slots
+        const int h = c >> 1;
+        const bool first = i < h;
+        if (moving) {
+          if (first) put_col<G, R>(bufB, ldw, g, l, bv, qeff, nb, idb);
+          else put_col<G, R>(bufB, ldw, g, l, av, qeff, na, ida);
         }
         __syncthreads();
-        if (active && g >= 1) {
-          if (g == last) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) bv[r] = av[r];
-            nb = na;
-            idb = ida;
-          }
-          get_col<G, R>(bufA, ldw, g, l, av, qeff);
-          na = nrmA[g];
-          ida = idA[g];
+        if (moving) {
+          if (first) get_col<G, R>(bufB, ldw, g + h, l, bv, qeff, nb, idb);
+          else get_col<G, R>(bufB, ldw, g - h, l, av, qeff, na, ida);
         }
         if (nbuf == 1) __syncthreads();
-        // phase 2: new bottoms
-        if (active && g >= 1 && g <= last - 1) {
-          put_col<G, R>(bufB, ldw, g, l, bv, qeff);
-          if (l == 0) { nrmB[g] = nb; idB[g] = idb; }
+        c = h;
+        ring = (c & 1) == 0;
+        s0 = (g / c) * c;
+        i = g - s0;
+        r = 0;
+      } else {
+        // circle tournament over the range's 2c columns: slot 0 keeps its top,
+        // the other tops move one slot up (slot 1 takes slot 0's bottom), the
+        // bottoms move one slot down and the last slot's top becomes its
+        // bottom.  The range owns exchange positions pos0 .. pos0 + c of bufA;
+        // phase 1 stores tops at pos0 + i (slot 0's bottom at pos0 + c), phase 2
+        // stores the bottoms of slots 1.. one position lower, so that position
+        // pos0 + i then holds slot i's new bottom, the last slot's included.
+        const int pos0 = s0 + s0 / c;
+        if (moving) {
+          put_col<G, R>(bufA, ldw, pos0 + i, l, av, qeff, na, ida);
+          if (i == 0) put_col<G, R>(bufA, ldw, pos0 + c, l, bv, qeff, nb, idb);
         }
         __syncthreads();
-        if (active && g <= last - 1) {
-          if (g <= last - 2) {
-            get_col<G, R>(bufB, ldw, g + 1, l, bv, qeff);
-            nb = nrmB[g + 1];
-            idb = idB[g + 1];
-          } else {
-            get_col<G, R>(pbuf, ldw, 0, l, bv, qeff);
-            nb = pnrm[0];
-            idb = pid[0];
-          }
+        if (moving && i != 0) {
+          get_col<G, R>(bufA, ldw, pos0 + (i == 1 ? c : i - 1), l, av, qeff, na, ida);
+          put_col<G, R>(bufA, ldw, pos0 + i - 1, l, bv, qeff, nb, idb);
         }
-        if (nbuf == 1) __syncthreads();
+        __syncthreads();
+        if (moving) get_col<G, R>(bufA, ldw, pos0 + i, l, bv, qeff, nb, idb);
+        ++r;
       }
     }
     // counters of the next sweep are cleared before the barrier that precedes
@@ -363,29 +454,32 @@ __device__ void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf,
     ctl[2] = acc;
   }
   __syncthreads();
+  // kept columns, scaled, through LDS: tops, then bottoms
   float* out = jb.out + (long long)subr * jb.stride;
+  const int j0 = active ? ctl[3 + g] : 0;
+  double sca, scb;
+  int da, db;
   if (jb.mode == 0) {
-    int j = active ? ctl[3 + g] : 0;
-    if (ka) {
-      const float sc = (float)(sqrt(1.0 - jb.tau / sa) / sa);
-      store_col<G, R>(out + (long long)j * m, l, m, av, sc, qeff);
-      ++j;
-    }
-    if (kb) {
-      const float sc = (float)(sqrt(1.0 - jb.tau / sb) / sb);
-      store_col<G, R>(out + (long long)j * m, l, m, bv, sc, qeff);
-    }
+    sca = ka ? sqrt(1.0 - jb.tau / sa) / sa : 0.0;
+    scb = kb ? sqrt(1.0 - jb.tau / sb) / sb : 0.0;
+    da = ka ? j0 : -1;
+    db = kb ? j0 + (int)ka : -1;
   } else {
     // all columns, at their original column index, plus their norms
-    if (ka) {
-      store_col<G, R>(out + (long long)ida * m, l, m, av, 1.f, qeff);
-      if (l == 0) jb.sigma[(long long)subr * n + ida] = sa;
-    }
-    if (kb) {
-      store_col<G, R>(out + (long long)idb * m, l, m, bv, 1.f, qeff);
-      if (l == 0) jb.sigma[(long long)subr * n + idb] = sb;
-    }
+    sca = 1.0;
+    scb = 1.0;
+    da = ka ? ida : -1;
+    db = kb ? idb : -1;
+    if (l == 0 && ka) jb.sigma[(long long)subr * n + ida] = sa;
+    if (l == 0 && kb) jb.sigma[(long long)subr * n + idb] = sb;
   }
+  if (active) put_col<G, R>(bufA, ldw, g, l, av, qeff, sca, da);
+  __syncthreads();
+  if (active) stage_out(out, bufA, ldw, m, npairs, t2, tps);
+  __syncthreads();
+  if (active) put_col<G, R>(bufA, ldw, g, l, bv, qeff, scb, db);
+  __syncthreads();
+  if (active) stage_out(out, bufA, ldw, m, npairs, t2, tps);
   if (active && t2 == 0) {
     if (jb.rank) jb.rank[sub] = ctl[2];
     if (jb.sweeps) jb.sweeps[sub] = my_sweeps;
