@@ -74,6 +74,29 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
+// The same group sum for FP32 values (DPP modifiers on the adds).
+__device__ inline float dpp_addf(float v, int ctrl_sel) {
+  const int x = __float_as_int(v);
+  int y;
+  switch (ctrl_sel) {
+    case 0: y = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false); break;
+    case 1: y = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false); break;
+    default: y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); break;
+  }
+  return v + __int_as_float(y);
+}
+
+template <int G>
+__device__ inline float group_sumf(float v) {
+  v = dpp_addf(v, 0);
+  if (G >= 4) v = dpp_addf(v, 1);
+  if (G >= 8) v = dpp_addf(v, 2);
+  if (G >= 16) v += __shfl_xor(v, 8, 64);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // FP64 dot product of two FP32 register columns (FP32 x FP32 products are exact
 // in FP64), over the first qeff 4-row chunks.  The scheduling barriers keep the
 // compiler from converting a whole column to FP64 ahead of use.
@@ -95,10 +118,11 @@ __device__ inline double dot64(const float (&x)[R], const float (&y)[R], int qef
 }
 
 // The same dot product with FP32 products and two FP32 accumulators per lane
-// (interleaved rows), returned in FP64 for the group sum: relative error about
-// (rows per lane) * 2^-24 of sum |x_i y_i|, below a 1e-6 orthogonality test.
+// (interleaved rows); with the FP32 group sum the relative error is about
+// (rows per lane + log2 G) * 2^-24 of sum |x_i y_i|, below a 1e-6 orthogonality
+// test.
 template <int R>
-__device__ inline double dot32x(const float (&x)[R], const float (&y)[R], int qeff) {
+__device__ inline float dot32x(const float (&x)[R], const float (&y)[R], int qeff) {
   float d0 = 0.f, d1 = 0.f;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
@@ -110,21 +134,16 @@ __device__ inline double dot32x(const float (&x)[R], const float (&y)[R], int qe
       d1 = fmaf(x[r + 3], y[r + 3], d1);
     }
   }
-  return (double)d0 + (double)d1;
+  return d0 + d1;
 }
 
-// Hardware reciprocal / reciprocal square root (FP64) refined by one Newton
-// step; the rotation is applied in FP32, so ~1e-15 relative is far below what
-// the result can resolve, and the IEEE-exact division sequence is not needed.
+// Hardware FP64 reciprocal refined by one Newton step (about 1e-15 relative):
+// it only forms the rotation's zeta, which is then rounded to FP32, so the
+// IEEE-exact division sequence is not needed.
 __device__ inline double rcp64(double x) {
   double r = __builtin_amdgcn_rcp(x);
   const double e = fma(-x, r, 1.0);
   return fma(r, e, r);
-}
-__device__ inline double rsq64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x * y;
-  return fma(y, fma(-h, y, 0.5), y);   // y (1.5 - 0.5 x y^2)
 }
 
 // Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
@@ -328,19 +347,24 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
     for (int k = 0; k < nrounds; ++k) {
       // one rotation of the slot's pair (av, bv)
       if (moving) {
-        const double d = group_sum<G>(dot32 ? dot32x<R>(av, bv, qeff) : dot64<R>(av, bv, qeff));
+        const double d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv, qeff))
+                               : group_sum<G>(dot64<R>(av, bv, qeff));
         const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
         if (d != 0.0 && d * d > tol * tol * (pa * pb)) {   // |d| > tol sqrt(pa pb)
           // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
-          // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
-          // every multiply-add is written as an explicit fma: the rounding must
-          // not depend on how the compiler contracts a particular instantiation
+          // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+          // c = 1 / sqrt(1 + t^2), s = c t.  zeta is formed in FP64 (a
+          // difference of FP64 norms) and clamped where t falls below FP32
+          // resolution; t, c and s are FP32, the precision the rotation is
+          // applied in.  Every multiply-add is an explicit fma, so the rounding
+          // does not depend on how the compiler contracts an instantiation.
           const double zeta = (pb - pa) * (0.5 * rcp64(d));
-          const double z2 = fma(zeta, zeta, 1.0);
-          const double q = fma(z2, rsq64(z2), fabs(zeta));
-          const double t = copysign(rcp64(q), zeta == 0.0 ? 1.0 : zeta);
-          const double cs = rsq64(fma(t, t, 1.0));
-          const float cf = (float)cs, sf = (float)(cs * t);
+          const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
+          const float z2 = fmaf(zf, zf, 1.f);
+          const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
+          const float t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
+          const float cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          const float sf = cf * t;
 #pragma unroll
           for (int e = 0; e < R; ++e) {
             if (e < 4 * qeff) {
@@ -350,8 +374,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
               bv[e] = fmaf(cf, y, sx);
             }
           }
-          na = fma(-t, d, pa);
-          nb = fma(t, d, pb);
+          na = fma(-(double)t, d, pa);
+          nb = fma((double)t, d, pb);
           my_rot += (l == 0);
         }
       }
