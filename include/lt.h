@@ -87,7 +87,16 @@ typedef struct {
                            <= 0 selects 1e-6 */
   int32_t max_sweeps;   /* sweep limit per slice; <= 0 selects 40 */
   int32_t precision;    /* lt_precision of the transform GEMMs */
+  int32_t no_precondition; /* SVT paths: 0 runs the Jacobi on the Cholesky-QR factor R^T of
+                              each slice where min(I1, I2) <= LT_PRECOND_MAX_N (fewer sweeps,
+                              same result to the Jacobi tolerance); nonzero runs it on the
+                              slice itself.  lt_lsvd always uses the slice itself. */
+  int32_t reserved;     /* set to 0 */
 } lt_svd_opts;
+
+/* Largest min(I1, I2) the preconditioned SVT path takes (its per-slice FP64
+ * Cholesky lives in LDS). */
+#define LT_PRECOND_MAX_N 200
 
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */
@@ -121,7 +130,8 @@ typedef struct {
 #define LT_PROF_REBUILD 2   /* rank-r rebuild of the thresholded slices */
 #define LT_PROF_INVERSE 3   /* L^{-1}: transform GEMM (with the fused stopping norms in PGA) */
 #define LT_PROF_OTHER 4     /* small reductions, transform-matrix builds, face-wise products */
-#define LT_PROF_NCLASS 5
+#define LT_PROF_PRECOND 5   /* Gram matrices and Cholesky factors of the preconditioned SVT */
+#define LT_PROF_NCLASS 6
 typedef struct {
   int64_t calls[LT_PROF_NCLASS];
   double ms[LT_PROF_NCLASS];   /* summed event-to-event durations */

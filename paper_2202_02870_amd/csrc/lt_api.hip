@@ -271,7 +271,19 @@ struct SvtWs {
   float* Bk = nullptr;
   int32_t* rank = nullptr;
   int32_t* sweeps = nullptr;
+  double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
 };
+
+// The preconditioned SVT path applies when the FP64 Cholesky of an n x n Gram
+// matrix fits one workgroup's LDS.
+static_assert(LT_PRECOND_MAX_N == 200, "the Cholesky kernel holds columns of at most 200 rows");
+
+bool precond_shape(const Shape& s) {
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  return n >= 2 && n <= LT_PRECOND_MAX_N;
+}
+
+long long precond_n(const Shape& s) { return s.I1 < s.I2 ? s.I1 : s.I2; }
 
 void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   carve_transform(c, s, prec, &w->t);
@@ -279,6 +291,7 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   w->Bk = c.take<float>((size_t)s.nel);
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
+  if (precond_shape(s)) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
 }
 
 struct PgaWs {
@@ -343,15 +356,42 @@ int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
 int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtWs& w,
                    double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
                    unsigned long long* sweep_total, unsigned long long* rot_total,
-                   unsigned int* hits) {
-  lt::JacobiConfig cfg;
-  int rc = jacobi_config(h, s, &cfg);
-  if (rc) return rc;
+                   unsigned int* hits, bool precond) {
+  precond = precond && w.C && precond_shape(s);
   lt::JacobiArgs j{};
-  j.src = Gh;
-  j.slice_stride = s.N;
-  j.I1 = (int)s.I1;
-  j.I2 = (int)s.I2;
+  lt::JacobiConfig cfg;
+  int rc;
+  if (precond) {
+    // Jacobi on L = R^T (n x n), C = W^T W = R^T R: its kept columns are the
+    // scaled right singular vectors B, and D_W = (W B) B^T
+    const int n = (int)precond_n(s);
+    const long long cst = (long long)n * n;
+    {
+      ProfScope ps(h, LT_PROF_PRECOND);
+      lt::GramArgs g{Gh, s.N, w.C, cst, (int)s.I1, (int)s.I2, (int)s.P};
+      HIP_TRY(h, lt::launch_gram(g, h->stream));
+    }
+    {
+      ProfScope ps(h, LT_PROF_PRECOND);
+      lt::CholArgs c{w.C, cst, n, (int)s.P};
+      HIP_TRY(h, lt::launch_chol(c, h->stream));
+    }
+    Shape sq = s;
+    sq.I1 = n;
+    sq.I2 = n;
+    if ((rc = jacobi_config(h, sq, &cfg))) return rc;
+    j.src = reinterpret_cast<const float*>(w.C);
+    j.slice_stride = 2 * cst;   // L slice s occupies the first half of the slice's FP64 block
+    j.I1 = n;
+    j.I2 = n;
+    j.bk_stride = s.N;
+  } else {
+    if ((rc = jacobi_config(h, s, &cfg))) return rc;
+    j.src = Gh;
+    j.slice_stride = s.N;
+    j.I1 = (int)s.I1;
+    j.I2 = (int)s.I2;
+  }
   j.nslices = (int)s.P;
   j.tau = tau;
   j.tol = tol;
@@ -376,11 +416,26 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   r.I1 = (int)s.I1;
   r.I2 = (int)s.I2;
   r.nslices = (int)s.P;
+  r.flip = precond ? 1 : 0;
   {
     ProfScope ps(h, LT_PROF_REBUILD);
     HIP_TRY(h, lt::launch_rebuild(r, h->stream));
   }
   return LT_OK;
+}
+
+bool precond_requested(const lt_svd_opts* o) { return !(o && o->no_precondition); }
+
+// The SVT of this shape is supported: by the preconditioned path (any m, n up
+// to LT_PRECOND_MAX_N) or by the Jacobi kernel on the slice itself.
+int check_svt_shape(lt_handle* h, const Shape& s, bool precond) {
+  lt::JacobiConfig probe;
+  if (precond && precond_shape(s)) {
+    Shape sq = s;
+    sq.I1 = sq.I2 = precond_n(s);
+    return jacobi_config(h, sq, &probe);
+  }
+  return jacobi_config(h, s, &probe);
 }
 
 
@@ -675,8 +730,7 @@ int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, floa
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  lt::JacobiConfig probe;
-  if ((rc = jacobi_config(h, s, &probe))) return rc;
+  if ((rc = check_svt_shape(h, s, precond_requested(opts)))) return rc;
   const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_SVT, prec);
   if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
   Carver c(ws);
@@ -687,7 +741,8 @@ int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, floa
                  lt::EPI_PLAIN, LT_PROF_FORWARD)))
     return rc;
   rc = run_jacobi_svt(h, s, w.Gh, w.Gh, w, tau, tol, max_sweeps, rank_out ? rank_out : w.rank,
-                      sweeps_out ? sweeps_out : w.sweeps, nullptr, nullptr, nullptr);
+                      sweeps_out ? sweeps_out : w.sweeps, nullptr, nullptr, nullptr,
+                      precond_requested(opts));
   if (rc) return rc;
   return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Gh, D), prec, lt::PRO_PLAIN,
               lt::EPI_PLAIN, LT_PROF_INVERSE);
@@ -825,8 +880,7 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   int max_sweeps, prec;
   resolve_opts(&p->svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  lt::JacobiConfig probe;
-  if ((rc = jacobi_config(h, s, &probe))) return rc;
+  if ((rc = check_svt_shape(h, s, precond_requested(&p->svd)))) return rc;
   const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_PGA, prec);
   if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
   Carver c(ws);
@@ -870,7 +924,8 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     f.beta = (float)beta;
     if ((rc = gemm(h, f, prec, lt::PRO_PGA, lt::EPI_PLAIN, LT_PROF_FORWARD))) return rc;
     rc = run_jacobi_svt(h, s, w.svt.Gh, w.svt.Gh, w.svt, mu_k, tol, max_sweeps, w.svt.rank,
-                        w.svt.sweeps, w.sweep_total, w.rot_total, w.maxsweep_hits);
+                        w.svt.sweeps, w.sweep_total, w.rot_total, w.maxsweep_hits,
+                        precond_requested(&p->svd));
     if (rc) return rc;
     lt::GemmArgs b = gemm_plain(w.svt.t, true, (int)s.P, s.N, w.svt.Gh, Xprev);
     b.X = Xcur;

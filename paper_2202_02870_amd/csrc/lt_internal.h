@@ -90,7 +90,8 @@ struct JacobiArgs {
   int max_sweeps;
   int qeff;                // 4-row chunks per lane that carry rows (set by launch_jacobi)
   int mode;                // 0: SVT (write kept, scaled columns); 1: all columns + norms
-  float* bk;               // out, slice s at bk + s * slice_stride: m x r columns (ld m)
+  float* bk;               // out, slice s at bk + s * bk_stride: m x r columns (ld m)
+  long long bk_stride;     // 0: slice_stride
   int32_t* rank;           // out [nslices] (svt mode: r; lsvd mode: n)
   int32_t* sweeps;         // out [nslices]
   double* sigma;           // lsvd mode: out [nslices][n] column norms (unsorted)
@@ -119,7 +120,26 @@ struct RebuildArgs {
   const int32_t* rank;
   long long slice_stride;
   int I1, I2, nslices;
+  int flip;                // 0: D_W = Bk (Bk^T W), Bk m x r; 1: D_W = (W B) B^T, B n x r
 };
+
+// Cholesky-QR preconditioning of the Jacobi SVD (lt_precond.hip).
+struct GramArgs {
+  const float* W;          // slices (working orientation as for the Jacobi kernel)
+  long long slice_stride;
+  double* C;               // out: n x n FP64 per slice at C + s * c_stride (lower triangle)
+  long long c_stride;      // >= n * n
+  int I1, I2, nslices;
+};
+hipError_t launch_gram(const GramArgs& a, hipStream_t s);
+
+struct CholArgs {
+  double* C;               // in: Gram lower triangles; out: L (FP32 n x n) over each slice's region
+  long long c_stride;      // doubles between slices (L slice s at (float*)(C + s * c_stride))
+  int n, nslices;
+};
+size_t chol_lds_bytes(int n);
+hipError_t launch_chol(const CholArgs& a, hipStream_t s);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s);
 
 // lsvd finalisation: sort, normalise, V = W^T U diag(1/sigma), write factors

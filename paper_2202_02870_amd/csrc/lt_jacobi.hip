@@ -520,7 +520,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
   const int s = blockIdx.x;
   Job jb;
   jb.src = a.src + (long long)s * a.slice_stride;
-  jb.out = a.bk + (long long)s * a.slice_stride;
+  jb.out = a.bk + (long long)s * (a.bk_stride ? a.bk_stride : a.slice_stride);
   jb.rank = a.rank ? a.rank + s : nullptr;
   jb.sweeps = a.sweeps ? a.sweeps + s : nullptr;
   const int n = a.I1 < a.I2 ? a.I1 : a.I2;
@@ -579,13 +579,16 @@ __device__ inline float w_at(const float* W, bool trans, int I1, int row, int co
 // Working columns j0 .. j0+15 of one slice: Z = Bk^T W(:, j0..) (r x 16), then
 // D_W(:, j0..) = Bk Z.  W and D may alias: the tile is read in full before any
 // of it is written, and no other workgroup touches these entries.
-__device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0) {
+__device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
+                             bool flip) {
   __shared__ float Ws[RB_TK][RB_TN + 1];
   __shared__ float Bs[RB_TK][RB_RMAX + 1];
   __shared__ float Z[RB_RMAX][RB_TN + 1];
-  const bool trans = I1 < I2;
-  const int m = trans ? I2 : I1;
-  const int n = trans ? I1 : I2;
+  // flip: the working matrix is W^T (n x m), so the same two products give
+  // D_W^T = B (B^T W^T), i.e. D_W = (W B) B^T with B n x r
+  const bool trans = (I1 < I2) != flip;
+  const int m = flip ? (I1 < I2 ? I1 : I2) : (I1 < I2 ? I2 : I1);
+  const int n = flip ? (I1 < I2 ? I2 : I1) : (I1 < I2 ? I1 : I2);
   const int nq = (r + 15) >> 4;
   const int rpad = nq << 4;
   const int tid = threadIdx.x;
@@ -648,11 +651,11 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
 
 __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
   const int s = blockIdx.y;
-  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
   const int j0 = blockIdx.x * RB_TN;
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
-  rebuild_body(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0);
+  rebuild_body(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
 }
 
 __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles) {
@@ -660,7 +663,7 @@ __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, co
   const ProbDev* pd = probs[t.prob];
   if (!pd->active) return;
   const long long off = (long long)t.slice * pd->N;
-  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0);
+  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0, false);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
@@ -981,7 +984,7 @@ hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles,
 
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
-  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
   hipLaunchKernelGGL(k_rebuild, grid, dim3(256), 0, s, a);
   return hipGetLastError();

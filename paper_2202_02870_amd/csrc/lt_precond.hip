@@ -1,0 +1,244 @@
+// Preconditioning of the per-slice one-sided Jacobi SVD by a QR factor
+// computed as Cholesky-QR (the SVD step of Alg. 3 / Alg. 4; how the SVD is
+// computed is not part of the method).
+//
+// For a working slice W (m x n, m >= n), C = W^T W = R^T R with R upper
+// triangular; W and R have the same singular values and right singular
+// vectors.  One-sided Jacobi applied to L = R^T (n x n) turns L J into
+// V Sigma, i.e. its converged columns are sigma_i v_i with v_i the right
+// singular vectors of W, and the SVT result is D_W = sum (1 - tau/sigma_i)
+// sigma_i u_i v_i^T = W (sum g_i v_i v_i^T) = W B B^T with B = [sqrt(g_i) v_i].
+// The Jacobi kernel writes B exactly as it writes its left-vector output on
+// the unpreconditioned path (kept columns scaled by sqrt(1 - tau/sigma)/sigma),
+// and the rebuild kernel forms (W B) B^T by treating W^T as its working matrix.
+//
+// Why: on the slices of the completion iterates the Jacobi sweeps needed on
+// R^T are about half of those on W once the iterate has become low-rank plus
+// noise, and R^T has n rows instead of m.
+//
+// Accuracy: C is accumulated in FP64 from FP32 products (exact), so the
+// eigenvalues sigma_i^2 carry an absolute error of about n eps64 sigma_max^2;
+// a pivot below n * 64 eps64 * max diag(C) (a column numerically in the span of
+// the earlier ones) is set to zero with its column of L, which perturbs the
+// singular values by at most about 1e-6 sigma_max.  L is handed to the Jacobi
+// kernel in FP32, the precision the slice itself has.
+#include "lt_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace lt {
+
+namespace {
+
+__device__ inline float w_elem(const float* W, bool trans, int I1, int row, int col) {
+  return trans ? W[(long long)row * I1 + col] : W[(long long)col * I1 + row];
+}
+
+constexpr int GT = 32;   // Gram output tile (GT x GT), rows of W per LDS chunk
+
+// C (lower triangle, n x n column-major FP64 per slice) = W^T W.  One workgroup
+// per lower-triangle tile pair (ti >= tj) of one slice; 256 lanes, 2 x 2
+// outputs each.
+__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+  __shared__ double Ai[GT][GT + 1];
+  __shared__ double Aj[GT][GT + 1];
+  const int s = blockIdx.y;
+  int t = blockIdx.x, ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const bool trans = a.I1 < a.I2;
+  const int m = trans ? a.I2 : a.I1;
+  const int n = trans ? a.I1 : a.I2;
+  const float* W = a.W + (long long)s * a.slice_stride;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+  for (int k0 = 0; k0 < m; k0 += GT) {
+    for (int idx = tid; idx < GT * GT; idx += 256) {
+      int kk, c;
+      if (trans) {   // W(row, col) = A[row * I1 + col]: columns contiguous
+        c = idx % GT;
+        kk = idx / GT;
+      } else {       // W(row, col) = A[col * I1 + row]: rows contiguous
+        kk = idx % GT;
+        c = idx / GT;
+      }
+      const int row = k0 + kk, ci = ti * GT + c, cj = tj * GT + c;
+      Ai[kk][c] = (row < m && ci < n) ? (double)w_elem(W, trans, a.I1, row, ci) : 0.0;
+      Aj[kk][c] = (row < m && cj < n) ? (double)w_elem(W, trans, a.I1, row, cj) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GT; ++kk) {
+      const double a0 = Ai[kk][2 * tx], a1 = Ai[kk][2 * tx + 1];
+      const double b0 = Aj[kk][2 * ty], b1 = Aj[kk][2 * ty + 1];
+      c00 = fma(a0, b0, c00);
+      c01 = fma(a0, b1, c01);
+      c10 = fma(a1, b0, c10);
+      c11 = fma(a1, b1, c11);
+    }
+    __syncthreads();
+  }
+  double* C = a.C + (long long)s * a.c_stride;
+  const int i0 = ti * GT + 2 * tx, j0 = tj * GT + 2 * ty;
+  const double v[2][2] = {{c00, c01}, {c10, c11}};
+#pragma unroll
+  for (int di = 0; di < 2; ++di)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj) {
+      const int i = i0 + di, j = j0 + dj;
+      if (i < n && j < n && i >= j) C[i + (long long)j * n] = v[di][dj];
+    }
+}
+
+__device__ inline int tri_off(int j, int n) { return j * n - (j * (j - 1)) / 2; }   // column j of a packed lower triangle
+
+constexpr int CH_NMAX = 200;   // largest n (= LT_PRECOND_MAX_N)
+constexpr int CB = 16;         // block width
+
+// 1 / sqrt(x) for x > 0: hardware estimate and two Newton steps (FP64 accuracy)
+__device__ inline double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double h = 0.5 * x * y;
+    y = fma(y, fma(-h, y, 0.5), y);
+  }
+  return y;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky C = L L^T of one slice's Gram matrix, blocked right-looking, on a
+// packed lower triangle in LDS (FP64).  Per block of CB columns: wave 0 factors
+// the CB x CB diagonal block (no workgroup barrier inside), every lane solves
+// one row of the panel below it against that block, and the workgroup applies
+// the block's rank-CB update to the trailing triangle: three barriers per
+// block.  A pivot at or below n * 64 eps64 * max diag(C) zeroes its column.
+// Writes L in FP32 (n x n column-major, zero above the diagonal) over the first
+// half of the slice's own C region.
+__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double T[];
+  __shared__ double dmax_s;
+  __shared__ double dinv_s[CB];   // reciprocals of the current block's diagonal (0: zeroed column)
+  const int s = blockIdx.x, n = a.n, tid = threadIdx.x, nt = blockDim.x;
+  const double* C = a.C + (long long)s * a.c_stride;
+  float* L = reinterpret_cast<float*>(a.C + (long long)s * a.c_stride);
+  // one flat pass (independent loads in flight), lower triangle only
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e % n, j = e / n;
+    if (i >= j) T[tri_off(j, n) + i - j] = C[e];
+  }
+  __syncthreads();
+  if (tid < 64) {   // max of the diagonal, one wave
+    double d = 0.0;
+    for (int j = tid; j < n; j += 64) d = fmax(d, T[tri_off(j, n)]);
+    for (int o = 32; o >= 1; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+    if (tid == 0) dmax_s = d;
+  }
+  __syncthreads();
+  const double thr = dmax_s * (64.0 * n * DBL_EPSILON);
+  const int lane = tid & 63, wave = tid >> 6;
+  const int l32 = tid & 31, grp = tid >> 5, ngrp = nt >> 5;
+  for (int K = 0; K < n; K += CB) {
+    const int kb = min(CB, n - K);
+    // (a) diagonal block, column by column, by wave 0; each step loads all
+    // its operands before storing (no load waits on a store)
+    if (wave == 0) {
+      for (int k = K; k < K + kb; ++k) {
+        const int ok = tri_off(k, n);
+        const double piv = T[ok];
+        const bool live = piv > thr;
+        const double inv = live ? rsq64(piv) : 0.0;   // 1 / L(k, k)
+        if (lane > 0 && k + lane < K + kb) T[ok + lane] *= inv;
+        wave_sync();
+        // T(i, j) -= L(i, k) L(j, k), k < j <= i < K + kb (offsets in a CB x CB square, 4 per lane)
+        const int r = K + kb - 1 - k;   // rows below k in the block
+        int ii[4], jj[4];
+        bool ok2[4];
+        double ti[4], tj[4], tt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u;   // index into the r x r square, lower part used
+          ii[u] = k + 1 + e / CB;
+          jj[u] = k + 1 + e % CB;
+          ok2[u] = e < CB * CB && e / CB < r && e % CB <= e / CB;
+          ti[u] = ok2[u] ? T[ok + ii[u] - k] : 0.0;
+          tj[u] = ok2[u] ? T[ok + jj[u] - k] : 0.0;
+          tt[u] = ok2[u] ? T[tri_off(jj[u], n) + ii[u] - jj[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (ok2[u]) T[tri_off(jj[u], n) + ii[u] - jj[u]] = fma(-ti[u], tj[u], tt[u]);
+        if (lane == 0) {
+          T[ok] = piv * inv;   // L(k, k) = sqrt(piv); 0 for a zeroed column
+          dinv_s[k - K] = inv;
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    // (b) panel: row i >= K + kb solves x L11^T = T(i, K .. K + kb - 1)
+    for (int i = K + kb + tid; i < n; i += nt) {
+      double x[CB];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        if (q < kb) {
+          double acc = T[tri_off(K + q, n) + i - K - q];
+#pragma unroll
+          for (int p = 0; p < q; ++p) acc = fma(-x[p], T[tri_off(K + p, n) + q - p], acc);
+          x[q] = acc * dinv_s[q];
+          T[tri_off(K + q, n) + i - K - q] = x[q];
+        }
+      }
+    }
+    __syncthreads();
+    // (c) trailing triangle: T(i, j) -= sum_q L(i, K+q) L(j, K+q), K + kb <= j <= i
+    for (int i = K + kb + grp; i < n; i += ngrp) {
+      double li[CB];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) li[q] = q < kb ? T[tri_off(K + q, n) + i - K - q] : 0.0;
+      for (int j = K + kb + l32; j <= i; j += 32) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+          if (q < kb) acc = fma(li[q], T[tri_off(K + q, n) + j - K - q], acc);
+        T[tri_off(j, n) + i - j] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e % n, j = e / n;
+    L[e] = i >= j ? (float)T[tri_off(j, n) + i - j] : 0.f;
+  }
+}
+
+}  // namespace
+
+size_t chol_lds_bytes(int n) { return (size_t)n * (n + 1) / 2 * sizeof(double); }
+
+hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  const int n = a.I1 < a.I2 ? a.I1 : a.I2;
+  const int nt = (n + GT - 1) / GT;
+  hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2, a.nslices), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  if (a.n < 1 || a.n > CH_NMAX) return hipErrorInvalidValue;
+  const size_t lds = chol_lds_bytes(a.n);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol, dim3(a.nslices), dim3(a.n <= 64 ? 256 : 1024), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lt

@@ -37,7 +37,8 @@ class Desc(ctypes.Structure):
 
 class SvdOpts(ctypes.Structure):
     _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("no_precondition", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class PgaParams(ctypes.Structure):
@@ -60,11 +61,11 @@ class ProblemC(ctypes.Structure):
                 ("ws_bytes", ctypes.c_size_t)]
 
 
-PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other")
+PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("calls", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5), ("dropped", ctypes.c_int64)]
+    _fields_ = [("calls", ctypes.c_int64 * 6), ("ms", ctypes.c_double * 6), ("dropped", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -213,11 +214,12 @@ def _workspace(nbytes, ws):
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
 
-def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32"):
-    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision])
+def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True):
+    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, 0)
 
 
-def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None):
+def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None,
+             precondition=True):
     """D_tau(A) (Alg. 4).  Returns (D, rank[P] int32, sweeps[P] int32)."""
     shape = tuple(A.shape)
     _check_tensor(A, shape, name="A")
@@ -230,7 +232,7 @@ def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", 
     nb = workspace_bytes(shape, kinds, "svt", precision)
     w = _workspace(nb, ws)
     h = _handle()
-    o = svd_opts(jacobi_tol, max_sweeps, precision)
+    o = svd_opts(jacobi_tol, max_sweeps, precision, precondition)
     st = _lib.lt_svt_prox(h, ctypes.byref(d), _ptr(A), float(tau), _ptr(D), _ptr(rank), _ptr(sweeps),
                           ctypes.byref(o), _ptr(w), nb)
     _check(h, st)
@@ -280,12 +282,13 @@ def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, pr
 
 
 def pga_params(mu0, nu=0.9, mu_bar=None, tol=0.0, max_iter=100, check_every=10,
-               gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32"):
+               gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32",
+               precondition=True):
     if mu_bar is None:
         mu_bar = 1e-4 * mu0
     return PgaParams(float(mu0), float(nu), float(mu_bar), float(tol), int(max_iter), int(check_every),
                      1 if gate_until_floor else 0, 1 if fixed_mu else 0,
-                     svd_opts(jacobi_tol, max_sweeps, precision))
+                     svd_opts(jacobi_tol, max_sweeps, precision, precondition))
 
 
 def complete_pga(M, mask, params, kinds=None, out=None, ws=None):

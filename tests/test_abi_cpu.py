@@ -68,7 +68,7 @@ def test_workspace_sizes_host_only():
 def test_descriptor_layout_matches_c():
     from paper_2202_02870_amd import lt
     assert ctypes.sizeof(lt.Desc) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 8
-    assert ctypes.sizeof(lt.SvdOpts) == 16
-    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 16
+    assert ctypes.sizeof(lt.SvdOpts) == 24
+    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 24
     assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(lt.Profile) == 5 * 8 + 5 * 8 + 8
+    assert ctypes.sizeof(lt.Profile) == 6 * 8 + 6 * 8 + 8

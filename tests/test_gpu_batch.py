@@ -139,6 +139,11 @@ def test_batch_matches_single_problem_path(lt):
     _run(lt, [gp], 80)
     import torch
     s = p.schedule
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
+    # the same algorithm (Jacobi on the slices themselves): equal to FP32 rounding
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80, precondition=False)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 1e-6
+    # the preconditioned single-problem path: the same result to the Jacobi tolerance
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
+    X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
+    assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 5e-5
