@@ -68,9 +68,10 @@ SVT_SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("precondition", [True, False])
 @pytest.mark.parametrize("shape,kinds", SVT_SHAPES)
-def test_svt_prox(lt, shape, kinds):
-    say("svt", shape, kinds)
+def test_svt_prox(lt, shape, kinds, precondition):
+    say("svt", shape, kinds, "precondition", precondition)
     rng = np.random.default_rng(101)
     r = max(1, min(shape[0], shape[1]) // 4)
     mats = o.mats_for(shape, list(kinds))
@@ -80,7 +81,7 @@ def test_svt_prox(lt, shape, kinds):
     A = A + 0.05 * rng.standard_normal(shape)
     s = o.singular_values(A, mats)
     for tau in (0.0, float(np.quantile(s, 0.7)), float(s.max()) * 1.01):
-        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds)
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=precondition)
         ref = o.svt(A, tau, mats)
         err = rel(lt.to_host(D), ref) if np.linalg.norm(ref) > 0 else float(np.abs(lt.to_host(D)).max())
         say("  tau", tau, "err", err, "sweeps", lt.to_host(sweeps).max())
@@ -90,6 +91,47 @@ def test_svt_prox(lt, shape, kinds):
         ref_rk = o.svt_ranks(A, tau, mats)
         near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
         assert np.all(np.abs(rk - ref_rk) <= near)
+
+
+def test_svt_degenerate_slices_preconditioned(lt):
+    """Exactly rank-deficient slices (zero, rank one, repeated columns) make the
+    Gram matrix singular: the Cholesky zeroes the dependent columns and the SVT
+    still equals the oracle's."""
+    rng = np.random.default_rng(105)
+    m, n = 60, 24
+    A = np.zeros((m, n, 4))
+    A[:, :, 1] = np.outer(rng.standard_normal(m), rng.standard_normal(n))            # rank 1
+    B = rng.standard_normal((m, n // 2))
+    A[:, :, 2] = np.concatenate([B, B], axis=1)                                        # repeated columns
+    A[:, :, 3] = rng.standard_normal((m, 3)) @ rng.standard_normal((3, n)) * 1e3     # rank 3, large scale
+    mats = o.mats_for(A.shape, ["identity"])
+    s = o.singular_values(A, mats)
+    for tau in (0.0, 0.5 * float(s.max())):
+        D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("identity",))
+        ref = o.svt(A, tau, mats)
+        err = rel(lt.to_host(D), ref)
+        say("  degenerate tau", tau, "err", err, "rank", lt.to_host(rank))
+        assert err < 2e-5
+        if tau > 0:   # at tau = 0 LAPACK's rounding-level singular values of the null space count
+            assert np.array_equal(lt.to_host(rank), o.svt_ranks(A, tau, mats))
+        else:         # the zeroed columns leave exactly the algebraic ranks
+            assert list(lt.to_host(rank)) == [0, 1, n // 2, 3]
+
+
+def test_svt_tall_slices_need_preconditioning(lt):
+    """600 x 128 slices exceed the register-resident Jacobi on the slice itself
+    (64 column pairs leave at most 16 lanes per pair, 32 rows each); the
+    preconditioned path factors the 128 x 128 Gram matrix instead."""
+    rng = np.random.default_rng(106)
+    shape = (600, 128, 2)
+    mats = o.mats_for(shape, ["dct"])
+    A = o.lproduct(rng.standard_normal((600, 6, 2)), rng.standard_normal((6, 128, 2)), mats)
+    A = A + 0.05 * rng.standard_normal(shape)
+    tau = float(np.quantile(o.singular_values(A, mats), 0.8))
+    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("dct",))
+    assert rel(lt.to_host(D), o.svt(A, tau, mats)) < 2e-5
+    with pytest.raises(lt.LtError):
+        lt.svt_prox(lt.to_device(A), tau, ("dct",), precondition=False)
 
 
 def test_svt_in_place_and_deterministic(lt):
