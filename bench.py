@@ -33,16 +33,19 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-def jacobi_flops(m, n, sweeps, rotations, slices):
-    """Algorithmic flops of the one-sided Jacobi SVT summed over `slices`
-    slice-SVDs that took `sweeps` sweeps (total) and applied `rotations`
-    rotations (total): per sweep and slice, n(n-1)/2 pair dot products
-    (2m FP64 flops each) and the n column norms (2m FP64 each); per rotation
-    6m FP32 flops (two columns of m rows, 3 flops per entry); per slice the
-    final column norms (2m n FP64)."""
+def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True):
+    """Algorithmic flops of the one-sided Jacobi SVT kernel summed over `slices`
+    slice-SVDs of n columns of `rows` rows (the slice's m, or n when the
+    Cholesky-QR preconditioned path runs the Jacobi on R^T) that took `sweeps`
+    sweeps and applied `rotations` rotations in total: per sweep and slice,
+    n(n-1)/2 pair dot products (2 rows flops each; FP32 when the tolerance is
+    1e-6 or looser, FP64 otherwise) and n column norms (2 rows FP64 flops); per
+    rotation 6 rows FP32 flops (two columns, 3 flops per entry); per slice the
+    final column norms (2 rows n FP64)."""
     pairs = n * (n - 1) // 2
-    f64 = sweeps * (pairs * 2 * m + n * 2 * m) + slices * n * 2 * m
-    f32 = rotations * 6 * m
+    dots = sweeps * pairs * 2 * rows
+    f64 = sweeps * n * 2 * rows + slices * n * 2 * rows + (0 if dot32 else dots)
+    f32 = rotations * 6 * rows + (dots if dot32 else 0)
     return f64, f32
 
 
@@ -73,6 +76,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=30,
                     help="oracle iterations timed on the host (bounded CPU sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precondition", action="store_true",
+                    help="run the Jacobi SVD on the slices themselves (no Cholesky-QR factor)")
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
@@ -106,7 +111,7 @@ def main():
 
     def params(iters):
         return lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=iters,
-                             precision=args.precision)
+                             precision=args.precision, precondition=not args.no_precondition)
 
     # warmup (untimed)
     if args.warmup > 0:
@@ -127,7 +132,9 @@ def main():
     # Jacobi kernel roofline (dominant kernel): algorithmic flops per launch over
     # its mean event-timed duration
     jcalls, jms = prof["jacobi"]
-    f64, f32 = jacobi_flops(m, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
+    precond = (not args.no_precondition) and 2 <= n <= 200
+    rows = n if precond else m
+    f64, f32 = jacobi_flops(rows, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
     per_launch = (f64 + f32) / max(jcalls, 1)
     t_launch = jms / 1e3 / max(jcalls, 1)
     t_peak = (f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU) / max(jcalls, 1)
@@ -137,7 +144,8 @@ def main():
                 "peak": round(peak, 2), "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None, "traffic": None,
                 "flops_per_launch": per_launch, "fp64_share": round(f64 / (f64 + f32), 4),
-                "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls}
+                "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
+                "jacobi_rows": rows, "preconditioned": precond}
 
     line = {
         "metric": "PGA iterations/s (slice-SVT/s alongside) at rel-err <= 1e-4 vs FP64 oracle",

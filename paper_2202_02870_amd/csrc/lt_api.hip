@@ -452,10 +452,17 @@ struct ProblemWs {
   double* mus = nullptr;
   double* partials = nullptr;
   unsigned int* scratch = nullptr;
+  double* C = nullptr;   // preconditioning: Gram matrices / Cholesky factors
   int n_partials = 0;
 };
 
-void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, ProblemWs* w) {
+// A problem of the batch engine runs the preconditioned SVT when its options
+// ask for it (the default) and its slices allow it.
+bool problem_precond(const Shape& s, const lt_pga_params* p) {
+  return precond_requested(&p->svd) && precond_shape(s);
+}
+
+void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool precond, ProblemWs* w) {
   w->st = c.take<lt::ProbDev>(1);
   carve_transform(c, s, prec, &w->t);
   w->Xb = c.take<float>((size_t)s.nel);
@@ -468,6 +475,7 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, ProblemWs*
   w->n_partials = (int)n_partials(s);
   w->partials = c.take<double>(2 * (size_t)w->n_partials);
   w->scratch = c.take<unsigned int>(4);
+  if (precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
 }
 
 int check_pga_params(lt_handle* h, const lt_pga_params* p) {
@@ -500,6 +508,9 @@ struct BatchTables {
   std::vector<lt::GemmTile> gemm;
   std::vector<lt::SvtItem> items;
   std::vector<lt::RebuildTile> rebuild;
+  std::vector<lt::GramTile> gram;
+  std::vector<lt::CholItem> chol;
+  int chol_nmax = 0;
   lt::JacobiBatchConfig cfg{};
   int prec = 0, max_sweeps = 40;
   double tol = 1e-6;
@@ -525,6 +536,7 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     }
     ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
     ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
+    if (problem_precond(shapes[i], &probs[i].params)) ms[i] = ns[i];   // Jacobi on the n x n factor
   }
   if (force_G == 0) {
     const char* env = getenv("LT_JACOBI_G");
@@ -538,7 +550,8 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
   for (int i = 0; i < n; ++i) {
     Carver c(probs[i].ws);
     ProblemWs w;
-    carve_problem(c, shapes[i], T->prec, probs[i].params.max_iter, &w);
+    const bool pc = problem_precond(shapes[i], &probs[i].params);
+    carve_problem(c, shapes[i], T->prec, probs[i].params.max_iter, pc, &w);
     T->ptrs[i] = w.st;
     const Shape& s = shapes[i];
     const int ntx = (int)((s.N + 63) / 64), nty = (int)((s.P + 63) / 64);
@@ -549,9 +562,21 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
       const int k = (int)(s.P - s0) < nsub[i] ? (int)(s.P - s0) : nsub[i];
       costed.push_back({(double)rounds * qeff[i], lt::SvtItem{i, s0, k, qeff[i]}});
     }
+    // rebuild tiles over the working matrix's columns: W's n columns, or W^T's
+    // m columns when the preconditioned SVT rebuilds (W B) B^T
+    const int mw = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
+    const int ncols = pc ? mw : ns[i];
     for (int sl = 0; sl < (int)s.P; ++sl)
-      for (int j0 = 0; j0 < ns[i]; j0 += 16) T->rebuild.push_back(lt::RebuildTile{i, sl, j0, 0});
+      for (int j0 = 0; j0 < ncols; j0 += 16) T->rebuild.push_back(lt::RebuildTile{i, sl, j0, 0});
     T->rebuild_slices += (size_t)s.P;
+    if (pc) {
+      const int tg = (ns[i] + 31) / 32;
+      for (int sl = 0; sl < (int)s.P; ++sl) {
+        for (int t = 0; t < tg * (tg + 1) / 2; ++t) T->gram.push_back(lt::GramTile{i, sl, t, 0});
+        T->chol.push_back(lt::CholItem{i, sl});
+      }
+      T->chol_nmax = ns[i] > T->chol_nmax ? ns[i] : T->chol_nmax;
+    }
   }
   // longest first, ties by problem then slice (deterministic)
   std::stable_sort(costed.begin(), costed.end(),
@@ -567,6 +592,8 @@ struct BatchWs {
   lt::GemmTile* gemm = nullptr;
   lt::SvtItem* items = nullptr;
   lt::RebuildTile* rebuild = nullptr;
+  lt::GramTile* gram = nullptr;
+  lt::CholItem* chol = nullptr;
 };
 
 // The item count depends on how many slices a workgroup packs (device LDS);
@@ -576,6 +603,8 @@ void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
   w->gemm = c.take<lt::GemmTile>(T.gemm.size());
   w->items = c.take<lt::SvtItem>(T.rebuild_slices);
   w->rebuild = c.take<lt::RebuildTile>(T.rebuild.size());
+  w->gram = c.take<lt::GramTile>(T.gram.size());
+  w->chol = c.take<lt::CholItem>(T.chol.size());
 }
 
 }  // namespace
@@ -997,7 +1026,7 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   if (p->svd.precision != LT_PREC_F32 && p->svd.precision != LT_PREC_BF16X3) return 0;
   Carver c(nullptr);
   ProblemWs w;
-  carve_problem(c, s, p->svd.precision, p->max_iter, &w);
+  carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), &w);
   return c.off + 256;
 }
 
@@ -1013,7 +1042,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
   {
-    const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+    int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+    if (problem_precond(s, &p->params)) m = n;   // the Jacobi runs on the n x n factor
     lt::JacobiBatchConfig cfg;
     int ns, qe;
     if (lt::jacobi_batch_config(&m, &n, 1, h->max_lds, 0, &cfg, &ns, &qe) != 0)
@@ -1024,7 +1054,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   if ((rc = check_ws(h, p->ws, p->ws_bytes, need))) return rc;
   Carver c(p->ws);
   ProblemWs w;
-  carve_problem(c, s, prec, p->params.max_iter, &w);
+  const bool pc = problem_precond(s, &p->params);
+  carve_problem(c, s, prec, p->params.max_iter, pc, &w);
   hipStream_t st = h->stream;
   HIP_TRY(h, lt::launch_fill_zero(w.scratch, 16, st));
   HIP_TRY(h, lt::launch_count_nonfinite(p->M, p->mask, s.nel, w.scratch, st));
@@ -1069,6 +1100,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   d.mu_bar = p->params.fixed_mu ? p->params.mu0 : p->params.mu_bar;
   d.gate_until_floor = p->params.gate_until_floor;
   d.enabled = 1;
+  d.C = w.C;
+  d.precond = pc ? 1 : 0;
   d.crit = NAN;
   HIP_TRY(h, hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, st));
   HIP_TRY(h, hipStreamSynchronize(st));   // host vectors and d go out of scope
@@ -1085,7 +1118,8 @@ int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
   Carver c(p->ws);
   ProblemWs w;
-  carve_problem(c, s, prec, p->params.max_iter, &w);
+  const bool pc = problem_precond(s, &p->params);
+  carve_problem(c, s, prec, p->params.max_iter, pc, &w);
   lt::ProbDev d;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   HIP_TRY(h, hipMemcpy(&d, w.st, sizeof(d), hipMemcpyDeviceToHost));
@@ -1163,6 +1197,8 @@ int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, siz
   if (e == hipSuccess) e = up(b->w.items, b->T.items.data(), b->T.items.size() * sizeof(lt::SvtItem));
   if (e == hipSuccess)
     e = up(b->w.rebuild, b->T.rebuild.data(), b->T.rebuild.size() * sizeof(lt::RebuildTile));
+  if (e == hipSuccess) e = up(b->w.gram, b->T.gram.data(), b->T.gram.size() * sizeof(lt::GramTile));
+  if (e == hipSuccess) e = up(b->w.chol, b->T.chol.data(), b->T.chol.size() * sizeof(lt::CholItem));
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -1185,6 +1221,12 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
   {
     ProfScope ps(prof ? h : nullptr, LT_PROF_FORWARD);
     if ((e = lt::launch_gemm_grouped(b->w.ptrs, b->w.gemm, (int)T.gemm.size(), T.prec, 0, s)) != hipSuccess)
+      return e;
+  }
+  if (!T.chol.empty()) {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_PRECOND);
+    if ((e = lt::launch_gram_tiles(b->w.ptrs, b->w.gram, (int)T.gram.size(), s)) != hipSuccess) return e;
+    if ((e = lt::launch_chol_items(b->w.ptrs, b->w.chol, (int)T.chol.size(), T.chol_nmax, s)) != hipSuccess)
       return e;
   }
   {

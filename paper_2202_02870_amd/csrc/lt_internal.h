@@ -180,6 +180,8 @@ struct ProbDev {
   int max_iter;
   double tol, mu_bar;
   int gate_until_floor, enabled;
+  double* C;                 // preconditioning: per-slice Gram matrix / Cholesky factor (or null)
+  int precond, pad2;         // nonzero: the SVT runs the Jacobi on R^T (n x n) and rebuilds (W B) B^T
   // dynamic
   int iter, parity, done, active;   // done: 1 converged, 2 iteration limit
   double beta, tau, num, den, crit;
@@ -190,12 +192,17 @@ struct ProbDev {
 struct GemmTile { int prob, tx, ty, part; };          // one 64x64 output tile
 struct SvtItem { int prob, slice0, nsub, qeff; };    // nsub same-shape slices, qeff row chunks
 struct RebuildTile { int prob, slice, j0, pad; };    // 16 working columns of one slice
+struct GramTile { int prob, slice, tile, pad; };     // one lower-triangle 32x32 tile of C = W^T W
+struct CholItem { int prob, slice; };                // one slice's Cholesky factorization
 
 hipError_t launch_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles, int ntiles, int precision,
                                int inverse, hipStream_t s);
 hipError_t launch_batch_begin(ProbDev* const* probs, int nprob, hipStream_t s);
 hipError_t launch_batch_end(ProbDev* const* probs, int nprob, hipStream_t s);
 hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, hipStream_t s);
+hipError_t launch_gram_tiles(ProbDev* const* probs, const GramTile* tiles, int ntiles, hipStream_t s);
+hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
+                             hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
 struct JacobiBatchConfig {

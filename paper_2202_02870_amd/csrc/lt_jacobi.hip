@@ -265,7 +265,8 @@ struct Job {
   int32_t* rank;
   int32_t* sweeps;
   double* sigma;
-  long long stride;
+  long long stride;       // between the packed slices' inputs
+  long long out_stride;   // between their outputs
   int I1, I2, nsub, qeff, mode;
   double tau;
   unsigned long long* sweep_total;
@@ -479,7 +480,7 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   }
   __syncthreads();
   // kept columns, scaled, through LDS: tops, then bottoms
-  float* out = jb.out + (long long)subr * jb.stride;
+  float* out = jb.out + (long long)subr * jb.out_stride;
   const int j0 = active ? ctl[3 + g] : 0;
   double sca, scb;
   int da, db;
@@ -526,6 +527,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
   const int n = a.I1 < a.I2 ? a.I1 : a.I2;
   jb.sigma = a.sigma ? a.sigma + (long long)s * n : nullptr;
   jb.stride = a.slice_stride;
+  jb.out_stride = a.bk_stride ? a.bk_stride : a.slice_stride;
   jb.I1 = a.I1;
   jb.I2 = a.I2;
   jb.nsub = 1;
@@ -549,14 +551,25 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
   ProbDev* pd = probs[it.prob];
   if (!pd->active) return;
   Job jb;
-  jb.src = pd->Gh + (long long)it.slice0 * pd->N;
   jb.out = pd->Bk + (long long)it.slice0 * pd->N;
+  jb.out_stride = pd->N;
+  if (pd->precond) {
+    // Jacobi on the slices' Cholesky factors L = R^T (n x n, FP32 over each
+    // slice's FP64 Gram block)
+    const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+    jb.src = reinterpret_cast<const float*>(pd->C) + (long long)it.slice0 * 2 * n * n;
+    jb.stride = 2LL * n * n;
+    jb.I1 = n;
+    jb.I2 = n;
+  } else {
+    jb.src = pd->Gh + (long long)it.slice0 * pd->N;
+    jb.stride = pd->N;
+    jb.I1 = pd->I1;
+    jb.I2 = pd->I2;
+  }
   jb.rank = pd->rank + it.slice0;
   jb.sweeps = pd->sweeps + it.slice0;
   jb.sigma = nullptr;
-  jb.stride = pd->N;
-  jb.I1 = pd->I1;
-  jb.I2 = pd->I2;
   jb.nsub = it.nsub;
   jb.qeff = it.qeff;
   jb.mode = 0;
@@ -663,7 +676,8 @@ __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, co
   const ProbDev* pd = probs[t.prob];
   if (!pd->active) return;
   const long long off = (long long)t.slice * pd->N;
-  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0, false);
+  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
+               pd->precond != 0);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------

@@ -37,20 +37,18 @@ __device__ inline float w_elem(const float* W, bool trans, int I1, int row, int 
 
 constexpr int GT = 32;   // Gram output tile (GT x GT), rows of W per LDS chunk
 
-// C (lower triangle, n x n column-major FP64 per slice) = W^T W.  One workgroup
-// per lower-triangle tile pair (ti >= tj) of one slice; 256 lanes, 2 x 2
+// C (lower triangle, n x n column-major FP64) = W^T W for one slice: one
+// lower-triangle tile pair (ti >= tj, index t) per workgroup; 256 lanes, 2 x 2
 // outputs each.
-__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+__device__ void gram_tile(const float* W, int I1, int I2, double* C, int t) {
   __shared__ double Ai[GT][GT + 1];
   __shared__ double Aj[GT][GT + 1];
-  const int s = blockIdx.y;
-  int t = blockIdx.x, ti = 0;
+  int ti = 0;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int tj = t - ti * (ti + 1) / 2;
-  const bool trans = a.I1 < a.I2;
-  const int m = trans ? a.I2 : a.I1;
-  const int n = trans ? a.I1 : a.I2;
-  const float* W = a.W + (long long)s * a.slice_stride;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
   for (int k0 = 0; k0 < m; k0 += GT) {
@@ -64,8 +62,8 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
         c = idx / GT;
       }
       const int row = k0 + kk, ci = ti * GT + c, cj = tj * GT + c;
-      Ai[kk][c] = (row < m && ci < n) ? (double)w_elem(W, trans, a.I1, row, ci) : 0.0;
-      Aj[kk][c] = (row < m && cj < n) ? (double)w_elem(W, trans, a.I1, row, cj) : 0.0;
+      Ai[kk][c] = (row < m && ci < n) ? (double)w_elem(W, trans, I1, row, ci) : 0.0;
+      Aj[kk][c] = (row < m && cj < n) ? (double)w_elem(W, trans, I1, row, cj) : 0.0;
     }
     __syncthreads();
 #pragma unroll 8
@@ -79,7 +77,6 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
     }
     __syncthreads();
   }
-  double* C = a.C + (long long)s * a.c_stride;
   const int i0 = ti * GT + 2 * tx, j0 = tj * GT + 2 * ty;
   const double v[2][2] = {{c00, c01}, {c10, c11}};
 #pragma unroll
@@ -89,6 +86,19 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
       const int i = i0 + di, j = j0 + dj;
       if (i < n && j < n && i >= j) C[i + (long long)j * n] = v[di][dj];
     }
+}
+
+__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+  const int s = blockIdx.y;
+  gram_tile(a.W + (long long)s * a.slice_stride, a.I1, a.I2, a.C + (long long)s * a.c_stride, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_gram_tiles(ProbDev* const* probs, const GramTile* tiles) {
+  const GramTile t = tiles[blockIdx.x];
+  const ProbDev* pd = probs[t.prob];
+  if (!pd->active) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  gram_tile(pd->Gh + (long long)t.slice * pd->N, pd->I1, pd->I2, pd->C + (long long)t.slice * n * n, t.tile);
 }
 
 __device__ inline int tri_off(int j, int n) { return j * n - (j * (j - 1)) / 2; }   // column j of a packed lower triangle
@@ -121,13 +131,13 @@ __device__ inline void wave_sync() {
 // block.  A pivot at or below n * 64 eps64 * max diag(C) zeroes its column.
 // Writes L in FP32 (n x n column-major, zero above the diagonal) over the first
 // half of the slice's own C region.
-__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
+__device__ void chol_slice(double* Cs, int n) {
   extern __shared__ __attribute__((aligned(16))) double T[];
   __shared__ double dmax_s;
   __shared__ double dinv_s[CB];   // reciprocals of the current block's diagonal (0: zeroed column)
-  const int s = blockIdx.x, n = a.n, tid = threadIdx.x, nt = blockDim.x;
-  const double* C = a.C + (long long)s * a.c_stride;
-  float* L = reinterpret_cast<float*>(a.C + (long long)s * a.c_stride);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* C = Cs;
+  float* L = reinterpret_cast<float*>(Cs);
   // one flat pass (independent loads in flight), lower triangle only
   for (int e = tid; e < n * n; e += nt) {
     const int i = e % n, j = e / n;
@@ -218,6 +228,18 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
+  chol_slice(a.C + (long long)blockIdx.x * a.c_stride, a.n);
+}
+
+__global__ __launch_bounds__(1024) void k_chol_items(ProbDev* const* probs, const CholItem* items) {
+  const CholItem it = items[blockIdx.x];
+  const ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  chol_slice(pd->C + (long long)it.slice * n * n, n);
+}
+
 }  // namespace
 
 size_t chol_lds_bytes(int n) { return (size_t)n * (n + 1) / 2 * sizeof(double); }
@@ -227,6 +249,24 @@ hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
   const int n = a.I1 < a.I2 ? a.I1 : a.I2;
   const int nt = (n + GT - 1) / GT;
   hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2, a.nslices), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_tiles(ProbDev* const* probs, const GramTile* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_tiles, dim3(ntiles), dim3(256), 0, s, probs, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
+                             hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (nmax < 1 || nmax > CH_NMAX) return hipErrorInvalidValue;
+  const size_t lds = chol_lds_bytes(nmax);
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_items, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_items, dim3(nitems), dim3(nmax <= 64 ? 256 : 1024), lds, s, probs, items);
   return hipGetLastError();
 }
 

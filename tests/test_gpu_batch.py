@@ -42,11 +42,12 @@ def _problems(iters, tol=0.0, seed0=300):
     return out
 
 
-def _gpu_problem(lt, p, precision="f32", check_every=1):
+def _gpu_problem(lt, p, precision="f32", check_every=1, precondition=True):
     import torch
     s = p.schedule
     params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=s["tol"],
-                           max_iter=s["max_iter"], check_every=check_every, precision=precision)
+                           max_iter=s["max_iter"], check_every=check_every, precision=precision,
+                           precondition=precondition)
     return lt.Problem(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
 
 
@@ -58,10 +59,11 @@ def _run(lt, gps, ticks, use_graph=True):
     return out
 
 
-def test_batch_mix_matches_oracle(lt):
+@pytest.mark.parametrize("precondition", [True, False])
+def test_batch_mix_matches_oracle(lt, precondition):
     iters = 60
     ps = _problems(iters)
-    gps = [_gpu_problem(lt, p) for p in ps]
+    gps = [_gpu_problem(lt, p, precondition=precondition) for p in ps]
     st = _run(lt, gps, iters)
     for p, gp, (rep, done) in zip(ps, gps, st):
         s = p.schedule
@@ -139,11 +141,11 @@ def test_batch_matches_single_problem_path(lt):
     _run(lt, [gp], 80)
     import torch
     s = p.schedule
-    # the same algorithm (Jacobi on the slices themselves): equal to FP32 rounding
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80, precondition=False)
+    # the same algorithm (both preconditioned): equal to FP32 rounding
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 1e-6
-    # the preconditioned single-problem path: the same result to the Jacobi tolerance
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
+    # the Jacobi on the slices themselves: the same result to the Jacobi tolerance
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80, precondition=False)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 5e-5
