@@ -40,7 +40,7 @@ constexpr int GT = 32;   // Gram output tile (GT x GT), rows of W per LDS chunk
 // C (lower triangle, n x n column-major FP64) = W^T W for one slice: one
 // lower-triangle tile pair (ti >= tj, index t) per workgroup; 256 lanes, 2 x 2
 // outputs each.
-__device__ void gram_tile(const float* W, int I1, int I2, double* C, int t) {
+__device__ __attribute__((always_inline)) void gram_tile(const float* W, int I1, int I2, double* C, int t) {
   __shared__ double Ai[GT][GT + 1];
   __shared__ double Aj[GT][GT + 1];
   int ti = 0;
@@ -131,7 +131,7 @@ __device__ inline void wave_sync() {
 // block.  A pivot at or below n * 64 eps64 * max diag(C) zeroes its column.
 // Writes L in FP32 (n x n column-major, zero above the diagonal) over the first
 // half of the slice's own C region.
-__device__ void chol_slice(double* Cs, int n) {
+__device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
   extern __shared__ __attribute__((aligned(16))) double T[];
   __shared__ double dmax_s;
   __shared__ double dinv_s[CB];   // reciprocals of the current block's diagonal (0: zeroed column)
