@@ -81,8 +81,9 @@ def main():
                     help="serve workload: Poisson arrival rate (1/s); 0 = calibrate to 0.7 x saturation")
     ap.add_argument("--per-request-iters", type=int, default=5,
                     help="mix workload: iterations of the plain per-request form timed for comparison")
-    ap.add_argument("--cpu-iters", type=int, default=30,
-                    help="oracle iterations timed on the host (bounded CPU sample)")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle iterations timed on the host (bounded CPU sample; default 30 for "
+                         "video, 10 for large: the iterates are nonzero from the sixth and eighth iterations)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="video/large: run one 256 MiB device copy before the timed region (counter reference)")
@@ -190,9 +191,10 @@ def main():
         "roofline": roofline,
     }
 
-    if not args.no_cpu_baseline and args.cpu_iters > 0:
+    cpu_iters = args.cpu_iters if args.cpu_iters is not None else (30 if args.workload == "video" else 10)
+    if not args.no_cpu_baseline and cpu_iters > 0:
         import oracle as o
-        k = args.cpu_iters
+        k = cpu_iters
         mats = o.mats_for(shape, list(p.kinds))
         c0 = time.perf_counter()
         Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"],
@@ -204,8 +206,13 @@ def main():
         Xg, _, _ = lt.complete_pga(M, mask, params(k), p.kinds, out=X, ws=ws)
         Xg = lt.to_host(Xg).astype(np.float64)
         nrm = float(np.linalg.norm(Xo))
-        err = float(np.linalg.norm(Xg - Xo) / nrm) if nrm > 0 else None
-        line["parity"] = {"iters": k, "rel_err_vs_oracle": err, "bound": 1e-4 if args.precision == "f32" else 1e-2}
+        # the first iterations threshold every singular value (mu_k is large), so a
+        # sample that short compares zero tensors: report the GPU iterate's own norm then
+        if nrm > 0:
+            err = {"rel_err_vs_oracle": float(np.linalg.norm(Xg - Xo) / nrm)}
+        else:
+            err = {"abs_norm_gpu_where_oracle_is_zero": float(np.linalg.norm(Xg))}
+        line["parity"] = {"iters": k, **err, "bound": 1e-4 if args.precision == "f32" else 1e-2}
 
     print(json.dumps(line), flush=True)
 

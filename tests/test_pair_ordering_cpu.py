@@ -1,0 +1,98 @@
+"""Host model of the Jacobi kernel's pair schedule (the slot moves of its ring
+phases, splits and final circle tournament, written with the kernel's index
+formulas): every sweep meets every column pair exactly once, in 2*ceil(n/2) - 1
+rounds, for any column count, starting from any arrangement."""
+import itertools
+
+import numpy as np
+import pytest
+
+
+def sweep(top, bot):
+    """One sweep on slots (top[g], bot[g]); yields the pairs of each round and
+    leaves the arrangement the kernel leaves."""
+    S = len(top)
+    c, ring, s0 = S, S % 2 == 0, [0] * S
+    idx = list(range(S))          # i = g - s0 per slot
+    r = 0
+    nrounds = 2 * S - 1
+    for k in range(nrounds):
+        yield list(zip(top, bot))
+        if k + 1 == nrounds:
+            break
+        if ring and r + 1 < c:
+            # bottoms move one slot down the range: slot g takes slot nxt's bottom
+            nb = list(bot)
+            for g in range(S):
+                i = idx[g]
+                nxt = s0[g] + (0 if i + 1 == c else i + 1)
+                nb[g] = bot[nxt]
+            bot[:] = nb
+            r += 1
+        elif ring:
+            h = c // 2
+            nt, nb = list(top), list(bot)
+            for g in range(S):
+                if idx[g] < h:
+                    nb[g] = top[g + h]       # first half takes the second half's tops as bottoms
+                else:
+                    nt[g] = bot[g - h]       # second half takes the first half's bottoms as tops
+            top[:], bot[:] = nt, nb
+            c = h
+            ring = c % 2 == 0
+            for g in range(S):
+                s0[g] = (g // c) * c
+                idx[g] = g - s0[g]
+            r = 0
+        else:
+            # circle over each range's 2c columns through positions pos0 .. pos0 + c
+            buf = {}
+            for g in range(S):
+                pos0 = s0[g] + s0[g] // c
+                buf[pos0 + idx[g]] = top[g]
+                if idx[g] == 0:
+                    buf[pos0 + c] = bot[g]
+            nt = list(top)
+            for g in range(S):
+                pos0 = s0[g] + s0[g] // c
+                i = idx[g]
+                if i != 0:
+                    nt[g] = buf[pos0 + (c if i == 1 else i - 1)]
+                    buf[pos0 + i - 1] = bot[g]
+            nb = [buf[s0[g] + s0[g] // c + idx[g]] for g in range(S)]
+            top[:], bot[:] = nt, nb
+            r += 1
+
+
+@pytest.mark.parametrize("n", list(range(2, 70)) + [96, 100, 128, 144, 150, 176, 200, 256])
+def test_every_pair_once_per_sweep(n):
+    S = (n + 1) // 2
+    rng = np.random.default_rng(n)
+    perm = rng.permutation(2 * S)
+    top, bot = list(perm[:S]), list(perm[S:])
+    for _ in range(3):           # consecutive sweeps start from the previous arrangement
+        seen = {}
+        rounds = 0
+        for pairs in sweep(top, bot):
+            rounds += 1
+            for a, b in pairs:
+                if a < n and b < n:   # ids >= n are the zero padding column
+                    key = (min(a, b), max(a, b))
+                    seen[key] = seen.get(key, 0) + 1
+        assert rounds == 2 * S - 1
+        assert len(seen) == n * (n - 1) // 2
+        assert all(v == 1 for v in seen.values())
+        assert sorted(top + bot) == list(range(2 * S))
+
+
+def test_ring_phases_move_one_column_per_slot():
+    """In a ring round only the bottoms change (the property that halves the
+    LDS exchange of the circle tournament, where both columns move)."""
+    top, bot = list(range(72)), list(range(72, 144))
+    it = sweep(top, bot)
+    prev = next(it)
+    for _ in range(71):          # the first ring phase (c = 72)
+        cur = next(it)
+        assert [a for a, _ in cur] == [a for a, _ in prev]
+        assert sorted(b for _, b in cur) == sorted(b for _, b in prev)
+        prev = cur
