@@ -272,6 +272,7 @@ struct SvtWs {
   int32_t* rank = nullptr;
   int32_t* sweeps = nullptr;
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
+  float* work = nullptr;  // blocked Jacobi: per-slice working buffers
 };
 
 // The preconditioned SVT path applies when the FP64 Cholesky of an n x n Gram
@@ -285,6 +286,30 @@ bool precond_shape(const Shape& s) {
 
 long long precond_n(const Shape& s) { return s.I1 < s.I2 ? s.I1 : s.I2; }
 
+// Slices the register-resident Jacobi kernel cannot hold (more than 256
+// columns, or columns too long for the lanes a pair can have) run the blocked
+// kernel.  Its layout is fixed by the shape and a 160 KiB LDS budget (MI355X),
+// so workspace sizes do not depend on the device; the launch checks the
+// device's LDS.
+constexpr int kBlkLdsBudget = 160 * 1024;
+
+bool blocked_shape(const Shape& s, lt::JacobiBlkConfig* cfg) {
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
+  const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  if (lt::jacobi_reg_shape(m, n)) return false;
+  lt::JacobiBlkConfig c;
+  if (lt::jacobi_blk_pick_config(m, n, kBlkLdsBudget, &c) != 0) return false;
+  if (cfg) *cfg = c;
+  return true;
+}
+
+int check_blk_lds(lt_handle* h, const Shape& s, const lt::JacobiBlkConfig& c) {
+  if (c.lds > (size_t)h->max_lds)
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the blocked Jacobi kernel needs %zu bytes of LDS",
+                s.I1, s.I2, c.lds);
+  return LT_OK;
+}
+
 void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   carve_transform(c, s, prec, &w->t);
   w->Gh = c.take<float>((size_t)s.nel);
@@ -292,6 +317,8 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
   if (precond_shape(s)) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
+  lt::JacobiBlkConfig bc;
+  if (blocked_shape(s, &bc)) w->work = c.take<float>((size_t)s.P * (size_t)bc.work_floats);
 }
 
 struct PgaWs {
@@ -360,6 +387,8 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   precond = precond && w.C && precond_shape(s);
   lt::JacobiArgs j{};
   lt::JacobiConfig cfg;
+  lt::JacobiBlkConfig bcfg;
+  bool blocked = false;
   int rc;
   if (precond) {
     // Jacobi on L = R^T (n x n), C = W^T W = R^T R: its kept columns are the
@@ -385,6 +414,15 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
     j.I1 = n;
     j.I2 = n;
     j.bk_stride = s.N;
+  } else if (blocked_shape(s, &bcfg)) {
+    if ((rc = check_blk_lds(h, s, bcfg))) return rc;
+    if (!w.work) return fail(h, LT_ERR_WORKSPACE, "no blocked-Jacobi working buffer in the workspace");
+    blocked = true;
+    j.src = Gh;
+    j.slice_stride = s.N;
+    j.I1 = (int)s.I1;
+    j.I2 = (int)s.I2;
+    j.work = w.work;
   } else {
     if ((rc = jacobi_config(h, s, &cfg))) return rc;
     j.src = Gh;
@@ -405,7 +443,8 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   j.maxsweep_hits = hits;
   {
     ProfScope ps(h, LT_PROF_JACOBI);
-    HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+    if (blocked) HIP_TRY(h, lt::launch_jacobi_blk(j, bcfg, h->stream));
+    else HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
   }
   lt::RebuildArgs r{};
   r.W = Gh;
@@ -427,7 +466,8 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
 bool precond_requested(const lt_svd_opts* o) { return !(o && o->no_precondition); }
 
 // The SVT of this shape is supported: by the preconditioned path (any m, n up
-// to LT_PRECOND_MAX_N) or by the Jacobi kernel on the slice itself.
+// to LT_PRECOND_MAX_N), by the register-resident Jacobi kernel on the slice
+// itself, or by the blocked kernel (n <= 512, m <= 2048).
 int check_svt_shape(lt_handle* h, const Shape& s, bool precond) {
   lt::JacobiConfig probe;
   if (precond && precond_shape(s)) {
@@ -435,6 +475,8 @@ int check_svt_shape(lt_handle* h, const Shape& s, bool precond) {
     sq.I1 = sq.I2 = precond_n(s);
     return jacobi_config(h, sq, &probe);
   }
+  lt::JacobiBlkConfig bc;
+  if (blocked_shape(s, &bc)) return check_blk_lds(h, s, bc);
   return jacobi_config(h, s, &probe);
 }
 
@@ -453,6 +495,7 @@ struct ProblemWs {
   double* partials = nullptr;
   unsigned int* scratch = nullptr;
   double* C = nullptr;   // preconditioning: Gram matrices / Cholesky factors
+  float* work = nullptr;  // blocked Jacobi: per-slice working buffers
   int n_partials = 0;
 };
 
@@ -476,6 +519,8 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool preco
   w->partials = c.take<double>(2 * (size_t)w->n_partials);
   w->scratch = c.take<unsigned int>(4);
   if (precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
+  lt::JacobiBlkConfig bc;
+  if (!precond && blocked_shape(s, &bc)) w->work = c.take<float>((size_t)s.P * (size_t)bc.work_floats);
 }
 
 int check_pga_params(lt_handle* h, const lt_pga_params* p) {
@@ -511,6 +556,14 @@ struct BatchTables {
   std::vector<lt::GramTile> gram;
   std::vector<lt::CholItem> chol;
   int chol_nmax = 0;
+  // blocked Jacobi: items grouped by lanes per pair (16, 32, 64), each group's
+  // launch shape; rebuild tiles of slices with more than 256 columns
+  std::vector<lt::CholItem> blk;
+  int blk_count[3] = {0, 0, 0};
+  int blk_threads[3] = {0, 0, 0};
+  size_t blk_lds[3] = {0, 0, 0};
+  std::vector<lt::RebuildTile> rebuild_wide;
+  bool any_reg = false;
   lt::JacobiBatchConfig cfg{};
   int prec = 0, max_sweeps = 40;
   double tol = 1e-6;
@@ -520,7 +573,9 @@ struct BatchTables {
 int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, BatchTables* T) {
   if (n <= 0 || !probs) return fail(h, LT_ERR_ARG, "empty batch");
   std::vector<Shape> shapes(n);
-  std::vector<int> ms(n), ns(n), nsub(n), qeff(n);
+  std::vector<int> ms(n), ns(n), nsub(n, 1), qeff(n, 1);
+  std::vector<int> blocked(n, 0);
+  std::vector<lt::JacobiBlkConfig> bcfg(n);
   for (int i = 0; i < n; ++i) {
     int rc = parse(h, probs[i].desc, &shapes[i]);
     if (rc) return rc;
@@ -536,15 +591,37 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     }
     ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
     ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
-    if (problem_precond(shapes[i], &probs[i].params)) ms[i] = ns[i];   // Jacobi on the n x n factor
+    if (problem_precond(shapes[i], &probs[i].params)) {
+      ms[i] = ns[i];   // Jacobi on the n x n factor
+    } else if (blocked_shape(shapes[i], &bcfg[i])) {
+      int rc2 = check_blk_lds(h, shapes[i], bcfg[i]);
+      if (rc2) return rc2;
+      blocked[i] = 1;
+    }
   }
   if (force_G == 0) {
     const char* env = getenv("LT_JACOBI_G");
     force_G = env ? atoi(env) : 0;
   }
-  if (lt::jacobi_batch_config(ms.data(), ns.data(), n, h->max_lds, force_G, &T->cfg,
-                              nsub.data(), qeff.data()) != 0)
-    return fail(h, LT_ERR_SHAPE, "a slice shape of the batch exceeds the register-resident Jacobi kernel");
+  // the register-resident kernel's configuration covers the other problems
+  std::vector<int> rm, rn, ridx;
+  for (int i = 0; i < n; ++i)
+    if (!blocked[i]) {
+      rm.push_back(ms[i]);
+      rn.push_back(ns[i]);
+      ridx.push_back(i);
+    }
+  T->any_reg = !ridx.empty();
+  if (T->any_reg) {
+    std::vector<int> rsub(ridx.size()), rq(ridx.size());
+    if (lt::jacobi_batch_config(rm.data(), rn.data(), (int)ridx.size(), h->max_lds, force_G, &T->cfg,
+                                rsub.data(), rq.data()) != 0)
+      return fail(h, LT_ERR_SHAPE, "a slice shape of the batch exceeds the register-resident Jacobi kernel");
+    for (size_t k = 0; k < ridx.size(); ++k) {
+      nsub[ridx[k]] = rsub[k];
+      qeff[ridx[k]] = rq[k];
+    }
+  }
   T->ptrs.resize(n);
   std::vector<std::pair<double, lt::SvtItem>> costed;
   for (int i = 0; i < n; ++i) {
@@ -557,17 +634,20 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     const int ntx = (int)((s.N + 63) / 64), nty = (int)((s.P + 63) / 64);
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) T->gemm.push_back(lt::GemmTile{i, tx, ty, ty * ntx + tx});
-    const int rounds = 2 * ((ns[i] + 1) / 2) - 1;
-    for (int s0 = 0; s0 < (int)s.P; s0 += nsub[i]) {
-      const int k = (int)(s.P - s0) < nsub[i] ? (int)(s.P - s0) : nsub[i];
-      costed.push_back({(double)rounds * qeff[i], lt::SvtItem{i, s0, k, qeff[i]}});
+    if (!blocked[i]) {
+      const int rounds = 2 * ((ns[i] + 1) / 2) - 1;
+      for (int s0 = 0; s0 < (int)s.P; s0 += nsub[i]) {
+        const int k = (int)(s.P - s0) < nsub[i] ? (int)(s.P - s0) : nsub[i];
+        costed.push_back({(double)rounds * qeff[i], lt::SvtItem{i, s0, k, qeff[i]}});
+      }
     }
     // rebuild tiles over the working matrix's columns: W's n columns, or W^T's
     // m columns when the preconditioned SVT rebuilds (W B) B^T
     const int mw = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
     const int ncols = pc ? mw : ns[i];
+    std::vector<lt::RebuildTile>& rt = ns[i] > 256 ? T->rebuild_wide : T->rebuild;
     for (int sl = 0; sl < (int)s.P; ++sl)
-      for (int j0 = 0; j0 < ncols; j0 += 16) T->rebuild.push_back(lt::RebuildTile{i, sl, j0, 0});
+      for (int j0 = 0; j0 < ncols; j0 += 16) rt.push_back(lt::RebuildTile{i, sl, j0, 0});
     T->rebuild_slices += (size_t)s.P;
     if (pc) {
       const int tg = (ns[i] + 31) / 32;
@@ -576,6 +656,17 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
         T->chol.push_back(lt::CholItem{i, sl});
       }
       T->chol_nmax = ns[i] > T->chol_nmax ? ns[i] : T->chol_nmax;
+    }
+  }
+  // blocked items, grouped by lanes per pair
+  const int blkG[3] = {16, 32, 64};
+  for (int gi = 0; gi < 3; ++gi) {
+    for (int i = 0; i < n; ++i) {
+      if (!blocked[i] || bcfg[i].G != blkG[gi]) continue;
+      for (int sl = 0; sl < (int)shapes[i].P; ++sl) T->blk.push_back(lt::CholItem{i, sl});
+      T->blk_count[gi] += (int)shapes[i].P;
+      T->blk_threads[gi] = bcfg[i].threads > T->blk_threads[gi] ? bcfg[i].threads : T->blk_threads[gi];
+      T->blk_lds[gi] = bcfg[i].lds > T->blk_lds[gi] ? bcfg[i].lds : T->blk_lds[gi];
     }
   }
   // longest first, ties by problem then slice (deterministic)
@@ -594,6 +685,8 @@ struct BatchWs {
   lt::RebuildTile* rebuild = nullptr;
   lt::GramTile* gram = nullptr;
   lt::CholItem* chol = nullptr;
+  lt::CholItem* blk = nullptr;
+  lt::RebuildTile* rebuild_wide = nullptr;
 };
 
 // The item count depends on how many slices a workgroup packs (device LDS);
@@ -605,6 +698,8 @@ void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
   w->rebuild = c.take<lt::RebuildTile>(T.rebuild.size());
   w->gram = c.take<lt::GramTile>(T.gram.size());
   w->chol = c.take<lt::CholItem>(T.chol.size());
+  w->blk = c.take<lt::CholItem>(T.blk.size());
+  w->rebuild_wide = c.take<lt::RebuildTile>(T.rebuild_wide.size());
 }
 
 }  // namespace
@@ -1041,14 +1136,17 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   int max_sweeps, prec;
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  {
+  lt::JacobiBlkConfig bcfg;
+  const bool blk = !problem_precond(s, &p->params) && blocked_shape(s, &bcfg);
+  if (blk) {
+    if ((rc = check_blk_lds(h, s, bcfg))) return rc;
+  } else {
     int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
     if (problem_precond(s, &p->params)) m = n;   // the Jacobi runs on the n x n factor
     lt::JacobiBatchConfig cfg;
     int ns, qe;
     if (lt::jacobi_batch_config(&m, &n, 1, h->max_lds, 0, &cfg, &ns, &qe) != 0)
-      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the register-resident Jacobi kernel",
-                  s.I1, s.I2);
+      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
   }
   const size_t need = lt_problem_workspace_bytes(p->desc, &p->params);
   if ((rc = check_ws(h, p->ws, p->ws_bytes, need))) return rc;
@@ -1102,6 +1200,14 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   d.enabled = 1;
   d.C = w.C;
   d.precond = pc ? 1 : 0;
+  if (blk) {
+    d.work = w.work;
+    d.work_stride = bcfg.work_floats;
+    d.blk_b = bcfg.b;
+    d.blk_n = bcfg.nblk;
+    d.blk_q = bcfg.qeff;
+    d.blk_G = bcfg.G;
+  }
   d.crit = NAN;
   HIP_TRY(h, hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, st));
   HIP_TRY(h, hipStreamSynchronize(st));   // host vectors and d go out of scope
@@ -1199,6 +1305,9 @@ int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, siz
     e = up(b->w.rebuild, b->T.rebuild.data(), b->T.rebuild.size() * sizeof(lt::RebuildTile));
   if (e == hipSuccess) e = up(b->w.gram, b->T.gram.data(), b->T.gram.size() * sizeof(lt::GramTile));
   if (e == hipSuccess) e = up(b->w.chol, b->T.chol.data(), b->T.chol.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess) e = up(b->w.blk, b->T.blk.data(), b->T.blk.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess)
+    e = up(b->w.rebuild_wide, b->T.rebuild_wide.data(), b->T.rebuild_wide.size() * sizeof(lt::RebuildTile));
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -1229,7 +1338,21 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
     if ((e = lt::launch_chol_items(b->w.ptrs, b->w.chol, (int)T.chol.size(), T.chol_nmax, s)) != hipSuccess)
       return e;
   }
-  {
+  if (!T.blk.empty()) {
+    // the long blocked slices first, so the register-resident items fill in behind them
+    ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
+    const int blkG[3] = {16, 32, 64};
+    int off = 0;
+    for (int gi = 0; gi < 3; ++gi) {
+      if (T.blk_count[gi] &&
+          (e = lt::launch_jacobi_blk_items(b->w.ptrs, b->w.blk + off, T.blk_count[gi], blkG[gi],
+                                           T.blk_threads[gi], T.blk_lds[gi], T.tol, T.max_sweeps, s)) !=
+              hipSuccess)
+        return e;
+      off += T.blk_count[gi];
+    }
+  }
+  if (T.any_reg) {
     ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
     if ((e = lt::launch_jacobi_items(b->w.ptrs, b->w.items, (int)T.items.size(), T.cfg, T.tol,
                                      T.max_sweeps, s)) != hipSuccess)
@@ -1237,7 +1360,10 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
   }
   {
     ProfScope ps(prof ? h : nullptr, LT_PROF_REBUILD);
-    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild, (int)T.rebuild.size(), s)) != hipSuccess)
+    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild, (int)T.rebuild.size(), 0, s)) != hipSuccess)
+      return e;
+    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild_wide, (int)T.rebuild_wide.size(), 1, s)) !=
+        hipSuccess)
       return e;
   }
   {

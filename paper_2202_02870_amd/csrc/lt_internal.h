@@ -98,6 +98,11 @@ struct JacobiArgs {
   unsigned long long* sweep_total;  // optional: atomic sum of sweeps
   unsigned long long* rot_total;    // optional: atomic sum of rotations
   unsigned int* maxsweep_hits;      // optional: atomic count of slices at max_sweeps
+  // blocked kernel only: per-slice working buffers (work_stride floats each) and
+  // the block layout (set by launch_jacobi_blk)
+  float* work;
+  long long work_stride;
+  int blk_b, blk_n;
 };
 
 struct JacobiConfig {
@@ -111,6 +116,22 @@ struct JacobiConfig {
 // Pick a kernel configuration for an m x n working matrix (0 on success).
 int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G);
 hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& cfg, hipStream_t s);
+// The register-resident kernel can hold an m x n working matrix (shape limits
+// only; the device's LDS is checked by jacobi_pick_config).
+bool jacobi_reg_shape(int m, int n);
+// Blocked Jacobi for working matrices the register-resident kernel cannot hold
+// (n <= 512, m <= 2048): columns live in a per-slice working buffer and one
+// workgroup per slice sweeps them block pair by block pair.
+struct JacobiBlkConfig {
+  int G;                 // lanes per column pair (16, 32 or 64)
+  int b, nblk;           // block width (even) and block count (even)
+  int qeff;              // 4-row chunks per lane (rows held: 4 G qeff)
+  int threads;
+  size_t lds;
+  long long work_floats; // working buffer per slice
+};
+int jacobi_blk_pick_config(int m, int n, int max_lds, JacobiBlkConfig* cfg);
+hipError_t launch_jacobi_blk(const JacobiArgs& a, const JacobiBlkConfig& cfg, hipStream_t s);
 
 // D (slice orientation) = rebuild from kept columns: D_W = Bk Bk^T W
 struct RebuildArgs {
@@ -182,6 +203,9 @@ struct ProbDev {
   int gate_until_floor, enabled;
   double* C;                 // preconditioning: per-slice Gram matrix / Cholesky factor (or null)
   int precond, pad2;         // nonzero: the SVT runs the Jacobi on R^T (n x n) and rebuilds (W B) B^T
+  float* work;               // blocked Jacobi: per-slice working buffers (or null)
+  long long work_stride;
+  int blk_b, blk_n, blk_q, blk_G;
   // dynamic
   int iter, parity, done, active;   // done: 1 converged, 2 iteration limit
   double beta, tau, num, den, crit;
@@ -199,7 +223,9 @@ hipError_t launch_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles, int
                                int inverse, hipStream_t s);
 hipError_t launch_batch_begin(ProbDev* const* probs, int nprob, hipStream_t s);
 hipError_t launch_batch_end(ProbDev* const* probs, int nprob, hipStream_t s);
-hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, hipStream_t s);
+// wide: tiles of slices with more than 256 columns (up to 512 kept columns)
+hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, int wide,
+                                hipStream_t s);
 hipError_t launch_gram_tiles(ProbDev* const* probs, const GramTile* tiles, int ntiles, hipStream_t s);
 hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
                              hipStream_t s);
@@ -216,5 +242,8 @@ int jacobi_batch_config(const int* m, const int* n, int count, int max_lds, int 
 hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int nitems,
                                const JacobiBatchConfig& cfg, double tol, int max_sweeps,
                                hipStream_t s);
+// Blocked kernel over items (problem, slice) of problems with blk_G == G.
+hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int G,
+                                   int threads, size_t lds, double tol, int max_sweeps, hipStream_t s);
 
 }  // namespace lt

@@ -514,6 +514,368 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   }
 }
 
+// The rounds of one sweep for the slot's pair (av, bv), for the blocked kernel
+// below: one rotation per round, then the move the pair schedule prescribes.
+// With ring_only, only the first ring phase runs (npairs rounds, npairs even),
+// in which every top meets every bottom once.  Returns this lane's count of
+// applied rotations (lane 0 of each group counts).  The register-resident body
+// keeps its own copy of these rounds: calling this function from it (inlined)
+// changed its register allocation and grew its stack frame.
+template <int G, int R>
+__device__ __attribute__((always_inline)) inline int sweep_rounds(
+    float (&av)[R], float (&bv)[R], double& na, double& nb, int& ida, int& idb, bool moving,
+    bool dot32, double tol, int npairs, int g, int l, int qeff, float* bufA, float* bufB, int nbuf,
+    int ldw, bool ring_only) {
+  int my_rot = 0;
+  // phase state: ranges of c slots; ring phase while c is even, circle
+  // tournament once c is odd; r counts the rounds of the current phase
+  int c = npairs;
+  bool ring = (c & 1) == 0;
+  int s0 = 0, i = g, r = 0;
+  const int nrounds = ring_only ? npairs : 2 * npairs - 1;
+  for (int k = 0; k < nrounds; ++k) {
+    // one rotation of the slot's pair (av, bv)
+    if (moving) {
+      const double d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv, qeff))
+                             : group_sum<G>(dot64<R>(av, bv, qeff));
+      const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
+      if (d != 0.0 && d * d > tol * tol * (pa * pb)) {   // |d| > tol sqrt(pa pb)
+        // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
+        // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+        // c = 1 / sqrt(1 + t^2), s = c t.  zeta is formed in FP64 (a
+        // difference of FP64 norms) and clamped where t falls below FP32
+        // resolution; t, c and s are FP32, the precision the rotation is
+        // applied in.  Every multiply-add is an explicit fma, so the rounding
+        // does not depend on how the compiler contracts an instantiation.
+        const double zeta = (pb - pa) * (0.5 * rcp64(d));
+        const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
+        const float z2 = fmaf(zf, zf, 1.f);
+        const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
+        const float t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
+        const float cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+        const float sf = cf * t;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          if (e < 4 * qeff) {
+            const float x = av[e], y = bv[e];
+            const float sy = sf * y, sx = sf * x;
+            av[e] = fmaf(cf, x, -sy);
+            bv[e] = fmaf(cf, y, sx);
+          }
+        }
+        na = fma(-(double)t, d, pa);
+        nb = fma((double)t, d, pb);
+        my_rot += (l == 0);
+      }
+    }
+    if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
+    if (ring && r + 1 < c) {
+      // ring: bottoms move one slot down the range (double-buffered: one barrier)
+      const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+      float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
+      if (moving) put_col<G, R>(buf, ldw, g, l, bv, qeff, nb, idb);
+      __syncthreads();
+      if (moving) get_col<G, R>(buf, ldw, nxt, l, bv, qeff, nb, idb);
+      if (nbuf == 1) __syncthreads();
+      ++r;
+    } else if (ring) {
+      // end of a ring phase: the first half's bottoms and the second half's
+      // tops trade places, leaving two ranges of c/2 slots
+      const int h = c >> 1;
+      const bool first = i < h;
+      if (moving) {
+        if (first) put_col<G, R>(bufB, ldw, g, l, bv, qeff, nb, idb);
+        else put_col<G, R>(bufB, ldw, g, l, av, qeff, na, ida);
+      }
+      __syncthreads();
+      if (moving) {
+        if (first) get_col<G, R>(bufB, ldw, g + h, l, bv, qeff, nb, idb);
+        else get_col<G, R>(bufB, ldw, g - h, l, av, qeff, na, ida);
+      }
+      if (nbuf == 1) __syncthreads();
+      c = h;
+      ring = (c & 1) == 0;
+      s0 = (g / c) * c;
+      i = g - s0;
+      r = 0;
+    } else {
+      // circle tournament over the range's 2c columns: slot 0 keeps its top,
+      // the other tops move one slot up (slot 1 takes slot 0's bottom), the
+      // bottoms move one slot down and the last slot's top becomes its
+      // bottom.  The range owns exchange positions pos0 .. pos0 + c of bufA;
+      // phase 1 stores tops at pos0 + i (slot 0's bottom at pos0 + c), phase 2
+      // stores the bottoms of slots 1.. one position lower, so that position
+      // pos0 + i then holds slot i's new bottom, the last slot's included.
+      const int pos0 = s0 + s0 / c;
+      if (moving) {
+        put_col<G, R>(bufA, ldw, pos0 + i, l, av, qeff, na, ida);
+        if (i == 0) put_col<G, R>(bufA, ldw, pos0 + c, l, bv, qeff, nb, idb);
+      }
+      __syncthreads();
+      if (moving && i != 0) {
+        get_col<G, R>(bufA, ldw, pos0 + (i == 1 ? c : i - 1), l, av, qeff, na, ida);
+        put_col<G, R>(bufA, ldw, pos0 + i - 1, l, bv, qeff, nb, idb);
+      }
+      __syncthreads();
+      if (moving) get_col<G, R>(bufA, ldw, pos0 + i, l, bv, qeff, nb, idb);
+      ++r;
+    }
+  }
+  return my_rot;
+}
+
+// ---- blocked Jacobi: slices whose columns do not fit one workgroup ----------
+//
+// The working matrix W (m x n) is copied to a per-slice buffer in the register
+// layout (column-major, mpad rows, nblk * b columns, zero padded).  The columns
+// form nblk (even) blocks of b (even) columns, and one workgroup runs every
+// sweep of its slice as nblk - 1 block rounds of the round-robin tournament over
+// the blocks: each block pair (A, B) of a round is loaded into the registers, A's
+// columns as the slots' tops and B's as their bottoms, and rotated.  In the
+// first block round of a sweep the rotations cover every pair among the 2b
+// columns (one sweep of the pair schedule on b slots); later block rounds run
+// one ring phase, which meets every column of A with every column of B.  So a
+// sweep again meets every column pair once.  Columns carry their index and go
+// back to their own place in the buffer; the norms are recomputed exactly at
+// every load.  Output: the kept columns in column order, as for the
+// register-resident kernel.
+struct BlkJob {
+  const float* src;
+  float* work;
+  float* out;
+  int32_t* rank;
+  int32_t* sweeps;
+  int I1, I2, b, nblk, qeff;
+  double tau;
+  unsigned long long* sweep_total;
+  unsigned long long* rot_total;
+  unsigned int* hits;
+};
+
+// Columns c0 .. c0 + ncols - 1 of W into LDS columns 0 .. ncols - 1 (rows
+// 0 .. mpad - 1, zeros beyond the slice), reads coalesced along the slice's
+// contiguous dimension.
+__device__ inline void stage_cols(const float* __restrict__ A, float* buf, int ldw, bool trans, int I1,
+                                  int m, int n, int c0, int ncols, int mpad, int t, int nt) {
+  const int total = ncols * mpad;
+  if (!trans) {
+    for (int e = t; e < total; e += nt) {
+      const int p = e / mpad, row = e - p * mpad;
+      const int col = c0 + p;
+      buf[(size_t)p * ldw + row] = (row < m && col < n) ? A[(long long)col * I1 + row] : 0.f;
+    }
+  } else {
+    for (int e = t; e < total; e += nt) {
+      const int row = e / ncols, p = e - row * ncols;
+      const int col = c0 + p;
+      buf[(size_t)p * ldw + row] = (row < m && col < n) ? A[(long long)row * I1 + col] : 0.f;
+    }
+  }
+}
+
+// A working-buffer column <-> a lane's register rows (the chunk layout of
+// put_col / get_col, ld = mpad = 4 G qeff).
+template <int G, int R>
+__device__ inline void load_work_col(const float* Wk, int mpad, int col, int l, float (&v)[R], int qeff) {
+  const float4* p = reinterpret_cast<const float4*>(Wk + (size_t)col * mpad);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    if (q < qeff) {
+      const float4 x = p[l + G * q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+  }
+}
+
+template <int G, int R>
+__device__ inline void store_work_col(float* Wk, int mpad, int col, int l, const float (&v)[R], int qeff) {
+  float4* p = reinterpret_cast<float4*>(Wk + (size_t)col * mpad);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q)
+    if (q < qeff) p[l + G * q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+// Block at position pos of block round br in the round-robin tournament over
+// nblk blocks: position 0 keeps block 0, the others rotate.
+__device__ inline int blk_at(int pos, int br, int nblk) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + br) % (nblk - 1);
+}
+
+__host__ __device__ inline size_t blk_lds_bytes(int b, int ldw) {
+  const size_t bytes = kWgCtlBytes + (size_t)exch_positions(b) * ldw * sizeof(float) +
+                       ((size_t)b + 4) * sizeof(int);
+  return (bytes + 15) & ~size_t(15);
+}
+
+template <int G, int R>
+__device__ __attribute__((noinline)) void jacobi_blk_body(const BlkJob& jb, double tol, int max_sweeps,
+                                                          unsigned char* smem) {
+  const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff, b = jb.b, nblk = jb.nblk;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int mpad = 4 * G * qeff;
+  const int ldw = mpad + 4;
+  const int ncols = nblk * b;
+  const int tps = b * G;   // lanes holding slots; the rest of the workgroup only joins barriers
+  const int tid = threadIdx.x;
+  const bool active = tid < tps;
+  const int g = active ? tid / G : 0, l = tid % G;
+  int* wg_ctl = reinterpret_cast<int*>(smem);
+  float* buf = reinterpret_cast<float*>(smem + kWgCtlBytes);
+  // ctl[2]: kept total; ctl[3 + g]: per-slot output offsets
+  int* ctl = reinterpret_cast<int*>(buf + (size_t)exch_positions(b) * ldw);
+  float* __restrict__ Wk = jb.work;
+
+  // ---- copy in: b columns at a time through LDS, written out coalesced ----
+  for (int c0 = 0; c0 < ncols; c0 += b) {
+    stage_cols(jb.src, buf, ldw, trans, I1, m, n, c0, b, mpad, tid, blockDim.x);
+    __syncthreads();
+    for (int e = tid; e < b * mpad; e += blockDim.x) {
+      const int p = e / mpad, row = e - p * mpad;
+      Wk[(size_t)(c0 + p) * mpad + row] = buf[(size_t)p * ldw + row];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    wg_ctl[0] = 0;
+    wg_ctl[1] = 0;
+  }
+  __syncthreads();
+
+  float av[R], bv[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    av[e] = 0.f;
+    bv[e] = 0.f;
+  }
+  const bool dot32 = tol >= 1e-6;
+  int sweep = 0, my_sweeps = 0;
+  bool converged = false;
+  long long rotations = 0;
+  for (;;) {
+    int my_rot = 0;
+    for (int br = 0; br < nblk - 1; ++br) {
+      for (int pi = 0; pi < nblk / 2; ++pi) {
+        const int A = blk_at(pi, br, nblk), B = blk_at(nblk - 1 - pi, br, nblk);
+        int ida = A * b + g, idb = B * b + g;
+        if (active) {
+          load_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
+          load_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
+        }
+        double na = group_sum<G>(dot64<R>(av, av, qeff));
+        double nb = group_sum<G>(dot64<R>(bv, bv, qeff));
+        my_rot += sweep_rounds<G, R>(av, bv, na, nb, ida, idb, active, dot32, tol, b, g, l, qeff, buf,
+                                     buf, 1, ldw, br > 0);
+        if (active) {
+          store_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
+          store_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
+        }
+        // the next block pair may hold columns other lanes just stored
+        __syncthreads();
+      }
+    }
+    if (my_rot) atomicAdd(&wg_ctl[sweep & 1], my_rot);
+    __syncthreads();
+    const int any = wg_ctl[sweep & 1];
+    if (tid == 0) wg_ctl[(sweep + 1) & 1] = 0;
+    __syncthreads();
+    ++sweep;
+    rotations += any;
+    my_sweeps = sweep;
+    converged = (any == 0);
+    if (converged || sweep >= max_sweeps) break;
+  }
+
+  // ---- output: b columns at a time, kept ones compacted in column order ----
+  if (tid == 0) ctl[2] = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < ncols; c0 += b) {
+    const int id = c0 + g;
+    if (active) load_work_col<G, R>(Wk, mpad, id, l, av, qeff);
+    const double sa = sqrt(group_sum<G>(dot64<R>(av, av, qeff)));
+    const bool ka = active && id < n && sa > jb.tau;
+    if (active && l == 0) ctl[3 + g] = ka ? 1 : 0;
+    __syncthreads();
+    if (tid == 0) {
+      int acc = ctl[2];
+      for (int i = 0; i < b; ++i) {
+        const int c = ctl[3 + i];
+        ctl[3 + i] = acc;
+        acc += c;
+      }
+      ctl[2] = acc;
+    }
+    __syncthreads();
+    const int d = ka ? ctl[3 + g] : -1;
+    const double sc = ka ? sqrt(1.0 - jb.tau / sa) / sa : 0.0;
+    if (active) put_col<G, R>(buf, ldw, g, l, av, qeff, sc, d);
+    __syncthreads();
+    if (active) stage_out(jb.out, buf, ldw, m, b, tid, tps);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (jb.rank) *jb.rank = ctl[2];
+    if (jb.sweeps) *jb.sweeps = my_sweeps;
+    if (jb.sweep_total) atomicAdd(jb.sweep_total, (unsigned long long)my_sweeps);
+    if (jb.rot_total) atomicAdd(jb.rot_total, (unsigned long long)rotations);
+    if (!converged && jb.hits) atomicAdd(jb.hits, 1u);
+  }
+}
+
+// One slice per workgroup (single problem), blocked.
+template <int G>
+__global__ __launch_bounds__(1024) void k_jacobi_blk(JacobiArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int s = blockIdx.x;
+  BlkJob jb;
+  jb.src = a.src + (long long)s * a.slice_stride;
+  jb.work = a.work + (long long)s * a.work_stride;
+  jb.out = a.bk + (long long)s * (a.bk_stride ? a.bk_stride : a.slice_stride);
+  jb.rank = a.rank ? a.rank + s : nullptr;
+  jb.sweeps = a.sweeps ? a.sweeps + s : nullptr;
+  jb.I1 = a.I1;
+  jb.I2 = a.I2;
+  jb.b = a.blk_b;
+  jb.nblk = a.blk_n;
+  jb.qeff = a.qeff;
+  jb.tau = a.tau;
+  jb.sweep_total = a.sweep_total;
+  jb.rot_total = a.rot_total;
+  jb.hits = a.maxsweep_hits;
+  jacobi_blk_body<G, 32>(jb, a.tol, a.max_sweeps, smem);
+}
+
+// Batch: one workgroup per slice of the problems whose slices take the blocked
+// kernel at this lane count.
+template <int G>
+__global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs, const CholItem* items,
+                                                          double tol, int max_sweeps) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const CholItem it = items[blockIdx.x];
+  ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  BlkJob jb;
+  jb.src = pd->Gh + (long long)it.slice * pd->N;
+  jb.work = pd->work + (long long)it.slice * pd->work_stride;
+  jb.out = pd->Bk + (long long)it.slice * pd->N;
+  jb.rank = pd->rank + it.slice;
+  jb.sweeps = pd->sweeps + it.slice;
+  jb.I1 = pd->I1;
+  jb.I2 = pd->I2;
+  jb.b = pd->blk_b;
+  jb.nblk = pd->blk_n;
+  jb.qeff = pd->blk_q;
+  jb.tau = pd->tau;
+  jb.sweep_total = &pd->sweep_total;
+  jb.rot_total = &pd->rot_total;
+  jb.hits = &pd->maxsweep_hits;
+  jacobi_blk_body<G, 32>(jb, tol, max_sweeps, smem);
+}
+
 // One slice per workgroup (single problem).
 template <int G, int R, int LB>
 __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
@@ -583,7 +945,8 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
 // ---- rebuild D_W = Bk (Bk^T W) ------------------------------------------------
 constexpr int RB_TN = 16;   // working columns per workgroup
 constexpr int RB_TK = 32;   // rows per LDS chunk
-constexpr int RB_RMAX = 256;
+constexpr int RB_RMAX = 256;       // kept columns of the register-resident kernel's slices
+constexpr int RB_RMAX_BLK = 512;   // kept columns of the blocked kernel's slices
 
 __device__ inline float w_at(const float* W, bool trans, int I1, int row, int col) {
   return trans ? W[(long long)row * I1 + col] : W[(long long)col * I1 + row];
@@ -592,11 +955,12 @@ __device__ inline float w_at(const float* W, bool trans, int I1, int row, int co
 // Working columns j0 .. j0+15 of one slice: Z = Bk^T W(:, j0..) (r x 16), then
 // D_W(:, j0..) = Bk Z.  W and D may alias: the tile is read in full before any
 // of it is written, and no other workgroup touches these entries.
+template <int RMAX>
 __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
                              bool flip) {
   __shared__ float Ws[RB_TK][RB_TN + 1];
-  __shared__ float Bs[RB_TK][RB_RMAX + 1];
-  __shared__ float Z[RB_RMAX][RB_TN + 1];
+  __shared__ float Bs[RB_TK][RMAX + 1];
+  __shared__ float Z[RMAX][RB_TN + 1];
   // flip: the working matrix is W^T (n x m), so the same two products give
   // D_W^T = B (B^T W^T), i.e. D_W = (W B) B^T with B n x r
   const bool trans = (I1 < I2) != flip;
@@ -608,9 +972,9 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
   const int jj = tid & 15, hi = tid >> 4;
 
   // phase A: Z[i][jj] = sum_k Bk[k][i] W[k][j0 + jj]
-  float zacc[16];
+  float zacc[RMAX / 16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) zacc[q] = 0.f;
+  for (int q = 0; q < RMAX / 16; ++q) zacc[q] = 0.f;
   if (r > 0) {
     for (int k0 = 0; k0 < m; k0 += RB_TK) {
       for (int idx = tid; idx < RB_TK * RB_TN; idx += 256) {
@@ -628,14 +992,14 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
       for (int kk = 0; kk < RB_TK; ++kk) {
         const float w = Ws[kk][jj];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
+        for (int q = 0; q < RMAX / 16; ++q)
           if (q < nq) zacc[q] = fmaf(Bs[kk][hi + 16 * q], w, zacc[q]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
+  for (int q = 0; q < RMAX / 16; ++q)
     if (q < nq) Z[hi + 16 * q][jj] = zacc[q];
   __syncthreads();
 
@@ -662,22 +1026,24 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
   }
 }
 
+template <int RMAX>
 __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
   const int s = blockIdx.y;
   const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
   const int j0 = blockIdx.x * RB_TN;
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
-  rebuild_body(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
+  rebuild_body<RMAX>(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
 }
 
+template <int RMAX>
 __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles) {
   const RebuildTile t = tiles[blockIdx.x];
   const ProbDev* pd = probs[t.prob];
   if (!pd->active) return;
   const long long off = (long long)t.slice * pd->N;
-  rebuild_body(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
-               pd->precond != 0);
+  rebuild_body<RMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
+                     pd->precond != 0);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
@@ -869,6 +1235,26 @@ hipError_t launch_items_g(ProbDev* const* probs, const SvtItem* items, int nitem
 #undef LT_ITEMS_CASE
 }
 
+template <int G>
+hipError_t launch_blk_one(const JacobiArgs& a, const JacobiBlkConfig& c, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk<G>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_jacobi_blk<G>, dim3(a.nslices), dim3(c.threads), c.lds, s, a);
+  return hipGetLastError();
+}
+
+template <int G>
+hipError_t launch_blk_items_one(ProbDev* const* probs, const CholItem* items, int nitems, int threads,
+                                size_t lds, double tol, int max_sweeps, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk_items<G>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_jacobi_blk_items<G>, dim3(nitems), dim3(threads), lds, s, probs, items, tol,
+                     max_sweeps);
+  return hipGetLastError();
+}
+
 size_t jacobi_lds_bytes(int npairs, int ldw, int nbuf) {
   return kWgCtlBytes + slice_lds_bytes(npairs, ldw, nbuf);
 }
@@ -990,17 +1376,97 @@ hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int 
   }
 }
 
-hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, hipStream_t s) {
+bool jacobi_reg_shape(int m, int n) {
+  if (m < 1 || n < 1 || m < n || n > RB_RMAX) return false;
+  const int npairs = (n + 1) / 2;
+  for (int G = 4; G <= 64; G *= 2) {
+    const int threads = ((npairs * G + 63) / 64) * 64;
+    int R = (m + G - 1) / G;
+    R = ((R + 3) / 4) * 4;
+    if (threads <= 1024 && R <= 32) return true;
+  }
+  return false;
+}
+
+int jacobi_blk_pick_config(int m, int n, int max_lds, JacobiBlkConfig* cfg) {
+  if (m < 2 || n < 2 || m < n || n > RB_RMAX_BLK) return -1;
+  const int Gs[3] = {16, 32, 64};   // fewest lanes per pair that hold the column: widest blocks
+  for (int gi = 0; gi < 3; ++gi) {
+    const int G = Gs[gi];
+    const int qeff = (m + 4 * G - 1) / (4 * G);
+    if (qeff > 8) continue;   // the kernels hold 32 rows per lane
+    const int mpad = 4 * G * qeff, ldw = mpad + 4;
+    int bmax = (1024 / G) & ~1;
+    while (bmax >= 2 && blk_lds_bytes(bmax, ldw) > (size_t)max_lds) bmax -= 2;
+    if (bmax < 2) continue;
+    int nblk = (n + bmax - 1) / bmax;
+    nblk += nblk & 1;
+    if (nblk < 2) nblk = 2;
+    for (; nblk <= n + 1; nblk += 2) {
+      int b = (n + nblk - 1) / nblk;
+      b += b & 1;
+      if (b < 2) b = 2;
+      if (b > bmax || blk_lds_bytes(b, ldw) > (size_t)max_lds) continue;
+      cfg->G = G;
+      cfg->b = b;
+      cfg->nblk = nblk;
+      cfg->qeff = qeff;
+      cfg->threads = ((b * G + 63) / 64) * 64;
+      cfg->lds = blk_lds_bytes(b, ldw);
+      cfg->work_floats = (long long)nblk * b * mpad;
+      return 0;
+    }
+  }
+  return -1;
+}
+
+hipError_t launch_jacobi_blk(const JacobiArgs& a0, const JacobiBlkConfig& c, hipStream_t s) {
+  if (a0.nslices <= 0) return hipSuccess;
+  if (a0.mode != 0 || !a0.work) return hipErrorInvalidValue;
+  JacobiArgs a = a0;
+  a.qeff = c.qeff;
+  a.blk_b = c.b;
+  a.blk_n = c.nblk;
+  a.work_stride = c.work_floats;
+  switch (c.G) {
+    case 16: return launch_blk_one<16>(a, c, s);
+    case 32: return launch_blk_one<32>(a, c, s);
+    case 64: return launch_blk_one<64>(a, c, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int G,
+                                   int threads, size_t lds, double tol, int max_sweeps, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  switch (G) {
+    case 16: return launch_blk_items_one<16>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    case 32: return launch_blk_items_one<32>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    case 64: return launch_blk_items_one<64>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, int wide,
+                                hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rebuild_tiles, dim3(ntiles), dim3(256), 0, s, probs, tiles);
+  if (wide)
+    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX_BLK>, dim3(ntiles), dim3(256), 0, s, probs, tiles);
+  else
+    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX>, dim3(ntiles), dim3(256), 0, s, probs, tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
   const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
+  const int kmax = a.I1 < a.I2 ? a.I1 : a.I2;   // kept columns are at most min(I1, I2)
+  if (kmax > RB_RMAX_BLK) return hipErrorInvalidValue;
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
-  hipLaunchKernelGGL(k_rebuild, grid, dim3(256), 0, s, a);
+  if (kmax > RB_RMAX)
+    hipLaunchKernelGGL(k_rebuild<RB_RMAX_BLK>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_rebuild<RB_RMAX>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

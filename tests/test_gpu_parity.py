@@ -118,20 +118,23 @@ def test_svt_degenerate_slices_preconditioned(lt):
             assert list(lt.to_host(rank)) == [0, 1, n // 2, 3]
 
 
-def test_svt_tall_slices_need_preconditioning(lt):
+def test_svt_tall_slices_both_paths(lt):
     """600 x 128 slices exceed the register-resident Jacobi on the slice itself
-    (64 column pairs leave at most 16 lanes per pair, 32 rows each); the
-    preconditioned path factors the 128 x 128 Gram matrix instead."""
+    (64 column pairs leave at most 16 lanes per pair, 32 rows each): the
+    preconditioned path factors the 128 x 128 Gram matrix, and without it the
+    blocked kernel sweeps the slice from its working buffer."""
     rng = np.random.default_rng(106)
     shape = (600, 128, 2)
     mats = o.mats_for(shape, ["dct"])
     A = o.lproduct(rng.standard_normal((600, 6, 2)), rng.standard_normal((6, 128, 2)), mats)
     A = A + 0.05 * rng.standard_normal(shape)
     tau = float(np.quantile(o.singular_values(A, mats), 0.8))
-    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("dct",))
-    assert rel(lt.to_host(D), o.svt(A, tau, mats)) < 2e-5
-    with pytest.raises(lt.LtError):
-        lt.svt_prox(lt.to_device(A), tau, ("dct",), precondition=False)
+    ref = o.svt(A, tau, mats)
+    for pc in (True, False):
+        D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("dct",), precondition=pc)
+        err = rel(lt.to_host(D), ref)
+        say("  tall 600x128 precondition", pc, "err", err)
+        assert err < 2e-5
 
 
 def test_svt_in_place_and_deterministic(lt):

@@ -1,21 +1,25 @@
-"""Host model of the Jacobi kernel's pair schedule (the slot moves of its ring
-phases, splits and final circle tournament, written with the kernel's index
-formulas): every sweep meets every column pair exactly once, in 2*ceil(n/2) - 1
-rounds, for any column count, starting from any arrangement."""
+"""Host model of the Jacobi kernels' pair schedules, written with the kernels'
+index formulas.  Register-resident kernel (the slot moves of its ring phases,
+splits and final circle tournament): every sweep meets every column pair
+exactly once, in 2*ceil(n/2) - 1 rounds, for any column count, starting from
+any arrangement.  Blocked kernel (round-robin tournament over column blocks,
+a full sweep of the slot schedule on the first block round's pairs and one ring
+phase on the later ones): every sweep meets every column pair exactly once."""
 import itertools
 
 import numpy as np
 import pytest
 
 
-def sweep(top, bot):
+def sweep(top, bot, ring_only=False):
     """One sweep on slots (top[g], bot[g]); yields the pairs of each round and
-    leaves the arrangement the kernel leaves."""
+    leaves the arrangement the kernel leaves.  ring_only: the first ring phase
+    alone (S rounds, S even)."""
     S = len(top)
     c, ring, s0 = S, S % 2 == 0, [0] * S
     idx = list(range(S))          # i = g - s0 per slot
     r = 0
-    nrounds = 2 * S - 1
+    nrounds = S if ring_only else 2 * S - 1
     for k in range(nrounds):
         yield list(zip(top, bot))
         if k + 1 == nrounds:
@@ -96,3 +100,51 @@ def test_ring_phases_move_one_column_per_slot():
         assert [a for a, _ in cur] == [a for a, _ in prev]
         assert sorted(b for _, b in cur) == sorted(b for _, b in prev)
         prev = cur
+
+
+def blk_at(pos, br, nblk):
+    return 0 if pos == 0 else 1 + (pos - 1 + br) % (nblk - 1)
+
+
+def blocked_sweep_pairs(n, b, nblk):
+    """Pairs met in one sweep of the blocked kernel (columns >= n are padding)."""
+    seen = {}
+    rounds = 0
+    for br in range(nblk - 1):
+        for pi in range(nblk // 2):
+            A, B = blk_at(pi, br, nblk), blk_at(nblk - 1 - pi, br, nblk)
+            top = [A * b + g for g in range(b)]
+            bot = [B * b + g for g in range(b)]
+            for pairs in sweep(top, bot, ring_only=br > 0):
+                rounds += 1
+                for x, y in pairs:
+                    if x < n and y < n:
+                        key = (min(x, y), max(x, y))
+                        seen[key] = seen.get(key, 0) + 1
+            # columns go back to their own place: the pair's column set is unchanged
+            assert sorted(top + bot) == sorted([A * b + g for g in range(b)] + [B * b + g for g in range(b)])
+    return seen, rounds
+
+
+# (n, b, nblk) as the blocked kernel's configuration picks them for working
+# matrices of 512 x 512 (G 16), 300 x 300, 600 x 256 (G 32), 2048 x 512 (G 64),
+# and small cases
+@pytest.mark.parametrize("n,b,nblk", [(512, 64, 8), (300, 50, 6), (256, 32, 8), (512, 16, 32),
+                                      (257, 44, 6), (10, 2, 6), (9, 4, 4), (6, 2, 4), (40, 10, 4)])
+def test_blocked_sweep_meets_every_pair_once(n, b, nblk):
+    assert b % 2 == 0 and nblk % 2 == 0 and b * nblk >= n
+    seen, rounds = blocked_sweep_pairs(n, b, nblk)
+    assert len(seen) == n * (n - 1) // 2
+    assert all(v == 1 for v in seen.values())
+    assert rounds == (nblk // 2) * ((2 * b - 1) + (nblk - 2) * b)
+
+
+def test_block_tournament_pairs_every_block_once():
+    for nblk in (2, 4, 6, 8, 32):
+        met = set()
+        for br in range(nblk - 1):
+            pos = [blk_at(p, br, nblk) for p in range(nblk)]
+            assert sorted(pos) == list(range(nblk))
+            for pi in range(nblk // 2):
+                met.add(frozenset((pos[pi], pos[nblk - 1 - pi])))
+        assert len(met) == nblk * (nblk - 1) // 2
