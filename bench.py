@@ -72,10 +72,13 @@ def threads_used():
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default: 200 video, 300 large, 30 big; 50 mix ticks)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3"])
-    ap.add_argument("--workload", default="video", choices=["video", "large", "mix", "serve"])
+    ap.add_argument("--workload", default="video", choices=["video", "large", "big", "mix", "serve"])
+    ap.add_argument("--large-frac", type=float, default=0.1,
+                    help="serve workload: share of 512x512x3x64 requests")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serve workload: Poisson arrival rate (1/s); 0 = calibrate to 0.7 x saturation")
@@ -92,6 +95,8 @@ def main():
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"video": 200, "large": 300, "big": 30, "mix": 50, "serve": 0}[args.workload]
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -108,7 +113,7 @@ def main():
         return bench_mix(args, torch, lt, wl)
     if args.workload == "serve":
         return bench_serve(args, torch, lt, wl)
-    p = wl.config1() if args.workload == "video" else wl.config2()
+    p = {"video": wl.config1, "large": wl.config2, "big": wl.config4_large}[args.workload]()
     shape = p.shape
     I1, I2 = shape[0], shape[1]
     P = wl.n_slices(shape)
@@ -191,7 +196,7 @@ def main():
         "roofline": roofline,
     }
 
-    cpu_iters = args.cpu_iters if args.cpu_iters is not None else (30 if args.workload == "video" else 10)
+    cpu_iters = args.cpu_iters if args.cpu_iters is not None else {"video": 30, "large": 10, "big": 1}[args.workload]
     if not args.no_cpu_baseline and cpu_iters > 0:
         import oracle as o
         k = cpu_iters
@@ -305,7 +310,7 @@ def bench_serve(args, torch, lt, wl):
     iteration-level continuous batching.  Reports p50/p99 latency and the
     aggregate slice-SVT/s."""
     from paper_2202_02870_amd import serving
-    specs = wl.config3_specs(n=args.requests, seed=4)
+    specs = wl.config4_specs(n=args.requests, seed=4, large_frac=args.large_frac)
     reqs = []
     for i, sp in enumerate(specs):
         p = wl.make_problem(sp["shape"], sp["rank"], sp["observed"], sp["seed"])

@@ -559,9 +559,9 @@ struct BatchTables {
   // blocked Jacobi: items grouped by lanes per pair (16, 32, 64), each group's
   // launch shape; rebuild tiles of slices with more than 256 columns
   std::vector<lt::CholItem> blk;
-  int blk_count[3] = {0, 0, 0};
-  int blk_threads[3] = {0, 0, 0};
-  size_t blk_lds[3] = {0, 0, 0};
+  int blk_count[lt::kBlkNumVariants] = {};
+  int blk_threads[lt::kBlkNumVariants] = {};
+  size_t blk_lds[lt::kBlkNumVariants] = {};
   std::vector<lt::RebuildTile> rebuild_wide;
   bool any_reg = false;
   lt::JacobiBatchConfig cfg{};
@@ -658,11 +658,10 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
       T->chol_nmax = ns[i] > T->chol_nmax ? ns[i] : T->chol_nmax;
     }
   }
-  // blocked items, grouped by lanes per pair
-  const int blkG[3] = {16, 32, 64};
-  for (int gi = 0; gi < 3; ++gi) {
+  // blocked items, grouped by kernel variant
+  for (int gi = 0; gi < lt::kBlkNumVariants; ++gi) {
     for (int i = 0; i < n; ++i) {
-      if (!blocked[i] || bcfg[i].G != blkG[gi]) continue;
+      if (!blocked[i] || bcfg[i].variant != gi) continue;
       for (int sl = 0; sl < (int)shapes[i].P; ++sl) T->blk.push_back(lt::CholItem{i, sl});
       T->blk_count[gi] += (int)shapes[i].P;
       T->blk_threads[gi] = bcfg[i].threads > T->blk_threads[gi] ? bcfg[i].threads : T->blk_threads[gi];
@@ -1206,7 +1205,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
     d.blk_b = bcfg.b;
     d.blk_n = bcfg.nblk;
     d.blk_q = bcfg.qeff;
-    d.blk_G = bcfg.G;
+    d.blk_variant = bcfg.variant;
+    d.blk_nbuf = bcfg.nbuf;
   }
   d.crit = NAN;
   HIP_TRY(h, hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, st));
@@ -1341,11 +1341,10 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
   if (!T.blk.empty()) {
     // the long blocked slices first, so the register-resident items fill in behind them
     ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
-    const int blkG[3] = {16, 32, 64};
     int off = 0;
-    for (int gi = 0; gi < 3; ++gi) {
+    for (int gi = 0; gi < lt::kBlkNumVariants; ++gi) {
       if (T.blk_count[gi] &&
-          (e = lt::launch_jacobi_blk_items(b->w.ptrs, b->w.blk + off, T.blk_count[gi], blkG[gi],
+          (e = lt::launch_jacobi_blk_items(b->w.ptrs, b->w.blk + off, T.blk_count[gi], gi,
                                            T.blk_threads[gi], T.blk_lds[gi], T.tol, T.max_sweeps, s)) !=
               hipSuccess)
         return e;

@@ -102,7 +102,7 @@ struct JacobiArgs {
   // the block layout (set by launch_jacobi_blk)
   float* work;
   long long work_stride;
-  int blk_b, blk_n;
+  int blk_b, blk_n, blk_nbuf;
 };
 
 struct JacobiConfig {
@@ -122,11 +122,17 @@ bool jacobi_reg_shape(int m, int n);
 // Blocked Jacobi for working matrices the register-resident kernel cannot hold
 // (n <= 512, m <= 2048): columns live in a per-slice working buffer and one
 // workgroup per slice sweeps them block pair by block pair.
+// Kernel variants (lanes per pair G, rows per lane R): {16,16}, {32,16},
+// {64,16}, {64,32}.
+constexpr int kBlkNumVariants = 4;
+extern const int kBlkVariants[kBlkNumVariants][2];
 struct JacobiBlkConfig {
-  int G;                 // lanes per column pair (16, 32 or 64)
+  int G, R;              // lanes per column pair, register rows per lane
+  int variant;           // index into kBlkVariants
   int b, nblk;           // block width (even) and block count (even)
   int qeff;              // 4-row chunks per lane (rows held: 4 G qeff)
   int threads;
+  int nbuf;              // LDS exchange buffers (2 when they fit: one barrier per ring round)
   size_t lds;
   long long work_floats; // working buffer per slice
 };
@@ -205,7 +211,7 @@ struct ProbDev {
   int precond, pad2;         // nonzero: the SVT runs the Jacobi on R^T (n x n) and rebuilds (W B) B^T
   float* work;               // blocked Jacobi: per-slice working buffers (or null)
   long long work_stride;
-  int blk_b, blk_n, blk_q, blk_G;
+  int blk_b, blk_n, blk_q, blk_variant, blk_nbuf, pad3;
   // dynamic
   int iter, parity, done, active;   // done: 1 converged, 2 iteration limit
   double beta, tau, num, den, crit;
@@ -242,8 +248,8 @@ int jacobi_batch_config(const int* m, const int* n, int count, int max_lds, int 
 hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int nitems,
                                const JacobiBatchConfig& cfg, double tol, int max_sweeps,
                                hipStream_t s);
-// Blocked kernel over items (problem, slice) of problems with blk_G == G.
-hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int G,
+// Blocked kernel over items (problem, slice) of problems with blk_variant == variant.
+hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int variant,
                                    int threads, size_t lds, double tol, int max_sweeps, hipStream_t s);
 
 }  // namespace lt

@@ -645,7 +645,7 @@ struct BlkJob {
   float* out;
   int32_t* rank;
   int32_t* sweeps;
-  int I1, I2, b, nblk, qeff;
+  int I1, I2, b, nblk, qeff, nbuf;
   double tau;
   unsigned long long* sweep_total;
   unsigned long long* rot_total;
@@ -704,16 +704,16 @@ __device__ inline int blk_at(int pos, int br, int nblk) {
   return pos == 0 ? 0 : 1 + (pos - 1 + br) % (nblk - 1);
 }
 
-__host__ __device__ inline size_t blk_lds_bytes(int b, int ldw) {
-  const size_t bytes = kWgCtlBytes + (size_t)exch_positions(b) * ldw * sizeof(float) +
+__host__ __device__ inline size_t blk_lds_bytes(int b, int ldw, int nbuf) {
+  const size_t bytes = kWgCtlBytes + (size_t)nbuf * exch_positions(b) * ldw * sizeof(float) +
                        ((size_t)b + 4) * sizeof(int);
   return (bytes + 15) & ~size_t(15);
 }
 
 template <int G, int R>
-__device__ __attribute__((noinline)) void jacobi_blk_body(const BlkJob& jb, double tol, int max_sweeps,
+__device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJob& jb, double tol, int max_sweeps,
                                                           unsigned char* smem) {
-  const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff, b = jb.b, nblk = jb.nblk;
+  const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff, b = jb.b, nblk = jb.nblk, nbuf = jb.nbuf;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
   const int n = trans ? I1 : I2;
@@ -725,9 +725,11 @@ __device__ __attribute__((noinline)) void jacobi_blk_body(const BlkJob& jb, doub
   const bool active = tid < tps;
   const int g = active ? tid / G : 0, l = tid % G;
   int* wg_ctl = reinterpret_cast<int*>(smem);
+  // exchange buffers (two: one barrier per ring round) and control words
   float* buf = reinterpret_cast<float*>(smem + kWgCtlBytes);
+  float* bufB = nbuf == 2 ? buf + (size_t)exch_positions(b) * ldw : buf;
   // ctl[2]: kept total; ctl[3 + g]: per-slot output offsets
-  int* ctl = reinterpret_cast<int*>(buf + (size_t)exch_positions(b) * ldw);
+  int* ctl = reinterpret_cast<int*>(buf + (size_t)nbuf * exch_positions(b) * ldw);
   float* __restrict__ Wk = jb.work;
 
   // ---- copy in: b columns at a time through LDS, written out coalesced ----
@@ -769,7 +771,7 @@ __device__ __attribute__((noinline)) void jacobi_blk_body(const BlkJob& jb, doub
         double na = group_sum<G>(dot64<R>(av, av, qeff));
         double nb = group_sum<G>(dot64<R>(bv, bv, qeff));
         my_rot += sweep_rounds<G, R>(av, bv, na, nb, ida, idb, active, dot32, tol, b, g, l, qeff, buf,
-                                     buf, 1, ldw, br > 0);
+                                     bufB, nbuf, ldw, br > 0);
         if (active) {
           store_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
           store_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
@@ -826,8 +828,10 @@ __device__ __attribute__((noinline)) void jacobi_blk_body(const BlkJob& jb, doub
   }
 }
 
-// One slice per workgroup (single problem), blocked.
-template <int G>
+// One slice per workgroup (single problem), blocked.  The body is inlined: its
+// block loop around the rounds leaves too few registers for 32 rows per lane
+// and a call frame (16 rows per lane, inlined, do not spill).
+template <int G, int R>
 __global__ __launch_bounds__(1024) void k_jacobi_blk(JacobiArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int s = blockIdx.x;
@@ -841,17 +845,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk(JacobiArgs a) {
   jb.I2 = a.I2;
   jb.b = a.blk_b;
   jb.nblk = a.blk_n;
+  jb.nbuf = a.blk_nbuf;
   jb.qeff = a.qeff;
   jb.tau = a.tau;
   jb.sweep_total = a.sweep_total;
   jb.rot_total = a.rot_total;
   jb.hits = a.maxsweep_hits;
-  jacobi_blk_body<G, 32>(jb, a.tol, a.max_sweeps, smem);
+  jacobi_blk_body<G, R>(jb, a.tol, a.max_sweeps, smem);
 }
 
 // Batch: one workgroup per slice of the problems whose slices take the blocked
-// kernel at this lane count.
-template <int G>
+// kernel with this lane count and row capacity.
+template <int G, int R>
 __global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs, const CholItem* items,
                                                           double tol, int max_sweeps) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -868,12 +873,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs
   jb.I2 = pd->I2;
   jb.b = pd->blk_b;
   jb.nblk = pd->blk_n;
+  jb.nbuf = pd->blk_nbuf;
   jb.qeff = pd->blk_q;
   jb.tau = pd->tau;
   jb.sweep_total = &pd->sweep_total;
   jb.rot_total = &pd->rot_total;
   jb.hits = &pd->maxsweep_hits;
-  jacobi_blk_body<G, 32>(jb, tol, max_sweeps, smem);
+  jacobi_blk_body<G, R>(jb, tol, max_sweeps, smem);
 }
 
 // One slice per workgroup (single problem).
@@ -1235,22 +1241,22 @@ hipError_t launch_items_g(ProbDev* const* probs, const SvtItem* items, int nitem
 #undef LT_ITEMS_CASE
 }
 
-template <int G>
+template <int G, int R>
 hipError_t launch_blk_one(const JacobiArgs& a, const JacobiBlkConfig& c, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk<G>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk<G, R>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi_blk<G>, dim3(a.nslices), dim3(c.threads), c.lds, s, a);
+  hipLaunchKernelGGL((k_jacobi_blk<G, R>), dim3(a.nslices), dim3(c.threads), c.lds, s, a);
   return hipGetLastError();
 }
 
-template <int G>
+template <int G, int R>
 hipError_t launch_blk_items_one(ProbDev* const* probs, const CholItem* items, int nitems, int threads,
                                 size_t lds, double tol, int max_sweeps, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk_items<G>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_blk_items<G, R>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi_blk_items<G>, dim3(nitems), dim3(threads), lds, s, probs, items, tol,
+  hipLaunchKernelGGL((k_jacobi_blk_items<G, R>), dim3(nitems), dim3(threads), lds, s, probs, items, tol,
                      max_sweeps);
   return hipGetLastError();
 }
@@ -1388,16 +1394,19 @@ bool jacobi_reg_shape(int m, int n) {
   return false;
 }
 
+const int kBlkVariants[kBlkNumVariants][2] = {{16, 16}, {32, 16}, {64, 16}, {64, 32}};
+
 int jacobi_blk_pick_config(int m, int n, int max_lds, JacobiBlkConfig* cfg) {
   if (m < 2 || n < 2 || m < n || n > RB_RMAX_BLK) return -1;
-  const int Gs[3] = {16, 32, 64};   // fewest lanes per pair that hold the column: widest blocks
-  for (int gi = 0; gi < 3; ++gi) {
-    const int G = Gs[gi];
+  // (lanes per pair, rows per lane) in order of preference: the fewest lanes
+  // that hold the column (widest blocks) at 16 rows per lane, then 32 rows
+  for (int vi = 0; vi < kBlkNumVariants; ++vi) {
+    const int G = kBlkVariants[vi][0], R = kBlkVariants[vi][1];
     const int qeff = (m + 4 * G - 1) / (4 * G);
-    if (qeff > 8) continue;   // the kernels hold 32 rows per lane
+    if (qeff > R / 4) continue;
     const int mpad = 4 * G * qeff, ldw = mpad + 4;
     int bmax = (1024 / G) & ~1;
-    while (bmax >= 2 && blk_lds_bytes(bmax, ldw) > (size_t)max_lds) bmax -= 2;
+    while (bmax >= 2 && blk_lds_bytes(bmax, ldw, 1) > (size_t)max_lds) bmax -= 2;
     if (bmax < 2) continue;
     int nblk = (n + bmax - 1) / bmax;
     nblk += nblk & 1;
@@ -1406,13 +1415,17 @@ int jacobi_blk_pick_config(int m, int n, int max_lds, JacobiBlkConfig* cfg) {
       int b = (n + nblk - 1) / nblk;
       b += b & 1;
       if (b < 2) b = 2;
-      if (b > bmax || blk_lds_bytes(b, ldw) > (size_t)max_lds) continue;
+      if (b > bmax || blk_lds_bytes(b, ldw, 1) > (size_t)max_lds) continue;
+      const int nbuf = blk_lds_bytes(b, ldw, 2) <= (size_t)max_lds ? 2 : 1;
       cfg->G = G;
+      cfg->R = R;
+      cfg->variant = vi;
       cfg->b = b;
       cfg->nblk = nblk;
       cfg->qeff = qeff;
       cfg->threads = ((b * G + 63) / 64) * 64;
-      cfg->lds = blk_lds_bytes(b, ldw);
+      cfg->nbuf = nbuf;
+      cfg->lds = blk_lds_bytes(b, ldw, nbuf);
       cfg->work_floats = (long long)nblk * b * mpad;
       return 0;
     }
@@ -1427,22 +1440,25 @@ hipError_t launch_jacobi_blk(const JacobiArgs& a0, const JacobiBlkConfig& c, hip
   a.qeff = c.qeff;
   a.blk_b = c.b;
   a.blk_n = c.nblk;
+  a.blk_nbuf = c.nbuf;
   a.work_stride = c.work_floats;
-  switch (c.G) {
-    case 16: return launch_blk_one<16>(a, c, s);
-    case 32: return launch_blk_one<32>(a, c, s);
-    case 64: return launch_blk_one<64>(a, c, s);
+  switch (c.variant) {
+    case 0: return launch_blk_one<16, 16>(a, c, s);
+    case 1: return launch_blk_one<32, 16>(a, c, s);
+    case 2: return launch_blk_one<64, 16>(a, c, s);
+    case 3: return launch_blk_one<64, 32>(a, c, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int G,
+hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int variant,
                                    int threads, size_t lds, double tol, int max_sweeps, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  switch (G) {
-    case 16: return launch_blk_items_one<16>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
-    case 32: return launch_blk_items_one<32>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
-    case 64: return launch_blk_items_one<64>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+  switch (variant) {
+    case 0: return launch_blk_items_one<16, 16>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    case 1: return launch_blk_items_one<32, 16>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    case 2: return launch_blk_items_one<64, 16>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
+    case 3: return launch_blk_items_one<64, 32>(probs, items, nitems, threads, lds, tol, max_sweeps, s);
     default: return hipErrorInvalidValue;
   }
 }

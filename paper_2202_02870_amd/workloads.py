@@ -159,6 +159,34 @@ def config3(n=64, seed=3, max_iter=100):
     return probs
 
 
+LARGE_REQUEST_SHAPE = (512, 512, 3, 64)
+
+
+def config4_specs(n=200, seed=4, large_frac=0.1):
+    """Requests of the served stream: the uneven-mix distribution of
+    config3_specs, except that a request is, with probability large_frac, a
+    512x512x3x64 tensor (192 frontal slices of 512 x 512; L-rank and observed
+    fraction drawn as for the mix).  Same dict layout as config3_specs."""
+    specs = config3_specs(n, seed)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 512]))
+    for sp in specs:
+        big = rng.random() < large_frac
+        r = int(rng.integers(2, 17))
+        f = float(rng.uniform(0.15, 0.60))
+        if big:
+            sp.update(shape=LARGE_REQUEST_SHAPE, rank=r, observed=f)
+    return specs
+
+
+def config4_large():
+    """One large request of the served stream on its own: 512x512x3x64 of
+    L-rank 10, factors U[0,1], rescaled to [0,1], 30% observed, continuation
+    schedule as the video workload."""
+    p = make_problem(LARGE_REQUEST_SHAPE, 10, 0.3, seed=5, name="large-request-512x512x3x64-r10-obs0.3")
+    p.schedule = dict(pga_schedule_params(p.M, p.mask), max_iter=500, tol=0.0)
+    return p
+
+
 def n_slices(shape):
     P = 1
     for d in shape[2:]:

@@ -27,10 +27,10 @@ def rel(a, b):
     return float(np.linalg.norm((np.asarray(a, np.float64) - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-# working matrices 512 x 512 (16 lanes per pair, 8 blocks of 64 columns),
-# 300 x 280 (ragged: 6 blocks of 48, 8 padding columns), 600 x 260 from a
-# 260 x 600 slice (transposed, 32 lanes per pair), 2048 x 300 (64 lanes per
-# pair, 20 blocks of 16 columns)
+# working matrices 512 x 512 (32 lanes per pair, 16 blocks of 32 columns),
+# 300 x 280 (ragged: 10 blocks of 28), 600 x 260 from a 260 x 600 slice
+# (transposed, 64 lanes per pair, 18 blocks of 16 with 28 padding columns),
+# 2048 x 300 (64 lanes per pair and 32 rows per lane)
 BLK_SHAPES = [((512, 512, 2), ("dct",)), ((300, 280, 3), ("dct",)), ((260, 600, 2), ("dct",)),
               ((2048, 300, 1), ("identity",))]
 

@@ -127,10 +127,11 @@ def blocked_sweep_pairs(n, b, nblk):
 
 
 # (n, b, nblk) as the blocked kernel's configuration picks them for working
-# matrices of 512 x 512 (G 16), 300 x 300, 600 x 256 (G 32), 2048 x 512 (G 64),
-# and small cases
-@pytest.mark.parametrize("n,b,nblk", [(512, 64, 8), (300, 50, 6), (256, 32, 8), (512, 16, 32),
-                                      (257, 44, 6), (10, 2, 6), (9, 4, 4), (6, 2, 4), (40, 10, 4)])
+# matrices of 512 x 512 and 300 x 300 (32 lanes per pair), 600 x 256 and
+# 2048 x 512 (64 lanes per pair), 257 x 257, plus wider blocks and small cases
+@pytest.mark.parametrize("n,b,nblk", [(512, 32, 16), (300, 30, 10), (256, 16, 16), (512, 16, 32),
+                                      (257, 26, 10), (512, 64, 8), (300, 50, 6), (10, 2, 6), (9, 4, 4),
+                                      (6, 2, 4), (40, 10, 4)])
 def test_blocked_sweep_meets_every_pair_once(n, b, nblk):
     assert b % 2 == 0 and nblk % 2 == 0 and b * nblk >= n
     seen, rounds = blocked_sweep_pairs(n, b, nblk)
