@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="video", choices=["video", "large", "big", "mix", "serve"])
     ap.add_argument("--large-frac", type=float, default=0.1,
                     help="serve workload: share of 512x512x3x64 requests")
+    ap.add_argument("--no-lanes", action="store_true",
+                    help="serve workload: one batch for all requests (no lane for blocked-kernel requests)")
     ap.add_argument("--requests", type=int, default=200, help="serve workload: number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serve workload: Poisson arrival rate (1/s); 0 = calibrate to 0.7 x saturation")
@@ -304,13 +306,21 @@ def bench_mix(args, torch, lt, wl):
 
 def bench_serve(args, torch, lt, wl):
     """Served stream: Poisson arrivals of completion requests drawn from the
-    uneven-mix size distribution; each runs until the relative change
+    uneven-mix size distribution, with a share (--large-frac, 10%) of
+    512x512x3x64 requests; each runs until the relative change
     ||Y - X|| / ||X|| < 1e-5 (gated until mu reaches its floor) or 500
     iterations; admission by HBM footprint, iterates resident on the device,
     iteration-level continuous batching.  Reports p50/p99 latency and the
     aggregate slice-SVT/s."""
     from paper_2202_02870_amd import serving
     specs = wl.config4_specs(n=args.requests, seed=4, large_frac=args.large_frac)
+    n_large = sum(1 for sp in specs if tuple(sp["shape"]) == wl.LARGE_REQUEST_SHAPE)
+
+    def progress(r):
+        print("finished request %d %s: %d iterations, latency %.3f s" % (r.rid, "x".join(map(str, r.M.shape)),
+                                                                         r.iters, r.latency),
+              file=sys.stderr, flush=True)
+
     reqs = []
     for i, sp in enumerate(specs):
         p = wl.make_problem(sp["shape"], sp["rank"], sp["observed"], sp["seed"])
@@ -322,7 +332,8 @@ def bench_serve(args, torch, lt, wl):
         # saturation estimate: all requests at t = 0 on a small prefix
         probe = [serving.Request(rid=r.rid, arrival=0.0, M=r.M, mask=r.mask, params=r.params, kinds=r.kinds)
                  for r in reqs[:16]]
-        srv = serving.CompletionServer(serving.GpuExecutor(), hbm_budget=int(64e9), ticks_per_round=4)
+        srv = serving.CompletionServer(serving.GpuExecutor(lanes=not args.no_lanes), hbm_budget=int(64e9),
+                                       ticks_per_round=4, lane_ticks=2, on_finish=progress)
         for r in probe:
             srv.submit(r)
         c0 = time.perf_counter()
@@ -332,7 +343,8 @@ def bench_serve(args, torch, lt, wl):
     arr = serving.poisson_arrivals(len(reqs), rate, seed=4)
     for r, t in zip(reqs, arr):
         r.arrival = float(t)
-    srv = serving.CompletionServer(serving.GpuExecutor(), hbm_budget=int(64e9), ticks_per_round=4)
+    srv = serving.CompletionServer(serving.GpuExecutor(lanes=not args.no_lanes), hbm_budget=int(64e9),
+                                   ticks_per_round=4, lane_ticks=2, on_finish=progress)
     for r in reqs:
         srv.submit(r)
     c0 = time.perf_counter()
@@ -352,8 +364,10 @@ def bench_serve(args, torch, lt, wl):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "served-stream", "requests": len(reqs), "rate_per_s": round(rate, 3),
-                   "stop": "rel. change < 1e-5 or 500 iterations", "hbm_budget_GB": 64},
+        "config": {"workload": "served-stream", "requests": len(reqs), "large_512x512x3x64": n_large,
+                   "rate_per_s": round(rate, 3),
+                   "stop": "rel. change < 1e-5 or 500 iterations", "hbm_budget_GB": 64,
+                   "lanes": not args.no_lanes},
         "p50_s": round(st.get("p50", float("nan")), 4),
         "p99_s": round(st.get("p99", float("nan")), 4),
         "completed": st["completed"],

@@ -98,6 +98,21 @@ typedef struct {
  * Cholesky lives in LDS). */
 #define LT_PRECOND_MAX_N 200
 
+/* Jacobi kernels of the per-slice SVD (Alg. 3 / Alg. 4), chosen by slice shape
+ * (m = max(I1, I2), n = min(I1, I2)):
+ *   LT_SVT_PRECOND   the Jacobi on each slice's n x n Cholesky-QR factor
+ *                    (2 <= n <= LT_PRECOND_MAX_N, unless no_precondition);
+ *   LT_SVT_REGISTER  the slice's columns held in one workgroup's registers
+ *                    (n <= 256 and ceil(n/2) column pairs of G lanes holding
+ *                    m rows at 32 rows per lane, G <= 64, ceil(n/2) G <= 1024);
+ *   LT_SVT_BLOCKED   the other slices with n <= 512 and m <= 2048: columns in a
+ *                    per-slice working buffer of the workspace, swept block pair
+ *                    by block pair by one workgroup per slice.
+ * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only. */
+#define LT_SVT_REGISTER 0
+#define LT_SVT_PRECOND 1
+#define LT_SVT_BLOCKED 2
+
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */
 typedef struct {
@@ -172,6 +187,12 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
             float* V, float* sigma, int transform_domain, const lt_svd_opts* opts,
             void* ws, size_t ws_bytes);
+
+/* The Jacobi kernel (LT_SVT_*) the SVT of descriptor a's slices runs with
+ * options opts (may be NULL), or a negative status if no kernel takes the
+ * shape.  Host only: lets a scheduler keep requests of the long-running
+ * blocked kernel apart from the others. */
+int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts);
 
 /* D = D_tau(A) (Alg. 4): every slice of L(A) has its singular values
  * soft-thresholded by tau >= 0, then L^{-1}.  rank_out (device, P int32, may

@@ -18,12 +18,14 @@
 #include <string>
 #include <vector>
 
+constexpr size_t kPinnedDoubles = 128;   // host staging: scalars and one problem record
+
 struct lt_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   int max_lds = 65536;
   std::string err;
-  double* pinned = nullptr;   // small host staging for readbacks (16 doubles)
+  double* pinned = nullptr;   // small host staging for readbacks (kPinnedDoubles)
   // kernel timing (lt_profile_begin / lt_profile_end)
   bool prof_on = false;
   std::vector<hipEvent_t> events;          // pool, used in start/stop pairs
@@ -745,7 +747,7 @@ int lt_create(lt_handle** out, void* stream) {
           hipSuccess &&
       lds > 0)
     h->max_lds = lds;
-  if (hipHostMalloc((void**)&h->pinned, 16 * sizeof(double), hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&h->pinned, kPinnedDoubles * sizeof(double), hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
     return LT_ERR_HIP;
@@ -838,6 +840,17 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
     default: return 0;
   }
   return c.off + 256;
+}
+
+int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
+  Shape s;
+  int rc = parse(nullptr, a, &s);
+  if (rc) return rc;
+  if (precond_requested(opts) && precond_shape(s)) return LT_SVT_PRECOND;
+  if (blocked_shape(s, nullptr)) return LT_SVT_BLOCKED;
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
+  const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  return lt::jacobi_reg_shape(m, n) ? LT_SVT_REGISTER : LT_ERR_SHAPE;
 }
 
 int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
@@ -1226,9 +1239,13 @@ int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int
   ProblemWs w;
   const bool pc = problem_precond(s, &p->params);
   carve_problem(c, s, prec, p->params.max_iter, pc, &w);
+  // on the handle's stream only: work of other streams (other lanes of a
+  // server) is not waited for
+  static_assert(sizeof(lt::ProbDev) <= kPinnedDoubles * sizeof(double), "staging too small");
   lt::ProbDev d;
+  HIP_TRY(h, hipMemcpyAsync(h->pinned, w.st, sizeof(d), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  HIP_TRY(h, hipMemcpy(&d, w.st, sizeof(d), hipMemcpyDeviceToHost));
+  memcpy(&d, h->pinned, sizeof(d));
   if (d.done && d.parity) {
     // the last iterate is in the second buffer: move it to X and record that
     HIP_TRY(h, hipMemcpyAsync(p->X, w.Xb, (size_t)s.nel * sizeof(float), hipMemcpyDeviceToDevice,

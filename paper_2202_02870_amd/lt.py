@@ -62,6 +62,7 @@ class ProblemC(ctypes.Structure):
 
 
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
+SVT_PATHS = ("register", "precond", "blocked")   # LT_SVT_REGISTER, LT_SVT_PRECOND, LT_SVT_BLOCKED
 
 
 class Profile(ctypes.Structure):
@@ -82,6 +83,7 @@ _sig = {
                                    ctypes.c_int, _vp, ctypes.c_size_t]),
     "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_svt_path": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
     "lt_svt_prox": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_complete_pga": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, ctypes.POINTER(PgaParams),
@@ -216,6 +218,17 @@ def _workspace(nbytes, ws):
 
 def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True):
     return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, 0)
+
+
+def svt_path(shape, kinds=None, precondition=True):
+    """Which Jacobi kernel the SVT of these slices runs: "register", "precond"
+    or "blocked" (host only; LtError if no kernel takes the shape)."""
+    d = make_desc(tuple(shape), kinds)
+    o = svd_opts(precondition=precondition)
+    st = _lib.lt_svt_path(ctypes.byref(d), ctypes.byref(o))
+    if st < 0:
+        raise LtError(st, "no Jacobi kernel takes slices of %s" % (tuple(shape),))
+    return SVT_PATHS[st]
 
 
 def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None,

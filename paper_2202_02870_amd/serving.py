@@ -28,6 +28,7 @@ class Request:
     params: dict                # mu0, nu, mu_bar, tol, max_iter (+ optional precision)
     kinds: tuple = None
     footprint: int = 0          # device bytes while resident
+    lane: int = 0               # executor lane (see GpuExecutor)
     admitted: float = None
     finished: float = None
     iters: int = 0
@@ -41,20 +42,41 @@ class Request:
 
 
 class GpuExecutor:
-    """Executor on the HIP engine (paper_2202_02870_amd.lt)."""
+    """Executor on the HIP engine (paper_2202_02870_amd.lt).
 
-    def __init__(self, use_graph=True, precision="f32"):
-        import torch  # noqa: F401
+    Lanes: requests whose slices take the blocked Jacobi kernel (slices wider
+    than 256 columns: a tick of tens of milliseconds) run in lane 1, a batch of
+    their own on a second stream, and the others in lane 0, so the long ticks do
+    not set the tick length of the short requests; the two streams' kernels
+    share the GPU.  lanes=False puts every request in lane 0."""
+
+    def __init__(self, use_graph=True, precision="f32", lanes=True):
+        import torch
         from . import lt
+        self.torch = torch
         self.lt = lt
         self.use_graph = use_graph
         self.precision = precision
-        self.batch = None
+        self.lanes = lanes
+        self.batches = {}
+        self.streams = {}
 
     def _params(self, req):
         p = req.params
         return self.lt.pga_params(mu0=p["mu0"], nu=p.get("nu", 0.9), mu_bar=p["mu_bar"], tol=p.get("tol", 0.0),
                                   max_iter=p["max_iter"], precision=p.get("precision", self.precision))
+
+    def _stream(self, lane):
+        s = self.streams.get(lane)
+        if s is None:
+            s = self.torch.cuda.Stream()   # default priority
+            self.streams[lane] = s
+        return s
+
+    def lane(self, req):
+        if not self.lanes:
+            return 0
+        return 1 if self.lt.svt_path(req.M.shape, req.kinds) == "blocked" else 0
 
     def footprint(self, req):
         lt = self.lt
@@ -65,25 +87,37 @@ class GpuExecutor:
         return int(ws) + 9 * n          # + M (4 B), mask (1 B), X (4 B) per entry
 
     def make(self, req):
-        import torch
         lt = self.lt
         M = lt.to_device(req.M)
-        mask = lt.to_device(np.asarray(req.mask, dtype=np.uint8), dtype=torch.uint8)
-        return lt.Problem(M, mask, self._params(req), req.kinds)
+        mask = lt.to_device(np.asarray(req.mask, dtype=np.uint8), dtype=self.torch.uint8)
+        h = lt.Problem(M, mask, self._params(req), req.kinds)
+        h.lane = self.lane(req)
+        return h
 
-    def rebuild(self, handles):
-        if self.batch is not None:
-            self.batch.close()
-            self.batch = None
+    def rebuild(self, handles, lane=0):
+        """New batch of the lane's running problems (the lane's stream is idle)."""
+        b = self.batches.pop(lane, None)
+        if b is not None:
+            b.close()
         if handles:
-            self.batch = self.lt.Batch(handles, use_graph=self.use_graph)
+            with self.torch.cuda.stream(self._stream(lane)):
+                self.batches[lane] = self.lt.Batch(handles, use_graph=self.use_graph)
 
-    def step(self, ticks):
-        if self.batch is not None:
-            self.batch.step(ticks)
+    def step(self, ticks, lane=0):
+        """Enqueue ticks on the lane's stream (returns without waiting)."""
+        b = self.batches.get(lane)
+        if b is not None:
+            with self.torch.cuda.stream(self._stream(lane)):
+                b.step(ticks)
+
+    def busy(self, lane):
+        s = self.streams.get(lane)
+        return s is not None and not s.query()
 
     def poll(self, handle):
-        rep, done = handle.status()
+        """(iterations, done, converged); waits for the handle's lane."""
+        with self.torch.cuda.stream(self._stream(getattr(handle, "lane", 0))):
+            rep, done = handle.status()
         return rep["iters"], done, rep["converged"]
 
     def result(self, handle):
@@ -101,12 +135,21 @@ class CompletionServer:
     requests (a request may overrun its stopping point by up to this many
     ticks' worth of idle work, never by iterations: finished problems are
     skipped on the device).
+
+    Lanes (when the executor has `lane`, `busy`): lane 0 is stepped and polled
+    every round; every other lane runs asynchronously: it is polled, rebuilt
+    and given new ticks (lane_ticks per enqueue) only when its previous ticks
+    have finished, so its long ticks overlap lane 0's rounds instead of
+    lengthening them.
     """
 
-    def __init__(self, executor, hbm_budget, ticks_per_round=1, clock=None):
+    def __init__(self, executor, hbm_budget, ticks_per_round=1, clock=None, on_finish=None,
+                 lane_ticks=1):
         self.ex = executor
+        self.on_finish = on_finish      # called with each finished request
         self.budget = int(hbm_budget)
         self.ticks = int(ticks_per_round)
+        self.lane_ticks = int(lane_ticks)
         self.clock = clock or time.perf_counter
         self.t0 = None
         self.waiting = []           # heap of (arrival, rid)
@@ -118,17 +161,27 @@ class CompletionServer:
         self.rejected = []
         self.ticks_run = 0
         self.rebuilds = 0
+        self.dirty = set()          # lanes whose running set changed since their last batch
 
     def now(self):
         if self.t0 is None:
             self.t0 = self.clock()
         return self.clock() - self.t0
 
+    def _lane(self, req):
+        f = getattr(self.ex, "lane", None)
+        return f(req) if f is not None else 0
+
+    def _busy(self, lane):
+        f = getattr(self.ex, "busy", None)
+        return f(lane) if f is not None else False
+
     def submit(self, req):
         req.footprint = self.ex.footprint(req)
         if req.footprint > self.budget:
             self.rejected.append(req)     # could never fit: refused, not queued forever
             return False
+        req.lane = self._lane(req)
         self.requests[req.rid] = req
         heapq.heappush(self.waiting, (req.arrival, req.rid))
         return True
@@ -148,25 +201,34 @@ class CompletionServer:
                 self.peak_used = max(self.peak_used, self.used)
                 self.running.append(req)
                 admitted.append(req)
+                self.dirty.add(req.lane)
             else:
                 skipped.append((arr, rid))
         for item in skipped:
             heapq.heappush(self.waiting, item)
         return admitted
 
-    def step(self):
-        """One scheduling round: admit, (re)batch, run ticks, retire."""
-        now = self.now()
-        changed = bool(self._admit(now))
-        if changed:
-            self.ex.rebuild([r.handle for r in self.running])
-            self.rebuilds += 1
-        if not self.running:
-            return False
-        self.ex.step(self.ticks)
-        self.ticks_run += self.ticks
+    def _in_lane(self, lane):
+        return [r for r in self.running if r.lane == lane]
+
+    def _rebuild(self, lane):
+        if lane == 0 and not hasattr(self.ex, "lane"):
+            self.ex.rebuild([r.handle for r in self._in_lane(0)])
+        else:
+            self.ex.rebuild([r.handle for r in self._in_lane(lane)], lane=lane)
+        self.rebuilds += 1
+        self.dirty.discard(lane)
+
+    def _step_lane(self, lane, ticks):
+        if lane == 0 and not hasattr(self.ex, "lane"):
+            self.ex.step(ticks)
+        else:
+            self.ex.step(ticks, lane=lane)
+
+    def _retire(self, lane):
+        """Poll the lane's running requests and retire the finished ones."""
         finished = []
-        for r in self.running:
+        for r in self._in_lane(lane):
             iters, done, conv = self.ex.poll(r.handle)
             r.iters = iters
             if done:
@@ -174,15 +236,44 @@ class CompletionServer:
                 r.finished = self.now()
                 r.result = self.ex.result(r.handle)
                 finished.append(r)
-        if finished:
-            for r in finished:
-                self.running.remove(r)
-                self.used -= r.footprint
-                self.ex.release(r.handle)
-                r.handle = None
-                self.done.append(r)
-            self.ex.rebuild([r.handle for r in self.running])
-            self.rebuilds += 1
+        for r in finished:
+            self.running.remove(r)
+            self.used -= r.footprint
+            self.ex.release(r.handle)
+            r.handle = None
+            self.done.append(r)
+            self.dirty.add(lane)
+            if self.on_finish is not None:
+                self.on_finish(r)
+
+    def step(self):
+        """One scheduling round: admit, (re)batch, run ticks, retire.  Returns
+        False when nothing is resident."""
+        now = self.now()
+        self._admit(now)
+        if not self.running:
+            return False
+        lanes = sorted({r.lane for r in self.running} | {l for l in self.dirty})
+        for lane in lanes:
+            if lane == 0 or self._busy(lane):
+                continue
+            # an idle asynchronous lane: retire, rebatch, enqueue its next ticks
+            self._retire(lane)
+            if lane in self.dirty:
+                self._rebuild(lane)
+            if self._in_lane(lane):
+                self._step_lane(lane, self.lane_ticks)
+                self.ticks_run += self.lane_ticks
+        if 0 in self.dirty:
+            self._rebuild(0)
+        if self._in_lane(0):
+            self._step_lane(0, self.ticks)
+            self.ticks_run += self.ticks
+            self._retire(0)
+            if 0 in self.dirty:
+                self._rebuild(0)
+        elif self.running:
+            time.sleep(0.0005)      # only asynchronous lanes are running: wait for them
         return True
 
     def idle(self):

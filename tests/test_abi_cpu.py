@@ -72,3 +72,21 @@ def test_descriptor_layout_matches_c():
     assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 24
     assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lt.Profile) == 6 * 8 + 6 * 8 + 8
+
+
+def test_svt_path_by_shape():
+    """The kernel choice is a host decision on the slice shape and options."""
+    from paper_2202_02870_amd import lt
+    assert lt.svt_path((144, 176, 3, 50)) == "precond"
+    assert lt.svt_path((144, 176, 3, 50), precondition=False) == "register"
+    assert lt.svt_path((256, 256, 3, 100)) == "register"        # n = 256 > 200: no preconditioner
+    assert lt.svt_path((512, 512, 3, 64)) == "blocked"
+    assert lt.svt_path((600, 128, 2)) == "precond"
+    assert lt.svt_path((600, 128, 2), precondition=False) == "blocked"
+    assert lt.svt_path((128, 600, 2), precondition=False) == "blocked"   # transposed working matrix
+    assert lt.svt_path((1024, 64)) == "precond"
+    assert lt.svt_path((1024, 64), precondition=False) == "register"
+    assert lt.svt_path((2048, 300)) == "blocked"
+    for bad in ((2048, 2048), (513, 513), (3000, 16)):
+        with pytest.raises(lt.LtError):
+            lt.svt_path(bad, precondition=False)

@@ -35,8 +35,8 @@ class TickedGpu(serving.GpuExecutor):
         super().__init__(use_graph=True)
         self.clock = clock
 
-    def step(self, ticks):
-        super().step(ticks)
+    def step(self, ticks, lane=0):
+        super().step(ticks, lane)
         self.clock.t += ticks
 
 
@@ -90,3 +90,40 @@ def test_budget_limits_residency(lt):
         srv.submit(r)
     st = srv.run()
     assert st["completed"] == 4 and srv.peak_used <= 2 * one
+
+
+def test_blocked_requests_run_in_their_own_lane(lt):
+    """A request whose slices take the blocked Jacobi kernel runs in lane 1 (its
+    own batch and stream) beside small requests in lane 0; every result equals
+    the request run alone (bitwise) and matches the oracle."""
+    specs = [((300, 280, 2), 4, 0.4, 25), ((32, 48, 3), 3, 0.5, 30), ((64, 40, 3, 2), 3, 0.4, 20),
+             ((96, 64, 8), 3, 0.4, 25)]
+    reqs = []
+    for i, (shape, r, f, iters) in enumerate(specs):
+        p = wl.make_problem(shape, r, f, seed=820 + i)
+        prm = dict(wl.pga_schedule_params(p.M, p.mask), max_iter=iters, tol=0.0)
+        reqs.append(serving.Request(rid=i, arrival=0.0, M=p.M.astype(np.float32), mask=p.mask,
+                                    params=prm, kinds=p.kinds))
+    ex = serving.GpuExecutor(use_graph=True)
+    srv = serving.CompletionServer(ex, hbm_budget=1 << 34, ticks_per_round=2)
+    for r in reqs:
+        assert srv.submit(r)
+    assert [r.lane for r in reqs] == [1, 0, 0, 0]
+    st = srv.run()
+    print("laned serving stats", st, flush=True)
+    assert st["completed"] == len(reqs)
+    done = {r.rid: r for r in srv.done}
+    alone_ex = serving.GpuExecutor(use_graph=False, lanes=False)
+    for r in reqs:
+        assert done[r.rid].iters == r.params["max_iter"]
+        h = alone_ex.make(r)
+        alone_ex.rebuild([h])
+        alone_ex.step(r.params["max_iter"])
+        assert alone_ex.poll(h)[1]
+        assert np.array_equal(alone_ex.result(h), done[r.rid].result), r.rid
+        X, _ = o.complete_pga(r.M.astype(np.float64), r.mask, o.mats_for(r.M.shape, list(r.kinds)),
+                              mu0=r.params["mu0"], nu=r.params["nu"], mu_bar=r.params["mu_bar"],
+                              max_iter=r.params["max_iter"])
+        if np.linalg.norm(X) > 0:
+            assert np.linalg.norm(done[r.rid].result - X) / np.linalg.norm(X) < 1e-4
+    alone_ex.rebuild([])

@@ -119,3 +119,59 @@ def test_poisson_arrivals():
     t = serving.poisson_arrivals(2000, rate=5.0, seed=0)
     assert np.all(np.diff(t) > 0)
     assert abs(np.mean(np.diff(t)) - 0.2) < 0.02
+
+
+class LanedFakeExecutor(FakeExecutor):
+    """Two lanes: requests with more than 100 entries per slice in lane 1.
+    Lane 1's enqueued ticks stay 'in flight' for `lag` polls of busy()."""
+
+    def __init__(self, clock, lag=2):
+        super().__init__(clock)
+        self.batches = {0: [], 1: []}
+        self.lane_sizes = {0: [], 1: []}
+        self.inflight = {0: 0, 1: 0}
+        self.lag = lag
+        self.steps = {0: 0, 1: 0}
+
+    def lane(self, req):
+        return 1 if req.M.shape[0] * req.M.shape[1] > 100 else 0
+
+    def rebuild(self, handles, lane=0):
+        assert not self.busy(lane)
+        self.batches[lane] = list(handles)
+        self.lane_sizes[lane].append(len(handles))
+
+    def step(self, ticks, lane=0):
+        self.batch = self.batches[lane]
+        super().step(ticks)
+        self.steps[lane] += ticks
+        if lane:
+            self.inflight[lane] = self.lag
+
+    def busy(self, lane):
+        if self.inflight[lane] > 0:
+            self.inflight[lane] -= 1
+            return True
+        return False
+
+
+def test_lanes_keep_long_requests_apart():
+    clock = FakeClock()
+    ex = LanedFakeExecutor(clock)
+    srv = serving.CompletionServer(ex, hbm_budget=10 ** 9, clock=clock)
+    reqs = [_req(0, 0.0, (12, 12, 2), 6, 11), _req(1, 0.0, (4, 5, 3), 9, 12), _req(2, 1.0, (5, 4, 2), 7, 13),
+            _req(3, 2.0, (11, 13, 2), 5, 14)]
+    for r in reqs:
+        assert srv.submit(r)
+    assert [r.lane for r in reqs] == [1, 0, 0, 1]
+    srv.run()
+    done = {r.rid: r for r in srv.done}
+    assert sorted(done) == [0, 1, 2, 3]
+    # batches of each lane hold only that lane's requests; both lanes ran
+    assert max(ex.lane_sizes[1]) == 2 and max(ex.lane_sizes[0]) == 2
+    assert ex.steps[0] > 0 and ex.steps[1] > 0
+    for r in reqs:
+        X, _ = o.complete_pga(r.M, r.mask, o.mats_for(r.M.shape, list(r.kinds)), mu0=r.params["mu0"],
+                              nu=r.params["nu"], mu_bar=r.params["mu_bar"], max_iter=r.params["max_iter"])
+        assert np.array_equal(done[r.rid].result, X), r.rid
+        assert done[r.rid].iters == r.params["max_iter"]
