@@ -159,7 +159,8 @@ def main():
     # Jacobi kernel roofline (dominant kernel): algorithmic flops per launch over
     # its mean event-timed duration
     jcalls, jms = prof["jacobi"]
-    precond = (not args.no_precondition) and 2 <= n <= 200
+    path = lt.svt_path(shape, p.kinds, precondition=not args.no_precondition)
+    precond = "precond" in path
     rows = n if precond else m
     f64, f32 = jacobi_flops(rows, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
     per_launch = (f64 + f32) / max(jcalls, 1)
@@ -174,7 +175,7 @@ def main():
                 "traffic": JACOBI_TRAFFIC_VIDEO_BYTES if measured_cfg else None,
                 "flops_per_launch": per_launch, "fp64_share": round(f64 / (f64 + f32), 4),
                 "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
-                "jacobi_rows": rows, "preconditioned": precond}
+                "jacobi_rows": rows, "preconditioned": precond, "svt_path": path}
 
     line = {
         "metric": "PGA iterations/s (slice-SVT/s alongside) at rel-err <= 1e-4 vs FP64 oracle",

@@ -88,30 +88,34 @@ typedef struct {
   int32_t max_sweeps;   /* sweep limit per slice; <= 0 selects 40 */
   int32_t precision;    /* lt_precision of the transform GEMMs */
   int32_t no_precondition; /* SVT paths: 0 runs the Jacobi on the Cholesky-QR factor R^T of
-                              each slice where min(I1, I2) <= LT_PRECOND_MAX_N (fewer sweeps,
-                              same result to the Jacobi tolerance); nonzero runs it on the
-                              slice itself.  lt_lsvd always uses the slice itself. */
+                              each slice with 2 <= n <= 200 (n = min(I1, I2)), and with
+                              n <= LT_PRECOND_MAX_N where the slice itself would need the
+                              blocked kernel (fewer sweeps, same result to the Jacobi
+                              tolerance); nonzero runs it on the slice itself.  lt_lsvd
+                              always uses the slice itself. */
   int32_t reserved;     /* set to 0 */
 } lt_svd_opts;
 
-/* Largest min(I1, I2) the preconditioned SVT path takes (its per-slice FP64
- * Cholesky lives in LDS). */
-#define LT_PRECOND_MAX_N 200
+/* Largest min(I1, I2) the preconditioned SVT path takes (the per-slice FP64
+ * Cholesky runs in LDS up to n = 200, in global memory beyond). */
+#define LT_PRECOND_MAX_N 512
 
 /* Jacobi kernels of the per-slice SVD (Alg. 3 / Alg. 4), chosen by slice shape
- * (m = max(I1, I2), n = min(I1, I2)):
- *   LT_SVT_PRECOND   the Jacobi on each slice's n x n Cholesky-QR factor
- *                    (2 <= n <= LT_PRECOND_MAX_N, unless no_precondition);
- *   LT_SVT_REGISTER  the slice's columns held in one workgroup's registers
- *                    (n <= 256 and ceil(n/2) column pairs of G lanes holding
- *                    m rows at 32 rows per lane, G <= 64, ceil(n/2) G <= 1024);
- *   LT_SVT_BLOCKED   the other slices with n <= 512 and m <= 2048: columns in a
- *                    per-slice working buffer of the workspace, swept block pair
- *                    by block pair by one workgroup per slice.
+ * (m = max(I1, I2), n = min(I1, I2)).  The Jacobi's working matrix is the
+ * slice (m x n) or, with LT_SVT_PRECOND set, the slice's n x n Cholesky-QR
+ * factor (see no_precondition).  It runs
+ *   register-resident (LT_SVT_BLOCKED clear): its columns held in one
+ *                    workgroup's registers (n <= 256 and ceil(n/2) column pairs
+ *                    of G lanes holding all rows at 32 rows per lane, G <= 64,
+ *                    ceil(n/2) G <= 1024);
+ *   blocked (LT_SVT_BLOCKED set): the other working matrices with n <= 512 and
+ *                    at most 2048 rows: columns in a per-slice working buffer of
+ *                    the workspace, swept block pair by block pair by one
+ *                    workgroup per slice (a much longer kernel).
  * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only. */
 #define LT_SVT_REGISTER 0
-#define LT_SVT_PRECOND 1
-#define LT_SVT_BLOCKED 2
+#define LT_SVT_PRECOND 1   /* bit */
+#define LT_SVT_BLOCKED 2   /* bit */
 
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */
@@ -188,10 +192,10 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
             float* V, float* sigma, int transform_domain, const lt_svd_opts* opts,
             void* ws, size_t ws_bytes);
 
-/* The Jacobi kernel (LT_SVT_*) the SVT of descriptor a's slices runs with
- * options opts (may be NULL), or a negative status if no kernel takes the
- * shape.  Host only: lets a scheduler keep requests of the long-running
- * blocked kernel apart from the others. */
+/* How the SVT of descriptor a's slices runs with options opts (may be NULL):
+ * LT_SVT_PRECOND and LT_SVT_BLOCKED bits (0: the register kernel on the slice),
+ * or a negative status if no kernel takes the shape.  Host only: lets a
+ * scheduler keep requests of the long-running blocked kernel apart. */
 int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts);
 
 /* D = D_tau(A) (Alg. 4): every slice of L(A) has its singular values

@@ -277,9 +277,10 @@ struct SvtWs {
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
 };
 
-// The preconditioned SVT path applies when the FP64 Cholesky of an n x n Gram
-// matrix fits one workgroup's LDS.
-static_assert(LT_PRECOND_MAX_N == 200, "the Cholesky kernel holds columns of at most 200 rows");
+// The preconditioned SVT path takes slices with 2 <= n <= LT_PRECOND_MAX_N
+// (the Cholesky of the n x n Gram matrix runs in LDS up to n = 200, in global
+// memory beyond).
+static_assert(LT_PRECOND_MAX_N == 512, "the Cholesky kernels take n <= 512");
 
 bool precond_shape(const Shape& s) {
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
@@ -294,15 +295,46 @@ long long precond_n(const Shape& s) { return s.I1 < s.I2 ? s.I1 : s.I2; }
 // so workspace sizes do not depend on the device; the launch checks the
 // device's LDS.
 constexpr int kBlkLdsBudget = 160 * 1024;
+constexpr int kCholLdsMaxN = 200;   // the LDS Cholesky kernel's limit
 
-bool blocked_shape(const Shape& s, lt::JacobiBlkConfig* cfg) {
+// How the SVT of a slice shape runs: the Jacobi on the slice itself or on its
+// n x n Cholesky factor (precond), by the register-resident or the blocked
+// kernel; jm x jn is the Jacobi's working matrix.
+struct SvtPlan {
+  bool precond = false;
+  bool blocked = false;
+  int jm = 0, jn = 0;
+  lt::JacobiBlkConfig bcfg{};
+};
+
+// Preconditioning applies when requested for 2 <= n <= 200 (Cholesky in LDS),
+// and for n <= 512 when the register kernel cannot hold the slice itself: on
+// square slices of 256 columns the sweeps it saves (about one in eight on the
+// completion iterates measured) do not pay for the global-memory Cholesky,
+// while a slice that needs the blocked kernel gains both fewer sweeps and, when
+// tall, a shorter working matrix.  False if no kernel takes the shape.
+bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p) {
   const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
   const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
-  if (lt::jacobi_reg_shape(m, n)) return false;
-  lt::JacobiBlkConfig c;
-  if (lt::jacobi_blk_pick_config(m, n, kBlkLdsBudget, &c) != 0) return false;
-  if (cfg) *cfg = c;
+  p->precond = precond_req && precond_shape(s) && (n <= kCholLdsMaxN || !lt::jacobi_reg_shape(m, n));
+  p->jm = p->precond ? n : m;
+  p->jn = n;
+  p->blocked = false;
+  if (lt::jacobi_reg_shape(p->jm, p->jn)) return true;
+  if (lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) != 0) return false;
+  p->blocked = true;
   return true;
+}
+
+// Working-buffer floats per slice the blocked kernel may need for this shape
+// (with or without preconditioning).
+long long blocked_work_floats(const Shape& s) {
+  long long wf = 0;
+  for (int pc = 0; pc < 2; ++pc) {
+    SvtPlan p;
+    if (svt_plan(s, pc != 0, &p) && p.blocked && p.bcfg.work_floats > wf) wf = p.bcfg.work_floats;
+  }
+  return wf;
 }
 
 int check_blk_lds(lt_handle* h, const Shape& s, const lt::JacobiBlkConfig& c) {
@@ -318,9 +350,10 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   w->Bk = c.take<float>((size_t)s.nel);
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
-  if (precond_shape(s)) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
-  lt::JacobiBlkConfig bc;
-  if (blocked_shape(s, &bc)) w->work = c.take<float>((size_t)s.P * (size_t)bc.work_floats);
+  SvtPlan pp;
+  if (svt_plan(s, true, &pp) && pp.precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
+  const long long wf = blocked_work_floats(s);
+  if (wf) w->work = c.take<float>((size_t)s.P * (size_t)wf);
 }
 
 struct PgaWs {
@@ -386,12 +419,20 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
                    double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
                    unsigned long long* sweep_total, unsigned long long* rot_total,
                    unsigned int* hits, bool precond) {
-  precond = precond && w.C && precond_shape(s);
+  SvtPlan pl;
+  if (!svt_plan(s, precond && w.C, &pl))
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
+  precond = pl.precond;
   lt::JacobiArgs j{};
   lt::JacobiConfig cfg;
-  lt::JacobiBlkConfig bcfg;
-  bool blocked = false;
+  const lt::JacobiBlkConfig& bcfg = pl.bcfg;
+  const bool blocked = pl.blocked;
   int rc;
+  if (blocked) {
+    if ((rc = check_blk_lds(h, s, bcfg))) return rc;
+    if (!w.work) return fail(h, LT_ERR_WORKSPACE, "no blocked-Jacobi working buffer in the workspace");
+    j.work = w.work;
+  }
   if (precond) {
     // Jacobi on L = R^T (n x n), C = W^T W = R^T R: its kept columns are the
     // scaled right singular vectors B, and D_W = (W B) B^T
@@ -410,23 +451,14 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
     Shape sq = s;
     sq.I1 = n;
     sq.I2 = n;
-    if ((rc = jacobi_config(h, sq, &cfg))) return rc;
+    if (!blocked && (rc = jacobi_config(h, sq, &cfg))) return rc;
     j.src = reinterpret_cast<const float*>(w.C);
     j.slice_stride = 2 * cst;   // L slice s occupies the first half of the slice's FP64 block
     j.I1 = n;
     j.I2 = n;
     j.bk_stride = s.N;
-  } else if (blocked_shape(s, &bcfg)) {
-    if ((rc = check_blk_lds(h, s, bcfg))) return rc;
-    if (!w.work) return fail(h, LT_ERR_WORKSPACE, "no blocked-Jacobi working buffer in the workspace");
-    blocked = true;
-    j.src = Gh;
-    j.slice_stride = s.N;
-    j.I1 = (int)s.I1;
-    j.I2 = (int)s.I2;
-    j.work = w.work;
   } else {
-    if ((rc = jacobi_config(h, s, &cfg))) return rc;
+    if (!blocked && (rc = jacobi_config(h, s, &cfg))) return rc;
     j.src = Gh;
     j.slice_stride = s.N;
     j.I1 = (int)s.I1;
@@ -471,15 +503,16 @@ bool precond_requested(const lt_svd_opts* o) { return !(o && o->no_precondition)
 // to LT_PRECOND_MAX_N), by the register-resident Jacobi kernel on the slice
 // itself, or by the blocked kernel (n <= 512, m <= 2048).
 int check_svt_shape(lt_handle* h, const Shape& s, bool precond) {
+  SvtPlan p;
+  if (!svt_plan(s, precond, &p))
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels (n <= 512, m <= 2048 "
+                "without preconditioning)", s.I1, s.I2);
+  if (p.blocked) return check_blk_lds(h, s, p.bcfg);
   lt::JacobiConfig probe;
-  if (precond && precond_shape(s)) {
-    Shape sq = s;
-    sq.I1 = sq.I2 = precond_n(s);
-    return jacobi_config(h, sq, &probe);
-  }
-  lt::JacobiBlkConfig bc;
-  if (blocked_shape(s, &bc)) return check_blk_lds(h, s, bc);
-  return jacobi_config(h, s, &probe);
+  Shape sq = s;
+  sq.I1 = p.jm;
+  sq.I2 = p.jn;
+  return jacobi_config(h, sq, &probe);
 }
 
 
@@ -504,7 +537,8 @@ struct ProblemWs {
 // A problem of the batch engine runs the preconditioned SVT when its options
 // ask for it (the default) and its slices allow it.
 bool problem_precond(const Shape& s, const lt_pga_params* p) {
-  return precond_requested(&p->svd) && precond_shape(s);
+  SvtPlan pl;
+  return svt_plan(s, precond_requested(&p->svd), &pl) && pl.precond;
 }
 
 void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool precond, ProblemWs* w) {
@@ -521,8 +555,8 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool preco
   w->partials = c.take<double>(2 * (size_t)w->n_partials);
   w->scratch = c.take<unsigned int>(4);
   if (precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
-  lt::JacobiBlkConfig bc;
-  if (!precond && blocked_shape(s, &bc)) w->work = c.take<float>((size_t)s.P * (size_t)bc.work_floats);
+  SvtPlan pl;
+  if (svt_plan(s, precond, &pl) && pl.blocked) w->work = c.take<float>((size_t)s.P * (size_t)pl.bcfg.work_floats);
 }
 
 int check_pga_params(lt_handle* h, const lt_pga_params* p) {
@@ -556,8 +590,10 @@ struct BatchTables {
   std::vector<lt::SvtItem> items;
   std::vector<lt::RebuildTile> rebuild;
   std::vector<lt::GramTile> gram;
-  std::vector<lt::CholItem> chol;
+  std::vector<lt::CholItem> chol;    // Cholesky in LDS (n <= 200)
   int chol_nmax = 0;
+  std::vector<lt::CholItem> cholg;   // Cholesky in global memory (n > 200)
+  int cholg_nmax = 0;
   // blocked Jacobi: items grouped by lanes per pair (16, 32, 64), each group's
   // launch shape; rebuild tiles of slices with more than 256 columns
   std::vector<lt::CholItem> blk;
@@ -593,12 +629,15 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     }
     ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
     ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
-    if (problem_precond(shapes[i], &probs[i].params)) {
-      ms[i] = ns[i];   // Jacobi on the n x n factor
-    } else if (blocked_shape(shapes[i], &bcfg[i])) {
-      int rc2 = check_blk_lds(h, shapes[i], bcfg[i]);
+    SvtPlan pl;
+    if (!svt_plan(shapes[i], problem_precond(shapes[i], &probs[i].params), &pl))
+      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", shapes[i].I1, shapes[i].I2);
+    ms[i] = pl.jm;   // n for the Jacobi on the n x n factor
+    if (pl.blocked) {
+      int rc2 = check_blk_lds(h, shapes[i], pl.bcfg);
       if (rc2) return rc2;
       blocked[i] = 1;
+      bcfg[i] = pl.bcfg;
     }
   }
   if (force_G == 0) {
@@ -653,11 +692,13 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     T->rebuild_slices += (size_t)s.P;
     if (pc) {
       const int tg = (ns[i] + 31) / 32;
+      const bool lds = ns[i] <= kCholLdsMaxN;
       for (int sl = 0; sl < (int)s.P; ++sl) {
         for (int t = 0; t < tg * (tg + 1) / 2; ++t) T->gram.push_back(lt::GramTile{i, sl, t, 0});
-        T->chol.push_back(lt::CholItem{i, sl});
+        (lds ? T->chol : T->cholg).push_back(lt::CholItem{i, sl});
       }
-      T->chol_nmax = ns[i] > T->chol_nmax ? ns[i] : T->chol_nmax;
+      int& nmax = lds ? T->chol_nmax : T->cholg_nmax;
+      nmax = ns[i] > nmax ? ns[i] : nmax;
     }
   }
   // blocked items, grouped by kernel variant
@@ -686,6 +727,7 @@ struct BatchWs {
   lt::RebuildTile* rebuild = nullptr;
   lt::GramTile* gram = nullptr;
   lt::CholItem* chol = nullptr;
+  lt::CholItem* cholg = nullptr;
   lt::CholItem* blk = nullptr;
   lt::RebuildTile* rebuild_wide = nullptr;
 };
@@ -699,6 +741,7 @@ void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
   w->rebuild = c.take<lt::RebuildTile>(T.rebuild.size());
   w->gram = c.take<lt::GramTile>(T.gram.size());
   w->chol = c.take<lt::CholItem>(T.chol.size());
+  w->cholg = c.take<lt::CholItem>(T.cholg.size());
   w->blk = c.take<lt::CholItem>(T.blk.size());
   w->rebuild_wide = c.take<lt::RebuildTile>(T.rebuild_wide.size());
 }
@@ -846,11 +889,9 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   Shape s;
   int rc = parse(nullptr, a, &s);
   if (rc) return rc;
-  if (precond_requested(opts) && precond_shape(s)) return LT_SVT_PRECOND;
-  if (blocked_shape(s, nullptr)) return LT_SVT_BLOCKED;
-  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
-  const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
-  return lt::jacobi_reg_shape(m, n) ? LT_SVT_REGISTER : LT_ERR_SHAPE;
+  SvtPlan p;
+  if (!svt_plan(s, precond_requested(opts), &p)) return LT_ERR_SHAPE;
+  return (p.precond ? LT_SVT_PRECOND : 0) | (p.blocked ? LT_SVT_BLOCKED : 0);
 }
 
 int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
@@ -1148,13 +1189,15 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   int max_sweeps, prec;
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  lt::JacobiBlkConfig bcfg;
-  const bool blk = !problem_precond(s, &p->params) && blocked_shape(s, &bcfg);
+  SvtPlan plan;
+  if (!svt_plan(s, problem_precond(s, &p->params), &plan))
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
+  const lt::JacobiBlkConfig& bcfg = plan.bcfg;
+  const bool blk = plan.blocked;
   if (blk) {
     if ((rc = check_blk_lds(h, s, bcfg))) return rc;
   } else {
-    int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
-    if (problem_precond(s, &p->params)) m = n;   // the Jacobi runs on the n x n factor
+    int m = plan.jm, n = plan.jn;
     lt::JacobiBatchConfig cfg;
     int ns, qe;
     if (lt::jacobi_batch_config(&m, &n, 1, h->max_lds, 0, &cfg, &ns, &qe) != 0)
@@ -1322,6 +1365,7 @@ int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, siz
     e = up(b->w.rebuild, b->T.rebuild.data(), b->T.rebuild.size() * sizeof(lt::RebuildTile));
   if (e == hipSuccess) e = up(b->w.gram, b->T.gram.data(), b->T.gram.size() * sizeof(lt::GramTile));
   if (e == hipSuccess) e = up(b->w.chol, b->T.chol.data(), b->T.chol.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess) e = up(b->w.cholg, b->T.cholg.data(), b->T.cholg.size() * sizeof(lt::CholItem));
   if (e == hipSuccess) e = up(b->w.blk, b->T.blk.data(), b->T.blk.size() * sizeof(lt::CholItem));
   if (e == hipSuccess)
     e = up(b->w.rebuild_wide, b->T.rebuild_wide.data(), b->T.rebuild_wide.size() * sizeof(lt::RebuildTile));
@@ -1349,10 +1393,13 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
     if ((e = lt::launch_gemm_grouped(b->w.ptrs, b->w.gemm, (int)T.gemm.size(), T.prec, 0, s)) != hipSuccess)
       return e;
   }
-  if (!T.chol.empty()) {
+  if (!T.gram.empty()) {
     ProfScope ps(prof ? h : nullptr, LT_PROF_PRECOND);
     if ((e = lt::launch_gram_tiles(b->w.ptrs, b->w.gram, (int)T.gram.size(), s)) != hipSuccess) return e;
     if ((e = lt::launch_chol_items(b->w.ptrs, b->w.chol, (int)T.chol.size(), T.chol_nmax, s)) != hipSuccess)
+      return e;
+    if ((e = lt::launch_chol_items(b->w.ptrs, b->w.cholg, (int)T.cholg.size(), T.cholg_nmax, s)) !=
+        hipSuccess)
       return e;
   }
   if (!T.blk.empty()) {

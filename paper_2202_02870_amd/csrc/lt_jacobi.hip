@@ -864,13 +864,21 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs
   ProbDev* pd = probs[it.prob];
   if (!pd->active) return;
   BlkJob jb;
-  jb.src = pd->Gh + (long long)it.slice * pd->N;
+  if (pd->precond) {
+    // the slice's Cholesky factor L = R^T (n x n, FP32 over its FP64 Gram block)
+    const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+    jb.src = reinterpret_cast<const float*>(pd->C) + (long long)it.slice * 2 * n * n;
+    jb.I1 = n;
+    jb.I2 = n;
+  } else {
+    jb.src = pd->Gh + (long long)it.slice * pd->N;
+    jb.I1 = pd->I1;
+    jb.I2 = pd->I2;
+  }
   jb.work = pd->work + (long long)it.slice * pd->work_stride;
   jb.out = pd->Bk + (long long)it.slice * pd->N;
   jb.rank = pd->rank + it.slice;
   jb.sweeps = pd->sweeps + it.slice;
-  jb.I1 = pd->I1;
-  jb.I2 = pd->I2;
   jb.b = pd->blk_b;
   jb.nblk = pd->blk_n;
   jb.nbuf = pd->blk_nbuf;

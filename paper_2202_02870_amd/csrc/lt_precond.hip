@@ -192,18 +192,14 @@ __device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
       }
     }
     __syncthreads();
-    // (b) panel: row i >= K + kb solves x L11^T = T(i, K .. K + kb - 1)
+    // (b) panel: row i >= K + kb solves x L11^T = T(i, K .. K + kb - 1), in place
+    // (each lane owns its row)
     for (int i = K + kb + tid; i < n; i += nt) {
-      double x[CB];
-#pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        if (q < kb) {
-          double acc = T[tri_off(K + q, n) + i - K - q];
-#pragma unroll
-          for (int p = 0; p < q; ++p) acc = fma(-x[p], T[tri_off(K + p, n) + q - p], acc);
-          x[q] = acc * dinv_s[q];
-          T[tri_off(K + q, n) + i - K - q] = x[q];
-        }
+      for (int q = 0; q < kb; ++q) {
+        double acc = T[tri_off(K + q, n) + i - K - q];
+        for (int p = 0; p < q; ++p)
+          acc = fma(-T[tri_off(K + p, n) + i - K - p], T[tri_off(K + p, n) + q - p], acc);
+        T[tri_off(K + q, n) + i - K - q] = acc * dinv_s[q];
       }
     }
     __syncthreads();
@@ -226,6 +222,150 @@ __device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
     const int i = e % n, j = e / n;
     L[e] = i >= j ? (float)T[tri_off(j, n) + i - j] : 0.f;
   }
+}
+
+constexpr int CG = 32;          // block width of the global-memory Cholesky
+constexpr int CG_NMAX = 512;    // largest n it takes
+
+// LDS of the global-memory Cholesky: the diagonal block and the panel rows.
+__host__ __device__ inline size_t cholg_lds_doubles(int n) {
+  return (size_t)CG * (CG + 1) + (size_t)(n > CG ? n - CG : 0) * CG;
+}
+
+// Cholesky C = L L^T of one slice's Gram matrix for n beyond the LDS kernel,
+// in place in global memory (FP64 lower triangle), blocked right-looking with
+// CG columns per block.  Per block: the diagonal block goes to LDS and wave 0
+// factors it; every lane solves one panel row against it, into LDS; then the
+// block's columns of L are written in FP32 (the layout of the LDS kernel's
+// output: n x n column-major over the first half of the slice's region, zero
+// above the diagonal) while the workgroup applies the block's rank-CG update to
+// the trailing lower triangle in global memory, 4 x 4 entries per lane.  The
+// FP32 columns of a block overwrite FP64 columns that are no longer read (those
+// of this and earlier blocks).  Pivots: as the LDS kernel.
+__device__ __attribute__((always_inline)) void chol_slice_global(double* Cs, int n) {
+  extern __shared__ __attribute__((aligned(16))) double S[];
+  double* Dg = S;                      // CG x (CG + 1), row-major: Dg[i][j] = block (i, j)
+  double* Pn = S + CG * (CG + 1);      // panel rows, row-major CG wide
+  __shared__ double red_s[16];
+  __shared__ double dinv_s[CG];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double* C = Cs;
+  float* L = reinterpret_cast<float*>(Cs);
+  {   // max of the diagonal
+    double d = 0.0;
+    for (int j = tid; j < n; j += nt) d = fmax(d, C[j + (long long)j * n]);
+    for (int o = 32; o >= 1; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+    if (lane == 0) red_s[wave] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < nt / 64; ++w) m = fmax(m, red_s[w]);
+      red_s[0] = m;
+    }
+    __syncthreads();
+  }
+  const double thr = red_s[0] * (64.0 * n * DBL_EPSILON);
+  for (int K = 0; K < n; K += CG) {
+    const int kb = min(CG, n - K);
+    const int t = n - K - kb;   // trailing rows (and columns)
+    // (a) diagonal block
+    for (int e = tid; e < kb * kb; e += nt) {
+      const int i = e % kb, j = e / kb;
+      Dg[i * (CG + 1) + j] = i >= j ? C[(K + i) + (long long)(K + j) * n] : 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int k = 0; k < kb; ++k) {
+        const double piv = Dg[k * (CG + 1) + k];
+        const double inv = piv > thr ? rsq64(piv) : 0.0;   // 1 / L(k, k); 0 zeroes the column
+        if (lane > k && lane < kb) Dg[lane * (CG + 1) + k] *= inv;
+        wave_sync();
+        const int r = kb - 1 - k;   // rows below k in the block
+        for (int e = lane; e < r * r; e += 64) {
+          const int ii = k + 1 + e / r, jj = k + 1 + e % r;
+          if (jj <= ii) Dg[ii * (CG + 1) + jj] = fma(-Dg[ii * (CG + 1) + k], Dg[jj * (CG + 1) + k],
+                                                     Dg[ii * (CG + 1) + jj]);
+        }
+        if (lane == 0) {
+          Dg[k * (CG + 1) + k] = piv * inv;   // sqrt(piv), or 0
+          dinv_s[k] = inv;
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    // (b) panel: row K + kb + r solves x L11^T = C(row, K .. K + kb - 1), in
+    // place in its LDS row (each lane owns its row)
+    for (int r = tid; r < t; r += nt) {
+      const int i = K + kb + r;
+      double* x = Pn + (size_t)r * CG;
+      for (int q = 0; q < kb; ++q) x[q] = C[i + (long long)(K + q) * n];
+      for (int q = 0; q < kb; ++q) {
+        double acc = x[q];
+        for (int p = 0; p < q; ++p) acc = fma(-x[p], Dg[q * (CG + 1) + p], acc);
+        x[q] = acc * dinv_s[q];
+      }
+    }
+    __syncthreads();
+    // (c) FP32 columns K .. K + kb - 1 of L
+    for (long long e = tid; e < (long long)kb * n; e += nt) {
+      const int j = K + (int)(e / n), i = (int)(e % n);
+      double v = 0.0;
+      if (i >= j) v = i < K + kb ? Dg[(i - K) * (CG + 1) + (j - K)] : Pn[(size_t)(i - K - kb) * CG + (j - K)];
+      L[(long long)j * n + i] = (float)v;
+    }
+    // (d) trailing update C(i, j) -= sum_q P(i, q) P(j, q), K + kb <= j <= i < n,
+    // in 4 x 4 tiles (bi >= bj) of the trailing triangle
+    const int T4 = (t + 3) / 4;
+    const int ntiles = T4 * (T4 + 1) / 2;
+    for (int tt = tid; tt < ntiles; tt += nt) {
+      int bi = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+      while ((bi + 1) * (bi + 2) / 2 <= tt) ++bi;
+      while (bi * (bi + 1) / 2 > tt) --bi;
+      const int bj = tt - bi * (bi + 1) / 2;
+      const int i0 = 4 * bi, j0 = 4 * bj;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int q = 0; q < kb; ++q) {
+        double pa[4], pb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          pa[a] = i0 + a < t ? Pn[(size_t)(i0 + a) * CG + q] : 0.0;
+          pb[a] = j0 + a < t ? Pn[(size_t)(j0 + a) * CG + q] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(pa[a], pb[b], acc[a][b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = K + kb + j0 + b;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = K + kb + i0 + a;
+          if (i0 + a < t && j0 + b < t && i >= j) C[i + (long long)j * n] -= acc[a][b];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_chol_global(CholArgs a) {
+  chol_slice_global(a.C + (long long)blockIdx.x * a.c_stride, a.n);
+}
+
+__global__ __launch_bounds__(1024) void k_chol_global_items(ProbDev* const* probs, const CholItem* items) {
+  const CholItem it = items[blockIdx.x];
+  const ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  chol_slice_global(pd->C + (long long)it.slice * n * n, n);
 }
 
 __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
@@ -261,7 +401,17 @@ hipError_t launch_gram_tiles(ProbDev* const* probs, const GramTile* tiles, int n
 hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
                              hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  if (nmax < 1 || nmax > CH_NMAX) return hipErrorInvalidValue;
+  if (nmax > CH_NMAX) {
+    // items of slices beyond the LDS kernel (every item of this list)
+    if (nmax > CG_NMAX) return hipErrorInvalidValue;
+    const size_t lds = cholg_lds_doubles(nmax) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)k_chol_global_items,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chol_global_items, dim3(nitems), dim3(1024), lds, s, probs, items);
+    return hipGetLastError();
+  }
+  if (nmax < 1) return hipErrorInvalidValue;
   const size_t lds = chol_lds_bytes(nmax);
   hipError_t e = hipFuncSetAttribute((const void*)k_chol_items, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -272,7 +422,16 @@ hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int n
 
 hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
-  if (a.n < 1 || a.n > CH_NMAX) return hipErrorInvalidValue;
+  if (a.n > CH_NMAX) {
+    if (a.n > CG_NMAX) return hipErrorInvalidValue;
+    const size_t lds = cholg_lds_doubles(a.n) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)k_chol_global, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chol_global, dim3(a.nslices), dim3(1024), lds, s, a);
+    return hipGetLastError();
+  }
+  if (a.n < 1) return hipErrorInvalidValue;
   const size_t lds = chol_lds_bytes(a.n);
   hipError_t e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);

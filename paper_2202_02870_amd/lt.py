@@ -62,7 +62,7 @@ class ProblemC(ctypes.Structure):
 
 
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
-SVT_PATHS = ("register", "precond", "blocked")   # LT_SVT_REGISTER, LT_SVT_PRECOND, LT_SVT_BLOCKED
+SVT_PATHS = ("register", "precond", "blocked", "precond+blocked")   # LT_SVT_PRECOND / LT_SVT_BLOCKED bits
 
 
 class Profile(ctypes.Structure):
@@ -221,8 +221,10 @@ def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True):
 
 
 def svt_path(shape, kinds=None, precondition=True):
-    """Which Jacobi kernel the SVT of these slices runs: "register", "precond"
-    or "blocked" (host only; LtError if no kernel takes the shape)."""
+    """How the SVT of these slices runs: "register" (register-resident Jacobi
+    on the slice), "precond" (on its Cholesky-QR factor), "blocked" (blocked
+    Jacobi on the slice) or "precond+blocked" (blocked, on the factor); host
+    only, LtError if no kernel takes the shape."""
     d = make_desc(tuple(shape), kinds)
     o = svd_opts(precondition=precondition)
     st = _lib.lt_svt_path(ctypes.byref(d), ctypes.byref(o))

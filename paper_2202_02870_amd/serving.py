@@ -76,7 +76,7 @@ class GpuExecutor:
     def lane(self, req):
         if not self.lanes:
             return 0
-        return 1 if self.lt.svt_path(req.M.shape, req.kinds) == "blocked" else 0
+        return 1 if "blocked" in self.lt.svt_path(req.M.shape, req.kinds) else 0
 
     def footprint(self, req):
         lt = self.lt

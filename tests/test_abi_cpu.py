@@ -79,14 +79,20 @@ def test_svt_path_by_shape():
     from paper_2202_02870_amd import lt
     assert lt.svt_path((144, 176, 3, 50)) == "precond"
     assert lt.svt_path((144, 176, 3, 50), precondition=False) == "register"
-    assert lt.svt_path((256, 256, 3, 100)) == "register"        # n = 256 > 200: no preconditioner
-    assert lt.svt_path((512, 512, 3, 64)) == "blocked"
+    assert lt.svt_path((256, 256, 3, 100)) == "register"          # register kernel holds it: no factor
+    assert lt.svt_path((600, 256, 2)) == "precond"                  # it does not: 256 x 256 factor
+    assert lt.svt_path((256, 256, 3, 100), precondition=False) == "register"
+    assert lt.svt_path((512, 512, 3, 64)) == "precond+blocked"
+    assert lt.svt_path((512, 512, 3, 64), precondition=False) == "blocked"
     assert lt.svt_path((600, 128, 2)) == "precond"
     assert lt.svt_path((600, 128, 2), precondition=False) == "blocked"
     assert lt.svt_path((128, 600, 2), precondition=False) == "blocked"   # transposed working matrix
     assert lt.svt_path((1024, 64)) == "precond"
     assert lt.svt_path((1024, 64), precondition=False) == "register"
-    assert lt.svt_path((2048, 300)) == "blocked"
-    for bad in ((2048, 2048), (513, 513), (3000, 16)):
+    assert lt.svt_path((2048, 300)) == "precond+blocked"
+    assert lt.svt_path((2048, 300), precondition=False) == "blocked"
+    assert lt.svt_path((3000, 16)) == "precond"                     # any column length on the factor
+    assert lt.svt_path((1, 7)) == "register"                        # n = 1: nothing to factor
+    for bad, pc in (((2048, 2048), True), ((513, 513), True), ((3000, 16), False), ((2049, 300), False)):
         with pytest.raises(lt.LtError):
-            lt.svt_path(bad, precondition=False)
+            lt.svt_path(bad, precondition=pc)

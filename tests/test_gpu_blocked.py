@@ -1,6 +1,8 @@
 """GPU parity of the blocked Jacobi kernel (slices with more than 256 columns,
-or columns too long for the register-resident kernel): SVT, completion and the
-batch engine against the FP64 oracle, alone equal to in a mix."""
+or columns too long for the register-resident kernel) and of the
+global-memory Cholesky of the preconditioned path (n > 200): SVT, completion
+and the batch engine against the FP64 oracle, on the slices themselves and on
+their Cholesky factors, alone equal to in a mix."""
 import numpy as np
 import pytest
 
@@ -30,14 +32,16 @@ def rel(a, b):
 # working matrices 512 x 512 (32 lanes per pair, 16 blocks of 32 columns),
 # 300 x 280 (ragged: 10 blocks of 28), 600 x 260 from a 260 x 600 slice
 # (transposed, 64 lanes per pair, 18 blocks of 16 with 28 padding columns),
-# 2048 x 300 (64 lanes per pair and 32 rows per lane)
+# 2048 x 300 (64 lanes per pair and 32 rows per lane), 600 x 256 (preconditioned:
+# the global-memory Cholesky and the register kernel on the 256 x 256 factor)
 BLK_SHAPES = [((512, 512, 2), ("dct",)), ((300, 280, 3), ("dct",)), ((260, 600, 2), ("dct",)),
-              ((2048, 300, 1), ("identity",))]
+              ((2048, 300, 1), ("identity",)), ((600, 256, 2), ("dct",))]
 
 
+@pytest.mark.parametrize("precondition", [False, True])
 @pytest.mark.parametrize("shape,kinds", BLK_SHAPES)
-def test_svt_blocked_matches_oracle(lt, shape, kinds):
-    say("svt blocked", shape, kinds)
+def test_svt_blocked_matches_oracle(lt, shape, kinds, precondition):
+    say("svt blocked", shape, kinds, lt.svt_path(shape, kinds, precondition=precondition))
     rng = np.random.default_rng(110)
     r = 12
     mats = o.mats_for(shape, list(kinds))
@@ -46,7 +50,7 @@ def test_svt_blocked_matches_oracle(lt, shape, kinds):
     A = A + 0.05 * rng.standard_normal(shape)
     s = o.singular_values(A, mats)
     for tau in (0.0, float(np.quantile(s, 0.7)), float(s.max()) * 1.01):
-        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=False)
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=precondition)
         ref = o.svt(A, tau, mats)
         err = rel(lt.to_host(D), ref) if np.linalg.norm(ref) > 0 else float(np.abs(lt.to_host(D)).max())
         say("  tau", tau, "err", err, "sweeps", lt.to_host(sweeps).max(), "rank", lt.to_host(rank))
@@ -57,9 +61,10 @@ def test_svt_blocked_matches_oracle(lt, shape, kinds):
         assert np.all(np.abs(rk - ref_rk) <= near)
 
 
-def test_svt_blocked_rank_deficient(lt):
-    """Zero slice, rank one, repeated columns: zero pairs never rotate and the
-    exact ranks come out."""
+@pytest.mark.parametrize("precondition", [False, True])
+def test_svt_blocked_rank_deficient(lt, precondition):
+    """Zero slice, rank one, repeated columns: zero pairs never rotate (and the
+    Cholesky zeroes the dependent columns) and the exact ranks come out."""
     rng = np.random.default_rng(111)
     m, n = 320, 300
     A = np.zeros((m, n, 3))
@@ -68,19 +73,20 @@ def test_svt_blocked_rank_deficient(lt):
     A[:, :, 2] = np.concatenate([B, B], axis=1)
     mats = o.mats_for(A.shape, ["identity"])
     tau = 1e-3 * float(o.singular_values(A, mats).max())
-    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("identity",))
+    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, ("identity",), precondition=precondition)
     assert rel(lt.to_host(D), o.svt(A, tau, mats)) < 2e-5
     assert list(lt.to_host(rank)) == [0, 1, n // 2]
 
 
-def test_pga_blocked_fixed_threshold(lt):
+@pytest.mark.parametrize("precondition", [False, True])
+def test_pga_blocked_fixed_threshold(lt, precondition):
     """512 x 512 x 3 completion with a fixed threshold (the iterate carries rank
     from the first iteration), 12 iterations against the oracle."""
     import torch
     p = wl.make_problem((512, 512, 3), 10, 0.3, seed=112)
     mats = o.mats_for(p.shape, list(p.kinds))
     mu = 0.05 * float(np.linalg.norm(p.M * p.mask))
-    params = lt.pga_params(mu0=mu, max_iter=12, fixed_mu=True)
+    params = lt.pga_params(mu0=mu, max_iter=12, fixed_mu=True, precondition=precondition)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=mu, max_iter=12, fixed_mu=mu)
     err = rel(lt.to_host(X), Xo)
@@ -89,12 +95,14 @@ def test_pga_blocked_fixed_threshold(lt):
     assert err < 1e-4
 
 
-def test_pga_blocked_continuation(lt):
+@pytest.mark.parametrize("precondition", [False, True])
+def test_pga_blocked_continuation(lt, precondition):
     """300 x 280 x 2 x 2 completion with the continuation schedule, 40 iterations."""
     import torch
     p = wl.make_problem((300, 280, 2, 2), 5, 0.4, seed=113)
     s = wl.pga_schedule_params(p.M, p.mask)
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=40)
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=40,
+                           precondition=precondition)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     Xo, _ = o.complete_pga(p.M, p.mask, o.mats_for(p.shape, list(p.kinds)), mu0=s["mu0"], nu=s["nu"],
                            mu_bar=s["mu_bar"], max_iter=40)
@@ -104,10 +112,11 @@ def test_pga_blocked_continuation(lt):
     assert err < 1e-4
 
 
-def _gpu_problem(lt, p):
+def _gpu_problem(lt, p, precondition=True):
     import torch
     s = p.schedule
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=s["max_iter"])
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=s["max_iter"],
+                           precondition=precondition)
     return lt.Problem(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
 
 
@@ -123,10 +132,11 @@ def _mix(iters, seed0):
     return out
 
 
-def test_batch_with_blocked_problems(lt):
+@pytest.mark.parametrize("precondition", [False, True])
+def test_batch_with_blocked_problems(lt, precondition):
     iters = 30
     ps = _mix(iters, 900)
-    gps = [_gpu_problem(lt, p) for p in ps]
+    gps = [_gpu_problem(lt, p, precondition) for p in ps]
     b = lt.Batch(gps)
     b.step(iters)
     b.close()
@@ -142,7 +152,7 @@ def test_batch_with_blocked_problems(lt):
         assert err < 1e-4
     # alone equals in the mix, bitwise
     for i in (0, 2):
-        alone = _gpu_problem(lt, ps[i])
+        alone = _gpu_problem(lt, ps[i], precondition)
         b = lt.Batch([alone])
         b.step(iters)
         b.close()
