@@ -257,6 +257,14 @@ __host__ __device__ inline size_t slice_lds_bytes(int npairs, int ldw, int nbuf)
 }
 constexpr size_t kWgCtlBytes = 16;   // workgroup-wide rotation counters
 
+// A lane's rotation count holds two counts: rotations in the low 16 bits and
+// large rotations (cosine of the pair's angle above sqrt(tol) / 4) in the high
+// 16.  Cyclic Jacobi converges quadratically, so after a sweep whose rotations
+// were all small the next sweep's would fall below tol: a slice stops after
+// such a sweep instead of running a last sweep that only checks.
+constexpr unsigned kBigOne = 1u << 16;
+__device__ inline double big_rotation2(double tol) { return tol * (1.0 / 16.0); }
+
 // One workgroup's work: nsub slices of identical shape (I1 x I2), slice q at
 // src + q * stride; outputs likewise.
 struct Job {
@@ -330,11 +338,12 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   // tolerance is above what FP32 rounding of the products could fake; FP64
   // products otherwise.
   const bool dot32 = tol >= 1e-6;
+  const double big2 = big_rotation2(tol);
   // single-exit loop (max_sweeps >= 1): the columns stay in one register set
   for (;;) {
     na = group_sum<G>(dot64<R>(av, av, qeff));
     nb = group_sum<G>(dot64<R>(bv, bv, qeff));
-    int my_rot = 0;
+    unsigned my_rot = 0;   // this lane's rotations | large rotations << 16
     // a converged slice stays frozen in place (no rotations, no moves) while
     // the rest of its pack finishes, so its result and column order do not
     // depend on what it is packed with
@@ -377,7 +386,7 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
           }
           na = fma(-(double)t, d, pa);
           nb = fma((double)t, d, pb);
-          my_rot += (l == 0);
+          my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
         }
       }
       if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
@@ -435,23 +444,25 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
     }
     // counters of the next sweep are cleared before the barrier that precedes
     // any of their increments
+    // both halves of the sums stay below 2^16: at most 1024 / G slots of a
+    // workgroup, each meeting 2 ceil(n/2) - 1 <= 255 pairs per sweep
     if (my_rot) {
-      atomicAdd(&ctl[sweep & 1], my_rot);
-      atomicAdd(&wg_ctl[sweep & 1], my_rot);
+      atomicAdd(reinterpret_cast<unsigned*>(&ctl[sweep & 1]), my_rot);
+      atomicAdd(reinterpret_cast<unsigned*>(&wg_ctl[sweep & 1]), my_rot);
     }
     __syncthreads();
-    const int mine = ctl[sweep & 1];
-    const int any = wg_ctl[sweep & 1];
+    const unsigned mine = static_cast<unsigned>(ctl[sweep & 1]);
+    const unsigned any = static_cast<unsigned>(wg_ctl[sweep & 1]);
     if (active && t2 == 0) ctl[(sweep + 1) & 1] = 0;
     if (tid == 0) wg_ctl[(sweep + 1) & 1] = 0;
     __syncthreads();
     ++sweep;
     if (!converged) {
-      rotations += mine;
+      rotations += mine & 0xFFFFu;
       my_sweeps = sweep;
-      converged = (mine == 0);
+      converged = (mine >> 16) == 0;
     }
-    if (any == 0 || sweep >= max_sweeps) break;
+    if ((any >> 16) == 0 || sweep >= max_sweeps) break;
   }
 
   // ---- output -------------------------------------------------------------
@@ -518,15 +529,17 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
 // below: one rotation per round, then the move the pair schedule prescribes.
 // With ring_only, only the first ring phase runs (npairs rounds, npairs even),
 // in which every top meets every bottom once.  Returns this lane's count of
-// applied rotations (lane 0 of each group counts).  The register-resident body
+// applied rotations (lane 0 of each group counts; large ones also in the high
+// half, see kBigOne).  The register-resident body
 // keeps its own copy of these rounds: calling this function from it (inlined)
 // changed its register allocation and grew its stack frame.
 template <int G, int R>
-__device__ __attribute__((always_inline)) inline int sweep_rounds(
+__device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
     float (&av)[R], float (&bv)[R], double& na, double& nb, int& ida, int& idb, bool moving,
     bool dot32, double tol, int npairs, int g, int l, int qeff, float* bufA, float* bufB, int nbuf,
     int ldw, bool ring_only) {
-  int my_rot = 0;
+  unsigned my_rot = 0;
+  const double big2 = big_rotation2(tol);
   // phase state: ranges of c slots; ring phase while c is even, circle
   // tournament once c is odd; r counts the rounds of the current phase
   int c = npairs;
@@ -565,7 +578,7 @@ __device__ __attribute__((always_inline)) inline int sweep_rounds(
         }
         na = fma(-(double)t, d, pa);
         nb = fma((double)t, d, pb);
-        my_rot += (l == 0);
+        my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
       }
     }
     if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
@@ -742,9 +755,12 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
     }
     __syncthreads();
   }
+  // wg_ctl[0], [1]: rotations of even / odd sweeps; [2], [3]: large rotations
   if (tid == 0) {
     wg_ctl[0] = 0;
     wg_ctl[1] = 0;
+    wg_ctl[2] = 0;
+    wg_ctl[3] = 0;
   }
   __syncthreads();
 
@@ -759,7 +775,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
   bool converged = false;
   long long rotations = 0;
   for (;;) {
-    int my_rot = 0;
+    unsigned my_rot = 0;   // per lane at most one rotation per round: < 2^16 per sweep
     for (int br = 0; br < nblk - 1; ++br) {
       for (int pi = 0; pi < nblk / 2; ++pi) {
         const int A = blk_at(pi, br, nblk), B = blk_at(nblk - 1 - pi, br, nblk);
@@ -780,15 +796,20 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
         __syncthreads();
       }
     }
-    if (my_rot) atomicAdd(&wg_ctl[sweep & 1], my_rot);
+    if (my_rot & 0xFFFFu) atomicAdd(&wg_ctl[sweep & 1], (int)(my_rot & 0xFFFFu));
+    if (my_rot >> 16) atomicAdd(&wg_ctl[2 + (sweep & 1)], (int)(my_rot >> 16));
     __syncthreads();
     const int any = wg_ctl[sweep & 1];
-    if (tid == 0) wg_ctl[(sweep + 1) & 1] = 0;
+    const int anybig = wg_ctl[2 + (sweep & 1)];
+    if (tid == 0) {
+      wg_ctl[(sweep + 1) & 1] = 0;
+      wg_ctl[2 + ((sweep + 1) & 1)] = 0;
+    }
     __syncthreads();
     ++sweep;
     rotations += any;
     my_sweeps = sweep;
-    converged = (any == 0);
+    converged = (anybig == 0);
     if (converged || sweep >= max_sweeps) break;
   }
 
