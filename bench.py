@@ -38,7 +38,7 @@ PEAK_HBM = 8.0e12
 # and WRITE_SIZE passes scaled by a 256 MiB device copy in the same run (fetch x2.0,
 # write x1.0); the command lines and raw figures are in profiles/.  Reported only
 # for that configuration and this kernel version (null elsewhere).
-JACOBI_TRAFFIC_VIDEO_BYTES = 26678412
+JACOBI_TRAFFIC_VIDEO_BYTES = 26619301
 
 
 def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True):

@@ -131,6 +131,9 @@ __device__ inline void wave_sync() {
 // block.  A pivot at or below n * 64 eps64 * max diag(C) zeroes its column.
 // Writes L in FP32 (n x n column-major, zero above the diagonal) over the first
 // half of the slice's own C region.
+// PANEL_IN_LDS: solve the panel rows in place in LDS (the batch kernel, where
+// a register copy of the row spilled) rather than in registers.
+template <bool PANEL_IN_LDS>
 __device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
   extern __shared__ __attribute__((aligned(16))) double T[];
   __shared__ double dmax_s;
@@ -192,14 +195,28 @@ __device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
       }
     }
     __syncthreads();
-    // (b) panel: row i >= K + kb solves x L11^T = T(i, K .. K + kb - 1), in place
-    // (each lane owns its row)
+    // (b) panel: row i >= K + kb solves x L11^T = T(i, K .. K + kb - 1) (each
+    // lane owns its row)
     for (int i = K + kb + tid; i < n; i += nt) {
-      for (int q = 0; q < kb; ++q) {
-        double acc = T[tri_off(K + q, n) + i - K - q];
-        for (int p = 0; p < q; ++p)
-          acc = fma(-T[tri_off(K + p, n) + i - K - p], T[tri_off(K + p, n) + q - p], acc);
-        T[tri_off(K + q, n) + i - K - q] = acc * dinv_s[q];
+      if (PANEL_IN_LDS) {
+        for (int q = 0; q < kb; ++q) {
+          double acc = T[tri_off(K + q, n) + i - K - q];
+          for (int p = 0; p < q; ++p)
+            acc = fma(-T[tri_off(K + p, n) + i - K - p], T[tri_off(K + p, n) + q - p], acc);
+          T[tri_off(K + q, n) + i - K - q] = acc * dinv_s[q];
+        }
+      } else {
+        double x[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+          if (q < kb) {
+            double acc = T[tri_off(K + q, n) + i - K - q];
+#pragma unroll
+            for (int p = 0; p < q; ++p) acc = fma(-x[p], T[tri_off(K + p, n) + q - p], acc);
+            x[q] = acc * dinv_s[q];
+            T[tri_off(K + q, n) + i - K - q] = x[q];
+          }
+        }
       }
     }
     __syncthreads();
@@ -369,7 +386,7 @@ __global__ __launch_bounds__(1024) void k_chol_global_items(ProbDev* const* prob
 }
 
 __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
-  chol_slice(a.C + (long long)blockIdx.x * a.c_stride, a.n);
+  chol_slice<false>(a.C + (long long)blockIdx.x * a.c_stride, a.n);
 }
 
 __global__ __launch_bounds__(1024) void k_chol_items(ProbDev* const* probs, const CholItem* items) {
@@ -377,7 +394,7 @@ __global__ __launch_bounds__(1024) void k_chol_items(ProbDev* const* probs, cons
   const ProbDev* pd = probs[it.prob];
   if (!pd->active) return;
   const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
-  chol_slice(pd->C + (long long)it.slice * n * n, n);
+  chol_slice<true>(pd->C + (long long)it.slice * n * n, n);
 }
 
 }  // namespace
