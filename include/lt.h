@@ -70,7 +70,8 @@ typedef enum {
 } lt_precision;
 
 /* Operations, for lt_workspace_bytes. */
-typedef enum { LT_OP_LPRODUCT = 0, LT_OP_LSVD = 1, LT_OP_SVT = 2, LT_OP_PGA = 3 } lt_op;
+typedef enum { LT_OP_LPRODUCT = 0, LT_OP_LSVD = 1, LT_OP_SVT = 2, LT_OP_PGA = 3,
+               LT_OP_TRUNCATE = 4 } lt_op;
 
 /* Tensor shape and transform.  Host struct, read during the call only. */
 typedef struct {
@@ -191,6 +192,15 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
             float* V, float* sigma, int transform_domain, const lt_svd_opts* opts,
             void* ws, size_t ws_bytes);
+
+/* A_k = U(:, 1:k) *_L S(1:k, 1:k) *_L V(:, 1:k)^T, the best approximation of A
+ * by products X *_L Y with X of k lateral slices (Eckart-Young theorem,
+ * Section 3.2): every slice of L(A) keeps its k largest singular triplets
+ * (all of them when k >= min(I1, I2); A_k = 0 when k <= 0), then L^{-1}.
+ * Same slice limits as lt_lsvd (min(I1, I2) <= 256, max(I1, I2) <= 2048).
+ * Ak may alias A.  Workspace: lt_workspace_bytes(a, NULL, LT_OP_TRUNCATE, prec). */
+int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, float* Ak,
+                 const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 
 /* How the SVT of descriptor a's slices runs with options opts (may be NULL):
  * LT_SVT_PRECOND and LT_SVT_BLOCKED bits (0: the register kernel on the slice),

@@ -257,6 +257,24 @@ def svt(A, tau, mats):
     return D
 
 
+def truncate(A, k, mats):
+    """Rank-k approximation A_k = U(:, 1:k) *_L S(1:k, 1:k) *_L V(:, 1:k)^T of
+    the Eckart-Young theorem (Section 3.2): the best approximation of A by
+    X *_L Y with X of k lateral slices; per slice of L(A), the k largest
+    singular triplets, then L^{-1}."""
+    Ah = slices(transform(A, mats))
+    P = Ah.shape[0]
+    Th = np.empty_like(Ah)
+    for p in range(P):
+        U, s, Vt = np.linalg.svd(Ah[p], full_matrices=False)
+        kk = max(0, min(int(k), s.size))
+        Th[p] = (U[:, :kk] * s[:kk]) @ Vt[:kk]
+    T = inverse_transform(unslices(Th, A.shape), mats)
+    if np.iscomplexobj(T) and not np.iscomplexobj(A):
+        T = T.real
+    return T
+
+
 def svt_ranks(A, tau, mats):
     """Number of transform-domain singular values above tau, per slice: the rank
     of every slice of L(D_tau(A)) (multirank of the SVT result)."""

@@ -880,6 +880,12 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
       carve_lsvd(c, s, precision, &w);
       break;
     }
+    case LT_OP_TRUNCATE: {
+      LsvdWs w;
+      carve_lsvd(c, s, precision, &w);
+      (void)c.take<int32_t>((size_t)s.P);   // kept count per slice
+      break;
+    }
     default: return 0;
   }
   return c.off + 256;
@@ -1039,6 +1045,91 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
       return rc;
   }
   return LT_OK;
+}
+
+int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, float* Ak,
+                 const lt_svd_opts* opts, void* ws, size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!A || !Ak) return fail(h, LT_ERR_ARG, "A or Ak is NULL");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  lt::JacobiConfig cfg;
+  if ((rc = jacobi_config(h, s, &cfg))) return rc;
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
+  if (n > 256 || mrows > 2048)
+    return fail(h, LT_ERR_SHAPE, "truncation supports min(I1, I2) <= 256 and max(I1, I2) <= 2048");
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_TRUNCATE, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdWs w;
+  carve_lsvd(c, s, prec, &w);
+  int32_t* kept = c.take<int32_t>((size_t)s.P);
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  const int P = (int)s.P;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_FORWARD)))
+    return rc;
+  // per slice: all singular triplets (Jacobi, then sorted and normalised),
+  // transform domain
+  lt::JacobiArgs j{};
+  j.src = w.Ah;
+  j.slice_stride = s.N;
+  j.I1 = (int)s.I1;
+  j.I2 = (int)s.I2;
+  j.nslices = P;
+  j.tau = 0.0;
+  j.tol = tol;
+  j.max_sweeps = max_sweeps;
+  j.mode = 1;
+  j.bk = w.cols;
+  j.sweeps = w.sweeps;
+  j.sigma = w.sigma;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+  }
+  lt::LsvdArgs f{};
+  f.W = w.Ah;
+  f.cols = w.cols;
+  f.sigma = w.sigma;
+  f.slice_stride = s.N;
+  f.I1 = (int)s.I1;
+  f.I2 = (int)s.I2;
+  f.nslices = P;
+  f.U = w.Uh;
+  f.S = w.Sh;
+  f.V = w.Vh;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_lsvd_finalize(f, h->stream));
+  }
+  // A_k's slice in working orientation: U_k U_k^T W = U_k S_k V_k^T, with U_k
+  // the first k left singular vectors of the working matrix (m x n, slice
+  // stride m n = I1 I2)
+  const int kk = k <= 0 ? 0 : (k < n ? (int)k : (int)n);
+  HIP_TRY(h, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(kept), kk, (size_t)P, h->stream));
+  lt::RebuildArgs r{};
+  r.W = w.Ah;
+  r.D = w.Ah;
+  r.bk = s.I1 < s.I2 ? w.Vh : w.Uh;
+  r.rank = kept;
+  r.slice_stride = s.N;
+  r.I1 = (int)s.I1;
+  r.I2 = (int)s.I2;
+  r.nslices = P;
+  r.flip = 0;
+  {
+    ProfScope ps(h, LT_PROF_REBUILD);
+    HIP_TRY(h, lt::launch_rebuild(r, h->stream));
+  }
+  return gemm(h, gemm_plain(w.t, true, P, s.N, w.Ah, Ak), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+              LT_PROF_INVERSE);
 }
 
 int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_t* mask,

@@ -27,7 +27,7 @@ ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1,
 WARN_MAXSWEEPS, WARN_NOT_CONVERGED = 1, 2
 KIND = {"dct": 0, "dft": 1, "identity": 2, "custom": 3}
 PREC = {"f32": 0, "bf16x3": 1}
-OP = {"lproduct": 0, "lsvd": 1, "svt": 2, "pga": 3}
+OP = {"lproduct": 0, "lsvd": 1, "svt": 2, "pga": 3, "truncate": 4}
 
 
 class Desc(ctypes.Structure):
@@ -84,6 +84,8 @@ _sig = {
     "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_svt_path": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
+    "lt_ltruncate": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_int32, _vp,
+                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_svt_prox": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_complete_pga": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, ctypes.POINTER(PgaParams),
@@ -218,6 +220,32 @@ def _workspace(nbytes, ws):
 
 def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True):
     return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, 0)
+
+
+def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None):
+    """Rank-k approximation A_k = U(:, 1:k) *_L S(1:k, 1:k) *_L V(:, 1:k)^T
+    (Eckart-Young theorem); out may be A."""
+    shape = tuple(A.shape)
+    _check_tensor(A, shape, name="A")
+    d = make_desc(shape, kinds)
+    Ak = out if out is not None else fortran_empty(shape)
+    _check_tensor(Ak, shape, name="Ak")
+    nb = workspace_bytes(shape, kinds, "truncate", precision)
+    w = _workspace(nb, ws)
+    h = _handle()
+    o = svd_opts(jacobi_tol, max_sweeps, precision)
+    _check(h, _lib.lt_ltruncate(h, ctypes.byref(d), _ptr(A), int(k), _ptr(Ak), ctypes.byref(o), _ptr(w), nb))
+    return Ak
+
+
+def multirank(A, kinds=None, rtol=1e-5):
+    """Multirank (rank of every slice of L(A), counting singular values above
+    rtol times the largest of the tensor), its average, and the tubal rank
+    (the largest), from the transform-domain singular values of lsvd."""
+    sigma = to_host(lsvd(A, kinds, transform_domain=True)[3]).astype(np.float64)
+    smax = float(sigma.max()) if sigma.size else 0.0
+    rho = (sigma > rtol * max(smax, 1e-300)).sum(axis=1)
+    return rho, float(rho.mean()), int(rho.max()) if rho.size else 0
 
 
 def svt_path(shape, kinds=None, precondition=True):

@@ -53,6 +53,22 @@ def test_lproduct(lt, sa, sb, kinds, precision, tol):
     assert rel(lt.to_host(C), ref) < tol
 
 
+@pytest.mark.parametrize("trailing", [(5,), (3, 4)])
+def test_cproduct_block_toeplitz_plus_hankel(lt, trailing):
+    """The c-product on the GPU (the transform M_c as a custom matrix per mode):
+    btph(A *_c B) = btph(A) btph(B), the block Toeplitz-plus-Hankel structure
+    of the c-product (eq. (3.22) and the order-N construction)."""
+    rng = np.random.default_rng(103)
+    A = rng.standard_normal((6, 4) + trailing)
+    B = rng.standard_normal((4, 5) + trailing)
+    mats = o.mats_for(A.shape, ["cprod"] * len(trailing))
+    C = lt.to_host(lt.lproduct(lt.to_device(A), lt.to_device(B), tuple(mats))).astype(np.float64)
+    lhs, rhs = o.btph(C), o.btph(A) @ o.btph(B)
+    err = float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs))
+    say("c-product btph", trailing, err)
+    assert err < 1e-5
+
+
 # --------------------------------------------------------------------- SVT --
 
 SVT_SHAPES = [
@@ -182,6 +198,46 @@ def test_lsvd_rank_deficient_completes_basis(lt):
     for Q in (U, V):
         for q in o.slices(o.transform(Q, mats)):
             assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 1e-4
+
+
+# ------------------------------------------- rank-k truncation (Eckart-Young) --
+
+@pytest.mark.parametrize("shape,kinds", [((12, 9, 5), ("dct",)), ((9, 14, 3, 2), ("dct", "dct")),
+                                         ((64, 48, 4), ("identity",)), ((100, 160, 3), ("dct",))])
+def test_ltruncate_matches_oracle(lt, shape, kinds):
+    """A_k on the GPU against the oracle's Eckart-Young tensor, on a rank-3
+    signal plus small noise (a clear gap after the third singular value), for
+    k = 0, 3 and min(I1, I2); the error norm equals the tail of the oracle's
+    singular values."""
+    rng = np.random.default_rng(107)
+    mats = o.mats_for(shape, list(kinds))
+    A = o.lproduct(rng.standard_normal((shape[0], 3) + shape[2:]),
+                   rng.standard_normal((3, shape[1]) + shape[2:]), mats)
+    A = A + 0.01 * rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    n = min(shape[0], shape[1])
+    for k in (0, 3, n):
+        Ak = lt.to_host(lt.ltruncate(lt.to_device(A), k, kinds)).astype(np.float64)
+        ref = o.truncate(A, k, mats)
+        if k == 0:
+            assert np.abs(Ak).max() == 0.0
+            continue
+        err = rel(Ak, ref)
+        tail = float(np.sqrt((s[:, k:] ** 2).sum()))
+        resid = float(np.linalg.norm(A - Ak))
+        say("  truncate", shape, "k", k, "err", err, "residual", resid, "tail", tail)
+        assert err < 2e-5
+        assert abs(resid - tail) <= 1e-4 * np.linalg.norm(A) + 1e-3 * tail
+
+
+def test_multirank_of_low_rank_product(lt):
+    rng = np.random.default_rng(108)
+    shape = (20, 16, 3, 2)
+    mats = o.mats_for(shape, ["dct", "dct"])
+    A = o.lproduct(rng.standard_normal((20, 4, 3, 2)), rng.standard_normal((4, 16, 3, 2)), mats)
+    rho, avg, tubal = lt.multirank(lt.to_device(A), ("dct", "dct"))
+    assert np.all(rho == 4) and avg == 4.0 and tubal == 4
+    assert np.array_equal(rho, o.multirank(A, mats, rtol=1e-5)[0])
 
 
 # --------------------------------------------------------- completion (PGA) --

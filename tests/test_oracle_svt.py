@@ -61,6 +61,42 @@ def test_eckart_young_error():
     assert abs(o.fro(A - Ak) ** 2 - sum(tubes[k:])) < 1e-10
 
 
+@pytest.mark.parametrize("kinds", [["dct"], ["dft"], ["dct", "identity"]])
+def test_truncate_is_the_eckart_young_tensor(kinds):
+    """truncate(A, k) equals the theorem's U(:,1:k) *_L S(1:k,1:k) *_L V(:,1:k)^T
+    built from lsvd and lproduct, its error is the tail of the singular tubes,
+    and no product X *_L Y with k lateral slices does better."""
+    rng = np.random.default_rng(24)
+    shape = (7, 5) + ((4,) if len(kinds) == 1 else (3, 2))
+    A = rng.standard_normal(shape)
+    mats = o.mats_for(shape, kinds)
+    U, S, V = o.lsvd(A, mats)
+    for k in (1, 2, 4):
+        Ak = o.truncate(A, k, mats)
+        ref = o.lproduct(o.lproduct(U[:, :k], S[:k, :k], mats), o.ttranspose(V[:, :k], mats), mats)
+        assert np.abs(Ak - ref).max() < 1e-10
+        tails = sum(o.fro(S[i, i]) ** 2 for i in range(k, 5))
+        err = o.fro(A - Ak)
+        assert abs(err ** 2 - tails) < 1e-9 * o.fro(A) ** 2
+        for _ in range(20):
+            X = rng.standard_normal((7, k) + shape[2:])
+            Y = rng.standard_normal((k, 5) + shape[2:])
+            B = o.lproduct(X, Y, mats)
+            if np.iscomplexobj(B):
+                B = B.real
+            assert o.fro(A - B) >= err - 1e-12
+        rho, _ = o.multirank(Ak, mats, rtol=1e-9)
+        assert np.all(rho <= k)
+
+
+def test_truncate_limits():
+    A = np.random.default_rng(25).standard_normal((6, 4, 3))
+    mats = o.mats_for(A.shape, ["dct"])
+    assert np.abs(o.truncate(A, 4, mats) - A).max() < 1e-12
+    assert np.abs(o.truncate(A, 9, mats) - A).max() < 1e-12
+    assert np.abs(o.truncate(A, 0, mats)).max() == 0.0
+
+
 def test_multirank_of_product():
     rng = np.random.default_rng(23)
     mats = o.mats_for((8, 7, 3, 2), ["dct", "dct"])
