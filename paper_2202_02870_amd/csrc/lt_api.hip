@@ -88,6 +88,7 @@ struct Shape {
   int kind[LT_MAX_ORDER] = {0};
   const double* custom[LT_MAX_ORDER] = {nullptr};
   bool any_custom = false;
+  bool any_dft = false;   // Fourier modes: complex transform-domain slices
 };
 
 int parse(lt_handle* h, const lt_desc* d, Shape* s) {
@@ -104,9 +105,7 @@ int parse(lt_handle* h, const lt_desc* d, Shape* s) {
   s->nmodes = d->order - 2;
   for (int i = 2; i < d->order; ++i) {
     const int k = d->kind[i];
-    if (k == LT_DFT)
-      return fail(h, LT_ERR_UNSUPPORTED, "mode %d: the DFT (complex slices) is not run on the GPU", i + 1);
-    if (k != LT_DCT && k != LT_IDENTITY && k != LT_CUSTOM)
+    if (k != LT_DCT && k != LT_DFT && k != LT_IDENTITY && k != LT_CUSTOM)
       return fail(h, LT_ERR_ARG, "mode %d: unknown kind %d", i + 1, k);
     if (k == LT_CUSTOM && !d->custom[i])
       return fail(h, LT_ERR_ARG, "mode %d: LT_CUSTOM without a matrix", i + 1);
@@ -114,6 +113,7 @@ int parse(lt_handle* h, const lt_desc* d, Shape* s) {
     s->kind[i - 2] = k;
     s->custom[i - 2] = d->custom[i];
     s->any_custom |= (k == LT_CUSTOM);
+    s->any_dft |= (k == LT_DFT);
     s->P *= d->dims[i];
     if (s->P > kMaxP) return fail(h, LT_ERR_SHAPE, "more than %d frontal slices", kMaxP);
   }
@@ -145,9 +145,10 @@ struct TransformWs {
 
 void carve_transform(Carver& c, const Shape& s, int precision, TransformWs* t) {
   const size_t P2 = (size_t)s.P * s.P;
-  t->K = c.take<float>(P2);
-  t->Kinv = c.take<float>(P2);
-  if (precision == LT_PREC_BF16X3) {
+  // Fourier modes: the stacked real forms, 2P x P and P x 2P (FP32 only)
+  t->K = c.take<float>(s.any_dft ? 2 * P2 : P2);
+  t->Kinv = c.take<float>(s.any_dft ? 2 * P2 : P2);
+  if (precision == LT_PREC_BF16X3 && !s.any_dft) {
     t->Khi = c.take<uint16_t>(P2);
     t->Klo = c.take<uint16_t>(P2);
     t->Kihi = c.take<uint16_t>(P2);
@@ -216,6 +217,11 @@ int build_transform(lt_handle* h, const Shape& s, int precision, const Transform
     }
   }
   ProfScope ps(h, LT_PROF_OTHER);
+  if (s.any_dft) {
+    HIP_TRY(h, lt::launch_build_kron_dft(fwd, (int)s.P, 0, t.K, h->stream));
+    HIP_TRY(h, lt::launch_build_kron_dft(inv, (int)s.P, 1, t.Kinv, h->stream));
+    return LT_OK;
+  }
   HIP_TRY(h, lt::launch_build_kron(fwd, (int)s.P, 0, t.K, t.Khi, t.Klo, h->stream));
   HIP_TRY(h, lt::launch_build_kron(inv, (int)s.P, 1, t.Kinv, t.Kihi, t.Kilo, h->stream));
   (void)precision;
@@ -223,7 +229,7 @@ int build_transform(lt_handle* h, const Shape& s, int precision, const Transform
 }
 
 lt::GemmArgs gemm_plain(const TransformWs& t, bool inverse, int P, long long N, const float* in,
-                        float* out) {
+                        float* out, bool dft = false) {
   lt::GemmArgs g{};
   g.K = inverse ? t.Kinv : t.K;
   g.Khi = inverse ? t.Kihi : t.Khi;
@@ -232,6 +238,10 @@ lt::GemmArgs gemm_plain(const TransformWs& t, bool inverse, int P, long long N, 
   g.N = N;
   g.B = in;
   g.out = out;
+  if (dft) {   // real and imaginary planes: 2P rows out of the forward, into the inverse
+    if (inverse) g.Kd = 2 * P;
+    else g.Mo = 2 * P;
+  }
   return g;
 }
 
@@ -267,6 +277,30 @@ int jacobi_config(lt_handle* h, const Shape& s, lt::JacobiConfig* cfg) {
   return LT_OK;
 }
 
+// The SVT buffers of slices of one shape (the Jacobi's kept columns, counters,
+// Gram / Cholesky blocks, blocked-kernel working buffers).
+struct SvtCore {
+  float* Bk = nullptr;
+  int32_t* rank = nullptr;
+  int32_t* sweeps = nullptr;
+  double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
+  float* work = nullptr;  // blocked Jacobi: per-slice working buffers
+};
+
+// Fourier modes: the transform-domain slices are complex, in two planes (real
+// then imaginary, P x N each).  For real data slice q = conj(p) of its partner
+// (negated frequency indices along the Fourier modes), so one slice per pair is
+// thresholded, through the real embedding [[X, -Y], [Y, X]] (2 I1 x 2 I2): its
+// singular values are those of X + iY, each twice, and its SVT is the
+// embedding of the complex SVT (of which the left block column is [Re; Im]).
+struct DftWs {
+  float* E = nullptr;         // embeddings of the representatives, npairs x 4N
+  int32_t* rep = nullptr;     // representative slice of each pair (p <= its partner)
+  int32_t* partner = nullptr;
+  int npairs = 0;
+  SvtCore inner;              // SVT buffers of the embeddings
+};
+
 struct SvtWs {
   TransformWs t;
   float* Gh = nullptr;
@@ -275,7 +309,42 @@ struct SvtWs {
   int32_t* sweeps = nullptr;
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
+  DftWs dft;              // Fourier modes only
 };
+
+// Representatives and partners of the conjugate pairs of slices (slice index:
+// first trailing mode fastest; partner: Fourier indices negated modulo I_i).
+void dft_pairs(const Shape& s, std::vector<int>* rep, std::vector<int>* partner) {
+  rep->clear();
+  partner->clear();
+  for (long long p = 0; p < s.P; ++p) {
+    long long rem = p, q = 0, stride = 1;
+    for (int m = 0; m < s.nmodes; ++m) {
+      const long long d = s.n[m], k = rem % d;
+      rem /= d;
+      q += (s.kind[m] == LT_DFT ? (d - k) % d : k) * stride;
+      stride *= d;
+    }
+    if (p <= q) {
+      rep->push_back((int)p);
+      partner->push_back((int)q);
+    }
+  }
+}
+
+Shape embed_shape(const Shape& s, int npairs) {
+  Shape e;
+  e.order = 3;
+  e.I1 = 2 * s.I1;
+  e.I2 = 2 * s.I2;
+  e.P = npairs;
+  e.N = e.I1 * e.I2;
+  e.nel = e.N * e.P;
+  e.nmodes = 1;
+  e.n[0] = npairs;
+  e.kind[0] = LT_IDENTITY;
+  return e;
+}
 
 // The preconditioned SVT path takes slices with 2 <= n <= LT_PRECOND_MAX_N
 // (the Cholesky of the n x n Gram matrix runs in LDS up to n = 200, in global
@@ -344,9 +413,7 @@ int check_blk_lds(lt_handle* h, const Shape& s, const lt::JacobiBlkConfig& c) {
   return LT_OK;
 }
 
-void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
-  carve_transform(c, s, prec, &w->t);
-  w->Gh = c.take<float>((size_t)s.nel);
+void carve_svt_core(Carver& c, const Shape& s, SvtCore* w) {
   w->Bk = c.take<float>((size_t)s.nel);
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
@@ -354,6 +421,45 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   if (svt_plan(s, true, &pp) && pp.precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
   const long long wf = blocked_work_floats(s);
   if (wf) w->work = c.take<float>((size_t)s.P * (size_t)wf);
+}
+
+void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
+  carve_transform(c, s, prec, &w->t);
+  if (!s.any_dft) {
+    w->Gh = c.take<float>((size_t)s.nel);
+    SvtCore core;
+    carve_svt_core(c, s, &core);
+    w->Bk = core.Bk;
+    w->rank = core.rank;
+    w->sweeps = core.sweeps;
+    w->C = core.C;
+    w->work = core.work;
+    return;
+  }
+  w->Gh = c.take<float>(2 * (size_t)s.nel);   // real plane, then imaginary plane
+  w->rank = c.take<int32_t>((size_t)s.P);
+  w->sweeps = c.take<int32_t>((size_t)s.P);
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  DftWs& d = w->dft;
+  d.npairs = (int)rep.size();
+  d.rep = c.take<int32_t>(rep.size());
+  d.partner = c.take<int32_t>(rep.size());
+  const Shape se = embed_shape(s, d.npairs);
+  d.E = c.take<float>((size_t)se.nel);
+  carve_svt_core(c, se, &d.inner);
+}
+
+// Upload the pair tables of a Fourier workspace (once per call).
+int dft_prepare(lt_handle* h, const Shape& s, const SvtWs& w) {
+  if (!s.any_dft) return LT_OK;
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  HIP_TRY(h, hipMemcpyAsync(w.dft.rep, rep.data(), rep.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(w.dft.partner, partner.data(), partner.size() * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));   // the host vectors go out of scope
+  return LT_OK;
 }
 
 struct PgaWs {
@@ -415,7 +521,7 @@ int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
   return LT_OK;
 }
 
-int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtWs& w,
+int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtCore& w,
                    double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
                    unsigned long long* sweep_total, unsigned long long* rot_total,
                    unsigned int* hits, bool precond) {
@@ -497,12 +603,64 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   return LT_OK;
 }
 
+SvtCore core_of(const SvtWs& w) {
+  SvtCore c;
+  c.Bk = w.Bk;
+  c.rank = w.rank;
+  c.sweeps = w.sweeps;
+  c.C = w.C;
+  c.work = w.work;
+  return c;
+}
+
+// SVT of the transform-domain slices of w.Gh in place: real slices directly,
+// complex ones (Fourier modes) through the real embeddings of one slice per
+// conjugate pair.  rank / sweeps: per slice (P entries).
+int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol, int max_sweeps,
+            int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total, unsigned long long* rot_total,
+            unsigned int* hits, bool precond) {
+  if (!s.any_dft)
+    return run_jacobi_svt(h, s, w.Gh, w.Gh, core_of(w), tau, tol, max_sweeps, rank, sweeps, sweep_total,
+                          rot_total, hits, precond);
+  const DftWs& d = w.dft;
+  const Shape se = embed_shape(s, d.npairs);
+  float* Re = w.Gh;
+  float* Im = w.Gh + s.nel;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_dft_embed(Re, Im, d.rep, d.npairs, (int)s.I1, (int)s.I2, d.E, h->stream));
+  }
+  int rc = run_jacobi_svt(h, se, d.E, d.E, d.inner, tau, tol, max_sweeps, d.inner.rank, d.inner.sweeps,
+                          sweep_total, rot_total, hits, precond);
+  if (rc) return rc;
+  ProfScope ps(h, LT_PROF_OTHER);
+  HIP_TRY(h, lt::launch_dft_extract(d.E, d.rep, d.partner, d.npairs, (int)s.I1, (int)s.I2, Re, Im,
+                                    d.inner.rank, rank, d.inner.sweeps, sweeps, h->stream));
+  return LT_OK;
+}
+
+// Operations that take Fourier modes: the SVT and the completion, FP32 only.
+int check_dft(lt_handle* h, const Shape& s, int prec, bool op_supports) {
+  if (!s.any_dft) return LT_OK;
+  if (!op_supports)
+    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes are supported by lt_svt_prox and lt_complete_pga only");
+  if (prec != LT_PREC_F32)
+    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes take the FP32 transform only");
+  return LT_OK;
+}
+
 bool precond_requested(const lt_svd_opts* o) { return !(o && o->no_precondition); }
 
 // The SVT of this shape is supported: by the preconditioned path (any m, n up
 // to LT_PRECOND_MAX_N), by the register-resident Jacobi kernel on the slice
 // itself, or by the blocked kernel (n <= 512, m <= 2048).
-int check_svt_shape(lt_handle* h, const Shape& s, bool precond) {
+int check_svt_shape(lt_handle* h, const Shape& s0, bool precond) {
+  Shape s = s0;
+  if (s0.any_dft) {
+    std::vector<int> rep, partner;
+    dft_pairs(s0, &rep, &partner);
+    s = embed_shape(s0, (int)rep.size());
+  }
   SvtPlan p;
   if (!svt_plan(s, precond, &p))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels (n <= 512, m <= 2048 "
@@ -617,6 +775,7 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
   for (int i = 0; i < n; ++i) {
     int rc = parse(h, probs[i].desc, &shapes[i]);
     if (rc) return rc;
+    if ((rc = check_dft(h, shapes[i], LT_PREC_F32, false))) return rc;
     double tol;
     int max_sweeps, prec;
     resolve_opts(&probs[i].params.svd, &tol, &max_sweeps, &prec);
@@ -853,6 +1012,7 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
   Shape s;
   if (parse(nullptr, a, &s) != LT_OK) return 0;
   if (precision != LT_PREC_F32 && precision != LT_PREC_BF16X3) return 0;
+  if (s.any_dft && (precision != LT_PREC_F32 || (op != LT_OP_SVT && op != LT_OP_PGA))) return 0;
   Carver c(nullptr);
   switch (op) {
     case LT_OP_SVT: {
@@ -895,6 +1055,11 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   Shape s;
   int rc = parse(nullptr, a, &s);
   if (rc) return rc;
+  if (s.any_dft) {   // the Jacobi runs on the real embeddings of the complex slices
+    std::vector<int> rep, partner;
+    dft_pairs(s, &rep, &partner);
+    s = embed_shape(s, (int)rep.size());
+  }
   SvtPlan p;
   if (!svt_plan(s, precond_requested(opts), &p)) return LT_ERR_SHAPE;
   return (p.precond ? LT_SVT_PRECOND : 0) | (p.blocked ? LT_SVT_BLOCKED : 0);
@@ -913,21 +1078,22 @@ int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, floa
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
   if ((rc = check_svt_shape(h, s, precond_requested(opts)))) return rc;
   const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_SVT, prec);
   if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
   Carver c(ws);
   SvtWs w;
   carve_svt(c, s, prec, &w);
+  if ((rc = dft_prepare(h, s, w))) return rc;
   if ((rc = build_transform(h, s, prec, w.t))) return rc;
-  if ((rc = gemm(h, gemm_plain(w.t, false, (int)s.P, s.N, A, w.Gh), prec, lt::PRO_PLAIN,
+  if ((rc = gemm(h, gemm_plain(w.t, false, (int)s.P, s.N, A, w.Gh, s.any_dft), prec, lt::PRO_PLAIN,
                  lt::EPI_PLAIN, LT_PROF_FORWARD)))
     return rc;
-  rc = run_jacobi_svt(h, s, w.Gh, w.Gh, w, tau, tol, max_sweeps, rank_out ? rank_out : w.rank,
-                      sweeps_out ? sweeps_out : w.sweeps, nullptr, nullptr, nullptr,
-                      precond_requested(opts));
+  rc = run_svt(h, s, w, tau, tol, max_sweeps, rank_out ? rank_out : w.rank, sweeps_out ? sweeps_out : w.sweeps,
+               nullptr, nullptr, nullptr, precond_requested(opts));
   if (rc) return rc;
-  return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Gh, D), prec, lt::PRO_PLAIN,
+  return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Gh, D, s.any_dft), prec, lt::PRO_PLAIN,
               lt::EPI_PLAIN, LT_PROF_INVERSE);
 }
 
@@ -940,6 +1106,7 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
   if ((rc = parse(h, b, &sb))) return rc;
   if (!A || !B || !C) return fail(h, LT_ERR_ARG, "A, B or C is NULL");
   if ((rc = check_prec(h, precision))) return rc;
+  if ((rc = check_dft(h, sa, precision, false))) return rc;
   if (sa.order != sb.order || sa.I2 != sb.I1)
     return fail(h, LT_ERR_SHAPE, "inner dimensions differ (%lld vs %lld)", sa.I2, sb.I1);
   for (int i = 2; i < sa.order; ++i)
@@ -983,6 +1150,7 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, false))) return rc;
   lt::JacobiConfig cfg;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
@@ -1058,6 +1226,7 @@ int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, floa
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, false))) return rc;
   lt::JacobiConfig cfg;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
@@ -1148,12 +1317,14 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   int max_sweeps, prec;
   resolve_opts(&p->svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
   if ((rc = check_svt_shape(h, s, precond_requested(&p->svd)))) return rc;
   const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_PGA, prec);
   if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
   Carver c(ws);
   PgaWs w;
   carve_pga(c, s, prec, &w);
+  if ((rc = dft_prepare(h, s, w.svt))) return rc;
   hipStream_t st = h->stream;
 
   // NaN / Inf among the observed entries: one host sync before any iteration
@@ -1184,18 +1355,17 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     const double beta = (t_prev - 1.0) / t;   // eq. (52)
     const double mu_k = p->fixed_mu ? p->mu0 : mu;
 
-    lt::GemmArgs f = gemm_plain(w.svt.t, false, (int)s.P, s.N, nullptr, w.svt.Gh);
+    lt::GemmArgs f = gemm_plain(w.svt.t, false, (int)s.P, s.N, nullptr, w.svt.Gh, s.any_dft);
     f.X = Xcur;
     f.Xp = Xprev;
     f.M = M;
     f.mask = mask;
     f.beta = (float)beta;
     if ((rc = gemm(h, f, prec, lt::PRO_PGA, lt::EPI_PLAIN, LT_PROF_FORWARD))) return rc;
-    rc = run_jacobi_svt(h, s, w.svt.Gh, w.svt.Gh, w.svt, mu_k, tol, max_sweeps, w.svt.rank,
-                        w.svt.sweeps, w.sweep_total, w.rot_total, w.maxsweep_hits,
-                        precond_requested(&p->svd));
+    rc = run_svt(h, s, w.svt, mu_k, tol, max_sweeps, w.svt.rank, w.svt.sweeps, w.sweep_total, w.rot_total,
+                 w.maxsweep_hits, precond_requested(&p->svd));
     if (rc) return rc;
-    lt::GemmArgs b = gemm_plain(w.svt.t, true, (int)s.P, s.N, w.svt.Gh, Xprev);
+    lt::GemmArgs b = gemm_plain(w.svt.t, true, (int)s.P, s.N, w.svt.Gh, Xprev, s.any_dft);
     b.X = Xcur;
     b.Xp = Xprev;
     b.beta = (float)beta;
@@ -1251,7 +1421,8 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     rep->reserved = 0;
     rep->last_crit = crit;
     rep->total_sweeps = (int64_t)sweeps_total;
-    rep->total_slices = (int64_t)iters * s.P;
+    // slice SVDs performed: one per conjugate pair under Fourier modes
+    rep->total_slices = (int64_t)iters * (s.any_dft ? w.svt.dft.npairs : s.P);
     rep->total_rotations = (int64_t)rots;
   }
   if (p->tol > 0 && !converged) return LT_WARN_NOT_CONVERGED;
@@ -1263,6 +1434,7 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   Shape s;
   if (parse(nullptr, a, &s) != LT_OK || !p || p->max_iter < 1) return 0;
   if (p->svd.precision != LT_PREC_F32 && p->svd.precision != LT_PREC_BF16X3) return 0;
+  if (s.any_dft) return 0;   // the batch engine runs real transforms only
   Carver c(nullptr);
   ProblemWs w;
   carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), &w);
@@ -1280,6 +1452,7 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   int max_sweeps, prec;
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, false))) return rc;
   SvtPlan plan;
   if (!svt_plan(s, problem_precond(s, &p->params), &plan))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);

@@ -47,6 +47,9 @@ struct GemmArgs {
   // the output position and accumulates ||Y - out||^2, ||out||^2 per workgroup
   float* out;
   double* partials;        // [gridDim.x * gridDim.y][2]
+  // Fourier transforms (stacked real form): output rows Mo and contraction
+  // length Kd when nonzero (K is Mo x Kd row-major), else P and P
+  int Mo, Kd;
 };
 
 hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int epi,
@@ -68,6 +71,16 @@ hipError_t launch_build_kron(const KronDesc& d, int P, int inverse, float* K,
 
 hipError_t launch_reduce_partials(const double* partials, int n, double* out2,
                                   hipStream_t s);
+// Transforms with Fourier modes (kind 1 in KronDesc), stacked real form:
+// forward [Re K; Im K] (2P x P), inverse [Re K^{-1}, -Im K^{-1}] (P x 2P).
+hipError_t launch_build_kron_dft(const KronDesc& d, int P, int inverse, float* K, hipStream_t s);
+// Complex slices (planes Re, Im: P x I1 x I2) <-> real embeddings of the
+// representatives rep[0..npairs) of their conjugate pairs (2 I1 x 2 I2 each).
+hipError_t launch_dft_embed(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
+                            float* E, hipStream_t s);
+hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner, int npairs, int I1, int I2,
+                              float* Re, float* Im, const int32_t* rankE, int32_t* rank,
+                              const int32_t* sweepsE, int32_t* sweeps, hipStream_t s);
 
 // C^p = A^p B^p for p < P; A^p: I1 x L (ld I1), B^p: L x I2 (ld L), C^p: I1 x I2.
 hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L,

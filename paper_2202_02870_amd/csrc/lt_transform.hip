@@ -68,23 +68,24 @@ __device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const long long e0 = (long long)tx * TE;
   const int q0 = ty * TQ;
-  const int P = a.P;
+  const int Mo = a.Mo ? a.Mo : a.P;   // output rows
+  const int Kd = a.Kd ? a.Kd : a.P;   // contraction length (input rows)
   const long long N = a.N;
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int p0 = 0; p0 < P; p0 += TPK) {
+  for (int p0 = 0; p0 < Kd; p0 += TPK) {
     for (int idx = tid; idx < TQ * TPK; idx += 256) {
       const int i = idx / TPK, k = idx - i * TPK;
       const int q = q0 + i, p = p0 + k;
-      Ks[i][k] = (q < P && p < P) ? a.K[(long long)q * P + p] : 0.f;
+      Ks[i][k] = (q < Mo && p < Kd) ? a.K[(long long)q * Kd + p] : 0.f;
     }
     for (int idx = tid; idx < TPK * TE; idx += 256) {
       const int k = idx / TE, j = idx - k * TE;
       const int p = p0 + k;
       const long long e = e0 + j;
-      Bs[k][j] = (p < P && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
+      Bs[k][j] = (p < Kd && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -106,7 +107,7 @@ __device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
     for (int v = 0; v < 4; ++v) {
       const int q = q0 + 16 * w + 4 * (l >> 4) + v;
       const long long e = e0 + 16 * t + (l & 15);
-      if (q < P && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
+      if (q < Mo && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
     }
   }
   if (EPI == EPI_PGA) {
@@ -138,25 +139,26 @@ __device__ void gemm_bf16x3_tile(const GemmArgs& a, int tx, int ty, double* part
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const long long e0 = (long long)tx * TE;
   const int q0 = ty * TQ;
-  const int P = a.P;
+  const int Mo = a.Mo ? a.Mo : a.P;
+  const int Kd = a.Kd ? a.Kd : a.P;
   const long long N = a.N;
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int p0 = 0; p0 < P; p0 += TPK) {
+  for (int p0 = 0; p0 < Kd; p0 += TPK) {
     for (int idx = tid; idx < TQ * TPK; idx += 256) {
       const int i = idx / TPK, k = idx - i * TPK;
       const int q = q0 + i, p = p0 + k;
-      const bool in = (q < P && p < P);
-      Kh[i][k] = in ? a.Khi[(long long)q * P + p] : (uint16_t)0;
-      Kl[i][k] = in ? a.Klo[(long long)q * P + p] : (uint16_t)0;
+      const bool in = (q < Mo && p < Kd);
+      Kh[i][k] = in ? a.Khi[(long long)q * Kd + p] : (uint16_t)0;
+      Kl[i][k] = in ? a.Klo[(long long)q * Kd + p] : (uint16_t)0;
     }
     for (int idx = tid; idx < TPK * TE; idx += 256) {
       const int k = idx / TE, j = idx - k * TE;
       const int p = p0 + k;
       const long long e = e0 + j;
-      const float v = (p < P && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
+      const float v = (p < Kd && e < N) ? load_operand<PRO>(a, (long long)p * N + e) : 0.f;
       const uint16_t h = f32_to_bf16_bits(v);
       Bh[j][k] = h;
       Bl[j][k] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
@@ -187,7 +189,7 @@ __device__ void gemm_bf16x3_tile(const GemmArgs& a, int tx, int ty, double* part
     for (int v = 0; v < 4; ++v) {
       const int q = q0 + 16 * w + 4 * (l >> 4) + v;
       const long long e = e0 + 16 * t + (l & 15);
-      if (q < P && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
+      if (q < Mo && e < N) store_result<EPI>(a, (long long)q * N + e, acc[t][v], s1, s2);
     }
   }
   if (EPI == EPI_PGA) {
@@ -322,6 +324,100 @@ __global__ void k_build_kron(KronDesc d, int P, int inverse, float* K, uint16_t*
   }
 }
 
+// Stacked real form of a transform with Fourier modes (Section 2: F_n =
+// [w^{jk}], w = exp(-2 pi i / n), F_n^{-1} = F_n^* / n).  Forward: [Re K; Im K]
+// (2P x P, row-major), so that for a real input the GEMM writes the real plane
+// (rows 0..P-1) and the imaginary plane (rows P..2P-1) of the transform-domain
+// slices.  Inverse: [Re K^{-1}, -Im K^{-1}] (P x 2P), so that the GEMM over both
+// planes writes Re(K^{-1} (Dr + i Di)), the (real) result for
+// conjugate-symmetric slices.
+__global__ void k_build_kron_dft(KronDesc d, int P, int inverse, float* K) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)P * P) return;
+  const int q = (int)(idx / P), p = (int)(idx % P);
+  int rq = q, rp = p;
+  double vr = 1.0, vi = 0.0;
+  for (int m = 0; m < d.nmodes; ++m) {
+    const int n = d.n[m];
+    const int j = rq % n, k = rp % n;
+    rq /= n;
+    rp /= n;
+    double er, ei = 0.0;
+    if (d.kind[m] == 1) {
+      const double ang = 2.0 * M_PI * (double)(((long long)j * k) % n) / (double)n;
+      er = cos(ang);
+      ei = inverse ? sin(ang) : -sin(ang);
+      if (inverse) {
+        er /= n;
+        ei /= n;
+      }
+    } else if (d.kind[m] == 0) {
+      er = inverse ? dct_entry(k, j, n) : dct_entry(j, k, n);
+    } else if (d.kind[m] == 2) {
+      er = (j == k) ? 1.0 : 0.0;
+    } else {
+      er = d.custom[m][(long long)j * n + k];
+    }
+    const double tr = vr * er - vi * ei;
+    vi = vr * ei + vi * er;
+    vr = tr;
+  }
+  if (!inverse) {
+    K[(long long)q * P + p] = (float)vr;
+    K[(long long)(P + q) * P + p] = (float)vi;
+  } else {
+    K[(long long)q * 2 * P + p] = (float)vr;
+    K[(long long)q * 2 * P + P + p] = (float)(-vi);
+  }
+}
+
+// Real embedding [[X, -Y], [Y, X]] (2 I1 x 2 I2, column-major) of the complex
+// slice X + iY of every representative slice rep[t] of a conjugate pair: its
+// singular values are those of X + iY, each twice, and its SVT is the
+// embedding of the complex SVT.
+__global__ void k_dft_embed(const float* __restrict__ Re, const float* __restrict__ Im, const int* rep,
+                            int I1, int I2, long long N, float* __restrict__ E) {
+  const int t = blockIdx.y;
+  const long long n4 = 4 * N;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n4) return;
+  const int r = (int)(e % (2 * I1)), c = (int)(e / (2 * I1));
+  const bool top = r < I1, left = c < I2;
+  const int i = top ? r : r - I1, j = left ? c : c - I2;
+  const long long src = (long long)rep[t] * N + (long long)j * I1 + i;
+  const float x = Re[src], y = Im[src];
+  E[(long long)t * n4 + e] = top ? (left ? x : -y) : (left ? y : x);
+}
+
+// Complex SVT result of slice rep[t] from the thresholded embedding (its left
+// block column holds [Re D; Im D]); the partner slice gets the conjugate, a
+// self-conjugate slice a zero imaginary part.  Ranks and sweeps per slice (the
+// embedding counts every singular value twice).
+__global__ void k_dft_extract(const float* __restrict__ E, const int* rep, const int* partner, int I1,
+                              int I2, long long N, float* __restrict__ Re, float* __restrict__ Im,
+                              const int32_t* rankE, int32_t* rank, const int32_t* sweepsE,
+                              int32_t* sweeps) {
+  const int t = blockIdx.y;
+  const int p = rep[t], q = partner[t];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {
+    if (rank) rank[p] = rank[q] = rankE[t] / 2;
+    if (sweeps) sweeps[p] = sweeps[q] = sweepsE[t];
+  }
+  if (e >= N) return;
+  const int i = (int)(e % I1), j = (int)(e / I1);
+  const float* Et = E + (long long)t * 4 * N + (long long)j * 2 * I1;
+  const float re = Et[i], im = Et[I1 + i];
+  Re[(long long)p * N + e] = re;
+  if (q == p) {
+    Im[(long long)p * N + e] = 0.f;
+  } else {
+    Im[(long long)p * N + e] = im;
+    Re[(long long)q * N + e] = re;
+    Im[(long long)q * N + e] = -im;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n, double* out) {
   double s1 = 0.0, s2 = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -410,7 +506,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int epi,
                                  hipStream_t s, int* n_partials) {
   if (a.P <= 0 || a.N <= 0) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((a.N + TE - 1) / TE), (unsigned)((a.P + TQ - 1) / TQ));
+  const int Mo = a.Mo ? a.Mo : a.P;
+  dim3 grid((unsigned)((a.N + TE - 1) / TE), (unsigned)((Mo + TQ - 1) / TQ));
   if (n_partials) *n_partials = (int)(grid.x * grid.y);
   const int key = (precision ? 4 : 0) | (pro << 1) | epi;
   switch (key) {
@@ -432,6 +529,33 @@ hipError_t launch_build_kron(const KronDesc& d, int P, int inverse, float* K, ui
   const long long n = (long long)P * P;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_build_kron, dim3(blocks), dim3(256), 0, s, d, P, inverse, K, Khi, Klo);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_kron_dft(const KronDesc& d, int P, int inverse, float* K, hipStream_t s) {
+  const long long n = (long long)P * P;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_build_kron_dft, dim3(blocks), dim3(256), 0, s, d, P, inverse, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_embed(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
+                            float* E, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const long long N = (long long)I1 * I2;
+  dim3 grid((unsigned)((4 * N + 255) / 256), (unsigned)npairs);
+  hipLaunchKernelGGL(k_dft_embed, grid, dim3(256), 0, s, Re, Im, rep, I1, I2, N, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner, int npairs, int I1, int I2,
+                              float* Re, float* Im, const int32_t* rankE, int32_t* rank,
+                              const int32_t* sweepsE, int32_t* sweeps, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const long long N = (long long)I1 * I2;
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)npairs);
+  hipLaunchKernelGGL(k_dft_extract, grid, dim3(256), 0, s, E, rep, partner, I1, I2, N, Re, Im, rankE, rank,
+                     sweepsE, sweeps);
   return hipGetLastError();
 }
 

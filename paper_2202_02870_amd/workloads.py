@@ -8,8 +8,8 @@ This module draws random numbers and assembles inputs; it holds none of the
 completion arithmetic (no SVD, thresholding, momentum or transform matrices of
 the library or of the oracle).  A tensor of prescribed L-rank is assembled as
 A *_L B from random factors; that one product is done with SciPy's orthonormal
-DCT-II (`scipy.fft.dctn` / `idctn`) and `numpy.matmul`, library routines that
-neither the oracle nor the HIP library uses.
+DCT-II (`scipy.fft.dctn` / `idctn`), its FFT for Fourier modes, and a per-slice
+matmul, library routines that neither the oracle nor the HIP library uses.
 
 Draw order for one problem: factor A, factor B, noise, mask (all float64 from
 `numpy.random.default_rng(seed)`, PCG64).
@@ -38,15 +38,24 @@ def _dct_axes(kinds):
     return [i + 2 for i, k in enumerate(kinds) if k == "dct"]
 
 
+def _dft_axes(kinds):
+    return [i + 2 for i, k in enumerate(kinds) if k == "dft"]
+
+
 def _low_lrank(A, B, kinds):
-    """A *_L B for L = orthonormal DCT-II along the modes marked 'dct'
-    (identity elsewhere), via SciPy's DCT and per-slice matmul."""
-    axes = _dct_axes(kinds)
-    Ah = sfft.dctn(A, type=2, norm="ortho", axes=axes) if axes else A
-    Bh = sfft.dctn(B, type=2, norm="ortho", axes=axes) if axes else B
-    # per-frontal-slice matrix product over the trailing modes
-    Ch = np.einsum("ik...,kj...->ij...", Ah, Bh)
-    return sfft.idctn(Ch, type=2, norm="ortho", axes=axes) if axes else Ch
+    """A *_L B for L = orthonormal DCT-II along the modes marked 'dct' and the
+    DFT along those marked 'dft' (identity elsewhere), via SciPy's DCT / FFT and
+    per-slice matmul; real part (exact for real factors)."""
+    dct, dft = _dct_axes(kinds), _dft_axes(kinds)
+
+    def fwd(X):
+        X = sfft.dctn(X, type=2, norm="ortho", axes=dct) if dct else X
+        return sfft.fftn(X, axes=dft) if dft else X
+
+    Ch = np.einsum("ik...,kj...->ij...", fwd(A), fwd(B))
+    C = sfft.ifftn(Ch, axes=dft) if dft else Ch
+    C = sfft.idctn(C.real if dft else C, type=2, norm="ortho", axes=dct) if dct else C
+    return np.real(C)
 
 
 def make_problem(shape, rank, observed, seed, kinds=None, dist="uniform",

@@ -59,8 +59,16 @@ def test_workspace_sizes_host_only():
     assert lt.workspace_bytes((144, 176, 3, 50), None, "pga", "bf16x3") > n_pga
     assert lt.workspace_bytes((8, 3, 5), None, "lproduct", shape_b=(3, 7, 5)) > 0
     assert lt.workspace_bytes((16, 12, 4), None, "lsvd") > 0
-    with pytest.raises(ValueError):          # DFT slices are complex: rejected
-        lt.workspace_bytes((8, 8, 4), ("dft",), "svt")
+    # Fourier modes: SVT and completion (FP32) hold two planes and the real
+    # embeddings of one slice per conjugate pair (P = 4: pairs {0}, {1, 3}, {2})
+    n_dft = lt.workspace_bytes((8, 8, 4), ("dft",), "svt")
+    assert n_dft >= 2 * 8 * 8 * 4 * 4 + 3 * 16 * 16 * 4 * 2
+    assert lt.workspace_bytes((8, 8, 4), ("dft",), "pga") > n_dft
+    for op, prec in (("svt", "bf16x3"), ("lsvd", "f32"), ("truncate", "f32")):
+        with pytest.raises(ValueError):      # other operations and BF16 transforms: rejected
+            lt.workspace_bytes((8, 8, 4), ("dft",), op, prec)
+    with pytest.raises(ValueError):
+        lt.workspace_bytes((8, 3, 4), ("dft",), "lproduct", shape_b=(3, 5, 4))
     with pytest.raises(ValueError):          # zero-sized mode
         lt.workspace_bytes((8, 0, 4), None, "svt")
 
@@ -93,6 +101,10 @@ def test_svt_path_by_shape():
     assert lt.svt_path((2048, 300), precondition=False) == "blocked"
     assert lt.svt_path((3000, 16)) == "precond"                     # any column length on the factor
     assert lt.svt_path((1, 7)) == "register"                        # n = 1: nothing to factor
+    # Fourier modes: the Jacobi runs on 2 I1 x 2 I2 real embeddings
+    assert lt.svt_path((100, 80, 4), ("dft",)) == "precond"                 # 200 x 160
+    assert lt.svt_path((100, 80, 4), ("dft",), precondition=False) == "register"
+    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "precond+blocked"   # 288 x 352
     for bad, pc in (((2048, 2048), True), ((513, 513), True), ((3000, 16), False), ((2049, 300), False)):
         with pytest.raises(lt.LtError):
             lt.svt_path(bad, precondition=pc)

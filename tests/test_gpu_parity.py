@@ -200,6 +200,60 @@ def test_lsvd_rank_deficient_completes_basis(lt):
             assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 1e-4
 
 
+# ------------------------------------------------ Fourier transform (complex) --
+
+DFT_SHAPES = [((8, 6, 5), ("dft",)), ((10, 7, 4, 3), ("dft", "dct")), ((5, 9, 6), ("dft",)),
+              ((12, 10, 4, 2), ("dft", "dft")), ((48, 40, 3, 4), ("dct", "dft"))]
+
+
+@pytest.mark.parametrize("shape,kinds", DFT_SHAPES)
+def test_svt_prox_fourier(lt, shape, kinds):
+    """SVT with the DFT along some trailing modes (complex transform-domain
+    slices, thresholded through their real embeddings, one per conjugate pair)
+    against the oracle's complex SVT."""
+    say("svt dft", shape, kinds)
+    rng = np.random.default_rng(109)
+    mats = o.mats_for(shape, list(kinds))
+    r = max(1, min(shape[0], shape[1]) // 4)
+    A = o.lproduct(rng.standard_normal((shape[0], r) + shape[2:]),
+                   rng.standard_normal((r, shape[1]) + shape[2:]), mats).real
+    A = A + 0.05 * rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    for tau in (0.0, float(np.quantile(s, 0.7)), float(s.max()) * 1.01):
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds)
+        ref = o.svt(A, tau, mats)
+        err = rel(lt.to_host(D), ref) if np.linalg.norm(ref) > 0 else float(np.abs(lt.to_host(D)).max())
+        say("  tau", tau, "err", err, "ranks", lt.to_host(rank)[:6])
+        assert err < 2e-5
+        rk = lt.to_host(rank)
+        ref_rk = o.svt_ranks(A, tau, mats)
+        near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
+        assert np.all(np.abs(rk - ref_rk) <= near)
+
+
+@pytest.mark.parametrize("shape,kinds,fixed", [((32, 32, 8), ("dft",), True), ((24, 20, 4, 3), ("dft", "dft"), False)])
+def test_pga_fourier(lt, shape, kinds, fixed):
+    """Completion with the DFT transform (the t-product's TNN-PGA-F variant)
+    against the oracle."""
+    import torch
+    p = wl.make_problem(shape, 3, 0.5, seed=114, kinds=kinds, dist="normal", rescale=False)
+    mats = o.mats_for(shape, list(kinds))
+    s = wl.pga_schedule_params(p.M, p.mask)
+    iters = 50
+    if fixed:
+        mu = 0.05 * s["mu0"]
+        params = lt.pga_params(mu0=mu, max_iter=iters, fixed_mu=True)
+        Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=mu, max_iter=iters, fixed_mu=mu)
+    else:
+        params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
+        Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
+    X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, kinds)
+    err = rel(lt.to_host(X), Xo)
+    say("pga dft", shape, kinds, "err", err, rep)
+    assert np.linalg.norm(Xo) > 0
+    assert err < 1e-4
+
+
 # ------------------------------------------- rank-k truncation (Eckart-Young) --
 
 @pytest.mark.parametrize("shape,kinds", [((12, 9, 5), ("dct",)), ((9, 14, 3, 2), ("dct", "dct")),
@@ -343,8 +397,10 @@ def test_pga_degenerate_masks(lt):
 def test_error_paths(lt):
     import torch
     A = lt.to_device(np.ones((8, 8, 4)))
+    with pytest.raises(ValueError):                   # Fourier modes: SVT and completion only
+        lt.lproduct(A, A, ("dft",))
     with pytest.raises(ValueError):
-        lt.svt_prox(A, 0.1, ("dft",))                # workspace query rejects the DFT
+        lt.svt_prox(A, 0.1, ("dft",), precision="bf16x3")
     M = np.ones((8, 8, 4))
     M[1, 2, 3] = np.nan
     mask = np.ones(M.shape, np.uint8)
