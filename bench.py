@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="video/large: run one 256 MiB device copy before the timed region (counter reference)")
+    ap.add_argument("--transform", default="dct", choices=["dct", "dft"],
+                    help="video workload: transform along the trailing modes (dft: the t-product form)")
     ap.add_argument("--no-precondition", action="store_true",
                     help="run the Jacobi SVD on the slices themselves (no Cholesky-QR factor)")
     ap.add_argument("--lanes", default="auto",
@@ -115,7 +117,10 @@ def main():
         return bench_mix(args, torch, lt, wl)
     if args.workload == "serve":
         return bench_serve(args, torch, lt, wl)
-    p = {"video": wl.config1, "large": wl.config2, "big": wl.config4_large}[args.workload]()
+    if args.workload == "video":
+        p = wl.config1(transform=args.transform)
+    else:
+        p = {"large": wl.config2, "big": wl.config4_large}[args.workload]()
     shape = p.shape
     I1, I2 = shape[0], shape[1]
     P = wl.n_slices(shape)
@@ -161,14 +166,15 @@ def main():
     jcalls, jms = prof["jacobi"]
     path = lt.svt_path(shape, p.kinds, precondition=not args.no_precondition)
     precond = "precond" in path
-    rows = n if precond else m
-    f64, f32 = jacobi_flops(rows, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
+    jm, jn = (2 * m, 2 * n) if "dft" in p.kinds else (m, n)   # Fourier: real embeddings of the slices
+    rows = jn if precond else jm
+    f64, f32 = jacobi_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
     per_launch = (f64 + f32) / max(jcalls, 1)
     t_launch = jms / 1e3 / max(jcalls, 1)
     t_peak = (f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU) / max(jcalls, 1)
     achieved = per_launch / t_launch / 1e12 if t_launch > 0 else 0.0
     peak = per_launch / t_peak / 1e12 if t_peak > 0 else 0.0
-    measured_cfg = args.workload == "video" and args.precision == "f32" and precond
+    measured_cfg = args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
     roofline = {"bound": "alu", "kernel": "k_jacobi", "achieved": round(achieved, 3),
                 "peak": round(peak, 2), "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None,

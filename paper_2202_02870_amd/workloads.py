@@ -116,13 +116,15 @@ def config0():
     return p
 
 
-def config1(trailing=(3, 50)):
+def config1(trailing=(3, 50), transform="dct"):
     """Order-4 video-shaped completion: 144x176x3x50 of L-rank 10 (DCT along
-    modes 3 and 4), factors U[0,1], rescaled to [0,1], 30% observed; 200
-    iterations with continuation mu0 = 0.9 ||P_Omega M||, nu = 0.9,
-    mu_bar = 1e-4 mu0."""
-    p = make_problem((144, 176) + tuple(trailing), 10, 0.3, seed=1,
-                     name="video-144x176x%s-r10-obs0.3" % "x".join(map(str, trailing)))
+    modes 3 and 4; transform="dft": the DFT, the t-product form), factors
+    U[0,1], rescaled to [0,1], 30% observed; 200 iterations with continuation
+    mu0 = 0.9 ||P_Omega M||, nu = 0.9, mu_bar = 1e-4 mu0."""
+    kinds = (transform,) * len(trailing)
+    p = make_problem((144, 176) + tuple(trailing), 10, 0.3, seed=1, kinds=kinds,
+                     name="video-144x176x%s-r10-obs0.3%s" % ("x".join(map(str, trailing)),
+                                                             "" if transform == "dct" else "-" + transform))
     p.schedule = dict(pga_schedule_params(p.M, p.mask), max_iter=200, tol=0.0)
     return p
 
