@@ -759,6 +759,7 @@ struct BatchTables {
   int blk_threads[lt::kBlkNumVariants] = {};
   size_t blk_lds[lt::kBlkNumVariants] = {};
   std::vector<lt::RebuildTile> rebuild_wide;
+  int rebuild_kmax = 0, rebuild_wide_kmax = 0;   // largest min(I1, I2) of each tile list
   bool any_reg = false;
   lt::JacobiBatchConfig cfg{};
   int prec = 0, max_sweeps = 40;
@@ -846,6 +847,8 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     const int mw = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
     const int ncols = pc ? mw : ns[i];
     std::vector<lt::RebuildTile>& rt = ns[i] > 256 ? T->rebuild_wide : T->rebuild;
+    int& kmax = ns[i] > 256 ? T->rebuild_wide_kmax : T->rebuild_kmax;
+    kmax = ns[i] > kmax ? ns[i] : kmax;
     for (int sl = 0; sl < (int)s.P; ++sl)
       for (int j0 = 0; j0 < ncols; j0 += 16) rt.push_back(lt::RebuildTile{i, sl, j0, 0});
     T->rebuild_slices += (size_t)s.P;
@@ -1687,10 +1690,11 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
   }
   {
     ProfScope ps(prof ? h : nullptr, LT_PROF_REBUILD);
-    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild, (int)T.rebuild.size(), 0, s)) != hipSuccess)
-      return e;
-    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild_wide, (int)T.rebuild_wide.size(), 1, s)) !=
+    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild, (int)T.rebuild.size(), 0, T.rebuild_kmax, s)) !=
         hipSuccess)
+      return e;
+    if ((e = lt::launch_rebuild_tiles(b->w.ptrs, b->w.rebuild_wide, (int)T.rebuild_wide.size(), 1,
+                                      T.rebuild_wide_kmax, s)) != hipSuccess)
       return e;
   }
   {

@@ -161,6 +161,7 @@ struct RebuildArgs {
   long long slice_stride;
   int I1, I2, nslices;
   int flip;                // 0: D_W = Bk (Bk^T W), Bk m x r; 1: D_W = (W B) B^T, B n x r
+  int rcap;                // set by launch_rebuild: kept-column capacity of its LDS
 };
 
 // Cholesky-QR preconditioning of the Jacobi SVD (lt_precond.hip).
@@ -242,9 +243,10 @@ hipError_t launch_gemm_grouped(ProbDev* const* probs, const GemmTile* tiles, int
                                int inverse, hipStream_t s);
 hipError_t launch_batch_begin(ProbDev* const* probs, int nprob, hipStream_t s);
 hipError_t launch_batch_end(ProbDev* const* probs, int nprob, hipStream_t s);
-// wide: tiles of slices with more than 256 columns (up to 512 kept columns)
+// wide: tiles of slices with more than 256 columns (up to 512 kept columns);
+// kmax: the largest min(I1, I2) of the tiles' problems (bounds the kept count)
 hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, int wide,
-                                hipStream_t s);
+                                int kmax, hipStream_t s);
 hipError_t launch_gram_tiles(ProbDev* const* probs, const GramTile* tiles, int ntiles, hipStream_t s);
 hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
                              hipStream_t s);

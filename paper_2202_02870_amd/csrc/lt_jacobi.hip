@@ -989,13 +989,23 @@ __device__ inline float w_at(const float* W, bool trans, int I1, int row, int co
 
 // Working columns j0 .. j0+15 of one slice: Z = Bk^T W(:, j0..) (r x 16), then
 // D_W(:, j0..) = Bk Z.  W and D may alias: the tile is read in full before any
-// of it is written, and no other workgroup touches these entries.
+// of it is written, and no other workgroup touches these entries.  The kept
+// columns' LDS (a chunk of Bk and Z) is sized by the launch for rcap >= r
+// columns (dynamic), so small slices keep more workgroups per CU.
+__host__ __device__ inline size_t rebuild_lds_bytes(int rcap) {
+  return ((size_t)RB_TK * (rcap + 1) + (size_t)rcap * (RB_TN + 1)) * sizeof(float);
+}
+
+__host__ __device__ inline int rebuild_rcap(int kmax) { return ((kmax + 15) / 16) * 16; }
+
 template <int RMAX>
 __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
-                             bool flip) {
+                             bool flip, int rcap) {
   __shared__ float Ws[RB_TK][RB_TN + 1];
-  __shared__ float Bs[RB_TK][RMAX + 1];
-  __shared__ float Z[RMAX][RB_TN + 1];
+  extern __shared__ float rb_dyn[];
+  const int ldb = rcap + 1;
+  float* Bs = rb_dyn;                    // RB_TK x ldb: a chunk of rows of Bk
+  float* Z = rb_dyn + RB_TK * ldb;       // rcap x (RB_TN + 1)
   // flip: the working matrix is W^T (n x m), so the same two products give
   // D_W^T = B (B^T W^T), i.e. D_W = (W B) B^T with B n x r
   const bool trans = (I1 < I2) != flip;
@@ -1021,21 +1031,21 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
       for (int idx = tid; idx < RB_TK * rpad; idx += 256) {
         const int kk = idx % RB_TK, i = idx / RB_TK;
         const int row = k0 + kk;
-        Bs[kk][i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
+        Bs[kk * ldb + i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
       }
       __syncthreads();
       for (int kk = 0; kk < RB_TK; ++kk) {
         const float w = Ws[kk][jj];
 #pragma unroll
         for (int q = 0; q < RMAX / 16; ++q)
-          if (q < nq) zacc[q] = fmaf(Bs[kk][hi + 16 * q], w, zacc[q]);
+          if (q < nq) zacc[q] = fmaf(Bs[kk * ldb + hi + 16 * q], w, zacc[q]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
   for (int q = 0; q < RMAX / 16; ++q)
-    if (q < nq) Z[hi + 16 * q][jj] = zacc[q];
+    if (q < nq) Z[(hi + 16 * q) * (RB_TN + 1) + jj] = zacc[q];
   __syncthreads();
 
   // phase B: D_W[k][j0 + jj] = sum_i Bk[k][i] Z[i][jj]
@@ -1043,14 +1053,14 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
     for (int idx = tid; idx < RB_TK * rpad; idx += 256) {
       const int kk = idx % RB_TK, i = idx / RB_TK;
       const int row = k0 + kk;
-      Bs[kk][i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
+      Bs[kk * ldb + i] = (row < m && i < r) ? Bk[(long long)i * m + row] : 0.f;
     }
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int kk = hi + 16 * h;
       float acc = 0.f;
-      for (int i = 0; i < r; ++i) acc = fmaf(Bs[kk][i], Z[i][jj], acc);
+      for (int i = 0; i < r; ++i) acc = fmaf(Bs[kk * ldb + i], Z[i * (RB_TN + 1) + jj], acc);
       const int row = k0 + kk, col = j0 + jj;
       if (row < m && col < n) {
         if (trans) D[(long long)row * I1 + col] = acc;
@@ -1068,17 +1078,18 @@ __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
   const int j0 = blockIdx.x * RB_TN;
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
-  rebuild_body<RMAX>(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
+  rebuild_body<RMAX>(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0, a.rcap);
 }
 
 template <int RMAX>
-__global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles) {
+__global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles,
+                                                       int rcap) {
   const RebuildTile t = tiles[blockIdx.x];
   const ProbDev* pd = probs[t.prob];
   if (!pd->active) return;
   const long long off = (long long)t.slice * pd->N;
   rebuild_body<RMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
-                     pd->precond != 0);
+                     pd->precond != 0, rcap);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
@@ -1493,12 +1504,22 @@ hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items,
 }
 
 hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles, int ntiles, int wide,
-                                hipStream_t s) {
+                                int kmax, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (wide)
-    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX_BLK>, dim3(ntiles), dim3(256), 0, s, probs, tiles);
-  else
-    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX>, dim3(ntiles), dim3(256), 0, s, probs, tiles);
+  const int rcap = rebuild_rcap(kmax);
+  if (kmax < 1 || rcap > (wide ? RB_RMAX_BLK : RB_RMAX)) return hipErrorInvalidValue;
+  const size_t lds = rebuild_lds_bytes(rcap);
+  if (wide) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rebuild_tiles<RB_RMAX_BLK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX_BLK>, dim3(ntiles), dim3(256), lds, s, probs, tiles, rcap);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rebuild_tiles<RB_RMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rebuild_tiles<RB_RMAX>, dim3(ntiles), dim3(256), lds, s, probs, tiles, rcap);
+  }
   return hipGetLastError();
 }
 
@@ -1508,10 +1529,20 @@ hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   const int kmax = a.I1 < a.I2 ? a.I1 : a.I2;   // kept columns are at most min(I1, I2)
   if (kmax > RB_RMAX_BLK) return hipErrorInvalidValue;
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
-  if (kmax > RB_RMAX)
-    hipLaunchKernelGGL(k_rebuild<RB_RMAX_BLK>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_rebuild<RB_RMAX>, grid, dim3(256), 0, s, a);
+  RebuildArgs b = a;
+  b.rcap = rebuild_rcap(kmax);
+  const size_t lds = rebuild_lds_bytes(b.rcap);
+  if (kmax > RB_RMAX) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rebuild<RB_RMAX_BLK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rebuild<RB_RMAX_BLK>, grid, dim3(256), lds, s, b);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rebuild<RB_RMAX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rebuild<RB_RMAX>, grid, dim3(256), lds, s, b);
+  }
   return hipGetLastError();
 }
 
