@@ -419,3 +419,41 @@ def test_error_paths(lt):
     with pytest.raises(lt.LtError) as e:
         lt.svt_prox(A, -1.0)
     assert e.value.status == lt.ERR_ARG
+
+
+# ----------------------------------------------------- randomized shape sweep --
+
+def _random_svt_cases(n_cases=24, seed=120):
+    """Seeded slice shapes covering every Jacobi path: register-resident (packed
+    and not), preconditioned (LDS and global-memory Cholesky), blocked, and the
+    Fourier embeddings; odd and even column counts, transposed and not."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    small = [1, 2, 3, 5, 8, 17, 31, 64, 97, 130]
+    large = [201, 230, 257, 300, 390]
+    for c in range(n_cases):
+        if c % 2:   # both sides large: global-memory Cholesky, blocked kernel
+            I1, I2 = (int(x) for x in rng.choice(large, 2))
+        else:
+            I1, I2 = (int(x) for x in rng.choice(small + large, 2))
+        kind = str(rng.choice(["dct", "identity", "dft"]))
+        P = int(rng.choice([1, 2, 3]))
+        if kind == "dft" and min(I1, I2) > 130:
+            kind = "dct"                      # the embeddings double both sides
+        cases.append(((I1, I2, P), (kind,), bool(rng.random() < 0.5)))
+    return cases
+
+
+@pytest.mark.parametrize("shape,kinds,precondition", _random_svt_cases())
+def test_svt_random_shapes(lt, shape, kinds, precondition):
+    rng = np.random.default_rng(hash(shape) % (2 ** 31))
+    mats = o.mats_for(shape, list(kinds))
+    A = rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    tau = float(np.quantile(s, 0.5)) if s.size else 0.0
+    path = lt.svt_path(shape, kinds, precondition=precondition)
+    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=precondition)
+    ref = o.svt(A, tau, mats)
+    err = rel(lt.to_host(D), ref) if np.linalg.norm(ref) > 0 else float(np.abs(lt.to_host(D)).max())
+    say("  random svt", shape, kinds, path, "err", err)
+    assert err < 2e-5
