@@ -241,7 +241,8 @@ def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", o
 def multirank(A, kinds=None, rtol=1e-5):
     """Multirank (rank of every slice of L(A), counting singular values above
     rtol times the largest of the tensor), its average, and the tubal rank
-    (the largest), from the transform-domain singular values of lsvd."""
+    (the largest), from the transform-domain singular values of lsvd (slices
+    up to 256 columns, real transforms)."""
     sigma = to_host(lsvd(A, kinds, transform_domain=True)[3]).astype(np.float64)
     smax = float(sigma.max()) if sigma.size else 0.0
     rho = (sigma > rtol * max(smax, 1e-300)).sum(axis=1)

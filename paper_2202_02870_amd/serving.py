@@ -83,6 +83,8 @@ class GpuExecutor:
         d = lt.make_desc(req.M.shape, req.kinds)
         prm = self._params(req)
         ws = lt._lib.lt_problem_workspace_bytes(lt.ctypes.byref(d), lt.ctypes.byref(prm))
+        if ws == 0:
+            raise ValueError("the batch engine does not take this problem")
         n = int(np.prod(req.M.shape))
         return int(ws) + 9 * n          # + M (4 B), mask (1 B), X (4 B) per entry
 
@@ -177,11 +179,15 @@ class CompletionServer:
         return f(lane) if f is not None else False
 
     def submit(self, req):
-        req.footprint = self.ex.footprint(req)
-        if req.footprint > self.budget:
+        try:
+            req.footprint = self.ex.footprint(req)
+            req.lane = self._lane(req)
+        except Exception:                 # a shape no kernel takes: refused
+            self.rejected.append(req)
+            return False
+        if req.footprint <= 0 or req.footprint > self.budget:
             self.rejected.append(req)     # could never fit: refused, not queued forever
             return False
-        req.lane = self._lane(req)
         self.requests[req.rid] = req
         heapq.heappush(self.waiting, (req.arrival, req.rid))
         return True

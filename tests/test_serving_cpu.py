@@ -175,3 +175,14 @@ def test_lanes_keep_long_requests_apart():
                               nu=r.params["nu"], mu_bar=r.params["mu_bar"], max_iter=r.params["max_iter"])
         assert np.array_equal(done[r.rid].result, X), r.rid
         assert done[r.rid].iters == r.params["max_iter"]
+
+
+def test_request_no_kernel_takes_is_rejected():
+    class Picky(FakeExecutor):
+        def lane(self, req):
+            raise RuntimeError("no Jacobi kernel takes this shape")
+
+    clock = FakeClock()
+    srv = serving.CompletionServer(Picky(clock), hbm_budget=10 ** 9, clock=clock)
+    assert not srv.submit(_req(0, 0.0, (6, 5, 2), 3, 31))
+    assert srv.stats()["rejected"] == 1 and srv.idle()
