@@ -33,27 +33,29 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
 
-# HBM bytes per k_jacobi launch on the default video workload (FP32, Cholesky-QR
-# preconditioned, 150 slices of 144 x 144 factors), from rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE passes scaled by a 256 MiB device copy in the same run (fetch x2.0,
-# write x1.0); the command lines and raw figures are in profiles/.  Reported only
-# for that configuration and this kernel version (null elsewhere).
-JACOBI_TRAFFIC_VIDEO_BYTES = 26619301
+# HBM bytes per k_jacobi_warm launch on the default video workload (FP32,
+# Cholesky-QR preconditioned, warm-started, 150 slices of 144 x 144 factors), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes scaled by a 256 MiB device copy
+# in the same run; the command lines and raw figures are in profiles/.  Reported
+# only for that configuration and this kernel version (null elsewhere, and null
+# until the counters are taken for it).
+JACOBI_WARM_TRAFFIC_VIDEO_BYTES = None
 
 
-def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True):
+def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):
     """Algorithmic flops of the one-sided Jacobi SVT kernel summed over `slices`
     slice-SVDs of n columns of `rows` rows (the slice's m, or n when the
     Cholesky-QR preconditioned path runs the Jacobi on R^T) that took `sweeps`
     sweeps and applied `rotations` rotations in total: per sweep and slice,
     n(n-1)/2 pair dot products (2 rows flops each; FP32 when the tolerance is
     1e-6 or looser, FP64 otherwise) and n column norms (2 rows FP64 flops); per
-    rotation 6 rows FP32 flops (two columns, 3 flops per entry); per slice the
-    final column norms (2 rows n FP64)."""
+    rotation 6 rot_rows FP32 flops (two columns, 3 flops per entry; rot_rows =
+    rows unless the columns carry more rows than the dot products read); per
+    slice the final column norms (2 rows n FP64)."""
     pairs = n * (n - 1) // 2
     dots = sweeps * pairs * 2 * rows
     f64 = sweeps * n * 2 * rows + slices * n * 2 * rows + (0 if dot32 else dots)
-    f32 = rotations * 6 * rows + (dots if dot32 else 0)
+    f32 = rotations * 6 * (rot_rows or rows) + (dots if dot32 else 0)
     return f64, f32
 
 
@@ -96,6 +98,9 @@ def main():
                     help="video workload: transform along the trailing modes (dft: the t-product form)")
     ap.add_argument("--no-precondition", action="store_true",
                     help="run the Jacobi SVD on the slices themselves (no Cholesky-QR factor)")
+    ap.add_argument("--warm-restart", type=int, default=0,
+                    help="video/large/big: cold Jacobi start every this many iterations "
+                         "(0: the library default, 64; -1: every iteration, no warm start)")
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
@@ -134,7 +139,8 @@ def main():
 
     def params(iters):
         return lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=iters,
-                             precision=args.precision, precondition=not args.no_precondition)
+                             precision=args.precision, precondition=not args.no_precondition,
+                             warm_restart=args.warm_restart)
 
     # warmup (untimed)
     if args.warmup > 0:
@@ -168,20 +174,27 @@ def main():
     precond = "precond" in path
     jm, jn = (2 * m, 2 * n) if "dft" in p.kinds else (m, n)   # Fourier: real embeddings of the slices
     rows = jn if precond else jm
-    f64, f32 = jacobi_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
+    # warm-started Jacobi: every rotation also updates the accumulated rotations
+    # (a second block of 4 ceil(n/4) rows below the factor's)
+    warm = lt.pga_warm(shape, p.kinds, precondition=not args.no_precondition, warm_restart=args.warm_restart)
+    rot_rows = rows + 4 * ((jn + 3) // 4) if warm else rows
+    f64, f32 = jacobi_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
+                            rot_rows=rot_rows)
     per_launch = (f64 + f32) / max(jcalls, 1)
     t_launch = jms / 1e3 / max(jcalls, 1)
     t_peak = (f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU) / max(jcalls, 1)
     achieved = per_launch / t_launch / 1e12 if t_launch > 0 else 0.0
     peak = per_launch / t_peak / 1e12 if t_peak > 0 else 0.0
-    measured_cfg = args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
-    roofline = {"bound": "alu", "kernel": "k_jacobi", "achieved": round(achieved, 3),
+    measured_cfg = (args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
+                    and warm)
+    roofline = {"bound": "alu", "kernel": "k_jacobi_warm" if warm else "k_jacobi", "achieved": round(achieved, 3),
                 "peak": round(peak, 2), "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None,
-                "traffic": JACOBI_TRAFFIC_VIDEO_BYTES if measured_cfg else None,
+                "traffic": JACOBI_WARM_TRAFFIC_VIDEO_BYTES if measured_cfg else None,
                 "flops_per_launch": per_launch, "fp64_share": round(f64 / (f64 + f32), 4),
                 "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
-                "jacobi_rows": rows, "preconditioned": precond, "svt_path": path}
+                "jacobi_rows": rows, "rotated_rows": rot_rows, "preconditioned": precond,
+                "warm_start": warm, "svt_path": path}
 
     line = {
         "metric": "PGA iterations/s (slice-SVT/s alongside) at rel-err <= 1e-4 vs FP64 oracle",

@@ -94,7 +94,13 @@ typedef struct {
                               blocked kernel (fewer sweeps, same result to the Jacobi
                               tolerance); nonzero runs it on the slice itself.  lt_lsvd
                               always uses the slice itself. */
-  int32_t reserved;     /* set to 0 */
+  int32_t warm_restart; /* lt_complete_pga on preconditioned slices of real transforms held by
+                           the register-resident kernel: the Jacobi of iteration k runs on
+                           L Z, Z the rotations accumulated since the last cold start
+                           (Z = I), which its columns leave nearly orthogonal (fewer
+                           sweeps, same result to the Jacobi tolerance).  0: a cold start
+                           every 64 iterations; k > 0: every k; < 0: every iteration (no
+                           warm start).  Ignored by the other entry points. */
 } lt_svd_opts;
 
 /* Largest min(I1, I2) the preconditioned SVT path takes (the per-slice FP64
@@ -207,6 +213,13 @@ int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, floa
  * or a negative status if no kernel takes the shape.  Host only: lets a
  * scheduler keep requests of the long-running blocked kernel apart. */
 int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts);
+
+/* 1 if lt_complete_pga with options opts warm-starts the Jacobi of descriptor
+ * a's slices (see lt_svd_opts.warm_restart: preconditioned slices of real
+ * transforms with n = min(I1, I2) small enough for the register-resident
+ * kernel to hold the factor's rows and those of the accumulated rotations), 0
+ * if not, a negative status for an invalid descriptor.  Host only. */
+int lt_pga_warm(const lt_desc* a, const lt_svd_opts* opts);
 
 /* D = D_tau(A) (Alg. 4): every slice of L(A) has its singular values
  * soft-thresholded by tau >= 0, then L^{-1}.  rank_out (device, P int32, may

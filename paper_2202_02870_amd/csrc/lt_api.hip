@@ -462,8 +462,29 @@ int dft_prepare(lt_handle* h, const Shape& s, const SvtWs& w) {
   return LT_OK;
 }
 
+// Warm start of the completion's SVT (real transforms, preconditioned slices
+// on the register-resident kernel): per slice the rotations Z (n x n)
+// accumulated since the last cold start.
+constexpr int kWarmRestartDefault = 64;
+
+bool warm_shape(const Shape& s) {
+  if (s.any_dft) return false;
+  SvtPlan pl;
+  if (!svt_plan(s, true, &pl) || !pl.precond || pl.blocked) return false;
+  const int n = (int)precond_n(s);
+  lt::JacobiConfig cfg;
+  return lt::jacobi_warm_config(n, kBlkLdsBudget, &cfg) == 0 &&
+         lt::warm_product_lds_bytes(n) <= (size_t)kBlkLdsBudget;
+}
+
+struct WarmState {
+  float* Z = nullptr;       // P x n x n
+  bool cold = true;
+};
+
 struct PgaWs {
   SvtWs svt;
+  float* Z = nullptr;       // warm start (warm_shape only)
   float* Xb = nullptr;
   double* partials = nullptr;
   double* norms = nullptr;
@@ -479,6 +500,7 @@ long long n_partials(const Shape& s) {
 
 void carve_pga(Carver& c, const Shape& s, int prec, PgaWs* w) {
   carve_svt(c, s, prec, &w->svt);
+  if (warm_shape(s)) w->Z = c.take<float>((size_t)(s.P * precond_n(s) * precond_n(s)));
   w->Xb = c.take<float>((size_t)s.nel);
   w->partials = c.take<double>(2 * (size_t)n_partials(s));
   w->norms = c.take<double>(2);
@@ -521,10 +543,29 @@ int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
   return LT_OK;
 }
 
+// D = the SVT of the slices from the Jacobi's kept columns: D_W = Bk (Bk^T W),
+// or (W B) B^T on the preconditioned path.
+int rebuild_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtCore& w, int32_t* rank,
+                bool precond) {
+  lt::RebuildArgs r{};
+  r.W = Gh;
+  r.D = Dh;
+  r.bk = w.Bk;
+  r.rank = rank;
+  r.slice_stride = s.N;
+  r.I1 = (int)s.I1;
+  r.I2 = (int)s.I2;
+  r.nslices = (int)s.P;
+  r.flip = precond ? 1 : 0;
+  ProfScope ps(h, LT_PROF_REBUILD);
+  HIP_TRY(h, lt::launch_rebuild(r, h->stream));
+  return LT_OK;
+}
+
 int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtCore& w,
                    double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
                    unsigned long long* sweep_total, unsigned long long* rot_total,
-                   unsigned int* hits, bool precond) {
+                   unsigned int* hits, bool precond, const WarmState* warm = nullptr) {
   SvtPlan pl;
   if (!svt_plan(s, precond && w.C, &pl))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
@@ -563,6 +604,42 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
     j.I1 = n;
     j.I2 = n;
     j.bk_stride = s.N;
+    if (warm && warm->Z && !blocked) {
+      // warm start: the Jacobi runs on M = L Z (written over the second half of
+      // each slice's block), carrying Z along
+      lt::JacobiConfig wc;
+      if (lt::jacobi_warm_config(n, h->max_lds, &wc) != 0)
+        return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: no warm-start Jacobi configuration", s.I1, s.I2);
+      lt::WarmArgs wa{};
+      wa.M = j.src;
+      wa.m_stride = 2 * cst;
+      if (!warm->cold) {
+        float* Mw = reinterpret_cast<float*>(w.C) + cst;
+        ProfScope ps(h, LT_PROF_PRECOND);
+        HIP_TRY(h, lt::launch_warm_product(reinterpret_cast<const float*>(w.C), 2 * cst, warm->Z, Mw, 2 * cst,
+                                           n, (int)s.P, h->stream));
+        wa.M = Mw;
+      }
+      wa.Z = warm->Z;
+      wa.bk = w.Bk;
+      wa.bk_stride = s.N;
+      wa.rank = rank;
+      wa.sweeps = sweeps;
+      wa.sweep_total = sweep_total;
+      wa.rot_total = rot_total;
+      wa.hits = hits;
+      wa.tau = tau;
+      wa.tol = tol;
+      wa.n = n;
+      wa.nslices = (int)s.P;
+      wa.max_sweeps = max_sweeps;
+      wa.cold = warm->cold ? 1 : 0;
+      {
+        ProfScope ps(h, LT_PROF_JACOBI);
+        HIP_TRY(h, lt::launch_jacobi_warm(wa, wc, h->stream));
+      }
+      return rebuild_svt(h, s, Gh, Dh, w, rank, true);
+    }
   } else {
     if (!blocked && (rc = jacobi_config(h, s, &cfg))) return rc;
     j.src = Gh;
@@ -586,21 +663,7 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
     if (blocked) HIP_TRY(h, lt::launch_jacobi_blk(j, bcfg, h->stream));
     else HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
   }
-  lt::RebuildArgs r{};
-  r.W = Gh;
-  r.D = Dh;
-  r.bk = w.Bk;
-  r.rank = rank;
-  r.slice_stride = s.N;
-  r.I1 = (int)s.I1;
-  r.I2 = (int)s.I2;
-  r.nslices = (int)s.P;
-  r.flip = precond ? 1 : 0;
-  {
-    ProfScope ps(h, LT_PROF_REBUILD);
-    HIP_TRY(h, lt::launch_rebuild(r, h->stream));
-  }
-  return LT_OK;
+  return rebuild_svt(h, s, Gh, Dh, w, rank, precond);
 }
 
 SvtCore core_of(const SvtWs& w) {
@@ -618,10 +681,10 @@ SvtCore core_of(const SvtWs& w) {
 // conjugate pair.  rank / sweeps: per slice (P entries).
 int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol, int max_sweeps,
             int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total, unsigned long long* rot_total,
-            unsigned int* hits, bool precond) {
+            unsigned int* hits, bool precond, const WarmState* warm = nullptr) {
   if (!s.any_dft)
     return run_jacobi_svt(h, s, w.Gh, w.Gh, core_of(w), tau, tol, max_sweeps, rank, sweeps, sweep_total,
-                          rot_total, hits, precond);
+                          rot_total, hits, precond, warm);
   const DftWs& d = w.dft;
   const Shape se = embed_shape(s, d.npairs);
   float* Re = w.Gh;
@@ -1068,6 +1131,14 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   return (p.precond ? LT_SVT_PRECOND : 0) | (p.blocked ? LT_SVT_BLOCKED : 0);
 }
 
+int lt_pga_warm(const lt_desc* a, const lt_svd_opts* opts) {
+  Shape s;
+  int rc = parse(nullptr, a, &s);
+  if (rc) return rc;
+  if (!precond_requested(opts) || (opts && opts->warm_restart < 0)) return 0;
+  return warm_shape(s) ? 1 : 0;
+}
+
 int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
                 int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts, void* ws,
                 size_t ws_bytes) {
@@ -1350,6 +1421,7 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   HIP_TRY(h, hipMemsetAsync(w.maxsweep_hits, 0, sizeof(unsigned int), st));
 
   const int check_every = p->check_every > 0 ? p->check_every : 1;
+  const int restart = p->svd.warm_restart == 0 ? kWarmRestartDefault : p->svd.warm_restart;
   double t_prev = 1.0, t = 1.0, mu = p->mu0;   // t_0 = t_1 = 1, mu_1 = mu0
   int iters = 0;
   bool converged = false;
@@ -1365,8 +1437,13 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     f.mask = mask;
     f.beta = (float)beta;
     if ((rc = gemm(h, f, prec, lt::PRO_PGA, lt::EPI_PLAIN, LT_PROF_FORWARD))) return rc;
+    WarmState warm;
+    if (w.Z && restart > 0) {
+      warm.Z = w.Z;
+      warm.cold = k % restart == 0;
+    }
     rc = run_svt(h, s, w.svt, mu_k, tol, max_sweeps, w.svt.rank, w.svt.sweeps, w.sweep_total, w.rot_total,
-                 w.maxsweep_hits, precond_requested(&p->svd));
+                 w.maxsweep_hits, precond_requested(&p->svd), warm.Z ? &warm : nullptr);
     if (rc) return rc;
     lt::GemmArgs b = gemm_plain(w.svt.t, true, (int)s.P, s.N, w.svt.Gh, Xprev, s.any_dft);
     b.X = Xcur;

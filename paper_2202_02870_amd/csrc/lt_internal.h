@@ -129,6 +129,37 @@ struct JacobiConfig {
 // Pick a kernel configuration for an m x n working matrix (0 on success).
 int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G);
 hipError_t launch_jacobi(const JacobiArgs& a, const JacobiConfig& cfg, hipStream_t s);
+
+// Warm-started Jacobi on the preconditioned factors (one slice per workgroup):
+// the Jacobi runs on M = L Z, L = R^T the slice's n x n Cholesky factor and Z
+// the orthogonal matrix of the rotations accumulated since the last cold start
+// (Z = I, M = L), and rewrites Z with this call's rotations appended.
+struct WarmArgs {
+  const float* M;          // slice s at M + s * m_stride (n x n, column-major): L Z, or L when cold
+  long long m_stride;
+  float* Z;                // slice s at Z + s * n * n (column-major): read unless cold, rewritten
+  float* bk;               // kept columns, scaled (as JacobiArgs::bk in SVT mode)
+  long long bk_stride;
+  int32_t* rank;
+  int32_t* sweeps;
+  unsigned long long* sweep_total;
+  unsigned long long* rot_total;
+  unsigned int* hits;
+  double tau;
+  double tol;
+  int n;
+  int nslices;
+  int max_sweeps;
+  int cold;
+};
+// Configuration for n x n factors (0 on success, -1 if the kernel cannot hold
+// them), launch, and the product M = L Z (LDS bytes it needs).
+int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg);
+hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& cfg, hipStream_t s);
+size_t warm_product_lds_bytes(int n);
+hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
+                               long long m_stride, int n, int nslices, hipStream_t s);
+
 // The register-resident kernel can hold an m x n working matrix (shape limits
 // only; the device's LDS is checked by jacobi_pick_config).
 bool jacobi_reg_shape(int m, int n);

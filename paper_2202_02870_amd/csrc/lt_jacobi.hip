@@ -98,20 +98,19 @@ __device__ inline float group_sumf(float v) {
 }
 
 // FP64 dot product of two FP32 register columns (FP32 x FP32 products are exact
-// in FP64), over the first qeff 4-row chunks.  The scheduling barriers keep the
-// compiler from converting a whole column to FP64 ahead of use.
+// in FP64) over all R rows of the lane: the chunks beyond the slice's qeff hold
+// zeros (see get_rows), so no per-chunk predicate is needed.  The scheduling
+// barriers keep the compiler from converting a whole column to FP64 ahead of use.
 template <int R>
-__device__ inline double dot64(const float (&x)[R], const float (&y)[R], int qeff) {
+__device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
   double d0 = 0.0, d1 = 0.0;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    if (q < qeff) {
-      const int r = 4 * q;
-      d0 = fma((double)x[r], (double)y[r], d0);
-      d1 = fma((double)x[r + 1], (double)y[r + 1], d1);
-      d0 = fma((double)x[r + 2], (double)y[r + 2], d0);
-      d1 = fma((double)x[r + 3], (double)y[r + 3], d1);
-    }
+    const int r = 4 * q;
+    d0 = fma((double)x[r], (double)y[r], d0);
+    d1 = fma((double)x[r + 1], (double)y[r + 1], d1);
+    d0 = fma((double)x[r + 2], (double)y[r + 2], d0);
+    d1 = fma((double)x[r + 3], (double)y[r + 3], d1);
     __builtin_amdgcn_sched_barrier(0);
   }
   return d0 + d1;
@@ -122,17 +121,15 @@ __device__ inline double dot64(const float (&x)[R], const float (&y)[R], int qef
 // (rows per lane + log2 G) * 2^-24 of sum |x_i y_i|, below a 1e-6 orthogonality
 // test.
 template <int R>
-__device__ inline float dot32x(const float (&x)[R], const float (&y)[R], int qeff) {
+__device__ inline float dot32x(const float (&x)[R], const float (&y)[R]) {
   float d0 = 0.f, d1 = 0.f;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    if (q < qeff) {
-      const int r = 4 * q;
-      d0 = fmaf(x[r], y[r], d0);
-      d1 = fmaf(x[r + 1], y[r + 1], d1);
-      d0 = fmaf(x[r + 2], y[r + 2], d0);
-      d1 = fmaf(x[r + 3], y[r + 3], d1);
-    }
+    const int r = 4 * q;
+    d0 = fmaf(x[r], y[r], d0);
+    d1 = fmaf(x[r + 1], y[r + 1], d1);
+    d0 = fmaf(x[r + 2], y[r + 2], d0);
+    d1 = fmaf(x[r + 3], y[r + 3], d1);
   }
   return d0 + d1;
 }
@@ -147,7 +144,10 @@ __device__ inline double rcp64(double x) {
 }
 
 // Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
-// 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows.  An
+// 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows; the
+// others are zero in every lane from the first load on (get_rows,
+// load_work_col), stay zero under rotations, and are neither stored nor
+// reloaded, so dots and rotations run over all R rows without predicates.  An
 // LDS column slot is ldw = G R + 4 floats: the rows, then 16 bytes of metadata
 // (an FP64 value and an int: the column's norm and id while sweeping, the
 // output scale and destination when writing out), moved with the column.
@@ -190,13 +190,11 @@ __device__ inline void get_rows(const float* buf, int ldw, int idx, int l, float
   const float4* p = reinterpret_cast<const float4*>(buf + (size_t)idx * ldw);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    if (q < qeff) {
-      const float4 t = p[l + G * q];
-      v[4 * q] = t.x;
-      v[4 * q + 1] = t.y;
-      v[4 * q + 2] = t.z;
-      v[4 * q + 3] = t.w;
-    }
+    const float4 t = (q < qeff) ? p[l + G * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
   }
 }
 
@@ -310,6 +308,11 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
 
   // ---- load: slot g holds columns g (top) and 2*npairs - 1 - g (bottom) ----
   float av[R], bv[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {   // idle lanes too: every lane's rotation is finite
+    av[e] = 0.f;
+    bv[e] = 0.f;
+  }
   int ida = g, idb = 2 * npairs - 1 - g;
   const int mpad = 4 * G * qeff;   // rows a lane group holds per column (>= m)
   if (active) stage_in(A, bufA, ldw, trans, I1, m, n, npairs, mpad, 0, t2, tps);
@@ -341,8 +344,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   const double big2 = big_rotation2(tol);
   // single-exit loop (max_sweeps >= 1): the columns stay in one register set
   for (;;) {
-    na = group_sum<G>(dot64<R>(av, av, qeff));
-    nb = group_sum<G>(dot64<R>(bv, bv, qeff));
+    na = group_sum<G>(dot64<R>(av, av));
+    nb = group_sum<G>(dot64<R>(bv, bv));
     unsigned my_rot = 0;   // this lane's rotations | large rotations << 16
     // a converged slice stays frozen in place (no rotations, no moves) while
     // the rest of its pack finishes, so its result and column order do not
@@ -355,12 +358,20 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
     int s0 = 0, i = g, r = 0;
     const int nrounds = 2 * npairs - 1;
     for (int k = 0; k < nrounds; ++k) {
-      // one rotation of the slot's pair (av, bv)
+      // one rotation of the slot's pair (av, bv).  The angle is found per lane;
+      // the rows are rotated under a wave-uniform branch in which lanes without a
+      // rotation take c = 1, s = 0 (the identity on finite values, up to the sign
+      // of a zero), so the column registers are updated in place rather than
+      // merged lane by lane after a divergent branch.
+      float cf = 1.f, sf = 0.f, t = 0.f;
+      double d = 0.0, pa = 0.0, pb = 0.0;
+      bool rot = false;
       if (moving) {
-        const double d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv, qeff))
-                               : group_sum<G>(dot64<R>(av, bv, qeff));
-        const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
-        if (d != 0.0 && d * d > tol * tol * (pa * pb)) {   // |d| > tol sqrt(pa pb)
+        d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv)) : group_sum<G>(dot64<R>(av, bv));
+        pa = fmax(na, 0.0);
+        pb = fmax(nb, 0.0);
+        rot = d != 0.0 && d * d > tol * tol * (pa * pb);   // |d| > tol sqrt(pa pb)
+        if (rot) {
           // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
           // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
           // c = 1 / sqrt(1 + t^2), s = c t.  zeta is formed in FP64 (a
@@ -372,22 +383,24 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
           const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
           const float z2 = fmaf(zf, zf, 1.f);
           const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
-          const float t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
-          const float cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-          const float sf = cf * t;
-#pragma unroll
-          for (int e = 0; e < R; ++e) {
-            if (e < 4 * qeff) {
-              const float x = av[e], y = bv[e];
-              const float sy = sf * y, sx = sf * x;
-              av[e] = fmaf(cf, x, -sy);
-              bv[e] = fmaf(cf, y, sx);
-            }
-          }
-          na = fma(-(double)t, d, pa);
-          nb = fma((double)t, d, pb);
-          my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
+          t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
+          cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          sf = cf * t;
         }
+      }
+      {
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const float x = av[e], y = bv[e];
+          const float sy = sf * y, sx = sf * x;
+          av[e] = fmaf(cf, x, -sy);
+          bv[e] = fmaf(cf, y, sx);
+        }
+      }
+      if (rot) {
+        na = fma(-(double)t, d, pa);
+        nb = fma((double)t, d, pb);
+        my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
       }
       if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
       if (ring && r + 1 < c) {
@@ -466,8 +479,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   }
 
   // ---- output -------------------------------------------------------------
-  na = group_sum<G>(dot64<R>(av, av, qeff));
-  nb = group_sum<G>(dot64<R>(bv, bv, qeff));
+  na = group_sum<G>(dot64<R>(av, av));
+  nb = group_sum<G>(dot64<R>(bv, bv));
   const double sa = sqrt(na), sb = sqrt(nb);
   bool ka, kb;
   if (jb.mode == 0) {
@@ -547,12 +560,20 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
   int s0 = 0, i = g, r = 0;
   const int nrounds = ring_only ? npairs : 2 * npairs - 1;
   for (int k = 0; k < nrounds; ++k) {
-    // one rotation of the slot's pair (av, bv)
+    // one rotation of the slot's pair (av, bv).  The angle is found per lane;
+    // the rows are rotated under a wave-uniform branch in which lanes without a
+    // rotation take c = 1, s = 0 (the identity on finite values, up to the sign
+    // of a zero), so the column registers are updated in place rather than
+    // merged lane by lane after a divergent branch.
+    float cf = 1.f, sf = 0.f, t = 0.f;
+    double d = 0.0, pa = 0.0, pb = 0.0;
+    bool rot = false;
     if (moving) {
-      const double d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv, qeff))
-                             : group_sum<G>(dot64<R>(av, bv, qeff));
-      const double pa = fmax(na, 0.0), pb = fmax(nb, 0.0);
-      if (d != 0.0 && d * d > tol * tol * (pa * pb)) {   // |d| > tol sqrt(pa pb)
+      d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv)) : group_sum<G>(dot64<R>(av, bv));
+      pa = fmax(na, 0.0);
+      pb = fmax(nb, 0.0);
+      rot = d != 0.0 && d * d > tol * tol * (pa * pb);   // |d| > tol sqrt(pa pb)
+      if (rot) {
         // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
         // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
         // c = 1 / sqrt(1 + t^2), s = c t.  zeta is formed in FP64 (a
@@ -564,22 +585,24 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
         const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
         const float z2 = fmaf(zf, zf, 1.f);
         const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
-        const float t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
-        const float cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-        const float sf = cf * t;
-#pragma unroll
-        for (int e = 0; e < R; ++e) {
-          if (e < 4 * qeff) {
-            const float x = av[e], y = bv[e];
-            const float sy = sf * y, sx = sf * x;
-            av[e] = fmaf(cf, x, -sy);
-            bv[e] = fmaf(cf, y, sx);
-          }
-        }
-        na = fma(-(double)t, d, pa);
-        nb = fma((double)t, d, pb);
-        my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
+        t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
+        cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+        sf = cf * t;
       }
+    }
+    {
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const float x = av[e], y = bv[e];
+        const float sy = sf * y, sx = sf * x;
+        av[e] = fmaf(cf, x, -sy);
+        bv[e] = fmaf(cf, y, sx);
+      }
+    }
+    if (rot) {
+      na = fma(-(double)t, d, pa);
+      nb = fma((double)t, d, pb);
+      my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
     }
     if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
     if (ring && r + 1 < c) {
@@ -693,13 +716,11 @@ __device__ inline void load_work_col(const float* Wk, int mpad, int col, int l, 
   const float4* p = reinterpret_cast<const float4*>(Wk + (size_t)col * mpad);
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    if (q < qeff) {
-      const float4 x = p[l + G * q];
-      v[4 * q] = x.x;
-      v[4 * q + 1] = x.y;
-      v[4 * q + 2] = x.z;
-      v[4 * q + 3] = x.w;
-    }
+    const float4 x = (q < qeff) ? p[l + G * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    v[4 * q] = x.x;
+    v[4 * q + 1] = x.y;
+    v[4 * q + 2] = x.z;
+    v[4 * q + 3] = x.w;
   }
 }
 
@@ -784,8 +805,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
           load_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
           load_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
         }
-        double na = group_sum<G>(dot64<R>(av, av, qeff));
-        double nb = group_sum<G>(dot64<R>(bv, bv, qeff));
+        double na = group_sum<G>(dot64<R>(av, av));
+        double nb = group_sum<G>(dot64<R>(bv, bv));
         my_rot += sweep_rounds<G, R>(av, bv, na, nb, ida, idb, active, dot32, tol, b, g, l, qeff, buf,
                                      bufB, nbuf, ldw, br > 0);
         if (active) {
@@ -819,7 +840,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
   for (int c0 = 0; c0 < ncols; c0 += b) {
     const int id = c0 + g;
     if (active) load_work_col<G, R>(Wk, mpad, id, l, av, qeff);
-    const double sa = sqrt(group_sum<G>(dot64<R>(av, av, qeff)));
+    const double sa = sqrt(group_sum<G>(dot64<R>(av, av)));
     const bool ka = active && id < n && sa > jb.tau;
     if (active && l == 0) ctl[3 + g] = ka ? 1 : 0;
     __syncthreads();
@@ -975,6 +996,322 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
   jb.rot_total = &pd->rot_total;
   jb.hits = &pd->maxsweep_hits;
   jacobi_body<G, R>(jb, tol, max_sweeps, nbuf, ldw, smem);
+}
+
+// ---- warm-started Jacobi on the preconditioned factor ----------------------------
+// Completion thresholds slices that change little from one iteration to the
+// next.  The one-sided Jacobi of a preconditioned slice can then run on
+// M = L Z instead of L (= R^T, the slice's n x n Cholesky factor), Z orthogonal:
+// M has the singular values and left singular vectors of L, all the SVT uses,
+// and when Z holds the rotations of the previous iterations M's columns start
+// close to orthogonal, so far fewer sweeps are needed.  Each working column
+// carries its column of Z below it: rows 0 .. npad-1 hold M (zero beyond n),
+// rows npad .. npad+n-1 hold Z, npad = 4 ceil(n / 4).  Every rotation applies
+// to the whole column, so Z accumulates them, while the dot products and norms
+// take the M rows only.  A cold call starts from Z = I (M = L).  One slice per
+// workgroup; pair schedule, angle and stopping rule are those of jacobi_body.
+
+// M = L Z per slice (L lower triangular, both n x n column-major): L staged in
+// the LDS with leading dimension npad, Z in blocks of 16 columns; a thread
+// forms 4 rows of one column.
+constexpr int kWarmCols = 16;
+__host__ __device__ inline size_t warm_product_lds(int n) {
+  const size_t npad = (size_t)((n + 3) / 4) * 4;
+  return (npad * n + (size_t)kWarmCols * n) * sizeof(float);
+}
+
+__global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long l_stride, const float* Z,
+                                                       float* M, long long m_stride, int n) {
+  extern __shared__ __attribute__((aligned(16))) float wp_lds[];
+  const int npad = (n + 3) / 4 * 4;
+  float* Ls = wp_lds;                      // L(row, k) at Ls[k * npad + row]
+  float* Zb = wp_lds + (size_t)npad * n;   // Z(k, c0 + cc) at Zb[cc * n + k]
+  const float* Lg = L + (long long)blockIdx.x * l_stride;
+  const float* Zg = Z + (long long)blockIdx.x * n * n;
+  float* Mg = M + (long long)blockIdx.x * m_stride;
+  for (int e = threadIdx.x; e < npad * n; e += blockDim.x) {
+    const int k = e / npad, row = e - k * npad;
+    Ls[e] = row < n ? Lg[(long long)k * n + row] : 0.f;
+  }
+  const int nr4 = npad / 4;
+  for (int c0 = 0; c0 < n; c0 += kWarmCols) {
+    const int nc = n - c0 < kWarmCols ? n - c0 : kWarmCols;
+    __syncthreads();   // L staged / the previous block of Z no longer read
+    for (int e = threadIdx.x; e < nc * n; e += blockDim.x) Zb[e] = Zg[(long long)c0 * n + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * nr4; e += blockDim.x) {
+      const int cc = e / nr4, r0 = 4 * (e - cc * nr4);
+      const int kend = r0 + 4 < n ? r0 + 4 : n;   // L(row, k) = 0 for k > row
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int k = 0; k < kend; ++k) {
+        const float4 lv = *reinterpret_cast<const float4*>(Ls + (size_t)k * npad + r0);
+        const float z = Zb[cc * n + k];
+        acc.x = fmaf(lv.x, z, acc.x);
+        acc.y = fmaf(lv.y, z, acc.y);
+        acc.z = fmaf(lv.z, z, acc.z);
+        acc.w = fmaf(lv.w, z, acc.w);
+      }
+      float* mc = Mg + (long long)(c0 + cc) * n;
+      if (r0 < n) mc[r0] = acc.x;
+      if (r0 + 1 < n) mc[r0 + 1] = acc.y;
+      if (r0 + 2 < n) mc[r0 + 2] = acc.z;
+      if (r0 + 3 < n) mc[r0 + 3] = acc.w;
+    }
+  }
+}
+
+// Dot products over the M rows: chunk q of this lane is an M chunk when bit q
+// of mq is set (rows beyond npad are Z rows).
+template <int R>
+__device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsigned mq) {
+  float d0 = 0.f, d1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    const int r = 4 * q;
+    float p = x[r] * y[r];
+    p = fmaf(x[r + 1], y[r + 1], p);
+    p = fmaf(x[r + 2], y[r + 2], p);
+    p = fmaf(x[r + 3], y[r + 3], p);
+    p = ((mq >> q) & 1u) ? p : 0.f;
+    if (q & 1) d1 += p;
+    else d0 += p;
+  }
+  return d0 + d1;
+}
+
+template <int R>
+__device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsigned mq) {
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    const int r = 4 * q;
+    double p = (double)x[r] * (double)y[r];
+    p = fma((double)x[r + 1], (double)y[r + 1], p);
+    p = fma((double)x[r + 2], (double)y[r + 2], p);
+    p = fma((double)x[r + 3], (double)y[r + 3], p);
+    p = ((mq >> q) & 1u) ? p : 0.0;
+    if (q & 1) d1 += p;
+    else d0 += p;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return d0 + d1;
+}
+
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int Q = R / 4;
+  const int n = a.n;
+  const int npad = (n + 3) / 4 * 4;
+  const int npairs = (n + 1) >> 1;
+  const int npos = exch_positions(npairs);
+  const int tps = npairs * G;
+  const int tid = threadIdx.x;
+  const bool active = tid < tps;
+  const int t2 = active ? tid : 0;   // idle lanes alias lane 0 and never write
+  const int g = t2 / G, l = t2 - (t2 / G) * G;
+  int* wg_ctl = reinterpret_cast<int*>(smem);
+  float* bufA = reinterpret_cast<float*>(smem + kWgCtlBytes);
+  float* bufB = (nbuf == 2) ? bufA + (size_t)npos * ldw : bufA;
+  int* ctl = reinterpret_cast<int*>(bufA + (size_t)nbuf * npos * ldw);
+  const float* __restrict__ Ms = a.M + (long long)blockIdx.x * a.m_stride;
+  float* Zs = a.Z + (long long)blockIdx.x * n * n;
+
+  unsigned mq = 0;   // this lane's M chunks
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (4 * (l + G * q) < npad) mq |= 1u << q;
+
+  // ---- load: slot g holds columns g (top) and 2 npairs - 1 - g (bottom) ----
+  float av[R], bv[R];
+  int ida = g, idb = 2 * npairs - 1 - g;   // idb == n: the zero column of odd n
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 4 * (l + G * q) + e;
+      float x = 0.f, y = 0.f;
+      if (active) {
+        if (row < npad) {
+          if (row < n) {
+            x = Ms[(long long)ida * n + row];
+            y = idb < n ? Ms[(long long)idb * n + row] : 0.f;
+          }
+        } else if (row - npad < n) {
+          const int zr = row - npad;
+          if (a.cold) {
+            x = zr == ida ? 1.f : 0.f;
+            y = zr == idb ? 1.f : 0.f;
+          } else {
+            x = Zs[(long long)ida * n + zr];
+            y = idb < n ? Zs[(long long)idb * n + zr] : 0.f;
+          }
+        }
+      }
+      av[4 * q + e] = x;
+      bv[4 * q + e] = y;
+    }
+  if (tid == 0) {
+    wg_ctl[0] = 0;
+    wg_ctl[1] = 0;
+  }
+  __syncthreads();
+
+  const double tol = a.tol;
+  const bool dot32 = tol >= 1e-6;
+  const double big2 = big_rotation2(tol);
+  double na = 0.0, nb = 0.0;
+  int sweep = 0, my_sweeps = 0;
+  bool converged = false;
+  long long rotations = 0;
+  for (;;) {
+    na = group_sum<G>(dot64_m<R>(av, av, mq));
+    nb = group_sum<G>(dot64_m<R>(bv, bv, mq));
+    unsigned my_rot = 0;
+    int c = npairs;
+    bool ring = (c & 1) == 0;
+    int s0 = 0, i = g, r = 0;
+    const int nrounds = 2 * npairs - 1;
+    for (int k = 0; k < nrounds; ++k) {
+      // the rotation of the slot's pair, on the whole column (identity, c = 1
+      // and s = 0, on lanes without one)
+      float cf = 1.f, sf = 0.f, t = 0.f;
+      double d = 0.0, pa = 0.0, pb = 0.0;
+      bool rot = false;
+      if (active) {
+        d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, mq)) : group_sum<G>(dot64_m<R>(av, bv, mq));
+        pa = fmax(na, 0.0);
+        pb = fmax(nb, 0.0);
+        rot = d != 0.0 && d * d > tol * tol * (pa * pb);
+        if (rot) {
+          const double zeta = (pb - pa) * (0.5 * rcp64(d));
+          const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
+          const float z2 = fmaf(zf, zf, 1.f);
+          const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
+          t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
+          cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          sf = cf * t;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const float x = av[e], y = bv[e];
+        const float sy = sf * y, sx = sf * x;
+        av[e] = fmaf(cf, x, -sy);
+        bv[e] = fmaf(cf, y, sx);
+      }
+      if (rot) {
+        na = fma(-(double)t, d, pa);
+        nb = fma((double)t, d, pb);
+        my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
+      }
+      if (k + 1 == nrounds) break;
+      if (ring && r + 1 < c) {
+        const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+        float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
+        if (active) put_col<G, R>(buf, ldw, g, l, bv, Q, nb, idb);
+        __syncthreads();
+        if (active) get_col<G, R>(buf, ldw, nxt, l, bv, Q, nb, idb);
+        if (nbuf == 1) __syncthreads();
+        ++r;
+      } else if (ring) {
+        const int h = c >> 1;
+        const bool first = i < h;
+        if (active) {
+          if (first) put_col<G, R>(bufB, ldw, g, l, bv, Q, nb, idb);
+          else put_col<G, R>(bufB, ldw, g, l, av, Q, na, ida);
+        }
+        __syncthreads();
+        if (active) {
+          if (first) get_col<G, R>(bufB, ldw, g + h, l, bv, Q, nb, idb);
+          else get_col<G, R>(bufB, ldw, g - h, l, av, Q, na, ida);
+        }
+        if (nbuf == 1) __syncthreads();
+        c = h;
+        ring = (c & 1) == 0;
+        s0 = (g / c) * c;
+        i = g - s0;
+        r = 0;
+      } else {
+        const int pos0 = s0 + s0 / c;
+        if (active) {
+          put_col<G, R>(bufA, ldw, pos0 + i, l, av, Q, na, ida);
+          if (i == 0) put_col<G, R>(bufA, ldw, pos0 + c, l, bv, Q, nb, idb);
+        }
+        __syncthreads();
+        if (active && i != 0) {
+          get_col<G, R>(bufA, ldw, pos0 + (i == 1 ? c : i - 1), l, av, Q, na, ida);
+          put_col<G, R>(bufA, ldw, pos0 + i - 1, l, bv, Q, nb, idb);
+        }
+        __syncthreads();
+        if (active) get_col<G, R>(bufA, ldw, pos0 + i, l, bv, Q, nb, idb);
+        ++r;
+      }
+    }
+    // one slice per workgroup: the workgroup's counters are the slice's
+    if (my_rot) atomicAdd(reinterpret_cast<unsigned*>(&wg_ctl[sweep & 1]), my_rot);
+    __syncthreads();
+    const unsigned any = static_cast<unsigned>(wg_ctl[sweep & 1]);
+    if (tid == 0) wg_ctl[(sweep + 1) & 1] = 0;
+    __syncthreads();
+    ++sweep;
+    rotations += any & 0xFFFFu;
+    my_sweeps = sweep;
+    converged = (any >> 16) == 0;
+    if (converged || sweep >= a.max_sweeps) break;
+  }
+
+  // ---- output: the accumulated Z, then the kept columns as jacobi_body ------
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int zr = 4 * (l + G * q) + e - npad;
+        if (zr >= 0 && zr < n) {
+          if (ida < n) Zs[(long long)ida * n + zr] = av[4 * q + e];
+          if (idb < n) Zs[(long long)idb * n + zr] = bv[4 * q + e];
+        }
+      }
+  }
+  na = group_sum<G>(dot64_m<R>(av, av, mq));
+  nb = group_sum<G>(dot64_m<R>(bv, bv, mq));
+  const double sa = sqrt(na), sb = sqrt(nb);
+  const bool ka = active && ida < n && sa > a.tau;
+  const bool kb = active && idb < n && sb > a.tau;
+  if (active && l == 0) ctl[3 + g] = (int)ka + (int)kb;
+  __syncthreads();
+  if (active && t2 == 0) {
+    int acc = 0;
+    for (int p = 0; p < npairs; ++p) {
+      const int cnt = ctl[3 + p];
+      ctl[3 + p] = acc;
+      acc += cnt;
+    }
+    ctl[2] = acc;
+  }
+  __syncthreads();
+  float* out = a.bk + (long long)blockIdx.x * a.bk_stride;
+  const int j0 = active ? ctl[3 + g] : 0;
+  const double sca = ka ? sqrt(1.0 - a.tau / sa) / sa : 0.0;
+  const double scb = kb ? sqrt(1.0 - a.tau / sb) / sb : 0.0;
+  const int da = ka ? j0 : -1;
+  const int db = kb ? j0 + (int)ka : -1;
+  // the LDS columns' first n rows are the M rows
+  if (active) put_col<G, R>(bufA, ldw, g, l, av, Q, sca, da);
+  __syncthreads();
+  if (active) stage_out(out, bufA, ldw, n, npairs, t2, tps);
+  __syncthreads();
+  if (active) put_col<G, R>(bufA, ldw, g, l, bv, Q, scb, db);
+  __syncthreads();
+  if (active) stage_out(out, bufA, ldw, n, npairs, t2, tps);
+  if (active && t2 == 0) {
+    if (a.rank) a.rank[blockIdx.x] = ctl[2];
+    if (a.sweeps) a.sweeps[blockIdx.x] = my_sweeps;
+    if (a.sweep_total) atomicAdd(a.sweep_total, (unsigned long long)my_sweeps);
+    if (a.rot_total) atomicAdd(a.rot_total, (unsigned long long)rotations);
+    if (!converged && a.hits) atomicAdd(a.hits, 1u);
+  }
 }
 
 // ---- rebuild D_W = Bk (Bk^T W) ------------------------------------------------
@@ -1355,6 +1692,88 @@ hipError_t launch_jacobi(const JacobiArgs& a0, const JacobiConfig& c, hipStream_
     case 64: return launch_g<64>(a, c, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int G, int R, int LB>
+static hipError_t launch_warm_one(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
+  const int ldw = G * R + 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_warm<G, R, LB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_jacobi_warm<G, R, LB>), dim3(a.nslices), dim3(c.threads), c.lds, s, a, c.nbuf, ldw);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_warm_g(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
+#define LT_WARM_CASE(RR)                                                                      \
+  case RR:                                                                                    \
+    return c.threads <= 768 ? launch_warm_one<G, RR, 768>(a, c, s) : launch_warm_one<G, RR, 1024>(a, c, s);
+  switch (c.R) {
+    LT_WARM_CASE(4)
+    LT_WARM_CASE(8)
+    LT_WARM_CASE(12)
+    LT_WARM_CASE(16)
+    LT_WARM_CASE(20)
+    LT_WARM_CASE(24)
+    LT_WARM_CASE(28)
+    LT_WARM_CASE(32)
+    LT_WARM_CASE(36)
+    default: return hipErrorInvalidValue;
+  }
+#undef LT_WARM_CASE
+}
+
+// The warm kernel's columns hold 2 npad rows (M, then Z), at most 36 per lane.
+int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg) {
+  if (n < 2 || n > RB_RMAX) return -1;
+  const int npairs = (n + 1) / 2;
+  const int rows = 2 * ((n + 3) / 4) * 4;
+  const int Gs[3] = {16, 8, 4};
+  int pick = 0, fallback = 0;
+  for (int i = 0; i < 3; ++i) {
+    const int G = Gs[i];
+    const int threads = ((npairs * G + 63) / 64) * 64;
+    int R = (rows + G - 1) / G;
+    R = ((R + 3) / 4) * 4;
+    if (threads > 1024 || R > 36) continue;
+    if (jacobi_lds_bytes(npairs, G * R + 4, 1) > (size_t)max_lds) continue;
+    if (R >= 8 && !pick) pick = G;
+    fallback = G;
+  }
+  const int G = pick ? pick : fallback;
+  if (!G) return -1;
+  int R = (rows + G - 1) / G;
+  R = ((R + 3) / 4) * 4;
+  cfg->G = G;
+  cfg->R = R;
+  cfg->threads = ((npairs * G + 63) / 64) * 64;
+  cfg->nbuf = jacobi_lds_bytes(npairs, G * R + 4, 2) <= (size_t)max_lds ? 2 : 1;
+  cfg->lds = jacobi_lds_bytes(npairs, G * R + 4, cfg->nbuf);
+  return 0;
+}
+
+size_t warm_product_lds_bytes(int n) { return warm_product_lds(n); }
+
+hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  switch (c.G) {
+    case 4: return launch_warm_g<4>(a, c, s);
+    case 8: return launch_warm_g<8>(a, c, s);
+    case 16: return launch_warm_g<16>(a, c, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
+                               long long m_stride, int n, int nslices, hipStream_t s) {
+  if (nslices <= 0) return hipSuccess;
+  const size_t lds = warm_product_lds(n);
+  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_warm_product, dim3(nslices), dim3(1024), lds, s, L, l_stride, Z, M, m_stride, n);
+  return hipGetLastError();
 }
 
 int jacobi_batch_config(const int* m, const int* n, int count, int max_lds, int force_G,

@@ -38,7 +38,7 @@ class Desc(ctypes.Structure):
 class SvdOpts(ctypes.Structure):
     _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("no_precondition", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("warm_restart", ctypes.c_int32)]
 
 
 class PgaParams(ctypes.Structure):
@@ -84,6 +84,7 @@ _sig = {
     "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_svt_path": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
+    "lt_pga_warm": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
     "lt_ltruncate": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_int32, _vp,
                                     ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_svt_prox": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
@@ -218,8 +219,10 @@ def _workspace(nbytes, ws):
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
 
-def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True):
-    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, 0)
+def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True, warm_restart=0):
+    """warm_restart (completion only): 0 a cold Jacobi start every 64 iterations,
+    k > 0 every k, < 0 every iteration (no warm start)."""
+    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, int(warm_restart))
 
 
 def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None):
@@ -260,6 +263,16 @@ def svt_path(shape, kinds=None, precondition=True):
     if st < 0:
         raise LtError(st, "no Jacobi kernel takes slices of %s" % (tuple(shape),))
     return SVT_PATHS[st]
+
+
+def pga_warm(shape, kinds=None, precondition=True, warm_restart=0):
+    """True if complete_pga warm-starts the Jacobi of these slices (host only)."""
+    d = make_desc(tuple(shape), kinds)
+    o = svd_opts(precondition=precondition, warm_restart=warm_restart)
+    st = _lib.lt_pga_warm(ctypes.byref(d), ctypes.byref(o))
+    if st < 0:
+        raise LtError(st, "invalid shape %s" % (tuple(shape),))
+    return st == 1
 
 
 def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None,
@@ -327,12 +340,12 @@ def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, pr
 
 def pga_params(mu0, nu=0.9, mu_bar=None, tol=0.0, max_iter=100, check_every=10,
                gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32",
-               precondition=True):
+               precondition=True, warm_restart=0):
     if mu_bar is None:
         mu_bar = 1e-4 * mu0
     return PgaParams(float(mu0), float(nu), float(mu_bar), float(tol), int(max_iter), int(check_every),
                      1 if gate_until_floor else 0, 1 if fixed_mu else 0,
-                     svd_opts(jacobi_tol, max_sweeps, precision, precondition))
+                     svd_opts(jacobi_tol, max_sweeps, precision, precondition, warm_restart))
 
 
 def complete_pga(M, mask, params, kinds=None, out=None, ws=None):

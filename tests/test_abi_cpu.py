@@ -108,3 +108,24 @@ def test_svt_path_by_shape():
     for bad, pc in (((2048, 2048), True), ((513, 513), True), ((3000, 16), False), ((2049, 300), False)):
         with pytest.raises(lt.LtError):
             lt.svt_path(bad, precondition=pc)
+
+
+def test_pga_warm_by_shape():
+    """Completion warm-starts the Jacobi of preconditioned slices of real
+    transforms that the register-resident kernel holds with the accumulated
+    rotations; the workspace carries those rotations (n x n per slice)."""
+    from paper_2202_02870_amd import lt
+    assert lt.pga_warm((144, 176, 3, 50))
+    assert lt.pga_warm((100, 80, 4))
+    assert not lt.pga_warm((144, 176, 3, 50), warm_restart=-1)
+    assert not lt.pga_warm((144, 176, 3, 50), precondition=False)
+    assert not lt.pga_warm((256, 256, 3, 100))           # no factor: the register kernel takes the slice
+    assert not lt.pga_warm((512, 512, 3, 64))            # blocked kernel
+    assert not lt.pga_warm((144, 176, 3, 50), ("dft", "dft"))
+    assert not lt.pga_warm((1, 7))                       # n = 1: nothing to factor
+    shape, n, P = (144, 176, 3, 50), 144, 150
+    cold_shape = (256, 256, 3, 100)
+    assert (lt.workspace_bytes(shape, None, "pga") - lt.workspace_bytes(shape, None, "svt")
+            >= 144 * 176 * P * 4 + P * n * n * 4)
+    assert (lt.workspace_bytes(cold_shape, None, "pga") - lt.workspace_bytes(cold_shape, None, "svt")
+            < 256 * 256 * 300 * 4 + 300 * 256 * 256 * 4)

@@ -366,6 +366,43 @@ def test_pga_video_full_size_first_iterations(lt):
     assert err < 1e-4
 
 
+def test_pga_warm_start_periods(lt):
+    """The warm-started Jacobi (rotations accumulated over iterations, cold start
+    every warm_restart iterations): cold every iteration, the default period,
+    every 5 and never after the first all match the oracle over 200 iterations
+    of the reduced video workload (no drift of the accumulated rotations), and
+    the warm runs need fewer sweeps."""
+    import torch
+    p = wl.config1(trailing=(3, 4))
+    assert lt.pga_warm(p.shape, p.kinds)
+    Xo, _ = _oracle_pga(p, 200)
+    s = p.schedule
+    sweeps = {}
+    for wr in (-1, 0, 5, 1000):
+        params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=200, warm_restart=wr)
+        X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
+        err = rel(lt.to_host(X), Xo)
+        sweeps[wr] = rep["total_sweeps"] / rep["total_slices"]
+        say("  warm_restart", wr, "err", err, "mean sweeps", sweeps[wr])
+        assert err < 1e-4
+    assert sweeps[0] < 0.7 * sweeps[-1] and sweeps[1000] < 0.7 * sweeps[-1]
+
+
+@pytest.mark.parametrize("shape", [(101, 120, 6), (120, 101, 5), (9, 7, 5), (64, 64, 3)])
+def test_pga_warm_start_shapes(lt, shape):
+    """Warm start on factors with odd n (a zero padding column), n not a multiple
+    of 4 (padding rows between the factor's rows and the rotations'), a small
+    slice, and n = 64: 80 iterations against the oracle."""
+    p = wl.make_problem(shape, 3, 0.5, seed=sum(shape))
+    p.schedule = dict(wl.pga_schedule_params(p.M, p.mask))
+    assert lt.pga_warm(p.shape, p.kinds)
+    X, rep, st = _run_pga(lt, p, 80)
+    Xo, _ = _oracle_pga(p, 80)
+    err = rel(X, Xo)
+    say("pga warm", shape, "err", err, "mean sweeps", rep["total_sweeps"] / rep["total_slices"])
+    assert err < 1e-4
+
+
 def test_pga_stopping_rule(lt):
     p = wl.make_problem((24, 20, 3, 2), 2, 0.6, seed=7)
     p.schedule = dict(wl.pga_schedule_params(p.M, p.mask))
