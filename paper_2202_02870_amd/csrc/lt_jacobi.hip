@@ -1060,6 +1060,43 @@ __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long
   }
 }
 
+// (x, y) <- (c x - s y, c y + s x) on every row, with the same roundings as the
+// rotations of jacobi_body (s y and s x rounded, then one fma each).  Written
+// as VALU-only inline assembly whose outputs are tied to its inputs, so that a
+// wave-uniform branch around it updates the column registers in place (the
+// compiler would otherwise rotate into fresh registers and copy back at the
+// join).  The leading s_nop covers the wait a transcendental result (c comes
+// from v_rsq) needs before a VALU reads it.
+template <int R>
+__device__ inline void rotate_in_place(float (&av)[R], float (&bv)[R], float cf, float sf) {
+  asm volatile("s_nop 1" ::);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    float t0, t1;
+    asm volatile(
+        "v_mul_f32 %8, %10, %4\n\t"
+        "v_mul_f32 %9, %10, %0\n\t"
+        "v_fma_f32 %0, %11, %0, -%8\n\t"
+        "v_fma_f32 %4, %11, %4, %9\n\t"
+        "v_mul_f32 %8, %10, %5\n\t"
+        "v_mul_f32 %9, %10, %1\n\t"
+        "v_fma_f32 %1, %11, %1, -%8\n\t"
+        "v_fma_f32 %5, %11, %5, %9\n\t"
+        "v_mul_f32 %8, %10, %6\n\t"
+        "v_mul_f32 %9, %10, %2\n\t"
+        "v_fma_f32 %2, %11, %2, -%8\n\t"
+        "v_fma_f32 %6, %11, %6, %9\n\t"
+        "v_mul_f32 %8, %10, %7\n\t"
+        "v_mul_f32 %9, %10, %3\n\t"
+        "v_fma_f32 %3, %11, %3, -%8\n\t"
+        "v_fma_f32 %7, %11, %7, %9"
+        : "+v"(av[4 * q]), "+v"(av[4 * q + 1]), "+v"(av[4 * q + 2]), "+v"(av[4 * q + 3]),
+          "+v"(bv[4 * q]), "+v"(bv[4 * q + 1]), "+v"(bv[4 * q + 2]), "+v"(bv[4 * q + 3]),
+          "=&v"(t0), "=&v"(t1)
+        : "v"(sf), "v"(cf));
+  }
+}
+
 // Dot products over the M rows: chunk q of this lane is an M chunk when bit q
 // of mq is set (rows beyond npad are Z rows).
 template <int R>
@@ -1193,13 +1230,9 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
           sf = cf * t;
         }
       }
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const float x = av[e], y = bv[e];
-        const float sy = sf * y, sx = sf * x;
-        av[e] = fmaf(cf, x, -sy);
-        bv[e] = fmaf(cf, y, sx);
-      }
+      // waves without a rotation skip the update (most of them in the late
+      // sweeps of a warm start)
+      if (__builtin_amdgcn_ballot_w64(rot) != 0) rotate_in_place<R>(av, bv, cf, sf);
       if (rot) {
         na = fma(-(double)t, d, pa);
         nb = fma((double)t, d, pb);
