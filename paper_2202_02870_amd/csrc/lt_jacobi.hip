@@ -143,6 +143,43 @@ __device__ inline double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// (x, y) <- (c x - s y, c y + s x) on every row: s y and s x rounded, then one
+// fma each (the rounding every Jacobi kernel here applies).  Written
+// as VALU-only inline assembly whose outputs are tied to its inputs, so that a
+// wave-uniform branch around it updates the column registers in place (the
+// compiler would otherwise rotate into fresh registers and copy back at the
+// join).  The leading s_nop covers the wait a transcendental result (c comes
+// from v_rsq) needs before a VALU reads it.
+template <int R>
+__device__ inline void rotate_in_place(float (&av)[R], float (&bv)[R], float cf, float sf) {
+  asm volatile("s_nop 1" ::);
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    float t0, t1;
+    asm volatile(
+        "v_mul_f32 %8, %10, %4\n\t"
+        "v_mul_f32 %9, %10, %0\n\t"
+        "v_fma_f32 %0, %11, %0, -%8\n\t"
+        "v_fma_f32 %4, %11, %4, %9\n\t"
+        "v_mul_f32 %8, %10, %5\n\t"
+        "v_mul_f32 %9, %10, %1\n\t"
+        "v_fma_f32 %1, %11, %1, -%8\n\t"
+        "v_fma_f32 %5, %11, %5, %9\n\t"
+        "v_mul_f32 %8, %10, %6\n\t"
+        "v_mul_f32 %9, %10, %2\n\t"
+        "v_fma_f32 %2, %11, %2, -%8\n\t"
+        "v_fma_f32 %6, %11, %6, %9\n\t"
+        "v_mul_f32 %8, %10, %7\n\t"
+        "v_mul_f32 %9, %10, %3\n\t"
+        "v_fma_f32 %3, %11, %3, -%8\n\t"
+        "v_fma_f32 %7, %11, %7, %9"
+        : "+v"(av[4 * q]), "+v"(av[4 * q + 1]), "+v"(av[4 * q + 2]), "+v"(av[4 * q + 3]),
+          "+v"(bv[4 * q]), "+v"(bv[4 * q + 1]), "+v"(bv[4 * q + 2]), "+v"(bv[4 * q + 3]),
+          "=&v"(t0), "=&v"(t1)
+        : "v"(sf), "v"(cf));
+  }
+}
+
 // Columns are stored as R/4 chunks of 4 rows; chunk q of lane l holds rows
 // 4 (l + G q) .. 4 (l + G q) + 3.  Only the first qeff chunks carry rows; the
 // others are zero in every lane from the first load on (get_rows,
@@ -359,10 +396,10 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
     const int nrounds = 2 * npairs - 1;
     for (int k = 0; k < nrounds; ++k) {
       // one rotation of the slot's pair (av, bv).  The angle is found per lane;
-      // the rows are rotated under a wave-uniform branch in which lanes without a
-      // rotation take c = 1, s = 0 (the identity on finite values, up to the sign
-      // of a zero), so the column registers are updated in place rather than
-      // merged lane by lane after a divergent branch.
+      // the rows are rotated on every lane, lanes without a rotation taking
+      // c = 1, s = 0 (the identity on finite values, up to the sign of a zero),
+      // so the column registers are updated in place rather than merged lane by
+      // lane after a divergent branch.
       float cf = 1.f, sf = 0.f, t = 0.f;
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
@@ -388,14 +425,15 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
           sf = cf * t;
         }
       }
-      {
+      // (the in-place update with a wave-uniform skip, rotate_in_place, leaves
+      // this out-of-line body's columns in registers the LDS exchange cannot
+      // store as float4 tuples: the update stays unconditional here)
 #pragma unroll
-        for (int e = 0; e < R; ++e) {
-          const float x = av[e], y = bv[e];
-          const float sy = sf * y, sx = sf * x;
-          av[e] = fmaf(cf, x, -sy);
-          bv[e] = fmaf(cf, y, sx);
-        }
+      for (int e = 0; e < R; ++e) {
+        const float x = av[e], y = bv[e];
+        const float sy = sf * y, sx = sf * x;
+        av[e] = fmaf(cf, x, -sy);
+        bv[e] = fmaf(cf, y, sx);
       }
       if (rot) {
         na = fma(-(double)t, d, pa);
@@ -590,15 +628,8 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
         sf = cf * t;
       }
     }
-    {
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const float x = av[e], y = bv[e];
-        const float sy = sf * y, sx = sf * x;
-        av[e] = fmaf(cf, x, -sy);
-        bv[e] = fmaf(cf, y, sx);
-      }
-    }
+    // waves without a rotation skip the column update
+    if (__builtin_amdgcn_ballot_w64(rot) != 0) rotate_in_place<R>(av, bv, cf, sf);
     if (rot) {
       na = fma(-(double)t, d, pa);
       nb = fma((double)t, d, pb);
@@ -1057,43 +1088,6 @@ __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long
       if (r0 + 2 < n) mc[r0 + 2] = acc.z;
       if (r0 + 3 < n) mc[r0 + 3] = acc.w;
     }
-  }
-}
-
-// (x, y) <- (c x - s y, c y + s x) on every row, with the same roundings as the
-// rotations of jacobi_body (s y and s x rounded, then one fma each).  Written
-// as VALU-only inline assembly whose outputs are tied to its inputs, so that a
-// wave-uniform branch around it updates the column registers in place (the
-// compiler would otherwise rotate into fresh registers and copy back at the
-// join).  The leading s_nop covers the wait a transcendental result (c comes
-// from v_rsq) needs before a VALU reads it.
-template <int R>
-__device__ inline void rotate_in_place(float (&av)[R], float (&bv)[R], float cf, float sf) {
-  asm volatile("s_nop 1" ::);
-#pragma unroll
-  for (int q = 0; q < R / 4; ++q) {
-    float t0, t1;
-    asm volatile(
-        "v_mul_f32 %8, %10, %4\n\t"
-        "v_mul_f32 %9, %10, %0\n\t"
-        "v_fma_f32 %0, %11, %0, -%8\n\t"
-        "v_fma_f32 %4, %11, %4, %9\n\t"
-        "v_mul_f32 %8, %10, %5\n\t"
-        "v_mul_f32 %9, %10, %1\n\t"
-        "v_fma_f32 %1, %11, %1, -%8\n\t"
-        "v_fma_f32 %5, %11, %5, %9\n\t"
-        "v_mul_f32 %8, %10, %6\n\t"
-        "v_mul_f32 %9, %10, %2\n\t"
-        "v_fma_f32 %2, %11, %2, -%8\n\t"
-        "v_fma_f32 %6, %11, %6, %9\n\t"
-        "v_mul_f32 %8, %10, %7\n\t"
-        "v_mul_f32 %9, %10, %3\n\t"
-        "v_fma_f32 %3, %11, %3, -%8\n\t"
-        "v_fma_f32 %7, %11, %7, %9"
-        : "+v"(av[4 * q]), "+v"(av[4 * q + 1]), "+v"(av[4 * q + 2]), "+v"(av[4 * q + 3]),
-          "+v"(bv[4 * q]), "+v"(bv[4 * q + 1]), "+v"(bv[4 * q + 2]), "+v"(bv[4 * q + 3]),
-          "=&v"(t0), "=&v"(t1)
-        : "v"(sf), "v"(cf));
   }
 }
 
