@@ -36,10 +36,10 @@ PEAK_HBM = 8.0e12
 # HBM bytes per k_jacobi_warm launch on the default video workload (FP32,
 # Cholesky-QR preconditioned, warm-started, 150 slices of 144 x 144 factors), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes scaled by a 256 MiB device copy
-# in the same run; the command lines and raw figures are in profiles/.  Reported
-# only for that configuration and this kernel version (null elsewhere, and null
-# until the counters are taken for it).
-JACOBI_WARM_TRAFFIC_VIDEO_BYTES = None
+# in the same run (fetch x2.0, write x1.0), warm launches; the command lines and
+# raw figures are in profiles/.  Reported only for that configuration and this
+# kernel version (null elsewhere).
+JACOBI_WARM_TRAFFIC_VIDEO_BYTES = 41601469
 
 
 def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):

@@ -617,7 +617,7 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
         float* Mw = reinterpret_cast<float*>(w.C) + cst;
         ProfScope ps(h, LT_PROF_PRECOND);
         HIP_TRY(h, lt::launch_warm_product(reinterpret_cast<const float*>(w.C), 2 * cst, warm->Z, Mw, 2 * cst,
-                                           n, (int)s.P, h->stream));
+                                           n, (int)s.P, h->max_lds, h->stream));
         wa.M = Mw;
       }
       wa.Z = warm->Z;

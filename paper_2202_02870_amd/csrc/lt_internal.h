@@ -158,7 +158,7 @@ int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg);
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& cfg, hipStream_t s);
 size_t warm_product_lds_bytes(int n);
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
-                               long long m_stride, int n, int nslices, hipStream_t s);
+                               long long m_stride, int n, int nslices, int max_lds, hipStream_t s);
 
 // The register-resident kernel can hold an m x n working matrix (shape limits
 // only; the device's LDS is checked by jacobi_pick_config).

@@ -1043,20 +1043,27 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
 // workgroup; pair schedule, angle and stopping rule are those of jacobi_body.
 
 // M = L Z per slice (L lower triangular, both n x n column-major): L staged in
-// the LDS with leading dimension npad, Z in blocks of 16 columns; a thread
-// forms 4 rows of one column.
-constexpr int kWarmCols = 16;
-__host__ __device__ inline size_t warm_product_lds(int n) {
+// the LDS with leading dimension npad, Z in blocks of cb columns (stored k-major,
+// so that 4 consecutive columns are one float4); a thread forms a 4 x 4 block
+// of M (4 rows of 4 columns) over k <= its last row.
+__host__ __device__ inline size_t warm_product_lds(int n, int cb) {
   const size_t npad = (size_t)((n + 3) / 4) * 4;
-  return (npad * n + (size_t)kWarmCols * n) * sizeof(float);
+  return (npad * n + (size_t)cb * n) * sizeof(float);
+}
+
+// Columns per block of Z: the most (a multiple of 4, at most 64) the LDS takes.
+__host__ __device__ inline int warm_product_cb(int n, size_t max_lds) {
+  int cb = 64;
+  while (cb > 4 && warm_product_lds(n, cb) > max_lds) cb -= 4;
+  return cb;
 }
 
 __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long l_stride, const float* Z,
-                                                       float* M, long long m_stride, int n) {
+                                                       float* M, long long m_stride, int n, int cb) {
   extern __shared__ __attribute__((aligned(16))) float wp_lds[];
   const int npad = (n + 3) / 4 * 4;
   float* Ls = wp_lds;                      // L(row, k) at Ls[k * npad + row]
-  float* Zb = wp_lds + (size_t)npad * n;   // Z(k, c0 + cc) at Zb[cc * n + k]
+  float* Zt = wp_lds + (size_t)npad * n;   // Z(k, c0 + cc) at Zt[k * cb + cc]
   const float* Lg = L + (long long)blockIdx.x * l_stride;
   const float* Zg = Z + (long long)blockIdx.x * n * n;
   float* Mg = M + (long long)blockIdx.x * m_stride;
@@ -1065,28 +1072,39 @@ __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long
     Ls[e] = row < n ? Lg[(long long)k * n + row] : 0.f;
   }
   const int nr4 = npad / 4;
-  for (int c0 = 0; c0 < n; c0 += kWarmCols) {
-    const int nc = n - c0 < kWarmCols ? n - c0 : kWarmCols;
+  for (int c0 = 0; c0 < n; c0 += cb) {
+    const int nc = n - c0 < cb ? n - c0 : cb;
     __syncthreads();   // L staged / the previous block of Z no longer read
-    for (int e = threadIdx.x; e < nc * n; e += blockDim.x) Zb[e] = Zg[(long long)c0 * n + e];
+    for (int e = threadIdx.x; e < cb * n; e += blockDim.x) {
+      const int cc = e / n, k = e - cc * n;   // coalesced along Z's columns
+      Zt[k * cb + cc] = cc < nc ? Zg[(long long)(c0 + cc) * n + k] : 0.f;
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < nc * nr4; e += blockDim.x) {
-      const int cc = e / nr4, r0 = 4 * (e - cc * nr4);
+    const int nc4 = (nc + 3) / 4;
+    for (int e = threadIdx.x; e < nc4 * nr4; e += blockDim.x) {
+      const int cg = e / nr4, r0 = 4 * (e - cg * nr4);
       const int kend = r0 + 4 < n ? r0 + 4 : n;   // L(row, k) = 0 for k > row
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      float acc[4][4] = {};
       for (int k = 0; k < kend; ++k) {
         const float4 lv = *reinterpret_cast<const float4*>(Ls + (size_t)k * npad + r0);
-        const float z = Zb[cc * n + k];
-        acc.x = fmaf(lv.x, z, acc.x);
-        acc.y = fmaf(lv.y, z, acc.y);
-        acc.z = fmaf(lv.z, z, acc.z);
-        acc.w = fmaf(lv.w, z, acc.w);
+        const float4 zv = *reinterpret_cast<const float4*>(Zt + (size_t)k * cb + 4 * cg);
+        const float lr[4] = {lv.x, lv.y, lv.z, lv.w};
+        const float zc[4] = {zv.x, zv.y, zv.z, zv.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(lr[i], zc[j], acc[i][j]);
       }
-      float* mc = Mg + (long long)(c0 + cc) * n;
-      if (r0 < n) mc[r0] = acc.x;
-      if (r0 + 1 < n) mc[r0 + 1] = acc.y;
-      if (r0 + 2 < n) mc[r0 + 2] = acc.z;
-      if (r0 + 3 < n) mc[r0 + 3] = acc.w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + 4 * cg + j;
+        if (col < c0 + nc) {
+          float* mc = Mg + (long long)col * n;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (r0 + i < n) mc[r0 + i] = acc[i][j];
+        }
+      }
     }
   }
 }
@@ -1780,7 +1798,7 @@ int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg) {
   return 0;
 }
 
-size_t warm_product_lds_bytes(int n) { return warm_product_lds(n); }
+size_t warm_product_lds_bytes(int n) { return warm_product_lds(n, 4); }
 
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
@@ -1793,13 +1811,14 @@ hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& c, hipStrea
 }
 
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
-                               long long m_stride, int n, int nslices, hipStream_t s) {
+                               long long m_stride, int n, int nslices, int max_lds, hipStream_t s) {
   if (nslices <= 0) return hipSuccess;
-  const size_t lds = warm_product_lds(n);
-  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  const int cb = warm_product_cb(n, (size_t)max_lds);
+  const size_t lds = warm_product_lds(n, cb);
+  if (lds > (size_t)max_lds) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_warm_product, dim3(nslices), dim3(1024), lds, s, L, l_stride, Z, M, m_stride, n);
+  hipLaunchKernelGGL(k_warm_product, dim3(nslices), dim3(1024), lds, s, L, l_stride, Z, M, m_stride, n, cb);
   return hipGetLastError();
 }
 
