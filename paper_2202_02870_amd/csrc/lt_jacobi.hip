@@ -1110,37 +1110,42 @@ __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long
 }
 
 // Dot products over the M rows: chunk q of this lane is an M chunk when bit q
-// of mq is set (rows beyond npad are Z rows).
+// of mq is set (rows beyond npad are Z rows); chunks from qm on (the same for
+// every lane) hold Z rows only and are skipped.
 template <int R>
-__device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsigned mq) {
+__device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsigned mq, int qm) {
   float d0 = 0.f, d1 = 0.f;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    const int r = 4 * q;
-    float p = x[r] * y[r];
-    p = fmaf(x[r + 1], y[r + 1], p);
-    p = fmaf(x[r + 2], y[r + 2], p);
-    p = fmaf(x[r + 3], y[r + 3], p);
-    p = ((mq >> q) & 1u) ? p : 0.f;
-    if (q & 1) d1 += p;
-    else d0 += p;
+    if (q < qm) {   // a uniform branch per chunk: the loop stays unrolled over registers
+      const int r = 4 * q;
+      float p = x[r] * y[r];
+      p = fmaf(x[r + 1], y[r + 1], p);
+      p = fmaf(x[r + 2], y[r + 2], p);
+      p = fmaf(x[r + 3], y[r + 3], p);
+      p = ((mq >> q) & 1u) ? p : 0.f;
+      if (q & 1) d1 += p;
+      else d0 += p;
+    }
   }
   return d0 + d1;
 }
 
 template <int R>
-__device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsigned mq) {
+__device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsigned mq, int qm) {
   double d0 = 0.0, d1 = 0.0;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
-    const int r = 4 * q;
-    double p = (double)x[r] * (double)y[r];
-    p = fma((double)x[r + 1], (double)y[r + 1], p);
-    p = fma((double)x[r + 2], (double)y[r + 2], p);
-    p = fma((double)x[r + 3], (double)y[r + 3], p);
-    p = ((mq >> q) & 1u) ? p : 0.0;
-    if (q & 1) d1 += p;
-    else d0 += p;
+    if (q < qm) {
+      const int r = 4 * q;
+      double p = (double)x[r] * (double)y[r];
+      p = fma((double)x[r + 1], (double)y[r + 1], p);
+      p = fma((double)x[r + 2], (double)y[r + 2], p);
+      p = fma((double)x[r + 3], (double)y[r + 3], p);
+      p = ((mq >> q) & 1u) ? p : 0.0;
+      if (q & 1) d1 += p;
+      else d0 += p;
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   return d0 + d1;
@@ -1170,6 +1175,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
 #pragma unroll
   for (int q = 0; q < Q; ++q)
     if (4 * (l + G * q) < npad) mq |= 1u << q;
+  const int qm = (npad + 4 * G - 1) / (4 * G);   // chunks that hold M rows in some lane
 
   // ---- load: slot g holds columns g (top) and 2 npairs - 1 - g (bottom) ----
   float av[R], bv[R];
@@ -1214,8 +1220,8 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
   bool converged = false;
   long long rotations = 0;
   for (;;) {
-    na = group_sum<G>(dot64_m<R>(av, av, mq));
-    nb = group_sum<G>(dot64_m<R>(bv, bv, mq));
+    na = group_sum<G>(dot64_m<R>(av, av, mq, qm));
+    nb = group_sum<G>(dot64_m<R>(bv, bv, mq, qm));
     unsigned my_rot = 0;
     int c = npairs;
     bool ring = (c & 1) == 0;
@@ -1228,7 +1234,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
       if (active) {
-        d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, mq)) : group_sum<G>(dot64_m<R>(av, bv, mq));
+        d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, mq, qm)) : group_sum<G>(dot64_m<R>(av, bv, mq, qm));
         pa = fmax(na, 0.0);
         pb = fmax(nb, 0.0);
         rot = d != 0.0 && d * d > tol * tol * (pa * pb);
@@ -1252,16 +1258,29 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
       }
       if (k + 1 == nrounds) break;
       if (ring && r + 1 < c) {
-        const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
-        float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
-        if (active) put_col<G, R>(buf, ldw, g, l, bv, Q, nb, idb);
-        __syncthreads();
-        if (active) get_col<G, R>(buf, ldw, nxt, l, bv, Q, nb, idb);
-        if (nbuf == 1) __syncthreads();
+        if (nbuf == 2) {
+          const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+          float* buf = (r & 1) ? bufB : bufA;
+          if (active) put_col<G, R>(buf, ldw, g, l, bv, Q, nb, idb);
+          __syncthreads();
+          if (active) get_col<G, R>(buf, ldw, nxt, l, bv, Q, nb, idb);
+        } else {
+          // one buffer, one barrier: in round r of the phase slot i writes
+          // position (i + r) mod c of its range and reads (i + 1 + r) mod c,
+          // slot i+1's; the position it writes next round is the one only it
+          // read this round, so no second barrier is needed
+          const int wpos = i + r < c ? i + r : i + r - c;
+          const int rpos = wpos + 1 == c ? 0 : wpos + 1;
+          if (active) put_col<G, R>(bufA, ldw, s0 + wpos, l, bv, Q, nb, idb);
+          __syncthreads();
+          if (active) get_col<G, R>(bufA, ldw, s0 + rpos, l, bv, Q, nb, idb);
+        }
         ++r;
       } else if (ring) {
         const int h = c >> 1;
         const bool first = i < h;
+        // the ring rounds' last reads may still be in flight (single buffer)
+        if (nbuf == 1 && r > 0) __syncthreads();
         if (active) {
           if (first) put_col<G, R>(bufB, ldw, g, l, bv, Q, nb, idb);
           else put_col<G, R>(bufB, ldw, g, l, av, Q, na, ida);
@@ -1319,8 +1338,8 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
         }
       }
   }
-  na = group_sum<G>(dot64_m<R>(av, av, mq));
-  nb = group_sum<G>(dot64_m<R>(bv, bv, mq));
+  na = group_sum<G>(dot64_m<R>(av, av, mq, qm));
+  nb = group_sum<G>(dot64_m<R>(bv, bv, mq, qm));
   const double sa = sqrt(na), sb = sqrt(nb);
   const bool ka = active && ida < n && sa > a.tau;
   const bool kb = active && idb < n && sb > a.tau;
