@@ -442,19 +442,23 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
       }
       if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
       if (ring && r + 1 < c) {
-        // ring: bottoms move one slot down the range (double-buffered: one barrier)
-        const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+        // ring: bottoms move one slot down the range, one barrier.  Two buffers
+        // alternate; with one, slot i writes position (i + r) mod c of its range
+        // and reads (i + 1 + r) mod c, slot i+1's, and the position it writes in
+        // the next round is the one only it read in this one.
+        const int wpos = (nbuf == 2) ? i : (i + r < c ? i + r : i + r - c);
+        const int rpos = wpos + 1 == c ? 0 : wpos + 1;
         float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
-        if (moving) put_col<G, R>(buf, ldw, g, l, bv, qeff, nb, idb);
+        if (moving) put_col<G, R>(buf, ldw, s0 + wpos, l, bv, qeff, nb, idb);
         __syncthreads();
-        if (moving) get_col<G, R>(buf, ldw, nxt, l, bv, qeff, nb, idb);
-        if (nbuf == 1) __syncthreads();
+        if (moving) get_col<G, R>(buf, ldw, s0 + rpos, l, bv, qeff, nb, idb);
         ++r;
       } else if (ring) {
         // end of a ring phase: the first half's bottoms and the second half's
         // tops trade places, leaving two ranges of c/2 slots
         const int h = c >> 1;
         const bool first = i < h;
+        if (nbuf == 1 && r > 0) __syncthreads();   // the last ring round's reads (one buffer)
         if (moving) {
           if (first) put_col<G, R>(bufB, ldw, g, l, bv, qeff, nb, idb);
           else put_col<G, R>(bufB, ldw, g, l, av, qeff, na, ida);
@@ -637,19 +641,23 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
     }
     if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
     if (ring && r + 1 < c) {
-      // ring: bottoms move one slot down the range (double-buffered: one barrier)
-      const int nxt = s0 + (i + 1 == c ? 0 : i + 1);
+      // ring: bottoms move one slot down the range, one barrier.  Two buffers
+      // alternate; with one, slot i writes position (i + r) mod c of its range
+      // and reads (i + 1 + r) mod c, slot i+1's, and the position it writes in
+      // the next round is the one only it read in this one.
+      const int wpos = (nbuf == 2) ? i : (i + r < c ? i + r : i + r - c);
+      const int rpos = wpos + 1 == c ? 0 : wpos + 1;
       float* buf = (nbuf == 2 && (r & 1)) ? bufB : bufA;
-      if (moving) put_col<G, R>(buf, ldw, g, l, bv, qeff, nb, idb);
+      if (moving) put_col<G, R>(buf, ldw, s0 + wpos, l, bv, qeff, nb, idb);
       __syncthreads();
-      if (moving) get_col<G, R>(buf, ldw, nxt, l, bv, qeff, nb, idb);
-      if (nbuf == 1) __syncthreads();
+      if (moving) get_col<G, R>(buf, ldw, s0 + rpos, l, bv, qeff, nb, idb);
       ++r;
     } else if (ring) {
       // end of a ring phase: the first half's bottoms and the second half's
       // tops trade places, leaving two ranges of c/2 slots
       const int h = c >> 1;
       const bool first = i < h;
+      if (nbuf == 1 && r > 0) __syncthreads();   // the last ring round's reads (one buffer)
       if (moving) {
         if (first) put_col<G, R>(bufB, ldw, g, l, bv, qeff, nb, idb);
         else put_col<G, R>(bufB, ldw, g, l, av, qeff, na, ida);
