@@ -752,6 +752,7 @@ struct ProblemWs {
   unsigned int* scratch = nullptr;
   double* C = nullptr;   // preconditioning: Gram matrices / Cholesky factors
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
+  float* Z = nullptr;     // warm-started Jacobi: per-slice accumulated rotations
   int n_partials = 0;
 };
 
@@ -762,7 +763,14 @@ bool problem_precond(const Shape& s, const lt_pga_params* p) {
   return svt_plan(s, precond_requested(&p->svd), &pl) && pl.precond;
 }
 
-void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool precond, ProblemWs* w) {
+// A batch problem warm-starts its Jacobi as lt_complete_pga does (same shapes,
+// same cold-start period); 0: never.
+int problem_warm_period(const Shape& s, const lt_pga_params* p) {
+  if (!problem_precond(s, p) || p->svd.warm_restart < 0 || !warm_shape(s)) return 0;
+  return p->svd.warm_restart == 0 ? kWarmRestartDefault : p->svd.warm_restart;
+}
+
+void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool precond, bool warm, ProblemWs* w) {
   w->st = c.take<lt::ProbDev>(1);
   carve_transform(c, s, prec, &w->t);
   w->Xb = c.take<float>((size_t)s.nel);
@@ -778,6 +786,7 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool preco
   if (precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
   SvtPlan pl;
   if (svt_plan(s, precond, &pl) && pl.blocked) w->work = c.take<float>((size_t)s.P * (size_t)pl.bcfg.work_floats);
+  if (warm) w->Z = c.take<float>((size_t)(s.P * precond_n(s) * precond_n(s)));
 }
 
 int check_pga_params(lt_handle* h, const lt_pga_params* p) {
@@ -823,6 +832,12 @@ struct BatchTables {
   size_t blk_lds[lt::kBlkNumVariants] = {};
   std::vector<lt::RebuildTile> rebuild_wide;
   int rebuild_kmax = 0, rebuild_wide_kmax = 0;   // largest min(I1, I2) of each tile list
+  // warm-started Jacobi: items grouped by configuration (G, R, nbuf), each
+  // group's launch shape; the products M = L Z over the same slices
+  std::vector<lt::CholItem> warm;
+  std::vector<lt::JacobiConfig> warm_cfg;
+  std::vector<int> warm_count;
+  int warm_nmax = 0;
   bool any_reg = false;
   lt::JacobiBatchConfig cfg{};
   int prec = 0, max_sweeps = 40;
@@ -836,6 +851,8 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
   std::vector<int> ms(n), ns(n), nsub(n, 1), qeff(n, 1);
   std::vector<int> blocked(n, 0);
   std::vector<lt::JacobiBlkConfig> bcfg(n);
+  std::vector<int> warm(n, 0);
+  std::vector<lt::JacobiConfig> wcfg(n);
   for (int i = 0; i < n; ++i) {
     int rc = parse(h, probs[i].desc, &shapes[i]);
     if (rc) return rc;
@@ -856,6 +873,9 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     if (!svt_plan(shapes[i], problem_precond(shapes[i], &probs[i].params), &pl))
       return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", shapes[i].I1, shapes[i].I2);
     ms[i] = pl.jm;   // n for the Jacobi on the n x n factor
+    if (problem_warm_period(shapes[i], &probs[i].params) > 0 &&
+        lt::jacobi_warm_config(ns[i], h->max_lds, &wcfg[i]) == 0)
+      warm[i] = 1;
     if (pl.blocked) {
       int rc2 = check_blk_lds(h, shapes[i], pl.bcfg);
       if (rc2) return rc2;
@@ -892,13 +912,14 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     Carver c(probs[i].ws);
     ProblemWs w;
     const bool pc = problem_precond(shapes[i], &probs[i].params);
-    carve_problem(c, shapes[i], T->prec, probs[i].params.max_iter, pc, &w);
+    carve_problem(c, shapes[i], T->prec, probs[i].params.max_iter, pc,
+                  problem_warm_period(shapes[i], &probs[i].params) > 0, &w);
     T->ptrs[i] = w.st;
     const Shape& s = shapes[i];
     const int ntx = (int)((s.N + 63) / 64), nty = (int)((s.P + 63) / 64);
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) T->gemm.push_back(lt::GemmTile{i, tx, ty, ty * ntx + tx});
-    if (!blocked[i]) {
+    if (!blocked[i] && !warm[i]) {
       const int rounds = 2 * ((ns[i] + 1) / 2) - 1;
       for (int s0 = 0; s0 < (int)s.P; s0 += nsub[i]) {
         const int k = (int)(s.P - s0) < nsub[i] ? (int)(s.P - s0) : nsub[i];
@@ -936,6 +957,30 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
       T->blk_lds[gi] = bcfg[i].lds > T->blk_lds[gi] ? bcfg[i].lds : T->blk_lds[gi];
     }
   }
+  // warm-started items, grouped by configuration
+  for (int i = 0; i < n; ++i) {
+    if (!warm[i]) continue;
+    size_t gi = 0;
+    while (gi < T->warm_cfg.size() &&
+           !(T->warm_cfg[gi].G == wcfg[i].G && T->warm_cfg[gi].R == wcfg[i].R && T->warm_cfg[gi].nbuf == wcfg[i].nbuf))
+      ++gi;
+    if (gi == T->warm_cfg.size()) {
+      T->warm_cfg.push_back(wcfg[i]);
+      T->warm_count.push_back(0);
+    }
+    lt::JacobiConfig& g = T->warm_cfg[gi];
+    g.threads = wcfg[i].threads > g.threads ? wcfg[i].threads : g.threads;
+    g.lds = wcfg[i].lds > g.lds ? wcfg[i].lds : g.lds;
+    T->warm_nmax = ns[i] > T->warm_nmax ? ns[i] : T->warm_nmax;
+  }
+  for (size_t gi = 0; gi < T->warm_cfg.size(); ++gi) {
+    const lt::JacobiConfig& g = T->warm_cfg[gi];
+    for (int i = 0; i < n; ++i) {
+      if (!warm[i] || wcfg[i].G != g.G || wcfg[i].R != g.R || wcfg[i].nbuf != g.nbuf) continue;
+      for (int sl = 0; sl < (int)shapes[i].P; ++sl) T->warm.push_back(lt::CholItem{i, sl});
+      T->warm_count[gi] += (int)shapes[i].P;
+    }
+  }
   // longest first, ties by problem then slice (deterministic)
   std::stable_sort(costed.begin(), costed.end(),
                    [](const std::pair<double, lt::SvtItem>& a, const std::pair<double, lt::SvtItem>& b) {
@@ -955,6 +1000,7 @@ struct BatchWs {
   lt::CholItem* cholg = nullptr;
   lt::CholItem* blk = nullptr;
   lt::RebuildTile* rebuild_wide = nullptr;
+  lt::CholItem* warm = nullptr;
 };
 
 // The item count depends on how many slices a workgroup packs (device LDS);
@@ -969,6 +1015,7 @@ void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
   w->cholg = c.take<lt::CholItem>(T.cholg.size());
   w->blk = c.take<lt::CholItem>(T.blk.size());
   w->rebuild_wide = c.take<lt::RebuildTile>(T.rebuild_wide.size());
+  w->warm = c.take<lt::CholItem>(T.warm.size());
 }
 
 }  // namespace
@@ -1517,7 +1564,7 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   if (s.any_dft) return 0;   // the batch engine runs real transforms only
   Carver c(nullptr);
   ProblemWs w;
-  carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), &w);
+  carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), problem_warm_period(s, p) > 0, &w);
   return c.off + 256;
 }
 
@@ -1552,7 +1599,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   Carver c(p->ws);
   ProblemWs w;
   const bool pc = problem_precond(s, &p->params);
-  carve_problem(c, s, prec, p->params.max_iter, pc, &w);
+  const int wp = problem_warm_period(s, &p->params);
+  carve_problem(c, s, prec, p->params.max_iter, pc, wp > 0, &w);
   hipStream_t st = h->stream;
   HIP_TRY(h, lt::launch_fill_zero(w.scratch, 16, st));
   HIP_TRY(h, lt::launch_count_nonfinite(p->M, p->mask, s.nel, w.scratch, st));
@@ -1599,6 +1647,8 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   d.enabled = 1;
   d.C = w.C;
   d.precond = pc ? 1 : 0;
+  d.Z = w.Z;
+  d.warm_period = wp;
   if (blk) {
     d.work = w.work;
     d.work_stride = bcfg.work_floats;
@@ -1625,7 +1675,7 @@ int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int
   Carver c(p->ws);
   ProblemWs w;
   const bool pc = problem_precond(s, &p->params);
-  carve_problem(c, s, prec, p->params.max_iter, pc, &w);
+  carve_problem(c, s, prec, p->params.max_iter, pc, problem_warm_period(s, &p->params) > 0, &w);
   // on the handle's stream only: work of other streams (other lanes of a
   // server) is not waited for
   static_assert(sizeof(lt::ProbDev) <= kPinnedDoubles * sizeof(double), "staging too small");
@@ -1713,6 +1763,7 @@ int lt_batch_create(lt_handle* h, int n, const lt_problem* probs, void* bws, siz
   if (e == hipSuccess) e = up(b->w.blk, b->T.blk.data(), b->T.blk.size() * sizeof(lt::CholItem));
   if (e == hipSuccess)
     e = up(b->w.rebuild_wide, b->T.rebuild_wide.data(), b->T.rebuild_wide.size() * sizeof(lt::RebuildTile));
+  if (e == hipSuccess) e = up(b->w.warm, b->T.warm.data(), b->T.warm.size() * sizeof(lt::CholItem));
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && use_graph) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -1745,6 +1796,9 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
     if ((e = lt::launch_chol_items(b->w.ptrs, b->w.cholg, (int)T.cholg.size(), T.cholg_nmax, s)) !=
         hipSuccess)
       return e;
+    if ((e = lt::launch_warm_product_items(b->w.ptrs, b->w.warm, (int)T.warm.size(), T.warm_nmax, h->max_lds,
+                                           s)) != hipSuccess)
+      return e;
   }
   if (!T.blk.empty()) {
     // the long blocked slices first, so the register-resident items fill in behind them
@@ -1759,7 +1813,17 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
       off += T.blk_count[gi];
     }
   }
-  if (T.any_reg) {
+  if (!T.warm.empty()) {
+    ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
+    int off = 0;
+    for (size_t gi = 0; gi < T.warm_cfg.size(); ++gi) {
+      if ((e = lt::launch_jacobi_warm_items(b->w.ptrs, b->w.warm + off, T.warm_count[gi], T.warm_cfg[gi], T.tol,
+                                            T.max_sweeps, s)) != hipSuccess)
+        return e;
+      off += T.warm_count[gi];
+    }
+  }
+  if (T.any_reg && !T.items.empty()) {
     ProfScope ps(prof ? h : nullptr, LT_PROF_JACOBI);
     if ((e = lt::launch_jacobi_items(b->w.ptrs, b->w.items, (int)T.items.size(), T.cfg, T.tol,
                                      T.max_sweeps, s)) != hipSuccess)

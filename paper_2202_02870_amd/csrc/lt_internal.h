@@ -257,6 +257,8 @@ struct ProbDev {
   float* work;               // blocked Jacobi: per-slice working buffers (or null)
   long long work_stride;
   int blk_b, blk_n, blk_q, blk_variant, blk_nbuf, pad3;
+  float* Z;                  // warm-started Jacobi: per-slice accumulated rotations (n x n), or null
+  int warm_period, pad4;     // cold start (Z = I) when iter % warm_period == 0; 0: always cold
   // dynamic
   int iter, parity, done, active;   // done: 1 converged, 2 iteration limit
   double beta, tau, num, den, crit;
@@ -297,5 +299,12 @@ hipError_t launch_jacobi_items(ProbDev* const* probs, const SvtItem* items, int 
 // Blocked kernel over items (problem, slice) of problems with blk_variant == variant.
 hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items, int nitems, int variant,
                                    int threads, size_t lds, double tol, int max_sweeps, hipStream_t s);
+// Warm-started Jacobi over items (problem, slice) of warm-started problems
+// sharing one configuration (G, R, nbuf; threads and LDS the items' maxima),
+// and the products M = L Z they need (nmax: the items' largest n).
+hipError_t launch_jacobi_warm_items(ProbDev* const* probs, const CholItem* items, int nitems,
+                                    const JacobiConfig& cfg, double tol, int max_sweeps, hipStream_t s);
+hipError_t launch_warm_product_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
+                                     int max_lds, hipStream_t s);
 
 }  // namespace lt

@@ -1066,15 +1066,12 @@ __host__ __device__ inline int warm_product_cb(int n, size_t max_lds) {
   return cb;
 }
 
-__global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long l_stride, const float* Z,
-                                                       float* M, long long m_stride, int n, int cb) {
+__device__ __attribute__((always_inline)) inline void warm_product_body(const float* Lg, const float* Zg, float* Mg,
+                                                                       int n, int cb) {
   extern __shared__ __attribute__((aligned(16))) float wp_lds[];
   const int npad = (n + 3) / 4 * 4;
   float* Ls = wp_lds;                      // L(row, k) at Ls[k * npad + row]
   float* Zt = wp_lds + (size_t)npad * n;   // Z(k, c0 + cc) at Zt[k * cb + cc]
-  const float* Lg = L + (long long)blockIdx.x * l_stride;
-  const float* Zg = Z + (long long)blockIdx.x * n * n;
-  float* Mg = M + (long long)blockIdx.x * m_stride;
   for (int e = threadIdx.x; e < npad * n; e += blockDim.x) {
     const int k = e / npad, row = e - k * npad;
     Ls[e] = row < n ? Lg[(long long)k * n + row] : 0.f;
@@ -1115,6 +1112,29 @@ __global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long
       }
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long l_stride, const float* Z,
+                                                       float* M, long long m_stride, int n, int cb) {
+  warm_product_body(L + (long long)blockIdx.x * l_stride, Z + (long long)blockIdx.x * n * n,
+                    M + (long long)blockIdx.x * m_stride, n, cb);
+}
+
+// Whether a batch problem's Jacobi starts cold this iteration (Z = I, M = L).
+__device__ inline bool warm_cold(const ProbDev* pd) {
+  return pd->warm_period <= 0 || pd->iter % pd->warm_period == 0;
+}
+
+// Batch: one workgroup per slice of the warm-started problems (L over the first
+// half of the slice's FP64 Gram block, M written over the second half); cold
+// problems skip it.
+__global__ __launch_bounds__(1024) void k_warm_product_items(ProbDev* const* probs, const CholItem* items, int cb) {
+  const CholItem it = items[blockIdx.x];
+  const ProbDev* pd = probs[it.prob];
+  if (!pd->active || warm_cold(pd)) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  const float* L = reinterpret_cast<const float*>(pd->C) + (long long)it.slice * 2 * n * n;
+  warm_product_body(L, pd->Z + (long long)it.slice * n * n, const_cast<float*>(L) + (long long)n * n, n, cb);
 }
 
 // Dot products over the M rows: chunk q of this lane is an M chunk when bit q
@@ -1159,9 +1179,23 @@ __device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsig
   return d0 + d1;
 }
 
-template <int G, int R, int LB>
-__global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ldw) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+// One slice of the warm-started Jacobi.
+struct WarmJob {
+  const float* M;           // n x n, column-major: L Z, or L when cold
+  float* Z;                 // n x n, column-major: read unless cold, rewritten
+  float* out;               // kept columns, scaled
+  int32_t* rank;
+  int32_t* sweeps;
+  unsigned long long* sweep_total;
+  unsigned long long* rot_total;
+  unsigned int* hits;
+  double tau, tol;
+  int n, max_sweeps, cold;
+};
+
+template <int G, int R>
+__device__ __attribute__((always_inline)) inline void jacobi_warm_body(const WarmJob& a, int nbuf, int ldw,
+                                                                       unsigned char* smem) {
   constexpr int Q = R / 4;
   const int n = a.n;
   const int npad = (n + 3) / 4 * 4;
@@ -1176,8 +1210,8 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
   float* bufA = reinterpret_cast<float*>(smem + kWgCtlBytes);
   float* bufB = (nbuf == 2) ? bufA + (size_t)npos * ldw : bufA;
   int* ctl = reinterpret_cast<int*>(bufA + (size_t)nbuf * npos * ldw);
-  const float* __restrict__ Ms = a.M + (long long)blockIdx.x * a.m_stride;
-  float* Zs = a.Z + (long long)blockIdx.x * n * n;
+  const float* __restrict__ Ms = a.M;
+  float* Zs = a.Z;
 
   unsigned mq = 0;   // this lane's M chunks
 #pragma unroll
@@ -1363,7 +1397,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
     ctl[2] = acc;
   }
   __syncthreads();
-  float* out = a.bk + (long long)blockIdx.x * a.bk_stride;
+  float* out = a.out;
   const int j0 = active ? ctl[3 + g] : 0;
   const double sca = ka ? sqrt(1.0 - a.tau / sa) / sa : 0.0;
   const double scb = kb ? sqrt(1.0 - a.tau / sb) / sb : 0.0;
@@ -1378,12 +1412,61 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
   __syncthreads();
   if (active) stage_out(out, bufA, ldw, n, npairs, t2, tps);
   if (active && t2 == 0) {
-    if (a.rank) a.rank[blockIdx.x] = ctl[2];
-    if (a.sweeps) a.sweeps[blockIdx.x] = my_sweeps;
+    if (a.rank) *a.rank = ctl[2];
+    if (a.sweeps) *a.sweeps = my_sweeps;
     if (a.sweep_total) atomicAdd(a.sweep_total, (unsigned long long)my_sweeps);
     if (a.rot_total) atomicAdd(a.rot_total, (unsigned long long)rotations);
     if (!converged && a.hits) atomicAdd(a.hits, 1u);
   }
+}
+
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const long long s = blockIdx.x;
+  WarmJob j;
+  j.M = a.M + s * a.m_stride;
+  j.Z = a.Z + s * a.n * a.n;
+  j.out = a.bk + s * a.bk_stride;
+  j.rank = a.rank ? a.rank + s : nullptr;
+  j.sweeps = a.sweeps ? a.sweeps + s : nullptr;
+  j.sweep_total = a.sweep_total;
+  j.rot_total = a.rot_total;
+  j.hits = a.hits;
+  j.tau = a.tau;
+  j.tol = a.tol;
+  j.n = a.n;
+  j.max_sweeps = a.max_sweeps;
+  j.cold = a.cold;
+  jacobi_warm_body<G, R>(j, nbuf, ldw, smem);
+}
+
+// Batch: one workgroup per slice of the warm-started problems.
+template <int G, int R, int LB>
+__global__ __launch_bounds__(LB) void k_jacobi_warm_items(ProbDev* const* probs, const CholItem* items, double tol,
+                                                         int max_sweeps, int nbuf, int ldw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const CholItem it = items[blockIdx.x];
+  ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  const bool cold = warm_cold(pd);
+  const float* L = reinterpret_cast<const float*>(pd->C) + (long long)it.slice * 2 * n * n;
+  WarmJob j;
+  j.M = cold ? L : L + (long long)n * n;
+  j.Z = pd->Z + (long long)it.slice * n * n;
+  j.out = pd->Bk + (long long)it.slice * pd->N;
+  j.rank = pd->rank + it.slice;
+  j.sweeps = pd->sweeps + it.slice;
+  j.sweep_total = &pd->sweep_total;
+  j.rot_total = &pd->rot_total;
+  j.hits = &pd->maxsweep_hits;
+  j.tau = pd->tau;
+  j.tol = tol;
+  j.n = n;
+  j.max_sweeps = max_sweeps;
+  j.cold = cold ? 1 : 0;
+  jacobi_warm_body<G, R>(j, nbuf, ldw, smem);
 }
 
 // ---- rebuild D_W = Bk (Bk^T W) ------------------------------------------------
@@ -1835,6 +1918,64 @@ hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& c, hipStrea
     case 16: return launch_warm_g<16>(a, c, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int G, int R, int LB>
+static hipError_t launch_warm_items_one(ProbDev* const* probs, const CholItem* items, int nitems,
+                                        const JacobiConfig& c, double tol, int max_sweeps, hipStream_t s) {
+  const int ldw = G * R + 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_warm_items<G, R, LB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_jacobi_warm_items<G, R, LB>), dim3(nitems), dim3(c.threads), c.lds, s, probs, items, tol,
+                     max_sweeps, c.nbuf, ldw);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_warm_items_g(ProbDev* const* probs, const CholItem* items, int nitems,
+                                      const JacobiConfig& c, double tol, int max_sweeps, hipStream_t s) {
+#define LT_WARM_ITEMS_CASE(RR)                                                                      \
+  case RR:                                                                                          \
+    return c.threads <= 768 ? launch_warm_items_one<G, RR, 768>(probs, items, nitems, c, tol, max_sweeps, s) \
+                            : launch_warm_items_one<G, RR, 1024>(probs, items, nitems, c, tol, max_sweeps, s);
+  switch (c.R) {
+    LT_WARM_ITEMS_CASE(4)
+    LT_WARM_ITEMS_CASE(8)
+    LT_WARM_ITEMS_CASE(12)
+    LT_WARM_ITEMS_CASE(16)
+    LT_WARM_ITEMS_CASE(20)
+    LT_WARM_ITEMS_CASE(24)
+    LT_WARM_ITEMS_CASE(28)
+    LT_WARM_ITEMS_CASE(32)
+    LT_WARM_ITEMS_CASE(36)
+    default: return hipErrorInvalidValue;
+  }
+#undef LT_WARM_ITEMS_CASE
+}
+
+hipError_t launch_jacobi_warm_items(ProbDev* const* probs, const CholItem* items, int nitems, const JacobiConfig& c,
+                                    double tol, int max_sweeps, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  switch (c.G) {
+    case 4: return launch_warm_items_g<4>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 8: return launch_warm_items_g<8>(probs, items, nitems, c, tol, max_sweeps, s);
+    case 16: return launch_warm_items_g<16>(probs, items, nitems, c, tol, max_sweeps, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_warm_product_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
+                                     int max_lds, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const int cb = warm_product_cb(nmax, (size_t)max_lds);
+  const size_t lds = warm_product_lds(nmax, cb);
+  if (lds > (size_t)max_lds) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product_items, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_warm_product_items, dim3(nitems), dim3(1024), lds, s, probs, items, cb);
+  return hipGetLastError();
 }
 
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,

@@ -141,14 +141,14 @@ def test_batch_matches_single_problem_path(lt):
     _run(lt, [gp], 80)
     import torch
     s = p.schedule
-    # the same algorithm (both preconditioned, each Jacobi from a cold start):
-    # equal to FP32 rounding
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80, warm_restart=-1)
+    # the same algorithm (both preconditioned and warm-started with the default
+    # cold-start period): equal to FP32 rounding
+    assert lt.pga_warm(p.shape, p.kinds)
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 1e-6
-    # the single-problem path's default warm-started Jacobi: the same result to
-    # the Jacobi tolerance
-    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80)
+    # every Jacobi from a cold start: the same result to the Jacobi tolerance
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=80, warm_restart=-1)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     assert rel(lt.to_host(gp.X), lt.to_host(X).astype(np.float64)) < 5e-5
     # the Jacobi on the slices themselves: the same result to the Jacobi tolerance
