@@ -184,3 +184,27 @@ def test_svt_ranks():
     D = o.svt(A, tau, mats)
     rho, _ = o.multirank(D, mats, rtol=1e-9)
     assert np.array_equal(rho, o.svt_ranks(A, tau, mats))
+
+
+def test_warm_start_invariance():
+    """The warm-started SVT's premise (reading R22): for the n x n factor L and
+    any orthogonal Z, L Z has the singular values of L and the same left
+    singular subspaces, so the projector sum (1 - tau/sigma_i) u_i u_i^T that
+    the preconditioned rebuild uses is unchanged."""
+    rng = np.random.default_rng(22)
+    n, tau = 12, 0.8
+    L = np.tril(rng.standard_normal((n, n)))
+    Z, _ = np.linalg.qr(rng.standard_normal((n, n)))
+
+    def proj(A):
+        U, s, _ = np.linalg.svd(A)
+        keep = s > tau
+        return s, (U[:, keep] * (1.0 - tau / s[keep])) @ U[:, keep].T
+
+    s1, P1 = proj(L)
+    s2, P2 = proj(L @ Z)
+    assert np.allclose(s1, s2, rtol=1e-12, atol=1e-12)
+    assert np.allclose(P1, P2, atol=1e-11)
+    # and the non-orthogonal case is not invariant (a wrong Z would show)
+    s3, _ = proj(L @ (Z + 0.1 * rng.standard_normal((n, n))))
+    assert not np.allclose(s1, s3, rtol=1e-3)

@@ -149,3 +149,39 @@ def test_block_tournament_pairs_every_block_once():
             for pi in range(nblk // 2):
                 met.add(frozenset((pos[pi], pos[nblk - 1 - pi])))
         assert len(met) == nblk * (nblk - 1) // 2
+
+
+def ring_positions(c, r, i):
+    """Single exchange buffer, ring round r of a phase over c slots: the position
+    slot i writes its bottom to and the one it reads its new bottom from (the
+    kernels' formulas)."""
+    wpos = i + r if i + r < c else i + r - c
+    rpos = 0 if wpos + 1 == c else wpos + 1
+    return wpos, rpos
+
+
+@pytest.mark.parametrize("c", [2, 4, 6, 8, 18, 36, 72, 128])
+def test_single_buffer_ring_positions(c):
+    """With one buffer and one barrier per ring round: every slot reads slot
+    i+1's bottom (the ring move), and the position a slot writes in round r+1
+    was read in round r by that slot alone, so no other lane can still be
+    reading it when it is overwritten."""
+    bottoms = list(range(100, 100 + c))
+    for r in range(c - 1):
+        buf = {}
+        for i in range(c):
+            w, _ = ring_positions(c, r, i)
+            assert w not in buf
+            buf[w] = bottoms[i]
+        new = []
+        readers = {}
+        for i in range(c):
+            _, rd = ring_positions(c, r, i)
+            new.append(buf[rd])
+            readers.setdefault(rd, []).append(i)
+        assert new == [bottoms[(i + 1) % c] for i in range(c)]
+        if r + 1 < c - 1:
+            for i in range(c):
+                w_next, _ = ring_positions(c, r + 1, i)
+                assert readers.get(w_next, []) in ([], [i])
+        bottoms = new
