@@ -1137,11 +1137,11 @@ __global__ __launch_bounds__(1024) void k_warm_product_items(ProbDev* const* pro
   warm_product_body(L, pd->Z + (long long)it.slice * n * n, const_cast<float*>(L) + (long long)n * n, n, cb);
 }
 
-// Dot products over the M rows: chunk q of this lane is an M chunk when bit q
-// of mq is set (rows beyond npad are Z rows); chunks from qm on (the same for
-// every lane) hold Z rows only and are skipped.
+// Dot products over the M rows.  Chunks q < qm - 1 hold M rows in every lane,
+// chunk qm - 1 in the lanes where lastm is set, later chunks only Z rows (those
+// are skipped: the bound is the same for every lane).
 template <int R>
-__device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsigned mq, int qm) {
+__device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], bool lastm, int qm) {
   float d0 = 0.f, d1 = 0.f;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
@@ -1151,7 +1151,7 @@ __device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsign
       p = fmaf(x[r + 1], y[r + 1], p);
       p = fmaf(x[r + 2], y[r + 2], p);
       p = fmaf(x[r + 3], y[r + 3], p);
-      p = ((mq >> q) & 1u) ? p : 0.f;
+      p = (q + 1 < qm || lastm) ? p : 0.f;
       if (q & 1) d1 += p;
       else d0 += p;
     }
@@ -1160,7 +1160,7 @@ __device__ inline float dot32_m(const float (&x)[R], const float (&y)[R], unsign
 }
 
 template <int R>
-__device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsigned mq, int qm) {
+__device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], bool lastm, int qm) {
   double d0 = 0.0, d1 = 0.0;
 #pragma unroll
   for (int q = 0; q < R / 4; ++q) {
@@ -1170,7 +1170,7 @@ __device__ inline double dot64_m(const float (&x)[R], const float (&y)[R], unsig
       p = fma((double)x[r + 1], (double)y[r + 1], p);
       p = fma((double)x[r + 2], (double)y[r + 2], p);
       p = fma((double)x[r + 3], (double)y[r + 3], p);
-      p = ((mq >> q) & 1u) ? p : 0.0;
+      p = (q + 1 < qm || lastm) ? p : 0.0;
       if (q & 1) d1 += p;
       else d0 += p;
     }
@@ -1213,11 +1213,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
   const float* __restrict__ Ms = a.M;
   float* Zs = a.Z;
 
-  unsigned mq = 0;   // this lane's M chunks
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-    if (4 * (l + G * q) < npad) mq |= 1u << q;
   const int qm = (npad + 4 * G - 1) / (4 * G);   // chunks that hold M rows in some lane
+  const bool lastm = 4 * (l + G * (qm - 1)) < npad;   // chunk qm - 1 holds M rows in this lane
 
   // ---- load: slot g holds columns g (top) and 2 npairs - 1 - g (bottom) ----
   float av[R], bv[R];
@@ -1262,8 +1259,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
   bool converged = false;
   long long rotations = 0;
   for (;;) {
-    na = group_sum<G>(dot64_m<R>(av, av, mq, qm));
-    nb = group_sum<G>(dot64_m<R>(bv, bv, mq, qm));
+    na = group_sum<G>(dot64_m<R>(av, av, lastm, qm));
+    nb = group_sum<G>(dot64_m<R>(bv, bv, lastm, qm));
     unsigned my_rot = 0;
     int c = npairs;
     bool ring = (c & 1) == 0;
@@ -1276,7 +1273,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
       if (active) {
-        d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, mq, qm)) : group_sum<G>(dot64_m<R>(av, bv, mq, qm));
+        d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, lastm, qm)) : group_sum<G>(dot64_m<R>(av, bv, lastm, qm));
         pa = fmax(na, 0.0);
         pb = fmax(nb, 0.0);
         rot = d != 0.0 && d * d > tol * tol * (pa * pb);
@@ -1380,8 +1377,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
         }
       }
   }
-  na = group_sum<G>(dot64_m<R>(av, av, mq, qm));
-  nb = group_sum<G>(dot64_m<R>(bv, bv, mq, qm));
+  na = group_sum<G>(dot64_m<R>(av, av, lastm, qm));
+  nb = group_sum<G>(dot64_m<R>(bv, bv, lastm, qm));
   const double sa = sqrt(na), sb = sqrt(nb);
   const bool ka = active && ida < n && sa > a.tau;
   const bool kb = active && idb < n && sb > a.tau;
