@@ -388,11 +388,12 @@ def test_pga_warm_start_periods(lt):
     assert sweeps[0] < 0.7 * sweeps[-1] and sweeps[1000] < 0.7 * sweeps[-1]
 
 
-@pytest.mark.parametrize("shape", [(101, 120, 6), (120, 101, 5), (9, 7, 5), (64, 64, 3)])
+@pytest.mark.parametrize("shape", [(101, 120, 6), (120, 101, 5), (9, 7, 5), (64, 64, 3), (2, 5, 4), (3, 3, 2)])
 def test_pga_warm_start_shapes(lt, shape):
     """Warm start on factors with odd n (a zero padding column), n not a multiple
-    of 4 (padding rows between the factor's rows and the rotations'), a small
-    slice, and n = 64: 80 iterations against the oracle."""
+    of 4 (padding rows between the factor's rows and the rotations'), small
+    slices down to n = 2 (one pair, no exchange), and n = 64: 80 iterations
+    against the oracle."""
     p = wl.make_problem(shape, 3, 0.5, seed=sum(shape))
     p.schedule = dict(wl.pga_schedule_params(p.M, p.mask))
     assert lt.pga_warm(p.shape, p.kinds)
