@@ -39,7 +39,7 @@ PEAK_HBM = 8.0e12
 # in the same run (fetch x2.0, write x1.0), warm launches; the command lines and
 # raw figures are in profiles/.  Reported only for that configuration and this
 # kernel version (null elsewhere).
-JACOBI_WARM_TRAFFIC_VIDEO_BYTES = None   # to be retaken: the kernel changed since the last passes
+JACOBI_WARM_TRAFFIC_VIDEO_BYTES = 42333651
 
 
 def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):
