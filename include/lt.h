@@ -246,9 +246,14 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
  * of every frontal slice of every problem (one launch over a longest-first work
  * list; small slices of one problem are packed several per workgroup), the
  * rank-r rebuild (one launch), inverse L with the stopping norms (one grouped
- * launch), tick end (stopping rule evaluated on the device).  A problem's whole
- * state (iterates, scalars, counters) lives in its own workspace, so problems
- * can join or leave between ticks by building a new batch. */
+ * launch), tick end (stopping rule evaluated on the device).  The slices of
+ * problems that lt_complete_pga would warm-start (lt_svd_opts.warm_restart,
+ * lt_pga_warm) take the warm-started Jacobi instead, one slice per workgroup
+ * (plus one launch forming L Z per slice before it, and one Jacobi launch per
+ * kernel configuration), cold every warm_restart iterations of the problem.
+ * A problem's whole state (iterates, scalars, counters, accumulated rotations)
+ * lives in its own workspace, so problems can join or leave between ticks by
+ * building a new batch. */
 typedef struct {
   const lt_desc* desc;   /* shape and transform (host, read during lt_problem_init) */
   const float* M;        /* device, observed tensor */
