@@ -1080,9 +1080,15 @@ __device__ __attribute__((always_inline)) inline void warm_product_body(const fl
   for (int c0 = 0; c0 < n; c0 += cb) {
     const int nc = n - c0 < cb ? n - c0 : cb;
     __syncthreads();   // L staged / the previous block of Z no longer read
-    for (int e = threadIdx.x; e < cb * n; e += blockDim.x) {
-      const int cc = e / n, k = e - cc * n;   // coalesced along Z's columns
-      Zt[k * cb + cc] = cc < nc ? Zg[(long long)(c0 + cc) * n + k] : 0.f;
+    // consecutive threads take consecutive columns (the transposed LDS stores
+    // then hit consecutive banks), each 4 consecutive rows of its column
+    const int n4 = (n + 3) / 4;
+    for (int e = threadIdx.x; e < cb * n4; e += blockDim.x) {
+      const int cc = e % cb, k0 = 4 * (e / cb);
+      const float* zc = Zg + (long long)(c0 + cc) * n;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (k0 + i < n) Zt[(k0 + i) * cb + cc] = cc < nc ? zc[k0 + i] : 0.f;
     }
     __syncthreads();
     const int nc4 = (nc + 3) / 4;
