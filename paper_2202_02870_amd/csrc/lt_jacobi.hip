@@ -1096,6 +1096,7 @@ __device__ __attribute__((always_inline)) inline void warm_product_body(const fl
       const int cg = e / nr4, r0 = 4 * (e - cg * nr4);
       const int kend = r0 + 4 < n ? r0 + 4 : n;   // L(row, k) = 0 for k > row
       float acc[4][4] = {};
+#pragma unroll 4
       for (int k = 0; k < kend; ++k) {
         const float4 lv = *reinterpret_cast<const float4*>(Ls + (size_t)k * npad + r0);
         const float4 zv = *reinterpret_cast<const float4*>(Zt + (size_t)k * cb + 4 * cg);
