@@ -39,7 +39,7 @@ PEAK_HBM = 8.0e12
 # in the same run (fetch x2.0, write x1.0), warm launches; the command lines and
 # raw figures are in profiles/.  Reported only for that configuration and this
 # kernel version (null elsewhere).
-JACOBI_WARM_TRAFFIC_VIDEO_BYTES = 42333651
+JACOBI_WARM_TRAFFIC_VIDEO_BYTES = 42332974
 
 
 def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):
@@ -100,7 +100,7 @@ def main():
                     help="run the Jacobi SVD on the slices themselves (no Cholesky-QR factor)")
     ap.add_argument("--warm-restart", type=int, default=0,
                     help="video/large/big: cold Jacobi start every this many iterations "
-                         "(0: the library default, 64; -1: every iteration, no warm start)")
+                         "(0: the library default, 256; -1: every iteration, no warm start)")
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()

@@ -99,7 +99,7 @@ typedef struct {
                            L Z, Z the rotations accumulated since the last cold start
                            (Z = I), which its columns leave nearly orthogonal (fewer
                            sweeps, same result to the Jacobi tolerance).  0: a cold start
-                           every 64 iterations; k > 0: every k; < 0: every iteration (no
+                           every 256 iterations; k > 0: every k; < 0: every iteration (no
                            warm start).  Ignored by the other entry points. */
 } lt_svd_opts;
 

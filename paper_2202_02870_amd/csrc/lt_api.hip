@@ -465,7 +465,7 @@ int dft_prepare(lt_handle* h, const Shape& s, const SvtWs& w) {
 // Warm start of the completion's SVT (real transforms, preconditioned slices
 // on the register-resident kernel): per slice the rotations Z (n x n)
 // accumulated since the last cold start.
-constexpr int kWarmRestartDefault = 64;
+constexpr int kWarmRestartDefault = 256;
 
 bool warm_shape(const Shape& s) {
   if (s.any_dft) return false;

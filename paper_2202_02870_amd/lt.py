@@ -220,7 +220,7 @@ def _workspace(nbytes, ws):
 
 
 def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True, warm_restart=0):
-    """warm_restart (completion only): 0 a cold Jacobi start every 64 iterations,
+    """warm_restart (completion only): 0 a cold Jacobi start every 256 iterations,
     k > 0 every k, < 0 every iteration (no warm start)."""
     return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, int(warm_restart))
 
