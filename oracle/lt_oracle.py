@@ -67,11 +67,6 @@ def cprod_matrix(n):
     return np.linalg.inv(W) @ C @ (np.eye(n) + Z)
 
 
-def upshift(n):
-    """Z_n: ones on the first superdiagonal (Section 2)."""
-    return np.diag(np.ones(n - 1), 1)
-
-
 # ---------------------------------------------------------------------------
 # Mode products, slices, transform L (Section 2 eq. (3); Section 3.2)
 # ---------------------------------------------------------------------------
@@ -290,10 +285,31 @@ def multirank(A, mats, rtol=1e-10):
     return rho, rho.mean()
 
 
-def nuclear_norm(A, mats, alpha=1.0):
-    """Tensor nuclear norm (Theorem 21, eq. (24)): (1/alpha) sum_p sum_i
-    sigma_i(L(A)^p)."""
-    return singular_values(A, mats).sum() / alpha
+def transform_alpha(mats):
+    """alpha of Section 3.2 for L = x_3 M_3 ... x_N M_N with M_i = alpha_i R_i,
+    R_i unitary.  Reading: alpha = prod alpha_i^2, the factor with
+    ||L(A)||_F^2 = alpha ||A||_F^2 (the printed alpha = prod alpha_i would not
+    give the norm relation the section states); alpha_i^2 is read off
+    M_i M_i^H = alpha_i^2 I.  Orthonormal DCT: 1; DFT of size n: n.  Raises
+    ValueError for a matrix that is not a scaled unitary (the c-product's
+    W^{-1} C (I + Z)), for which the section's norm relations do not hold."""
+    alpha = 1.0
+    for M in mats:
+        if M is None:
+            continue
+        G = M @ M.conj().T
+        a2 = float(np.real(np.trace(G))) / M.shape[0]
+        if np.abs(G - a2 * np.eye(M.shape[0])).max() > 1e-10 * a2:
+            raise ValueError("mode matrix is not a scaled unitary")
+        alpha *= a2
+    return alpha
+
+
+def nuclear_norm(A, mats):
+    """Tensor nuclear norm (Theorem 21, eq. (24)): (1/alpha) times the sum of
+    the singular values of every transform-domain slice L(A)^p, alpha as in
+    `transform_alpha`."""
+    return singular_values(A, mats).sum() / transform_alpha(mats)
 
 
 def fro(X):
