@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--warm-restart", type=int, default=0,
                     help="video/large/big: cold Jacobi start every this many iterations "
                          "(0: the library default, 256; -1: every iteration, no warm start)")
+    ap.add_argument("--fp32-dots", action="store_true",
+                    help="FP32 pair dot products in the Jacobi (default: FP64)")
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
@@ -140,7 +142,7 @@ def main():
     def params(iters):
         return lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=iters,
                              precision=args.precision, precondition=not args.no_precondition,
-                             warm_restart=args.warm_restart)
+                             warm_restart=args.warm_restart, fp32_dots=args.fp32_dots)
 
     # warmup (untimed)
     if args.warmup > 0:

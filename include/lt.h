@@ -57,7 +57,8 @@ extern "C" {
 /* ---- transform kinds (one per trailing mode) ----------------------------- */
 typedef enum {
   LT_DCT = 0,       /* orthonormal DCT-II C_n (Section 2; the transform of TNN-PGA-C) */
-  LT_DFT = 1,       /* Fourier matrix F_n (Section 2); complex -- not run on the GPU */
+  LT_DFT = 1,       /* Fourier matrix F_n (Section 2); complex transform-domain slices, taken by
+                       lt_svt_prox and lt_complete_pga (FP32 transforms) */
   LT_IDENTITY = 2,  /* M_i = I (mode i not transformed) */
   LT_CUSTOM = 3     /* caller-given invertible M_i (e.g. the c-product W^{-1} C (I+Z)) */
 } lt_mode_kind;
@@ -71,7 +72,9 @@ typedef enum {
 
 /* Operations, for lt_workspace_bytes. */
 typedef enum { LT_OP_LPRODUCT = 0, LT_OP_LSVD = 1, LT_OP_SVT = 2, LT_OP_PGA = 3,
-               LT_OP_TRUNCATE = 4 } lt_op;
+               LT_OP_TRUNCATE = 4, LT_OP_LSVD_FULL = 5 } lt_op;
+/* LT_OP_LSVD: lt_lsvd with economy != 0 and lt_multirank; LT_OP_LSVD_FULL:
+ * lt_lsvd with economy == 0. */
 
 /* Tensor shape and transform.  Host struct, read during the call only. */
 typedef struct {
@@ -101,6 +104,12 @@ typedef struct {
                            sweeps, same result to the Jacobi tolerance).  0: a cold start
                            every 256 iterations; k > 0: every k; < 0: every iteration (no
                            warm start).  Ignored by the other entry points. */
+  int32_t fp32_dots;    /* 0 (default): the column-pair dot products that decide each rotation
+                           are formed in FP64 (exact products of the FP32 columns, FP64 sums),
+                           as are the column norms and the rotation angle; the columns are
+                           rotated in FP32.  Nonzero: the pair dot products use FP32 products
+                           and per-lane FP32 sums (FP64 across lanes) -- faster, with a
+                           rounding error of the order of a 1e-6 tolerance. */
 } lt_svd_opts;
 
 /* Largest min(I1, I2) the preconditioned SVT path takes (the per-slice FP64
@@ -147,6 +156,11 @@ typedef struct {
   int64_t total_sweeps;   /* Jacobi sweeps summed over all slices and iterations */
   int64_t total_slices;   /* slice SVDs performed (iters x P) */
   int64_t total_rotations; /* column-pair rotations applied, summed likewise */
+  double nuclear_norm;    /* tensor nuclear norm of the returned iterate (Theorem 21, eq. (24)):
+                             (1/alpha) x the sum of the singular values of its transform-domain
+                             slices, here the last prox's sigma_i - mu_k over the kept ones
+                             (alpha = 1 for DCT and identity modes, x I_i per Fourier mode);
+                             NaN with custom mode matrices or before any iteration */
 } lt_pga_report;
 
 /* Kernel timing, recorded with HIP events on the handle's stream around every
@@ -189,15 +203,34 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
 int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b,
                 const float* B, float* C, int precision, void* ws, size_t ws_bytes);
 
-/* *_L-SVD (Alg. 3), economy size: with n = min(I1, I2),
- *   U: I1 x n x I3..IN, S: n x n x I3..IN, V: I2 x n x I3..IN,
- * such that A = U *_L S *_L V^T.  Transform-domain singular values of every
- * slice are sorted in descending order.  transform_domain != 0 returns L(U),
- * L(S), L(V) (the per-slice factors) instead.  sigma (may be NULL): P x n
- * float array of transform-domain singular values, slice-major. */
+/* *_L-SVD (Alg. 3): A = U *_L S *_L V^T with L(U)^p, L(V)^p orthogonal and
+ * L(S)^p diagonal for every slice p (Section 3.2).
+ *   economy == 0: Alg. 3's shapes, U: I1 x I1 x I3..IN, S: I1 x I2 x I3..IN,
+ *     V: I2 x I2 x I3..IN; the factor of the longer side is the economy one
+ *     completed by an orthonormal basis of the complement of its columns (any
+ *     basis is valid: the extra columns meet zero rows of S).  Workspace:
+ *     lt_workspace_bytes(a, NULL, LT_OP_LSVD_FULL, prec).
+ *   economy != 0: with n = min(I1, I2), U: I1 x n x ..., S: n x n x ...,
+ *     V: I2 x n x ....  Workspace: LT_OP_LSVD.
+ * Transform-domain singular values of every slice are sorted in descending
+ * order; singular vectors of zero singular values are some orthonormal
+ * completion.  transform_domain != 0 returns L(U), L(S), L(V) (the per-slice
+ * factors) instead.  sigma (may be NULL): P x n float array of
+ * transform-domain singular values, slice-major.  Slices up to
+ * min(I1, I2) <= 256 and max(I1, I2) <= 2048 (LT_ERR_SHAPE beyond); real
+ * transforms (LT_ERR_UNSUPPORTED for Fourier modes). */
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
-            float* V, float* sigma, int transform_domain, const lt_svd_opts* opts,
+            float* V, float* sigma, int economy, int transform_domain, const lt_svd_opts* opts,
             void* ws, size_t ws_bytes);
+
+/* Multirank of A (Section 3.2: rank of every transform-domain slice L(A)^p),
+ * counting singular values above rtol times the largest singular value of all
+ * slices: rank (device, P int32) per slice; avg (host, may be NULL) their mean
+ * (the average rank), tubal (host, may be NULL) their maximum (the tubal
+ * rank).  Synchronises the stream when avg or tubal is requested.  Same slice
+ * limits as lt_lsvd; workspace lt_workspace_bytes(a, NULL, LT_OP_LSVD, prec). */
+int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, int32_t* rank,
+                 double* avg, int32_t* tubal, const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 
 /* A_k = U(:, 1:k) *_L S(1:k, 1:k) *_L V(:, 1:k)^T, the best approximation of A
  * by products X *_L Y with X of k lateral slices (Eckart-Young theorem,
@@ -228,6 +261,23 @@ int lt_pga_warm(const lt_desc* a, const lt_svd_opts* opts);
 int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
                 int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts,
                 void* ws, size_t ws_bytes);
+
+/* Batched SVT: D[i] = D_{tau[i]}(A[i]) (Alg. 4, Theorem 23) for n tensors of
+ * possibly different shapes and orders (real transforms), as one pass of the
+ * batch engine below: one grouped forward-transform launch over all tensors,
+ * the Jacobi SVDs of all their frontal slices in one launch per kernel family
+ * (register-resident items packed longest first, preconditioned ones, blocked
+ * ones), one rebuild launch and one grouped inverse-transform launch.  a, A,
+ * D: arrays of n descriptors (host) and device pointers; tau: host array,
+ * tau[i] >= 0; D[i] may alias A[i].  rank_out (host array of n device
+ * pointers, or NULL; entries may be NULL): per slice of tensor i, the number of
+ * singular values above tau[i].  Workspace: lt_svt_batched_workspace_bytes
+ * (same n, a, opts).  Set-up synchronises the stream (tables are uploaded); the
+ * SVT itself is then asynchronous.  Fourier modes: LT_ERR_UNSUPPORTED. */
+size_t lt_svt_batched_workspace_bytes(int n, const lt_desc* const* a, const lt_svd_opts* opts);
+int lt_svt_prox_batched(lt_handle* h, int n, const lt_desc* const* a, const float* const* A,
+                        const double* tau, float* const* D, int32_t* const* rank_out,
+                        const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 
 /* Completion by PGA (Alg. 5) from X^0 = X^1 = 0.  M: observed tensor; mask:
  * uint8 per entry, nonzero = observed (the set Omega of eq. (48)); X: output,

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblt.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["lt_api.hip", "lt_transform.hip", "lt_jacobi.hip", "lt_precond.hip"]
+SOURCES = ["lt_api.hip", "lt_transform.hip", "lt_jacobi.hip", "lt_precond.hip", "lt_factors.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -254,6 +254,8 @@ int gemm(lt_handle* h, const lt::GemmArgs& g, int prec, int pro, int epi, int cl
 
 void resolve_opts(const lt_svd_opts* o, double* tol, int* max_sweeps, int* prec) {
   *tol = (o && o->jacobi_tol > 0) ? o->jacobi_tol : 1e-6;
+  // the kernels take FP32 pair dot products when handed the tolerance negated
+  if (o && o->fp32_dots) *tol = -*tol;
   *max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
   *prec = o ? o->precision : LT_PREC_F32;
 }
@@ -285,6 +287,7 @@ struct SvtCore {
   int32_t* sweeps = nullptr;
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
+  double* nuc = nullptr;  // per slice: sum of (sigma_i - tau) over the kept singular values
 };
 
 // Fourier modes: the transform-domain slices are complex, in two planes (real
@@ -309,6 +312,7 @@ struct SvtWs {
   int32_t* sweeps = nullptr;
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
+  double* nuc = nullptr;  // per slice: sum of (sigma_i - tau) over the kept singular values
   DftWs dft;              // Fourier modes only
 };
 
@@ -417,6 +421,7 @@ void carve_svt_core(Carver& c, const Shape& s, SvtCore* w) {
   w->Bk = c.take<float>((size_t)s.nel);
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
+  w->nuc = c.take<double>((size_t)s.P);
   SvtPlan pp;
   if (svt_plan(s, true, &pp) && pp.precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
   const long long wf = blocked_work_floats(s);
@@ -434,11 +439,13 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
     w->sweeps = core.sweeps;
     w->C = core.C;
     w->work = core.work;
+    w->nuc = core.nuc;
     return;
   }
   w->Gh = c.take<float>(2 * (size_t)s.nel);   // real plane, then imaginary plane
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
+  w->nuc = c.take<double>((size_t)s.P);
   std::vector<int> rep, partner;
   dft_pairs(s, &rep, &partner);
   DftWs& d = w->dft;
@@ -488,6 +495,7 @@ struct PgaWs {
   float* Xb = nullptr;
   double* partials = nullptr;
   double* norms = nullptr;
+  double* nucsum = nullptr;
   unsigned long long* sweep_total = nullptr;
   unsigned long long* rot_total = nullptr;
   unsigned int* maxsweep_hits = nullptr;
@@ -504,6 +512,7 @@ void carve_pga(Carver& c, const Shape& s, int prec, PgaWs* w) {
   w->Xb = c.take<float>((size_t)s.nel);
   w->partials = c.take<double>(2 * (size_t)n_partials(s));
   w->norms = c.take<double>(2);
+  w->nucsum = c.take<double>(1);
   w->sweep_total = c.take<unsigned long long>(1);
   w->rot_total = c.take<unsigned long long>(1);
   w->maxsweep_hits = c.take<unsigned int>(1);
@@ -522,10 +531,17 @@ struct LsvdWs {
   double* sigma = nullptr;
   float *Uh = nullptr, *Sh = nullptr, *Vh = nullptr;
   int32_t* sweeps = nullptr;
+  // full factors (Alg. 3 shapes): U I1 x I1, S I1 x I2, V I2 x I2 per slice, and
+  // the Householder reflectors (FP64, m x n per slice) completing the longer side
+  float *Uf = nullptr, *Sf = nullptr, *Vf = nullptr;
+  double* H = nullptr;
+  double* beta = nullptr;
+  double* mr = nullptr;   // multirank: mean and maximum
 };
 
-void carve_lsvd(Carver& c, const Shape& s, int prec, LsvdWs* w) {
+void carve_lsvd(Carver& c, const Shape& s, int prec, LsvdWs* w, bool full = false) {
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  const long long m = s.I1 < s.I2 ? s.I2 : s.I1;
   carve_transform(c, s, prec, &w->t);
   w->Ah = c.take<float>((size_t)s.nel);
   w->cols = c.take<float>((size_t)s.nel);
@@ -534,6 +550,16 @@ void carve_lsvd(Carver& c, const Shape& s, int prec, LsvdWs* w) {
   w->Sh = c.take<float>((size_t)(s.P * n * n));
   w->Vh = c.take<float>((size_t)(s.P * s.I2 * n));
   w->sweeps = c.take<int32_t>((size_t)s.P);
+  w->mr = c.take<double>(2);
+  if (full) {
+    w->Uf = c.take<float>((size_t)(s.P * s.I1 * s.I1));
+    w->Sf = c.take<float>((size_t)(s.P * s.I1 * s.I2));
+    w->Vf = c.take<float>((size_t)(s.P * s.I2 * s.I2));
+    if (m > n) {
+      w->H = c.take<double>((size_t)(s.P * m * n));
+      w->beta = c.take<double>((size_t)(s.P * n));
+    }
+  }
 }
 
 int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
@@ -628,6 +654,7 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
       wa.sweep_total = sweep_total;
       wa.rot_total = rot_total;
       wa.hits = hits;
+      wa.nuc = w.nuc;
       wa.tau = tau;
       wa.tol = tol;
       wa.n = n;
@@ -658,6 +685,7 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   j.sweep_total = sweep_total;
   j.rot_total = rot_total;
   j.maxsweep_hits = hits;
+  j.nuc = w.nuc;
   {
     ProfScope ps(h, LT_PROF_JACOBI);
     if (blocked) HIP_TRY(h, lt::launch_jacobi_blk(j, bcfg, h->stream));
@@ -673,6 +701,7 @@ SvtCore core_of(const SvtWs& w) {
   c.sweeps = w.sweeps;
   c.C = w.C;
   c.work = w.work;
+  c.nuc = w.nuc;
   return c;
 }
 
@@ -698,7 +727,8 @@ int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol
   if (rc) return rc;
   ProfScope ps(h, LT_PROF_OTHER);
   HIP_TRY(h, lt::launch_dft_extract(d.E, d.rep, d.partner, d.npairs, (int)s.I1, (int)s.I2, Re, Im,
-                                    d.inner.rank, rank, d.inner.sweeps, sweeps, h->stream));
+                                    d.inner.rank, rank, d.inner.sweeps, sweeps, d.inner.nuc, w.nuc,
+                                    h->stream));
   return LT_OK;
 }
 
@@ -713,6 +743,19 @@ int check_dft(lt_handle* h, const Shape& s, int prec, bool op_supports) {
 }
 
 bool precond_requested(const lt_svd_opts* o) { return !(o && o->no_precondition); }
+
+// alpha of Section 3.2 (||L(A)||_F^2 = alpha ||A||_F^2) for the DCT, identity
+// and Fourier modes (alpha_i^2 = 1, 1 and I_i): the tensor nuclear norm of
+// Theorem 21 is the sum of the transform-domain singular values over alpha.
+// 0 when a custom mode matrix is present (not known to be a scaled unitary).
+double nuclear_alpha(const Shape& s) {
+  double a = 1.0;
+  for (int i = 0; i < s.nmodes; ++i) {
+    if (s.kind[i] == LT_CUSTOM) return 0.0;
+    if (s.kind[i] == LT_DFT) a *= (double)s.n[i];
+  }
+  return a;
+}
 
 // The SVT of this shape is supported: by the preconditioned path (any m, n up
 // to LT_PRECOND_MAX_N), by the register-resident Jacobi kernel on the slice
@@ -746,6 +789,7 @@ struct ProblemWs {
   float* Bk = nullptr;
   int32_t* rank = nullptr;
   int32_t* sweeps = nullptr;
+  double* nuc = nullptr;  // per slice: the last prox's sum of (sigma_i - mu_k)
   double* betas = nullptr;
   double* mus = nullptr;
   double* partials = nullptr;
@@ -778,6 +822,7 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool preco
   w->Bk = c.take<float>((size_t)s.nel);
   w->rank = c.take<int32_t>((size_t)s.P);
   w->sweeps = c.take<int32_t>((size_t)s.P);
+  w->nuc = c.take<double>((size_t)s.P + 1);   // + the sum for lt_problem_status
   w->betas = c.take<double>((size_t)max_iter);
   w->mus = c.take<double>((size_t)max_iter);
   w->n_partials = (int)n_partials(s);
@@ -1153,6 +1198,11 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
       carve_lsvd(c, s, precision, &w);
       break;
     }
+    case LT_OP_LSVD_FULL: {
+      LsvdWs w;
+      carve_lsvd(c, s, precision, &w, true);
+      break;
+    }
     case LT_OP_TRUNCATE: {
       LsvdWs w;
       carve_lsvd(c, s, precision, &w);
@@ -1259,30 +1309,14 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
               lt::EPI_PLAIN, LT_PROF_INVERSE);
 }
 
-int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, float* V,
-            float* sigma, int transform_domain, const lt_svd_opts* opts, void* ws,
-            size_t ws_bytes) {
-  if (!h) return LT_ERR_ARG;
-  Shape s;
-  int rc = parse(h, a, &s);
-  if (rc) return rc;
-  if (!A || !U || !S || !V) return fail(h, LT_ERR_ARG, "A, U, S or V is NULL");
-  double tol;
-  int max_sweeps, prec;
-  resolve_opts(opts, &tol, &max_sweeps, &prec);
-  if ((rc = check_prec(h, prec))) return rc;
-  if ((rc = check_dft(h, s, prec, false))) return rc;
+// Transform-domain singular values of every slice (the Jacobi in its
+// all-columns mode), unsorted, into w.sigma; w.Ah holds L(A) and w.cols the
+// final columns.
+int lsvd_core(lt_handle* h, const Shape& s, const float* A, int prec, double tol, int max_sweeps,
+              const LsvdWs& w) {
   lt::JacobiConfig cfg;
+  int rc;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
-  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
-  const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
-  if (n > 256 || mrows > 2048)
-    return fail(h, LT_ERR_SHAPE, "lsvd supports min(I1, I2) <= 256 and max(I1, I2) <= 2048");
-  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
-  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
-  Carver c(ws);
-  LsvdWs w;
-  carve_lsvd(c, s, prec, &w);
   if ((rc = build_transform(h, s, prec, w.t))) return rc;
   const int P = (int)s.P;
   if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
@@ -1302,10 +1336,74 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
   j.rank = nullptr;
   j.sweeps = w.sweeps;
   j.sigma = w.sigma;
+  ProfScope ps(h, LT_PROF_JACOBI);
+  HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+  return LT_OK;
+}
+
+int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, int32_t* rank, double* avg,
+                 int32_t* tubal, const lt_svd_opts* opts, void* ws, size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!A || !rank) return fail(h, LT_ERR_ARG, "A or rank is NULL");
+  if (!(rtol >= 0.0) || !isfinite(rtol)) return fail(h, LT_ERR_ARG, "rtol must be finite and >= 0");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, false))) return rc;
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
+  if (n > 256 || mrows > 2048)
+    return fail(h, LT_ERR_SHAPE, "multirank supports min(I1, I2) <= 256 and max(I1, I2) <= 2048");
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdWs w;
+  carve_lsvd(c, s, prec, &w);
+  if ((rc = lsvd_core(h, s, A, prec, tol, max_sweeps, w))) return rc;
   {
-    ProfScope ps(h, LT_PROF_JACOBI);
-    HIP_TRY(h, lt::launch_jacobi(j, cfg, h->stream));
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_multirank(w.sigma, (int)s.P, (int)n, rtol, rank, w.mr, h->stream));
   }
+  if (avg || tubal) {
+    HIP_TRY(h, hipMemcpyAsync(h->pinned, w.mr, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (avg) *avg = h->pinned[0];
+    if (tubal) *tubal = (int32_t)h->pinned[1];
+  }
+  return LT_OK;
+}
+
+int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, float* V,
+            float* sigma, int economy, int transform_domain, const lt_svd_opts* opts, void* ws,
+            size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  Shape s;
+  int rc = parse(h, a, &s);
+  if (rc) return rc;
+  if (!A || !U || !S || !V) return fail(h, LT_ERR_ARG, "A, U, S or V is NULL");
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  if ((rc = check_prec(h, prec))) return rc;
+  if ((rc = check_dft(h, s, prec, false))) return rc;
+  lt::JacobiConfig cfg;
+  if ((rc = jacobi_config(h, s, &cfg))) return rc;
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
+  if (n > 256 || mrows > 2048)
+    return fail(h, LT_ERR_SHAPE, "lsvd supports min(I1, I2) <= 256 and max(I1, I2) <= 2048");
+  const bool full = economy == 0;
+  const size_t need = lt_workspace_bytes(a, nullptr, full ? LT_OP_LSVD_FULL : LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdWs w;
+  carve_lsvd(c, s, prec, &w, full);
+  if ((rc = lsvd_core(h, s, A, prec, tol, max_sweeps, w))) return rc;
+  const int P = (int)s.P;
   lt::LsvdArgs f{};
   f.W = w.Ah;
   f.cols = w.cols;
@@ -1314,13 +1412,42 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
   f.I1 = (int)s.I1;
   f.I2 = (int)s.I2;
   f.nslices = P;
-  f.U = transform_domain ? U : w.Uh;
-  f.S = transform_domain ? S : w.Sh;
-  f.V = transform_domain ? V : w.Vh;
+  const bool direct = transform_domain && !full;   // economy factors straight into the outputs
+  f.U = direct ? U : w.Uh;
+  f.S = direct ? S : w.Sh;
+  f.V = direct ? V : w.Vh;
   f.sig_out = sigma;
   {
     ProfScope ps(h, LT_PROF_OTHER);
     HIP_TRY(h, lt::launch_lsvd_finalize(f, h->stream));
+  }
+  if (full) {
+    // Alg. 3's shapes: the economy factors padded, the longer side's factor
+    // completed to an orthonormal basis, S padded with zeros
+    const int I1 = (int)s.I1, I2 = (int)s.I2, nn = (int)n;
+    float* Uf = transform_domain ? U : w.Uf;
+    float* Sf = transform_domain ? S : w.Sf;
+    float* Vf = transform_domain ? V : w.Vf;
+    {
+      ProfScope ps(h, LT_PROF_OTHER);
+      HIP_TRY(h, lt::launch_pad_copy(w.Uh, Uf, I1, nn, I1, I1, P, h->stream));
+      HIP_TRY(h, lt::launch_pad_copy(w.Sh, Sf, nn, nn, I1, I2, P, h->stream));
+      HIP_TRY(h, lt::launch_pad_copy(w.Vh, Vf, I2, nn, I2, I2, P, h->stream));
+      if (I1 > nn) HIP_TRY(h, lt::launch_complete_basis(Uf, w.H, w.beta, I1, nn, P, h->stream));
+      if (I2 > nn) HIP_TRY(h, lt::launch_complete_basis(Vf, w.H, w.beta, I2, nn, P, h->stream));
+    }
+    if (!transform_domain) {
+      if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * s.I1, Uf, U), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                     LT_PROF_INVERSE)))
+        return rc;
+      if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * s.I2, Sf, S), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                     LT_PROF_INVERSE)))
+        return rc;
+      if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I2 * s.I2, Vf, V), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                     LT_PROF_INVERSE)))
+        return rc;
+    }
+    return LT_OK;
   }
   if (!transform_domain) {
     if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * n, w.Uh, U), prec, lt::PRO_PLAIN,
@@ -1525,6 +1652,14 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     }
   }
   if (Xcur != X) HIP_TRY(h, hipMemcpyAsync(X, Xcur, bytes, hipMemcpyDeviceToDevice, st));
+  // nuclear norm of the last iterate (Theorem 21): its transform-domain
+  // singular values are the last prox's sigma_i - mu_k
+  const double alpha = nuclear_alpha(s);
+  if (alpha > 0) {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_sum_scaled(w.svt.nuc, (int)s.P, 1.0 / alpha, w.nucsum, st));
+    HIP_TRY(h, hipMemcpyAsync(h->pinned + 5, w.nucsum, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   HIP_TRY(h, hipMemcpyAsync(h->pinned, w.norms, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(h, hipMemcpyAsync(h->pinned + 2, w.sweep_total, sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, st));
@@ -1551,6 +1686,7 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     // slice SVDs performed: one per conjugate pair under Fourier modes
     rep->total_slices = (int64_t)iters * (s.any_dft ? w.svt.dft.npairs : s.P);
     rep->total_rotations = (int64_t)rots;
+    rep->nuclear_norm = alpha > 0 ? h->pinned[5] : NAN;
   }
   if (p->tol > 0 && !converged) return LT_WARN_NOT_CONVERGED;
   if (hits) return LT_WARN_MAXSWEEPS;
@@ -1568,13 +1704,20 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   return c.off + 256;
 }
 
-int lt_problem_init(lt_handle* h, const lt_problem* p) {
+}  // extern "C"
+
+namespace {
+
+// Device record and schedule of one batch problem.  svt_only: a single SVT
+// D = D_tau(M) as one tick (mask NULL: every entry observed, so the forward
+// pass reads M; X^k = X^{k-1} = X, the output; threshold tau, momentum 0).
+int init_problem(lt_handle* h, const lt_problem* p, bool svt_only, double tau) {
   if (!h || !p) return LT_ERR_ARG;
   Shape s;
   int rc = parse(h, p->desc, &s);
   if (rc) return rc;
-  if (!p->M || !p->mask || !p->X) return fail(h, LT_ERR_ARG, "M, mask or X is NULL");
-  if ((rc = check_pga_params(h, &p->params))) return rc;
+  if (!p->M || (!p->mask && !svt_only) || !p->X) return fail(h, LT_ERR_ARG, "M, mask or X is NULL");
+  if (!svt_only && (rc = check_pga_params(h, &p->params))) return rc;
   double tol;
   int max_sweeps, prec;
   resolve_opts(&p->params.svd, &tol, &max_sweeps, &prec);
@@ -1602,20 +1745,29 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   const int wp = problem_warm_period(s, &p->params);
   carve_problem(c, s, prec, p->params.max_iter, pc, wp > 0, &w);
   hipStream_t st = h->stream;
-  HIP_TRY(h, lt::launch_fill_zero(w.scratch, 16, st));
-  HIP_TRY(h, lt::launch_count_nonfinite(p->M, p->mask, s.nel, w.scratch, st));
-  HIP_TRY(h, hipMemcpyAsync(h->pinned, w.scratch, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(h, hipStreamSynchronize(st));
-  if (*reinterpret_cast<unsigned int*>(h->pinned) != 0)
-    return fail(h, LT_ERR_NONFINITE, "%u non-finite observed entries in M",
-                *reinterpret_cast<unsigned int*>(h->pinned));
+  if (!svt_only) {
+    HIP_TRY(h, lt::launch_fill_zero(w.scratch, 16, st));
+    HIP_TRY(h, lt::launch_count_nonfinite(p->M, p->mask, s.nel, w.scratch, st));
+    HIP_TRY(h, hipMemcpyAsync(h->pinned, w.scratch, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    if (*reinterpret_cast<unsigned int*>(h->pinned) != 0)
+      return fail(h, LT_ERR_NONFINITE, "%u non-finite observed entries in M",
+                  *reinterpret_cast<unsigned int*>(h->pinned));
+  }
   if ((rc = build_transform(h, s, prec, w.t))) return rc;
   std::vector<double> betas, mus;
-  pga_schedule(&p->params, betas, mus);
+  if (svt_only) {
+    betas.assign(1, 0.0);
+    mus.assign(1, tau);
+  } else {
+    pga_schedule(&p->params, betas, mus);
+  }
   HIP_TRY(h, hipMemcpyAsync(w.betas, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice, st));
   HIP_TRY(h, hipMemcpyAsync(w.mus, mus.data(), mus.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  HIP_TRY(h, lt::launch_fill_zero(p->X, (size_t)s.nel * sizeof(float), st));
-  HIP_TRY(h, lt::launch_fill_zero(w.Xb, (size_t)s.nel * sizeof(float), st));
+  if (!svt_only) {
+    HIP_TRY(h, lt::launch_fill_zero(p->X, (size_t)s.nel * sizeof(float), st));
+    HIP_TRY(h, lt::launch_fill_zero(w.Xb, (size_t)s.nel * sizeof(float), st));
+  }
   lt::ProbDev d{};
   d.I1 = (int)s.I1;
   d.I2 = (int)s.I2;
@@ -1625,11 +1777,12 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   d.M = p->M;
   d.mask = p->mask;
   d.Xa = p->X;
-  d.Xb = w.Xb;
+  d.Xb = svt_only ? p->X : w.Xb;
   d.Gh = w.Gh;
   d.Bk = w.Bk;
   d.rank = w.rank;
   d.sweeps = w.sweeps;
+  d.nuc = w.nuc;
   d.K = w.t.K;
   d.Kinv = w.t.Kinv;
   d.Khi = w.t.Khi;
@@ -1663,6 +1816,12 @@ int lt_problem_init(lt_handle* h, const lt_problem* p) {
   HIP_TRY(h, hipStreamSynchronize(st));   // host vectors and d go out of scope
   return LT_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int lt_problem_init(lt_handle* h, const lt_problem* p) { return init_problem(h, p, false, 0.0); }
 
 int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int32_t* done) {
   if (!h || !p) return LT_ERR_ARG;
@@ -1702,6 +1861,14 @@ int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int
     rep->total_sweeps = (int64_t)d.sweep_total;
     rep->total_slices = (int64_t)d.iter * s.P;
     rep->total_rotations = (int64_t)d.rot_total;
+    rep->nuclear_norm = NAN;
+    const double alpha = nuclear_alpha(s);
+    if (d.iter > 0 && alpha > 0) {
+      HIP_TRY(h, lt::launch_sum_scaled(w.nuc, (int)s.P, 1.0 / alpha, w.nuc + s.P, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(h->pinned, w.nuc + s.P, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+      rep->nuclear_norm = h->pinned[0];
+    }
   }
   return LT_OK;
 }
@@ -1886,6 +2053,119 @@ int lt_batch_destroy(lt_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
+  return LT_OK;
+}
+
+// ---- batched SVT: D_i = D_{tau_i}(A_i) for n tensors through one batch tick ----
+// Each tensor is a one-iteration problem of the batch engine (every entry
+// observed, threshold tau_i, no momentum), so the forward transforms of all
+// tensors run as one grouped GEMM, the Jacobi SVDs of all their slices as one
+// launch per kernel family, then one rebuild and one grouped inverse GEMM.
+
+}  // extern "C"
+
+namespace {
+
+void svt_batch_problem(const lt_desc* d, const float* A, float* D, double tau, const lt_svd_opts* o,
+                       lt_problem* p) {
+  memset(p, 0, sizeof(*p));
+  p->desc = d;
+  p->M = A;
+  p->mask = nullptr;
+  p->X = D;
+  p->params.mu0 = tau;
+  p->params.nu = 1.0;
+  p->params.mu_bar = tau;
+  p->params.max_iter = 1;
+  p->params.check_every = 1;
+  p->params.fixed_mu = 1;
+  if (o) p->params.svd = *o;
+  p->params.svd.warm_restart = -1;   // a single SVT: no rotations to carry
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+size_t lt_svt_batched_workspace_bytes(int n, const lt_desc* const* a, const lt_svd_opts* opts) {
+  if (n <= 0 || !a) return 0;
+  std::vector<lt_problem> probs((size_t)n);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    svt_batch_problem(a[i], nullptr, nullptr, 1.0, opts, &probs[i]);
+    const size_t b = lt_problem_workspace_bytes(a[i], &probs[i].params);
+    if (b == 0) return 0;
+    total += align256(b);
+  }
+  const size_t tb = lt_batch_workspace_bytes(n, probs.data());
+  if (tb == 0) return 0;
+  return total + align256(tb);
+}
+
+int lt_svt_prox_batched(lt_handle* h, int n, const lt_desc* const* a, const float* const* A, const double* tau,
+                        float* const* D, int32_t* const* rank_out, const lt_svd_opts* opts, void* ws,
+                        size_t ws_bytes) {
+  if (!h) return LT_ERR_ARG;
+  if (n <= 0 || !a || !A || !tau || !D) return fail(h, LT_ERR_ARG, "empty batch or NULL array");
+  for (int i = 0; i < n; ++i) {
+    if (!a[i] || !A[i] || !D[i]) return fail(h, LT_ERR_ARG, "tensor %d: NULL descriptor or pointer", i);
+    if (!(tau[i] >= 0.0) || !isfinite(tau[i])) return fail(h, LT_ERR_ARG, "tau[%d] must be finite and >= 0", i);
+    Shape s;
+    int rc = parse(h, a[i], &s);
+    if (rc) return rc;
+    if ((rc = check_dft(h, s, LT_PREC_F32, false))) return rc;
+  }
+  const size_t need = lt_svt_batched_workspace_bytes(n, a, opts);
+  if (need == 0) return fail(h, LT_ERR_SHAPE, "a tensor of the batch is not supported by the batch engine");
+  int rc = check_ws(h, ws, ws_bytes, need);
+  if (rc) return rc;
+  std::vector<lt_problem> probs((size_t)n);
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    svt_batch_problem(a[i], A[i], D[i], tau[i], opts, &probs[i]);
+    const size_t b = lt_problem_workspace_bytes(a[i], &probs[i].params);
+    probs[i].ws = base + off;
+    probs[i].ws_bytes = b;
+    off += align256(b);
+    if ((rc = init_problem(h, &probs[i], true, tau[i]))) return rc;
+  }
+  lt_batch b;
+  b.h = h;
+  b.n = n;
+  if ((rc = build_tables(h, n, probs.data(), 0, &b.T))) return rc;
+  Carver c(base + off);
+  carve_batch(c, b.T, &b.w);
+  hipStream_t st = h->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  const BatchTables& T = b.T;
+  hipError_t e = up(b.w.ptrs, T.ptrs.data(), T.ptrs.size() * sizeof(lt::ProbDev*));
+  if (e == hipSuccess) e = up(b.w.gemm, T.gemm.data(), T.gemm.size() * sizeof(lt::GemmTile));
+  if (e == hipSuccess) e = up(b.w.items, T.items.data(), T.items.size() * sizeof(lt::SvtItem));
+  if (e == hipSuccess) e = up(b.w.rebuild, T.rebuild.data(), T.rebuild.size() * sizeof(lt::RebuildTile));
+  if (e == hipSuccess) e = up(b.w.gram, T.gram.data(), T.gram.size() * sizeof(lt::GramTile));
+  if (e == hipSuccess) e = up(b.w.chol, T.chol.data(), T.chol.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess) e = up(b.w.cholg, T.cholg.data(), T.cholg.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess) e = up(b.w.blk, T.blk.data(), T.blk.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess)
+    e = up(b.w.rebuild_wide, T.rebuild_wide.data(), T.rebuild_wide.size() * sizeof(lt::RebuildTile));
+  if (e == hipSuccess) e = up(b.w.warm, T.warm.data(), T.warm.size() * sizeof(lt::CholItem));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host tables go out of scope
+  if (e == hipSuccess) e = enqueue_tick(&b, st, true);
+  if (e != hipSuccess) return fail(h, LT_ERR_HIP, "batched SVT launch failed: %s", hipGetErrorString(e));
+  for (int i = 0; rank_out && i < n; ++i) {
+    if (!rank_out[i]) continue;
+    Shape s;
+    (void)parse(h, a[i], &s);
+    Carver pc(probs[i].ws);
+    ProblemWs pw;
+    carve_problem(pc, s, T.prec, 1, problem_precond(s, &probs[i].params), false, &pw);
+    HIP_TRY(h, hipMemcpyAsync(rank_out[i], pw.rank, (size_t)s.P * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  }
   return LT_OK;
 }
 

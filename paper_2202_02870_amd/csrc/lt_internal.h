@@ -80,7 +80,10 @@ hipError_t launch_dft_embed(const float* Re, const float* Im, const int* rep, in
                             float* E, hipStream_t s);
 hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner, int npairs, int I1, int I2,
                               float* Re, float* Im, const int32_t* rankE, int32_t* rank,
-                              const int32_t* sweepsE, int32_t* sweeps, hipStream_t s);
+                              const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
+                              hipStream_t s);
+// out[0] = scale * (v[0] + ... + v[n-1]) in a fixed summation order (one workgroup).
+hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s);
 
 // C^p = A^p B^p for p < P; A^p: I1 x L (ld I1), B^p: L x I2 (ld L), C^p: I1 x I2.
 hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L,
@@ -111,6 +114,7 @@ struct JacobiArgs {
   unsigned long long* sweep_total;  // optional: atomic sum of sweeps
   unsigned long long* rot_total;    // optional: atomic sum of rotations
   unsigned int* maxsweep_hits;      // optional: atomic count of slices at max_sweeps
+  double* nuc;             // optional, SVT mode: [nslices] sum of (sigma_i - tau) over kept columns
   // blocked kernel only: per-slice working buffers (work_stride floats each) and
   // the block layout (set by launch_jacobi_blk)
   float* work;
@@ -145,6 +149,7 @@ struct WarmArgs {
   unsigned long long* sweep_total;
   unsigned long long* rot_total;
   unsigned int* hits;
+  double* nuc;             // optional: [nslices] sum of (sigma_i - tau) over kept columns
   double tau;
   double tol;
   int n;
@@ -228,6 +233,17 @@ struct LsvdArgs {
 };
 hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s);
 
+// Full factors and multirank (lt_factors.hip).  dst (rd x cd per slice) = src
+// (rs x cs per slice) padded with zeros; complete_basis fills columns n..m-1 of
+// each slice's m x m factor Q (first n columns orthonormal, m <= 2048) with an
+// orthonormal basis of their complement, H (P x m x n FP64) and beta (P x n)
+// being scratch; multirank counts sigma (P x n) above rtol * max sigma per
+// slice into rank and writes their mean and maximum to out[0], out[1].
+hipError_t launch_pad_copy(const float* src, float* dst, int rs, int cs, int rd, int cd, int P, hipStream_t s);
+hipError_t launch_complete_basis(float* Q, double* H, double* beta, int m, int n, int P, hipStream_t s);
+hipError_t launch_multirank(const double* sigma, int P, int n, double rtol, int32_t* rank, double* out,
+                            hipStream_t s);
+
 // ---- batched completion engine (many problems, one tick = one PGA iteration) --
 // Device-resident state of one problem.  Static fields are written once at
 // initialisation; the dynamic fields advance on the device every tick.
@@ -242,6 +258,7 @@ struct ProbDev {
   float* Bk;                 // kept columns of the Jacobi SVT
   int32_t* rank;
   int32_t* sweeps;
+  double* nuc;               // [P] per slice: sum of (sigma_i - mu_k) over the kept singular values
   const float* K;            // forward / inverse Kronecker transforms (FP32)
   const float* Kinv;
   const uint16_t *Khi, *Klo, *Kihi, *Kilo;   // bf16 splits

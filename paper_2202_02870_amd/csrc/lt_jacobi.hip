@@ -11,9 +11,9 @@
 // of G lanes; each lane keeps R rows of the slot's two columns in registers
 // (FP32), as R/4 chunks of 4 consecutive rows interleaved across the group
 // (chunk c of a column belongs to lane c mod G), so a group moves a column
-// through LDS as contiguous 16-byte pieces.  Column norms and rotation angles
-// are FP64; the pair dot products are FP64, or FP32 within a lane and FP64
-// across the group when the tolerance is 1e-6 or looser.
+// through LDS as contiguous 16-byte pieces.  Column norms, pair dot products
+// (exact FP32 x FP32 products summed in FP64) and rotation angles are FP64;
+// the columns are rotated in FP32.  FP32 pair dot products are an opt-in.
 //
 // Pair schedule (one sweep meets every column pair exactly once, in
 // 2*ceil(n/2) - 1 rounds).  The ceil(n/2) slots form one range of c slots; while
@@ -117,9 +117,10 @@ __device__ inline double dot64(const float (&x)[R], const float (&y)[R]) {
 }
 
 // The same dot product with FP32 products and two FP32 accumulators per lane
-// (interleaved rows); with the FP32 group sum the relative error is about
-// (rows per lane + log2 G) * 2^-24 of sum |x_i y_i|, below a 1e-6 orthogonality
-// test.
+// (interleaved rows), the opt-in FP32 form: with the FP32 group sum the error
+// bound is about (R/2 + 2 + log2 G) * 2^-24 of sum |x_i y_i| (about 2e-6 at 32
+// rows per lane and G = 8), the same order as a 1e-6 orthogonality test, so
+// near the tolerance the rotate-or-skip decision is decided by rounding.
 template <int R>
 __device__ inline float dot32x(const float (&x)[R], const float (&y)[R]) {
   float d0 = 0.f, d1 = 0.f;
@@ -141,6 +142,34 @@ __device__ inline double rcp64(double x) {
   double r = __builtin_amdgcn_rcp(x);
   const double e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+
+// The rotation that zeroes the off-diagonal entry of the 2 x 2 Gram matrix
+// [[pa, d], [d, pb]] of a column pair (d != 0), all in FP64:
+// zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) (the
+// smaller root of t^2 + 2 zeta t - 1 = 0, so |angle| <= pi/4),
+// c = 1 / sqrt(1 + t^2), s = c t.  c and s are then rounded to FP32, the
+// precision the columns are rotated in; t stays FP64 for the norm updates
+// pa - t d and pb + t d.  zeta is clamped so zeta^2 cannot overflow (t is then
+// below 1e-100 either way).
+__device__ inline void jacobi_angle(double d, double pa, double pb, double& t, float& cf, float& sf) {
+  const double zeta = fmin(fmax((pb - pa) * (0.5 * rcp64(d)), -1e100), 1e100);
+  const double az = fabs(zeta);
+  const double tt = rcp64(az + sqrt(fma(az, az, 1.0)));
+  t = zeta < 0.0 ? -tt : tt;
+  const double c = rcp64(sqrt(fma(tt, tt, 1.0)));
+  cf = (float)c;
+  sf = (float)(c * t);
+}
+
+// Pair dot-product precision travels with the Jacobi tolerance: a negative
+// tolerance asks for FP32 products and per-lane FP32 sums (an opt-in of the
+// library's svd options); decode_tol restores the magnitude and returns that
+// request.  The default is FP64 dot products of the FP32 columns.
+__device__ inline bool decode_tol(double& tol) {
+  const bool fp32 = tol < 0.0;
+  tol = fabs(tol);
+  return fp32;
 }
 
 // (x, y) <- (c x - s y, c y + s x) on every row: s y and s x rounded, then one
@@ -315,6 +344,7 @@ struct Job {
   unsigned long long* sweep_total;
   unsigned long long* rot_total;
   unsigned int* hits;
+  double* nuc;   // SVT: sum of (sigma_i - tau) over the kept columns (may be null)
 };
 
 template <int G, int R>
@@ -374,10 +404,9 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   int my_sweeps = 0;            // sweeps this slice needed (first sweep without rotations)
   bool converged = false;
   long long rotations = 0;
-  // Per-lane FP32 partial dot products (FP64 sum over the group) when the
-  // tolerance is above what FP32 rounding of the products could fake; FP64
-  // products otherwise.
-  const bool dot32 = tol >= 1e-6;
+  // pair dot products in FP64 (exact FP32 products, FP64 sums) unless the
+  // caller asked for FP32 ones (tolerance passed negated, see decode_tol)
+  const bool dot32 = decode_tol(tol);
   const double big2 = big_rotation2(tol);
   // single-exit loop (max_sweeps >= 1): the columns stay in one register set
   for (;;) {
@@ -400,7 +429,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
       // c = 1, s = 0 (the identity on finite values, up to the sign of a zero),
       // so the column registers are updated in place rather than merged lane by
       // lane after a divergent branch.
-      float cf = 1.f, sf = 0.f, t = 0.f;
+      float cf = 1.f, sf = 0.f;
+      double t = 0.0;
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
       if (moving) {
@@ -408,22 +438,7 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
         pa = fmax(na, 0.0);
         pb = fmax(nb, 0.0);
         rot = d != 0.0 && d * d > tol * tol * (pa * pb);   // |d| > tol sqrt(pa pb)
-        if (rot) {
-          // rotation that zeroes the off-diagonal of [[pa, d], [d, pb]]:
-          // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-          // c = 1 / sqrt(1 + t^2), s = c t.  zeta is formed in FP64 (a
-          // difference of FP64 norms) and clamped where t falls below FP32
-          // resolution; t, c and s are FP32, the precision the rotation is
-          // applied in.  Every multiply-add is an explicit fma, so the rounding
-          // does not depend on how the compiler contracts an instantiation.
-          const double zeta = (pb - pa) * (0.5 * rcp64(d));
-          const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
-          const float z2 = fmaf(zf, zf, 1.f);
-          const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
-          t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
-          cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-          sf = cf * t;
-        }
+        if (rot) jacobi_angle(d, pa, pb, t, cf, sf);
       }
       // (the in-place update with a wave-uniform skip, rotate_in_place, leaves
       // this out-of-line body's columns in registers the LDS exchange cannot
@@ -436,8 +451,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
         bv[e] = fmaf(cf, y, sx);
       }
       if (rot) {
-        na = fma(-(double)t, d, pa);
-        nb = fma((double)t, d, pb);
+        na = fma(-t, d, pa);
+        nb = fma(t, d, pb);
         my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
       }
       if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
@@ -533,16 +548,25 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
     kb = active && idb < n;
   }
   __syncthreads();
-  if (active && l == 0) ctl[3 + g] = (int)ka + (int)kb;
+  // per slot: kept count, and the slot's share of the slice's nuclear norm
+  // (the exchange buffer is free here), summed below in slot order
+  double* nucs = reinterpret_cast<double*>(bufA);
+  if (active && l == 0) {
+    ctl[3 + g] = (int)ka + (int)kb;
+    nucs[g] = (ka ? sa - jb.tau : 0.0) + (kb ? sb - jb.tau : 0.0);
+  }
   __syncthreads();
   if (active && t2 == 0) {
     int acc = 0;
+    double nsum = 0.0;
     for (int i = 0; i < npairs; ++i) {
       const int c = ctl[3 + i];
       ctl[3 + i] = acc;
       acc += c;
+      nsum += nucs[i];
     }
     ctl[2] = acc;
+    if (jb.mode == 0 && jb.nuc) jb.nuc[sub] = nsum;
   }
   __syncthreads();
   // kept columns, scaled, through LDS: tops, then bottoms
@@ -607,7 +631,8 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
     // rotation take c = 1, s = 0 (the identity on finite values, up to the sign
     // of a zero), so the column registers are updated in place rather than
     // merged lane by lane after a divergent branch.
-    float cf = 1.f, sf = 0.f, t = 0.f;
+    float cf = 1.f, sf = 0.f;
+      double t = 0.0;
     double d = 0.0, pa = 0.0, pb = 0.0;
     bool rot = false;
     if (moving) {
@@ -623,20 +648,14 @@ __device__ __attribute__((always_inline)) inline unsigned sweep_rounds(
         // resolution; t, c and s are FP32, the precision the rotation is
         // applied in.  Every multiply-add is an explicit fma, so the rounding
         // does not depend on how the compiler contracts an instantiation.
-        const double zeta = (pb - pa) * (0.5 * rcp64(d));
-        const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
-        const float z2 = fmaf(zf, zf, 1.f);
-        const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
-        t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
-        cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-        sf = cf * t;
+        jacobi_angle(d, pa, pb, t, cf, sf);
       }
     }
     // waves without a rotation skip the column update
     if (__builtin_amdgcn_ballot_w64(rot) != 0) rotate_in_place<R>(av, bv, cf, sf);
     if (rot) {
-      na = fma(-(double)t, d, pa);
-      nb = fma((double)t, d, pb);
+      na = fma(-t, d, pa);
+      nb = fma(t, d, pb);
       my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
     }
     if (k + 1 == nrounds) break;   // no exchange after the sweep's last round
@@ -725,6 +744,7 @@ struct BlkJob {
   unsigned long long* sweep_total;
   unsigned long long* rot_total;
   unsigned int* hits;
+  double* nuc;   // SVT: sum of (sigma_i - tau) over the kept columns (may be null)
 };
 
 // Columns c0 .. c0 + ncols - 1 of W into LDS columns 0 .. ncols - 1 (rows
@@ -830,7 +850,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
     av[e] = 0.f;
     bv[e] = 0.f;
   }
-  const bool dot32 = tol >= 1e-6;
+  const bool dot32 = decode_tol(tol);
   int sweep = 0, my_sweeps = 0;
   bool converged = false;
   long long rotations = 0;
@@ -876,12 +896,17 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
   // ---- output: b columns at a time, kept ones compacted in column order ----
   if (tid == 0) ctl[2] = 0;
   __syncthreads();
+  double nsum = 0.0;   // thread 0: nuclear-norm share, in column order
+  double* nucs = reinterpret_cast<double*>(buf);
   for (int c0 = 0; c0 < ncols; c0 += b) {
     const int id = c0 + g;
     if (active) load_work_col<G, R>(Wk, mpad, id, l, av, qeff);
     const double sa = sqrt(group_sum<G>(dot64<R>(av, av)));
     const bool ka = active && id < n && sa > jb.tau;
-    if (active && l == 0) ctl[3 + g] = ka ? 1 : 0;
+    if (active && l == 0) {
+      ctl[3 + g] = ka ? 1 : 0;
+      nucs[g] = ka ? sa - jb.tau : 0.0;
+    }
     __syncthreads();
     if (tid == 0) {
       int acc = ctl[2];
@@ -889,6 +914,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
         const int c = ctl[3 + i];
         ctl[3 + i] = acc;
         acc += c;
+        nsum += nucs[i];
       }
       ctl[2] = acc;
     }
@@ -902,6 +928,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_blk_body(const BlkJ
   }
   if (tid == 0) {
     if (jb.rank) *jb.rank = ctl[2];
+    if (jb.nuc) *jb.nuc = nsum;
     if (jb.sweeps) *jb.sweeps = my_sweeps;
     if (jb.sweep_total) atomicAdd(jb.sweep_total, (unsigned long long)my_sweeps);
     if (jb.rot_total) atomicAdd(jb.rot_total, (unsigned long long)rotations);
@@ -932,6 +959,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk(JacobiArgs a) {
   jb.sweep_total = a.sweep_total;
   jb.rot_total = a.rot_total;
   jb.hits = a.maxsweep_hits;
+  jb.nuc = a.nuc ? a.nuc + s : nullptr;
   jacobi_blk_body<G, R>(jb, a.tol, a.max_sweeps, smem);
 }
 
@@ -968,6 +996,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs
   jb.sweep_total = &pd->sweep_total;
   jb.rot_total = &pd->rot_total;
   jb.hits = &pd->maxsweep_hits;
+  jb.nuc = pd->nuc + it.slice;
   jacobi_blk_body<G, R>(jb, tol, max_sweeps, smem);
 }
 
@@ -994,6 +1023,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
   jb.sweep_total = a.sweep_total;
   jb.rot_total = a.rot_total;
   jb.hits = a.maxsweep_hits;
+  jb.nuc = a.nuc ? a.nuc + s : nullptr;
   jacobi_body<G, R>(jb, a.tol, a.max_sweeps, nbuf, ldw, smem);
 }
 
@@ -1034,6 +1064,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
   jb.sweep_total = &pd->sweep_total;
   jb.rot_total = &pd->rot_total;
   jb.hits = &pd->maxsweep_hits;
+  jb.nuc = pd->nuc + it.slice0;
   jacobi_body<G, R>(jb, tol, max_sweeps, nbuf, ldw, smem);
 }
 
@@ -1196,6 +1227,7 @@ struct WarmJob {
   unsigned long long* sweep_total;
   unsigned long long* rot_total;
   unsigned int* hits;
+  double* nuc;              // sum of (sigma_i - tau) over the kept columns (may be null)
   double tau, tol;
   int n, max_sweeps, cold;
 };
@@ -1258,8 +1290,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
   }
   __syncthreads();
 
-  const double tol = a.tol;
-  const bool dot32 = tol >= 1e-6;
+  double tol = a.tol;
+  const bool dot32 = decode_tol(tol);
   const double big2 = big_rotation2(tol);
   double na = 0.0, nb = 0.0;
   int sweep = 0, my_sweeps = 0;
@@ -1276,7 +1308,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
     for (int k = 0; k < nrounds; ++k) {
       // the rotation of the slot's pair, on the whole column (identity, c = 1
       // and s = 0, on lanes without one)
-      float cf = 1.f, sf = 0.f, t = 0.f;
+      float cf = 1.f, sf = 0.f;
+      double t = 0.0;
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
       if (active) {
@@ -1285,21 +1318,15 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
         pb = fmax(nb, 0.0);
         rot = d != 0.0 && d * d > tol * tol * (pa * pb);
         if (rot) {
-          const double zeta = (pb - pa) * (0.5 * rcp64(d));
-          const float zf = (float)fmin(fmax(zeta, -1e18), 1e18);
-          const float z2 = fmaf(zf, zf, 1.f);
-          const float qf = fmaf(z2, __builtin_amdgcn_rsqf(z2), fabsf(zf));
-          t = copysignf(__builtin_amdgcn_rcpf(qf), zf == 0.f ? 1.f : zf);
-          cf = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-          sf = cf * t;
+          jacobi_angle(d, pa, pb, t, cf, sf);
         }
       }
       // waves without a rotation skip the update (most of them in the late
       // sweeps of a warm start)
       if (__builtin_amdgcn_ballot_w64(rot) != 0) rotate_in_place<R>(av, bv, cf, sf);
       if (rot) {
-        na = fma(-(double)t, d, pa);
-        nb = fma((double)t, d, pb);
+        na = fma(-t, d, pa);
+        nb = fma(t, d, pb);
         my_rot += (l == 0) ? 1u + (d * d > big2 * (pa * pb) ? kBigOne : 0u) : 0u;
       }
       if (k + 1 == nrounds) break;
@@ -1389,16 +1416,24 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
   const double sa = sqrt(na), sb = sqrt(nb);
   const bool ka = active && ida < n && sa > a.tau;
   const bool kb = active && idb < n && sb > a.tau;
-  if (active && l == 0) ctl[3 + g] = (int)ka + (int)kb;
+  // the exchange buffer is free once the last sweep's barriers have passed
+  double* nucs = reinterpret_cast<double*>(bufA);
+  if (active && l == 0) {
+    ctl[3 + g] = (int)ka + (int)kb;
+    nucs[g] = (ka ? sa - a.tau : 0.0) + (kb ? sb - a.tau : 0.0);
+  }
   __syncthreads();
   if (active && t2 == 0) {
     int acc = 0;
+    double nsum = 0.0;
     for (int p = 0; p < npairs; ++p) {
       const int cnt = ctl[3 + p];
       ctl[3 + p] = acc;
       acc += cnt;
+      nsum += nucs[p];
     }
     ctl[2] = acc;
+    if (a.nuc) *a.nuc = nsum;
   }
   __syncthreads();
   float* out = a.out;
@@ -1437,6 +1472,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm(WarmArgs a, int nbuf, int ld
   j.sweep_total = a.sweep_total;
   j.rot_total = a.rot_total;
   j.hits = a.hits;
+  j.nuc = a.nuc ? a.nuc + s : nullptr;
   j.tau = a.tau;
   j.tol = a.tol;
   j.n = a.n;
@@ -1465,6 +1501,7 @@ __global__ __launch_bounds__(LB) void k_jacobi_warm_items(ProbDev* const* probs,
   j.sweep_total = &pd->sweep_total;
   j.rot_total = &pd->rot_total;
   j.hits = &pd->maxsweep_hits;
+  j.nuc = pd->nuc + it.slice;
   j.tau = pd->tau;
   j.tol = tol;
   j.n = n;

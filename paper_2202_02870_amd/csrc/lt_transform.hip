@@ -39,6 +39,7 @@ __device__ inline void block_sum2(double& s1, double& s2) {
 template <int PRO>
 __device__ inline float load_operand(const GemmArgs& a, long long g) {
   if (PRO == PRO_PLAIN) return a.B[g];
+  if (!a.mask) return a.M[g];                           // every entry observed: G = M
   const float x = a.X[g];
   const float y = x + a.beta * (x - a.Xp[g]);          // eq. (52)
   return a.mask[g] ? a.M[g] : y;                        // eq. (51), step 1/l_f = 1
@@ -396,13 +397,16 @@ __global__ void k_dft_embed(const float* __restrict__ Re, const float* __restric
 __global__ void k_dft_extract(const float* __restrict__ E, const int* rep, const int* partner, int I1,
                               int I2, long long N, float* __restrict__ Re, float* __restrict__ Im,
                               const int32_t* rankE, int32_t* rank, const int32_t* sweepsE,
-                              int32_t* sweeps) {
+                              int32_t* sweeps, const double* nucE, double* nuc) {
   const int t = blockIdx.y;
   const int p = rep[t], q = partner[t];
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e == 0) {
+    // the embedding holds every singular value of the complex slice twice; the
+    // partner slice (its conjugate) has the same ones
     if (rank) rank[p] = rank[q] = rankE[t] / 2;
     if (sweeps) sweeps[p] = sweeps[q] = sweepsE[t];
+    if (nuc) nuc[p] = nuc[q] = 0.5 * nucE[t];
   }
   if (e >= N) return;
   const int i = (int)(e % I1), j = (int)(e / I1);
@@ -416,6 +420,15 @@ __global__ void k_dft_extract(const float* __restrict__ E, const int* rep, const
     Re[(long long)q * N + e] = re;
     Im[(long long)q * N + e] = -im;
   }
+}
+
+// out = scale * sum of v[0..n): per-thread sums over a fixed stride, then the
+// fixed-order workgroup sum (the same bits on every call).
+__global__ __launch_bounds__(256) void k_sum_scaled(const double* v, int n, double scale, double* out) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += v[i];
+  block_sum2(a, b);
+  if (threadIdx.x == 0) *out = scale * a;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n, double* out) {
@@ -550,12 +563,18 @@ hipError_t launch_dft_embed(const float* Re, const float* Im, const int* rep, in
 
 hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner, int npairs, int I1, int I2,
                               float* Re, float* Im, const int32_t* rankE, int32_t* rank,
-                              const int32_t* sweepsE, int32_t* sweeps, hipStream_t s) {
+                              const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
+                              hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   const long long N = (long long)I1 * I2;
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)npairs);
   hipLaunchKernelGGL(k_dft_extract, grid, dim3(256), 0, s, E, rep, partner, I1, I2, N, Re, Im, rankE, rank,
-                     sweepsE, sweeps);
+                     sweepsE, sweeps, nuc ? nucE : nullptr, nuc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_scaled, dim3(1), dim3(256), 0, s, v, n, scale, out);
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE = -1,
 WARN_MAXSWEEPS, WARN_NOT_CONVERGED = 1, 2
 KIND = {"dct": 0, "dft": 1, "identity": 2, "custom": 3}
 PREC = {"f32": 0, "bf16x3": 1}
-OP = {"lproduct": 0, "lsvd": 1, "svt": 2, "pga": 3, "truncate": 4}
+OP = {"lproduct": 0, "lsvd": 1, "svt": 2, "pga": 3, "truncate": 4, "lsvd_full": 5}
 
 
 class Desc(ctypes.Structure):
@@ -38,7 +38,7 @@ class Desc(ctypes.Structure):
 class SvdOpts(ctypes.Structure):
     _fields_ = [("jacobi_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("no_precondition", ctypes.c_int32),
-                ("warm_restart", ctypes.c_int32)]
+                ("warm_restart", ctypes.c_int32), ("fp32_dots", ctypes.c_int32)]
 
 
 class PgaParams(ctypes.Structure):
@@ -52,7 +52,8 @@ class PgaReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("max_sweeps_hit", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("last_crit", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
-                ("total_slices", ctypes.c_int64), ("total_rotations", ctypes.c_int64)]
+                ("total_slices", ctypes.c_int64), ("total_rotations", ctypes.c_int64),
+                ("nuclear_norm", ctypes.c_double)]
 
 
 class ProblemC(ctypes.Structure):
@@ -81,8 +82,17 @@ _sig = {
     "lt_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Desc), ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_int]),
     "lt_lproduct": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.POINTER(Desc), _vp, _vp,
                                    ctypes.c_int, _vp, ctypes.c_size_t]),
-    "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+    "lt_lsvd": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int,
                                ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_multirank": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_svt_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Desc)),
+                                                         ctypes.POINTER(SvdOpts)]),
+    "lt_svt_prox_batched": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Desc)),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(SvdOpts),
+                                           _vp, ctypes.c_size_t]),
     "lt_svt_path": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
     "lt_pga_warm": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(SvdOpts)]),
     "lt_ltruncate": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_int32, _vp,
@@ -219,10 +229,13 @@ def _workspace(nbytes, ws):
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
 
-def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True, warm_restart=0):
+def svd_opts(jacobi_tol=0.0, max_sweeps=0, precision="f32", precondition=True, warm_restart=0,
+             fp32_dots=False):
     """warm_restart (completion only): 0 a cold Jacobi start every 256 iterations,
-    k > 0 every k, < 0 every iteration (no warm start)."""
-    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, int(warm_restart))
+    k > 0 every k, < 0 every iteration (no warm start).  fp32_dots: FP32 pair dot
+    products in the Jacobi (default FP64)."""
+    return SvdOpts(jacobi_tol, max_sweeps, PREC[precision], 0 if precondition else 1, int(warm_restart),
+                   1 if fp32_dots else 0)
 
 
 def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None):
@@ -241,15 +254,24 @@ def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", o
     return Ak
 
 
-def multirank(A, kinds=None, rtol=1e-5):
-    """Multirank (rank of every slice of L(A), counting singular values above
-    rtol times the largest of the tensor), its average, and the tubal rank
-    (the largest), from the transform-domain singular values of lsvd (slices
-    up to 256 columns, real transforms)."""
-    sigma = to_host(lsvd(A, kinds, transform_domain=True)[3]).astype(np.float64)
-    smax = float(sigma.max()) if sigma.size else 0.0
-    rho = (sigma > rtol * max(smax, 1e-300)).sum(axis=1)
-    return rho, float(rho.mean()), int(rho.max()) if rho.size else 0
+def multirank(A, kinds=None, rtol=1e-5, jacobi_tol=0.0, max_sweeps=0, precision="f32", ws=None):
+    """lt_multirank: the rank of every slice of L(A) (singular values above rtol
+    times the largest of the tensor) as an int32 CUDA tensor, the average rank
+    and the tubal rank (slices up to 256 columns, real transforms)."""
+    shape = tuple(A.shape)
+    _check_tensor(A, shape, name="A")
+    d = make_desc(shape, kinds)
+    P = int(np.prod(shape[2:])) if len(shape) > 2 else 1
+    rank = torch.empty(P, dtype=torch.int32, device="cuda")
+    nb = workspace_bytes(shape, kinds, "lsvd", precision)
+    w = _workspace(nb, ws)
+    h = _handle()
+    o = svd_opts(jacobi_tol, max_sweeps, precision)
+    avg = ctypes.c_double()
+    tubal = ctypes.c_int32()
+    _check(h, _lib.lt_multirank(h, ctypes.byref(d), _ptr(A), float(rtol), _ptr(rank), ctypes.byref(avg),
+                                ctypes.byref(tubal), ctypes.byref(o), _ptr(w), nb))
+    return rank, float(avg.value), int(tubal.value)
 
 
 def svt_path(shape, kinds=None, precondition=True):
@@ -276,7 +298,7 @@ def pga_warm(shape, kinds=None, precondition=True, warm_restart=0):
 
 
 def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", out=None, ws=None,
-             precondition=True):
+             precondition=True, fp32_dots=False):
     """D_tau(A) (Alg. 4).  Returns (D, rank[P] int32, sweeps[P] int32)."""
     shape = tuple(A.shape)
     _check_tensor(A, shape, name="A")
@@ -289,11 +311,44 @@ def svt_prox(A, tau, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", 
     nb = workspace_bytes(shape, kinds, "svt", precision)
     w = _workspace(nb, ws)
     h = _handle()
-    o = svd_opts(jacobi_tol, max_sweeps, precision, precondition)
+    o = svd_opts(jacobi_tol, max_sweeps, precision, precondition, fp32_dots=fp32_dots)
     st = _lib.lt_svt_prox(h, ctypes.byref(d), _ptr(A), float(tau), _ptr(D), _ptr(rank), _ptr(sweeps),
                           ctypes.byref(o), _ptr(w), nb)
     _check(h, st)
     return D, rank, sweeps
+
+
+def svt_prox_batched(As, taus, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", outs=None,
+                     precondition=True, fp32_dots=False):
+    """lt_svt_prox_batched: D_i = D_{tau_i}(A_i) for a list of column-major
+    tensors (shapes and orders may differ) in one pass of the batch engine.
+    kinds: None (DCT on every trailing mode) or one kinds tuple per tensor.
+    Returns (list of D_i, list of rank_i int32 tensors)."""
+    n = len(As)
+    if len(taus) != n:
+        raise ValueError("one tau per tensor")
+    kl = kinds if kinds is not None else [None] * n
+    descs = [make_desc(tuple(A.shape), k) for A, k in zip(As, kl)]
+    Ds = list(outs) if outs is not None else [fortran_empty(tuple(A.shape)) for A in As]
+    ranks = []
+    for A, D in zip(As, Ds):
+        _check_tensor(A, tuple(A.shape), name="A")
+        _check_tensor(D, tuple(A.shape), name="D")
+        P = int(np.prod(A.shape[2:])) if A.dim() > 2 else 1
+        ranks.append(torch.empty(P, dtype=torch.int32, device="cuda"))
+    darr = (ctypes.POINTER(Desc) * n)(*[ctypes.pointer(d) for d in descs])
+    aarr = (_vp * n)(*[A.data_ptr() for A in As])
+    tarr = (ctypes.c_double * n)(*[float(t) for t in taus])
+    oarr = (_vp * n)(*[D.data_ptr() for D in Ds])
+    rarr = (_vp * n)(*[r.data_ptr() for r in ranks])
+    o = svd_opts(jacobi_tol, max_sweeps, precision, precondition, fp32_dots=fp32_dots)
+    nb = int(_lib.lt_svt_batched_workspace_bytes(n, darr, ctypes.byref(o)))
+    if nb == 0:
+        raise ValueError("a tensor of the batch is not supported by the batch engine")
+    w = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    h = _handle()
+    _check(h, _lib.lt_svt_prox_batched(h, n, darr, aarr, tarr, oarr, rarr, ctypes.byref(o), _ptr(w), nb))
+    return Ds, ranks
 
 
 def lproduct(A, B, kinds=None, precision="f32", out=None, ws=None):
@@ -314,9 +369,12 @@ def lproduct(A, B, kinds=None, precision="f32", out=None, ws=None):
     return C
 
 
-def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, precision="f32", ws=None):
-    """Economy *_L-SVD (Alg. 3): returns (U, S, V, sigma) with U: I1 x n x ...,
-    S: n x n x ..., V: I2 x n x ..., sigma: P x n (transform domain, descending)."""
+def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, precision="f32", ws=None,
+         economy=True):
+    """*_L-SVD (Alg. 3): returns (U, S, V, sigma).  Economy: U: I1 x n x ...,
+    S: n x n x ..., V: I2 x n x ...; full (economy=False): U: I1 x I1 x ...,
+    S: I1 x I2 x ..., V: I2 x I2 x ....  sigma: P x n (transform domain,
+    descending)."""
     shape = tuple(A.shape)
     _check_tensor(A, shape, name="A")
     d = make_desc(shape, kinds)
@@ -324,28 +382,29 @@ def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, pr
     n = min(I1, I2)
     tr = shape[2:]
     P = int(np.prod(tr)) if tr else 1
-    U = fortran_empty((I1, n) + tr)
-    S = fortran_empty((n, n) + tr)
-    V = fortran_empty((I2, n) + tr)
+    ku, kv, (sr, sc) = (n, n, (n, n)) if economy else (I1, I2, (I1, I2))
+    U = fortran_empty((I1, ku) + tr)
+    S = fortran_empty((sr, sc) + tr)
+    V = fortran_empty((I2, kv) + tr)
     sig = torch.empty((P, n), dtype=torch.float32, device="cuda")
-    nb = workspace_bytes(shape, kinds, "lsvd", precision)
+    nb = workspace_bytes(shape, kinds, "lsvd" if economy else "lsvd_full", precision)
     w = _workspace(nb, ws)
     h = _handle()
     o = svd_opts(jacobi_tol, max_sweeps, precision)
     st = _lib.lt_lsvd(h, ctypes.byref(d), _ptr(A), _ptr(U), _ptr(S), _ptr(V), _ptr(sig),
-                      1 if transform_domain else 0, ctypes.byref(o), _ptr(w), nb)
+                      1 if economy else 0, 1 if transform_domain else 0, ctypes.byref(o), _ptr(w), nb)
     _check(h, st)
     return U, S, V, sig
 
 
 def pga_params(mu0, nu=0.9, mu_bar=None, tol=0.0, max_iter=100, check_every=10,
                gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32",
-               precondition=True, warm_restart=0):
+               precondition=True, warm_restart=0, fp32_dots=False):
     if mu_bar is None:
         mu_bar = 1e-4 * mu0
     return PgaParams(float(mu0), float(nu), float(mu_bar), float(tol), int(max_iter), int(check_every),
                      1 if gate_until_floor else 0, 1 if fixed_mu else 0,
-                     svd_opts(jacobi_tol, max_sweeps, precision, precondition, warm_restart))
+                     svd_opts(jacobi_tol, max_sweeps, precision, precondition, warm_restart, fp32_dots))
 
 
 def complete_pga(M, mask, params, kinds=None, out=None, ws=None):
@@ -365,10 +424,7 @@ def complete_pga(M, mask, params, kinds=None, out=None, ws=None):
     st = _lib.lt_complete_pga(h, ctypes.byref(d), _ptr(M), _ptr(mask), ctypes.byref(params), _ptr(X),
                               ctypes.byref(rep), _ptr(w), nb)
     _check(h, st)
-    report = dict(iters=rep.iters, converged=bool(rep.converged), max_sweeps_hit=rep.max_sweeps_hit,
-                  last_crit=rep.last_crit, total_sweeps=rep.total_sweeps, total_slices=rep.total_slices,
-                  total_rotations=rep.total_rotations)
-    return X, report, st
+    return X, _report(rep), st
 
 
 def profile_begin():
@@ -394,7 +450,7 @@ def profile_end():
 def _report(rep):
     return dict(iters=rep.iters, converged=bool(rep.converged), max_sweeps_hit=rep.max_sweeps_hit,
                 last_crit=rep.last_crit, total_sweeps=rep.total_sweeps, total_slices=rep.total_slices,
-                total_rotations=rep.total_rotations)
+                total_rotations=rep.total_rotations, nuclear_norm=rep.nuclear_norm)
 
 
 class Problem:

@@ -59,6 +59,9 @@ def test_workspace_sizes_host_only():
     assert lt.workspace_bytes((144, 176, 3, 50), None, "pga", "bf16x3") > n_pga
     assert lt.workspace_bytes((8, 3, 5), None, "lproduct", shape_b=(3, 7, 5)) > 0
     assert lt.workspace_bytes((16, 12, 4), None, "lsvd") > 0
+    # full factors: U 16 x 16, S 16 x 12, V 12 x 12 per slice plus FP64 reflectors
+    assert (lt.workspace_bytes((16, 12, 4), None, "lsvd_full") - lt.workspace_bytes((16, 12, 4), None, "lsvd")
+            >= 4 * 4 * (16 * 16 + 16 * 12 + 12 * 12) + 4 * 8 * 16 * 12)
     # Fourier modes: SVT and completion (FP32) hold two planes and the real
     # embeddings of one slice per conjugate pair (P = 4: pairs {0}, {1, 3}, {2})
     n_dft = lt.workspace_bytes((8, 8, 4), ("dft",), "svt")
@@ -76,9 +79,9 @@ def test_workspace_sizes_host_only():
 def test_descriptor_layout_matches_c():
     from paper_2202_02870_amd import lt
     assert ctypes.sizeof(lt.Desc) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 8
-    assert ctypes.sizeof(lt.SvdOpts) == 24
-    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 24
-    assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(lt.SvdOpts) == 32            # double + 5 int32, padded to 8
+    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 32
+    assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lt.Profile) == 6 * 8 + 6 * 8 + 8
 
 
