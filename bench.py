@@ -7,18 +7,28 @@ along modes 3..N as one MFMA GEMM), per-slice one-sided-Jacobi SVD and singular
 value soft-threshold, rank-r rebuild, inverse L with the stopping-rule norms.
 
 Default workload: the video-shaped completion 144x176x3x50 of L-rank 10, 30%
-observed (150 frontal slices of 144x176 per step), the continuation schedule
-mu0 = 0.9 ||P_Omega(M)||_F, nu = 0.9, mu_bar = 1e-4 mu0, run for --steps
-iterations from X = 0 (the full job is 200 iterations).  Inputs are resident in
-HBM before the timed region.
+observed (150 frontal slices of 144x176 per step), continuation schedule
+mu0 = 0.9 ||P_Omega(M)||_F, nu = 0.9, mu_bar = 1e-4 mu0.  The timed steps are
+iterations start+warmup+1 .. start+warmup+steps of one run: an untimed prefix of
+--start iterations (default 100: past the zero iterates of the first ~7
+iterations and into the rank-carrying, floor-threshold regime), then --warmup
+untimed and --steps timed iterations, each call continuing the previous one
+(lt_pga_params.start_iter).  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0).  Extra fields: slice-SVT/s, the Jacobi kernel's
-roofline (VALU-bound: FP64 dots and angles, FP32 rotations), the FP64 oracle
-timed on this host on a bounded sample, and the sample's error vs that oracle.
+Prints one JSON line.  Besides the contract's keys: slice-SVT/s; the dominant
+kernel's roofline (VALU: FP64 dot products and FP32 rotations, counted as the
+method needs them); the FP64 oracle on this host (all threads and one thread,
+CPU model); and, in the default run, further legs of the metric: the
+256x256x3x100 workload with FP32 and BF16x3 transforms and their errors vs the
+oracle, the 64-problem mix through the batch engine (mixed-precision batched
+form vs the plain FP32 per-request form), a bounded served stream (p50/p99),
+and the whole 200-iteration video job from X = 0.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,26 +42,28 @@ PEAK_FP64_VALU = 78.6e12
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12
 
-
-# HBM bytes per k_jacobi_warm launch on the default video workload (FP32,
-# Cholesky-QR preconditioned, warm-started, 150 slices of 144 x 144 factors), from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes scaled by a 256 MiB device copy
-# in the same run (fetch x2.0, write x1.0), warm launches; the command lines and
-# raw figures are in profiles/.  Reported only for that configuration and this
-# kernel version (null elsewhere).
-JACOBI_WARM_TRAFFIC_VIDEO_BYTES = 42332974
+JACOBI_SRC = os.path.join(ROOT, "paper_2202_02870_amd", "csrc", "lt_jacobi.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_jacobi_warm_video_144x176x3x50.md")
 
 
-def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):
-    """Algorithmic flops of the one-sided Jacobi SVT kernel summed over `slices`
-    slice-SVDs of n columns of `rows` rows (the slice's m, or n when the
-    Cholesky-QR preconditioned path runs the Jacobi on R^T) that took `sweeps`
-    sweeps and applied `rotations` rotations in total: per sweep and slice,
-    n(n-1)/2 pair dot products (2 rows flops each; FP32 when the tolerance is
-    1e-6 or looser, FP64 otherwise) and n column norms (2 rows FP64 flops); per
-    rotation 6 rot_rows FP32 flops (two columns, 3 flops per entry; rot_rows =
-    rows unless the columns carry more rows than the dot products read); per
-    slice the final column norms (2 rows n FP64)."""
+def svt_time_at_peak(m, n, sweeps_total):
+    """Algorithmic work of the one-sided Jacobi SVD of m x n slices (m rows,
+    n columns) summed over slices with sweeps_total sweeps in all: per sweep,
+    n(n-1)/2 column pairs, each with three FP64 dot products (6 m flops) and the
+    FP32 rotation of the pair's data and rotation-accumulator columns
+    (6 m + 6 n flops).  Returns (FP64 flops, FP32 flops, seconds at the MI355X
+    vector peaks)."""
+    pairs = n * (n - 1) // 2
+    f64 = float(sweeps_total) * pairs * 6 * m
+    f32 = float(sweeps_total) * pairs * (6 * m + 6 * n)
+    return f64, f32, f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU
+
+
+def kernel_flops(rows, n, sweeps, rotations, slices, dot32=False, rot_rows=None):
+    """What the kernel itself executes: per sweep and slice n(n-1)/2 pair dot
+    products of 2 rows flops and n column norms of 2 rows FP64 flops (rows: the
+    Jacobi's working rows, n on the Cholesky-QR factor); per applied rotation
+    6 rot_rows FP32 flops; the final column norms."""
     pairs = n * (n - 1) // 2
     dots = sweeps * pairs * 2 * rows
     f64 = sweeps * n * 2 * rows + slices * n * 2 * rows + (0 if dot32 else dots)
@@ -62,8 +74,7 @@ def jacobi_flops(rows, n, sweeps, rotations, slices, dot32=True, rot_rows=None):
 def threads_used():
     try:
         from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        blas = [i for i in info if i.get("user_api") == "blas"]
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
         if blas:
             return int(blas[0]["num_threads"])
     except Exception:
@@ -71,14 +82,49 @@ def threads_used():
     return os.cpu_count() or 1
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measured_traffic():
+    """HBM bytes per k_jacobi_warm launch on the default video workload from the
+    committed FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
+    kernel source (its SHA-256 is recorded there), else None."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(JACOBI_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    mt = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    ms = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if mt and ms and ms.group(1) == src:
+        return int(mt.group(1))
+    return None
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed iterations (default: 200 video, 300 large, 30 big; 50 mix ticks)")
-    ap.add_argument("--warmup", type=int, default=10)
+                    help="timed iterations (default: 200 video, 100 large, 30 big; 50 mix ticks)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--start", type=int, default=None,
+                    help="untimed iterations before the warm-up (default 100 video/large, 20 big)")
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3"])
     ap.add_argument("--workload", default="video", choices=["video", "large", "big", "mix", "serve"])
+    ap.add_argument("--legs", default="all",
+                    help="video workload: extra legs, comma list of job,large,mix,serve, 'all' or 'none'")
     ap.add_argument("--large-frac", type=float, default=0.1,
                     help="serve workload: share of 512x512x3x64 requests")
     ap.add_argument("--no-lanes", action="store_true",
@@ -89,25 +135,26 @@ def main():
     ap.add_argument("--per-request-iters", type=int, default=5,
                     help="mix workload: iterations of the plain per-request form timed for comparison")
     ap.add_argument("--cpu-iters", type=int, default=None,
-                    help="oracle iterations timed on the host (bounded CPU sample; default 30 for "
-                         "video, 10 for large: the iterates are nonzero from the sixth and eighth iterations)")
+                    help="oracle iterations timed on the host with all threads (default 30 video, 10 large)")
+    ap.add_argument("--cpu-iters-1t", type=int, default=None,
+                    help="oracle iterations timed on one thread (default 5 video, 2 large)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-calibrate", action="store_true",
-                    help="video/large: run one 256 MiB device copy before the timed region (counter reference)")
+                    help="run one 256 MiB device copy before the timed region (counter reference)")
     ap.add_argument("--transform", default="dct", choices=["dct", "dft"],
                     help="video workload: transform along the trailing modes (dft: the t-product form)")
     ap.add_argument("--no-precondition", action="store_true",
                     help="run the Jacobi SVD on the slices themselves (no Cholesky-QR factor)")
     ap.add_argument("--warm-restart", type=int, default=0,
-                    help="video/large/big: cold Jacobi start every this many iterations "
-                         "(0: the library default, 256; -1: every iteration, no warm start)")
-    ap.add_argument("--fp32-dots", action="store_true",
-                    help="FP32 pair dot products in the Jacobi (default: FP64)")
+                    help="cold Jacobi start every this many iterations (0: library default 256; -1: never warm)")
+    ap.add_argument("--fp32-dots", action="store_true", help="FP32 pair dot products in the Jacobi (default FP64)")
     ap.add_argument("--lanes", default="auto",
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"video": 200, "large": 300, "big": 30, "mix": 50, "serve": 0}[args.workload]
+        args.steps = {"video": 200, "large": 100, "big": 30, "mix": 50, "serve": 0}[args.workload]
+    if args.start is None:
+        args.start = {"video": 100, "large": 100, "big": 20}.get(args.workload, 0)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -121,34 +168,48 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "mix":
-        return bench_mix(args, torch, lt, wl)
+        print(json.dumps(bench_mix(args, torch, lt, wl)), flush=True)
+        return
     if args.workload == "serve":
-        return bench_serve(args, torch, lt, wl)
-    if args.workload == "video":
-        p = wl.config1(transform=args.transform)
-    else:
-        p = {"large": wl.config2, "big": wl.config4_large}[args.workload]()
-    shape = p.shape
-    I1, I2 = shape[0], shape[1]
-    P = wl.n_slices(shape)
-    m, n = max(I1, I2), min(I1, I2)
+        print(json.dumps(bench_serve(args, torch, lt, wl)), flush=True)
+        return
+    line = bench_completion(args, torch, lt, wl)
+    if args.workload == "video" and args.transform == "dct":
+        legs = set() if args.legs == "none" else (
+            {"large", "mix", "serve", "job"} if args.legs == "all" else set(args.legs.split(",")))
+        extra = {}
+        for name, fn in (("job", leg_job), ("large", leg_large), ("mix", leg_mix), ("serve", leg_serve)):
+            if name in legs:
+                say("leg", name)
+                try:
+                    extra[name] = fn(args, torch, lt, wl)
+                except Exception as e:   # a failed leg is reported; the headline is still printed
+                    extra[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+                torch.cuda.empty_cache()
+        if extra:
+            line["legs"] = extra
+    print(json.dumps(line), flush=True)
+
+
+def run_window(lt, M, mask, p, X, ws, args, precision, start, warmup, steps, fp32_dots=False):
+    """start untimed iterations from X = 0, warmup more, then steps timed ones,
+    each call continuing the run; returns (seconds, report, profile, window)."""
+    import torch
     s = p.schedule
-    M = lt.to_device(p.M)
-    mask = lt.to_device(p.mask, dtype=torch.uint8)
-    X = lt.fortran_empty(shape)
-    ws = torch.empty(lt.workspace_bytes(shape, p.kinds, "pga", args.precision), dtype=torch.uint8,
-                     device="cuda")
 
-    def params(iters):
+    def params(iters, k0):
         return lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=iters,
-                             precision=args.precision, precondition=not args.no_precondition,
-                             warm_restart=args.warm_restart, fp32_dots=args.fp32_dots)
+                             precision=precision, precondition=not args.no_precondition,
+                             warm_restart=args.warm_restart, fp32_dots=fp32_dots, start_iter=k0)
 
-    # warmup (untimed)
-    if args.warmup > 0:
-        lt.complete_pga(M, mask, params(args.warmup), p.kinds, out=X, ws=ws)
+    k = 0
+    if start > 0:
+        lt.complete_pga(M, mask, params(start, 0), p.kinds, out=X, ws=ws)
+        k = start
+    if warmup > 0:
+        lt.complete_pga(M, mask, params(warmup, k), p.kinds, out=X, ws=ws)
+        k += warmup
     torch.cuda.synchronize()
-
     if args.pmc_calibrate:
         # a plain device copy of known size (256 MiB read + 256 MiB written): the
         # reference that turns hardware byte counters into HBM bytes
@@ -157,47 +218,93 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    # timed region: exactly --steps iterations, kernel durations recorded with HIP events
     lt.profile_begin()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, rep, st = lt.complete_pga(M, mask, params(args.steps), p.kinds, out=X, ws=ws)
+    _, rep, _ = lt.complete_pga(M, mask, params(steps, k), p.kinds, out=X, ws=ws)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof, dropped = lt.profile_end()
-    elapsed = t1 - t0
+    prof, _ = lt.profile_end()
+    return t1 - t0, rep, prof, (k + 1, k + steps)
+
+
+def oracle_rate(o, p, iters, threads=None):
+    """The FP64 oracle's iterations/s over the first `iters` iterations, its
+    iterate, and the BLAS threads used."""
+    s = p.schedule
+    mats = o.mats_for(p.shape, list(p.kinds))
+
+    def run():
+        c0 = time.perf_counter()
+        Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0,
+                               max_iter=iters)
+        return iters / (time.perf_counter() - c0), Xo
+
+    if threads is None:
+        return run() + (threads_used(),)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=threads):
+        return run() + (threads,)
+
+
+def gpu_iterate(lt, M, mask, p, precision, iters, fp32_dots=False):
+    s = p.schedule
+    prm = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=iters,
+                        precision=precision, fp32_dots=fp32_dots)
+    X, _, _ = lt.complete_pga(M, mask, prm, p.kinds)
+    return lt.to_host(X).astype(np.float64)
+
+
+def bench_completion(args, torch, lt, wl):
+    if args.workload == "video":
+        p = wl.config1(transform=args.transform)
+    else:
+        p = {"large": wl.config2, "big": wl.config4_large}[args.workload]()
+    shape = p.shape
+    I1, I2 = shape[0], shape[1]
+    P = wl.n_slices(shape)
+    m, n = max(I1, I2), min(I1, I2)
+    M = lt.to_device(p.M)
+    mask = lt.to_device(p.mask, dtype=torch.uint8)
+    X = lt.fortran_empty(shape)
+    ws = torch.empty(lt.workspace_bytes(shape, p.kinds, "pga", args.precision), dtype=torch.uint8, device="cuda")
+    elapsed, rep, prof, window = run_window(lt, M, mask, p, X, ws, args, args.precision, args.start, args.warmup,
+                                            args.steps, args.fp32_dots)
     value = args.steps / elapsed
 
-    # Jacobi kernel roofline (dominant kernel): algorithmic flops per launch over
-    # its mean event-timed duration
+    # dominant kernel: the Jacobi SVT.  Work counted as the method needs it (three
+    # FP64 dots and the FP32 rotations of data and accumulator per column pair of
+    # the m x n slice, at the measured sweeps), over the kernel's mean event-timed
+    # launch duration on the library's stream.
     jcalls, jms = prof["jacobi"]
     path = lt.svt_path(shape, p.kinds, precondition=not args.no_precondition)
     precond = "precond" in path
-    jm, jn = (2 * m, 2 * n) if "dft" in p.kinds else (m, n)   # Fourier: real embeddings of the slices
-    rows = jn if precond else jm
-    # warm-started Jacobi: every rotation also updates the accumulated rotations
-    # (a second block of 4 ceil(n/4) rows below the factor's)
+    dft = "dft" in p.kinds
+    jm, jn = (2 * m, 2 * n) if dft else (m, n)   # Fourier: real embeddings of the slices
     warm = lt.pga_warm(shape, p.kinds, precondition=not args.no_precondition, warm_restart=args.warm_restart)
-    rot_rows = rows + 4 * ((jn + 3) // 4) if warm else rows
-    f64, f32 = jacobi_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
-                            rot_rows=rot_rows)
-    per_launch = (f64 + f32) / max(jcalls, 1)
     t_launch = jms / 1e3 / max(jcalls, 1)
-    t_peak = (f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU) / max(jcalls, 1)
-    achieved = per_launch / t_launch / 1e12 if t_launch > 0 else 0.0
-    peak = per_launch / t_peak / 1e12 if t_peak > 0 else 0.0
-    measured_cfg = (args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
-                    and warm)
-    roofline = {"bound": "alu", "kernel": "k_jacobi_warm" if warm else "k_jacobi", "achieved": round(achieved, 3),
-                "peak": round(peak, 2), "unit": "TFLOP/s",
+    f64, f32, t_peak = svt_time_at_peak(jm, jn, rep["total_sweeps"])
+    flops = (f64 + f32) / max(jcalls, 1)
+    t_peak /= max(jcalls, 1)
+    rows = jn if precond else jm
+    rot_rows = rows + 4 * ((jn + 3) // 4) if warm else rows
+    k64, k32 = kernel_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
+                            dot32=args.fp32_dots, rot_rows=rot_rows)
+    tk_peak = (k64 / PEAK_FP64_VALU + k32 / PEAK_FP32_VALU) / max(jcalls, 1)
+    default_cfg = (args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
+                   and warm and not args.fp32_dots)
+    roofline = {"bound": "alu", "kernel": "k_jacobi_warm" if warm else "k_jacobi",
+                "achieved": round(flops / t_launch / 1e12, 3) if t_launch > 0 else None,
+                "peak": round(flops / t_peak / 1e12, 2) if t_peak > 0 else None, "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None,
-                "traffic": JACOBI_WARM_TRAFFIC_VIDEO_BYTES if measured_cfg else None,
-                "flops_per_launch": per_launch, "fp64_share": round(f64 / (f64 + f32), 4),
+                "traffic": measured_traffic() if default_cfg else None,
+                "count": "per sweep of an m x n slice: n(n-1)/2 pairs x (6m FP64 + 6m+6n FP32) flops, "
+                         "measured sweeps; peak = time at 78.6 (FP64) and 157.3 (FP32) TFLOP/s",
+                "flops_per_launch": flops, "time_at_peak_us": round(t_peak * 1e6, 2),
                 "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
-                "jacobi_rows": rows, "rotated_rows": rot_rows, "preconditioned": precond,
-                "warm_start": warm, "svt_path": path}
-
+                "frac_kernel_count": round(tk_peak / t_launch, 4) if t_launch > 0 else None,
+                "slice": [jm, jn], "jacobi_rows": rows, "rotated_rows": rot_rows, "preconditioned": precond,
+                "warm_start": warm, "svt_path": path, "pair_dots": "fp32" if args.fp32_dots else "fp64"}
     line = {
         "metric": "PGA iterations/s (slice-SVT/s alongside) at rel-err <= 1e-4 vs FP64 oracle",
         "value": round(value, 3),
@@ -211,47 +318,115 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "f32" else "bf16x3+f32",
         "data": "synthetic",
-        "config": {"workload": p.name, "shape": list(shape), "slices_per_step": P,
-                   "precision": args.precision, "schedule": "mu0=0.9||P_Omega M||, nu=0.9, mu_bar=1e-4 mu0"},
+        "config": {"workload": p.name, "shape": list(shape), "slices_per_step": P, "precision": args.precision,
+                   "schedule": "mu0=0.9||P_Omega M||, nu=0.9, mu_bar=1e-4 mu0",
+                   "timed_iterations": list(window)},
         "slice_svt_per_s": round(value * P, 1),
         "mean_sweeps": round(rep["total_sweeps"] / max(rep["total_slices"], 1), 3),
         "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()},
         "kernel_calls": {k: v[0] for k, v in prof.items()},
         "roofline": roofline,
     }
-
     cpu_iters = args.cpu_iters if args.cpu_iters is not None else {"video": 30, "large": 10, "big": 1}[args.workload]
+    cpu_1t = args.cpu_iters_1t if args.cpu_iters_1t is not None else {"video": 5, "large": 2, "big": 0}[args.workload]
     if not args.no_cpu_baseline and cpu_iters > 0:
         import oracle as o
-        k = cpu_iters
-        mats = o.mats_for(shape, list(p.kinds))
-        c0 = time.perf_counter()
-        Xo, _ = o.complete_pga(p.M, p.mask, mats, mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"],
-                               tol=0.0, max_iter=k)
-        c1 = time.perf_counter()
-        line["cpu_baseline"] = {"value": round(k / (c1 - c0), 4), "unit": "iters/s",
-                                "cores": threads_used(), "kind": "oracle",
-                                "sample": "first %d PGA iterations of the same workload, FP64 NumPy/LAPACK" % k}
-        Xg, _, _ = lt.complete_pga(M, mask, params(k), p.kinds, out=X, ws=ws)
-        Xg = lt.to_host(Xg).astype(np.float64)
+        say("oracle on the host:", cpu_iters, "iterations, all threads")
+        rate, Xo, cores = oracle_rate(o, p, cpu_iters)
+        cb = {"value": round(rate, 4), "unit": "iters/s", "cores": cores, "kind": "oracle",
+              "sample": "first %d PGA iterations of the same workload, FP64 NumPy/LAPACK, %d BLAS threads"
+                        % (cpu_iters, cores),
+              "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        if cpu_1t > 0:
+            say("oracle on the host:", cpu_1t, "iterations, one thread")
+            r1, _, _ = oracle_rate(o, p, cpu_1t, threads=1)
+            cb["single_thread"] = {"value": round(r1, 4), "unit": "iters/s", "cores": 1,
+                                   "sample": "first %d PGA iterations, one BLAS thread (the paper's "
+                                             "single-core protocol)" % cpu_1t}
+        line["cpu_baseline"] = cb
+        Xg = gpu_iterate(lt, M, mask, p, args.precision, cpu_iters, args.fp32_dots)
         nrm = float(np.linalg.norm(Xo))
-        # the first iterations threshold every singular value (mu_k is large), so a
-        # sample that short compares zero tensors: report the GPU iterate's own norm then
-        if nrm > 0:
-            err = {"rel_err_vs_oracle": float(np.linalg.norm(Xg - Xo) / nrm)}
-        else:
-            err = {"abs_norm_gpu_where_oracle_is_zero": float(np.linalg.norm(Xg))}
-        line["parity"] = {"iters": k, **err, "bound": 1e-4 if args.precision == "f32" else 1e-2}
+        err = ({"rel_err_vs_oracle": float(np.linalg.norm(Xg - Xo) / nrm)} if nrm > 0 else
+               {"abs_norm_gpu_where_oracle_is_zero": float(np.linalg.norm(Xg))})
+        line["parity"] = {"iters": cpu_iters, **err, "bound": 1e-4 if args.precision == "f32" else 1e-2,
+                          "full_length": "200 iterations at full size in tests/test_gpu_configs.py"}
+    return line
 
-    print(json.dumps(line), flush=True)
+
+def leg_job(args, torch, lt, wl):
+    """The whole 200-iteration video job from X = 0, one call."""
+    p = wl.config1()
+    s = p.schedule
+    M = lt.to_device(p.M)
+    mask = lt.to_device(p.mask, dtype=torch.uint8)
+    prm = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0, max_iter=200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep, _ = lt.complete_pga(M, mask, prm, p.kinds)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"iterations": 200, "seconds": round(dt, 4), "iters_per_s": round(200 / dt, 2),
+            "mean_sweeps": round(rep["total_sweeps"] / rep["total_slices"], 3),
+            "nuclear_norm": rep["nuclear_norm"]}
+
+
+def leg_large(args, torch, lt, wl):
+    """256x256x3x100 (300 slices of 256 x 256), FP32 and BF16x3 transforms:
+    iterations 103..132 of a run timed, and the error of the first 12
+    iterations vs the FP64 oracle (the iterates are nonzero from the eighth)."""
+    import oracle as o
+    p = wl.config2()
+    M = lt.to_device(p.M)
+    mask = lt.to_device(p.mask, dtype=torch.uint8)
+    X = lt.fortran_empty(p.shape)
+    out = {"workload": p.name}
+    k_or = 12
+    say("  oracle", k_or, "iterations")
+    rate, Xo, cores = oracle_rate(o, p, k_or)
+    out["oracle"] = {"iters_per_s": round(rate, 4), "cores": cores, "iters": k_or}
+    nrm = float(np.linalg.norm(Xo))
+    for prec in ("f32", "bf16x3"):
+        ws = torch.empty(lt.workspace_bytes(p.shape, p.kinds, "pga", prec), dtype=torch.uint8, device="cuda")
+        dt, rep, prof, window = run_window(lt, M, mask, p, X, ws, args, prec, 100, 2, 30)
+        del ws
+        Xg = gpu_iterate(lt, M, mask, p, prec, k_or)
+        out[prec] = {"iters_per_s": round(30 / dt, 2), "timed_iterations": list(window),
+                     "slice_svt_per_s": round(30 * 300 / dt, 1),
+                     "mean_sweeps": round(rep["total_sweeps"] / rep["total_slices"], 3),
+                     "jacobi_ms_per_launch": round(prof["jacobi"][1] / max(prof["jacobi"][0], 1), 3),
+                     "rel_err_vs_oracle_at_%d" % k_or: float(np.linalg.norm(Xg - Xo) / nrm) if nrm > 0 else None,
+                     "bound": 1e-4 if prec == "f32" else 1e-2}
+    return out
+
+
+def leg_mix(args, torch, lt, wl):
+    """The benchmark spec's comparison on the 64-problem mix: mixed-precision
+    batched form (BF16x3 transforms, one batch-engine tick per iteration over
+    all problems, graph-replayed) vs the plain FP32 per-request form."""
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup, a.precision, a.per_request_iters, a.lanes = 30, 5, "bf16x3", 3, "auto"
+    r = bench_mix(a, torch, lt, wl)
+    keep = ("value", "unit", "slice_svt_per_s", "per_request_f32_slice_svt_per_s", "batched_over_per_request",
+            "mean_sweeps", "jacobi_lanes", "config")
+    return {k: r[k] for k in keep}
+
+
+def leg_serve(args, torch, lt, wl):
+    """A bounded served stream: 40 requests (10% of 512x512x3x64), Poisson
+    arrivals at 0.7x the measured saturation rate."""
+    a = argparse.Namespace(**vars(args))
+    a.requests, a.rate, a.large_frac = 40, 0.0, 0.1
+    r = bench_serve(a, torch, lt, wl)
+    keep = ("value", "unit", "p50_s", "p99_s", "completed", "rejected", "mean_iters", "peak_resident_GB", "config")
+    return {k: r[k] for k in keep}
 
 
 def bench_mix(args, torch, lt, wl):
     """64 independent problems of uneven shapes (order 3/4, I1, I2 in 32..256,
     trailing {3,8,16} x {1,10,30}); a step is one tick of the batch engine: one
     PGA iteration of every problem, with all frontal slices of all problems in
-    one Jacobi launch (graph-replayed ticks).  The plain per-request form (one
-    lt_complete_pga call per problem) is timed alongside."""
+    one Jacobi launch per kernel family (graph-replayed ticks).  The plain FP32
+    per-request form (one lt_complete_pga call per problem) is timed alongside."""
     probs = wl.config3(max_iter=args.steps + args.warmup)
     total_slices = sum(wl.n_slices(p.shape) for p in probs)
     dev = []
@@ -279,6 +454,7 @@ def bench_mix(args, torch, lt, wl):
     elapsed = t1 - t0
     reps = [gp.status()[0] for gp in gps]
     batch.close()
+    del gps
     # eager ticks with per-kernel events (same work, no graph) for the kernel split
     gps2 = [lt.Problem(M, mask, params, p.kinds) for (p, M, mask, params) in dev]
     b2 = lt.Batch(gps2, use_graph=False, jacobi_lanes=lanes)
@@ -287,6 +463,7 @@ def bench_mix(args, torch, lt, wl):
     b2.step(min(args.steps, 20))
     prof, _ = lt.profile_end()
     b2.close()
+    del gps2
     # plain FP32 per-request form: one problem after another, the same first iterations
     k = args.per_request_iters
     torch.cuda.synchronize()
@@ -299,7 +476,7 @@ def bench_mix(args, torch, lt, wl):
     c1 = time.perf_counter()
     per_req_slices = k * total_slices / (c1 - c0)
     value = args.steps / elapsed
-    line = {
+    return {
         "metric": "slice-SVT/s of the batched engine (PGA ticks/s as value) at rel-err <= 1e-4 vs FP64 oracle",
         "value": round(value, 3),
         "unit": "ticks/s",
@@ -313,7 +490,7 @@ def bench_mix(args, torch, lt, wl):
         "dtype": "f32" if args.precision == "f32" else "bf16x3+f32",
         "data": "synthetic",
         "config": {"workload": "mix-64-problems", "problems": len(probs), "slices_per_tick": total_slices,
-                   "precision": args.precision},
+                   "precision": args.precision, "per_request_precision": "f32"},
         "slice_svt_per_s": round(value * total_slices, 1),
         "per_request_f32_slice_svt_per_s": round(per_req_slices, 1),
         "batched_over_per_request": round(value * total_slices / per_req_slices, 3),
@@ -323,7 +500,6 @@ def bench_mix(args, torch, lt, wl):
         "autotune_jacobi_ms_per_tick": ({str(g): round(t, 4) for g, t in sorted(tune_ms.items())}
                                         if tune_ms else None),
     }
-    print(json.dumps(line), flush=True)
 
 
 def bench_serve(args, torch, lt, wl):
@@ -339,9 +515,8 @@ def bench_serve(args, torch, lt, wl):
     n_large = sum(1 for sp in specs if tuple(sp["shape"]) == wl.LARGE_REQUEST_SHAPE)
 
     def progress(r):
-        print("finished request %d %s: %d iterations, latency %.3f s" % (r.rid, "x".join(map(str, r.M.shape)),
-                                                                         r.iters, r.latency),
-              file=sys.stderr, flush=True)
+        say("finished request %d %s: %d iterations, latency %.3f s" % (r.rid, "x".join(map(str, r.M.shape)),
+                                                                       r.iters, r.latency))
 
     reqs = []
     for i, sp in enumerate(specs):
@@ -373,7 +548,7 @@ def bench_serve(args, torch, lt, wl):
     st = srv.run(sleep=0.001)
     wall = time.perf_counter() - c0
     slices = sum(r.iters * wl.n_slices(r.M.shape) for r in srv.done)
-    line = {
+    return {
         "metric": "served p50/p99 latency and aggregate slice-SVT/s",
         "value": round(slices / wall, 1),
         "unit": "slice-SVT/s",
@@ -397,7 +572,6 @@ def bench_serve(args, torch, lt, wl):
         "mean_iters": round(float(np.mean([r.iters for r in srv.done])), 2) if srv.done else None,
         "peak_resident_GB": round(st["peak_bytes"] / 1e9, 3),
     }
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -145,6 +145,12 @@ typedef struct {
   int32_t gate_until_floor; /* nonzero: the test may stop the run only once mu_k == mu_bar */
   int32_t fixed_mu;       /* nonzero: every iteration thresholds at mu0 */
   lt_svd_opts svd;
+  int32_t start_iter;     /* lt_complete_pga: 0 starts from X^0 = X^1 = 0; k0 > 0 continues a run
+                             that the previous call on the same workspace (same descriptor and
+                             parameters apart from max_iter and start_iter) ended at iteration
+                             k0: X holds X^k0 and the workspace X^(k0-1) and the accumulated
+                             rotations; the call then runs iterations k0 + 1 .. k0 + max_iter
+                             with the schedule's t_k and mu_k.  The batch engine ignores it. */
 } lt_pga_params;
 
 typedef struct {
@@ -279,7 +285,9 @@ int lt_svt_prox_batched(lt_handle* h, int n, const lt_desc* const* a, const floa
                         const double* tau, float* const* D, int32_t* const* rank_out,
                         const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 
-/* Completion by PGA (Alg. 5) from X^0 = X^1 = 0.  M: observed tensor; mask:
+/* Completion by PGA (Alg. 5) from X^0 = X^1 = 0 (or continued, see
+ * lt_pga_params.start_iter); on return X holds the last iterate and the
+ * workspace the one before it.  M: observed tensor; mask:
  * uint8 per entry, nonzero = observed (the set Omega of eq. (48)); X: output,
  * the last iterate.  Checks M on Omega for NaN/Inf (LT_ERR_NONFINITE).
  * Synchronises the host with the stream when tol > 0 (every check_every

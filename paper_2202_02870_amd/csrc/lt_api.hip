@@ -1558,9 +1558,9 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   if (rc) return rc;
   if (!M || !mask || !X || !p) return fail(h, LT_ERR_ARG, "M, mask, X or params is NULL");
   if (!(p->mu0 > 0) || !(p->nu > 0 && p->nu <= 1) || !(p->mu_bar > 0 && p->mu_bar <= p->mu0) ||
-      p->max_iter < 1 || !isfinite(p->mu0))
+      p->max_iter < 1 || !isfinite(p->mu0) || p->start_iter < 0)
     return fail(h, LT_ERR_ARG, "invalid PGA parameters (need mu0 > 0, 0 < nu <= 1, "
-                               "0 < mu_bar <= mu0, max_iter >= 1)");
+                               "0 < mu_bar <= mu0, max_iter >= 1, start_iter >= 0)");
   double tol;
   int max_sweeps, prec;
   resolve_opts(&p->svd, &tol, &max_sweeps, &prec);
@@ -1588,8 +1588,11 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   const size_t bytes = (size_t)s.nel * sizeof(float);
   float* Xcur = X;        // X^k
   float* Xprev = w.Xb;    // X^{k-1}
-  HIP_TRY(h, hipMemsetAsync(Xcur, 0, bytes, st));
-  HIP_TRY(h, hipMemsetAsync(Xprev, 0, bytes, st));
+  const int k0 = p->start_iter;
+  if (k0 == 0) {
+    HIP_TRY(h, hipMemsetAsync(Xcur, 0, bytes, st));
+    HIP_TRY(h, hipMemsetAsync(Xprev, 0, bytes, st));
+  }
   HIP_TRY(h, hipMemsetAsync(w.sweep_total, 0, sizeof(unsigned long long), st));
   HIP_TRY(h, hipMemsetAsync(w.rot_total, 0, sizeof(unsigned long long), st));
   HIP_TRY(h, hipMemsetAsync(w.maxsweep_hits, 0, sizeof(unsigned int), st));
@@ -1597,10 +1600,15 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   const int check_every = p->check_every > 0 ? p->check_every : 1;
   const int restart = p->svd.warm_restart == 0 ? kWarmRestartDefault : p->svd.warm_restart;
   double t_prev = 1.0, t = 1.0, mu = p->mu0;   // t_0 = t_1 = 1, mu_1 = mu0
+  for (int k = 0; k < k0; ++k) {                // the schedule at a continued run's start
+    t_prev = t;
+    t = (1.0 + sqrt(4.0 * t * t + 1.0)) / 2.0;
+    mu = fmax(p->nu * mu, p->mu_bar);
+  }
   int iters = 0;
   bool converged = false;
   double crit = NAN;
-  for (int k = 0; k < p->max_iter; ++k) {
+  for (int k = k0; k < k0 + p->max_iter; ++k) {
     const double beta = (t_prev - 1.0) / t;   // eq. (52)
     const double mu_k = p->fixed_mu ? p->mu0 : mu;
 
@@ -1633,7 +1641,7 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     float* tmp = Xcur;   // X^{k+1} now lives in the old X^{k-1} buffer
     Xcur = Xprev;
     Xprev = tmp;
-    iters = k + 1;
+    iters = k + 1 - k0;
 
     t_prev = t;
     t = (1.0 + sqrt(4.0 * t * t + 1.0)) / 2.0;
@@ -1651,7 +1659,13 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
       }
     }
   }
-  if (Xcur != X) HIP_TRY(h, hipMemcpyAsync(X, Xcur, bytes, hipMemcpyDeviceToDevice, st));
+  if (Xcur != X) {
+    // X gets the last iterate and the workspace the one before it (for a
+    // continued run); the transform-domain buffer is free to hold one of them
+    HIP_TRY(h, hipMemcpyAsync(w.svt.Gh, X, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(X, Xcur, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(w.Xb, w.svt.Gh, bytes, hipMemcpyDeviceToDevice, st));
+  }
   // nuclear norm of the last iterate (Theorem 21): its transform-domain
   // singular values are the last prox's sigma_i - mu_k
   const double alpha = nuclear_alpha(s);

@@ -45,7 +45,7 @@ class PgaParams(ctypes.Structure):
     _fields_ = [("mu0", ctypes.c_double), ("nu", ctypes.c_double), ("mu_bar", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("gate_until_floor", ctypes.c_int32),
-                ("fixed_mu", ctypes.c_int32), ("svd", SvdOpts)]
+                ("fixed_mu", ctypes.c_int32), ("svd", SvdOpts), ("start_iter", ctypes.c_int32)]
 
 
 class PgaReport(ctypes.Structure):
@@ -399,12 +399,15 @@ def lsvd(A, kinds=None, transform_domain=False, jacobi_tol=0.0, max_sweeps=0, pr
 
 def pga_params(mu0, nu=0.9, mu_bar=None, tol=0.0, max_iter=100, check_every=10,
                gate_until_floor=True, fixed_mu=False, jacobi_tol=0.0, max_sweeps=0, precision="f32",
-               precondition=True, warm_restart=0, fp32_dots=False):
+               precondition=True, warm_restart=0, fp32_dots=False, start_iter=0):
+    """start_iter > 0 (complete_pga only): continue the run that the previous
+    call with the same workspace and output tensor ended at that iteration."""
     if mu_bar is None:
         mu_bar = 1e-4 * mu0
     return PgaParams(float(mu0), float(nu), float(mu_bar), float(tol), int(max_iter), int(check_every),
                      1 if gate_until_floor else 0, 1 if fixed_mu else 0,
-                     svd_opts(jacobi_tol, max_sweeps, precision, precondition, warm_restart, fp32_dots))
+                     svd_opts(jacobi_tol, max_sweeps, precision, precondition, warm_restart, fp32_dots),
+                     int(start_iter))
 
 
 def complete_pga(M, mask, params, kinds=None, out=None, ws=None):

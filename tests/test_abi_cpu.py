@@ -80,7 +80,7 @@ def test_descriptor_layout_matches_c():
     from paper_2202_02870_amd import lt
     assert ctypes.sizeof(lt.Desc) == 4 + 4 * 8 + 4 + 8 * 8 + 8 * 8
     assert ctypes.sizeof(lt.SvdOpts) == 32            # double + 5 int32, padded to 8
-    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 32
+    assert ctypes.sizeof(lt.PgaParams) == 4 * 8 + 4 * 4 + 32 + 8   # + start_iter, padded
     assert ctypes.sizeof(lt.PgaReport) == 4 * 4 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lt.Profile) == 6 * 8 + 6 * 8 + 8
 
