@@ -268,6 +268,22 @@ int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, floa
                 int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts,
                 void* ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lt_svt_prox with the
+ * workspace taken from a static device array of LT_NOALLOC_SCRATCH_BYTES bytes
+ * that the library holds on each GPU until the process ends (its address is
+ * resolved for the handle's device by lt_create).  Arguments and results as
+ * lt_svt_prox; the call allocates nothing.  LT_ERR_WORKSPACE when the shape
+ * needs more workspace than the array holds (lt_workspace_bytes(a, NULL,
+ * LT_OP_SVT, prec) > LT_NOALLOC_SCRATCH_BYTES); LT_ERR_ARG when the current
+ * device is not the handle's.  Every call on one GPU shares that GPU's array
+ * (nothing in it needs clearing between calls: each call writes what it
+ * reads): calls that overlap on one GPU -- on two streams, two handles or two
+ * threads -- race and must be serialised by the caller. */
+#define LT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lt_svt_prox_noalloc(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
+                        int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts);
+
 /* Batched SVT: D[i] = D_{tau[i]}(A[i]) (Alg. 4, Theorem 23) for n tensors of
  * possibly different shapes and orders (real transforms), as one pass of the
  * batch engine below: one grouped forward-transform launch over all tensors,

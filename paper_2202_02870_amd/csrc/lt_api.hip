@@ -14,15 +14,45 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 constexpr size_t kPinnedDoubles = 128;   // host staging: scalars and one problem record
 
+// Workspace of lt_svt_prox_noalloc: a file-scope device array, one copy per
+// GPU, kept until the process ends.  Host code never passes `scratch` itself to
+// a kernel (on the host it only names the symbol): lt_create resolves each
+// device's copy to its device address with hipGetSymbolAddress, with that
+// device current, and the entry point uses that address.
+constexpr size_t kNoallocScratchBytes = LT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch copy (dev: the current device).
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 struct lt_handle {
   hipStream_t stream = nullptr;
   int device = 0;
+  void* scratch = nullptr;             // this device's copy of `scratch` (device address)
+  hipError_t scratch_rc = hipSuccess;  // why it is null, if it is
   int max_lds = 65536;
   std::string err;
   double* pinned = nullptr;   // small host staging for readbacks (kPinnedDoubles)
@@ -1107,6 +1137,8 @@ int lt_create(lt_handle** out, void* stream) {
           hipSuccess &&
       lds > 0)
     h->max_lds = lds;
+  // the handle's device is current here: resolve its scratch copy once
+  h->scratch_rc = scratch_address(h->device, &h->scratch);
   if (hipHostMalloc((void**)&h->pinned, kPinnedDoubles * sizeof(double), hipHostMallocDefault) !=
       hipSuccess) {
     delete h;
@@ -1266,6 +1298,27 @@ int lt_svt_prox(lt_handle* h, const lt_desc* a, const float* A, double tau, floa
   if (rc) return rc;
   return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Gh, D, s.any_dft), prec, lt::PRO_PLAIN,
               lt::EPI_PLAIN, LT_PROF_INVERSE);
+}
+
+int lt_svt_prox_noalloc(lt_handle* h, const lt_desc* a, const float* A, double tau, float* D,
+                        int32_t* rank_out, int32_t* sweeps_out, const lt_svd_opts* opts) {
+  if (!h) return LT_ERR_ARG;
+  if (!h->scratch)
+    return fail(h, LT_ERR_HIP, "no device address for the static scratch on device %d: %s", h->device,
+                hipGetErrorString(h->scratch_rc));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(h, LT_ERR_ARG, "the handle belongs to device %d, the current device is %d", h->device, dev);
+  double tol;
+  int max_sweeps, prec;
+  resolve_opts(opts, &tol, &max_sweeps, &prec);
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_SVT, prec);
+  if (need > kNoallocScratchBytes)
+    return fail(h, LT_ERR_WORKSPACE,
+                "this SVT needs %zu bytes of workspace; the static scratch holds %zu (LT_NOALLOC_SCRATCH_BYTES)",
+                need, kNoallocScratchBytes);
+  // need == 0 (invalid descriptor or options): lt_svt_prox reports the reason
+  return lt_svt_prox(h, a, A, tau, D, rank_out, sweeps_out, opts, h->scratch, kNoallocScratchBytes);
 }
 
 int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b,

@@ -99,6 +99,8 @@ _sig = {
                                     ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
     "lt_svt_prox": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
                                    ctypes.POINTER(SvdOpts), _vp, ctypes.c_size_t]),
+    "lt_svt_prox_noalloc": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, ctypes.c_double, _vp, _vp, _vp,
+                                           ctypes.POINTER(SvdOpts)]),
     "lt_complete_pga": (ctypes.c_int, [_vp, ctypes.POINTER(Desc), _vp, _vp, ctypes.POINTER(PgaParams),
                                        _vp, ctypes.POINTER(PgaReport), _vp, ctypes.c_size_t]),
     "lt_problem_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Desc), ctypes.POINTER(PgaParams)]),
@@ -349,6 +351,24 @@ def svt_prox_batched(As, taus, kinds=None, jacobi_tol=0.0, max_sweeps=0, precisi
     h = _handle()
     _check(h, _lib.lt_svt_prox_batched(h, n, darr, aarr, tarr, oarr, rarr, ctypes.byref(o), _ptr(w), nb))
     return Ds, ranks
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # LT_NOALLOC_SCRATCH_BYTES
+
+
+def svt_prox_noalloc(A, tau, D, rank=None, sweeps=None, kinds=None, jacobi_tol=0.0, max_sweeps=0,
+                     precision="f32", precondition=True, fp32_dots=False):
+    """lt_svt_prox_noalloc: D_tau(A) into the caller's D (and optional int32
+    rank / sweeps tensors of P entries) with the library's static scratch as
+    workspace; allocates nothing.  Returns the status."""
+    shape = tuple(A.shape)
+    _check_tensor(A, shape, name="A")
+    _check_tensor(D, shape, name="D")
+    d = make_desc(shape, kinds)
+    h = _handle()
+    o = svd_opts(jacobi_tol, max_sweeps, precision, precondition, fp32_dots=fp32_dots)
+    return _check(h, _lib.lt_svt_prox_noalloc(h, ctypes.byref(d), _ptr(A), float(tau), _ptr(D), _ptr(rank),
+                                              _ptr(sweeps), ctypes.byref(o)))
 
 
 def lproduct(A, B, kinds=None, precision="f32", out=None, ws=None):
