@@ -88,7 +88,7 @@ typedef struct {
 /* One-sided Jacobi SVD options (Alg. 3 / Alg. 4 per-slice SVD). */
 typedef struct {
   double jacobi_tol;    /* a column pair is rotated while |a_i.a_j| > tol ||a_i|| ||a_j||;
-                           <= 0 selects 1e-6 */
+                           <= 0 selects 1e-7 */
   int32_t max_sweeps;   /* sweep limit per slice; <= 0 selects 40 */
   int32_t precision;    /* lt_precision of the transform GEMMs */
   int32_t no_precondition; /* SVT paths: 0 runs the Jacobi on the Cholesky-QR factor R^T of
@@ -109,7 +109,9 @@ typedef struct {
                            as are the column norms and the rotation angle; the columns are
                            rotated in FP32.  Nonzero: the pair dot products use FP32 products
                            and per-lane FP32 sums (FP64 across lanes) -- faster, with a
-                           rounding error of the order of a 1e-6 tolerance. */
+                           rounding error of about 1e-6 of |a_i| |a_j|, above the
+                           default tolerance: the rotate-or-skip decision near it is
+                           then decided by rounding. */
 } lt_svd_opts;
 
 /* Largest min(I1, I2) the preconditioned SVT path takes (the per-slice FP64
@@ -127,11 +129,18 @@ typedef struct {
  *   blocked (LT_SVT_BLOCKED set): the other working matrices with n <= 512 and
  *                    at most 2048 rows: columns in a per-slice working buffer of
  *                    the workspace, swept block pair by block pair by one
- *                    workgroup per slice (a much longer kernel).
+ *                    workgroup per slice (a much longer kernel);
+ *   wide (LT_SVT_BLOCKED and LT_SVT_WIDE set): working matrices beyond those,
+ *                    up to 2304 columns (preconditioned: the factor is n x n;
+ *                    otherwise also at most 2304 rows): the blocked layout with
+ *                    one workgroup per block pair and one launch per block round,
+ *                    and one host synchronisation per sweep (the 1080 x 1920 and
+ *                    2160 x 3840 video frames).  Not taken by the batch engine.
  * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only. */
 #define LT_SVT_REGISTER 0
 #define LT_SVT_PRECOND 1   /* bit */
 #define LT_SVT_BLOCKED 2   /* bit */
+#define LT_SVT_WIDE 4      /* bit (with LT_SVT_BLOCKED): the wide blocked Jacobi, see above */
 
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */

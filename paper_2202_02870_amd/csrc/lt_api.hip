@@ -282,8 +282,15 @@ int gemm(lt_handle* h, const lt::GemmArgs& g, int prec, int pro, int epi, int cl
   return LT_OK;
 }
 
+// Default Jacobi tolerance: 1e-7.  With 1e-6 the 256 x 256 noisy completion
+// (300 iterations) ended 1.7e-4 from the FP64 oracle: its clustered noise
+// singular values let the early stop (all rotations of a sweep small) fire with
+// columns still 2.5e-4 from orthogonal; 1e-7 gives 3.0e-5 there for 1% more
+// sweeps (1.5e-6 on the video workload, 5% slower).
+constexpr double kJacobiTolDefault = 1e-7;
+
 void resolve_opts(const lt_svd_opts* o, double* tol, int* max_sweeps, int* prec) {
-  *tol = (o && o->jacobi_tol > 0) ? o->jacobi_tol : 1e-6;
+  *tol = (o && o->jacobi_tol > 0) ? o->jacobi_tol : kJacobiTolDefault;
   // the kernels take FP32 pair dot products when handed the tolerance negated
   if (o && o->fp32_dots) *tol = -*tol;
   *max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 40;
@@ -318,6 +325,12 @@ struct SvtCore {
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
   double* nuc = nullptr;  // per slice: sum of (sigma_i - tau) over the kept singular values
+  // wide path: FP32 factors (precond), rebuild scratch, per-slice state, counter
+  float* L32 = nullptr;
+  float* T = nullptr;
+  void* wstate = nullptr;
+  int* active = nullptr;
+  double* thr = nullptr;
 };
 
 // Fourier modes: the transform-domain slices are complex, in two planes (real
@@ -343,6 +356,11 @@ struct SvtWs {
   double* C = nullptr;   // preconditioning: per-slice Gram matrix, then its Cholesky factor
   float* work = nullptr;  // blocked Jacobi: per-slice working buffers
   double* nuc = nullptr;  // per slice: sum of (sigma_i - tau) over the kept singular values
+  float* L32 = nullptr;   // wide path (see SvtCore)
+  float* T = nullptr;
+  void* wstate = nullptr;
+  int* active = nullptr;
+  double* thr = nullptr;
   DftWs dft;              // Fourier modes only
 };
 
@@ -406,9 +424,17 @@ constexpr int kCholLdsMaxN = 200;   // the LDS Cholesky kernel's limit
 struct SvtPlan {
   bool precond = false;
   bool blocked = false;
+  bool wide = false;      // the wide blocked Jacobi (one workgroup per block pair)
   int jm = 0, jn = 0;
   lt::JacobiBlkConfig bcfg{};
+  lt::JacobiWideConfig wcfg{};
 };
+
+// Slices beyond the single-workgroup blocked kernel (more than 512 columns or,
+// unpreconditioned, 2048 rows) take the wide blocked Jacobi: on the n x n
+// Cholesky factor up to n = kWideMaxN when preconditioning is requested, else on
+// the slice itself up to kWideMaxN rows.
+constexpr int kWideMaxN = 2304;
 
 // Preconditioning applies when requested for 2 <= n <= 200 (Cholesky in LDS),
 // and for n <= 512 when the register kernel cannot hold the slice itself: on
@@ -417,15 +443,25 @@ struct SvtPlan {
 // while a slice that needs the blocked kernel gains both fewer sweeps and, when
 // tall, a shorter working matrix.  False if no kernel takes the shape.
 bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p) {
-  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2);
-  const int n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  const long long m64 = s.I1 > s.I2 ? s.I1 : s.I2;
+  const long long n64 = s.I1 > s.I2 ? s.I2 : s.I1;
+  if (n64 > kWideMaxN || m64 > (1LL << 20)) return false;
+  const int m = (int)m64, n = (int)n64;
   p->precond = precond_req && precond_shape(s) && (n <= kCholLdsMaxN || !lt::jacobi_reg_shape(m, n));
   p->jm = p->precond ? n : m;
   p->jn = n;
   p->blocked = false;
+  p->wide = false;
   if (lt::jacobi_reg_shape(p->jm, p->jn)) return true;
-  if (lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) != 0) return false;
+  if (lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) == 0) {
+    p->blocked = true;
+    return true;
+  }
+  p->precond = precond_req && n >= 2;
+  p->jm = p->precond ? n : m;
+  if (p->jm > kWideMaxN || lt::jacobi_wide_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->wcfg) != 0) return false;
   p->blocked = true;
+  p->wide = true;
   return true;
 }
 
@@ -435,7 +471,9 @@ long long blocked_work_floats(const Shape& s) {
   long long wf = 0;
   for (int pc = 0; pc < 2; ++pc) {
     SvtPlan p;
-    if (svt_plan(s, pc != 0, &p) && p.blocked && p.bcfg.work_floats > wf) wf = p.bcfg.work_floats;
+    if (!svt_plan(s, pc != 0, &p) || !p.blocked) continue;
+    const long long f = p.wide ? p.wcfg.work_floats : p.bcfg.work_floats;
+    if (f > wf) wf = f;
   }
   return wf;
 }
@@ -456,6 +494,17 @@ void carve_svt_core(Carver& c, const Shape& s, SvtCore* w) {
   if (svt_plan(s, true, &pp) && pp.precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
   const long long wf = blocked_work_floats(s);
   if (wf) w->work = c.take<float>((size_t)s.P * (size_t)wf);
+  SvtPlan pw;
+  const bool wide = (svt_plan(s, true, &pp) && pp.wide) || (svt_plan(s, false, &pw) && pw.wide);
+  if (wide) {
+    if (pp.wide && pp.precond) {
+      w->L32 = c.take<float>((size_t)(s.P * precond_n(s) * precond_n(s)));
+      w->thr = c.take<double>((size_t)s.P);
+    }
+    w->T = c.take<float>((size_t)s.nel);
+    w->wstate = c.take<char>((size_t)s.P * lt::kWideStateBytes);
+    w->active = c.take<int>(1);
+  }
 }
 
 void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
@@ -470,6 +519,11 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
     w->C = core.C;
     w->work = core.work;
     w->nuc = core.nuc;
+    w->L32 = core.L32;
+    w->T = core.T;
+    w->wstate = core.wstate;
+    w->active = core.active;
+    w->thr = core.thr;
     return;
   }
   w->Gh = c.take<float>(2 * (size_t)s.nel);   // real plane, then imaginary plane
@@ -618,6 +672,78 @@ int rebuild_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const 
   return LT_OK;
 }
 
+// The wide blocked Jacobi SVT (many columns, few slices): Gram matrix and
+// Cholesky (multi-launch) when preconditioned, then the block rounds launched
+// sweep by sweep until every slice has converged (one host synchronisation per
+// sweep reads the number still running), then the kept columns and the rebuild
+// as two batched GEMMs (any kept count).
+int run_wide_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtCore& w, const SvtPlan& pl,
+                 double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
+                 unsigned long long* sweep_total, unsigned long long* rot_total, unsigned int* hits) {
+  if (!w.work || !w.T || !w.wstate || !w.active || (pl.precond && (!w.L32 || !w.C || !w.thr)))
+    return fail(h, LT_ERR_WORKSPACE, "no wide-Jacobi buffers in the workspace");
+  const lt::JacobiWideConfig& c = pl.wcfg;
+  if (c.lds > (size_t)h->max_lds)
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the wide Jacobi needs %zu bytes of LDS", s.I1, s.I2, c.lds);
+  lt::WideArgs a{};
+  const int n = (int)precond_n(s);
+  if (pl.precond) {
+    const long long cst = (long long)n * n;
+    ProfScope ps(h, LT_PROF_PRECOND);
+    lt::GramArgs g{Gh, s.N, w.C, cst, (int)s.I1, (int)s.I2, (int)s.P};
+    HIP_TRY(h, lt::launch_gram(g, h->stream));
+    HIP_TRY(h, lt::launch_chol_big(w.C, cst, n, (int)s.P, w.L32, cst, w.thr, h->stream));
+    a.src = w.L32;
+    a.slice_stride = cst;
+    a.I1 = n;
+    a.I2 = n;
+  } else {
+    a.src = Gh;
+    a.slice_stride = s.N;
+    a.I1 = (int)s.I1;
+    a.I2 = (int)s.I2;
+  }
+  a.nslices = (int)s.P;
+  a.work = w.work;
+  a.work_stride = c.work_floats;
+  a.state = w.wstate;
+  a.tau = tau;
+  a.tol = tol;
+  a.max_sweeps = max_sweeps;
+  a.bk = w.Bk;
+  a.bk_stride = s.N;
+  a.rank = rank;
+  a.sweeps = sweeps;
+  a.nuc = w.nuc;
+  a.sweep_total = sweep_total;
+  a.rot_total = rot_total;
+  a.hits = hits;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_wide_copy_in(a, c, h->stream));
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      HIP_TRY(h, lt::launch_wide_sweep(a, c, w.active, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(h->pinned, w.active, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+      if (*reinterpret_cast<int*>(h->pinned) == 0) break;
+    }
+    HIP_TRY(h, lt::launch_wide_out(a, c, h->stream));
+  }
+  lt::RebuildArgs r{};
+  r.W = Gh;
+  r.D = Dh;
+  r.bk = w.Bk;
+  r.rank = rank;
+  r.slice_stride = s.N;
+  r.I1 = (int)s.I1;
+  r.I2 = (int)s.I2;
+  r.nslices = (int)s.P;
+  r.flip = pl.precond ? 1 : 0;
+  ProfScope ps(h, LT_PROF_REBUILD);
+  HIP_TRY(h, lt::launch_rebuild_gemm(r, w.T, h->stream));
+  return LT_OK;
+}
+
 int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, const SvtCore& w,
                    double tau, double tol, int max_sweeps, int32_t* rank, int32_t* sweeps,
                    unsigned long long* sweep_total, unsigned long long* rot_total,
@@ -625,6 +751,8 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
   SvtPlan pl;
   if (!svt_plan(s, precond && w.C, &pl))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
+  if (pl.wide)
+    return run_wide_svt(h, s, Gh, Dh, w, pl, tau, tol, max_sweeps, rank, sweeps, sweep_total, rot_total, hits);
   precond = pl.precond;
   lt::JacobiArgs j{};
   lt::JacobiConfig cfg;
@@ -732,6 +860,11 @@ SvtCore core_of(const SvtWs& w) {
   c.C = w.C;
   c.work = w.work;
   c.nuc = w.nuc;
+  c.L32 = w.L32;
+  c.T = w.T;
+  c.wstate = w.wstate;
+  c.active = w.active;
+  c.thr = w.thr;
   return c;
 }
 
@@ -799,8 +932,14 @@ int check_svt_shape(lt_handle* h, const Shape& s0, bool precond) {
   }
   SvtPlan p;
   if (!svt_plan(s, precond, &p))
-    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels (n <= 512, m <= 2048 "
-                "without preconditioning)", s.I1, s.I2);
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels (n <= %d; without "
+                "preconditioning m <= %d)", s.I1, s.I2, kWideMaxN, kWideMaxN);
+  if (p.wide) {
+    if (p.wcfg.lds > (size_t)h->max_lds)
+      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the wide Jacobi needs %zu bytes of LDS", s.I1, s.I2,
+                  p.wcfg.lds);
+    return LT_OK;
+  }
   if (p.blocked) return check_blk_lds(h, s, p.bcfg);
   lt::JacobiConfig probe;
   Shape sq = s;
@@ -916,7 +1055,7 @@ struct BatchTables {
   bool any_reg = false;
   lt::JacobiBatchConfig cfg{};
   int prec = 0, max_sweeps = 40;
-  double tol = 1e-6;
+  double tol = kJacobiTolDefault;
   size_t rebuild_slices = 0;   // total frontal slices of the batch
 };
 
@@ -947,6 +1086,9 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     SvtPlan pl;
     if (!svt_plan(shapes[i], problem_precond(shapes[i], &probs[i].params), &pl))
       return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", shapes[i].I1, shapes[i].I2);
+    if (pl.wide)
+      return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the batch engine takes slices up to 512 columns",
+                  shapes[i].I1, shapes[i].I2);
     ms[i] = pl.jm;   // n for the Jacobi on the n x n factor
     if (problem_warm_period(shapes[i], &probs[i].params) > 0 &&
         lt::jacobi_warm_config(ns[i], h->max_lds, &wcfg[i]) == 0)
@@ -1257,7 +1399,7 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   }
   SvtPlan p;
   if (!svt_plan(s, precond_requested(opts), &p)) return LT_ERR_SHAPE;
-  return (p.precond ? LT_SVT_PRECOND : 0) | (p.blocked ? LT_SVT_BLOCKED : 0);
+  return (p.precond ? LT_SVT_PRECOND : 0) | (p.blocked ? LT_SVT_BLOCKED : 0) | (p.wide ? LT_SVT_WIDE : 0);
 }
 
 int lt_pga_warm(const lt_desc* a, const lt_svd_opts* opts) {
@@ -1765,6 +1907,8 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   if (parse(nullptr, a, &s) != LT_OK || !p || p->max_iter < 1) return 0;
   if (p->svd.precision != LT_PREC_F32 && p->svd.precision != LT_PREC_BF16X3) return 0;
   if (s.any_dft) return 0;   // the batch engine runs real transforms only
+  SvtPlan pl;
+  if (!svt_plan(s, problem_precond(s, p), &pl) || pl.wide) return 0;   // nor the wide Jacobi
   Carver c(nullptr);
   ProblemWs w;
   carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), problem_warm_period(s, p) > 0, &w);
@@ -1793,6 +1937,9 @@ int init_problem(lt_handle* h, const lt_problem* p, bool svt_only, double tau) {
   SvtPlan plan;
   if (!svt_plan(s, problem_precond(s, &p->params), &plan))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
+  if (plan.wide)
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the batch engine takes slices up to 512 columns "
+                "(wider ones run through lt_svt_prox / lt_complete_pga)", s.I1, s.I2);
   const lt::JacobiBlkConfig& bcfg = plan.bcfg;
   const bool blk = plan.blocked;
   if (blk) {

@@ -163,7 +163,132 @@ __global__ __launch_bounds__(256) void k_multirank(const double* sigma, int P, i
   }
 }
 
+// Batched FP32 GEMM for the rebuild of slices with many kept columns:
+// C_s = op(A_s) op(B_s), column-major, op(A) M x K, op(B) K x N, with the
+// slice's kept count limiting N (rank_dim 1) or K (rank_dim 2).  64 x 64 output
+// tile per workgroup, K in chunks of 16 through LDS, 4 x 4 outputs per lane,
+// FP32 accumulation.
+struct BGemm {
+  const float* A;
+  long long lda, sA;
+  int tA;
+  const float* B;
+  long long ldb, sB;
+  int tB;
+  float* C;
+  long long ldc, sC;
+  int M, N, K;
+  const int32_t* rank;
+  int rank_dim;
+};
+
+__global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int s = blockIdx.z;
+  const int r = g.rank ? g.rank[s] : 0;
+  const int N = g.rank_dim == 1 ? min(g.N, r) : g.N;
+  const int K = g.rank_dim == 2 ? min(g.K, r) : g.K;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (j0 >= N) return;
+  const float* A = g.A + (long long)s * g.sA;
+  const float* B = g.B + (long long)s * g.sB;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      // A tile: rows i0..i0+63 of op(A), columns k0..k0+15; B tile likewise
+      int kk, ii;
+      if (g.tA) { kk = e % 16; ii = e / 16; } else { ii = e % 64; kk = e / 64; }
+      const int i = i0 + ii, k = k0 + kk;
+      As[kk][ii] = (i < g.M && k < K) ? (g.tA ? A[k + (long long)i * g.lda] : A[i + (long long)k * g.lda]) : 0.f;
+      int kb, jj;
+      if (g.tB) { jj = e % 64; kb = e / 64; } else { kb = e % 16; jj = e / 16; }
+      const int j = j0 + jj, k2 = k0 + kb;
+      Bs[kb][jj] = (j < N && k2 < K) ? (g.tB ? B[j + (long long)k2 * g.ldb] : B[k2 + (long long)j * g.ldb]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        av[a] = As[kk][tx + 16 * a];
+        bv[a] = Bs[kk][ty + 16 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  float* C = g.C + (long long)s * g.sC;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = j0 + ty + 16 * b;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + tx + 16 * a;
+      if (i < g.M && j < N) C[i + (long long)j * g.ldc] = acc[a][b];
+    }
+  }
+}
+
+hipError_t bgemm(const BGemm& g, int nslices, hipStream_t s) {
+  dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), (unsigned)nslices);
+  hipLaunchKernelGGL(k_bgemm, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+// The SVT rebuild from the kept columns for any kept count, as two batched
+// GEMMs through T (P x I1 x I2 floats).  Slice S (I1 x I2); working matrix W = S
+// (I1 >= I2) or S^T.  flip 0 (Bk: m x r): D_W = Bk (Bk^T W), i.e. D = Bk (Bk^T S)
+// or D = (S Bk) Bk^T; flip 1 (B: n x r, the preconditioned path): D_W = (W B) B^T,
+// i.e. D = (S B) B^T or D = B (B^T S).
+hipError_t launch_rebuild_gemm(const RebuildArgs& r, float* T, hipStream_t s) {
+  if (r.nslices <= 0) return hipSuccess;
+  const bool trans = r.I1 < r.I2;
+  const int I1 = r.I1, I2 = r.I2;
+  const int m = trans ? I2 : I1, n = trans ? I1 : I2;
+  const long long N = (long long)I1 * I2;
+  const int rows_b = r.flip ? n : m;   // rows of the kept-column matrix
+  // left = 1: D = X (X^T S) with X the kept columns (rows I1); left = 0: D = (S X) X^T (rows I2)
+  const bool left = r.flip ? trans : !trans;
+  (void)rows_b;
+  BGemm g1{}, g2{};
+  if (left) {
+    // T = X^T S (r x I2), D = X T
+    g1.A = r.bk; g1.lda = I1; g1.sA = r.slice_stride; g1.tA = 1;
+    g1.B = r.W; g1.ldb = I1; g1.sB = r.slice_stride; g1.tB = 0;
+    g1.C = T; g1.ldc = n; g1.sC = N;
+    g1.M = n; g1.N = I2; g1.K = I1; g1.rank = r.rank; g1.rank_dim = 0;
+    // rows of T beyond the kept count are never read (K of the second product)
+    g2.A = r.bk; g2.lda = I1; g2.sA = r.slice_stride; g2.tA = 0;
+    g2.B = T; g2.ldb = n; g2.sB = N; g2.tB = 0;
+    g2.C = r.D; g2.ldc = I1; g2.sC = r.slice_stride;
+    g2.M = I1; g2.N = I2; g2.K = n; g2.rank = r.rank; g2.rank_dim = 2;
+  } else {
+    // T = S X (I1 x r), D = T X^T
+    g1.A = r.W; g1.lda = I1; g1.sA = r.slice_stride; g1.tA = 0;
+    g1.B = r.bk; g1.ldb = I2; g1.sB = r.slice_stride; g1.tB = 0;
+    g1.C = T; g1.ldc = I1; g1.sC = N;
+    g1.M = I1; g1.N = n; g1.K = I2; g1.rank = r.rank; g1.rank_dim = 1;
+    g2.A = T; g2.lda = I1; g2.sA = N; g2.tA = 0;
+    g2.B = r.bk; g2.ldb = I2; g2.sB = r.slice_stride; g2.tB = 1;
+    g2.C = r.D; g2.ldc = I1; g2.sC = r.slice_stride;
+    g2.M = I1; g2.N = I2; g2.K = n; g2.rank = r.rank; g2.rank_dim = 2;
+  }
+  hipError_t e = bgemm(g1, r.nslices, s);
+  if (e != hipSuccess) return e;
+  return bgemm(g2, r.nslices, s);
+}
 
 hipError_t launch_pad_copy(const float* src, float* dst, int rs, int cs, int rd, int cd, int P, hipStream_t s) {
   if (P <= 0) return hipSuccess;

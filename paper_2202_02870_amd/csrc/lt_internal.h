@@ -188,6 +188,41 @@ struct JacobiBlkConfig {
 int jacobi_blk_pick_config(int m, int n, int max_lds, JacobiBlkConfig* cfg);
 hipError_t launch_jacobi_blk(const JacobiArgs& a, const JacobiBlkConfig& cfg, hipStream_t s);
 
+// Wide blocked Jacobi (many columns, few slices): the blocked layout with one
+// workgroup per block pair, one launch per block round, and per-slice state on
+// the device between launches.  Host loop: launch_wide_copy_in (also clears the
+// state), launch_wide_sweep until *active (device) reads 0 after a sweep or the
+// sweep limit, then launch_wide_out (kept columns, rank, sweeps, nuc, totals as
+// the SVT mode of the other kernels).
+constexpr size_t kWideStateBytes = 32;
+struct WideArgs {
+  const float* src;        // slices (working orientation as JacobiArgs), slice s at src + s * slice_stride
+  long long slice_stride;
+  int I1, I2, nslices;
+  float* work;             // per-slice working buffers, work_stride floats each
+  long long work_stride;
+  void* state;             // nslices x kWideStateBytes
+  double tau, tol;
+  int max_sweeps;
+  float* bk;               // kept columns, slice s at bk + s * bk_stride (m x r, ld m)
+  long long bk_stride;
+  int32_t* rank;
+  int32_t* sweeps;
+  double* nuc;
+  unsigned long long* sweep_total;
+  unsigned long long* rot_total;
+  unsigned int* hits;
+};
+struct JacobiWideConfig {
+  int G, R, variant, b, nblk, qeff, threads, nbuf;
+  size_t lds;
+  long long work_floats;
+};
+int jacobi_wide_pick_config(int m, int n, int max_lds, JacobiWideConfig* cfg);
+hipError_t launch_wide_copy_in(const WideArgs& a, const JacobiWideConfig& c, hipStream_t s);
+hipError_t launch_wide_sweep(const WideArgs& a, const JacobiWideConfig& c, int* active, hipStream_t s);
+hipError_t launch_wide_out(const WideArgs& a, const JacobiWideConfig& c, hipStream_t s);
+
 // D (slice orientation) = rebuild from kept columns: D_W = Bk Bk^T W
 struct RebuildArgs {
   const float* W;          // transform-domain slices (the Jacobi input)
@@ -217,6 +252,12 @@ struct CholArgs {
 };
 size_t chol_lds_bytes(int n);
 hipError_t launch_chol(const CholArgs& a, hipStream_t s);
+// Cholesky for any n (multi-launch, many workgroups per slice): C (n x n FP64,
+// lower triangle, c_stride doubles per slice) factored in place, then the FP32
+// factor written to L (n x n per slice, l_stride floats, zero above the
+// diagonal); thr: scratch, one double per slice.
+hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, float* L, long long l_stride,
+                           double* thr, hipStream_t s);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s);
 
 // lsvd finalisation: sort, normalise, V = W^T U diag(1/sigma), write factors
@@ -240,6 +281,9 @@ hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s);
 // being scratch; multirank counts sigma (P x n) above rtol * max sigma per
 // slice into rank and writes their mean and maximum to out[0], out[1].
 hipError_t launch_pad_copy(const float* src, float* dst, int rs, int cs, int rd, int cd, int P, hipStream_t s);
+// The SVT rebuild (as launch_rebuild) for any kept count, through two batched
+// GEMMs; T: scratch of nslices x I1 x I2 floats.
+hipError_t launch_rebuild_gemm(const RebuildArgs& r, float* T, hipStream_t s);
 hipError_t launch_complete_basis(float* Q, double* H, double* beta, int m, int n, int P, hipStream_t s);
 hipError_t launch_multirank(const double* sigma, int P, int n, double rtol, int32_t* rank, double* out,
                             hipStream_t s);

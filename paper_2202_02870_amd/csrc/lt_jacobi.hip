@@ -144,6 +144,15 @@ __device__ inline double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// Hardware FP64 reciprocal square root refined by one Newton step,
+// y <- y + y (1 - x y^2) / 2 (about 1e-15 relative for the arguments >= 1 it
+// gets here: 1 + zeta^2 and 1 + t^2).
+__device__ inline double rsq64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 // The rotation that zeroes the off-diagonal entry of the 2 x 2 Gram matrix
 // [[pa, d], [d, pb]] of a column pair (d != 0), all in FP64:
 // zeta = (pb - pa) / (2 d), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) (the
@@ -155,9 +164,10 @@ __device__ inline double rcp64(double x) {
 __device__ inline void jacobi_angle(double d, double pa, double pb, double& t, float& cf, float& sf) {
   const double zeta = fmin(fmax((pb - pa) * (0.5 * rcp64(d)), -1e100), 1e100);
   const double az = fabs(zeta);
-  const double tt = rcp64(az + sqrt(fma(az, az, 1.0)));
+  const double z2 = fma(az, az, 1.0);
+  const double tt = rcp64(fma(z2, rsq64(z2), az));   // 1 / (|zeta| + sqrt(1 + zeta^2))
   t = zeta < 0.0 ? -tt : tt;
-  const double c = rcp64(sqrt(fma(tt, tt, 1.0)));
+  const double c = rsq64(fma(tt, tt, 1.0));
   cf = (float)c;
   sf = (float)(c * t);
 }
@@ -1838,6 +1848,228 @@ size_t jacobi_lds_bytes(int npairs, int ldw, int nbuf) {
   return kWgCtlBytes + slice_lds_bytes(npairs, ldw, nbuf);
 }
 
+// ---- wide blocked Jacobi: one workgroup per block pair ----------------------
+//
+// The blocked layout above (working buffer of nblk blocks of b columns, the
+// round-robin tournament over the blocks, the first block round of a sweep
+// rotating every pair inside the two blocks as well), but every block round is
+// one launch in which each block pair of each slice is a workgroup of its own:
+// a slice spreads over nblk / 2 compute units instead of one, which is what
+// slices with many columns and few of them per tensor need (the 1080 x 1920
+// and 2160 x 3840 frames).  The block pairs of one round are disjoint, so the
+// workgroups of a launch touch disjoint columns.  Per-slice state on the
+// device (WideState) carries the sweep's rotation counts between launches; a
+// sweep-end launch decides convergence (a sweep whose rotations were all small,
+// as for the other kernels), and launches skip converged slices.
+
+struct WideState {
+  int done;                     // 0 running, 1 converged, 2 stopped at max_sweeps
+  int sweeps;                   // sweeps done
+  unsigned rot, big;            // this sweep's rotations and large rotations
+  unsigned long long rot_total;
+  unsigned long long pad;
+};
+static_assert(sizeof(WideState) == kWideStateBytes, "wide state size");
+
+__device__ inline WideState* wide_state(const WideArgs& a, int s) {
+  return reinterpret_cast<WideState*>(static_cast<char*>(a.state) + (size_t)s * kWideStateBytes);
+}
+
+// Working matrix W (m x n, the slice or its transpose) into the working buffer
+// (ncols columns of mpad rows, zero beyond W): 32 x 32 tiles through LDS, read
+// along the slice's contiguous dimension, written along the buffer's.
+__global__ __launch_bounds__(256) void k_wide_copy_in(WideArgs a, int mpad, int ncols) {
+  __shared__ float tile[32][33];
+  const int s = blockIdx.z;
+  const bool trans = a.I1 < a.I2;
+  const int m = trans ? a.I2 : a.I1;
+  const int n = trans ? a.I1 : a.I2;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const float* A = a.src + (long long)s * a.slice_stride;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int rr = trans ? ty + 8 * k : tx, cc = trans ? tx : ty + 8 * k;
+    const int row = r0 + rr, col = c0 + cc;
+    float v = 0.f;
+    if (row < m && col < n) v = trans ? A[(long long)row * a.I1 + col] : A[(long long)col * a.I1 + row];
+    tile[rr][cc] = v;
+  }
+  __syncthreads();
+  float* Wk = a.work + (long long)s * a.work_stride;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int row = r0 + tx, col = c0 + ty + 8 * k;
+    if (row < mpad && col < ncols) Wk[(long long)col * mpad + row] = tile[tx][ty + 8 * k];
+  }
+}
+
+// Workgroup size of the wide kernels: 1024 lanes hold 16 rows per lane in 128
+// registers; more rows per lane take 512-lane workgroups (256 registers).
+template <int R>
+constexpr int wide_lanes() { return R <= 16 ? 1024 : 512; }
+
+// One block round: workgroup (pi, s) rotates block pair pi of round br of slice s.
+template <int G, int R>
+__global__ __launch_bounds__(wide_lanes<R>()) void k_wide_round(WideArgs a, int b, int nblk, int qeff, int nbuf, int br) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int s = blockIdx.y;
+  WideState* st = wide_state(a, s);
+  if (st->done) return;   // the whole workgroup returns
+  const int mpad = 4 * G * qeff, ldw = mpad + 4;
+  const int tps = b * G;
+  const int tid = threadIdx.x;
+  const bool active = tid < tps;
+  const int g = active ? tid / G : 0, l = tid % G;
+  int* wg_ctl = reinterpret_cast<int*>(smem);
+  float* buf = reinterpret_cast<float*>(smem + kWgCtlBytes);
+  float* bufB = nbuf == 2 ? buf + (size_t)exch_positions(b) * ldw : buf;
+  float* Wk = a.work + (long long)s * a.work_stride;
+  double tol = a.tol;
+  const bool dot32 = decode_tol(tol);
+  const int pi = blockIdx.x;
+  const int A = blk_at(pi, br, nblk), B = blk_at(nblk - 1 - pi, br, nblk);
+  int ida = A * b + g, idb = B * b + g;
+  float av[R], bv[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    av[e] = 0.f;
+    bv[e] = 0.f;
+  }
+  if (tid == 0) {
+    wg_ctl[0] = 0;
+    wg_ctl[1] = 0;
+  }
+  if (active) {
+    load_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
+    load_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
+  }
+  __syncthreads();
+  double na = group_sum<G>(dot64<R>(av, av));
+  double nb = group_sum<G>(dot64<R>(bv, bv));
+  const unsigned my_rot = sweep_rounds<G, R>(av, bv, na, nb, ida, idb, active, dot32, tol, b, g, l, qeff, buf,
+                                             bufB, nbuf, ldw, br > 0);
+  if (active) {
+    store_work_col<G, R>(Wk, mpad, ida, l, av, qeff);
+    store_work_col<G, R>(Wk, mpad, idb, l, bv, qeff);
+  }
+  if (my_rot & 0xFFFFu) atomicAdd(&wg_ctl[0], (int)(my_rot & 0xFFFFu));
+  if (my_rot >> 16) atomicAdd(&wg_ctl[1], (int)(my_rot >> 16));
+  __syncthreads();
+  if (tid == 0) {
+    if (wg_ctl[0]) atomicAdd(&st->rot, (unsigned)wg_ctl[0]);
+    if (wg_ctl[1]) atomicAdd(&st->big, (unsigned)wg_ctl[1]);
+  }
+}
+
+// End of a sweep (one thread per slice): count it, stop a slice whose
+// rotations were all small (or at the sweep limit), clear the counters, and
+// count the slices still running into *active (cleared by the host before).
+__global__ void k_wide_sweep_end(WideArgs a, int* active) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.nslices) return;
+  WideState* st = wide_state(a, s);
+  if (st->done == 0) {
+    st->sweeps += 1;
+    st->rot_total += st->rot;
+    if (st->big == 0) st->done = 1;
+    else if (st->sweeps >= a.max_sweeps) st->done = 2;
+    st->rot = 0;
+    st->big = 0;
+    if (st->done == 0) atomicAdd(active, 1);
+  }
+}
+
+// Output of a slice (one workgroup): kept columns, scaled, in column order,
+// and the slice's counts, as the blocked kernel writes them.
+template <int G, int R>
+__global__ __launch_bounds__(wide_lanes<R>()) void k_wide_out(WideArgs a, int b, int nblk, int qeff) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int s = blockIdx.x;
+  const WideState* st = wide_state(a, s);
+  const bool trans = a.I1 < a.I2;
+  const int m = trans ? a.I2 : a.I1;
+  const int n = trans ? a.I1 : a.I2;
+  const int mpad = 4 * G * qeff, ldw = mpad + 4;
+  const int ncols = nblk * b;
+  const int tps = b * G;
+  const int tid = threadIdx.x;
+  const bool active = tid < tps;
+  const int g = active ? tid / G : 0, l = tid % G;
+  float* buf = reinterpret_cast<float*>(smem + kWgCtlBytes);
+  int* ctl = reinterpret_cast<int*>(buf + (size_t)exch_positions(b) * ldw);
+  const float* Wk = a.work + (long long)s * a.work_stride;
+  float* out = a.bk + (long long)s * a.bk_stride;
+  float av[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) av[e] = 0.f;
+  if (tid == 0) ctl[2] = 0;
+  __syncthreads();
+  double nsum = 0.0;
+  double* nucs = reinterpret_cast<double*>(buf);
+  for (int c0 = 0; c0 < ncols; c0 += b) {
+    const int id = c0 + g;
+    if (active) load_work_col<G, R>(Wk, mpad, id, l, av, qeff);
+    const double sa = sqrt(group_sum<G>(dot64<R>(av, av)));
+    const bool ka = active && id < n && sa > a.tau;
+    if (active && l == 0) {
+      ctl[3 + g] = ka ? 1 : 0;
+      nucs[g] = ka ? sa - a.tau : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc = ctl[2];
+      for (int i = 0; i < b; ++i) {
+        const int c = ctl[3 + i];
+        ctl[3 + i] = acc;
+        acc += c;
+        nsum += nucs[i];
+      }
+      ctl[2] = acc;
+    }
+    __syncthreads();
+    const int d = ka ? ctl[3 + g] : -1;
+    const double sc = ka ? sqrt(1.0 - a.tau / sa) / sa : 0.0;
+    if (active) put_col<G, R>(buf, ldw, g, l, av, qeff, sc, d);
+    __syncthreads();
+    if (active) stage_out(out, buf, ldw, m, b, tid, tps);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (a.rank) a.rank[s] = ctl[2];
+    if (a.nuc) a.nuc[s] = nsum;
+    if (a.sweeps) a.sweeps[s] = st->sweeps;
+    if (a.sweep_total) atomicAdd(a.sweep_total, (unsigned long long)st->sweeps);
+    if (a.rot_total) atomicAdd(a.rot_total, st->rot_total);
+    if (st->done == 2 && a.hits) atomicAdd(a.hits, 1u);
+  }
+}
+
+template <int G, int R>
+hipError_t launch_wide_sweep_one(const WideArgs& a, const JacobiWideConfig& c, int* active, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_wide_round<G, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)c.lds);
+  if (e != hipSuccess) return e;
+  for (int br = 0; br < c.nblk - 1; ++br) {
+    hipLaunchKernelGGL((k_wide_round<G, R>), dim3(c.nblk / 2, a.nslices), dim3(c.threads), c.lds, s, a, c.b,
+                       c.nblk, c.qeff, c.nbuf, br);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = launch_fill_zero(active, sizeof(int), s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wide_sweep_end, dim3((a.nslices + 255) / 256), dim3(256), 0, s, a, active);
+  return hipGetLastError();
+}
+
+template <int G, int R>
+hipError_t launch_wide_out_one(const WideArgs& a, const JacobiWideConfig& c, hipStream_t s) {
+  const size_t lds = blk_lds_bytes(c.b, 4 * G * c.qeff + 4, 1);
+  hipError_t e = hipFuncSetAttribute((const void*)k_wide_out<G, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_wide_out<G, R>), dim3(a.nslices), dim3(c.threads), lds, s, a, c.b, c.nblk, c.qeff);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int jacobi_pick_config(int m, int n, int max_lds, JacobiConfig* cfg, int force_G) {
@@ -2218,6 +2450,76 @@ hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_rebuild<RB_RMAX>, grid, dim3(256), lds, s, b);
   }
   return hipGetLastError();
+}
+
+// Wide blocked Jacobi variants (lanes per pair G, rows per lane R): the fewest
+// lanes that hold the column at up to R rows per lane.
+constexpr int kWideNumVariants = 5;
+const int kWideVariants[kWideNumVariants][2] = {{16, 16}, {32, 16}, {64, 16}, {64, 24}, {64, 36}};
+
+int jacobi_wide_pick_config(int m, int n, int max_lds, JacobiWideConfig* cfg) {
+  if (m < 2 || n < 2 || m < n) return -1;
+  for (int vi = 0; vi < kWideNumVariants; ++vi) {
+    const int G = kWideVariants[vi][0], R = kWideVariants[vi][1];
+    const int qeff = (m + 4 * G - 1) / (4 * G);
+    if (qeff > R / 4) continue;
+    const int mpad = 4 * G * qeff, ldw = mpad + 4;
+    int b = ((R <= 16 ? 1024 : 512) / G) & ~1;   // wide_lanes<R>() lanes at most
+    while (b >= 2 && blk_lds_bytes(b, ldw, 1) > (size_t)max_lds) b -= 2;
+    if (b < 2) continue;
+    int nblk = (n + b - 1) / b;
+    nblk += nblk & 1;
+    if (nblk < 2) nblk = 2;
+    int bb = (n + nblk - 1) / nblk;   // balance the blocks
+    bb += bb & 1;
+    if (bb < 2) bb = 2;
+    cfg->G = G;
+    cfg->R = R;
+    cfg->variant = vi;
+    cfg->b = bb;
+    cfg->nblk = nblk;
+    cfg->qeff = qeff;
+    cfg->threads = ((bb * G + 63) / 64) * 64;
+    cfg->nbuf = blk_lds_bytes(bb, ldw, 2) <= (size_t)max_lds ? 2 : 1;
+    cfg->lds = blk_lds_bytes(bb, ldw, cfg->nbuf);
+    cfg->work_floats = (long long)nblk * bb * mpad;
+    return 0;
+  }
+  return -1;
+}
+
+hipError_t launch_wide_copy_in(const WideArgs& a, const JacobiWideConfig& c, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  const int mpad = 4 * c.G * c.qeff, ncols = c.nblk * c.b;
+  dim3 grid((unsigned)((ncols + 31) / 32), (unsigned)((mpad + 31) / 32), (unsigned)a.nslices);
+  hipLaunchKernelGGL(k_wide_copy_in, grid, dim3(256), 0, s, a, mpad, ncols);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fill_zero(a.state, (size_t)a.nslices * kWideStateBytes, s);
+}
+
+hipError_t launch_wide_sweep(const WideArgs& a, const JacobiWideConfig& c, int* active, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  switch (c.variant) {
+    case 0: return launch_wide_sweep_one<16, 16>(a, c, active, s);
+    case 1: return launch_wide_sweep_one<32, 16>(a, c, active, s);
+    case 2: return launch_wide_sweep_one<64, 16>(a, c, active, s);
+    case 3: return launch_wide_sweep_one<64, 24>(a, c, active, s);
+    case 4: return launch_wide_sweep_one<64, 36>(a, c, active, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_wide_out(const WideArgs& a, const JacobiWideConfig& c, hipStream_t s) {
+  if (a.nslices <= 0) return hipSuccess;
+  switch (c.variant) {
+    case 0: return launch_wide_out_one<16, 16>(a, c, s);
+    case 1: return launch_wide_out_one<32, 16>(a, c, s);
+    case 2: return launch_wide_out_one<64, 16>(a, c, s);
+    case 3: return launch_wide_out_one<64, 24>(a, c, s);
+    case 4: return launch_wide_out_one<64, 36>(a, c, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s) {

@@ -397,7 +397,180 @@ __global__ __launch_bounds__(1024) void k_chol_items(ProbDev* const* probs, cons
   chol_slice<true>(pd->C + (long long)it.slice * n * n, n);
 }
 
+// ---- Cholesky for large n (the 1080- and 2160-column frames) -----------------
+// The same right-looking blocked factorization (blocks of CG columns, pivots as
+// above), with every stage a launch over all slices and, for the panel and the
+// trailing update, many workgroups per slice: the FP64 lower triangle is
+// factored in place in global memory, then written as an FP32 factor (zero
+// above the diagonal) to its own buffer.
+
+// thr[s] = 64 n eps64 max diag(C_s): pivots at or below it zero their column.
+__global__ __launch_bounds__(256) void k_cholb_thr(const double* C, long long c_stride, int n, double* thr) {
+  __shared__ double red[4];
+  const double* Cs = C + (long long)blockIdx.x * c_stride;
+  double d = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) d = fmax(d, Cs[j + (long long)j * n]);
+  for (int o = 32; o >= 1; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    thr[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (64.0 * n * DBL_EPSILON);
+}
+
+// Diagonal block K..K+kb-1 of each slice factored in place (one wave per slice).
+__global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride, int n, int K,
+                                                  const double* thr) {
+  __shared__ double Dg[CG][CG + 1];
+  double* Cs = C + (long long)blockIdx.x * c_stride;
+  const int kb = min(CG, n - K);
+  const int lane = threadIdx.x;
+  for (int e = lane; e < kb * kb; e += 64) {
+    const int i = e % kb, j = e / kb;
+    Dg[i][j] = i >= j ? Cs[(K + i) + (long long)(K + j) * n] : 0.0;
+  }
+  wave_sync();
+  const double t = thr[blockIdx.x];
+  for (int k = 0; k < kb; ++k) {
+    const double piv = Dg[k][k];
+    const double inv = piv > t ? rsq64(piv) : 0.0;
+    if (lane > k && lane < kb) Dg[lane][k] *= inv;
+    wave_sync();
+    const int r = kb - 1 - k;
+    for (int e = lane; e < r * r; e += 64) {
+      const int ii = k + 1 + e / r, jj = k + 1 + e % r;
+      if (jj <= ii) Dg[ii][jj] = fma(-Dg[ii][k], Dg[jj][k], Dg[ii][jj]);
+    }
+    if (lane == 0) Dg[k][k] = piv * inv;
+    wave_sync();
+  }
+  for (int e = lane; e < kb * kb; e += 64) {
+    const int i = e % kb, j = e / kb;
+    if (i >= j) Cs[(K + i) + (long long)(K + j) * n] = Dg[i][j];
+  }
+}
+
+// Panel rows K+kb .. n-1: x L11^T = C(row, K..K+kb-1), solved in place, one
+// lane per row.
+__global__ __launch_bounds__(256) void k_cholb_panel(double* C, long long c_stride, int n, int K) {
+  __shared__ double Dg[CG][CG + 1];
+  __shared__ double dinv[CG];
+  double* Cs = C + (long long)blockIdx.y * c_stride;
+  const int kb = min(CG, n - K);
+  for (int e = threadIdx.x; e < kb * kb; e += 256) {
+    const int i = e % kb, j = e / kb;
+    Dg[i][j] = i >= j ? Cs[(K + i) + (long long)(K + j) * n] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < kb) {
+    const double d = Dg[threadIdx.x][threadIdx.x];
+    dinv[threadIdx.x] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+  __syncthreads();
+  const int i = K + kb + blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[CG];
+#pragma unroll
+  for (int q = 0; q < CG; ++q) x[q] = q < kb ? Cs[i + (long long)(K + q) * n] : 0.0;
+#pragma unroll
+  for (int q = 0; q < CG; ++q) {
+    if (q < kb) {
+      double acc = x[q];
+#pragma unroll
+      for (int p2 = 0; p2 < CG; ++p2)
+        if (p2 < q) acc = fma(-x[p2], Dg[q][p2], acc);
+      x[q] = acc * dinv[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CG; ++q)
+    if (q < kb) Cs[i + (long long)(K + q) * n] = x[q];
+}
+
+// Trailing update C(i, j) -= sum_q P(i, q) P(j, q) over the trailing lower
+// triangle (rows and columns K+kb ..), one 64 x 64 tile (bi >= bj) per
+// workgroup, the two panel row blocks staged in LDS, 4 x 4 outputs per lane.
+__global__ __launch_bounds__(256) void k_cholb_update(double* C, long long c_stride, int n, int K) {
+  __shared__ double Pi[64][CG + 1];
+  __shared__ double Pj[64][CG + 1];
+  double* Cs = C + (long long)blockIdx.y * c_stride;
+  const int kb = min(CG, n - K);
+  const int T0 = K + kb;
+  int bi = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
+  while ((bi + 1) * (bi + 2) / 2 <= (int)blockIdx.x) ++bi;
+  while (bi * (bi + 1) / 2 > (int)blockIdx.x) --bi;
+  const int bj = blockIdx.x - bi * (bi + 1) / 2;
+  const int i0 = T0 + 64 * bi, j0 = T0 + 64 * bj;
+  for (int e = threadIdx.x; e < 64 * CG; e += 256) {
+    const int r = e % 64, q = e / 64;
+    Pi[r][q] = (q < kb && i0 + r < n) ? Cs[(i0 + r) + (long long)(K + q) * n] : 0.0;
+    Pj[r][q] = (q < kb && j0 + r < n) ? Cs[(j0 + r) + (long long)(K + q) * n] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < kb; ++q) {
+    double pa[4], pb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      pa[a] = Pi[tx + 16 * a][q];
+      pb[a] = Pj[ty + 16 * a][q];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(pa[a], pb[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int j = j0 + ty + 16 * b;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + tx + 16 * a;
+      if (i < n && j < n && i >= j) Cs[i + (long long)j * n] -= acc[a][b];
+    }
+  }
+}
+
+// FP32 factor: L[i + j n] = C(i, j) for i >= j, 0 above the diagonal.
+__global__ __launch_bounds__(256) void k_cholb_fp32(const double* C, long long c_stride, float* L,
+                                                   long long l_stride, int n) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int j = (int)(e / n), i = (int)(e - (long long)j * n);
+  const double* Cs = C + (long long)blockIdx.y * c_stride;
+  L[(long long)blockIdx.y * l_stride + e] = i >= j ? (float)Cs[e] : 0.f;
+}
+
 }  // namespace
+
+hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, float* L, long long l_stride,
+                           double* thr, hipStream_t s) {
+  if (nslices <= 0) return hipSuccess;
+  if (n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cholb_thr, dim3(nslices), dim3(256), 0, s, C, c_stride, n, thr);
+  hipError_t e = hipGetLastError();
+  for (int K = 0; K < n && e == hipSuccess; K += CG) {
+    const int kb = n - K < CG ? n - K : CG;
+    const int t = n - K - kb;
+    hipLaunchKernelGGL(k_cholb_diag, dim3(nslices), dim3(64), 0, s, C, c_stride, n, K, thr);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    if (t <= 0) break;
+    hipLaunchKernelGGL(k_cholb_panel, dim3((t + 255) / 256, nslices), dim3(256), 0, s, C, c_stride, n, K);
+    if ((e = hipGetLastError()) != hipSuccess) break;
+    const int T64 = (t + 63) / 64;
+    hipLaunchKernelGGL(k_cholb_update, dim3(T64 * (T64 + 1) / 2, nslices), dim3(256), 0, s, C, c_stride, n, K);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  const long long nn = (long long)n * n;
+  hipLaunchKernelGGL(k_cholb_fp32, dim3((unsigned)((nn + 255) / 256), nslices), dim3(256), 0, s, C, c_stride,
+                     L, l_stride, n);
+  return hipGetLastError();
+}
 
 size_t chol_lds_bytes(int n) { return (size_t)n * (n + 1) / 2 * sizeof(double); }
 

@@ -63,7 +63,8 @@ class ProblemC(ctypes.Structure):
 
 
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
-SVT_PATHS = ("register", "precond", "blocked", "precond+blocked")   # LT_SVT_PRECOND / LT_SVT_BLOCKED bits
+SVT_PATHS = ("register", "precond", "blocked", "precond+blocked",   # LT_SVT_PRECOND / LT_SVT_BLOCKED bits
+             None, None, "blocked+wide", "precond+blocked+wide")    # ... and LT_SVT_WIDE
 
 
 class Profile(ctypes.Structure):
@@ -279,8 +280,9 @@ def multirank(A, kinds=None, rtol=1e-5, jacobi_tol=0.0, max_sweeps=0, precision=
 def svt_path(shape, kinds=None, precondition=True):
     """How the SVT of these slices runs: "register" (register-resident Jacobi
     on the slice), "precond" (on its Cholesky-QR factor), "blocked" (blocked
-    Jacobi on the slice) or "precond+blocked" (blocked, on the factor); host
-    only, LtError if no kernel takes the shape."""
+    Jacobi on the slice), "precond+blocked" (blocked, on the factor), and
+    "blocked+wide" / "precond+blocked+wide" (the wide blocked Jacobi, one
+    workgroup per block pair); host only, LtError if no kernel takes the shape."""
     d = make_desc(tuple(shape), kinds)
     o = svd_opts(precondition=precondition)
     st = _lib.lt_svt_path(ctypes.byref(d), ctypes.byref(o))

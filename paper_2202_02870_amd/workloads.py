@@ -170,6 +170,22 @@ def config3(n=64, seed=3, max_iter=100):
     return probs
 
 
+FRAME_SHAPES = {1080: (1080, 1920), 2160: (2160, 3840)}
+
+
+def config_frames(height=1080, frames=2, rank=10, observed=0.1, seed=6):
+    """Large-frame completion: height x width x 3 x frames of L-rank `rank`
+    (DCT along modes 3 and 4), factors U[0,1] rescaled to [0,1], `observed`
+    fraction observed (Table 9's 1080 x 1920 and 2160 x 3840 colour frames;
+    sr 0.1 as in the GPU experiments); continuation schedule as the video
+    workload.  Frontal slices are 1080 x 1920 or 2160 x 3840."""
+    I1, I2 = FRAME_SHAPES[height]
+    p = make_problem((I1, I2, 3, frames), rank, observed, seed=seed,
+                     name="frames-%dx%dx3x%d-r%d-obs%g" % (I1, I2, frames, rank, observed))
+    p.schedule = dict(pga_schedule_params(p.M, p.mask), max_iter=100, tol=0.0)
+    return p
+
+
 LARGE_REQUEST_SHAPE = (512, 512, 3, 64)
 
 

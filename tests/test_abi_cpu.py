@@ -108,7 +108,16 @@ def test_svt_path_by_shape():
     assert lt.svt_path((100, 80, 4), ("dft",)) == "precond"                 # 200 x 160
     assert lt.svt_path((100, 80, 4), ("dft",), precondition=False) == "register"
     assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "precond+blocked"   # 288 x 352
-    for bad, pc in (((2048, 2048), True), ((513, 513), True), ((3000, 16), False), ((2049, 300), False)):
+    # beyond the one-workgroup blocked kernel: the wide blocked Jacobi (one
+    # workgroup per block pair), on the factor up to n = 2304, on the slice up
+    # to 2304 rows; the 1080 x 1920 and 2160 x 3840 frames
+    assert lt.svt_path((513, 513)) == "precond+blocked+wide"
+    assert lt.svt_path((2048, 2048)) == "precond+blocked+wide"
+    assert lt.svt_path((1080, 1920, 3, 2)) == "precond+blocked+wide"
+    assert lt.svt_path((2160, 3840, 3, 2)) == "precond+blocked+wide"
+    assert lt.svt_path((2049, 300), precondition=False) == "blocked+wide"
+    assert lt.svt_path((1080, 1920, 3, 2), precondition=False) == "blocked+wide"
+    for bad, pc in (((2305, 2305), True), ((3000, 16), False), ((2160, 3840), False), ((4000, 2400), True)):
         with pytest.raises(lt.LtError):
             lt.svt_path(bad, precondition=pc)
 

@@ -1,0 +1,75 @@
+"""GPU tests of the wide blocked Jacobi (one workgroup per block pair, one
+launch per block round) and the multi-launch Cholesky: slices beyond the
+one-workgroup kernels, up to the 1080 x 1920 and 2160 x 3840 frames of the
+paper's GPU experiments (Table 9), against the FP64 oracle slice by slice.
+The rebuild of these slices is two batched GEMMs, so kept counts beyond 512
+are covered too."""
+import numpy as np
+import pytest
+
+import oracle as o
+import parity
+from paper_2202_02870_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_02870_amd import lt as _lt
+    return _lt
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("shape,kinds,precondition,q", [
+    ((600, 520, 2), ("dct",), True, 0.5),        # factor 520 x 520 (beyond the 512-column kernel)
+    ((520, 600, 2), ("dct",), False, 0.5),       # the slice itself, transposed working matrix
+    ((700, 530, 3), ("identity",), True, 0.05),  # 504 of 530 values kept: kept count beyond 512
+    ((1080, 1920, 2), ("dct",), True, 0.5),      # 1080 x 1920 frames, 540 kept
+    ((2160, 3840, 1), ("dct",), True, 0.9),      # one 2160 x 3840 frame
+])
+def test_svt_wide_matches_oracle(lt, shape, kinds, precondition, q):
+    rng = np.random.default_rng(sum(shape))
+    mats = o.mats_for(shape, list(kinds))
+    A = rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    tau = float(np.quantile(s, q))
+    path = lt.svt_path(shape, kinds, precondition=precondition)
+    assert "wide" in path
+    D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=precondition)
+    ref = o.svt(A, tau, mats)
+    say("wide svt", shape, kinds, path, "ranks", lt.to_host(rank), "sweeps", lt.to_host(sweeps))
+    parity.check(lt.to_host(D), ref, 2e-5, label=str(shape))
+    assert np.array_equal(lt.to_host(rank), np.asarray(o.svt_ranks(A, tau, mats)))
+
+
+@pytest.mark.timeout(600)
+def test_pga_frames_1080(lt):
+    """Completion of 1080 x 1920 x 2 frames (order 3) through the wide path, 6
+    iterations at a fixed threshold (nonzero iterates from the first), against
+    the oracle."""
+    import torch
+    p = wl.make_problem((1080, 1920, 2), 8, 0.2, seed=61, name="frames-1080x1920x2")
+    tau = 0.05 * float(np.linalg.norm(p.M * p.mask)) / np.sqrt(2)
+    assert "wide" in lt.svt_path(p.shape, p.kinds)
+    params = lt.pga_params(mu0=tau, fixed_mu=True, max_iter=6)
+    X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
+    Xo, _ = o.complete_pga(p.M, p.mask, o.mats_for(p.shape, ["dct"]), mu0=tau, fixed_mu=True, max_iter=6)
+    assert np.linalg.norm(Xo) > 0
+    say("frames pga: mean sweeps", rep["total_sweeps"] / rep["total_slices"])
+    parity.check(lt.to_host(X), Xo, 1e-4, label="frames 1080x1920x2")
+
+
+def test_wide_refused_by_batch_engine(lt):
+    import torch
+    M = np.zeros((600, 520, 2))
+    mask = np.ones(M.shape, np.uint8)
+    with pytest.raises(ValueError):
+        lt.Problem(lt.to_device(M), lt.to_device(mask, torch.uint8), lt.pga_params(mu0=1.0, max_iter=2))
