@@ -122,9 +122,11 @@ def main():
     ap.add_argument("--start", type=int, default=None,
                     help="untimed iterations before the warm-up (default 100 video/large, 20 big)")
     ap.add_argument("--precision", default="f32", choices=["f32", "bf16x3"])
-    ap.add_argument("--workload", default="video", choices=["video", "large", "big", "mix", "serve"])
+    ap.add_argument("--workload", default="video", choices=["video", "large", "big", "frames", "mix", "serve"])
+    ap.add_argument("--frame-height", type=int, default=1080, choices=[1080, 2160],
+                    help="frames workload: 1080 x 1920 or 2160 x 3840 frontal slices")
     ap.add_argument("--legs", default="all",
-                    help="video workload: extra legs, comma list of job,large,mix,serve, 'all' or 'none'")
+                    help="video workload: extra legs, comma list of job,large,frames,mix,serve, 'all' or 'none'")
     ap.add_argument("--large-frac", type=float, default=0.1,
                     help="serve workload: share of 512x512x3x64 requests")
     ap.add_argument("--no-lanes", action="store_true",
@@ -152,9 +154,9 @@ def main():
                     help="mix workload: Jacobi lanes per column pair (4..64, 0 = built-in, auto = timed)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"video": 200, "large": 100, "big": 30, "mix": 50, "serve": 0}[args.workload]
+        args.steps = {"video": 200, "large": 100, "big": 30, "frames": 10, "mix": 50, "serve": 0}[args.workload]
     if args.start is None:
-        args.start = {"video": 100, "large": 100, "big": 20}.get(args.workload, 0)
+        args.start = {"video": 100, "large": 100, "big": 20, "frames": 10}.get(args.workload, 0)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -176,9 +178,10 @@ def main():
     line = bench_completion(args, torch, lt, wl)
     if args.workload == "video" and args.transform == "dct":
         legs = set() if args.legs == "none" else (
-            {"large", "mix", "serve", "job"} if args.legs == "all" else set(args.legs.split(",")))
+            {"large", "frames", "mix", "serve", "job"} if args.legs == "all" else set(args.legs.split(",")))
         extra = {}
-        for name, fn in (("job", leg_job), ("large", leg_large), ("mix", leg_mix), ("serve", leg_serve)):
+        for name, fn in (("job", leg_job), ("large", leg_large), ("frames", leg_frames), ("mix", leg_mix),
+                         ("serve", leg_serve)):
             if name in legs:
                 say("leg", name)
                 try:
@@ -258,6 +261,8 @@ def gpu_iterate(lt, M, mask, p, precision, iters, fp32_dots=False):
 def bench_completion(args, torch, lt, wl):
     if args.workload == "video":
         p = wl.config1(transform=args.transform)
+    elif args.workload == "frames":
+        p = wl.config_frames(args.frame_height)
     else:
         p = {"large": wl.config2, "big": wl.config4_large}[args.workload]()
     shape = p.shape
@@ -327,8 +332,10 @@ def bench_completion(args, torch, lt, wl):
         "kernel_calls": {k: v[0] for k, v in prof.items()},
         "roofline": roofline,
     }
-    cpu_iters = args.cpu_iters if args.cpu_iters is not None else {"video": 30, "large": 10, "big": 1}[args.workload]
-    cpu_1t = args.cpu_iters_1t if args.cpu_iters_1t is not None else {"video": 5, "large": 2, "big": 0}[args.workload]
+    cpu_iters = args.cpu_iters if args.cpu_iters is not None else \
+        {"video": 30, "large": 10, "big": 1, "frames": 0}[args.workload]
+    cpu_1t = args.cpu_iters_1t if args.cpu_iters_1t is not None else \
+        {"video": 5, "large": 2, "big": 0, "frames": 0}[args.workload]
     if not args.no_cpu_baseline and cpu_iters > 0:
         import oracle as o
         say("oracle on the host:", cpu_iters, "iterations, all threads")
@@ -397,6 +404,25 @@ def leg_large(args, torch, lt, wl):
                      "rel_err_vs_oracle_at_%d" % k_or: float(np.linalg.norm(Xg - Xo) / nrm) if nrm > 0 else None,
                      "bound": 1e-4 if prec == "f32" else 1e-2}
     return out
+
+
+def leg_frames(args, torch, lt, wl):
+    """The 1080 x 1920 x 3 x 2 frames (six slices of 1080 x 1920, sr 0.1):
+    iterations 11..15 of a run timed (the wide blocked Jacobi on the 1080 x 1080
+    Cholesky factors); parity of this path is in tests/test_gpu_wide.py."""
+    p = wl.config_frames(1080)
+    M = lt.to_device(p.M)
+    mask = lt.to_device(p.mask, dtype=torch.uint8)
+    X = lt.fortran_empty(p.shape)
+    ws = torch.empty(lt.workspace_bytes(p.shape, p.kinds, "pga"), dtype=torch.uint8, device="cuda")
+    a = argparse.Namespace(**vars(args))
+    a.no_precondition, a.warm_restart, a.pmc_calibrate = False, 0, False
+    dt, rep, prof, window = run_window(lt, M, mask, p, X, ws, a, "f32", 9, 1, 5)
+    P = wl.n_slices(p.shape)
+    return {"workload": p.name, "iters_per_s": round(5 / dt, 3), "timed_iterations": list(window),
+            "slice_svt_per_s": round(5 * P / dt, 2), "svt_path": lt.svt_path(p.shape, p.kinds),
+            "mean_sweeps": round(rep["total_sweeps"] / rep["total_slices"], 3),
+            "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()}}
 
 
 def leg_mix(args, torch, lt, wl):

@@ -1,11 +1,14 @@
 """Autotuner for the batched Jacobi SVT kernel.
 
 The kernel's main free parameter is the number of lanes G that hold one column
-pair (the rows per lane follow from it); one value serves a whole batch launch.
-For a set of slice shapes, each feasible G is timed on synthetic slices of
-exactly those shapes (one problem per distinct shape class, random data, a
-fixed number of Jacobi sweeps so every candidate does the same work), with the
-library's HIP-event kernel timing; the fastest is cached per shape signature.
+pair (the rows per lane follow from it); one value serves a whole batch: the
+register-resident items' launch and, where their kernel takes it (4, 8 or 16
+lanes), the warm-started items' launches.  For a set of slice shapes, each
+feasible G is timed on synthetic problems of exactly those shape classes (random
+data, the completion's default options, so the same kernels run as in the
+batch; a fixed number of Jacobi sweeps so every candidate does the same work),
+with the library's HIP-event timing of all Jacobi launches of a tick; the
+fastest is cached per shape signature, and the table can be saved and loaded.
 """
 import json
 import os

@@ -453,7 +453,9 @@ bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p) {
   p->blocked = false;
   p->wide = false;
   if (lt::jacobi_reg_shape(p->jm, p->jn)) return true;
-  if (lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) == 0) {
+  const char* env = getenv("LT_WIDE");   // 1: the wide kernel also for the blocked kernel's shapes
+  const bool prefer_wide = env && atoi(env) == 1;
+  if (!prefer_wide && lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) == 0) {
     p->blocked = true;
     return true;
   }
@@ -1061,6 +1063,10 @@ struct BatchTables {
 
 int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, BatchTables* T) {
   if (n <= 0 || !probs) return fail(h, LT_ERR_ARG, "empty batch");
+  if (force_G == 0) {
+    const char* env = getenv("LT_JACOBI_G");
+    force_G = env ? atoi(env) : 0;
+  }
   std::vector<Shape> shapes(n);
   std::vector<int> ms(n), ns(n), nsub(n, 1), qeff(n, 1);
   std::vector<int> blocked(n, 0);
@@ -1090,8 +1096,10 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
       return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the batch engine takes slices up to 512 columns",
                   shapes[i].I1, shapes[i].I2);
     ms[i] = pl.jm;   // n for the Jacobi on the n x n factor
+    // the lane count asked for (autotuner) applies to the warm-started items
+    // too when their kernel takes it (4, 8 or 16 lanes per pair)
     if (problem_warm_period(shapes[i], &probs[i].params) > 0 &&
-        lt::jacobi_warm_config(ns[i], h->max_lds, &wcfg[i]) == 0)
+        lt::jacobi_warm_config(ns[i], h->max_lds, &wcfg[i], force_G) == 0)
       warm[i] = 1;
     if (pl.blocked) {
       int rc2 = check_blk_lds(h, shapes[i], pl.bcfg);
@@ -1099,10 +1107,6 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
       blocked[i] = 1;
       bcfg[i] = pl.bcfg;
     }
-  }
-  if (force_G == 0) {
-    const char* env = getenv("LT_JACOBI_G");
-    force_G = env ? atoi(env) : 0;
   }
   // the register-resident kernel's configuration covers the other problems
   std::vector<int> rm, rn, ridx;

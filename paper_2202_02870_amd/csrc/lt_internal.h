@@ -159,7 +159,7 @@ struct WarmArgs {
 };
 // Configuration for n x n factors (0 on success, -1 if the kernel cannot hold
 // them), launch, and the product M = L Z (LDS bytes it needs).
-int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg);
+int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg, int force_G = 0);
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& cfg, hipStream_t s);
 size_t warm_product_lds_bytes(int n);
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,

@@ -2153,12 +2153,12 @@ static hipError_t launch_warm_g(const WarmArgs& a, const JacobiConfig& c, hipStr
 }
 
 // The warm kernel's columns hold 2 npad rows (M, then Z), at most 36 per lane.
-int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg) {
+int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg, int force_G) {
   if (n < 2 || n > RB_RMAX) return -1;
   const int npairs = (n + 1) / 2;
   const int rows = 2 * ((n + 3) / 4) * 4;
   const int Gs[3] = {16, 8, 4};
-  int pick = 0, fallback = 0;
+  int pick = 0, fallback = 0, forced = 0;
   for (int i = 0; i < 3; ++i) {
     const int G = Gs[i];
     const int threads = ((npairs * G + 63) / 64) * 64;
@@ -2168,8 +2168,11 @@ int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg) {
     if (jacobi_lds_bytes(npairs, G * R + 4, 1) > (size_t)max_lds) continue;
     if (R >= 8 && !pick) pick = G;
     fallback = G;
+    if (G == force_G) forced = G;
   }
-  const int G = pick ? pick : fallback;
+  // a requested lane count (autotuner) when it holds the factor, else the
+  // fewest-lanes choice with at least 8 rows per lane
+  const int G = forced ? forced : (pick ? pick : fallback);
   if (!G) return -1;
   int R = (rows + G - 1) / G;
   R = ((R + 3) / 4) * 4;

@@ -138,6 +138,13 @@ class CompletionServer:
     ticks' worth of idle work, never by iterations: finished problems are
     skipped on the device).
 
+    Admission: the arrived requests are admitted in order of HBM footprint,
+    smallest first, while they fit the budget (the most requests resident, the
+    small ones not held behind large ones); a request that has waited max_wait
+    seconds goes ahead of the others in arrival order, and while such a request
+    does not fit nothing behind it is admitted, so memory frees up for it
+    (large requests are not starved).
+
     Lanes (when the executor has `lane`, `busy`): lane 0 is stepped and polled
     every round; every other lane runs asynchronously: it is polled, rebuilt
     and given new ticks (lane_ticks per enqueue) only when its previous ticks
@@ -146,8 +153,9 @@ class CompletionServer:
     """
 
     def __init__(self, executor, hbm_budget, ticks_per_round=1, clock=None, on_finish=None,
-                 lane_ticks=1):
+                 lane_ticks=1, max_wait=2.0):
         self.ex = executor
+        self.max_wait = float(max_wait)
         self.on_finish = on_finish      # called with each finished request
         self.budget = int(hbm_budget)
         self.ticks = int(ticks_per_round)
@@ -193,14 +201,24 @@ class CompletionServer:
         return True
 
     def _admit(self, now):
-        """Admit arrived requests in arrival order; a request that does not fit
-        lets later, smaller ones in (backfill)."""
+        """Admit arrived requests by footprint, smallest first; requests that
+        waited max_wait seconds first, in arrival order (see the class)."""
+        arrived = []
+        while self.waiting and self.waiting[0][0] <= now:
+            arrived.append(heapq.heappop(self.waiting))
+
+        def order(item):
+            arr, rid = item
+            aged = now - arr >= self.max_wait
+            return (0, arr, rid) if aged else (1, self.requests[rid].footprint, rid)
+
+        arrived.sort(key=order)
         admitted = []
         skipped = []
-        while self.waiting and self.waiting[0][0] <= now:
-            arr, rid = heapq.heappop(self.waiting)
+        blocked = False   # an aged request does not fit: hold the rest back
+        for arr, rid in arrived:
             req = self.requests[rid]
-            if self.used + req.footprint <= self.budget:
+            if not blocked and self.used + req.footprint <= self.budget:
                 req.handle = self.ex.make(req)
                 req.admitted = now
                 self.used += req.footprint
@@ -210,6 +228,8 @@ class CompletionServer:
                 self.dirty.add(req.lane)
             else:
                 skipped.append((arr, rid))
+                if now - arr >= self.max_wait:
+                    blocked = True
         for item in skipped:
             heapq.heappush(self.waiting, item)
         return admitted

@@ -452,8 +452,8 @@ def test_error_paths(lt):
     assert np.isfinite(lt.to_host(X)).all()
     with pytest.raises(ValueError):
         lt.svt_prox(A, 0.1, ws=torch.empty(16, dtype=torch.uint8, device="cuda"))
-    with pytest.raises(lt.LtError) as e:              # 2048 x 2048 slices exceed the kernel
-        lt.svt_prox(lt.fortran_empty((2048, 2048)), 0.1)
+    with pytest.raises(lt.LtError) as e:              # 2305 x 2305 slices exceed every kernel
+        lt.svt_prox(lt.fortran_empty((2305, 2305)), 0.1)
     assert e.value.status == lt.ERR_SHAPE
     with pytest.raises(lt.LtError) as e:
         lt.svt_prox(A, -1.0)

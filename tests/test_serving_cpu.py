@@ -108,6 +108,37 @@ def test_admission_respects_budget_and_backfills():
     assert len(srv.done) == 3
 
 
+def test_admission_orders_by_footprint_and_ages():
+    """Arrived requests go in smallest footprint first; one that waited
+    max_wait seconds goes first and holds smaller ones back until it fits."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    big, mid, small = (16, 16, 4), (8, 8, 4), (4, 4, 2)
+    budget = 16 * (16 * 16 * 4) + 16 * (8 * 8 * 4)        # the big one and the mid one fit together
+    srv = serving.CompletionServer(ex, hbm_budget=budget, clock=clock, max_wait=1e9)
+    reqs = [_req(0, 0.0, big, 6, 10), _req(1, 0.0, mid, 6, 11), _req(2, 0.0, small, 6, 12)]
+    for r in reqs:
+        srv.submit(r)
+    srv.step()
+    # smallest first: small and mid are admitted, big does not fit beside them
+    assert [r.rid for r in srv.running] == [2, 1]
+    srv.run()
+    assert len(srv.done) == 3 and srv.peak_used <= budget
+    # aging: the big request has waited, so it goes first and the later small
+    # ones wait for memory instead of overtaking it again
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    srv = serving.CompletionServer(ex, hbm_budget=budget, clock=clock, max_wait=2.0)
+    first = [_req(0, 0.0, mid, 8, 13), _req(1, 0.0, mid, 8, 14)]
+    later = [_req(2, 0.0, big, 6, 15), _req(3, 3.0, small, 4, 16), _req(4, 3.0, small, 4, 17)]
+    for r in first + later:
+        srv.submit(r)
+    srv.run()
+    done = {r.rid: r for r in srv.done}
+    assert len(done) == 5 and srv.peak_used <= budget
+    assert done[2].admitted <= done[3].admitted and done[2].admitted <= done[4].admitted
+
+
 def test_oversized_request_is_rejected():
     clock = FakeClock()
     srv = serving.CompletionServer(FakeExecutor(clock), hbm_budget=1000, clock=clock)
