@@ -130,13 +130,17 @@ typedef struct {
  *                    at most 2048 rows: columns in a per-slice working buffer of
  *                    the workspace, swept block pair by block pair by one
  *                    workgroup per slice (a much longer kernel);
- *   wide (LT_SVT_BLOCKED and LT_SVT_WIDE set): working matrices beyond those,
- *                    up to 2304 columns (preconditioned: the factor is n x n;
- *                    otherwise also at most 2304 rows): the blocked layout with
- *                    one workgroup per block pair and one launch per block round,
- *                    and one host synchronisation per sweep (the 1080 x 1920 and
- *                    2160 x 3840 video frames).  Not taken by the batch engine.
- * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only. */
+ *   wide (LT_SVT_BLOCKED and LT_SVT_WIDE set): the blocked layout with one
+ *                    workgroup per block pair and one launch per block round,
+ *                    and one host synchronisation per sweep, up to 2304 columns
+ *                    (preconditioned: the factor is n x n; otherwise also at most
+ *                    2304 rows; the 1080 x 1920 and 2160 x 3840 video frames).
+ *                    lt_svt_prox and lt_complete_pga run every working matrix
+ *                    the register-resident kernel cannot hold through it; the
+ *                    batch engine (graph-captured ticks) uses the one-workgroup
+ *                    blocked kernel up to 512 columns and refuses wider slices.
+ * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only.
+ * lt_svt_path reports the single-problem calls' choice. */
 #define LT_SVT_REGISTER 0
 #define LT_SVT_PRECOND 1   /* bit */
 #define LT_SVT_BLOCKED 2   /* bit */

@@ -442,7 +442,15 @@ constexpr int kWideMaxN = 2304;
 // completion iterates measured) do not pay for the global-memory Cholesky,
 // while a slice that needs the blocked kernel gains both fewer sweeps and, when
 // tall, a shorter working matrix.  False if no kernel takes the shape.
-bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p) {
+// batch: the batch engine's choice (its ticks are captured as graphs: the
+// one-workgroup blocked kernel up to 512 columns, never the wide kernel, which
+// synchronises the host once per sweep); otherwise (lt_svt_prox,
+// lt_complete_pga, ...) every shape beyond the register-resident kernel takes
+// the wide kernel, which spreads a slice over nblk / 2 workgroups (measured:
+// the 512 x 512 x 3 x 64 request 10.0 -> 12.4 iterations/s, the Fourier video's
+// 288 x 288 factors 28 -> 63); LT_WIDE=0 in the environment restores the
+// one-workgroup kernel there.
+bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p, bool batch = false) {
   const long long m64 = s.I1 > s.I2 ? s.I1 : s.I2;
   const long long n64 = s.I1 > s.I2 ? s.I2 : s.I1;
   if (n64 > kWideMaxN || m64 > (1LL << 20)) return false;
@@ -453,8 +461,8 @@ bool svt_plan(const Shape& s, bool precond_req, SvtPlan* p) {
   p->blocked = false;
   p->wide = false;
   if (lt::jacobi_reg_shape(p->jm, p->jn)) return true;
-  const char* env = getenv("LT_WIDE");   // 1: the wide kernel also for the blocked kernel's shapes
-  const bool prefer_wide = env && atoi(env) == 1;
+  const char* env = getenv("LT_WIDE");
+  const bool prefer_wide = !batch && !(env && atoi(env) == 0);
   if (!prefer_wide && lt::jacobi_blk_pick_config(p->jm, p->jn, kBlkLdsBudget, &p->bcfg) == 0) {
     p->blocked = true;
     return true;
@@ -975,7 +983,7 @@ struct ProblemWs {
 // ask for it (the default) and its slices allow it.
 bool problem_precond(const Shape& s, const lt_pga_params* p) {
   SvtPlan pl;
-  return svt_plan(s, precond_requested(&p->svd), &pl) && pl.precond;
+  return svt_plan(s, precond_requested(&p->svd), &pl, true) && pl.precond;
 }
 
 // A batch problem warm-starts its Jacobi as lt_complete_pga does (same shapes,
@@ -1001,7 +1009,7 @@ void carve_problem(Carver& c, const Shape& s, int prec, int max_iter, bool preco
   w->scratch = c.take<unsigned int>(4);
   if (precond) w->C = c.take<double>((size_t)(s.P * precond_n(s) * precond_n(s)));
   SvtPlan pl;
-  if (svt_plan(s, precond, &pl) && pl.blocked) w->work = c.take<float>((size_t)s.P * (size_t)pl.bcfg.work_floats);
+  if (svt_plan(s, precond, &pl, true) && pl.blocked) w->work = c.take<float>((size_t)s.P * (size_t)pl.bcfg.work_floats);
   if (warm) w->Z = c.take<float>((size_t)(s.P * precond_n(s) * precond_n(s)));
 }
 
@@ -1090,7 +1098,7 @@ int build_tables(lt_handle* h, int n, const lt_problem* probs, int force_G, Batc
     ms[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I1 : shapes[i].I2);
     ns[i] = (int)(shapes[i].I1 > shapes[i].I2 ? shapes[i].I2 : shapes[i].I1);
     SvtPlan pl;
-    if (!svt_plan(shapes[i], problem_precond(shapes[i], &probs[i].params), &pl))
+    if (!svt_plan(shapes[i], problem_precond(shapes[i], &probs[i].params), &pl, true))
       return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", shapes[i].I1, shapes[i].I2);
     if (pl.wide)
       return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the batch engine takes slices up to 512 columns",
@@ -1912,7 +1920,7 @@ size_t lt_problem_workspace_bytes(const lt_desc* a, const lt_pga_params* p) {
   if (p->svd.precision != LT_PREC_F32 && p->svd.precision != LT_PREC_BF16X3) return 0;
   if (s.any_dft) return 0;   // the batch engine runs real transforms only
   SvtPlan pl;
-  if (!svt_plan(s, problem_precond(s, p), &pl) || pl.wide) return 0;   // nor the wide Jacobi
+  if (!svt_plan(s, problem_precond(s, p), &pl, true) || pl.wide) return 0;   // nor the wide Jacobi
   Carver c(nullptr);
   ProblemWs w;
   carve_problem(c, s, p->svd.precision, p->max_iter, problem_precond(s, p), problem_warm_period(s, p) > 0, &w);
@@ -1939,7 +1947,7 @@ int init_problem(lt_handle* h, const lt_problem* p, bool svt_only, double tau) {
   if ((rc = check_prec(h, prec))) return rc;
   if ((rc = check_dft(h, s, prec, false))) return rc;
   SvtPlan plan;
-  if (!svt_plan(s, problem_precond(s, &p->params), &plan))
+  if (!svt_plan(s, problem_precond(s, &p->params), &plan, true))
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the Jacobi kernels", s.I1, s.I2);
   if (plan.wide)
     return fail(h, LT_ERR_SHAPE, "slice %lld x %lld: the batch engine takes slices up to 512 columns "

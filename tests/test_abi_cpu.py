@@ -93,21 +93,30 @@ def test_svt_path_by_shape():
     assert lt.svt_path((256, 256, 3, 100)) == "register"          # register kernel holds it: no factor
     assert lt.svt_path((600, 256, 2)) == "precond"                  # it does not: 256 x 256 factor
     assert lt.svt_path((256, 256, 3, 100), precondition=False) == "register"
-    assert lt.svt_path((512, 512, 3, 64)) == "precond+blocked"
-    assert lt.svt_path((512, 512, 3, 64), precondition=False) == "blocked"
+    # beyond the register-resident kernel, the single-problem calls take the
+    # wide blocked kernel (LT_WIDE=0: the one-workgroup blocked kernel)
+    assert lt.svt_path((512, 512, 3, 64)) == "precond+blocked+wide"
+    assert lt.svt_path((512, 512, 3, 64), precondition=False) == "blocked+wide"
     assert lt.svt_path((600, 128, 2)) == "precond"
-    assert lt.svt_path((600, 128, 2), precondition=False) == "blocked"
-    assert lt.svt_path((128, 600, 2), precondition=False) == "blocked"   # transposed working matrix
+    assert lt.svt_path((600, 128, 2), precondition=False) == "blocked+wide"
+    assert lt.svt_path((128, 600, 2), precondition=False) == "blocked+wide"   # transposed working matrix
     assert lt.svt_path((1024, 64)) == "precond"
     assert lt.svt_path((1024, 64), precondition=False) == "register"
-    assert lt.svt_path((2048, 300)) == "precond+blocked"
-    assert lt.svt_path((2048, 300), precondition=False) == "blocked"
+    assert lt.svt_path((2048, 300)) == "precond+blocked+wide"
+    assert lt.svt_path((2048, 300), precondition=False) == "blocked+wide"
+    os.environ["LT_WIDE"] = "0"
+    try:
+        assert lt.svt_path((512, 512, 3, 64)) == "precond+blocked"
+        assert lt.svt_path((2048, 300), precondition=False) == "blocked"
+        assert lt.svt_path((1080, 1920, 3, 2)) == "precond+blocked+wide"   # beyond the one-workgroup kernel
+    finally:
+        del os.environ["LT_WIDE"]
     assert lt.svt_path((3000, 16)) == "precond"                     # any column length on the factor
     assert lt.svt_path((1, 7)) == "register"                        # n = 1: nothing to factor
     # Fourier modes: the Jacobi runs on 2 I1 x 2 I2 real embeddings
     assert lt.svt_path((100, 80, 4), ("dft",)) == "precond"                 # 200 x 160
     assert lt.svt_path((100, 80, 4), ("dft",), precondition=False) == "register"
-    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "precond+blocked"   # 288 x 352
+    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "precond+blocked+wide"   # 288 x 352
     # beyond the one-workgroup blocked kernel: the wide blocked Jacobi (one
     # workgroup per block pair), on the factor up to n = 2304, on the slice up
     # to 2304 rows; the 1080 x 1920 and 2160 x 3840 frames

@@ -1,8 +1,10 @@
-"""GPU parity of the blocked Jacobi kernel (slices with more than 256 columns,
+"""GPU parity of the blocked Jacobi kernels (slices with more than 256 columns,
 or columns too long for the register-resident kernel) and of the
 global-memory Cholesky of the preconditioned path (n > 200): SVT, completion
 and the batch engine against the FP64 oracle, on the slices themselves and on
-their Cholesky factors, alone equal to in a mix."""
+their Cholesky factors, alone equal to in a mix.  The single-problem calls
+run both blocked kernels: the wide one (their default: one workgroup per block
+pair) and, with LT_WIDE=0, the one-workgroup kernel the batch engine uses."""
 import numpy as np
 import pytest
 
@@ -25,6 +27,16 @@ def say(*a):
     print(*a, flush=True)
 
 
+@pytest.fixture(params=["wide", "one-workgroup"])
+def kernel(request, monkeypatch):
+    """Which blocked kernel the single-problem calls take (read per call)."""
+    if request.param == "one-workgroup":
+        monkeypatch.setenv("LT_WIDE", "0")
+    else:
+        monkeypatch.delenv("LT_WIDE", raising=False)
+    return request.param
+
+
 def rel(a, b):
     return float(np.linalg.norm((np.asarray(a, np.float64) - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
@@ -40,8 +52,8 @@ BLK_SHAPES = [((512, 512, 2), ("dct",)), ((300, 280, 3), ("dct",)), ((260, 600, 
 
 @pytest.mark.parametrize("precondition", [False, True])
 @pytest.mark.parametrize("shape,kinds", BLK_SHAPES)
-def test_svt_blocked_matches_oracle(lt, shape, kinds, precondition):
-    say("svt blocked", shape, kinds, lt.svt_path(shape, kinds, precondition=precondition))
+def test_svt_blocked_matches_oracle(lt, kernel, shape, kinds, precondition):
+    say("svt blocked", kernel, shape, kinds, lt.svt_path(shape, kinds, precondition=precondition))
     rng = np.random.default_rng(110)
     r = 12
     mats = o.mats_for(shape, list(kinds))
@@ -62,7 +74,7 @@ def test_svt_blocked_matches_oracle(lt, shape, kinds, precondition):
 
 
 @pytest.mark.parametrize("precondition", [False, True])
-def test_svt_blocked_rank_deficient(lt, precondition):
+def test_svt_blocked_rank_deficient(lt, kernel, precondition):
     """Zero slice, rank one, repeated columns: zero pairs never rotate (and the
     Cholesky zeroes the dependent columns) and the exact ranks come out."""
     rng = np.random.default_rng(111)
@@ -79,7 +91,7 @@ def test_svt_blocked_rank_deficient(lt, precondition):
 
 
 @pytest.mark.parametrize("precondition", [False, True])
-def test_pga_blocked_fixed_threshold(lt, precondition):
+def test_pga_blocked_fixed_threshold(lt, kernel, precondition):
     """512 x 512 x 3 completion with a fixed threshold (the iterate carries rank
     from the first iteration), 12 iterations against the oracle."""
     import torch
@@ -96,7 +108,7 @@ def test_pga_blocked_fixed_threshold(lt, precondition):
 
 
 @pytest.mark.parametrize("precondition", [False, True])
-def test_pga_blocked_continuation(lt, precondition):
+def test_pga_blocked_continuation(lt, kernel, precondition):
     """300 x 280 x 2 x 2 completion with the continuation schedule, 40 iterations."""
     import torch
     p = wl.make_problem((300, 280, 2, 2), 5, 0.4, seed=113)
