@@ -93,8 +93,8 @@ typedef struct {
   int32_t precision;    /* lt_precision of the transform GEMMs */
   int32_t no_precondition; /* SVT paths: 0 runs the Jacobi on the Cholesky-QR factor R^T of
                               each slice with 2 <= n <= 200 (n = min(I1, I2)), and with
-                              n <= LT_PRECOND_MAX_N where the slice itself would need the
-                              blocked kernel (fewer sweeps, same result to the Jacobi
+                              any larger n where the slice itself would need the blocked
+                              or the wide kernel (fewer sweeps, same result to the Jacobi
                               tolerance); nonzero runs it on the slice itself.  lt_lsvd
                               always uses the slice itself. */
   int32_t warm_restart; /* lt_complete_pga on preconditioned slices of real transforms held by
@@ -114,8 +114,10 @@ typedef struct {
                            then decided by rounding. */
 } lt_svd_opts;
 
-/* Largest min(I1, I2) the preconditioned SVT path takes (the per-slice FP64
- * Cholesky runs in LDS up to n = 200, in global memory beyond). */
+/* Largest min(I1, I2) the one-workgroup preconditioned paths take (the
+ * per-slice FP64 Cholesky runs in LDS up to n = 200, in global memory up to
+ * 512); beyond it the wide path factors each slice's Gram matrix by a
+ * multi-launch blocked Cholesky, up to 2304 columns. */
 #define LT_PRECOND_MAX_N 512
 
 /* Jacobi kernels of the per-slice SVD (Alg. 3 / Alg. 4), chosen by slice shape

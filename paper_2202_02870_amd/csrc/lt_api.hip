@@ -398,9 +398,10 @@ Shape embed_shape(const Shape& s, int npairs) {
   return e;
 }
 
-// The preconditioned SVT path takes slices with 2 <= n <= LT_PRECOND_MAX_N
-// (the Cholesky of the n x n Gram matrix runs in LDS up to n = 200, in global
-// memory beyond).
+// The one-workgroup preconditioned SVT paths take slices with
+// 2 <= n <= LT_PRECOND_MAX_N (the Cholesky of the n x n Gram matrix runs in LDS
+// up to n = 200, in global memory beyond); the wide path preconditions wider
+// slices with its own multi-launch Cholesky (svt_plan).
 static_assert(LT_PRECOND_MAX_N == 512, "the Cholesky kernels take n <= 512");
 
 bool precond_shape(const Shape& s) {
@@ -930,9 +931,9 @@ double nuclear_alpha(const Shape& s) {
   return a;
 }
 
-// The SVT of this shape is supported: by the preconditioned path (any m, n up
-// to LT_PRECOND_MAX_N), by the register-resident Jacobi kernel on the slice
-// itself, or by the blocked kernel (n <= 512, m <= 2048).
+// The SVT of this shape is supported by one of the Jacobi kernels svt_plan
+// chooses (register-resident, blocked or wide; on the slice itself or on its
+// Cholesky-QR factor) and fits the device's LDS.
 int check_svt_shape(lt_handle* h, const Shape& s0, bool precond) {
   Shape s = s0;
   if (s0.any_dft) {

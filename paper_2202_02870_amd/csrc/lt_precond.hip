@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_gram_tiles(ProbDev* const* probs, const
 
 __device__ inline int tri_off(int j, int n) { return j * n - (j * (j - 1)) / 2; }   // column j of a packed lower triangle
 
-constexpr int CH_NMAX = 200;   // largest n (= LT_PRECOND_MAX_N)
+constexpr int CH_NMAX = 200;   // largest n of the Cholesky in LDS
 constexpr int CB = 16;         // block width
 
 // 1 / sqrt(x) for x > 0: hardware estimate and two Newton steps (FP64 accuracy)
