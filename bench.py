@@ -296,6 +296,10 @@ def bench_completion(args, torch, lt, wl):
     k64, k32 = kernel_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
                             dot32=args.fp32_dots, rot_rows=rot_rows)
     tk_peak = (k64 / PEAK_FP64_VALU + k32 / PEAK_FP32_VALU) / max(jcalls, 1)
+    # the slices run side by side, one workgroup each: a launch lasts as long as
+    # its slowest slice, whose sweeps per iteration are reported beside the mean
+    mean_sw = rep["total_sweeps"] / max(rep["total_slices"], 1)
+    slowest = rep["slowest_sweeps"] / max(rep["iters"], 1)
     default_cfg = (args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
                    and warm and not args.fp32_dots)
     roofline = {"bound": "alu", "kernel": "k_jacobi_warm" if warm else "k_jacobi",
@@ -308,6 +312,9 @@ def bench_completion(args, torch, lt, wl):
                 "flops_per_launch": flops, "time_at_peak_us": round(t_peak * 1e6, 2),
                 "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
                 "frac_kernel_count": round(tk_peak / t_launch, 4) if t_launch > 0 else None,
+                "slowest_slice_sweeps": round(slowest, 3),
+                "frac_at_slowest_sweeps": round(t_peak * slowest / mean_sw / t_launch, 4)
+                if t_launch > 0 and mean_sw > 0 else None,
                 "slice": [jm, jn], "jacobi_rows": rows, "rotated_rows": rot_rows, "preconditioned": precond,
                 "warm_start": warm, "svt_path": path, "pair_dots": "fp32" if args.fp32_dots else "fp64"}
     line = {
@@ -327,7 +334,8 @@ def bench_completion(args, torch, lt, wl):
                    "schedule": "mu0=0.9||P_Omega M||, nu=0.9, mu_bar=1e-4 mu0",
                    "timed_iterations": list(window)},
         "slice_svt_per_s": round(value * P, 1),
-        "mean_sweeps": round(rep["total_sweeps"] / max(rep["total_slices"], 1), 3),
+        "mean_sweeps": round(mean_sw, 3),
+        "slowest_slice_sweeps": round(slowest, 3),
         "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()},
         "kernel_calls": {k: v[0] for k, v in prof.items()},
         "roofline": roofline,

@@ -172,7 +172,10 @@ typedef struct {
   int32_t iters;          /* iterations performed */
   int32_t converged;      /* 1 if the stopping rule fired */
   int32_t max_sweeps_hit; /* number of slice SVDs that stopped at max_sweeps */
-  int32_t reserved;
+  int32_t slowest_sweeps; /* lt_complete_pga: the largest sweep count among the slices of each
+                             iteration, summed over the iterations (the slices run side by
+                             side, so a Jacobi launch lasts as long as its slowest slice);
+                             0 from lt_problem_status */
   double last_crit;       /* last evaluated stopping ratio (inf if X = 0; NaN if never evaluated) */
   int64_t total_sweeps;   /* Jacobi sweeps summed over all slices and iterations */
   int64_t total_slices;   /* slice SVDs performed (iters x P) */

@@ -592,6 +592,7 @@ struct PgaWs {
   double* norms = nullptr;
   double* nucsum = nullptr;
   unsigned long long* sweep_total = nullptr;
+  unsigned long long* slowest_total = nullptr;   // per-iteration largest slice sweep count, summed
   unsigned long long* rot_total = nullptr;
   unsigned int* maxsweep_hits = nullptr;
   unsigned int* nonfinite = nullptr;
@@ -609,6 +610,7 @@ void carve_pga(Carver& c, const Shape& s, int prec, PgaWs* w) {
   w->norms = c.take<double>(2);
   w->nucsum = c.take<double>(1);
   w->sweep_total = c.take<unsigned long long>(1);
+  w->slowest_total = c.take<unsigned long long>(1);
   w->rot_total = c.take<unsigned long long>(1);
   w->maxsweep_hits = c.take<unsigned int>(1);
   w->nonfinite = c.take<unsigned int>(1);
@@ -1802,8 +1804,10 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     HIP_TRY(h, hipMemsetAsync(Xprev, 0, bytes, st));
   }
   HIP_TRY(h, hipMemsetAsync(w.sweep_total, 0, sizeof(unsigned long long), st));
+  HIP_TRY(h, hipMemsetAsync(w.slowest_total, 0, sizeof(unsigned long long), st));
   HIP_TRY(h, hipMemsetAsync(w.rot_total, 0, sizeof(unsigned long long), st));
   HIP_TRY(h, hipMemsetAsync(w.maxsweep_hits, 0, sizeof(unsigned int), st));
+  const int nsvd = (int)(s.any_dft ? w.svt.dft.npairs : s.P);   // slice SVDs per iteration
 
   const int check_every = p->check_every > 0 ? p->check_every : 1;
   const int restart = p->svd.warm_restart == 0 ? kWarmRestartDefault : p->svd.warm_restart;
@@ -1844,7 +1848,7 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
     if ((rc = gemm(h, b, prec, lt::PRO_PLAIN, lt::EPI_PGA, LT_PROF_INVERSE, &np))) return rc;
     {
       ProfScope ps(h, LT_PROF_OTHER);
-      HIP_TRY(h, lt::launch_reduce_partials(w.partials, np, w.norms, st));
+      HIP_TRY(h, lt::launch_reduce_partials(w.partials, np, w.norms, st, w.svt.sweeps, nsvd, w.slowest_total));
     }
     float* tmp = Xcur;   // X^{k+1} now lives in the old X^{k-1} buffer
     Xcur = Xprev;
@@ -1889,6 +1893,8 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
                             hipMemcpyDeviceToHost, st));
   HIP_TRY(h, hipMemcpyAsync(h->pinned + 4, w.rot_total, sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipMemcpyAsync(h->pinned + 6, w.slowest_total, sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, st));
   HIP_TRY(h, hipStreamSynchronize(st));
   const double num = h->pinned[0], den = h->pinned[1];
   crit = den > 0 ? sqrt(num) / sqrt(den) : INFINITY;
@@ -1898,15 +1904,17 @@ int lt_complete_pga(lt_handle* h, const lt_desc* a, const float* M, const uint8_
   memcpy(&hits, h->pinned + 3, sizeof(hits));
   unsigned long long rots;
   memcpy(&rots, h->pinned + 4, sizeof(rots));
+  unsigned long long slowest;
+  memcpy(&slowest, h->pinned + 6, sizeof(slowest));
   if (rep) {
     rep->iters = iters;
     rep->converged = converged ? 1 : 0;
     rep->max_sweeps_hit = (int32_t)hits;
-    rep->reserved = 0;
+    rep->slowest_sweeps = (int32_t)(slowest > 0x7fffffffULL ? 0x7fffffffULL : slowest);
     rep->last_crit = crit;
     rep->total_sweeps = (int64_t)sweeps_total;
     // slice SVDs performed: one per conjugate pair under Fourier modes
-    rep->total_slices = (int64_t)iters * (s.any_dft ? w.svt.dft.npairs : s.P);
+    rep->total_slices = (int64_t)iters * nsvd;
     rep->total_rotations = (int64_t)rots;
     rep->nuclear_norm = alpha > 0 ? h->pinned[5] : NAN;
   }
@@ -2083,7 +2091,7 @@ int lt_problem_status(lt_handle* h, const lt_problem* p, lt_pga_report* rep, int
     rep->iters = d.iter;
     rep->converged = d.done == 1;
     rep->max_sweeps_hit = (int32_t)d.maxsweep_hits;
-    rep->reserved = 0;
+    rep->slowest_sweeps = 0;
     rep->last_crit = d.iter > 0 ? d.crit : NAN;
     rep->total_sweeps = (int64_t)d.sweep_total;
     rep->total_slices = (int64_t)d.iter * s.P;

@@ -69,8 +69,9 @@ struct KronDesc {
 hipError_t launch_build_kron(const KronDesc& d, int P, int inverse, float* K,
                              uint16_t* Khi, uint16_t* Klo, hipStream_t s);
 
-hipError_t launch_reduce_partials(const double* partials, int n, double* out2,
-                                  hipStream_t s);
+hipError_t launch_reduce_partials(const double* partials, int n, double* out2, hipStream_t s,
+                                  const int32_t* sweeps = nullptr, int nsl = 0,
+                                  unsigned long long* slowest = nullptr);
 // Transforms with Fourier modes (kind 1 in KronDesc), stacked real form:
 // forward [Re K; Im K] (2P x P), inverse [Re K^{-1}, -Im K^{-1}] (P x 2P).
 hipError_t launch_build_kron_dft(const KronDesc& d, int P, int inverse, float* K, hipStream_t s);

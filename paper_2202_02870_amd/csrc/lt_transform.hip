@@ -431,7 +431,12 @@ __global__ __launch_bounds__(256) void k_sum_scaled(const double* v, int n, doub
   if (threadIdx.x == 0) *out = scale * a;
 }
 
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n, double* out) {
+// Also, when sweeps is given, adds the largest of the nsl per-slice sweep counts
+// of this iteration to *slowest (the Jacobi launch lasts as long as its slowest
+// slice).
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n, double* out,
+                                                         const int32_t* sweeps, int nsl,
+                                                         unsigned long long* slowest) {
   double s1 = 0.0, s2 = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
     s1 += p[2 * i];
@@ -441,6 +446,16 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* p, int n,
   if (threadIdx.x == 0) {
     out[0] = s1;
     out[1] = s2;
+  }
+  if (sweeps) {
+    __shared__ int smax[4];
+    int m = 0;
+    for (int i = threadIdx.x; i < nsl; i += 256) m = max(m, sweeps[i]);
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      *slowest += (unsigned long long)max(max(smax[0], smax[1]), max(smax[2], smax[3]));
   }
 }
 
@@ -578,8 +593,9 @@ hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const double* partials, int n, double* out2, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out2);
+hipError_t launch_reduce_partials(const double* partials, int n, double* out2, hipStream_t s,
+                                  const int32_t* sweeps, int nsl, unsigned long long* slowest) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, n, out2, sweeps, nsl, slowest);
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ class PgaParams(ctypes.Structure):
 
 class PgaReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("max_sweeps_hit", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_sweeps_hit", ctypes.c_int32), ("slowest_sweeps", ctypes.c_int32),
                 ("last_crit", ctypes.c_double), ("total_sweeps", ctypes.c_int64),
                 ("total_slices", ctypes.c_int64), ("total_rotations", ctypes.c_int64),
                 ("nuclear_norm", ctypes.c_double)]
@@ -475,7 +475,8 @@ def profile_end():
 def _report(rep):
     return dict(iters=rep.iters, converged=bool(rep.converged), max_sweeps_hit=rep.max_sweeps_hit,
                 last_crit=rep.last_crit, total_sweeps=rep.total_sweeps, total_slices=rep.total_slices,
-                total_rotations=rep.total_rotations, nuclear_norm=rep.nuclear_norm)
+                total_rotations=rep.total_rotations, nuclear_norm=rep.nuclear_norm,
+                slowest_sweeps=rep.slowest_sweeps)
 
 
 class Problem:

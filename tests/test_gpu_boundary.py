@@ -150,6 +150,25 @@ def test_pga_report_nuclear_norm(lt, shape, kinds):
     assert abs(rep["nuclear_norm"] - nn) <= 2e-5 * nn
 
 
+def test_pga_report_slowest_sweeps(lt):
+    """rep.slowest_sweeps sums, over the iterations, the largest sweep count
+    among the slices: at least the mean, at most the sweep limit, and exactly
+    iterations x limit when every slice runs to the limit."""
+    import torch
+    p = wl.make_problem((48, 40, 3, 2), 3, 0.5, seed=13)
+    sch = wl.pga_schedule_params(p.M, p.mask)
+    M, mask = lt.to_device(p.M), lt.to_device(p.mask, torch.uint8)
+    _, rep, _ = lt.complete_pga(M, mask, lt.pga_params(mu0=sch["mu0"], nu=sch["nu"], mu_bar=sch["mu_bar"],
+                                                         max_iter=12))
+    P = 6
+    say("slowest sweeps", rep["slowest_sweeps"], "total", rep["total_sweeps"])
+    assert rep["total_sweeps"] / P <= rep["slowest_sweeps"] <= 12 * 40
+    assert rep["slowest_sweeps"] >= 12
+    _, rep, _ = lt.complete_pga(M, mask, lt.pga_params(mu0=sch["mu0"], nu=sch["nu"], mu_bar=sch["mu_bar"],
+                                                         max_iter=5, jacobi_tol=1e-300, max_sweeps=3))
+    assert rep["slowest_sweeps"] == 5 * 3 and rep["total_sweeps"] == 5 * 3 * P
+
+
 def test_batch_status_nuclear_norm(lt):
     import torch
     p = wl.make_problem((40, 36, 3, 2), 3, 0.5, seed=12)
