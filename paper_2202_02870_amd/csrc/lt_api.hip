@@ -782,15 +782,21 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
     // scaled right singular vectors B, and D_W = (W B) B^T
     const int n = (int)precond_n(s);
     const long long cst = (long long)n * n;
-    {
+    if (n <= lt::kGramCholMaxN) {
       ProfScope ps(h, LT_PROF_PRECOND);
       lt::GramArgs g{Gh, s.N, w.C, cst, (int)s.I1, (int)s.I2, (int)s.P};
-      HIP_TRY(h, lt::launch_gram(g, h->stream));
-    }
-    {
-      ProfScope ps(h, LT_PROF_PRECOND);
-      lt::CholArgs c{w.C, cst, n, (int)s.P};
-      HIP_TRY(h, lt::launch_chol(c, h->stream));
+      HIP_TRY(h, lt::launch_gram_chol(g, h->stream));
+    } else {
+      {
+        ProfScope ps(h, LT_PROF_PRECOND);
+        lt::GramArgs g{Gh, s.N, w.C, cst, (int)s.I1, (int)s.I2, (int)s.P};
+        HIP_TRY(h, lt::launch_gram(g, h->stream));
+      }
+      {
+        ProfScope ps(h, LT_PROF_PRECOND);
+        lt::CholArgs c{w.C, cst, n, (int)s.P};
+        HIP_TRY(h, lt::launch_chol(c, h->stream));
+      }
     }
     Shape sq = s;
     sq.I1 = n;

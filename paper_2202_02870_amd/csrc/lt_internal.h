@@ -253,6 +253,11 @@ struct CholArgs {
 };
 size_t chol_lds_bytes(int n);
 hipError_t launch_chol(const CholArgs& a, hipStream_t s);
+// Gram matrix and Cholesky in one launch (one workgroup per slice, the Gram on
+// FP64 MFMA into LDS): the same L as launch_gram + launch_chol, for
+// min(I1, I2) <= kGramCholMaxN; C receives only L (FP32, first half).
+constexpr int kGramCholMaxN = 176;
+hipError_t launch_gram_chol(const GramArgs& g, hipStream_t s);
 // Cholesky for any n (multi-launch, many workgroups per slice): C (n x n FP64,
 // lower triangle, c_stride doubles per slice) factored in place, then the FP32
 // factor written to L (n x n per slice, l_stride floats, zero above the

@@ -1162,10 +1162,52 @@ __device__ __attribute__((always_inline)) inline void warm_product_body(const fl
   }
 }
 
-__global__ __launch_bounds__(1024) void k_warm_product(const float* L, long long l_stride, const float* Z,
-                                                       float* M, long long m_stride, int n, int cb) {
-  warm_product_body(L + (long long)blockIdx.x * l_stride, Z + (long long)blockIdx.x * n * n,
-                    M + (long long)blockIdx.x * m_stride, n, cb);
+// M = L Z for every slice on FP32 MFMA (16x16x4): one 16 x 16 tile of M per
+// wave, many waves per slice.  The tile is formed as its transpose,
+// M^T = Z^T L^T, so that lane l's results are consecutive rows of the
+// column-major M (A[i][k] = Z(k, c0 + i), B[k][j] = L(r0 + j, k); lane l holds
+// D[4 (l / 16) + q][l % 16] = M(r0 + l % 16, c0 + 4 (l / 16) + q)).  Within a
+// chunk of 16 contraction indices, lane group g = l / 16 supplies k = 4 g + s at
+// step s, so each lane reads four consecutive entries of its Z column.  L is
+// lower triangular: a tile of rows r0 .. r0 + 15 stops at k = r0 + 15.
+typedef float wp_v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_warm_product_mfma(const float* L, long long l_stride, const float* Z,
+                                                            float* M, long long m_stride, int n, int nb,
+                                                            int nslices) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long job = (long long)blockIdx.x * 4 + wave;
+  const long long tiles = (long long)nb * nb;
+  const int s = (int)(job / tiles);
+  if (s >= nslices) return;
+  const int t = (int)(job - (long long)s * tiles);
+  const int r0 = 16 * (t % nb), c0 = 16 * (t / nb);
+  const float* Ls = L + (long long)s * l_stride;
+  const float* Zs = Z + (long long)s * n * n;
+  float* Ms = M + (long long)s * m_stride;
+  const int lr = lane & 15, g = lane >> 4;
+  const int zc = c0 + lr;   // the Z column this lane reads
+  const int lrow = r0 + lr; // the L row this lane reads
+  const int kend = n < r0 + 16 ? n : r0 + 16;
+  wp_v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < kend; k0 += 16) {
+    float za[4], lb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * g + u;
+      za[u] = (zc < n && k < kend) ? Zs[(long long)zc * n + k] : 0.f;
+      lb[u] = (lrow < n && k < kend) ? Ls[(long long)k * n + lrow] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(za[u], lb[u], acc, 0, 0, 0);
+  }
+  if (lrow < n) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int mc = c0 + 4 * g + q;
+      if (mc < n) Ms[(long long)mc * n + lrow] = acc[q];
+    }
+  }
 }
 
 // Whether a batch problem's Jacobi starts cold this iteration (Z = I, M = L).
@@ -2257,12 +2299,11 @@ hipError_t launch_warm_product_items(ProbDev* const* probs, const CholItem* item
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
                                long long m_stride, int n, int nslices, int max_lds, hipStream_t s) {
   if (nslices <= 0) return hipSuccess;
-  const int cb = warm_product_cb(n, (size_t)max_lds);
-  const size_t lds = warm_product_lds(n, cb);
-  if (lds > (size_t)max_lds) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_warm_product, dim3(nslices), dim3(1024), lds, s, L, l_stride, Z, M, m_stride, n, cb);
+  (void)max_lds;
+  const int nb = (n + 15) / 16;
+  const long long jobs = (long long)nslices * nb * nb;
+  hipLaunchKernelGGL(k_warm_product_mfma, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, s, L, l_stride, Z, M,
+                     m_stride, n, nb, nslices);
   return hipGetLastError();
 }
 

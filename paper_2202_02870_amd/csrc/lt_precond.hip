@@ -241,6 +241,293 @@ __device__ __attribute__((always_inline)) void chol_slice(double* Cs, int n) {
   }
 }
 
+// ---- Tiled LDS Cholesky (n <= CT_NMAX) -----------------------------------------
+// The same factorization (right-looking, blocks of CT = 16 columns, pivots at
+// or below 64 n eps64 max diag(C) zero their column), with the matrix held in
+// LDS as 16 x 16 tiles (tile (ti, tj), ti >= tj, column-major inside, the
+// diagonal tiles full and symmetric, padding beyond n set to the identity):
+//   (a) one wave factors the diagonal tile in registers: lane j + 16 g holds
+//       rows 4 g .. 4 g + 3 of column j of the symmetric tile; step k
+//       broadcasts column k within each 16-lane row (DPP) and row k of column
+//       j (= column k of row j, by symmetry) across the row groups, so every
+//       step is a rank-1 update in registers with no LDS round trip;
+//   (b) every lane solves one row of the panel tiles below against it;
+//   (c) the trailing tiles get C -= X_i X_j^T on FP64 MFMA (16x16x4, exact
+//       FP64 products and sums), one tile per wave at a time.
+constexpr int CT = 16;
+constexpr int CT_NMAX = 192;    // 78 tiles + the current factor: the LDS of one CU
+
+__host__ __device__ inline int ct_ntiles(int nb) { return nb * (nb + 1) / 2; }
+__device__ inline int ct_index(int ti, int tj) { return ti * (ti + 1) / 2 + tj; }
+__host__ __device__ inline size_t ct_lds_bytes(int n) {
+  const int nb = (n + CT - 1) / CT;
+  return ((size_t)ct_ntiles(nb) * CT * CT + CT * CT + CT) * sizeof(double);
+}
+
+// row index of entry t of a packed lower triangle of tiles (t = ti (ti + 1) / 2 + tj)
+__device__ inline int ct_row(int t) {
+  int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+  while (ti * (ti + 1) / 2 > t) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  return ti;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+typedef double ct_v4d __attribute__((ext_vector_type(4)));
+
+// Lane k of each 16-lane row to the whole row (DPP row_newbcast), FP64.
+template <int K>
+__device__ inline double row_bcast_k(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + K, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + K, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double row_bcast(double v, int k) {
+  switch (k) {
+    case 0: return row_bcast_k<0>(v);
+    case 1: return row_bcast_k<1>(v);
+    case 2: return row_bcast_k<2>(v);
+    case 3: return row_bcast_k<3>(v);
+    case 4: return row_bcast_k<4>(v);
+    case 5: return row_bcast_k<5>(v);
+    case 6: return row_bcast_k<6>(v);
+    case 7: return row_bcast_k<7>(v);
+    case 8: return row_bcast_k<8>(v);
+    case 9: return row_bcast_k<9>(v);
+    case 10: return row_bcast_k<10>(v);
+    case 11: return row_bcast_k<11>(v);
+    case 12: return row_bcast_k<12>(v);
+    case 13: return row_bcast_k<13>(v);
+    case 14: return row_bcast_k<14>(v);
+    default: return row_bcast_k<15>(v);
+  }
+}
+
+// Factor the tiles already in LDS (padding set) and write L in FP32 (n x n
+// column-major, zero above the diagonal) to L.
+__device__ __attribute__((always_inline)) void chol_tiles_factor(double* T, int n, float* L) {
+  __shared__ double dmax_s;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = (n + CT - 1) / CT;
+  const int ntl = ct_ntiles(nb);
+  double* L11 = T + (size_t)ntl * CT * CT;   // the current diagonal factor, column-major
+  double* dinv = L11 + CT * CT;              // its pivot reciprocals (0: zeroed column)
+  if (tid < 64) {   // max of the diagonal, one wave
+    double d = 0.0;
+    for (int j = tid; j < n; j += 64) d = fmax(d, T[(size_t)ct_index(j / CT, j / CT) * CT * CT + (CT + 1) * (j % CT)]);
+    for (int o = 32; o >= 1; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+    if (tid == 0) dmax_s = d;
+  }
+  __syncthreads();
+  const double thr = dmax_s * (64.0 * n * DBL_EPSILON);
+  const int wave = tid >> 6, lane = tid & 63, nwv = nt >> 6;
+  for (int tk = 0; tk < nb; ++tk) {
+    // (a) the diagonal tile, by wave 0: lane (j, g) = j + 16 g holds rows
+    // 4 g .. 4 g + 3 of column j of the symmetric tile
+    if (wave == 0) {
+      double* D = T + (size_t)ct_index(tk, tk) * CT * CT;
+      const int j = lane & 15, g = lane >> 4;
+      double c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = D[(4 * g + u) + CT * j];
+#pragma unroll
+      for (int k = 0; k < CT; ++k) {
+        const int kg = k >> 2, ku = k & 3;
+        const double piv = readlane_d(c[ku], k + 16 * kg);
+        const double inv = piv > thr ? rsq64(piv) : 0.0;   // 1 / L(k, k); 0 zeroes the column
+        double tik[4];   // T(4 g + u, k): column k's rows of this row group, from lane (k, g)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tik[u] = row_bcast(c[u], k);
+        const double tkj = __shfl(c[ku], j + 16 * kg, 64);   // T(k, j) = T(j, k)
+        if (j > k) {
+          // T(i, j) -= L(i, k) L(j, k) = T(i, k) T(k, j) / T(k, k), rows i > k
+          const double w = tkj * (inv * inv);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (4 * g + u > k) c[u] = fma(-tik[u], w, c[u]);
+        } else if (j == k) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = 4 * g + u;
+            c[u] = i < k ? 0.0 : (i == k ? piv * inv : tik[u] * inv);
+          }
+        }
+        if (lane == 0) dinv[k] = inv;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        D[(4 * g + u) + CT * j] = c[u];
+        L11[(4 * g + u) + CT * j] = c[u];
+      }
+    }
+    __syncthreads();
+    // (b) panel rows: x L11^T = c for each row of the tiles (ti, tk), ti > tk
+    const int prows = (nb - tk - 1) * CT;
+    for (int e = tid; e < prows; e += nt) {
+      const int ti = tk + 1 + (e >> 4), r = e & 15;
+      double* X = T + (size_t)ct_index(ti, tk) * CT * CT;
+      double x[CT];
+#pragma unroll
+      for (int q = 0; q < CT; ++q) {
+        double acc = X[r + CT * q];
+#pragma unroll
+        for (int p = 0; p < q; ++p) acc = fma(-x[p], L11[q + CT * p], acc);
+        x[q] = acc * dinv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < CT; ++q) X[r + CT * q] = x[q];
+    }
+    __syncthreads();
+    // (c) trailing tiles (ti, tj), tk < tj <= ti: C -= X_ti X_tj^T.  MFMA
+    // 16x16x4 operands: lane l gives A[l % 16][l / 16] and B[l / 16][l % 16]
+    // and holds D[l / 16 + 4 q][l % 16], q = 0..3.  The product is formed
+    // transposed, D = -X_tj X_ti^T, so that lane l's D entries are the tile's
+    // (row l % 16, column l / 16 + 4 q): consecutive lanes touch consecutive
+    // doubles of the column-major tile (no LDS bank conflicts)
+    const int mt = nb - tk - 1;
+    const int ntr = mt * (mt + 1) / 2;
+    const int lr = lane & 15, lq = lane >> 4;
+    for (int t = wave; t < ntr; t += nwv) {
+      const int a = ct_row(t), b = t - a * (a + 1) / 2;
+      const int ti = tk + 1 + a, tj = tk + 1 + b;
+      const double* Xi = T + (size_t)ct_index(ti, tk) * CT * CT;
+      const double* Xj = T + (size_t)ct_index(tj, tk) * CT * CT;
+      double* Cij = T + (size_t)ct_index(ti, tj) * CT * CT;
+      ct_v4d acc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = Cij[lr + CT * (lq + 4 * q)];
+#pragma unroll
+      for (int ks = 0; ks < CT / 4; ++ks) {
+        const double av = -Xj[lr + CT * (4 * ks + lq)];
+        const double bv = Xi[lr + CT * (4 * ks + lq)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Cij[lr + CT * (lq + 4 * q)] = acc[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int i = e % n, j = e / n;
+    L[e] = i >= j ? (float)T[(size_t)ct_index(i / CT, j / CT) * CT * CT + (i % CT) + CT * (j % CT)] : 0.f;
+  }
+}
+
+// Cholesky of one slice's Gram matrix C (n x n FP64, lower triangle): the tiles
+// loaded from C; L in FP32 over the first half of the slice's region.
+__device__ __attribute__((always_inline)) void chol_tiles(double* Cs, int n) {
+  extern __shared__ __attribute__((aligned(16))) double T[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = (n + CT - 1) / CT;
+  const int ntl = ct_ntiles(nb);
+  const double* C = Cs;
+  // the lower triangle into tiles; the diagonal tiles get the symmetric upper
+  // part too, the padding the identity
+  for (int e = tid; e < ntl * CT * CT; e += nt) {
+    const int t = e >> 8, r = e & 15, c = (e >> 4) & 15;
+    const int ti = ct_row(t), tj = t - ti * (ti + 1) / 2;
+    const int i = CT * ti + r, j = CT * tj + c;
+    double v;
+    if (i < n && j < n) v = i >= j ? C[i + (long long)j * n] : C[j + (long long)i * n];
+    else v = i == j ? 1.0 : 0.0;
+    T[e] = v;
+  }
+  __syncthreads();
+  chol_tiles_factor(T, n, reinterpret_cast<float*>(Cs));
+}
+
+// The Gram matrix C = W^T W of one slice formed straight into the tiles on
+// FP64 MFMA (the FP32 entries of W are exact in FP64, the products and sums are
+// FP64, as in k_gram), then factored as chol_tiles: no FP64 copy of C goes
+// through memory.  W: the slice in working orientation (m x n, n <= CTG_NMAX),
+// staged through LDS sixteen rows at a time (coalesced loads, each entry read
+// once); each wave accumulates up to CTG_TPW tiles across the chunks.
+constexpr int CTG_NMAX = 176;   // tiles (132 KiB at 176) + a 16-row chunk of W
+constexpr int CTG_TPW = 5;      // tiles per wave: 66 tiles at n = 176 over 16 waves
+constexpr int CTG_ROWS = 16;
+
+__host__ __device__ inline size_t ctg_lds_bytes(int n) {
+  const int nb = (n + CT - 1) / CT;
+  return ct_lds_bytes(n) + (size_t)CTG_ROWS * CT * nb * sizeof(float);
+}
+
+__device__ __attribute__((always_inline)) void gram_chol_tiles(const float* W, int I1, int I2, double* Cs) {
+  extern __shared__ __attribute__((aligned(16))) double T[];
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63, nwv = nt >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int nb = (n + CT - 1) / CT;
+  const int npad = CT * nb;
+  const int ntl = ct_ntiles(nb);
+  // the chunk of W after the tiles, the current factor and its reciprocals
+  float* Wst = reinterpret_cast<float*>(T + (size_t)ntl * CT * CT + CT * CT + CT);
+  // tile (ti, tj): lane l gives A[l % 16][l / 16] = W(k + l / 16, 16 tj + l % 16) and
+  // B[l / 16][l % 16] = W(k + l / 16, 16 ti + l % 16), so D = A B holds
+  // C(16 tj + l / 16 + 4 q, 16 ti + l % 16) = C(16 ti + l % 16, 16 tj + l / 16 + 4 q):
+  // the tile's (row l % 16, column l / 16 + 4 q), consecutive in LDS across lanes
+  ct_v4d acc[CTG_TPW];
+  int toff_i[CTG_TPW], toff_j[CTG_TPW];
+#pragma unroll
+  for (int u = 0; u < CTG_TPW; ++u) {
+    acc[u] = ct_v4d{0.0, 0.0, 0.0, 0.0};
+    const int t = wave + u * nwv;
+    const int ti = t < ntl ? ct_row(t) : 0, tj = t < ntl ? t - ti * (ti + 1) / 2 : 0;
+    toff_i[u] = CT * ti + lr;
+    toff_j[u] = CT * tj + lr;
+  }
+  for (int k0 = 0; k0 < m; k0 += CTG_ROWS) {
+    // stage rows k0 .. k0 + 15 of W (zero beyond m and n)
+    for (int e = tid; e < CTG_ROWS * npad; e += nt) {
+      int r, c;
+      if (trans) {   // W(r, c) = A[r * I1 + c]: columns contiguous
+        r = e / npad;
+        c = e - r * npad;
+      } else {       // W(r, c) = A[c * I1 + r]: rows contiguous
+        c = e / CTG_ROWS;
+        r = e - c * CTG_ROWS;
+      }
+      const int row = k0 + r;
+      Wst[r * npad + c] = (row < m && c < n) ? w_elem(W, trans, I1, row, c) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CTG_TPW; ++u) {
+      if (wave + u * nwv < ntl) {
+#pragma unroll
+        for (int st = 0; st < CTG_ROWS / 4; ++st) {
+          const float* row = Wst + (4 * st + lq) * npad;
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)row[toff_j[u]], (double)row[toff_i[u]], acc[u],
+                                                        0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < CTG_TPW; ++u) {
+    const int t = wave + u * nwv;
+    if (t < ntl) {
+      double* Tt = T + (size_t)t * CT * CT;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Tt[lr + CT * (lq + 4 * q)] = acc[u][q];
+    }
+  }
+  __syncthreads();
+  for (int i = n + tid; i < npad; i += nt)   // padding: identity on the diagonal
+    T[(size_t)ct_index(i / CT, i / CT) * CT * CT + (CT + 1) * (i % CT)] = 1.0;
+  __syncthreads();
+  chol_tiles_factor(T, n, reinterpret_cast<float*>(Cs));
+}
+
 constexpr int CG = 32;          // block width of the global-memory Cholesky
 constexpr int CG_NMAX = 512;    // largest n it takes
 
@@ -389,12 +676,29 @@ __global__ __launch_bounds__(1024) void k_chol(CholArgs a) {
   chol_slice<false>(a.C + (long long)blockIdx.x * a.c_stride, a.n);
 }
 
+__global__ __launch_bounds__(1024) void k_chol_tiles(CholArgs a) {
+  chol_tiles(a.C + (long long)blockIdx.x * a.c_stride, a.n);
+}
+
+__global__ __launch_bounds__(1024) void k_gram_chol_tiles(GramArgs g) {
+  const int s = blockIdx.x;
+  gram_chol_tiles(g.W + (long long)s * g.slice_stride, g.I1, g.I2, g.C + (long long)s * g.c_stride);
+}
+
 __global__ __launch_bounds__(1024) void k_chol_items(ProbDev* const* probs, const CholItem* items) {
   const CholItem it = items[blockIdx.x];
   const ProbDev* pd = probs[it.prob];
   if (!pd->active) return;
   const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
   chol_slice<true>(pd->C + (long long)it.slice * n * n, n);
+}
+
+__global__ __launch_bounds__(1024) void k_chol_tiles_items(ProbDev* const* probs, const CholItem* items) {
+  const CholItem it = items[blockIdx.x];
+  const ProbDev* pd = probs[it.prob];
+  if (!pd->active) return;
+  const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  chol_tiles(pd->C + (long long)it.slice * n * n, n);
 }
 
 // ---- Cholesky for large n (the 1080- and 2160-column frames) -----------------
@@ -572,7 +876,11 @@ hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, fl
   return hipGetLastError();
 }
 
-size_t chol_lds_bytes(int n) { return (size_t)n * (n + 1) / 2 * sizeof(double); }
+// LDS of the LDS Cholesky kernel for slices up to n columns: the tiled
+// kernel's up to CT_NMAX, the packed triangle's beyond.
+size_t chol_lds_bytes(int n) {
+  return n <= CT_NMAX ? ct_lds_bytes(n) : (size_t)n * (n + 1) / 2 * sizeof(double);
+}
 
 hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
@@ -602,11 +910,27 @@ hipError_t launch_chol_items(ProbDev* const* probs, const CholItem* items, int n
     return hipGetLastError();
   }
   if (nmax < 1) return hipErrorInvalidValue;
+  // every item by the tiled kernel when all fit it, else by the packed one
+  const void* fn = nmax <= CT_NMAX ? (const void*)k_chol_tiles_items : (const void*)k_chol_items;
   const size_t lds = chol_lds_bytes(nmax);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol_items, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (nmax <= CT_NMAX)
+    hipLaunchKernelGGL(k_chol_tiles_items, dim3(nitems), dim3(nmax <= 64 ? 256 : 1024), lds, s, probs, items);
+  else
+    hipLaunchKernelGGL(k_chol_items, dim3(nitems), dim3(1024), lds, s, probs, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_chol(const GramArgs& g, hipStream_t s) {
+  if (g.nslices <= 0) return hipSuccess;
+  const int n = g.I1 < g.I2 ? g.I1 : g.I2;
+  if (n < 1 || n > CTG_NMAX) return hipErrorInvalidValue;
+  const size_t lds = ctg_lds_bytes(n);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gram_chol_tiles, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_items, dim3(nitems), dim3(nmax <= 64 ? 256 : 1024), lds, s, probs, items);
+  hipLaunchKernelGGL(k_gram_chol_tiles, dim3(g.nslices), dim3(n <= 64 ? 256 : 1024), lds, s, g);
   return hipGetLastError();
 }
 
@@ -622,11 +946,14 @@ hipError_t launch_chol(const CholArgs& a, hipStream_t s) {
     return hipGetLastError();
   }
   if (a.n < 1) return hipErrorInvalidValue;
+  const void* fn = a.n <= CT_NMAX ? (const void*)k_chol_tiles : (const void*)k_chol;
   const size_t lds = chol_lds_bytes(a.n);
-  hipError_t e = hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol, dim3(a.nslices), dim3(a.n <= 64 ? 256 : 1024), lds, s, a);
+  if (a.n <= CT_NMAX)
+    hipLaunchKernelGGL(k_chol_tiles, dim3(a.nslices), dim3(a.n <= 64 ? 256 : 1024), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_chol, dim3(a.nslices), dim3(1024), lds, s, a);
   return hipGetLastError();
 }
 
