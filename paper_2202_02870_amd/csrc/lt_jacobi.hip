@@ -1633,7 +1633,11 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
     if (q < nq) Z[(hi + 16 * q) * (RB_TN + 1) + jj] = zacc[q];
   __syncthreads();
 
-  // phase B: D_W[k][j0 + jj] = sum_i Bk[k][i] Z[i][jj]
+  // phase B: D_W[k][j0 + jj] = sum_i Bk[k][i] Z[i][jj].  Consecutive lanes
+  // store consecutive addresses: along the columns when D_W's rows are
+  // contiguous (trans), else along the rows.
+  const int bc = trans ? jj : hi;   // this lane's output column in the block
+  const int br = trans ? hi : jj;   // and its row offset in the chunk (+ 16 h)
   for (int k0 = 0; k0 < m; k0 += RB_TK) {
     for (int idx = tid; idx < RB_TK * rpad; idx += 256) {
       const int kk = idx % RB_TK, i = idx / RB_TK;
@@ -1643,10 +1647,10 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int kk = hi + 16 * h;
+      const int kk = br + 16 * h;
       float acc = 0.f;
-      for (int i = 0; i < r; ++i) acc = fmaf(Bs[kk * ldb + i], Z[i * (RB_TN + 1) + jj], acc);
-      const int row = k0 + kk, col = j0 + jj;
+      for (int i = 0; i < r; ++i) acc = fmaf(Bs[kk * ldb + i], Z[i * (RB_TN + 1) + bc], acc);
+      const int row = k0 + kk, col = j0 + bc;
       if (row < m && col < n) {
         if (trans) D[(long long)row * I1 + col] = acc;
         else D[(long long)col * I1 + row] = acc;
@@ -1654,6 +1658,87 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
     }
     __syncthreads();
   }
+}
+
+// The same rebuild for working matrices of at most RBS_MMAX rows: the block's
+// 16 columns of W are staged once (all m rows), and the kept columns are taken
+// sixteen at a time (a chunk of Bk staged, Z = Bk^T W for the chunk, then
+// D_W += Bk Z), so a slice of low rank costs two staging passes and four
+// barriers instead of a pass per 32 rows.  LDS: the block, one chunk of Bk and
+// Z, each padded to an odd pitch.
+constexpr int RBS_MMAX = 256;
+constexpr int RBS_LD = RBS_MMAX + 1;
+
+__device__ void rebuild_body_small(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
+                                   bool flip) {
+  __shared__ float Xs[RB_TN][RBS_LD];    // W(:, j0 + c) at Xs[c][row]
+  __shared__ float Bs[RB_TN][RBS_LD];    // Bk(:, i0 + i) at Bs[i][row]
+  __shared__ float Zs[RB_TN][RB_TN + 1]; // Z(i0 + i, c)
+  const bool trans = (I1 < I2) != flip;
+  const int m = flip ? (I1 < I2 ? I1 : I2) : (I1 < I2 ? I2 : I1);
+  const int n = flip ? (I1 < I2 ? I2 : I1) : (I1 < I2 ? I1 : I2);
+  const int tid = threadIdx.x;
+  // the block, coalesced along whichever dimension W keeps contiguous
+  for (int idx = tid; idx < RB_TN * m; idx += 256) {
+    int row, c;
+    if (trans) { c = idx % RB_TN; row = idx / RB_TN; } else { row = idx % m; c = idx / m; }
+    const int col = j0 + c;
+    Xs[c][row] = col < n ? w_at(W, trans, I1, row, col) : 0.f;
+  }
+  // output ownership: consecutive lanes store consecutive addresses
+  const int nout = RB_TN * m;
+  float acc[(RB_TN * RBS_MMAX + 255) / 256];
+#pragma unroll
+  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) acc[u] = 0.f;
+  for (int i0 = 0; i0 < r; i0 += RB_TN) {
+    const int nc = r - i0 < RB_TN ? r - i0 : RB_TN;
+    for (int idx = tid; idx < RB_TN * m; idx += 256) {
+      const int row = idx % m, i = idx / m;
+      Bs[i][row] = i < nc ? Bk[(long long)(i0 + i) * m + row] : 0.f;
+    }
+    __syncthreads();
+    {   // Z(i, c) = sum_row Bk(row, i0 + i) W(row, j0 + c), one entry per lane
+      const int i = tid >> 4, c = tid & 15;
+      float z = 0.f;
+      for (int row = 0; row < m; ++row) z = fmaf(Bs[i][row], Xs[c][row], z);
+      Zs[i][c] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) {
+      const int o = tid + 256 * u;
+      if (o < nout) {
+        const int row = trans ? o / RB_TN : o % m;
+        const int c = trans ? o % RB_TN : o / m;
+        float v = acc[u];
+        for (int i = 0; i < nc; ++i) v = fmaf(Bs[i][row], Zs[i][c], v);
+        acc[u] = v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) {
+    const int o = tid + 256 * u;
+    if (o < nout) {
+      const int row = trans ? o / RB_TN : o % m;
+      const int c = trans ? o % RB_TN : o / m;
+      const int col = j0 + c;
+      if (col < n) {
+        if (trans) D[(long long)row * I1 + col] = acc[u];
+        else D[(long long)col * I1 + row] = acc[u];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rebuild_small(RebuildArgs a) {
+  const int s = blockIdx.y;
+  const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
+  const int j0 = blockIdx.x * RB_TN;
+  if (j0 >= n) return;
+  const long long off = (long long)s * a.slice_stride;
+  rebuild_body_small(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
 }
 
 template <int RMAX>
@@ -2479,6 +2564,11 @@ hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   const int kmax = a.I1 < a.I2 ? a.I1 : a.I2;   // kept columns are at most min(I1, I2)
   if (kmax > RB_RMAX_BLK) return hipErrorInvalidValue;
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
+  const int m = a.flip ? (a.I1 < a.I2 ? a.I1 : a.I2) : (a.I1 < a.I2 ? a.I2 : a.I1);
+  if (m <= RBS_MMAX) {
+    hipLaunchKernelGGL(k_rebuild_small, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   RebuildArgs b = a;
   b.rcap = rebuild_rcap(kmax);
   const size_t lds = rebuild_lds_bytes(b.rcap);
