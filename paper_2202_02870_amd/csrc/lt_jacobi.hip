@@ -332,12 +332,12 @@ __host__ __device__ inline size_t slice_lds_bytes(int npairs, int ldw, int nbuf)
 constexpr size_t kWgCtlBytes = 16;   // workgroup-wide rotation counters
 
 // A lane's rotation count holds two counts: rotations in the low 16 bits and
-// large rotations (cosine of the pair's angle above sqrt(tol) / 4) in the high
-// 16.  Cyclic Jacobi converges quadratically, so after a sweep whose rotations
-// were all small the next sweep's would fall below tol: a slice stops after
-// such a sweep instead of running a last sweep that only checks.
+// large rotations (the pair's |a_i . a_j| / (|a_i| |a_j|) above sqrt(tol) / 2)
+// in the high 16.  Cyclic Jacobi converges quadratically, so after a sweep
+// whose rotations were all small the next sweep's would fall near tol: a slice
+// stops after such a sweep instead of running a last sweep that only checks.
 constexpr unsigned kBigOne = 1u << 16;
-__device__ inline double big_rotation2(double tol) { return tol * (1.0 / 16.0); }
+__device__ inline double big_rotation2(double tol) { return tol * 0.25; }
 
 // One workgroup's work: nsub slices of identical shape (I1 x I2), slice q at
 // src + q * stride; outputs likewise.
@@ -1758,8 +1758,13 @@ __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, co
   const ProbDev* pd = probs[t.prob];
   if (!pd->active) return;
   const long long off = (long long)t.slice * pd->N;
-  rebuild_body<RMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
-                     pd->precond != 0, rcap);
+  const int m = pd->precond ? (pd->I1 < pd->I2 ? pd->I1 : pd->I2) : (pd->I1 < pd->I2 ? pd->I2 : pd->I1);
+  if (m <= RBS_MMAX)
+    rebuild_body_small(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
+                       pd->precond != 0);
+  else
+    rebuild_body<RMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
+                       pd->precond != 0, rcap);
 }
 
 // ---- lsvd: sort, normalise, V = W^T U / sigma, orthonormalise ---------------
