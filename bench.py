@@ -363,7 +363,11 @@ def bench_completion(args, torch, lt, wl):
         nrm = float(np.linalg.norm(Xo))
         err = ({"rel_err_vs_oracle": float(np.linalg.norm(Xg - Xo) / nrm)} if nrm > 0 else
                {"abs_norm_gpu_where_oracle_is_zero": float(np.linalg.norm(Xg))})
-        line["parity"] = {"iters": cpu_iters, **err, "bound": 1e-4 if args.precision == "f32" else 1e-2,
+        bound = 1e-4 if args.precision == "f32" else 1e-2
+        ok = err.get("rel_err_vs_oracle", 0.0) <= bound and err.get("abs_norm_gpu_where_oracle_is_zero", 0.0) == 0.0
+        if not ok:
+            say("PARITY: the GPU iterate after %d iterations is outside the bound %g: %s" % (cpu_iters, bound, err))
+        line["parity"] = {"iters": cpu_iters, **err, "bound": bound, "within_bound": ok,
                           "full_length": "200 iterations at full size in tests/test_gpu_configs.py"}
     return line
 
@@ -405,12 +409,16 @@ def leg_large(args, torch, lt, wl):
         dt, rep, prof, window = run_window(lt, M, mask, p, X, ws, args, prec, 100, 2, 30)
         del ws
         Xg = gpu_iterate(lt, M, mask, p, prec, k_or)
+        e = float(np.linalg.norm(Xg - Xo) / nrm) if nrm > 0 else None
+        bound = 1e-4 if prec == "f32" else 1e-2
+        if e is None or e > bound:
+            say("PARITY: %s large workload after %d iterations: %s (bound %g)" % (prec, k_or, e, bound))
         out[prec] = {"iters_per_s": round(30 / dt, 2), "timed_iterations": list(window),
                      "slice_svt_per_s": round(30 * 300 / dt, 1),
                      "mean_sweeps": round(rep["total_sweeps"] / rep["total_slices"], 3),
                      "jacobi_ms_per_launch": round(prof["jacobi"][1] / max(prof["jacobi"][0], 1), 3),
-                     "rel_err_vs_oracle_at_%d" % k_or: float(np.linalg.norm(Xg - Xo) / nrm) if nrm > 0 else None,
-                     "bound": 1e-4 if prec == "f32" else 1e-2}
+                     "rel_err_vs_oracle_at_%d" % k_or: e, "bound": bound,
+                     "within_bound": e is not None and e <= bound}
     return out
 
 
