@@ -172,6 +172,12 @@ __device__ inline void jacobi_angle(double d, double pa, double pb, double& t, f
   sf = (float)(c * t);
 }
 
+// A wave-uniform FP64 value moved to scalar registers.
+__device__ inline double uniform_d(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
 // Pair dot-product precision travels with the Jacobi tolerance: a negative
 // tolerance asks for FP32 products and per-lane FP32 sums (an opt-in of the
 // library's svd options); decode_tol restores the magnitude and returns that
@@ -1344,7 +1350,10 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
 
   double tol = a.tol;
   const bool dot32 = decode_tol(tol);
-  const double big2 = big_rotation2(tol);
+  // loop-invariant and uniform: held in scalar registers (frees vector
+  // registers the round loop would otherwise spill)
+  const double tol2 = uniform_d(tol * tol);
+  const double big2 = uniform_d(big_rotation2(tol));
   double na = 0.0, nb = 0.0;
   int sweep = 0, my_sweeps = 0;
   bool converged = false;
@@ -1368,7 +1377,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_warm_body(const War
         d = dot32 ? (double)group_sumf<G>(dot32_m<R>(av, bv, lastm, qm)) : group_sum<G>(dot64_m<R>(av, bv, lastm, qm));
         pa = fmax(na, 0.0);
         pb = fmax(nb, 0.0);
-        rot = d != 0.0 && d * d > tol * tol * (pa * pb);
+        rot = d != 0.0 && d * d > tol2 * (pa * pb);
         if (rot) {
           jacobi_angle(d, pa, pb, t, cf, sf);
         }

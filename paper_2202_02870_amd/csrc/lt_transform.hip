@@ -23,16 +23,23 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Deterministic workgroup sum of two doubles (256 threads), result in thread 0.
+// Workgroups of 4, 8 or 12 waves (a multiple of four, at most 16): the waves'
+// sums in groups of four, each group pairwise, the groups in order.
 __device__ inline void block_sum2(double& s1, double& s2) {
-  __shared__ double red[2][4];
+  __shared__ double red[2][16];
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = (int)(blockDim.x >> 6);
   if (l == 0) { red[0][w] = s1; red[1][w] = s2; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    s1 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-    s2 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nw; i += 4) {
+      a += (red[0][i] + red[0][i + 1]) + (red[0][i + 2] + red[0][i + 3]);
+      b += (red[1][i] + red[1][i + 1]) + (red[1][i + 2] + red[1][i + 3]);
+    }
+    s1 = a;
+    s2 = b;
   }
 }
 
@@ -58,17 +65,22 @@ __device__ inline void store_result(const GemmArgs& a, long long g, float o, dou
   a.out[g] = o;
 }
 
-// FP32 MFMA (v_mfma_f32_16x16x4_f32).  Workgroup = 4 waves; tile 64 x 64;
-// wave w owns output rows 16w..16w+15 and four 16-column sub-tiles.
+// FP32 MFMA (v_mfma_f32_16x16x4_f32).  Workgroup = NW waves; tile (16 NW) x 64;
+// wave w owns output rows 16w..16w+15 and four 16-column sub-tiles.  NW = 4
+// in general; with up to 192 output rows one workgroup of NW = 4, 8 or 12
+// waves takes them all, so the staged input (with the momentum prologue's four
+// reads per entry) is read from memory once instead of once per 64 rows.
 // Operand lane layout of the 16x16x4 instruction: A[i][k] at lane i + 16k,
 // B[k][j] at lane j + 16k, D[i][j] in element i%4 of lane j + 16(i/4).
-template <int PRO, int EPI>
+template <int PRO, int EPI, int NW = 4>
 __device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
-  __shared__ float Ks[TQ][TPK + 1];
+  constexpr int TQW = 16 * NW;
+  constexpr int NT = 64 * NW;
+  __shared__ float Ks[TQW][TPK + 1];
   __shared__ float Bs[TPK][TE + 4];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const long long e0 = (long long)tx * TE;
-  const int q0 = ty * TQ;
+  const int q0 = ty * TQW;
   const int Mo = a.Mo ? a.Mo : a.P;   // output rows
   const int Kd = a.Kd ? a.Kd : a.P;   // contraction length (input rows)
   const long long N = a.N;
@@ -77,12 +89,12 @@ __device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   for (int p0 = 0; p0 < Kd; p0 += TPK) {
-    for (int idx = tid; idx < TQ * TPK; idx += 256) {
+    for (int idx = tid; idx < TQW * TPK; idx += NT) {
       const int i = idx / TPK, k = idx - i * TPK;
       const int q = q0 + i, p = p0 + k;
       Ks[i][k] = (q < Mo && p < Kd) ? a.K[(long long)q * Kd + p] : 0.f;
     }
-    for (int idx = tid; idx < TPK * TE; idx += 256) {
+    for (int idx = tid; idx < TPK * TE; idx += NT) {
       const int k = idx / TE, j = idx - k * TE;
       const int p = p0 + k;
       const long long e = e0 + j;
@@ -120,10 +132,10 @@ __device__ void gemm_f32_tile(const GemmArgs& a, int tx, int ty, double* part) {
   }
 }
 
-template <int PRO, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
-  gemm_f32_tile<PRO, EPI>(a, blockIdx.x, blockIdx.y,
-                          a.partials + 2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
+template <int PRO, int EPI, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_f32(GemmArgs a) {
+  gemm_f32_tile<PRO, EPI, NW>(a, blockIdx.x, blockIdx.y,
+                              a.partials + 2 * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // BF16 MFMA (v_mfma_f32_16x16x32_bf16) on hi/lo splits: K ~ Kh + Kl and
@@ -535,14 +547,34 @@ hipError_t launch_transform_gemm(const GemmArgs& a, int precision, int pro, int 
                                  hipStream_t s, int* n_partials) {
   if (a.P <= 0 || a.N <= 0) return hipErrorInvalidValue;
   const int Mo = a.Mo ? a.Mo : a.P;
-  dim3 grid((unsigned)((a.N + TE - 1) / TE), (unsigned)((Mo + TQ - 1) / TQ));
+  // FP32: all output rows in one workgroup when they fit 12 waves
+  const int nw = precision ? 4 : (Mo <= 64 ? 4 : (Mo <= 128 ? 8 : (Mo <= 192 ? 12 : 4)));
+  const int rows = 16 * nw;
+  dim3 grid((unsigned)((a.N + TE - 1) / TE), (unsigned)((Mo + rows - 1) / rows));
   if (n_partials) *n_partials = (int)(grid.x * grid.y);
   const int key = (precision ? 4 : 0) | (pro << 1) | epi;
+  const dim3 blk(64 * nw);
   switch (key) {
-    case 0: hipLaunchKernelGGL((k_gemm_f32<0, 0>), grid, dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_gemm_f32<0, 1>), grid, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_gemm_f32<1, 0>), grid, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_gemm_f32<1, 1>), grid, dim3(256), 0, s, a); break;
+    case 0:
+      if (nw == 12) hipLaunchKernelGGL((k_gemm_f32<0, 0, 12>), grid, blk, 0, s, a);
+      else if (nw == 8) hipLaunchKernelGGL((k_gemm_f32<0, 0, 8>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f32<0, 0, 4>), grid, blk, 0, s, a);
+      break;
+    case 1:
+      if (nw == 12) hipLaunchKernelGGL((k_gemm_f32<0, 1, 12>), grid, blk, 0, s, a);
+      else if (nw == 8) hipLaunchKernelGGL((k_gemm_f32<0, 1, 8>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f32<0, 1, 4>), grid, blk, 0, s, a);
+      break;
+    case 2:
+      if (nw == 12) hipLaunchKernelGGL((k_gemm_f32<1, 0, 12>), grid, blk, 0, s, a);
+      else if (nw == 8) hipLaunchKernelGGL((k_gemm_f32<1, 0, 8>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f32<1, 0, 4>), grid, blk, 0, s, a);
+      break;
+    case 3:
+      if (nw == 12) hipLaunchKernelGGL((k_gemm_f32<1, 1, 12>), grid, blk, 0, s, a);
+      else if (nw == 8) hipLaunchKernelGGL((k_gemm_f32<1, 1, 8>), grid, blk, 0, s, a);
+      else hipLaunchKernelGGL((k_gemm_f32<1, 1, 4>), grid, blk, 0, s, a);
+      break;
     case 4: hipLaunchKernelGGL((k_gemm_bf16x3<0, 0>), grid, dim3(256), 0, s, a); break;
     case 5: hipLaunchKernelGGL((k_gemm_bf16x3<0, 1>), grid, dim3(256), 0, s, a); break;
     case 6: hipLaunchKernelGGL((k_gemm_bf16x3<1, 0>), grid, dim3(256), 0, s, a); break;
