@@ -1678,6 +1678,27 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
 constexpr int RBS_MMAX = 256;
 constexpr int RBS_LD = RBS_MMAX + 1;
 
+// Index (row, c) of entry e = row + m c (or c + 16 row when rows are the long
+// dimension) stepped by 256 entries without a division per step.
+struct RbIdx {
+  int a, b;          // a: the fast index, b: the slow one
+  int qa, qb, lim;   // 256 = qb lim + qa
+  __device__ RbIdx(int e, int lim_) : lim(lim_) {
+    b = e / lim_;
+    a = e - b * lim_;
+    qb = 256 / lim_;
+    qa = 256 - qb * lim_;
+  }
+  __device__ void step() {
+    a += qa;
+    b += qb;
+    if (a >= lim) {
+      a -= lim;
+      ++b;
+    }
+  }
+};
+
 __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
                                    bool flip) {
   __shared__ float Xs[RB_TN][RBS_LD];    // W(:, j0 + c) at Xs[c][row]
@@ -1687,23 +1708,27 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
   const int m = flip ? (I1 < I2 ? I1 : I2) : (I1 < I2 ? I2 : I1);
   const int n = flip ? (I1 < I2 ? I2 : I1) : (I1 < I2 ? I1 : I2);
   const int tid = threadIdx.x;
+  const int nout = RB_TN * m;
   // the block, coalesced along whichever dimension W keeps contiguous
-  for (int idx = tid; idx < RB_TN * m; idx += 256) {
-    int row, c;
-    if (trans) { c = idx % RB_TN; row = idx / RB_TN; } else { row = idx % m; c = idx / m; }
-    const int col = j0 + c;
-    Xs[c][row] = col < n ? w_at(W, trans, I1, row, col) : 0.f;
+  // (trans: entry e = c + 16 row, else e = row + m c)
+  {
+    RbIdx x(tid, trans ? RB_TN : m);
+    for (int idx = tid; idx < nout; idx += 256, x.step()) {
+      const int row = trans ? x.b : x.a, c = trans ? x.a : x.b;
+      const int col = j0 + c;
+      Xs[c][row] = col < n ? w_at(W, trans, I1, row, col) : 0.f;
+    }
   }
   // output ownership: consecutive lanes store consecutive addresses
-  const int nout = RB_TN * m;
   float acc[(RB_TN * RBS_MMAX + 255) / 256];
 #pragma unroll
   for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) acc[u] = 0.f;
   for (int i0 = 0; i0 < r; i0 += RB_TN) {
     const int nc = r - i0 < RB_TN ? r - i0 : RB_TN;
-    for (int idx = tid; idx < RB_TN * m; idx += 256) {
-      const int row = idx % m, i = idx / m;
-      Bs[i][row] = i < nc ? Bk[(long long)(i0 + i) * m + row] : 0.f;
+    {
+      RbIdx x(tid, m);
+      for (int idx = tid; idx < nout; idx += 256, x.step())
+        Bs[x.b][x.a] = x.b < nc ? Bk[(long long)(i0 + x.b) * m + x.a] : 0.f;
     }
     __syncthreads();
     {   // Z(i, c) = sum_row Bk(row, i0 + i) W(row, j0 + c), one entry per lane
@@ -1713,12 +1738,11 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
       Zs[i][c] = z;
     }
     __syncthreads();
+    RbIdx x(tid, trans ? RB_TN : m);
 #pragma unroll
-    for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) {
-      const int o = tid + 256 * u;
-      if (o < nout) {
-        const int row = trans ? o / RB_TN : o % m;
-        const int c = trans ? o % RB_TN : o / m;
+    for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u, x.step()) {
+      if (tid + 256 * u < nout) {
+        const int row = trans ? x.b : x.a, c = trans ? x.a : x.b;
         float v = acc[u];
         for (int i = 0; i < nc; ++i) v = fmaf(Bs[i][row], Zs[i][c], v);
         acc[u] = v;
@@ -1726,12 +1750,11 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
     }
     __syncthreads();
   }
+  RbIdx x(tid, trans ? RB_TN : m);
 #pragma unroll
-  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) {
-    const int o = tid + 256 * u;
-    if (o < nout) {
-      const int row = trans ? o / RB_TN : o % m;
-      const int c = trans ? o % RB_TN : o / m;
+  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u, x.step()) {
+    if (tid + 256 * u < nout) {
+      const int row = trans ? x.b : x.a, c = trans ? x.a : x.b;
       const int col = j0 + c;
       if (col < n) {
         if (trans) D[(long long)row * I1 + col] = acc[u];

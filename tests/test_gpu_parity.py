@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as o
+import parity
 from paper_2202_02870_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -151,6 +152,30 @@ def test_svt_tall_slices_both_paths(lt):
         err = rel(lt.to_host(D), ref)
         say("  tall 600x128 precondition", pc, "err", err)
         assert err < 2e-5
+
+
+@pytest.mark.parametrize("shape", [
+    (176, 200, 2),   # n = 176: Gram and Cholesky fused (the largest such n), kept count > 16
+    (300, 184, 2),   # n = 184: Gram kernel + tiled Cholesky
+    (199, 196, 2),   # n = 196: Gram kernel + packed-triangle Cholesky
+    (260, 150, 3),   # n = 150 with 260-row columns: fused, the Gram over 17 staged chunks
+    (40, 17, 4),     # n = 17: one tile plus one padded row and column
+])
+def test_svt_precondition_kernel_boundaries(lt, shape):
+    """The preconditioned SVT across the widths where the Cholesky changes kernel
+    (fused with the Gram up to 176 columns, tiled up to 192, packed up to 200),
+    against the oracle slice by slice; the rank of each slice exactly."""
+    rng = np.random.default_rng(sum(shape))
+    mats = o.mats_for(shape, ["dct"])
+    r = 20
+    A = o.lproduct(rng.standard_normal((shape[0], r) + shape[2:]), rng.standard_normal((r, shape[1]) + shape[2:]), mats)
+    A = A + 0.05 * rng.standard_normal(shape)
+    tau = float(np.quantile(o.singular_values(A, mats), 0.8))
+    assert "precond" in lt.svt_path(shape, ("dct",))
+    D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, ("dct",))
+    say("boundary", shape, lt.svt_path(shape, ("dct",)), "ranks", lt.to_host(rank), "sweeps", lt.to_host(sweeps))
+    parity.check(lt.to_host(D), o.svt(A, tau, mats), 2e-5, label=str(shape))
+    assert np.array_equal(lt.to_host(rank), np.asarray(o.svt_ranks(A, tau, mats)))
 
 
 def test_svt_in_place_and_deterministic(lt):
