@@ -575,8 +575,7 @@ bool warm_shape(const Shape& s) {
   if (!svt_plan(s, true, &pl) || !pl.precond || pl.blocked) return false;
   const int n = (int)precond_n(s);
   lt::JacobiConfig cfg;
-  return lt::jacobi_warm_config(n, kBlkLdsBudget, &cfg) == 0 &&
-         lt::warm_product_lds_bytes(n) <= (size_t)kBlkLdsBudget;
+  return lt::jacobi_warm_config(n, kBlkLdsBudget, &cfg) == 0;
 }
 
 struct WarmState {
@@ -820,7 +819,7 @@ int run_jacobi_svt(lt_handle* h, const Shape& s, const float* Gh, float* Dh, con
         float* Mw = reinterpret_cast<float*>(w.C) + cst;
         ProfScope ps(h, LT_PROF_PRECOND);
         HIP_TRY(h, lt::launch_warm_product(reinterpret_cast<const float*>(w.C), 2 * cst, warm->Z, Mw, 2 * cst,
-                                           n, (int)s.P, h->max_lds, h->stream));
+                                           n, (int)s.P, h->stream));
         wa.M = Mw;
       }
       wa.Z = warm->Z;
@@ -2204,8 +2203,8 @@ static hipError_t enqueue_tick(lt_batch* b, hipStream_t s, bool prof) {
     if ((e = lt::launch_chol_items(b->w.ptrs, b->w.cholg, (int)T.cholg.size(), T.cholg_nmax, s)) !=
         hipSuccess)
       return e;
-    if ((e = lt::launch_warm_product_items(b->w.ptrs, b->w.warm, (int)T.warm.size(), T.warm_nmax, h->max_lds,
-                                           s)) != hipSuccess)
+    if ((e = lt::launch_warm_product_items(b->w.ptrs, b->w.warm, (int)T.warm.size(), T.warm_nmax, s)) !=
+        hipSuccess)
       return e;
   }
   if (!T.blk.empty()) {

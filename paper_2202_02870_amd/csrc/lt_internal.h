@@ -159,12 +159,11 @@ struct WarmArgs {
   int cold;
 };
 // Configuration for n x n factors (0 on success, -1 if the kernel cannot hold
-// them), launch, and the product M = L Z (LDS bytes it needs).
+// them), launch, and the product M = L Z (FP32 MFMA, no LDS).
 int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg, int force_G = 0);
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& cfg, hipStream_t s);
-size_t warm_product_lds_bytes(int n);
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
-                               long long m_stride, int n, int nslices, int max_lds, hipStream_t s);
+                               long long m_stride, int n, int nslices, hipStream_t s);
 
 // The register-resident kernel can hold an m x n working matrix (shape limits
 // only; the device's LDS is checked by jacobi_pick_config).
@@ -372,6 +371,6 @@ hipError_t launch_jacobi_blk_items(ProbDev* const* probs, const CholItem* items,
 hipError_t launch_jacobi_warm_items(ProbDev* const* probs, const CholItem* items, int nitems,
                                     const JacobiConfig& cfg, double tol, int max_sweeps, hipStream_t s);
 hipError_t launch_warm_product_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
-                                     int max_lds, hipStream_t s);
+                                     hipStream_t s);
 
 }  // namespace lt

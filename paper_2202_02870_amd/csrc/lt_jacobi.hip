@@ -1097,100 +1097,20 @@ __global__ __launch_bounds__(LB) void k_jacobi_items(ProbDev* const* probs, cons
 // take the M rows only.  A cold call starts from Z = I (M = L).  One slice per
 // workgroup; pair schedule, angle and stopping rule are those of jacobi_body.
 
-// M = L Z per slice (L lower triangular, both n x n column-major): L staged in
-// the LDS with leading dimension npad, Z in blocks of cb columns (stored k-major,
-// so that 4 consecutive columns are one float4); a thread forms a 4 x 4 block
-// of M (4 rows of 4 columns) over k <= its last row.
-__host__ __device__ inline size_t warm_product_lds(int n, int cb) {
-  const size_t npad = (size_t)((n + 3) / 4) * 4;
-  return (npad * n + (size_t)cb * n) * sizeof(float);
-}
-
-// Columns per block of Z: the most (a multiple of 4, at most 64) the LDS takes.
-__host__ __device__ inline int warm_product_cb(int n, size_t max_lds) {
-  int cb = 64;
-  while (cb > 4 && warm_product_lds(n, cb) > max_lds) cb -= 4;
-  return cb;
-}
-
-__device__ __attribute__((always_inline)) inline void warm_product_body(const float* Lg, const float* Zg, float* Mg,
-                                                                       int n, int cb) {
-  extern __shared__ __attribute__((aligned(16))) float wp_lds[];
-  const int npad = (n + 3) / 4 * 4;
-  float* Ls = wp_lds;                      // L(row, k) at Ls[k * npad + row]
-  float* Zt = wp_lds + (size_t)npad * n;   // Z(k, c0 + cc) at Zt[k * cb + cc]
-  for (int e = threadIdx.x; e < npad * n; e += blockDim.x) {
-    const int k = e / npad, row = e - k * npad;
-    Ls[e] = row < n ? Lg[(long long)k * n + row] : 0.f;
-  }
-  const int nr4 = npad / 4;
-  for (int c0 = 0; c0 < n; c0 += cb) {
-    const int nc = n - c0 < cb ? n - c0 : cb;
-    __syncthreads();   // L staged / the previous block of Z no longer read
-    // consecutive threads take consecutive columns (the transposed LDS stores
-    // then hit consecutive banks), each 4 consecutive rows of its column
-    const int n4 = (n + 3) / 4;
-    for (int e = threadIdx.x; e < cb * n4; e += blockDim.x) {
-      const int cc = e % cb, k0 = 4 * (e / cb);
-      const float* zc = Zg + (long long)(c0 + cc) * n;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (k0 + i < n) Zt[(k0 + i) * cb + cc] = cc < nc ? zc[k0 + i] : 0.f;
-    }
-    __syncthreads();
-    const int nc4 = (nc + 3) / 4;
-    for (int e = threadIdx.x; e < nc4 * nr4; e += blockDim.x) {
-      const int cg = e / nr4, r0 = 4 * (e - cg * nr4);
-      const int kend = r0 + 4 < n ? r0 + 4 : n;   // L(row, k) = 0 for k > row
-      float acc[4][4] = {};
-#pragma unroll 4
-      for (int k = 0; k < kend; ++k) {
-        const float4 lv = *reinterpret_cast<const float4*>(Ls + (size_t)k * npad + r0);
-        const float4 zv = *reinterpret_cast<const float4*>(Zt + (size_t)k * cb + 4 * cg);
-        const float lr[4] = {lv.x, lv.y, lv.z, lv.w};
-        const float zc[4] = {zv.x, zv.y, zv.z, zv.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(lr[i], zc[j], acc[i][j]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int col = c0 + 4 * cg + j;
-        if (col < c0 + nc) {
-          float* mc = Mg + (long long)col * n;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (r0 + i < n) mc[r0 + i] = acc[i][j];
-        }
-      }
-    }
-  }
-}
-
-// M = L Z for every slice on FP32 MFMA (16x16x4): one 16 x 16 tile of M per
-// wave, many waves per slice.  The tile is formed as its transpose,
-// M^T = Z^T L^T, so that lane l's results are consecutive rows of the
-// column-major M (A[i][k] = Z(k, c0 + i), B[k][j] = L(r0 + j, k); lane l holds
-// D[4 (l / 16) + q][l % 16] = M(r0 + l % 16, c0 + 4 (l / 16) + q)).  Within a
-// chunk of 16 contraction indices, lane group g = l / 16 supplies k = 4 g + s at
-// step s, so each lane reads four consecutive entries of its Z column.  L is
-// lower triangular: a tile of rows r0 .. r0 + 15 stops at k = r0 + 15.
+// M = L Z per slice (L lower triangular, both n x n column-major) on FP32 MFMA
+// (16x16x4): one 16 x 16 tile of M per wave.  The tile is formed as its
+// transpose, M^T = Z^T L^T, so that lane l's results are consecutive rows of
+// the column-major M (A[i][k] = Z(k, c0 + i), B[k][j] = L(r0 + j, k); lane l
+// holds D[4 (l / 16) + q][l % 16] = M(r0 + l % 16, c0 + 4 (l / 16) + q)).
+// Within a chunk of 16 contraction indices, lane group g = l / 16 supplies
+// k = 4 g + s at step s, so each lane reads four consecutive entries of its Z
+// column.  L is lower triangular: a tile of rows r0 .. r0 + 15 stops at
+// k = r0 + 15.  The single-problem and batch kernels share this tile, so both
+// paths round M alike.
 typedef float wp_v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_warm_product_mfma(const float* L, long long l_stride, const float* Z,
-                                                            float* M, long long m_stride, int n, int nb,
-                                                            int nslices) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long job = (long long)blockIdx.x * 4 + wave;
-  const long long tiles = (long long)nb * nb;
-  const int s = (int)(job / tiles);
-  if (s >= nslices) return;
-  const int t = (int)(job - (long long)s * tiles);
-  const int r0 = 16 * (t % nb), c0 = 16 * (t / nb);
-  const float* Ls = L + (long long)s * l_stride;
-  const float* Zs = Z + (long long)s * n * n;
-  float* Ms = M + (long long)s * m_stride;
+__device__ __attribute__((always_inline)) inline void warm_tile_mfma(const float* Ls, const float* Zs, float* Ms,
+                                                                    int n, int r0, int c0, int lane) {
   const int lr = lane & 15, g = lane >> 4;
   const int zc = c0 + lr;   // the Z column this lane reads
   const int lrow = r0 + lr; // the L row this lane reads
@@ -1216,21 +1136,42 @@ __global__ __launch_bounds__(256) void k_warm_product_mfma(const float* L, long 
   }
 }
 
+// Single problem: job = 4 blockIdx.x + wave runs over (slice, tile), nb x nb
+// tiles per slice (nb = ceil(n / 16)), tile t at rows 16 (t % nb), columns
+// 16 (t / nb).
+__global__ __launch_bounds__(256) void k_warm_product_mfma(const float* L, long long l_stride, const float* Z,
+                                                            float* M, long long m_stride, int n, int nb,
+                                                            int nslices) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long job = (long long)blockIdx.x * 4 + wave;
+  const long long tiles = (long long)nb * nb;
+  const int s = (int)(job / tiles);
+  if (s >= nslices) return;
+  const int t = (int)(job - (long long)s * tiles);
+  warm_tile_mfma(L + (long long)s * l_stride, Z + (long long)s * n * n, M + (long long)s * m_stride, n,
+                 16 * (t % nb), 16 * (t / nb), lane);
+}
+
 // Whether a batch problem's Jacobi starts cold this iteration (Z = I, M = L).
 __device__ inline bool warm_cold(const ProbDev* pd) {
   return pd->warm_period <= 0 || pd->iter % pd->warm_period == 0;
 }
 
-// Batch: one workgroup per slice of the warm-started problems (L over the first
-// half of the slice's FP64 Gram block, M written over the second half); cold
-// problems skip it.
-__global__ __launch_bounds__(1024) void k_warm_product_items(ProbDev* const* probs, const CholItem* items, int cb) {
+// Batch: blockIdx.x is the item (one slice of a warm-started problem: L over
+// the first half of its FP64 Gram block, M written over the second half), the
+// wave's tile 4 blockIdx.y + wave of that slice's nb x nb; the grid covers the
+// largest item, waves past a smaller item's tiles return.  Cold problems skip.
+__global__ __launch_bounds__(256) void k_warm_product_items(ProbDev* const* probs, const CholItem* items) {
   const CholItem it = items[blockIdx.x];
   const ProbDev* pd = probs[it.prob];
   if (!pd->active || warm_cold(pd)) return;
   const int n = pd->I1 < pd->I2 ? pd->I1 : pd->I2;
+  const int nb = (n + 15) / 16;
+  const int t = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (t >= nb * nb) return;
   const float* L = reinterpret_cast<const float*>(pd->C) + (long long)it.slice * 2 * n * n;
-  warm_product_body(L, pd->Z + (long long)it.slice * n * n, const_cast<float*>(L) + (long long)n * n, n, cb);
+  warm_tile_mfma(L, pd->Z + (long long)it.slice * n * n, const_cast<float*>(L) + (long long)n * n, n,
+                 16 * (t % nb), 16 * (t / nb), threadIdx.x & 63);
 }
 
 // Dot products over the M rows.  Chunks q < qm - 1 hold M rows in every lane,
@@ -1732,10 +1673,18 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
     }
     __syncthreads();
     {   // Z(i, c) = sum_row Bk(row, i0 + i) W(row, j0 + c), one entry per lane
+        // (four interleaved partial sums: a shorter dependent chain)
       const int i = tid >> 4, c = tid & 15;
-      float z = 0.f;
-      for (int row = 0; row < m; ++row) z = fmaf(Bs[i][row], Xs[c][row], z);
-      Zs[i][c] = z;
+      float z0 = 0.f, z1 = 0.f, z2 = 0.f, z3 = 0.f;
+      int row = 0;
+      for (; row + 4 <= m; row += 4) {
+        z0 = fmaf(Bs[i][row], Xs[c][row], z0);
+        z1 = fmaf(Bs[i][row + 1], Xs[c][row + 1], z1);
+        z2 = fmaf(Bs[i][row + 2], Xs[c][row + 2], z2);
+        z3 = fmaf(Bs[i][row + 3], Xs[c][row + 3], z3);
+      }
+      for (; row < m; ++row) z0 = fmaf(Bs[i][row], Xs[c][row], z0);
+      Zs[i][c] = (z0 + z1) + (z2 + z3);
     }
     __syncthreads();
     RbIdx x(tid, trans ? RB_TN : m);
@@ -2348,8 +2297,6 @@ int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg, int force_G) {
   return 0;
 }
 
-size_t warm_product_lds_bytes(int n) { return warm_product_lds(n, 4); }
-
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
   switch (c.G) {
@@ -2406,22 +2353,18 @@ hipError_t launch_jacobi_warm_items(ProbDev* const* probs, const CholItem* items
 }
 
 hipError_t launch_warm_product_items(ProbDev* const* probs, const CholItem* items, int nitems, int nmax,
-                                     int max_lds, hipStream_t s) {
+                                     hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  const int cb = warm_product_cb(nmax, (size_t)max_lds);
-  const size_t lds = warm_product_lds(nmax, cb);
-  if (lds > (size_t)max_lds) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_warm_product_items, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_warm_product_items, dim3(nitems), dim3(1024), lds, s, probs, items, cb);
+  const int nb = (nmax + 15) / 16;
+  if (nmax < 1 || (nb * nb + 3) / 4 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_warm_product_items, dim3((unsigned)nitems, (unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s,
+                     probs, items);
   return hipGetLastError();
 }
 
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
-                               long long m_stride, int n, int nslices, int max_lds, hipStream_t s) {
+                               long long m_stride, int n, int nslices, hipStream_t s) {
   if (nslices <= 0) return hipSuccess;
-  (void)max_lds;
   const int nb = (n + 15) / 16;
   const long long jobs = (long long)nslices * nb * nb;
   hipLaunchKernelGGL(k_warm_product_mfma, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, s, L, l_stride, Z, M,

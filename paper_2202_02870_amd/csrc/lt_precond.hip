@@ -485,18 +485,25 @@ __device__ __attribute__((always_inline)) void gram_chol_tiles(const float* W, i
     toff_j[u] = CT * tj + lr;
   }
   for (int k0 = 0; k0 < m; k0 += CTG_ROWS) {
-    // stage rows k0 .. k0 + 15 of W (zero beyond m and n)
-    for (int e = tid; e < CTG_ROWS * npad; e += nt) {
-      int r, c;
-      if (trans) {   // W(r, c) = A[r * I1 + c]: columns contiguous
-        r = e / npad;
-        c = e - r * npad;
-      } else {       // W(r, c) = A[c * I1 + r]: rows contiguous
-        c = e / CTG_ROWS;
-        r = e - c * CTG_ROWS;
+    // stage rows k0 .. k0 + 15 of W (zero beyond m and n); entry e of the
+    // staging order is (r, c) = (e / npad, e % npad) when columns are
+    // contiguous (trans), (e % 16, e / 16) otherwise; each lane starts at
+    // e0 = tid and steps by nt
+    {
+      const int lim = trans ? npad : CTG_ROWS;
+      int b = tid / lim, a = tid - b * lim;
+      const int qb = nt / lim, qa = nt - qb * lim;
+      for (int e = tid; e < CTG_ROWS * npad; e += nt) {
+        const int r = trans ? b : a, c = trans ? a : b;
+        const int row = k0 + r;
+        Wst[r * npad + c] = (row < m && c < n) ? w_elem(W, trans, I1, row, c) : 0.f;
+        a += qa;
+        b += qb;
+        if (a >= lim) {
+          a -= lim;
+          ++b;
+        }
       }
-      const int row = k0 + r;
-      Wst[r * npad + c] = (row < m && c < n) ? w_elem(W, trans, I1, row, c) : 0.f;
     }
     __syncthreads();
 #pragma unroll
