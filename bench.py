@@ -59,6 +59,28 @@ def svt_time_at_peak(m, n, sweeps_total):
     return f64, f32, f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU
 
 
+def svt_time_at_peak_complex(m, n, sweeps_total):
+    """The same for complex m x n slices (Fourier transforms) under Hermitian
+    rotations: per column pair three complex dot products in FP64 (|a|^2 and
+    |b|^2, 4 m flops each, and a^H b, 8 m) and in FP32 the rotation of the pair's
+    data and accumulator columns (the phase on one column, 6 flops per entry,
+    and the real rotation of both, 12 flops per entry: 18 (m + n) flops)."""
+    pairs = n * (n - 1) // 2
+    f64 = float(sweeps_total) * pairs * 16 * m
+    f32 = float(sweeps_total) * pairs * 18 * (m + n)
+    return f64, f32, f64 / PEAK_FP64_VALU + f32 / PEAK_FP32_VALU
+
+
+def kernel_flops_complex(m, n, sweeps, rotations, slices):
+    """What the complex kernel executes: per sweep and slice n(n-1)/2 pair
+    products a^H b (8 m FP64 flops) and n column norms (4 m), the final norms,
+    and per applied rotation 18 m FP32 flops (phase, then rotation)."""
+    pairs = n * (n - 1) // 2
+    f64 = sweeps * (pairs * 8 * m + n * 4 * m) + slices * n * 4 * m
+    f32 = rotations * 18 * m
+    return f64, f32
+
+
 def kernel_flops(rows, n, sweeps, rotations, slices, dot32=False, rot_rows=None):
     """What the kernel itself executes: per sweep and slice n(n-1)/2 pair dot
     products of 2 rows flops and n column norms of 2 rows FP64 flops (rows: the
@@ -285,16 +307,24 @@ def bench_completion(args, torch, lt, wl):
     path = lt.svt_path(shape, p.kinds, precondition=not args.no_precondition)
     precond = "precond" in path
     dft = "dft" in p.kinds
-    jm, jn = (2 * m, 2 * n) if dft else (m, n)   # Fourier: real embeddings of the slices
+    cx = path == "complex"   # Fourier: complex slices, or else their real embeddings
+    jm, jn = (2 * m, 2 * n) if dft and not cx else (m, n)
     warm = lt.pga_warm(shape, p.kinds, precondition=not args.no_precondition, warm_restart=args.warm_restart)
     t_launch = jms / 1e3 / max(jcalls, 1)
-    f64, f32, t_peak = svt_time_at_peak(jm, jn, rep["total_sweeps"])
+    if cx:
+        f64, f32, t_peak = svt_time_at_peak_complex(m, n, rep["total_sweeps"])
+    else:
+        f64, f32, t_peak = svt_time_at_peak(jm, jn, rep["total_sweeps"])
     flops = (f64 + f32) / max(jcalls, 1)
     t_peak /= max(jcalls, 1)
     rows = jn if precond else jm
     rot_rows = rows + 4 * ((jn + 3) // 4) if warm else rows
-    k64, k32 = kernel_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
-                            dot32=args.fp32_dots, rot_rows=rot_rows)
+    if cx:
+        rows = rot_rows = 2 * m   # interleaved real rows of the complex columns
+        k64, k32 = kernel_flops_complex(m, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
+    else:
+        k64, k32 = kernel_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
+                                dot32=args.fp32_dots, rot_rows=rot_rows)
     tk_peak = (k64 / PEAK_FP64_VALU + k32 / PEAK_FP32_VALU) / max(jcalls, 1)
     # the slices run side by side, one workgroup each: a launch lasts as long as
     # its slowest slice, whose sweeps per iteration are reported beside the mean
@@ -307,15 +337,18 @@ def bench_completion(args, torch, lt, wl):
                 "peak": round(flops / t_peak / 1e12, 2) if t_peak > 0 else None, "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None,
                 "traffic": measured_traffic() if default_cfg else None,
-                "count": "per sweep of an m x n slice: n(n-1)/2 pairs x (6m FP64 + 6m+6n FP32) flops, "
-                         "measured sweeps; peak = time at 78.6 (FP64) and 157.3 (FP32) TFLOP/s",
+                "count": ("per sweep of a complex m x n slice: n(n-1)/2 pairs x (16m FP64 + 18(m+n) FP32) flops"
+                          if cx else
+                          "per sweep of an m x n slice: n(n-1)/2 pairs x (6m FP64 + 6m+6n FP32) flops")
+                + ", measured sweeps; peak = time at 78.6 (FP64) and 157.3 (FP32) TFLOP/s",
                 "flops_per_launch": flops, "time_at_peak_us": round(t_peak * 1e6, 2),
                 "launch_ms": round(t_launch * 1e3, 4), "launches": jcalls,
                 "frac_kernel_count": round(tk_peak / t_launch, 4) if t_launch > 0 else None,
                 "slowest_slice_sweeps": round(slowest, 3),
                 "frac_at_slowest_sweeps": round(t_peak * slowest / mean_sw / t_launch, 4)
                 if t_launch > 0 and mean_sw > 0 else None,
-                "slice": [jm, jn], "jacobi_rows": rows, "rotated_rows": rot_rows, "preconditioned": precond,
+                "slice": [jm, jn], "complex": cx, "jacobi_rows": rows, "rotated_rows": rot_rows,
+                "preconditioned": precond,
                 "warm_start": warm, "svt_path": path, "pair_dots": "fp32" if args.fp32_dots else "fp64"}
     line = {
         "metric": "PGA iterations/s (slice-SVT/s alongside) at rel-err <= 1e-4 vs FP64 oracle",

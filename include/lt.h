@@ -142,11 +142,25 @@ typedef struct {
  *                    batch engine (graph-captured ticks) uses the one-workgroup
  *                    blocked kernel up to 512 columns and refuses wider slices.
  * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only.
+ * Fourier slices (complex, one per conjugate pair, Section 2's t-SVD of the
+ * DFT) take
+ *   complex (LT_SVT_COMPLEX, alone): a one-sided Jacobi with Hermitian rotations
+ *                    (the pair's a^H b and the angle in FP64), register-resident,
+ *                    on the m x n complex slice held as 2m interleaved real
+ *                    rows (ceil(n/2) G <= 768 with G = 16 or 8 lanes per pair,
+ *                    at most 48 rows per lane, its exchange buffer within the
+ *                    LDS: up to n <= 96, m <= 384 at G = 16 and n, m <= 192 at
+ *                    G = 8, e.g. the 144 x 176 video slices), not
+ *                    preconditioned;
+ *   otherwise the kernels above on the real embedding [[X, -Y], [Y, X]]
+ *                    (2 I1 x 2 I2; also with LT_DFT_EMBED=1 in the
+ *                    environment).
  * lt_svt_path reports the single-problem calls' choice. */
 #define LT_SVT_REGISTER 0
 #define LT_SVT_PRECOND 1   /* bit */
 #define LT_SVT_BLOCKED 2   /* bit */
 #define LT_SVT_WIDE 4      /* bit (with LT_SVT_BLOCKED): the wide blocked Jacobi, see above */
+#define LT_SVT_COMPLEX 8   /* the complex Hermitian Jacobi of Fourier slices, see above */
 
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */

@@ -886,15 +886,92 @@ SvtCore core_of(const SvtWs& w) {
   return c;
 }
 
+// Fourier slices take the complex Hermitian Jacobi when its register-resident
+// kernel holds the representative's working matrix (2 max(I1, I2) interleaved
+// rows, min(I1, I2) columns); otherwise, or with LT_DFT_EMBED=1 in the
+// environment, the real embedding.  The complex path does not precondition.
+bool dft_complex(const Shape& s, int max_lds, lt::JacobiConfig* cc) {
+  if (!s.any_dft) return false;
+  const char* env = getenv("LT_DFT_EMBED");
+  if (env && atoi(env) == 1) return false;
+  const long long m = s.I1 > s.I2 ? s.I1 : s.I2, n = s.I1 > s.I2 ? s.I2 : s.I1;
+  if (m > 4096) return false;
+  return lt::jacobi_cx_config(2 * (int)m, (int)n, max_lds, cc) == 0;
+}
+
+// The complex path: the representatives' working matrices (2 N floats each)
+// into the embedding buffer, the Hermitian Jacobi (each kept column written
+// with its product by i: up to 2 n columns, 4 N floats per representative in
+// the embedding's Bk), the real rebuild over the interleaved rows in place, and
+// the results back to the planes.
+int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiConfig& cc, double tau, double tol,
+               int max_sweeps, int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total,
+               unsigned long long* rot_total, unsigned int* hits) {
+  const DftWs& d = w.dft;
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  const long long N = s.N;
+  float* Re = w.Gh;
+  float* Im = w.Gh + s.nel;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_dft_stack(Re, Im, d.rep, d.npairs, (int)s.I1, (int)s.I2, d.E, h->stream));
+  }
+  lt::JacobiArgs a{};
+  a.src = d.E;
+  a.slice_stride = 2 * N;
+  a.I1 = 2 * m;
+  a.I2 = n;
+  a.nslices = d.npairs;
+  a.tau = tau;
+  a.tol = fabs(tol);
+  a.max_sweeps = max_sweeps;
+  a.mode = 0;
+  a.bk = d.inner.Bk;
+  a.bk_stride = 4 * N;
+  a.rank = d.inner.rank;
+  a.sweeps = d.inner.sweeps;
+  a.sweep_total = sweep_total;
+  a.rot_total = rot_total;
+  a.maxsweep_hits = hits;
+  a.nuc = d.inner.nuc;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi_cx(a, cc, h->stream));
+  }
+  lt::RebuildArgs r{};
+  r.W = d.E;
+  r.D = d.E;
+  r.bk = d.inner.Bk;
+  r.rank = d.inner.rank;
+  r.slice_stride = 2 * N;
+  r.bk_stride = 4 * N;
+  r.kmax = 2 * n;
+  r.I1 = 2 * m;
+  r.I2 = n;
+  r.nslices = d.npairs;
+  r.flip = 0;
+  {
+    ProfScope ps(h, LT_PROF_REBUILD);
+    HIP_TRY(h, lt::launch_rebuild(r, h->stream));
+  }
+  ProfScope ps(h, LT_PROF_OTHER);
+  HIP_TRY(h, lt::launch_dft_unstack(d.E, d.rep, d.partner, d.npairs, (int)s.I1, (int)s.I2, Re, Im, d.inner.rank,
+                                    rank, d.inner.sweeps, sweeps, d.inner.nuc, w.nuc, h->stream));
+  return LT_OK;
+}
+
 // SVT of the transform-domain slices of w.Gh in place: real slices directly,
-// complex ones (Fourier modes) through the real embeddings of one slice per
-// conjugate pair.  rank / sweeps: per slice (P entries).
+// complex ones (Fourier modes) one slice per conjugate pair, by the complex
+// Jacobi or through the real embeddings.  rank / sweeps: per slice (P entries).
 int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol, int max_sweeps,
             int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total, unsigned long long* rot_total,
             unsigned int* hits, bool precond, const WarmState* warm = nullptr) {
   if (!s.any_dft)
     return run_jacobi_svt(h, s, w.Gh, w.Gh, core_of(w), tau, tol, max_sweeps, rank, sweeps, sweep_total,
                           rot_total, hits, precond, warm);
+  lt::JacobiConfig cc;
+  if (dft_complex(s, h->max_lds, &cc))
+    return run_cx_svt(h, s, w, cc, tau, tol, max_sweeps, rank, sweeps, sweep_total, rot_total, hits);
   const DftWs& d = w.dft;
   const Shape se = embed_shape(s, d.npairs);
   float* Re = w.Gh;
@@ -943,6 +1020,8 @@ double nuclear_alpha(const Shape& s) {
 // Cholesky-QR factor) and fits the device's LDS.
 int check_svt_shape(lt_handle* h, const Shape& s0, bool precond) {
   Shape s = s0;
+  lt::JacobiConfig cc;
+  if (dft_complex(s0, h->max_lds, &cc)) return LT_OK;
   if (s0.any_dft) {
     std::vector<int> rep, partner;
     dft_pairs(s0, &rep, &partner);
@@ -1412,6 +1491,8 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   Shape s;
   int rc = parse(nullptr, a, &s);
   if (rc) return rc;
+  lt::JacobiConfig cc;
+  if (dft_complex(s, kBlkLdsBudget, &cc)) return LT_SVT_COMPLEX;
   if (s.any_dft) {   // the Jacobi runs on the real embeddings of the complex slices
     std::vector<int> rep, partner;
     dft_pairs(s, &rep, &partner);

@@ -83,6 +83,15 @@ hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner
                               float* Re, float* Im, const int32_t* rankE, int32_t* rank,
                               const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
                               hipStream_t s);
+// The same slices <-> complex working matrices of the Hermitian Jacobi (2 max(I1,
+// I2) interleaved rows by min(I1, I2) columns, 2 I1 I2 floats each), and the
+// results back with the partners' conjugates.
+hipError_t launch_dft_stack(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
+                            float* W, hipStream_t s);
+hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner, int npairs, int I1, int I2,
+                              float* Re, float* Im, const int32_t* rankE, int32_t* rank,
+                              const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
+                              hipStream_t s);
 // out[0] = scale * (v[0] + ... + v[n-1]) in a fixed summation order (one workgroup).
 hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s);
 
@@ -161,6 +170,12 @@ struct WarmArgs {
 // Configuration for n x n factors (0 on success, -1 if the kernel cannot hold
 // them), launch, and the product M = L Z (FP32 MFMA, no LDS).
 int jacobi_warm_config(int n, int max_lds, JacobiConfig* cfg, int force_G = 0);
+// Complex (Hermitian) Jacobi for Fourier slices on their stacked working
+// matrices (ms = 2 m interleaved rows, n columns, SVT mode): configuration (0 on
+// success, -1 if the kernel cannot hold them) and launch.  Bk takes 2 r
+// columns of ms rows per slice (each kept column and its product by i).
+int jacobi_cx_config(int ms, int n, int max_lds, JacobiConfig* cfg);
+hipError_t launch_jacobi_cx(const JacobiArgs& a, const JacobiConfig& cfg, hipStream_t s);
 hipError_t launch_jacobi_warm(const WarmArgs& a, const JacobiConfig& cfg, hipStream_t s);
 hipError_t launch_warm_product(const float* L, long long l_stride, const float* Z, float* M,
                                long long m_stride, int n, int nslices, hipStream_t s);
@@ -233,6 +248,8 @@ struct RebuildArgs {
   int I1, I2, nslices;
   int flip;                // 0: D_W = Bk (Bk^T W), Bk m x r; 1: D_W = (W B) B^T, B n x r
   int rcap;                // set by launch_rebuild: kept-column capacity of its LDS
+  long long bk_stride;     // between the slices' kept columns (0: slice_stride)
+  int kmax;                // bound on the kept counts (0: min(I1, I2))
 };
 
 // Cholesky-QR preconditioning of the Jacobi SVD (lt_precond.hip).

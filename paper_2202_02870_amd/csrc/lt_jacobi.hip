@@ -135,6 +135,33 @@ __device__ inline float dot32x(const float (&x)[R], const float (&y)[R]) {
   return d0 + d1;
 }
 
+// Complex columns (Fourier slices) are held with their real and imaginary
+// parts in consecutive rows (row 2i: Re, row 2i + 1: Im), so that a lane's
+// 4-row chunks hold whole entries.  a^H b = sum conj(a_i) b_i: its real part is
+// the plain dot product of the interleaved rows, its imaginary part sums
+// Re a_i Im b_i - Im a_i Re b_i.  Both in FP64 from the exact FP32 products.
+template <int R>
+__device__ inline void dot64c(const float (&x)[R], const float (&y)[R], double& re, double& im) {
+  double r0 = 0.0, r1 = 0.0, i0 = 0.0, i1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < R / 4; ++q) {
+    const int r = 4 * q;
+    const double xr0 = x[r], xi0 = x[r + 1], xr1 = x[r + 2], xi1 = x[r + 3];
+    const double yr0 = y[r], yi0 = y[r + 1], yr1 = y[r + 2], yi1 = y[r + 3];
+    r0 = fma(xr0, yr0, r0);
+    r1 = fma(xr1, yr1, r1);
+    i0 = fma(xr0, yi0, i0);
+    i1 = fma(xr1, yi1, i1);
+    r0 = fma(xi0, yi0, r0);
+    r1 = fma(xi1, yi1, r1);
+    i0 = fma(-xi0, yr0, i0);
+    i1 = fma(-xi1, yr1, i1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  re = r0 + r1;
+  im = i0 + i1;
+}
+
 // Hardware FP64 reciprocal refined by one Newton step (about 1e-15 relative):
 // it only forms the rotation's zeta, which is then rounded to FP32, so the
 // IEEE-exact division sequence is not needed.
@@ -319,6 +346,25 @@ __device__ inline void stage_out(float* __restrict__ out, const float* buf, int 
   }
 }
 
+// stage_out for complex columns: output column d takes the scaled column and
+// column d + 1 its product with i ((Re, Im) -> (-Im, Re) per entry), so that
+// the real rebuild over the interleaved rows, D = B B^T W with B = [b, i b],
+// forms b b^H W.  m is even.
+__device__ inline void stage_out_cx(float* __restrict__ out, const float* buf, int ldw, int m, int npairs,
+                                    int t2, int tps) {
+  const int total = npairs * m;
+  for (int e = t2; e < total; e += tps) {
+    const int p = e / m, row = e - p * m;
+    const float* col = buf + (size_t)p * ldw;
+    const int d = __float_as_int(col[ldw - 2]);
+    if (d >= 0) {
+      const float sc = (float)__hiloint2double(__float_as_int(col[ldw - 3]), __float_as_int(col[ldw - 4]));
+      out[(long long)d * m + row] = col[row] * sc;
+      out[(long long)(d + 1) * m + row] = ((row & 1) ? col[row - 1] : -col[row + 1]) * sc;
+    }
+  }
+}
+
 // Exchange positions of one buffer: the ring phases use one per slot; the
 // circle phase of the odd-sized ranges uses c + 1 per range of c slots (one
 // extra for the bottom of the range's first slot).
@@ -363,9 +409,14 @@ struct Job {
   double* nuc;   // SVT: sum of (sigma_i - tau) over the kept columns (may be null)
 };
 
-template <int G, int R>
+// CX: complex columns (interleaved rows, see dot64c) under Hermitian
+// rotations, SVT mode only; each kept column is written with its product by i
+// (stage_out_cx) and counted twice in the rank and the nuclear-norm share, so
+// the output has the layout of the real SVT of the embedding [[X, -Y], [Y, X]].
+// Out of line: inlined into the kernels it needs more registers.
+template <int G, int R, bool CX = false>
 __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf, int ldw,
-                            unsigned char* smem) {
+                                                     unsigned char* smem) {
   const int I1 = jb.I1, I2 = jb.I2, qeff = jb.qeff;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
@@ -446,25 +497,58 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
       // so the column registers are updated in place rather than merged lane by
       // lane after a divergent branch.
       float cf = 1.f, sf = 0.f;
+      float er = 1.f, ei = 0.f;   // CX: the phase of a^H b
       double t = 0.0;
       double d = 0.0, pa = 0.0, pb = 0.0;
       bool rot = false;
       if (moving) {
-        d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv)) : group_sum<G>(dot64<R>(av, bv));
         pa = fmax(na, 0.0);
         pb = fmax(nb, 0.0);
-        rot = d != 0.0 && d * d > tol * tol * (pa * pb);   // |d| > tol sqrt(pa pb)
-        if (rot) jacobi_angle(d, pa, pb, t, cf, sf);
+        if (CX) {
+          // Hermitian rotation: with a^H b = |g| e^{i phi}, b e^{-i phi} meets a
+          // with the real product |g|, and the real rotation of that pair
+          // orthogonalises it
+          double gr, gi;
+          dot64c<R>(av, bv, gr, gi);
+          gr = group_sum<G>(gr);
+          gi = group_sum<G>(gi);
+          const double g2 = fma(gr, gr, gi * gi);
+          rot = g2 != 0.0 && g2 > tol * tol * (pa * pb);   // |g| > tol sqrt(pa pb)
+          if (rot) {
+            d = sqrt(g2);
+            jacobi_angle(d, pa, pb, t, cf, sf);
+            const double id = 1.0 / d;
+            er = (float)(gr * id);
+            ei = (float)(gi * id);
+          }
+        } else {
+          d = dot32 ? (double)group_sumf<G>(dot32x<R>(av, bv)) : group_sum<G>(dot64<R>(av, bv));
+          rot = d != 0.0 && d * d > tol * tol * (pa * pb);   // |d| > tol sqrt(pa pb)
+          if (rot) jacobi_angle(d, pa, pb, t, cf, sf);
+        }
       }
       // (the in-place update with a wave-uniform skip, rotate_in_place, leaves
       // this out-of-line body's columns in registers the LDS exchange cannot
       // store as float4 tuples: the update stays unconditional here)
+      if (CX) {
 #pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const float x = av[e], y = bv[e];
-        const float sy = sf * y, sx = sf * x;
-        av[e] = fmaf(cf, x, -sy);
-        bv[e] = fmaf(cf, y, sx);
+        for (int e = 0; e < R; e += 2) {
+          const float xr = av[e], xi = av[e + 1], br = bv[e], bi = bv[e + 1];
+          const float yr = fmaf(er, br, ei * bi);      // b e^{-i phi}
+          const float yi = fmaf(er, bi, -(ei * br));
+          av[e] = fmaf(cf, xr, -(sf * yr));
+          av[e + 1] = fmaf(cf, xi, -(sf * yi));
+          bv[e] = fmaf(cf, yr, sf * xr);
+          bv[e + 1] = fmaf(cf, yi, sf * xi);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const float x = av[e], y = bv[e];
+          const float sy = sf * y, sx = sf * x;
+          av[e] = fmaf(cf, x, -sy);
+          bv[e] = fmaf(cf, y, sx);
+        }
       }
       if (rot) {
         na = fma(-t, d, pa);
@@ -582,7 +666,7 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
       nsum += nucs[i];
     }
     ctl[2] = acc;
-    if (jb.mode == 0 && jb.nuc) jb.nuc[sub] = nsum;
+    if (jb.mode == 0 && jb.nuc) jb.nuc[sub] = CX ? 2.0 * nsum : nsum;
   }
   __syncthreads();
   // kept columns, scaled, through LDS: tops, then bottoms
@@ -593,8 +677,8 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   if (jb.mode == 0) {
     sca = ka ? sqrt(1.0 - jb.tau / sa) / sa : 0.0;
     scb = kb ? sqrt(1.0 - jb.tau / sb) / sb : 0.0;
-    da = ka ? j0 : -1;
-    db = kb ? j0 + (int)ka : -1;
+    da = ka ? (CX ? 2 * j0 : j0) : -1;
+    db = kb ? (CX ? 2 * (j0 + (int)ka) : j0 + (int)ka) : -1;
   } else {
     // all columns, at their original column index, plus their norms
     sca = 1.0;
@@ -606,13 +690,19 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   }
   if (active) put_col<G, R>(bufA, ldw, g, l, av, qeff, sca, da);
   __syncthreads();
-  if (active) stage_out(out, bufA, ldw, m, npairs, t2, tps);
+  if (active) {
+    if (CX) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
+    else stage_out(out, bufA, ldw, m, npairs, t2, tps);
+  }
   __syncthreads();
   if (active) put_col<G, R>(bufA, ldw, g, l, bv, qeff, scb, db);
   __syncthreads();
-  if (active) stage_out(out, bufA, ldw, m, npairs, t2, tps);
+  if (active) {
+    if (CX) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
+    else stage_out(out, bufA, ldw, m, npairs, t2, tps);
+  }
   if (active && t2 == 0) {
-    if (jb.rank) jb.rank[sub] = ctl[2];
+    if (jb.rank) jb.rank[sub] = CX ? 2 * ctl[2] : ctl[2];
     if (jb.sweeps) jb.sweeps[sub] = my_sweeps;
     if (jb.sweep_total) atomicAdd(jb.sweep_total, (unsigned long long)my_sweeps);
     if (jb.rot_total) atomicAdd(jb.rot_total, (unsigned long long)rotations);
@@ -1016,8 +1106,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_blk_items(ProbDev* const* probs
   jacobi_blk_body<G, R>(jb, tol, max_sweeps, smem);
 }
 
-// One slice per workgroup (single problem).
-template <int G, int R, int LB>
+// One slice per workgroup (single problem); CX: complex slices (SVT mode).
+template <int G, int R, int LB, bool CX = false>
 __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int s = blockIdx.x;
@@ -1040,7 +1130,7 @@ __global__ __launch_bounds__(LB) void k_jacobi(JacobiArgs a, int nbuf, int ldw) 
   jb.rot_total = a.rot_total;
   jb.hits = a.maxsweep_hits;
   jb.nuc = a.nuc ? a.nuc + s : nullptr;
-  jacobi_body<G, R>(jb, a.tol, a.max_sweeps, nbuf, ldw, smem);
+  jacobi_body<G, R, CX>(jb, a.tol, a.max_sweeps, nbuf, ldw, smem);
 }
 
 // Batch: one workgroup per item (nsub same-shape slices of one problem),
@@ -1719,7 +1809,8 @@ __global__ __launch_bounds__(256) void k_rebuild_small(RebuildArgs a) {
   const int j0 = blockIdx.x * RB_TN;
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
-  rebuild_body_small(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
+  const float* bk = a.bk + (long long)s * (a.bk_stride ? a.bk_stride : a.slice_stride);
+  rebuild_body_small(a.W + off, a.D + off, bk, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
 }
 
 template <int RMAX>
@@ -1729,7 +1820,8 @@ __global__ __launch_bounds__(256) void k_rebuild(RebuildArgs a) {
   const int j0 = blockIdx.x * RB_TN;
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
-  rebuild_body<RMAX>(a.W + off, a.D + off, a.bk + off, a.rank[s], a.I1, a.I2, j0, a.flip != 0, a.rcap);
+  const float* bk = a.bk + (long long)s * (a.bk_stride ? a.bk_stride : a.slice_stride);
+  rebuild_body<RMAX>(a.W + off, a.D + off, bk, a.rank[s], a.I1, a.I2, j0, a.flip != 0, a.rcap);
 }
 
 template <int RMAX>
@@ -2235,6 +2327,88 @@ hipError_t launch_jacobi(const JacobiArgs& a0, const JacobiConfig& c, hipStream_
   }
 }
 
+// Complex slices: the stacked working matrix has ms = 2 m interleaved rows and
+// n complex columns.  One 768-lane bound (up to 168 VGPRs per lane, for up to
+// 48 rows per lane), G = 16 or 8 lanes per pair, R from a short list.
+template <int G, int R>
+static hipError_t launch_cx_one(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
+  const int ldw = G * R + 4;
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi<G, R, 768, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_jacobi<G, R, 768, true>), dim3(a.nslices), dim3(c.threads), c.lds, s, a, c.nbuf, ldw);
+  return hipGetLastError();
+}
+
+// Rows per lane instantiated (a count rounds up to the next): G = 16 serves
+// columns of more than 128 rows only (more than 8 per lane), and G = 8 takes
+// columns of more than 128 rows only when 16 lanes per pair would exceed the
+// workgroup (n > 96, so more than 192 rows: more than 24 per lane).
+static int cx_round_r(int G, int r) {
+  static const int r8[] = {8, 16, 32, 36, 40, 44, 48};
+  static const int r16[] = {16, 24, 32, 40, 48};
+  const int* v = G == 8 ? r8 : r16;
+  const int nv = G == 8 ? 7 : 5;
+  for (int i = 0; i < nv; ++i)
+    if (r <= v[i]) return v[i];
+  return 0;
+}
+
+int jacobi_cx_config(int ms, int n, int max_lds, JacobiConfig* cfg) {
+  if (ms < 2 || (ms & 1) || n < 1 || ms < n || 2 * n > RB_RMAX_BLK) return -1;
+  const int npairs = (n + 1) / 2;
+  const int Gs[2] = {16, 8};
+  for (int gi = 0; gi < 2; ++gi) {
+    const int G = Gs[gi];
+    if (G == 16 && ms <= 128) continue;   // short columns: 8 lanes already hold them in <= 16 rows each
+    const int threads = ((npairs * G + 63) / 64) * 64;
+    if (threads > 768) continue;
+    const int R = cx_round_r(G, (ms + G - 1) / G);
+    if (!R) continue;
+    const int ldw = G * R + 4;
+    int nbuf = 2;
+    if (jacobi_lds_bytes(npairs, ldw, 2) > (size_t)max_lds) nbuf = 1;
+    if (jacobi_lds_bytes(npairs, ldw, nbuf) > (size_t)max_lds) continue;
+    cfg->G = G;
+    cfg->R = R;
+    cfg->threads = threads;
+    cfg->nbuf = nbuf;
+    cfg->lds = jacobi_lds_bytes(npairs, ldw, nbuf);
+    return 0;
+  }
+  return -1;
+}
+
+hipError_t launch_jacobi_cx(const JacobiArgs& a0, const JacobiConfig& c, hipStream_t s) {
+  if (a0.nslices <= 0) return hipSuccess;
+  if (a0.mode != 0 || (a0.I1 & 1) || a0.I1 < a0.I2 || a0.tol < 0.0) return hipErrorInvalidValue;
+  JacobiArgs a = a0;
+  a.qeff = c.R / 4;
+  if (c.G == 8) {
+    switch (c.R) {
+      case 8: return launch_cx_one<8, 8>(a, c, s);
+      case 16: return launch_cx_one<8, 16>(a, c, s);
+      case 32: return launch_cx_one<8, 32>(a, c, s);
+      case 36: return launch_cx_one<8, 36>(a, c, s);
+      case 40: return launch_cx_one<8, 40>(a, c, s);
+      case 44: return launch_cx_one<8, 44>(a, c, s);
+      case 48: return launch_cx_one<8, 48>(a, c, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (c.G == 16) {
+    switch (c.R) {
+      case 16: return launch_cx_one<16, 16>(a, c, s);
+      case 24: return launch_cx_one<16, 24>(a, c, s);
+      case 32: return launch_cx_one<16, 32>(a, c, s);
+      case 40: return launch_cx_one<16, 40>(a, c, s);
+      case 48: return launch_cx_one<16, 48>(a, c, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int G, int R, int LB>
 static hipError_t launch_warm_one(const WarmArgs& a, const JacobiConfig& c, hipStream_t s) {
   const int ldw = G * R + 4;
@@ -2541,7 +2715,8 @@ hipError_t launch_rebuild_tiles(ProbDev* const* probs, const RebuildTile* tiles,
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   if (a.nslices <= 0) return hipSuccess;
   const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
-  const int kmax = a.I1 < a.I2 ? a.I1 : a.I2;   // kept columns are at most min(I1, I2)
+  // kept columns are at most min(I1, I2), or the caller's bound
+  const int kmax = a.kmax ? a.kmax : (a.I1 < a.I2 ? a.I1 : a.I2);
   if (kmax > RB_RMAX_BLK) return hipErrorInvalidValue;
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
   const int m = a.flip ? (a.I1 < a.I2 ? a.I1 : a.I2) : (a.I1 < a.I2 ? a.I2 : a.I1);

@@ -434,6 +434,94 @@ __global__ void k_dft_extract(const float* __restrict__ E, const int* rep, const
   }
 }
 
+// Complex working matrices of the representatives rep[t] for the Hermitian
+// Jacobi: ms = 2 m interleaved rows (row 2r: Re, 2r + 1: Im) by n columns,
+// column-major, 2N floats per representative.  I1 >= I2: the slice's columns
+// (entry (i, j) at row pair i of column j); I1 < I2: its rows (entry (i, j) at
+// row pair j of column i, the plain transpose, whose SVT is the transpose of
+// the slice's).  A 32 x 32 tile per workgroup goes through LDS so that reads
+// and writes are both coalesced.
+__global__ __launch_bounds__(256) void k_dft_stack(const float* __restrict__ Re, const float* __restrict__ Im,
+                                                   const int* rep, int I1, int I2, long long N,
+                                                   float* __restrict__ W) {
+  __shared__ float2 T[32][33];   // T[j - j0][i - i0]
+  const int t = blockIdx.y;
+  const int ti = (I1 + 31) / 32;
+  const int i0 = 32 * (int)(blockIdx.x % ti), j0 = 32 * (int)(blockIdx.x / ti);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const long long src = (long long)rep[t] * N;
+  for (int jj = ty; jj < 32; jj += 8) {
+    const int i = i0 + tx, j = j0 + jj;
+    if (i < I1 && j < I2) {
+      const long long e = src + (long long)j * I1 + i;
+      T[jj][tx] = make_float2(Re[e], Im[e]);
+    }
+  }
+  __syncthreads();
+  float2* Wt = reinterpret_cast<float2*>(W + (long long)t * 2 * N);
+  if (I1 >= I2) {
+    for (int jj = ty; jj < 32; jj += 8) {
+      const int i = i0 + tx, j = j0 + jj;
+      if (i < I1 && j < I2) Wt[(long long)j * I1 + i] = T[jj][tx];
+    }
+  } else {
+    for (int ii = ty; ii < 32; ii += 8) {
+      const int i = i0 + ii, j = j0 + tx;
+      if (i < I1 && j < I2) Wt[(long long)i * I2 + j] = T[tx][ii];
+    }
+  }
+}
+
+// The complex SVT results back to the planes: slice rep[t] from its working
+// matrix (layout of k_dft_stack), its partner the conjugate, a self-conjugate
+// slice a zero imaginary part.  Ranks, sweeps and nuclear-norm shares as
+// k_dft_extract (the Jacobi counts each kept complex column twice).
+__global__ __launch_bounds__(256) void k_dft_unstack(const float* __restrict__ W, const int* rep,
+                                                     const int* partner, int I1, int I2, long long N,
+                                                     float* __restrict__ Re, float* __restrict__ Im,
+                                                     const int32_t* rankE, int32_t* rank, const int32_t* sweepsE,
+                                                     int32_t* sweeps, const double* nucE, double* nuc) {
+  __shared__ float2 T[32][33];
+  const int t = blockIdx.y;
+  const int p = rep[t], q = partner[t];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (rank) rank[p] = rank[q] = rankE[t] / 2;
+    if (sweeps) sweeps[p] = sweeps[q] = sweepsE[t];
+    if (nuc) nuc[p] = nuc[q] = 0.5 * nucE[t];
+  }
+  const int ti = (I1 + 31) / 32;
+  const int i0 = 32 * (int)(blockIdx.x % ti), j0 = 32 * (int)(blockIdx.x / ti);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const float2* Wt = reinterpret_cast<const float2*>(W + (long long)t * 2 * N);
+  if (I1 >= I2) {
+    for (int jj = ty; jj < 32; jj += 8) {
+      const int i = i0 + tx, j = j0 + jj;
+      if (i < I1 && j < I2) T[jj][tx] = Wt[(long long)j * I1 + i];
+    }
+  } else {
+    for (int ii = ty; ii < 32; ii += 8) {
+      const int i = i0 + ii, j = j0 + tx;
+      if (i < I1 && j < I2) T[tx][ii] = Wt[(long long)i * I2 + j];
+    }
+  }
+  __syncthreads();
+  for (int jj = ty; jj < 32; jj += 8) {
+    const int i = i0 + tx, j = j0 + jj;
+    if (i < I1 && j < I2) {
+      const float2 v = T[jj][tx];
+      const long long e = (long long)j * I1 + i;
+      Re[(long long)p * N + e] = v.x;
+      if (q == p) {
+        Im[(long long)p * N + e] = 0.f;
+      } else {
+        Im[(long long)p * N + e] = v.y;
+        Re[(long long)q * N + e] = v.x;
+        Im[(long long)q * N + e] = -v.y;
+      }
+    }
+  }
+}
+
 // out = scale * sum of v[0..n): per-thread sums over a fixed stride, then the
 // fixed-order workgroup sum (the same bits on every call).
 __global__ __launch_bounds__(256) void k_sum_scaled(const double* v, int n, double scale, double* out) {
@@ -617,6 +705,26 @@ hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)npairs);
   hipLaunchKernelGGL(k_dft_extract, grid, dim3(256), 0, s, E, rep, partner, I1, I2, N, Re, Im, rankE, rank,
                      sweepsE, sweeps, nuc ? nucE : nullptr, nuc);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_stack(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
+                            float* W, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const long long tiles = (long long)((I1 + 31) / 32) * ((I2 + 31) / 32);
+  hipLaunchKernelGGL(k_dft_stack, dim3((unsigned)tiles, (unsigned)npairs), dim3(256), 0, s, Re, Im, rep, I1, I2,
+                     (long long)I1 * I2, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner, int npairs, int I1, int I2,
+                              float* Re, float* Im, const int32_t* rankE, int32_t* rank,
+                              const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
+                              hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  const long long tiles = (long long)((I1 + 31) / 32) * ((I2 + 31) / 32);
+  hipLaunchKernelGGL(k_dft_unstack, dim3((unsigned)tiles, (unsigned)npairs), dim3(256), 0, s, W, rep, partner, I1,
+                     I2, (long long)I1 * I2, Re, Im, rankE, rank, sweepsE, sweeps, nuc ? nucE : nullptr, nuc);
   return hipGetLastError();
 }
 

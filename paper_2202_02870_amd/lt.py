@@ -64,7 +64,8 @@ class ProblemC(ctypes.Structure):
 
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
 SVT_PATHS = ("register", "precond", "blocked", "precond+blocked",   # LT_SVT_PRECOND / LT_SVT_BLOCKED bits
-             None, None, "blocked+wide", "precond+blocked+wide")    # ... and LT_SVT_WIDE
+             None, None, "blocked+wide", "precond+blocked+wide",    # ... and LT_SVT_WIDE
+             "complex")                                             # LT_SVT_COMPLEX (Fourier slices)
 
 
 class Profile(ctypes.Structure):
@@ -282,7 +283,9 @@ def svt_path(shape, kinds=None, precondition=True):
     on the slice), "precond" (on its Cholesky-QR factor), "blocked" (blocked
     Jacobi on the slice), "precond+blocked" (blocked, on the factor), and
     "blocked+wide" / "precond+blocked+wide" (the wide blocked Jacobi, one
-    workgroup per block pair); host only, LtError if no kernel takes the shape."""
+    workgroup per block pair), "complex" (Fourier slices: the Hermitian Jacobi
+    on the complex slices; otherwise the real embeddings take one of the
+    others); host only, LtError if no kernel takes the shape."""
     d = make_desc(tuple(shape), kinds)
     o = svd_opts(precondition=precondition)
     st = _lib.lt_svt_path(ctypes.byref(d), ctypes.byref(o))

@@ -1,0 +1,123 @@
+"""GPU tests of the complex Hermitian Jacobi that thresholds Fourier slices
+(one per conjugate pair, Section 2's t-SVD under the DFT): against the FP64
+oracle's complex SVT slice by slice, against the real-embedding path it
+replaces, and inside the completion.  The cases reach every instantiated
+(lanes per pair, rows per lane) and both orientations of the slice."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as o
+import parity
+from paper_2202_02870_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_02870_amd import lt as _lt
+    return _lt
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _low_rank_plus_noise(shape, kinds, seed):
+    rng = np.random.default_rng(seed)
+    mats = o.mats_for(shape, list(kinds))
+    r = max(1, min(shape[0], shape[1]) // 4)
+    A = o.lproduct(rng.standard_normal((shape[0], r) + shape[2:]),
+                   rng.standard_normal((r, shape[1]) + shape[2:]), mats).real
+    return A + 0.05 * rng.standard_normal(shape), mats
+
+
+# (shape, kinds, G, rows per lane) of the complex working matrix: 2 max(I1, I2)
+# interleaved rows by min(I1, I2) columns
+CX_CASES = [
+    ((8, 6, 5), ("dft",)),              # G 8, R 8; P = 5: one self-conjugate slice
+    ((5, 9, 6), ("dft",)),              # transposed; P = 6: two self-conjugate slices
+    ((60, 51, 4), ("dft",)),            # G 8, R 16, odd n
+    ((100, 80, 4), ("dft",)),           # G 16, R 16
+    ((96, 190, 2), ("dft",)),           # G 16, R 24, transposed
+    ((256, 64, 3), ("dft",)),           # G 16, R 32
+    ((60, 300, 2), ("dft",)),           # G 16, R 40, transposed
+    ((380, 12, 3), ("dft",)),           # G 16, R 48
+    ((128, 100, 2), ("dft",)),          # G 8, R 32
+    ((130, 101, 3), ("dft",)),          # G 8, R 36
+    ((120, 150, 2), ("dft",)),          # G 8, R 40, transposed
+    ((10, 7, 4, 3), ("dft", "dct")),    # mixed transforms
+    ((190, 192, 2), ("dft",)),          # G 8, R 48, one exchange buffer, transposed
+]
+
+
+@pytest.mark.parametrize("shape,kinds", CX_CASES)
+def test_svt_complex_matches_oracle(lt, shape, kinds):
+    assert lt.svt_path(shape, kinds) == "complex"
+    A, mats = _low_rank_plus_noise(shape, kinds, sum(shape))
+    s = o.singular_values(A, mats)
+    for tau in (0.0, float(np.quantile(s, 0.5)), float(s.max()) * 1.01):
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds)
+        ref = o.svt(A, tau, mats)
+        rk, ref_rk = lt.to_host(rank), np.asarray(o.svt_ranks(A, tau, mats))
+        say("complex svt", shape, kinds, "tau", tau, "ranks", rk[:6], "sweeps", lt.to_host(sweeps)[:6])
+        if np.linalg.norm(ref) > 0:
+            parity.check(lt.to_host(D), ref, 2e-5, label="%s tau %.3g" % (shape, tau))
+        else:
+            assert float(np.abs(lt.to_host(D)).max()) == 0.0
+        near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
+        assert np.all(np.abs(rk - ref_rk) <= near)
+
+
+def test_svt_complex_video_against_embedding(lt):
+    """The 144 x 176 x 3 x 50 video with the DFT along both trailing modes (76
+    representatives, 2 self-conjugate): the complex path and the real
+    embedding against the oracle, the same ranks, and a gap threshold's ranks
+    exactly."""
+    shape, kinds = (144, 176, 3, 50), ("dft", "dft")
+    A, mats = _low_rank_plus_noise(shape, kinds, 144)
+    s = o.singular_values(A, mats)
+    tau = float(np.quantile(s, 0.9))
+    ref = o.svt(A, tau, mats)
+    Dc, rc, sc = lt.svt_prox(lt.to_device(A), tau, kinds)
+    os.environ["LT_DFT_EMBED"] = "1"
+    try:
+        assert lt.svt_path(shape, kinds) != "complex"
+        De, re_, se = lt.svt_prox(lt.to_device(A), tau, kinds)
+    finally:
+        del os.environ["LT_DFT_EMBED"]
+    say("video dft: complex sweeps", lt.to_host(sc).mean(), "embedding sweeps", lt.to_host(se).mean())
+    parity.check(lt.to_host(Dc), ref, 2e-5, label="complex")
+    parity.check(lt.to_host(De), ref, 2e-5, label="embedding")
+    near = (np.abs(s - tau) < 1e-4 * s.max()).sum(axis=1)
+    assert np.all(np.abs(lt.to_host(rc) - np.asarray(o.svt_ranks(A, tau, mats))) <= near)
+    assert np.all(np.abs(lt.to_host(rc) - lt.to_host(re_)) <= near)
+    # a threshold in the gap between the rank-36 signal and the noise
+    tau = float(0.5 * (s[:, 35].min() + s[:, 36].max()))
+    assert s[:, 35].min() > 1.2 * s[:, 36].max()
+    D, rank, _ = lt.svt_prox(lt.to_device(A), tau, kinds)
+    assert np.all(lt.to_host(rank) == 36)
+    parity.check(lt.to_host(D), o.svt(A, tau, mats), 2e-5, label="gap")
+
+
+def test_pga_video_dft(lt):
+    """Completion of the 144 x 176 x 3 x 50 video tensor under the DFT (the
+    t-product's TNN-PGA-F) through the complex path, 10 iterations of the
+    default schedule, against the oracle."""
+    import torch
+    p = wl.make_problem((144, 176, 3, 50), 10, 0.3, seed=5, kinds=("dft", "dft"))
+    assert lt.svt_path(p.shape, p.kinds) == "complex"
+    s = wl.pga_schedule_params(p.M, p.mask)
+    iters = 10
+    params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
+    X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
+    Xo, _ = o.complete_pga(p.M, p.mask, o.mats_for(p.shape, list(p.kinds)), mu0=s["mu0"], nu=s["nu"],
+                           mu_bar=s["mu_bar"], max_iter=iters)
+    say("pga video dft:", rep)
+    assert np.linalg.norm(Xo) > 0
+    parity.check(lt.to_host(X), Xo, 1e-4, label="video dft pga")
