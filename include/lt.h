@@ -58,7 +58,7 @@ extern "C" {
 typedef enum {
   LT_DCT = 0,       /* orthonormal DCT-II C_n (Section 2; the transform of TNN-PGA-C) */
   LT_DFT = 1,       /* Fourier matrix F_n (Section 2); complex transform-domain slices, taken by
-                       lt_svt_prox and lt_complete_pga (FP32 transforms) */
+                       lt_lproduct, lt_svt_prox and lt_complete_pga (FP32 transforms) */
   LT_IDENTITY = 2,  /* M_i = I (mode i not transformed) */
   LT_CUSTOM = 3     /* caller-given invertible M_i (e.g. the c-product W^{-1} C (I+Z)) */
 } lt_mode_kind;

@@ -990,11 +990,13 @@ int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol
   return LT_OK;
 }
 
-// Operations that take Fourier modes: the SVT and the completion, FP32 only.
+// Operations that take Fourier modes: the product, the SVT and the completion,
+// FP32 only.
 int check_dft(lt_handle* h, const Shape& s, int prec, bool op_supports) {
   if (!s.any_dft) return LT_OK;
   if (!op_supports)
-    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes are supported by lt_svt_prox and lt_complete_pga only");
+    return fail(h, LT_ERR_UNSUPPORTED,
+                "Fourier modes are supported by lt_lproduct, lt_svt_prox and lt_complete_pga only");
   if (prec != LT_PREC_F32)
     return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes take the FP32 transform only");
   return LT_OK;
@@ -1443,7 +1445,8 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
   Shape s;
   if (parse(nullptr, a, &s) != LT_OK) return 0;
   if (precision != LT_PREC_F32 && precision != LT_PREC_BF16X3) return 0;
-  if (s.any_dft && (precision != LT_PREC_F32 || (op != LT_OP_SVT && op != LT_OP_PGA))) return 0;
+  if (s.any_dft && (precision != LT_PREC_F32 || (op != LT_OP_SVT && op != LT_OP_PGA && op != LT_OP_LPRODUCT)))
+    return 0;
   Carver c(nullptr);
   switch (op) {
     case LT_OP_SVT: {
@@ -1461,9 +1464,10 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
       if (!b || parse(nullptr, b, &sb) != LT_OK) return 0;
       LprodWs w;
       carve_transform(c, s, precision, &w.t);
-      w.Ah = c.take<float>((size_t)s.nel);
-      w.Bh = c.take<float>((size_t)sb.nel);
-      w.Ch = c.take<float>((size_t)(s.I1 * sb.I2 * s.P));
+      const size_t planes = s.any_dft ? 2 : 1;   // Fourier modes: real and imaginary planes
+      w.Ah = c.take<float>(planes * (size_t)s.nel);
+      w.Bh = c.take<float>(planes * (size_t)sb.nel);
+      w.Ch = c.take<float>(planes * (size_t)(s.I1 * sb.I2 * s.P));
       break;
     }
     case LT_OP_LSVD: {
@@ -1573,7 +1577,7 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
   if ((rc = parse(h, b, &sb))) return rc;
   if (!A || !B || !C) return fail(h, LT_ERR_ARG, "A, B or C is NULL");
   if ((rc = check_prec(h, precision))) return rc;
-  if ((rc = check_dft(h, sa, precision, false))) return rc;
+  if ((rc = check_dft(h, sa, precision, true))) return rc;
   if (sa.order != sb.order || sa.I2 != sb.I1)
     return fail(h, LT_ERR_SHAPE, "inner dimensions differ (%lld vs %lld)", sa.I2, sb.I1);
   for (int i = 2; i < sa.order; ++i)
@@ -1585,23 +1589,25 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
   Carver c(ws);
   LprodWs w;
   carve_transform(c, sa, precision, &w.t);
-  w.Ah = c.take<float>((size_t)sa.nel);
-  w.Bh = c.take<float>((size_t)sb.nel);
-  w.Ch = c.take<float>((size_t)(sa.I1 * sb.I2 * sa.P));
+  const bool dft = sa.any_dft;   // complex transform-domain slices, in real and imaginary planes
+  const size_t planes = dft ? 2 : 1;
+  w.Ah = c.take<float>(planes * (size_t)sa.nel);
+  w.Bh = c.take<float>(planes * (size_t)sb.nel);
+  w.Ch = c.take<float>(planes * (size_t)(sa.I1 * sb.I2 * sa.P));
   if ((rc = build_transform(h, sa, precision, w.t))) return rc;
   const int P = (int)sa.P;
-  if ((rc = gemm(h, gemm_plain(w.t, false, P, sa.N, A, w.Ah), precision, lt::PRO_PLAIN,
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, sa.N, A, w.Ah, dft), precision, lt::PRO_PLAIN,
                  lt::EPI_PLAIN, LT_PROF_FORWARD)))
     return rc;
-  if ((rc = gemm(h, gemm_plain(w.t, false, P, sb.N, B, w.Bh), precision, lt::PRO_PLAIN,
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, sb.N, B, w.Bh, dft), precision, lt::PRO_PLAIN,
                  lt::EPI_PLAIN, LT_PROF_FORWARD)))
     return rc;
   {
     ProfScope ps(h, LT_PROF_OTHER);
     HIP_TRY(h, lt::launch_facewise(w.Ah, w.Bh, w.Ch, (int)sa.I1, (int)sa.I2, (int)sb.I2, P,
-                                   h->stream));
+                                   h->stream, dft));
   }
-  return gemm(h, gemm_plain(w.t, true, P, sa.I1 * sb.I2, w.Ch, C), precision, lt::PRO_PLAIN,
+  return gemm(h, gemm_plain(w.t, true, P, sa.I1 * sb.I2, w.Ch, C, dft), precision, lt::PRO_PLAIN,
               lt::EPI_PLAIN, LT_PROF_INVERSE);
 }
 

@@ -96,8 +96,10 @@ hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner
 hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s);
 
 // C^p = A^p B^p for p < P; A^p: I1 x L (ld I1), B^p: L x I2 (ld L), C^p: I1 x I2.
+// complex_planes: complex slices, each operand a plane of real parts followed
+// by one of imaginary parts (the Fourier transform's output layout).
 hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L,
-                           int I2, int P, hipStream_t s);
+                           int I2, int P, hipStream_t s, bool complex_planes = false);
 
 // count of non-finite values among entries with mask != 0 (mask may be null)
 hipError_t launch_count_nonfinite(const float* X, const uint8_t* mask, long long n,

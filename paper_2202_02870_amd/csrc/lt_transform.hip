@@ -584,6 +584,44 @@ __global__ __launch_bounds__(256) void k_facewise(const float* A, const float* B
   if (i < I1 && j < I2) C[(long long)p * I1 * I2 + (long long)j * I1 + i] = acc;
 }
 
+// The face-wise product of complex slices (Fourier modes), each operand in two
+// planes (real parts of all P slices, then imaginary parts; plane strides
+// P I1 L, P L I2 and P I1 I2): C = (Ar Br - Ai Bi) + i (Ar Bi + Ai Br).
+__global__ __launch_bounds__(256) void k_facewise_cx(const float* A, const float* B, float* C, int I1, int L,
+                                                     int I2, int P) {
+  __shared__ float Ar[16][17], Ai[16][17];
+  __shared__ float Br[16][17], Bi[16][17];
+  const int p = blockIdx.z;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + ti, j = blockIdx.y * 16 + tj;
+  const long long pa = (long long)P * I1 * L, pb = (long long)P * L * I2;
+  const float* Ap = A + (long long)p * I1 * L;
+  const float* Bp = B + (long long)p * L * I2;
+  float cr = 0.f, ci = 0.f;
+  for (int k0 = 0; k0 < L; k0 += 16) {
+    const int ka = k0 + tj, kb = k0 + ti;
+    const bool ina = i < I1 && ka < L, inb = kb < L && j < I2;
+    Ar[ti][tj] = ina ? Ap[(long long)ka * I1 + i] : 0.f;
+    Ai[ti][tj] = ina ? Ap[pa + (long long)ka * I1 + i] : 0.f;
+    Br[ti][tj] = inb ? Bp[(long long)j * L + kb] : 0.f;
+    Bi[ti][tj] = inb ? Bp[pb + (long long)j * L + kb] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      cr = fmaf(Ar[ti][k], Br[k][tj], cr);
+      cr = fmaf(-Ai[ti][k], Bi[k][tj], cr);
+      ci = fmaf(Ar[ti][k], Bi[k][tj], ci);
+      ci = fmaf(Ai[ti][k], Br[k][tj], ci);
+    }
+    __syncthreads();
+  }
+  if (i < I1 && j < I2) {
+    const long long e = (long long)p * I1 * I2 + (long long)j * I1 + i;
+    C[e] = cr;
+    C[(long long)P * I1 * I2 + e] = ci;
+  }
+}
+
 __global__ void k_count_nonfinite(const float* X, const uint8_t* mask, long long n,
                                   unsigned int* count) {
   unsigned int c = 0;
@@ -740,9 +778,10 @@ hipError_t launch_reduce_partials(const double* partials, int n, double* out2, h
 }
 
 hipError_t launch_facewise(const float* A, const float* B, float* C, int I1, int L, int I2,
-                           int P, hipStream_t s) {
+                           int P, hipStream_t s, bool complex_planes) {
   dim3 grid((I1 + 15) / 16, (I2 + 15) / 16, P);
-  hipLaunchKernelGGL(k_facewise, grid, dim3(256), 0, s, A, B, C, I1, L, I2);
+  if (complex_planes) hipLaunchKernelGGL(k_facewise_cx, grid, dim3(256), 0, s, A, B, C, I1, L, I2, P);
+  else hipLaunchKernelGGL(k_facewise, grid, dim3(256), 0, s, A, B, C, I1, L, I2);
   return hipGetLastError();
 }
 

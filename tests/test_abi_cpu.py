@@ -70,8 +70,11 @@ def test_workspace_sizes_host_only():
     for op, prec in (("svt", "bf16x3"), ("lsvd", "f32"), ("truncate", "f32")):
         with pytest.raises(ValueError):      # other operations and BF16 transforms: rejected
             lt.workspace_bytes((8, 8, 4), ("dft",), op, prec)
+    # the product under the DFT: real and imaginary planes of A, B and C
+    n_lp = lt.workspace_bytes((8, 3, 4), ("dft",), "lproduct", shape_b=(3, 5, 4))
+    assert n_lp >= 2 * 4 * 4 * (8 * 3 + 3 * 5 + 8 * 5)
     with pytest.raises(ValueError):
-        lt.workspace_bytes((8, 3, 4), ("dft",), "lproduct", shape_b=(3, 5, 4))
+        lt.workspace_bytes((8, 3, 4), ("dft",), "lproduct", "bf16x3", shape_b=(3, 5, 4))
     with pytest.raises(ValueError):          # zero-sized mode
         lt.workspace_bytes((8, 0, 4), None, "svt")
 

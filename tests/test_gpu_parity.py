@@ -54,6 +54,30 @@ def test_lproduct(lt, sa, sb, kinds, precision, tol):
     assert rel(lt.to_host(C), ref) < tol
 
 
+@pytest.mark.parametrize("sa,sb,kinds", [
+    ((8, 3, 5), (3, 7, 5), ("dft",)),                          # odd P: one self-conjugate slice
+    ((33, 17, 6), (17, 40, 6), ("dft",)),                      # even P: two
+    ((10, 6, 4, 3), (6, 9, 4, 3), ("dft", "dct")),             # mixed transforms
+    ((7, 5, 3, 4), (5, 6, 3, 4), ("dft", "dft")),
+])
+def test_lproduct_fourier(lt, sa, sb, kinds):
+    """A *_L B under the DFT (complex face-wise products of the real and
+    imaginary planes) against the oracle and, along one Fourier mode, against
+    its closed form: circular convolution of the frontal slices (the t-product,
+    C_k = sum_j A_j B_{(k - j) mod P}, the convolution theorem)."""
+    say("lproduct dft", sa, sb, kinds)
+    rng = np.random.default_rng(104)
+    A = rng.standard_normal(sa)
+    B = rng.standard_normal(sb)
+    mats = o.mats_for(sa, list(kinds))
+    C = lt.to_host(lt.lproduct(lt.to_device(A), lt.to_device(B), kinds)).astype(np.float64)
+    assert rel(C, o.lproduct(A, B, mats)) < 2e-6
+    if len(sa) == 3:
+        P = sa[2]
+        conv = np.stack([sum(A[:, :, j] @ B[:, :, (k - j) % P] for j in range(P)) for k in range(P)], axis=2)
+        assert rel(C, conv) < 2e-6
+
+
 @pytest.mark.parametrize("trailing", [(5,), (3, 4)])
 def test_cproduct_block_toeplitz_plus_hankel(lt, trailing):
     """The c-product on the GPU (the transform M_c as a custom matrix per mode):
@@ -461,8 +485,10 @@ def test_pga_degenerate_masks(lt):
 def test_error_paths(lt):
     import torch
     A = lt.to_device(np.ones((8, 8, 4)))
-    with pytest.raises(ValueError):                   # Fourier modes: SVT and completion only
-        lt.lproduct(A, A, ("dft",))
+    with pytest.raises(ValueError):                   # Fourier modes: product, SVT and completion only
+        lt.lsvd(A, ("dft",))
+    with pytest.raises(ValueError):                   # and FP32 transforms only
+        lt.lproduct(A, A, ("dft",), precision="bf16x3")
     with pytest.raises(ValueError):
         lt.svt_prox(A, 0.1, ("dft",), precision="bf16x3")
     M = np.ones((8, 8, 4))
