@@ -20,9 +20,11 @@ kernel's roofline (VALU: FP64 dot products and FP32 rotations, counted as the
 method needs them); the FP64 oracle on this host (all threads and one thread,
 CPU model); and, in the default run, further legs of the metric: the
 256x256x3x100 workload with FP32 and BF16x3 transforms and their errors vs the
-oracle, the 64-problem mix through the batch engine (mixed-precision batched
-form vs the plain FP32 per-request form), a bounded served stream (p50/p99),
-and the whole 200-iteration video job from X = 0.
+oracle, the 1080 x 1920 frames, the video under the DFT (complex Hermitian
+Jacobi, and the real embeddings beside it), the 64-problem mix through the
+batch engine (mixed-precision batched form vs the plain FP32 per-request
+form), a bounded served stream (p50/p99), and the whole 200-iteration video
+job from X = 0.
 """
 import argparse
 import hashlib
@@ -148,7 +150,7 @@ def main():
     ap.add_argument("--frame-height", type=int, default=1080, choices=[1080, 2160],
                     help="frames workload: 1080 x 1920 or 2160 x 3840 frontal slices")
     ap.add_argument("--legs", default="all",
-                    help="video workload: extra legs, comma list of job,large,frames,mix,serve, 'all' or 'none'")
+                    help="video workload: extra legs, comma list of job,large,frames,dft,mix,serve, 'all' or 'none'")
     ap.add_argument("--large-frac", type=float, default=0.1,
                     help="serve workload: share of 512x512x3x64 requests")
     ap.add_argument("--no-lanes", action="store_true",
@@ -200,14 +202,15 @@ def main():
     line = bench_completion(args, torch, lt, wl)
     if args.workload == "video" and args.transform == "dct":
         legs = set() if args.legs == "none" else (
-            {"large", "frames", "mix", "serve", "job"} if args.legs == "all" else set(args.legs.split(",")))
+            {"large", "frames", "dft", "mix", "serve", "job"} if args.legs == "all" else set(args.legs.split(",")))
         extra = {}
-        for name, fn in (("job", leg_job), ("large", leg_large), ("frames", leg_frames), ("mix", leg_mix),
-                         ("serve", leg_serve)):
+        for name, fn in (("job", leg_job), ("large", leg_large), ("frames", leg_frames), ("dft", leg_dft),
+                         ("mix", leg_mix), ("serve", leg_serve)):
             if name in legs:
                 say("leg", name)
                 try:
-                    extra[name] = fn(args, torch, lt, wl)
+                    extra[name] = (fn(args, torch, lt, wl, line["ms_per_step"]) if name == "dft"
+                                   else fn(args, torch, lt, wl))
                 except Exception as e:   # a failed leg is reported; the headline is still printed
                     extra[name] = {"error": "%s: %s" % (type(e).__name__, e)}
                 torch.cuda.empty_cache()
@@ -472,6 +475,37 @@ def leg_frames(args, torch, lt, wl):
             "slice_svt_per_s": round(5 * P / dt, 2), "svt_path": lt.svt_path(p.shape, p.kinds),
             "mean_sweeps": round(rep["total_sweeps"] / rep["total_slices"], 3),
             "kernel_ms": {k: round(v[1], 3) for k, v in prof.items()}}
+
+
+def leg_dft(args, torch, lt, wl, dct_ms=None):
+    """The same video workload under the DFT along both trailing modes (the
+    t-product's TNN-PGA-F): iterations 106-125 timed on the complex Hermitian
+    Jacobi (76 conjugate-pair representatives of 144 x 176), then on the real
+    288 x 352 embeddings (LT_DFT_EMBED=1) for comparison."""
+    p = wl.config1(transform="dft")
+    M = lt.to_device(p.M)
+    mask = lt.to_device(p.mask, dtype=torch.uint8)
+    ws = torch.empty(lt.workspace_bytes(p.shape, p.kinds, "pga"), dtype=torch.uint8, device="cuda")
+    a = argparse.Namespace(**vars(args))
+    a.no_precondition, a.warm_restart, a.pmc_calibrate = False, 0, False
+    out = {"workload": p.name}
+    for key, embed in (("complex", False), ("embedding", True)):
+        if embed:
+            os.environ["LT_DFT_EMBED"] = "1"
+        try:
+            X = lt.fortran_empty(p.shape)
+            dt, rep, prof, window = run_window(lt, M, mask, p, X, ws, a, "f32", 100, 5, 20)
+            out[key] = {"iters_per_s": round(20 / dt, 3), "ms_per_iter": round(dt / 20 * 1e3, 4),
+                        "svt_path": lt.svt_path(p.shape, p.kinds),
+                        "mean_sweeps": round(rep["total_sweeps"] / max(rep["total_slices"], 1), 3),
+                        "jacobi_ms_per_iter": round(prof["jacobi"][1] / max(prof["jacobi"][0], 1), 4)}
+        finally:
+            if embed:
+                del os.environ["LT_DFT_EMBED"]
+    out["timed_iterations"] = list(window)
+    if dct_ms:
+        out["step_over_dct_step"] = round(out["complex"]["ms_per_iter"] / dct_ms, 3)
+    return out
 
 
 def leg_mix(args, torch, lt, wl):

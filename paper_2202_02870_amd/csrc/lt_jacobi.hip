@@ -1700,14 +1700,14 @@ __device__ void rebuild_body(const float* W, float* D, const float* Bk, int r, i
   }
 }
 
-// The same rebuild for working matrices of at most RBS_MMAX rows: the block's
-// 16 columns of W are staged once (all m rows), and the kept columns are taken
-// sixteen at a time (a chunk of Bk staged, Z = Bk^T W for the chunk, then
-// D_W += Bk Z), so a slice of low rank costs two staging passes and four
-// barriers instead of a pass per 32 rows.  LDS: the block, one chunk of Bk and
-// Z, each padded to an odd pitch.
+// The same rebuild for working matrices of at most MMAX rows (256, or 384 for
+// the complex slices' interleaved rows): the block's 16 columns of W are staged
+// once (all m rows), and the kept columns are taken sixteen at a time (a chunk
+// of Bk staged, Z = Bk^T W for the chunk, then D_W += Bk Z), so a slice of low
+// rank costs two staging passes and four barriers instead of a pass per 32
+// rows.  LDS: the block, one chunk of Bk and Z, each padded to an odd pitch.
 constexpr int RBS_MMAX = 256;
-constexpr int RBS_LD = RBS_MMAX + 1;
+constexpr int RBS_MMAX_CX = 384;
 
 // Index (row, c) of entry e = row + m c (or c + 16 row when rows are the long
 // dimension) stepped by 256 entries without a division per step.
@@ -1730,10 +1730,11 @@ struct RbIdx {
   }
 };
 
+template <int MMAX>
 __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, int r, int I1, int I2, int j0,
                                    bool flip) {
-  __shared__ float Xs[RB_TN][RBS_LD];    // W(:, j0 + c) at Xs[c][row]
-  __shared__ float Bs[RB_TN][RBS_LD];    // Bk(:, i0 + i) at Bs[i][row]
+  __shared__ float Xs[RB_TN][MMAX + 1];  // W(:, j0 + c) at Xs[c][row]
+  __shared__ float Bs[RB_TN][MMAX + 1];  // Bk(:, i0 + i) at Bs[i][row]
   __shared__ float Zs[RB_TN][RB_TN + 1]; // Z(i0 + i, c)
   const bool trans = (I1 < I2) != flip;
   const int m = flip ? (I1 < I2 ? I1 : I2) : (I1 < I2 ? I2 : I1);
@@ -1751,9 +1752,9 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
     }
   }
   // output ownership: consecutive lanes store consecutive addresses
-  float acc[(RB_TN * RBS_MMAX + 255) / 256];
+  float acc[(RB_TN * MMAX + 255) / 256];
 #pragma unroll
-  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u) acc[u] = 0.f;
+  for (int u = 0; u < (RB_TN * MMAX + 255) / 256; ++u) acc[u] = 0.f;
   for (int i0 = 0; i0 < r; i0 += RB_TN) {
     const int nc = r - i0 < RB_TN ? r - i0 : RB_TN;
     {
@@ -1779,7 +1780,7 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
     __syncthreads();
     RbIdx x(tid, trans ? RB_TN : m);
 #pragma unroll
-    for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u, x.step()) {
+    for (int u = 0; u < (RB_TN * MMAX + 255) / 256; ++u, x.step()) {
       if (tid + 256 * u < nout) {
         const int row = trans ? x.b : x.a, c = trans ? x.a : x.b;
         float v = acc[u];
@@ -1791,7 +1792,7 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
   }
   RbIdx x(tid, trans ? RB_TN : m);
 #pragma unroll
-  for (int u = 0; u < (RB_TN * RBS_MMAX + 255) / 256; ++u, x.step()) {
+  for (int u = 0; u < (RB_TN * MMAX + 255) / 256; ++u, x.step()) {
     if (tid + 256 * u < nout) {
       const int row = trans ? x.b : x.a, c = trans ? x.a : x.b;
       const int col = j0 + c;
@@ -1803,6 +1804,7 @@ __device__ void rebuild_body_small(const float* W, float* D, const float* Bk, in
   }
 }
 
+template <int MMAX>
 __global__ __launch_bounds__(256) void k_rebuild_small(RebuildArgs a) {
   const int s = blockIdx.y;
   const int n = a.flip ? (a.I1 < a.I2 ? a.I2 : a.I1) : (a.I1 < a.I2 ? a.I1 : a.I2);
@@ -1810,7 +1812,7 @@ __global__ __launch_bounds__(256) void k_rebuild_small(RebuildArgs a) {
   if (j0 >= n) return;
   const long long off = (long long)s * a.slice_stride;
   const float* bk = a.bk + (long long)s * (a.bk_stride ? a.bk_stride : a.slice_stride);
-  rebuild_body_small(a.W + off, a.D + off, bk, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
+  rebuild_body_small<MMAX>(a.W + off, a.D + off, bk, a.rank[s], a.I1, a.I2, j0, a.flip != 0);
 }
 
 template <int RMAX>
@@ -1833,8 +1835,8 @@ __global__ __launch_bounds__(256) void k_rebuild_tiles(ProbDev* const* probs, co
   const long long off = (long long)t.slice * pd->N;
   const int m = pd->precond ? (pd->I1 < pd->I2 ? pd->I1 : pd->I2) : (pd->I1 < pd->I2 ? pd->I2 : pd->I1);
   if (m <= RBS_MMAX)
-    rebuild_body_small(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
-                       pd->precond != 0);
+    rebuild_body_small<RBS_MMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2,
+                                 t.j0, pd->precond != 0);
   else
     rebuild_body<RMAX>(pd->Gh + off, pd->Gh + off, pd->Bk + off, pd->rank[t.slice], pd->I1, pd->I2, t.j0,
                        pd->precond != 0, rcap);
@@ -2721,7 +2723,11 @@ hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s) {
   dim3 grid((n + RB_TN - 1) / RB_TN, a.nslices);
   const int m = a.flip ? (a.I1 < a.I2 ? a.I1 : a.I2) : (a.I1 < a.I2 ? a.I2 : a.I1);
   if (m <= RBS_MMAX) {
-    hipLaunchKernelGGL(k_rebuild_small, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_rebuild_small<RBS_MMAX>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (m <= RBS_MMAX_CX) {   // e.g. the complex slices' interleaved rows
+    hipLaunchKernelGGL(k_rebuild_small<RBS_MMAX_CX>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   RebuildArgs b = a;
