@@ -144,14 +144,18 @@ typedef struct {
  * Larger slices are LT_ERR_SHAPE.  lt_lsvd runs the register kernel only.
  * Fourier slices (complex, one per conjugate pair, Section 2's t-SVD of the
  * DFT) take
- *   complex (LT_SVT_COMPLEX, alone): a one-sided Jacobi with Hermitian rotations
- *                    (the pair's a^H b and the angle in FP64), register-resident,
- *                    on the m x n complex slice held as 2m interleaved real
- *                    rows (ceil(n/2) G <= 768 with G = 16 or 8 lanes per pair,
- *                    at most 48 rows per lane, its exchange buffer within the
- *                    LDS: up to n <= 96, m <= 384 at G = 16 and n, m <= 192 at
- *                    G = 8, e.g. the 144 x 176 video slices), not
- *                    preconditioned;
+ *   complex (LT_SVT_COMPLEX): a one-sided Jacobi with Hermitian rotations (the
+ *                    pair's a^H b and the angle in FP64), register-resident, on
+ *                    complex columns held as interleaved (Re, Im) real rows:
+ *                    with LT_SVT_PRECOND also set (preconditioning requested,
+ *                    2 <= n, 2n <= LT_PRECOND_MAX_N) on the n x n complex
+ *                    Cholesky-QR factor (2n rows), taken from the real Cholesky
+ *                    factor of the real form [w_1, i w_1, ...] of the slice;
+ *                    otherwise on the m x n slice (2m rows).  It needs
+ *                    ceil(n/2) G <= 768 with G = 16 or 8 lanes per pair, at
+ *                    most 48 rows per lane and its exchange buffer within the
+ *                    LDS (e.g. the 144 x 176 video slices: G = 8, 36 rows per
+ *                    lane on the factor, 44 on the slice);
  *   otherwise the kernels above on the real embedding [[X, -Y], [Y, X]]
  *                    (2 I1 x 2 I2; also with LT_DFT_EMBED=1 in the
  *                    environment).
@@ -160,7 +164,8 @@ typedef struct {
 #define LT_SVT_PRECOND 1   /* bit */
 #define LT_SVT_BLOCKED 2   /* bit */
 #define LT_SVT_WIDE 4      /* bit (with LT_SVT_BLOCKED): the wide blocked Jacobi, see above */
-#define LT_SVT_COMPLEX 8   /* the complex Hermitian Jacobi of Fourier slices, see above */
+#define LT_SVT_COMPLEX 8   /* the complex Hermitian Jacobi of Fourier slices (with LT_SVT_PRECOND: on the
+                              complex Cholesky-QR factor), see above */
 
 /* Parameters of Alg. 5 (values used in the paper's Section 5: nu = 0.9,
  * mu0 = nu ||M||_F, tol = 1e-4, itermax 100). */

@@ -886,14 +886,40 @@ SvtCore core_of(const SvtWs& w) {
   return c;
 }
 
+// Preconditioning of the complex path: Cholesky-QR of the complex slice W = QR
+// through its real form T = [w_1, i w_1, w_2, i w_2, ...] (interleaved rows):
+// T^T T is the real form of W^H W, and its real Cholesky factor, unique with a
+// positive diagonal, is the real form of the complex one (L = R^H lower), so
+// the even columns of the real factor are L's columns.  The complex Jacobi then
+// runs on L (2 n interleaved rows), whose kept columns are the scaled right
+// singular vectors B: D = (W B) B^H, formed as (T B') B'^T with B' = [b, i b],
+// of whose columns the even ones are D's.  It applies when requested for
+// 2 <= n with 2 n <= LT_PRECOND_MAX_N, using the Gram blocks carve_svt_core
+// gives the embeddings when their own plan preconditions.
+bool dft_complex_precond(const Shape& s, bool precond_req, int max_lds, lt::JacobiConfig* cc) {
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  if (!precond_req || n < 2 || 2 * n > LT_PRECOND_MAX_N) return false;
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  SvtPlan pe;
+  if (!svt_plan(embed_shape(s, (int)rep.size()), true, &pe) || !pe.precond) return false;
+  return lt::jacobi_cx_config(2 * (int)n, (int)n, max_lds, cc) == 0;
+}
+
 // Fourier slices take the complex Hermitian Jacobi when its register-resident
-// kernel holds the representative's working matrix (2 max(I1, I2) interleaved
-// rows, min(I1, I2) columns); otherwise, or with LT_DFT_EMBED=1 in the
-// environment, the real embedding.  The complex path does not precondition.
-bool dft_complex(const Shape& s, int max_lds, lt::JacobiConfig* cc) {
+// kernel holds the Jacobi's working matrix: the complex Cholesky factor (2 n
+// interleaved rows, preconditioned, above) or else the representative itself
+// (2 max(I1, I2) rows by min(I1, I2) columns).  Otherwise, or with
+// LT_DFT_EMBED=1 in the environment, the real embedding.  *pc: preconditioned.
+bool dft_complex(const Shape& s, bool precond_req, int max_lds, lt::JacobiConfig* cc, bool* pc) {
+  *pc = false;
   if (!s.any_dft) return false;
   const char* env = getenv("LT_DFT_EMBED");
   if (env && atoi(env) == 1) return false;
+  if (dft_complex_precond(s, precond_req, max_lds, cc)) {
+    *pc = true;
+    return true;
+  }
   const long long m = s.I1 > s.I2 ? s.I1 : s.I2, n = s.I1 > s.I2 ? s.I2 : s.I1;
   if (m > 4096) return false;
   return lt::jacobi_cx_config(2 * (int)m, (int)n, max_lds, cc) == 0;
@@ -904,23 +930,47 @@ bool dft_complex(const Shape& s, int max_lds, lt::JacobiConfig* cc) {
 // with its product by i: up to 2 n columns, 4 N floats per representative in
 // the embedding's Bk), the real rebuild over the interleaved rows in place, and
 // the results back to the planes.
-int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiConfig& cc, double tau, double tol,
-               int max_sweeps, int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total,
+int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiConfig& cc, bool pc, double tau,
+               double tol, int max_sweeps, int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total,
                unsigned long long* rot_total, unsigned int* hits) {
   const DftWs& d = w.dft;
   const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
   const long long N = s.N;
   float* Re = w.Gh;
   float* Im = w.Gh + s.nel;
+  if (pc && !d.inner.C) return fail(h, LT_ERR_WORKSPACE, "no Gram blocks for the complex preconditioner");
   {
     ProfScope ps(h, LT_PROF_OTHER);
-    HIP_TRY(h, lt::launch_dft_stack(Re, Im, d.rep, d.npairs, (int)s.I1, (int)s.I2, d.E, h->stream));
+    HIP_TRY(h, lt::launch_dft_stack(Re, Im, d.rep, d.npairs, (int)s.I1, (int)s.I2, d.E, h->stream, pc));
   }
   lt::JacobiArgs a{};
-  a.src = d.E;
-  a.slice_stride = 2 * N;
-  a.I1 = 2 * m;
-  a.I2 = n;
+  if (pc) {
+    // T (2m x 2n, 4N floats per representative): real Gram and Cholesky, then
+    // L's columns (the even ones of the real factor, FP32 over the first half
+    // of each FP64 block) into the block's second half
+    const int n2 = 2 * n;
+    const long long cst = (long long)n2 * n2;
+    lt::GramArgs g{d.E, 4 * N, d.inner.C, cst, 2 * m, n2, d.npairs};
+    ProfScope ps(h, LT_PROF_PRECOND);
+    if (n2 <= lt::kGramCholMaxN) {
+      HIP_TRY(h, lt::launch_gram_chol(g, h->stream));
+    } else {
+      HIP_TRY(h, lt::launch_gram(g, h->stream));
+      lt::CholArgs c{d.inner.C, cst, n2, d.npairs};
+      HIP_TRY(h, lt::launch_chol(c, h->stream));
+    }
+    float* L = reinterpret_cast<float*>(d.inner.C);
+    HIP_TRY(h, lt::launch_even_columns(L, 2 * cst, L + cst, 2 * cst, n2, n, d.npairs, h->stream));
+    a.src = L + cst;
+    a.slice_stride = 2 * cst;
+    a.I1 = n2;
+    a.I2 = n;
+  } else {
+    a.src = d.E;
+    a.slice_stride = 2 * N;
+    a.I1 = 2 * m;
+    a.I2 = n;
+  }
   a.nslices = d.npairs;
   a.tau = tau;
   a.tol = fabs(tol);
@@ -943,20 +993,20 @@ int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiCon
   r.D = d.E;
   r.bk = d.inner.Bk;
   r.rank = d.inner.rank;
-  r.slice_stride = 2 * N;
+  r.slice_stride = pc ? 4 * N : 2 * N;
   r.bk_stride = 4 * N;
   r.kmax = 2 * n;
   r.I1 = 2 * m;
-  r.I2 = n;
+  r.I2 = pc ? 2 * n : n;
   r.nslices = d.npairs;
-  r.flip = 0;
+  r.flip = pc ? 1 : 0;
   {
     ProfScope ps(h, LT_PROF_REBUILD);
     HIP_TRY(h, lt::launch_rebuild(r, h->stream));
   }
   ProfScope ps(h, LT_PROF_OTHER);
   HIP_TRY(h, lt::launch_dft_unstack(d.E, d.rep, d.partner, d.npairs, (int)s.I1, (int)s.I2, Re, Im, d.inner.rank,
-                                    rank, d.inner.sweeps, sweeps, d.inner.nuc, w.nuc, h->stream));
+                                    rank, d.inner.sweeps, sweeps, d.inner.nuc, w.nuc, h->stream, pc));
   return LT_OK;
 }
 
@@ -970,8 +1020,9 @@ int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol
     return run_jacobi_svt(h, s, w.Gh, w.Gh, core_of(w), tau, tol, max_sweeps, rank, sweeps, sweep_total,
                           rot_total, hits, precond, warm);
   lt::JacobiConfig cc;
-  if (dft_complex(s, h->max_lds, &cc))
-    return run_cx_svt(h, s, w, cc, tau, tol, max_sweeps, rank, sweeps, sweep_total, rot_total, hits);
+  bool pc;
+  if (dft_complex(s, precond, h->max_lds, &cc, &pc))
+    return run_cx_svt(h, s, w, cc, pc, tau, tol, max_sweeps, rank, sweeps, sweep_total, rot_total, hits);
   const DftWs& d = w.dft;
   const Shape se = embed_shape(s, d.npairs);
   float* Re = w.Gh;
@@ -1023,7 +1074,8 @@ double nuclear_alpha(const Shape& s) {
 int check_svt_shape(lt_handle* h, const Shape& s0, bool precond) {
   Shape s = s0;
   lt::JacobiConfig cc;
-  if (dft_complex(s0, h->max_lds, &cc)) return LT_OK;
+  bool pc;
+  if (dft_complex(s0, precond, h->max_lds, &cc, &pc)) return LT_OK;
   if (s0.any_dft) {
     std::vector<int> rep, partner;
     dft_pairs(s0, &rep, &partner);
@@ -1496,7 +1548,9 @@ int lt_svt_path(const lt_desc* a, const lt_svd_opts* opts) {
   int rc = parse(nullptr, a, &s);
   if (rc) return rc;
   lt::JacobiConfig cc;
-  if (dft_complex(s, kBlkLdsBudget, &cc)) return LT_SVT_COMPLEX;
+  bool pc;
+  if (dft_complex(s, precond_requested(opts), kBlkLdsBudget, &cc, &pc))
+    return LT_SVT_COMPLEX | (pc ? LT_SVT_PRECOND : 0);
   if (s.any_dft) {   // the Jacobi runs on the real embeddings of the complex slices
     std::vector<int> rep, partner;
     dft_pairs(s, &rep, &partner);

@@ -84,14 +84,19 @@ hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner
                               const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
                               hipStream_t s);
 // The same slices <-> complex working matrices of the Hermitian Jacobi (2 max(I1,
-// I2) interleaved rows by min(I1, I2) columns, 2 I1 I2 floats each), and the
-// results back with the partners' conjugates.
+// I2) interleaved rows by min(I1, I2) columns, 2 I1 I2 floats each; twin: each
+// column followed by its product by i, 4 I1 I2 floats), and the results back
+// with the partners' conjugates (twin: read from the even columns).
 hipError_t launch_dft_stack(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
-                            float* W, hipStream_t s);
+                            float* W, hipStream_t s, bool twin = false);
 hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner, int npairs, int I1, int I2,
                               float* Re, float* Im, const int32_t* rankE, int32_t* rank,
                               const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
-                              hipStream_t s);
+                              hipStream_t s, bool twin = false);
+// Columns 0, 2, ..., 2 (ncols - 1) of rows-row column-major matrices (src_stride
+// floats apart) into contiguous rows x ncols ones (dst_stride apart).
+hipError_t launch_even_columns(const float* src, long long src_stride, float* dst, long long dst_stride, int rows,
+                               int ncols, int nslices, hipStream_t s);
 // out[0] = scale * (v[0] + ... + v[n-1]) in a fixed summation order (one workgroup).
 hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s);
 

@@ -439,11 +439,14 @@ __global__ void k_dft_extract(const float* __restrict__ E, const int* rep, const
 // column-major, 2N floats per representative.  I1 >= I2: the slice's columns
 // (entry (i, j) at row pair i of column j); I1 < I2: its rows (entry (i, j) at
 // row pair j of column i, the plain transpose, whose SVT is the transpose of
-// the slice's).  A 32 x 32 tile per workgroup goes through LDS so that reads
-// and writes are both coalesced.
+// the slice's).  twin: 2n columns, 4N floats per representative, column 2j
+// the working column j and column 2j + 1 its product by i ((Re, Im) ->
+// (-Im, Re)): the real form of the complex matrix, whose real Gram matrix and
+// Cholesky factor are the real forms of the complex ones.  A 32 x 32 tile per
+// workgroup goes through LDS so that reads and writes are both coalesced.
 __global__ __launch_bounds__(256) void k_dft_stack(const float* __restrict__ Re, const float* __restrict__ Im,
                                                    const int* rep, int I1, int I2, long long N,
-                                                   float* __restrict__ W) {
+                                                   float* __restrict__ W, int twin) {
   __shared__ float2 T[32][33];   // T[j - j0][i - i0]
   const int t = blockIdx.y;
   const int ti = (I1 + 31) / 32;
@@ -458,18 +461,42 @@ __global__ __launch_bounds__(256) void k_dft_stack(const float* __restrict__ Re,
     }
   }
   __syncthreads();
-  float2* Wt = reinterpret_cast<float2*>(W + (long long)t * 2 * N);
+  float2* Wt = reinterpret_cast<float2*>(W + (long long)t * (twin ? 4 : 2) * N);
+  const int m = I1 >= I2 ? I1 : I2;
+  const long long cp = twin ? 2LL * m : m;   // float2 entries between working columns
   if (I1 >= I2) {
     for (int jj = ty; jj < 32; jj += 8) {
       const int i = i0 + tx, j = j0 + jj;
-      if (i < I1 && j < I2) Wt[(long long)j * I1 + i] = T[jj][tx];
+      if (i < I1 && j < I2) {
+        const float2 v = T[jj][tx];
+        Wt[(long long)j * cp + i] = v;
+        if (twin) Wt[(long long)j * cp + m + i] = make_float2(-v.y, v.x);
+      }
     }
   } else {
     for (int ii = ty; ii < 32; ii += 8) {
       const int i = i0 + ii, j = j0 + tx;
-      if (i < I1 && j < I2) Wt[(long long)i * I2 + j] = T[tx][ii];
+      if (i < I1 && j < I2) {
+        const float2 v = T[tx][ii];
+        Wt[(long long)i * cp + j] = v;
+        if (twin) Wt[(long long)i * cp + m + j] = make_float2(-v.y, v.x);
+      }
     }
   }
+}
+
+// Columns 0, 2, 4, ... of per-slice column-major rows x (2 ncols) matrices
+// (leading dimension rows, src_stride floats apart) into rows x ncols ones
+// (dst_stride floats apart): the complex Cholesky factor out of the real
+// factor of the twinned matrix.
+__global__ __launch_bounds__(256) void k_even_columns(const float* __restrict__ src, long long src_stride,
+                                                      float* __restrict__ dst, long long dst_stride, int rows,
+                                                      int ncols) {
+  const int t = blockIdx.y;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)rows * ncols) return;
+  const int j = (int)(e / rows), r = (int)(e - (long long)j * rows);
+  dst[t * dst_stride + e] = src[t * src_stride + (long long)(2 * j) * rows + r];
 }
 
 // The complex SVT results back to the planes: slice rep[t] from its working
@@ -480,7 +507,7 @@ __global__ __launch_bounds__(256) void k_dft_unstack(const float* __restrict__ W
                                                      const int* partner, int I1, int I2, long long N,
                                                      float* __restrict__ Re, float* __restrict__ Im,
                                                      const int32_t* rankE, int32_t* rank, const int32_t* sweepsE,
-                                                     int32_t* sweeps, const double* nucE, double* nuc) {
+                                                     int32_t* sweeps, const double* nucE, double* nuc, int twin) {
   __shared__ float2 T[32][33];
   const int t = blockIdx.y;
   const int p = rep[t], q = partner[t];
@@ -492,16 +519,17 @@ __global__ __launch_bounds__(256) void k_dft_unstack(const float* __restrict__ W
   const int ti = (I1 + 31) / 32;
   const int i0 = 32 * (int)(blockIdx.x % ti), j0 = 32 * (int)(blockIdx.x / ti);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const float2* Wt = reinterpret_cast<const float2*>(W + (long long)t * 2 * N);
+  const float2* Wt = reinterpret_cast<const float2*>(W + (long long)t * (twin ? 4 : 2) * N);
+  const long long cp = twin ? 2LL * (I1 >= I2 ? I1 : I2) : (I1 >= I2 ? I1 : I2);
   if (I1 >= I2) {
     for (int jj = ty; jj < 32; jj += 8) {
       const int i = i0 + tx, j = j0 + jj;
-      if (i < I1 && j < I2) T[jj][tx] = Wt[(long long)j * I1 + i];
+      if (i < I1 && j < I2) T[jj][tx] = Wt[(long long)j * cp + i];
     }
   } else {
     for (int ii = ty; ii < 32; ii += 8) {
       const int i = i0 + ii, j = j0 + tx;
-      if (i < I1 && j < I2) T[tx][ii] = Wt[(long long)i * I2 + j];
+      if (i < I1 && j < I2) T[tx][ii] = Wt[(long long)i * cp + j];
     }
   }
   __syncthreads();
@@ -747,22 +775,32 @@ hipError_t launch_dft_extract(const float* E, const int* rep, const int* partner
 }
 
 hipError_t launch_dft_stack(const float* Re, const float* Im, const int* rep, int npairs, int I1, int I2,
-                            float* W, hipStream_t s) {
+                            float* W, hipStream_t s, bool twin) {
   if (npairs <= 0) return hipSuccess;
   const long long tiles = (long long)((I1 + 31) / 32) * ((I2 + 31) / 32);
   hipLaunchKernelGGL(k_dft_stack, dim3((unsigned)tiles, (unsigned)npairs), dim3(256), 0, s, Re, Im, rep, I1, I2,
-                     (long long)I1 * I2, W);
+                     (long long)I1 * I2, W, twin ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner, int npairs, int I1, int I2,
                               float* Re, float* Im, const int32_t* rankE, int32_t* rank,
                               const int32_t* sweepsE, int32_t* sweeps, const double* nucE, double* nuc,
-                              hipStream_t s) {
+                              hipStream_t s, bool twin) {
   if (npairs <= 0) return hipSuccess;
   const long long tiles = (long long)((I1 + 31) / 32) * ((I2 + 31) / 32);
   hipLaunchKernelGGL(k_dft_unstack, dim3((unsigned)tiles, (unsigned)npairs), dim3(256), 0, s, W, rep, partner, I1,
-                     I2, (long long)I1 * I2, Re, Im, rankE, rank, sweepsE, sweeps, nuc ? nucE : nullptr, nuc);
+                     I2, (long long)I1 * I2, Re, Im, rankE, rank, sweepsE, sweeps, nuc ? nucE : nullptr, nuc,
+                     twin ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_even_columns(const float* src, long long src_stride, float* dst, long long dst_stride, int rows,
+                               int ncols, int nslices, hipStream_t s) {
+  if (nslices <= 0 || rows <= 0 || ncols <= 0) return hipSuccess;
+  const long long e = (long long)rows * ncols;
+  hipLaunchKernelGGL(k_even_columns, dim3((unsigned)((e + 255) / 256), (unsigned)nslices), dim3(256), 0, s, src,
+                     src_stride, dst, dst_stride, rows, ncols);
   return hipGetLastError();
 }
 

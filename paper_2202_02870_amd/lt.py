@@ -65,7 +65,7 @@ class ProblemC(ctypes.Structure):
 PROF_CLASSES = ("forward", "jacobi", "rebuild", "inverse", "other", "precond")
 SVT_PATHS = ("register", "precond", "blocked", "precond+blocked",   # LT_SVT_PRECOND / LT_SVT_BLOCKED bits
              None, None, "blocked+wide", "precond+blocked+wide",    # ... and LT_SVT_WIDE
-             "complex")                                             # LT_SVT_COMPLEX (Fourier slices)
+             "complex", "precond+complex")                          # LT_SVT_COMPLEX (Fourier slices)
 
 
 class Profile(ctypes.Structure):
@@ -283,9 +283,10 @@ def svt_path(shape, kinds=None, precondition=True):
     on the slice), "precond" (on its Cholesky-QR factor), "blocked" (blocked
     Jacobi on the slice), "precond+blocked" (blocked, on the factor), and
     "blocked+wide" / "precond+blocked+wide" (the wide blocked Jacobi, one
-    workgroup per block pair), "complex" (Fourier slices: the Hermitian Jacobi
-    on the complex slices; otherwise the real embeddings take one of the
-    others); host only, LtError if no kernel takes the shape."""
+    workgroup per block pair), "complex" / "precond+complex" (Fourier slices:
+    the Hermitian Jacobi on the complex slices or on their complex Cholesky-QR
+    factors; otherwise the real embeddings take one of the others); host only,
+    LtError if no kernel takes the shape."""
     d = make_desc(tuple(shape), kinds)
     o = svd_opts(precondition=precondition)
     st = _lib.lt_svt_path(ctypes.byref(d), ctypes.byref(o))

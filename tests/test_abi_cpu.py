@@ -116,17 +116,24 @@ def test_svt_path_by_shape():
         del os.environ["LT_WIDE"]
     assert lt.svt_path((3000, 16)) == "precond"                     # any column length on the factor
     assert lt.svt_path((1, 7)) == "register"                        # n = 1: nothing to factor
-    # Fourier modes: the complex Hermitian Jacobi on the I1 x I2 complex slices
-    # (2 max(I1, I2) interleaved real rows) while its register kernel holds
-    # them, else the real 2 I1 x 2 I2 embeddings (also with LT_DFT_EMBED=1)
-    assert lt.svt_path((100, 80, 4), ("dft",)) == "complex"                 # G = 16, 13 -> 16 rows per lane
-    assert lt.svt_path((100, 80, 4), ("dft",), precondition=False) == "complex"
-    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "complex"      # G = 8, 44 rows per lane
-    assert lt.svt_path((190, 192, 2), ("dft",)) == "complex"                # G = 8, 48 rows, one LDS buffer
-    assert lt.svt_path((12, 380, 2), ("dft",)) == "complex"                 # G = 16, 760 -> 48 rows per lane
-    assert lt.svt_path((12, 400, 2), ("dft",)) == "precond"                 # 800 rows: the 24 x 800 embedding
-    assert lt.svt_path((300, 100, 2), ("dft",)) == "precond"                # 600 rows: the 600 x 200 embedding
+    # Fourier modes: the complex Hermitian Jacobi on the complex Cholesky-QR
+    # factors (2 min(I1, I2) interleaved real rows) or, unpreconditioned, on the
+    # complex slices (2 max(I1, I2) rows) while its register kernel holds them,
+    # else the real 2 I1 x 2 I2 embeddings (also with LT_DFT_EMBED=1)
+    assert lt.svt_path((100, 80, 4), ("dft",)) == "precond+complex"         # G = 16, 160 -> 16 rows per lane
+    assert lt.svt_path((100, 80, 4), ("dft",), precondition=False) == "complex"   # G = 16, 200 -> 16 rows
+    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft")) == "precond+complex"    # G = 8, 36 rows per lane
+    assert lt.svt_path((144, 176, 3, 50), ("dft", "dft"), precondition=False) == "complex"   # 44 rows
+    assert lt.svt_path((190, 192, 2), ("dft",)) == "precond+complex"        # G = 8, 48 rows, one LDS buffer
+    assert lt.svt_path((190, 192, 2), ("dft",), precondition=False) == "complex"
+    assert lt.svt_path((12, 380, 2), ("dft",), precondition=False) == "complex"   # G = 16, 760 -> 48 rows
+    assert lt.svt_path((12, 400, 2), ("dft",)) == "precond+complex"         # the factor: 24 rows
+    assert lt.svt_path((12, 400, 2), ("dft",), precondition=False) == "register"  # 800 rows: the 24 x 800 embedding
+    assert lt.svt_path((300, 100, 2), ("dft",), precondition=False) == "blocked+wide"   # the 600 x 200 embedding
+    assert lt.svt_path((300, 100, 2), ("dft",)) == "precond+complex"
     assert lt.svt_path((192, 192, 2), ("dft",)) == "precond+blocked+wide"   # 96 pairs x 48 rows: beyond the LDS
+    assert lt.svt_path((8, 6, 5), ("dft",)) == "precond+complex"
+    assert lt.svt_path((8, 1, 5), ("dft",)) == "complex"                    # n = 1: nothing to factor
     os.environ["LT_DFT_EMBED"] = "1"
     try:
         assert lt.svt_path((100, 80, 4), ("dft",)) == "precond"                 # 200 x 160

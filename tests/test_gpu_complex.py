@@ -1,8 +1,9 @@
 """GPU tests of the complex Hermitian Jacobi that thresholds Fourier slices
-(one per conjugate pair, Section 2's t-SVD under the DFT): against the FP64
-oracle's complex SVT slice by slice, against the real-embedding path it
-replaces, and inside the completion.  The cases reach every instantiated
-(lanes per pair, rows per lane) and both orientations of the slice."""
+(one per conjugate pair, Section 2's t-SVD under the DFT), on the complex
+slices and on their complex Cholesky-QR factors: against the FP64 oracle's
+complex SVT slice by slice, against the real-embedding path it replaces, and
+inside the completion.  The cases reach every instantiated (lanes per pair,
+rows per lane) and both orientations of the slice."""
 import os
 
 import numpy as np
@@ -37,8 +38,10 @@ def _low_rank_plus_noise(shape, kinds, seed):
     return A + 0.05 * rng.standard_normal(shape), mats
 
 
-# (shape, kinds, G, rows per lane) of the complex working matrix: 2 max(I1, I2)
-# interleaved rows by min(I1, I2) columns
+# (shape, kinds): G and rows per lane of the complex working matrix without
+# preconditioning (2 max(I1, I2) interleaved rows by min(I1, I2) columns); on
+# the factor (2 min(I1, I2) rows) they reach G 8 with 8, 16, 32, 48 rows and
+# G 16 with 16
 CX_CASES = [
     ((8, 6, 5), ("dft",)),              # G 8, R 8; P = 5: one self-conjugate slice
     ((5, 9, 6), ("dft",)),              # transposed; P = 6: two self-conjugate slices
@@ -56,13 +59,14 @@ CX_CASES = [
 ]
 
 
+@pytest.mark.parametrize("precondition", [False, True])
 @pytest.mark.parametrize("shape,kinds", CX_CASES)
-def test_svt_complex_matches_oracle(lt, shape, kinds):
-    assert lt.svt_path(shape, kinds) == "complex"
+def test_svt_complex_matches_oracle(lt, shape, kinds, precondition):
+    assert lt.svt_path(shape, kinds, precondition=precondition) == ("precond+complex" if precondition else "complex")
     A, mats = _low_rank_plus_noise(shape, kinds, sum(shape))
     s = o.singular_values(A, mats)
     for tau in (0.0, float(np.quantile(s, 0.5)), float(s.max()) * 1.01):
-        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds)
+        D, rank, sweeps = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=precondition)
         ref = o.svt(A, tau, mats)
         rk, ref_rk = lt.to_host(rank), np.asarray(o.svt_ranks(A, tau, mats))
         say("complex svt", shape, kinds, "tau", tau, "ranks", rk[:6], "sweeps", lt.to_host(sweeps)[:6])
@@ -72,6 +76,30 @@ def test_svt_complex_matches_oracle(lt, shape, kinds):
             assert float(np.abs(lt.to_host(D)).max()) == 0.0
         near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
         assert np.all(np.abs(rk - ref_rk) <= near)
+
+
+@pytest.mark.parametrize("shape,r", [((40, 30, 5), 7), ((20, 64, 4), 5), ((144, 176, 3, 2), 10)])
+def test_svt_complex_precond_rank_deficient(lt, shape, r):
+    """Slices of exact rank r < n: singular Gram matrices in the complex
+    preconditioner (its zeroed pivots), at tau = 0 (D = A) and at a threshold in
+    the spectrum, against the oracle, with the exact ranks."""
+    kinds = ("dft",) * (len(shape) - 2)
+    rng = np.random.default_rng(sum(shape) + r)
+    mats = o.mats_for(shape, list(kinds))
+    A = o.lproduct(rng.standard_normal((shape[0], r) + shape[2:]),
+                   rng.standard_normal((r, shape[1]) + shape[2:]), mats).real
+    assert lt.svt_path(shape, kinds) == "precond+complex"
+    s = o.singular_values(A, mats)
+    for tau in (0.0, float(np.quantile(s[:, :r], 0.5))):
+        D, rank, _ = lt.svt_prox(lt.to_device(A), tau, kinds)
+        ref = o.svt(A, tau, mats)
+        say("rank-deficient complex", shape, r, "tau", tau, "ranks", lt.to_host(rank)[:6])
+        parity.check(lt.to_host(D), ref, 2e-5, label="rank %d tau %.3g" % (r, tau))
+        ref_rk = np.asarray(o.svt_ranks(A, tau, mats))
+        near = (np.abs(s - tau) < 1e-4 * s.max()).sum(axis=1)
+        assert np.all(np.abs(lt.to_host(rank) - ref_rk) <= near)
+        if tau == 0.0:
+            assert np.all(lt.to_host(rank) == r)
 
 
 def test_svt_complex_video_against_embedding(lt):
@@ -85,18 +113,22 @@ def test_svt_complex_video_against_embedding(lt):
     tau = float(np.quantile(s, 0.9))
     ref = o.svt(A, tau, mats)
     Dc, rc, sc = lt.svt_prox(lt.to_device(A), tau, kinds)
+    Du, ru, su = lt.svt_prox(lt.to_device(A), tau, kinds, precondition=False)
     os.environ["LT_DFT_EMBED"] = "1"
     try:
         assert lt.svt_path(shape, kinds) != "complex"
         De, re_, se = lt.svt_prox(lt.to_device(A), tau, kinds)
     finally:
         del os.environ["LT_DFT_EMBED"]
-    say("video dft: complex sweeps", lt.to_host(sc).mean(), "embedding sweeps", lt.to_host(se).mean())
-    parity.check(lt.to_host(Dc), ref, 2e-5, label="complex")
+    say("video dft: complex sweeps", lt.to_host(sc).mean(), "(on the slices", lt.to_host(su).mean(), ")",
+        "embedding sweeps", lt.to_host(se).mean())
+    parity.check(lt.to_host(Dc), ref, 2e-5, label="complex, preconditioned")
+    parity.check(lt.to_host(Du), ref, 2e-5, label="complex")
     parity.check(lt.to_host(De), ref, 2e-5, label="embedding")
     near = (np.abs(s - tau) < 1e-4 * s.max()).sum(axis=1)
     assert np.all(np.abs(lt.to_host(rc) - np.asarray(o.svt_ranks(A, tau, mats))) <= near)
     assert np.all(np.abs(lt.to_host(rc) - lt.to_host(re_)) <= near)
+    assert np.all(np.abs(lt.to_host(ru) - lt.to_host(re_)) <= near)
     # a threshold in the gap between the rank-36 signal and the noise
     tau = float(0.5 * (s[:, 35].min() + s[:, 36].max()))
     assert s[:, 35].min() > 1.2 * s[:, 36].max()
@@ -111,7 +143,7 @@ def test_pga_video_dft(lt):
     default schedule, against the oracle."""
     import torch
     p = wl.make_problem((144, 176, 3, 50), 10, 0.3, seed=5, kinds=("dft", "dft"))
-    assert lt.svt_path(p.shape, p.kinds) == "complex"
+    assert lt.svt_path(p.shape, p.kinds) == "precond+complex"
     s = wl.pga_schedule_params(p.M, p.mask)
     iters = 10
     params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
