@@ -345,6 +345,8 @@ struct DftWs {
   int32_t* partner = nullptr;
   int npairs = 0;
   SvtCore inner;              // SVT buffers of the embeddings
+  float* Lc = nullptr;        // complex path: Cholesky factors (2n interleaved rows x n), npairs of them
+  double* thr = nullptr;      // complex path: the multi-launch Cholesky's per-slice pivot floor
 };
 
 struct SvtWs {
@@ -550,6 +552,9 @@ void carve_svt(Carver& c, const Shape& s, int prec, SvtWs* w) {
   const Shape se = embed_shape(s, d.npairs);
   d.E = c.take<float>((size_t)se.nel);
   carve_svt_core(c, se, &d.inner);
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  d.Lc = c.take<float>((size_t)(d.npairs * 2 * n * n));
+  d.thr = c.take<double>((size_t)d.npairs);
 }
 
 // Upload the pair tables of a Fourier workspace (once per call).
@@ -946,23 +951,32 @@ int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiCon
   lt::JacobiArgs a{};
   if (pc) {
     // T (2m x 2n, 4N floats per representative): real Gram and Cholesky, then
-    // L's columns (the even ones of the real factor, FP32 over the first half
-    // of each FP64 block) into the block's second half
+    // L's columns (the even ones of the real factor) into Lc.  Up to 192
+    // columns the one-kernel Cholesky (FP32 factor over the first half of
+    // each FP64 block), beyond it the multi-launch one, which converts the
+    // even columns itself
     const int n2 = 2 * n;
     const long long cst = (long long)n2 * n2;
+    const long long lcs = (long long)n2 * n;
     lt::GramArgs g{d.E, 4 * N, d.inner.C, cst, 2 * m, n2, d.npairs};
     ProfScope ps(h, LT_PROF_PRECOND);
     if (n2 <= lt::kGramCholMaxN) {
       HIP_TRY(h, lt::launch_gram_chol(g, h->stream));
     } else {
       HIP_TRY(h, lt::launch_gram(g, h->stream));
-      lt::CholArgs c{d.inner.C, cst, n2, d.npairs};
-      HIP_TRY(h, lt::launch_chol(c, h->stream));
     }
-    float* L = reinterpret_cast<float*>(d.inner.C);
-    HIP_TRY(h, lt::launch_even_columns(L, 2 * cst, L + cst, 2 * cst, n2, n, d.npairs, h->stream));
-    a.src = L + cst;
-    a.slice_stride = 2 * cst;
+    if (n2 <= 192) {
+      if (n2 > lt::kGramCholMaxN) {
+        lt::CholArgs c{d.inner.C, cst, n2, d.npairs};
+        HIP_TRY(h, lt::launch_chol(c, h->stream));
+      }
+      HIP_TRY(h, lt::launch_even_columns(reinterpret_cast<const float*>(d.inner.C), 2 * cst, d.Lc, lcs, n2, n,
+                                         d.npairs, h->stream));
+    } else {
+      HIP_TRY(h, lt::launch_chol_big(d.inner.C, cst, n2, d.npairs, d.Lc, lcs, d.thr, h->stream, 2));
+    }
+    a.src = d.Lc;
+    a.slice_stride = lcs;
     a.I1 = n2;
     a.I2 = n;
   } else {

@@ -284,9 +284,10 @@ hipError_t launch_gram_chol(const GramArgs& g, hipStream_t s);
 // Cholesky for any n (multi-launch, many workgroups per slice): C (n x n FP64,
 // lower triangle, c_stride doubles per slice) factored in place, then the FP32
 // factor written to L (n x n per slice, l_stride floats, zero above the
-// diagonal); thr: scratch, one double per slice.
+// diagonal; col_step 2: only the even columns, n x ceil(n/2)); thr: scratch,
+// one double per slice.
 hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, float* L, long long l_stride,
-                           double* thr, hipStream_t s);
+                           double* thr, hipStream_t s, int col_step = 1);
 hipError_t launch_rebuild(const RebuildArgs& a, hipStream_t s);
 
 // lsvd finalisation: sort, normalise, V = W^T U diag(1/sigma), write factors

@@ -846,20 +846,22 @@ __global__ __launch_bounds__(256) void k_cholb_update(double* C, long long c_str
   }
 }
 
-// FP32 factor: L[i + j n] = C(i, j) for i >= j, 0 above the diagonal.
+// FP32 factor: L[i + j n] = C(i, c) with c = j col_step, for i >= c, 0 above
+// the diagonal; j < ncols (col_step 2: the even columns only).
 __global__ __launch_bounds__(256) void k_cholb_fp32(const double* C, long long c_stride, float* L,
-                                                   long long l_stride, int n) {
+                                                   long long l_stride, int n, int ncols, int col_step) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long long)n * n) return;
+  if (e >= (long long)n * ncols) return;
   const int j = (int)(e / n), i = (int)(e - (long long)j * n);
+  const int c = j * col_step;
   const double* Cs = C + (long long)blockIdx.y * c_stride;
-  L[(long long)blockIdx.y * l_stride + e] = i >= j ? (float)Cs[e] : 0.f;
+  L[(long long)blockIdx.y * l_stride + e] = i >= c ? (float)Cs[(long long)c * n + i] : 0.f;
 }
 
 }  // namespace
 
 hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, float* L, long long l_stride,
-                           double* thr, hipStream_t s) {
+                           double* thr, hipStream_t s, int col_step) {
   if (nslices <= 0) return hipSuccess;
   if (n < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cholb_thr, dim3(nslices), dim3(256), 0, s, C, c_stride, n, thr);
@@ -877,9 +879,10 @@ hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, fl
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
-  const long long nn = (long long)n * n;
+  const int ncols = (n + col_step - 1) / col_step;
+  const long long nn = (long long)n * ncols;
   hipLaunchKernelGGL(k_cholb_fp32, dim3((unsigned)((nn + 255) / 256), nslices), dim3(256), 0, s, C, c_stride,
-                     L, l_stride, n);
+                     L, l_stride, n, ncols, col_step);
   return hipGetLastError();
 }
 
