@@ -310,7 +310,7 @@ def bench_completion(args, torch, lt, wl):
     path = lt.svt_path(shape, p.kinds, precondition=not args.no_precondition)
     precond = "precond" in path
     dft = "dft" in p.kinds
-    cx = path == "complex"   # Fourier: complex slices, or else their real embeddings
+    cx = "complex" in path   # Fourier: complex slices (or factors), or else their real embeddings
     jm, jn = (2 * m, 2 * n) if dft and not cx else (m, n)
     warm = lt.pga_warm(shape, p.kinds, precondition=not args.no_precondition, warm_restart=args.warm_restart)
     t_launch = jms / 1e3 / max(jcalls, 1)
@@ -323,8 +323,9 @@ def bench_completion(args, torch, lt, wl):
     rows = jn if precond else jm
     rot_rows = rows + 4 * ((jn + 3) // 4) if warm else rows
     if cx:
-        rows = rot_rows = 2 * m   # interleaved real rows of the complex columns
-        k64, k32 = kernel_flops_complex(m, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
+        cm = n if precond else m   # complex rows of the Jacobi's columns (the n x n factor, or the slice)
+        rows = rot_rows = 2 * cm   # as interleaved real rows
+        k64, k32 = kernel_flops_complex(cm, n, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"])
     else:
         k64, k32 = kernel_flops(rows, jn, rep["total_sweeps"], rep["total_rotations"], rep["total_slices"],
                                 dot32=args.fp32_dots, rot_rows=rot_rows)
