@@ -260,8 +260,12 @@ int lt_lproduct(lt_handle* h, const lt_desc* a, const float* A, const lt_desc* b
  * completion.  transform_domain != 0 returns L(U), L(S), L(V) (the per-slice
  * factors) instead.  sigma (may be NULL): P x n float array of
  * transform-domain singular values, slice-major.  Slices up to
- * min(I1, I2) <= 256 and max(I1, I2) <= 2048 (LT_ERR_SHAPE beyond); real
- * transforms (LT_ERR_UNSUPPORTED for Fourier modes). */
+ * min(I1, I2) <= 256 and max(I1, I2) <= 2048 (LT_ERR_SHAPE beyond).
+ * Fourier modes (Section 2's t-SVD; FP32 transforms): economy factors in the
+ * spatial domain only (LT_ERR_UNSUPPORTED for economy == 0 or
+ * transform_domain != 0), with A = U *_L S *_L V^H (the transpose of the
+ * Fourier L-product conjugates each slice), from the complex Jacobi, so for the
+ * slices it holds (LT_ERR_SHAPE otherwise, see LT_SVT_COMPLEX). */
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
             float* V, float* sigma, int economy, int transform_domain, const lt_svd_opts* opts,
             void* ws, size_t ws_bytes);

@@ -663,6 +663,45 @@ void carve_lsvd(Carver& c, const Shape& s, int prec, LsvdWs* w, bool full = fals
   }
 }
 
+// lt_lsvd under Fourier modes (economy factors): the transform's two planes,
+// the representatives' complex working matrices and the complex Jacobi's
+// columns (2 N floats each), their norms, the finalisation's scratch, and the
+// transform-domain factors in two planes each.
+struct LsvdDftWs {
+  TransformWs t;
+  float* Ah = nullptr;
+  float* E = nullptr;
+  float* cols = nullptr;
+  double* sigma = nullptr;
+  int32_t* sweeps = nullptr;
+  int32_t* rep = nullptr;
+  int32_t* partner = nullptr;
+  float* scratch = nullptr;
+  float *Uh = nullptr, *Sh = nullptr, *Vh = nullptr;
+  int npairs = 0;
+};
+
+void carve_lsvd_dft(Carver& c, const Shape& s, int prec, LsvdDftWs* w) {
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  const long long m = s.I1 < s.I2 ? s.I2 : s.I1;
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  w->npairs = (int)rep.size();
+  const size_t np = rep.size();
+  carve_transform(c, s, prec, &w->t);
+  w->Ah = c.take<float>(2 * (size_t)s.nel);
+  w->E = c.take<float>(np * 2 * (size_t)s.N);
+  w->cols = c.take<float>(np * 2 * (size_t)s.N);
+  w->sigma = c.take<double>(np * (size_t)n);
+  w->sweeps = c.take<int32_t>(np);
+  w->rep = c.take<int32_t>(np);
+  w->partner = c.take<int32_t>(np);
+  w->scratch = c.take<float>(np * (size_t)(2 * m * n + 2 * n * n));
+  w->Uh = c.take<float>(2 * (size_t)(s.P * s.I1 * n));
+  w->Sh = c.take<float>(2 * (size_t)(s.P * n * n));
+  w->Vh = c.take<float>(2 * (size_t)(s.P * s.I2 * n));
+}
+
 int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
   if (!ws) return fail(h, LT_ERR_WORKSPACE, "workspace is NULL");
   if (have < need)
@@ -1055,13 +1094,13 @@ int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol
   return LT_OK;
 }
 
-// Operations that take Fourier modes: the product, the SVT and the completion,
-// FP32 only.
+// Operations that take Fourier modes: the product, the SVT, the completion and
+// the economy *_L-SVD, FP32 only.
 int check_dft(lt_handle* h, const Shape& s, int prec, bool op_supports) {
   if (!s.any_dft) return LT_OK;
   if (!op_supports)
     return fail(h, LT_ERR_UNSUPPORTED,
-                "Fourier modes are supported by lt_lproduct, lt_svt_prox and lt_complete_pga only");
+                "Fourier modes are supported by lt_lproduct, lt_lsvd, lt_svt_prox and lt_complete_pga only");
   if (prec != LT_PREC_F32)
     return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes take the FP32 transform only");
   return LT_OK;
@@ -1511,7 +1550,8 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
   Shape s;
   if (parse(nullptr, a, &s) != LT_OK) return 0;
   if (precision != LT_PREC_F32 && precision != LT_PREC_BF16X3) return 0;
-  if (s.any_dft && (precision != LT_PREC_F32 || (op != LT_OP_SVT && op != LT_OP_PGA && op != LT_OP_LPRODUCT)))
+  if (s.any_dft && (precision != LT_PREC_F32 ||
+                    (op != LT_OP_SVT && op != LT_OP_PGA && op != LT_OP_LPRODUCT && op != LT_OP_LSVD)))
     return 0;
   Carver c(nullptr);
   switch (op) {
@@ -1537,6 +1577,11 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
       break;
     }
     case LT_OP_LSVD: {
+      if (s.any_dft) {
+        LsvdDftWs w;
+        carve_lsvd_dft(c, s, precision, &w);
+        break;
+      }
       LsvdWs w;
       carve_lsvd(c, s, precision, &w);
       break;
@@ -1747,6 +1792,90 @@ int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, in
   return LT_OK;
 }
 
+// lt_lsvd under Fourier modes (Section 2's t-SVD): one complex SVD per
+// conjugate pair by the complex Jacobi in its all-columns mode, the economy
+// factors completed on the device (k_lsvd_finalize_cx: the representative's
+// and, conjugated, its partner's, in two planes), then the inverse transform.
+int lsvd_fourier(lt_handle* h, const lt_desc* a, const Shape& s, const float* A, float* U, float* S, float* V,
+                 float* sigma, int economy, int transform_domain, double tol, int max_sweeps, int prec, void* ws,
+                 size_t ws_bytes) {
+  int rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
+  if (!economy || transform_domain)
+    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes: lt_lsvd returns economy factors in the spatial domain only");
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  lt::JacobiConfig cc;
+  if (n > 256 || 2 * m > 2048 || lt::jacobi_cx_config(2 * m, n, h->max_lds, &cc) != 0)
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the complex Jacobi kernel", s.I1, s.I2);
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdDftWs w;
+  carve_lsvd_dft(c, s, prec, &w);
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  const int P = (int)s.P;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_FORWARD)))
+    return rc;
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  HIP_TRY(h, hipMemcpyAsync(w.rep, rep.data(), rep.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(w.partner, partner.data(), partner.size() * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));   // the host vectors go out of scope
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_dft_stack(w.Ah, w.Ah + s.nel, w.rep, w.npairs, (int)s.I1, (int)s.I2, w.E, h->stream));
+  }
+  lt::JacobiArgs j{};
+  j.src = w.E;
+  j.slice_stride = 2 * s.N;
+  j.I1 = 2 * m;
+  j.I2 = n;
+  j.nslices = w.npairs;
+  j.tau = 0.0;
+  j.tol = fabs(tol);
+  j.max_sweeps = max_sweeps;
+  j.mode = 1;
+  j.bk = w.cols;
+  j.bk_stride = 2 * s.N;
+  j.sweeps = w.sweeps;
+  j.sigma = w.sigma;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi_cx(j, cc, h->stream));
+  }
+  lt::LsvdCxArgs f{};
+  f.W = w.E;
+  f.cols = w.cols;
+  f.sigma = w.sigma;
+  f.w_stride = 2 * s.N;
+  f.rep = w.rep;
+  f.partner = w.partner;
+  f.npairs = w.npairs;
+  f.P = P;
+  f.I1 = (int)s.I1;
+  f.I2 = (int)s.I2;
+  f.U = w.Uh;
+  f.S = w.Sh;
+  f.V = w.Vh;
+  f.sig_out = sigma;
+  f.scratch = w.scratch;
+  f.scratch_stride = 2LL * m * n + 2LL * n * n;
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_lsvd_finalize_cx(f, h->stream));
+  }
+  if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * n, w.Uh, U, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_INVERSE)))
+    return rc;
+  if ((rc = gemm(h, gemm_plain(w.t, true, P, (long long)n * n, w.Sh, S, true), prec, lt::PRO_PLAIN,
+                 lt::EPI_PLAIN, LT_PROF_INVERSE)))
+    return rc;
+  return gemm(h, gemm_plain(w.t, true, P, s.I2 * n, w.Vh, V, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+              LT_PROF_INVERSE);
+}
+
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, float* V,
             float* sigma, int economy, int transform_domain, const lt_svd_opts* opts, void* ws,
             size_t ws_bytes) {
@@ -1759,7 +1888,9 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, 
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  if ((rc = check_dft(h, s, prec, false))) return rc;
+  if (s.any_dft)
+    return lsvd_fourier(h, a, s, A, U, S, V, sigma, economy, transform_domain, tol, max_sweeps, prec, ws,
+                        ws_bytes);
   lt::JacobiConfig cfg;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;

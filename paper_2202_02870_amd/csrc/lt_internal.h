@@ -303,6 +303,29 @@ struct LsvdArgs {
   float* sig_out;          // optional [nslices][n]
 };
 hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s);
+// Economy factors of complex (Fourier) slices from the complex Jacobi's
+// all-columns output, one conjugate-pair representative per workgroup: W and
+// cols are its working matrix and final columns (2 m interleaved rows x n,
+// w_stride floats apart), sigma their norms; U, S, V receive real-part planes
+// then imaginary-part planes (P slices each, I1 x n, n x n, I2 x n) for the
+// representative and, conjugated, its partner; sig_out (optional) P x n.
+// scratch: 2 m n + 2 n^2 floats per representative (scratch_stride apart).
+struct LsvdCxArgs {
+  const float* W;
+  const float* cols;
+  const double* sigma;
+  long long w_stride;
+  const int* rep;
+  const int* partner;
+  int npairs, P, I1, I2;
+  float* U;
+  float* S;
+  float* V;
+  float* sig_out;
+  float* scratch;
+  long long scratch_stride;
+};
+hipError_t launch_lsvd_finalize_cx(const LsvdCxArgs& a, hipStream_t s);
 
 // Full factors and multirank (lt_factors.hip).  dst (rd x cd per slice) = src
 // (rs x cs per slice) padded with zeros; complete_basis fills columns n..m-1 of

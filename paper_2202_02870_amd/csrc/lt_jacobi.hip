@@ -410,9 +410,10 @@ struct Job {
 };
 
 // CX: complex columns (interleaved rows, see dot64c) under Hermitian
-// rotations, SVT mode only; each kept column is written with its product by i
+// rotations.  SVT mode: each kept column is written with its product by i
 // (stage_out_cx) and counted twice in the rank and the nuclear-norm share, so
-// the output has the layout of the real SVT of the embedding [[X, -Y], [Y, X]].
+// the output has the layout of the real SVT of the embedding [[X, -Y], [Y, X]];
+// all-columns mode: as for real columns (interleaved rows, norms).
 // Out of line: inlined into the kernels it needs more registers.
 template <int G, int R, bool CX = false>
 __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol, int max_sweeps, int nbuf, int ldw,
@@ -691,18 +692,18 @@ __device__ __attribute__((noinline)) void jacobi_body(const Job& jb, double tol,
   if (active) put_col<G, R>(bufA, ldw, g, l, av, qeff, sca, da);
   __syncthreads();
   if (active) {
-    if (CX) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
+    if (CX && jb.mode == 0) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
     else stage_out(out, bufA, ldw, m, npairs, t2, tps);
   }
   __syncthreads();
   if (active) put_col<G, R>(bufA, ldw, g, l, bv, qeff, scb, db);
   __syncthreads();
   if (active) {
-    if (CX) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
+    if (CX && jb.mode == 0) stage_out_cx(out, bufA, ldw, m, npairs, t2, tps);
     else stage_out(out, bufA, ldw, m, npairs, t2, tps);
   }
   if (active && t2 == 0) {
-    if (jb.rank) jb.rank[sub] = CX ? 2 * ctl[2] : ctl[2];
+    if (jb.rank) jb.rank[sub] = (CX && jb.mode == 0) ? 2 * ctl[2] : ctl[2];
     if (jb.sweeps) jb.sweeps[sub] = my_sweeps;
     if (jb.sweep_total) atomicAdd(jb.sweep_total, (unsigned long long)my_sweeps);
     if (jb.rot_total) atomicAdd(jb.rot_total, (unsigned long long)rotations);
@@ -1965,6 +1966,165 @@ __global__ __launch_bounds__(256) void k_lsvd_finalize(LsvdArgs a) {
     for (int k = tid; k < n; k += 256) a.sig_out[(long long)s * n + k] = (float)sg[k];
 }
 
+// cgs2_columns for complex columns held as interleaved (Re, Im) rows (2 len
+// floats per column): c_j = q_j^H v, v -= sum_j c_j q_j, twice, then
+// normalise; v and c hold interleaved FP64 pairs.
+__device__ void cgs2_columns_cx(float* Q, int len, int n, const int* ok, double* v, double* c, double* red) {
+  const int tid = threadIdx.x;
+  const long long cs = 2LL * len;
+  for (int k = 0; k < n; ++k) {
+    for (int cand = -1; cand < len; ++cand) {
+      if (cand < 0 && !ok[k]) continue;
+      for (int row = tid; row < len; row += 256) {
+        v[2 * row] = cand < 0 ? (double)Q[k * cs + 2 * row] : (row == cand ? 1.0 : 0.0);
+        v[2 * row + 1] = cand < 0 ? (double)Q[k * cs + 2 * row + 1] : 0.0;
+      }
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int j = tid; j < k; j += 256) {
+          double cr = 0.0, ci = 0.0;
+          for (int row = 0; row < len; ++row) {
+            const double qr = Q[j * cs + 2 * row], qi = Q[j * cs + 2 * row + 1];
+            cr += qr * v[2 * row] + qi * v[2 * row + 1];
+            ci += qr * v[2 * row + 1] - qi * v[2 * row];
+          }
+          c[2 * j] = cr;
+          c[2 * j + 1] = ci;
+        }
+        __syncthreads();
+        for (int row = tid; row < len; row += 256) {
+          double ar = v[2 * row], ai = v[2 * row + 1];
+          for (int j = 0; j < k; ++j) {
+            const double qr = Q[j * cs + 2 * row], qi = Q[j * cs + 2 * row + 1];
+            ar -= c[2 * j] * qr - c[2 * j + 1] * qi;
+            ai -= c[2 * j] * qi + c[2 * j + 1] * qr;
+          }
+          v[2 * row] = ar;
+          v[2 * row + 1] = ai;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int row = tid; row < len; row += 256) part += v[2 * row] * v[2 * row] + v[2 * row + 1] * v[2 * row + 1];
+      const double nrm = sqrt(block_sum256(part, red));
+      if (nrm > 0.5) {
+        for (int row = tid; row < len; row += 256) {
+          Q[k * cs + 2 * row] = (float)(v[2 * row] / nrm);
+          Q[k * cs + 2 * row + 1] = (float)(v[2 * row + 1] / nrm);
+        }
+        __syncthreads();
+        break;
+      }
+    }
+  }
+}
+
+// Economy factors of complex slices (Fourier modes), one workgroup per
+// conjugate-pair representative t: the singular values sorted descending,
+// Uw = cols / sigma, Vw = W^H Uw / sigma, both re-orthonormalised (complex
+// CGS2, in the scratch), then the factors of slice rep[t] (I1 >= I2: U = Uw,
+// V = Vw; I1 < I2, W the plain transpose: U = conj(Vw), V = conj(Uw)) and the
+// conjugates for its partner into real and imaginary planes.  A self-conjugate
+// slice (real data) gets zero imaginary parts.
+__global__ __launch_bounds__(256) void k_lsvd_finalize_cx(LsvdCxArgs a) {
+  __shared__ int perm[LS_NMAX];
+  __shared__ int ok[LS_NMAX];
+  __shared__ double sg[LS_NMAX];
+  __shared__ double cbuf[2 * LS_NMAX];
+  __shared__ double vbuf[LS_MMAX];
+  __shared__ double red[256];
+  const int t = blockIdx.x;
+  const int p = a.rep[t], q = a.partner[t];
+  const int I1 = a.I1, I2 = a.I2;
+  const bool trans = I1 < I2;
+  const int m = trans ? I2 : I1;
+  const int n = trans ? I1 : I2;
+  const int tid = threadIdx.x;
+  const double* sig = a.sigma + (long long)t * n;
+  for (int i = tid; i < n; i += 256) {
+    const double si = sig[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double sj = sig[j];
+      rk += (sj > si) || (sj == si && j < i);
+    }
+    perm[rk] = i;
+  }
+  __syncthreads();
+  for (int k = tid; k < n; k += 256) sg[k] = sig[perm[k]];
+  __syncthreads();
+  const double cut = (n > 0 ? sg[0] : 0.0) * 1e-6;
+  for (int k = tid; k < n; k += 256) ok[k] = sg[k] > cut;
+  const float* W = a.W + (long long)t * a.w_stride;
+  const float* cols = a.cols + (long long)t * a.w_stride;
+  float* Uw = a.scratch + (long long)t * a.scratch_stride;   // 2m x n
+  float* Vw = Uw + 2LL * m * n;                              // 2n x n
+  __syncthreads();
+  for (int idx = tid; idx < 2 * m * n; idx += 256) {
+    const int k = idx / (2 * m), r = idx - k * 2 * m;
+    const double sk = sg[k];
+    Uw[idx] = sk > cut ? (float)((double)cols[(long long)perm[k] * 2 * m + r] / sk) : 0.f;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int k = idx / n, j = idx - k * n;
+    const double sk = sg[k];
+    double ar = 0.0, ai = 0.0;
+    if (sk > cut) {
+      const float* wj = W + (long long)j * 2 * m;
+      const float* uk = Uw + (long long)k * 2 * m;
+      for (int row = 0; row < m; ++row) {   // conj(w) u
+        const double wr = wj[2 * row], wi = wj[2 * row + 1], ur = uk[2 * row], ui = uk[2 * row + 1];
+        ar += wr * ur + wi * ui;
+        ai += wr * ui - wi * ur;
+      }
+      ar /= sk;
+      ai /= sk;
+    }
+    Vw[(long long)k * 2 * n + 2 * j] = (float)ar;
+    Vw[(long long)k * 2 * n + 2 * j + 1] = (float)ai;
+  }
+  __syncthreads();
+  cgs2_columns_cx(Uw, m, n, ok, vbuf, cbuf, red);
+  cgs2_columns_cx(Vw, n, n, ok, vbuf, cbuf, red);
+  // U (I1 x n) and V (I2 x n) of slice p; Uw has m rows, Vw n rows
+  const float* Us = trans ? Vw : Uw;
+  const float* Vs = trans ? Uw : Vw;
+  const float sgn = trans ? -1.f : 1.f;   // conjugated when transposed
+  const long long pu = (long long)a.P * I1 * n, pv = (long long)a.P * I2 * n, ps = (long long)a.P * n * n;
+  for (int idx = tid; idx < I1 * n; idx += 256) {
+    const float re = Us[2 * idx], im = sgn * Us[2 * idx + 1];
+    a.U[(long long)p * I1 * n + idx] = re;
+    a.U[pu + (long long)p * I1 * n + idx] = q == p ? 0.f : im;
+    if (q != p) {
+      a.U[(long long)q * I1 * n + idx] = re;
+      a.U[pu + (long long)q * I1 * n + idx] = -im;
+    }
+  }
+  for (int idx = tid; idx < I2 * n; idx += 256) {
+    const float re = Vs[2 * idx], im = sgn * Vs[2 * idx + 1];
+    a.V[(long long)p * I2 * n + idx] = re;
+    a.V[pv + (long long)p * I2 * n + idx] = q == p ? 0.f : im;
+    if (q != p) {
+      a.V[(long long)q * I2 * n + idx] = re;
+      a.V[pv + (long long)q * I2 * n + idx] = -im;
+    }
+  }
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int k = idx / n, j = idx - k * n;
+    const float v = (j == k) ? (float)sg[k] : 0.f;
+    a.S[(long long)p * n * n + idx] = v;
+    a.S[ps + (long long)p * n * n + idx] = 0.f;
+    a.S[(long long)q * n * n + idx] = v;
+    a.S[ps + (long long)q * n * n + idx] = 0.f;
+  }
+  if (a.sig_out)
+    for (int k = tid; k < n; k += 256) {
+      a.sig_out[(long long)p * n + k] = (float)sg[k];
+      a.sig_out[(long long)q * n + k] = (float)sg[k];
+    }
+}
+
 template <int G, int R, int LB>
 hipError_t launch_one(const JacobiArgs& a, const JacobiConfig& c, hipStream_t s) {
   const int ldw = G * R + 4;
@@ -2383,7 +2543,7 @@ int jacobi_cx_config(int ms, int n, int max_lds, JacobiConfig* cfg) {
 
 hipError_t launch_jacobi_cx(const JacobiArgs& a0, const JacobiConfig& c, hipStream_t s) {
   if (a0.nslices <= 0) return hipSuccess;
-  if (a0.mode != 0 || (a0.I1 & 1) || a0.I1 < a0.I2 || a0.tol < 0.0) return hipErrorInvalidValue;
+  if ((a0.mode != 0 && a0.mode != 1) || (a0.I1 & 1) || a0.I1 < a0.I2 || a0.tol < 0.0) return hipErrorInvalidValue;
   JacobiArgs a = a0;
   a.qeff = c.R / 4;
   if (c.G == 8) {
@@ -2815,6 +2975,14 @@ hipError_t launch_wide_out(const WideArgs& a, const JacobiWideConfig& c, hipStre
     case 4: return launch_wide_out_one<64, 36>(a, c, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_lsvd_finalize_cx(const LsvdCxArgs& a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  const int m = a.I1 > a.I2 ? a.I1 : a.I2, n = a.I1 > a.I2 ? a.I2 : a.I1;
+  if (n > LS_NMAX || 2 * m > LS_MMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lsvd_finalize_cx, dim3(a.npairs), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_lsvd_finalize(const LsvdArgs& a, hipStream_t s) {

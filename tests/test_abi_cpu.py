@@ -67,7 +67,11 @@ def test_workspace_sizes_host_only():
     n_dft = lt.workspace_bytes((8, 8, 4), ("dft",), "svt")
     assert n_dft >= 2 * 8 * 8 * 4 * 4 + 3 * 16 * 16 * 4 * 2
     assert lt.workspace_bytes((8, 8, 4), ("dft",), "pga") > n_dft
-    for op, prec in (("svt", "bf16x3"), ("lsvd", "f32"), ("truncate", "f32")):
+    # the economy *_L-SVD: the two planes, the representatives' complex working
+    # matrices and columns (P = 4: 3 representatives), factors in two planes
+    assert lt.workspace_bytes((8, 6, 4), ("dft",), "lsvd") >= 4 * (2 * 8 * 6 * 4 + 2 * 3 * 2 * 8 * 6
+                                                                    + 2 * 4 * (8 * 6 + 6 * 6 + 6 * 6))
+    for op, prec in (("svt", "bf16x3"), ("lsvd", "bf16x3"), ("lsvd_full", "f32"), ("truncate", "f32")):
         with pytest.raises(ValueError):      # other operations and BF16 transforms: rejected
             lt.workspace_bytes((8, 8, 4), ("dft",), op, prec)
     # the product under the DFT: real and imaginary planes of A, B and C

@@ -137,6 +137,32 @@ def test_svt_complex_video_against_embedding(lt):
     parity.check(lt.to_host(D), o.svt(A, tau, mats), 2e-5, label="gap")
 
 
+@pytest.mark.parametrize("shape,kinds", [((8, 6, 5), ("dft",)), ((5, 9, 6), ("dft",)),
+                                         ((20, 14, 4, 3), ("dft", "dct")), ((33, 40, 4), ("dft",)),
+                                         ((100, 80, 3), ("dft",))])
+def test_lsvd_fourier_invariants(lt, shape, kinds):
+    """The t-SVD (economy *_L-SVD under the DFT): A = U *_L S *_L V^H with the
+    oracle's products and conjugate transpose, the transform-domain slices of U
+    and V orthonormal (complex), S's the diagonal of the sorted singular values,
+    which match the oracle's; both orientations, self-conjugate slices."""
+    rng = np.random.default_rng(sum(shape) + 7)
+    A = rng.standard_normal(shape)
+    mats = o.mats_for(shape, list(kinds))
+    U, S, V, sig = lt.lsvd(lt.to_device(A), kinds)
+    U, S, V, sig = (lt.to_host(x).astype(np.float64) for x in (U, S, V, sig))
+    R = o.lproduct(o.lproduct(U, S, mats), o.ttranspose(V, mats), mats)
+    assert np.abs(np.imag(R)).max() < 1e-9 * np.abs(A).max()
+    parity.check(np.real(R), A, 2e-5, label="t-SVD %s" % (shape,))
+    sv = o.singular_values(A, mats)
+    say("lsvd dft", shape, kinds, "sigma err", np.abs(sig - sv).max() / sv.max())
+    assert np.abs(sig - sv).max() < 2e-5 * sv.max()
+    for Q in (U, V):
+        for q in o.slices(o.transform(Q, mats)):
+            assert np.abs(q.conj().T @ q - np.eye(q.shape[1])).max() < 2e-5
+    for sh, sg in zip(o.slices(o.transform(S, mats)), sv):
+        assert np.abs(sh - np.diag(sg)).max() < 2e-5 * sv.max()
+
+
 def test_pga_video_dft(lt):
     """Completion of the 144 x 176 x 3 x 50 video tensor under the DFT (the
     t-product's TNN-PGA-F) through the complex path, 10 iterations of the

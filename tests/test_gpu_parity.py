@@ -485,8 +485,10 @@ def test_pga_degenerate_masks(lt):
 def test_error_paths(lt):
     import torch
     A = lt.to_device(np.ones((8, 8, 4)))
-    with pytest.raises(ValueError):                   # Fourier modes: product, SVT and completion only
-        lt.lsvd(A, ("dft",))
+    with pytest.raises(ValueError):                   # Fourier modes: economy factors only
+        lt.lsvd(A, ("dft",), economy=False)
+    with pytest.raises(ValueError):                   # and no truncation
+        lt.ltruncate(A, 2, ("dft",))
     with pytest.raises(ValueError):                   # and FP32 transforms only
         lt.lproduct(A, A, ("dft",), precision="bf16x3")
     with pytest.raises(ValueError):
