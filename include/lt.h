@@ -275,7 +275,9 @@ int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S,
  * slices: rank (device, P int32) per slice; avg (host, may be NULL) their mean
  * (the average rank), tubal (host, may be NULL) their maximum (the tubal
  * rank).  Synchronises the stream when avg or tubal is requested.  Same slice
- * limits as lt_lsvd; workspace lt_workspace_bytes(a, NULL, LT_OP_LSVD, prec). */
+ * limits as lt_lsvd (Fourier modes: the complex Jacobi's, the two slices of a
+ * conjugate pair sharing their singular values); workspace
+ * lt_workspace_bytes(a, NULL, LT_OP_LSVD, prec). */
 int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, int32_t* rank,
                  double* avg, int32_t* tubal, const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 
@@ -283,8 +285,10 @@ int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, in
  * by products X *_L Y with X of k lateral slices (Eckart-Young theorem,
  * Section 3.2): every slice of L(A) keeps its k largest singular triplets
  * (all of them when k >= min(I1, I2); A_k = 0 when k <= 0), then L^{-1}.
- * Same slice limits as lt_lsvd (min(I1, I2) <= 256, max(I1, I2) <= 2048).
- * Ak may alias A.  Workspace: lt_workspace_bytes(a, NULL, LT_OP_TRUNCATE, prec). */
+ * Same slice limits as lt_lsvd (min(I1, I2) <= 256, max(I1, I2) <= 2048; under
+ * Fourier modes those of the complex Jacobi, FP32 transforms, with V^H for
+ * V^T).  Ak may alias A.  Workspace: lt_workspace_bytes(a, NULL, LT_OP_TRUNCATE,
+ * prec). */
 int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, float* Ak,
                  const lt_svd_opts* opts, void* ws, size_t ws_bytes);
 

@@ -678,10 +678,14 @@ struct LsvdDftWs {
   int32_t* partner = nullptr;
   float* scratch = nullptr;
   float *Uh = nullptr, *Sh = nullptr, *Vh = nullptr;
+  double* sigP = nullptr;   // multirank: the norms of every slice (P x n)
+  double* mr = nullptr;     // multirank: mean and maximum
+  float* Bk = nullptr;      // truncation: the first k columns with their i-twins (4 N floats per representative)
+  int32_t* kept = nullptr;  // truncation: 2 k per representative
   int npairs = 0;
 };
 
-void carve_lsvd_dft(Carver& c, const Shape& s, int prec, LsvdDftWs* w) {
+void carve_lsvd_dft(Carver& c, const Shape& s, int prec, LsvdDftWs* w, bool truncate = false) {
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
   const long long m = s.I1 < s.I2 ? s.I2 : s.I1;
   std::vector<int> rep, partner;
@@ -700,6 +704,12 @@ void carve_lsvd_dft(Carver& c, const Shape& s, int prec, LsvdDftWs* w) {
   w->Uh = c.take<float>(2 * (size_t)(s.P * s.I1 * n));
   w->Sh = c.take<float>(2 * (size_t)(s.P * n * n));
   w->Vh = c.take<float>(2 * (size_t)(s.P * s.I2 * n));
+  w->sigP = c.take<double>((size_t)(s.P * n));
+  w->mr = c.take<double>(2);
+  if (truncate) {
+    w->Bk = c.take<float>(np * 4 * (size_t)s.N);
+    w->kept = c.take<int32_t>(np);
+  }
 }
 
 int check_ws(lt_handle* h, void* ws, size_t have, size_t need) {
@@ -1094,13 +1104,12 @@ int run_svt(lt_handle* h, const Shape& s, const SvtWs& w, double tau, double tol
   return LT_OK;
 }
 
-// Operations that take Fourier modes: the product, the SVT, the completion and
-// the economy *_L-SVD, FP32 only.
+// Operations that take Fourier modes: the product, the SVT, the completion, the
+// economy *_L-SVD, the truncation and the multirank, FP32 only.
 int check_dft(lt_handle* h, const Shape& s, int prec, bool op_supports) {
   if (!s.any_dft) return LT_OK;
   if (!op_supports)
-    return fail(h, LT_ERR_UNSUPPORTED,
-                "Fourier modes are supported by lt_lproduct, lt_lsvd, lt_svt_prox and lt_complete_pga only");
+    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes are not supported by this operation");
   if (prec != LT_PREC_F32)
     return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes take the FP32 transform only");
   return LT_OK;
@@ -1441,6 +1450,176 @@ void carve_batch(Carver& c, const BatchTables& T, BatchWs* w) {
   w->warm = c.take<lt::CholItem>(T.warm.size());
 }
 
+// The *_L-SVD under Fourier modes (Section 2's t-SVD): one complex SVD per
+// conjugate pair by the complex Jacobi in its all-columns mode.  The core
+// transforms A, stacks the representatives' working matrices and runs the
+// Jacobi (columns and norms); `finalize` adds the economy factors
+// (k_lsvd_finalize_cx: the representative's and, conjugated, its partner's, in
+// two planes; Uw sorted and orthonormal in the scratch).
+int lsvd_fourier_core(lt_handle* h, const Shape& s, const float* A, double tol, int max_sweeps, int prec,
+                      const LsvdDftWs& w, float* sigma_out, bool finalize) {
+  int rc;
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  lt::JacobiConfig cc;
+  if (n > 256 || 2 * m > 2048 || lt::jacobi_cx_config(2 * m, n, h->max_lds, &cc) != 0)
+    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the complex Jacobi kernel", s.I1, s.I2);
+  if ((rc = build_transform(h, s, prec, w.t))) return rc;
+  const int P = (int)s.P;
+  if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_FORWARD)))
+    return rc;
+  std::vector<int> rep, partner;
+  dft_pairs(s, &rep, &partner);
+  HIP_TRY(h, hipMemcpyAsync(w.rep, rep.data(), rep.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(w.partner, partner.data(), partner.size() * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));   // the host vectors go out of scope
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_dft_stack(w.Ah, w.Ah + s.nel, w.rep, w.npairs, (int)s.I1, (int)s.I2, w.E, h->stream));
+  }
+  lt::JacobiArgs j{};
+  j.src = w.E;
+  j.slice_stride = 2 * s.N;
+  j.I1 = 2 * m;
+  j.I2 = n;
+  j.nslices = w.npairs;
+  j.tau = 0.0;
+  j.tol = fabs(tol);
+  j.max_sweeps = max_sweeps;
+  j.mode = 1;
+  j.bk = w.cols;
+  j.bk_stride = 2 * s.N;
+  j.sweeps = w.sweeps;
+  j.sigma = w.sigma;
+  {
+    ProfScope ps(h, LT_PROF_JACOBI);
+    HIP_TRY(h, lt::launch_jacobi_cx(j, cc, h->stream));
+  }
+  if (!finalize) return LT_OK;
+  lt::LsvdCxArgs f{};
+  f.W = w.E;
+  f.cols = w.cols;
+  f.sigma = w.sigma;
+  f.w_stride = 2 * s.N;
+  f.rep = w.rep;
+  f.partner = w.partner;
+  f.npairs = w.npairs;
+  f.P = P;
+  f.I1 = (int)s.I1;
+  f.I2 = (int)s.I2;
+  f.U = w.Uh;
+  f.S = w.Sh;
+  f.V = w.Vh;
+  f.sig_out = sigma_out;
+  f.scratch = w.scratch;
+  f.scratch_stride = 2LL * m * n + 2LL * n * n;
+  ProfScope ps(h, LT_PROF_OTHER);
+  HIP_TRY(h, lt::launch_lsvd_finalize_cx(f, h->stream));
+  return LT_OK;
+}
+
+int lsvd_fourier(lt_handle* h, const lt_desc* a, const Shape& s, const float* A, float* U, float* S, float* V,
+                 float* sigma, int economy, int transform_domain, double tol, int max_sweeps, int prec, void* ws,
+                 size_t ws_bytes) {
+  int rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
+  if (!economy || transform_domain)
+    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes: lt_lsvd returns economy factors in the spatial domain only");
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdDftWs w;
+  carve_lsvd_dft(c, s, prec, &w);
+  if ((rc = lsvd_fourier_core(h, s, A, tol, max_sweeps, prec, w, sigma, true))) return rc;
+  const int P = (int)s.P;
+  const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
+  if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * n, w.Uh, U, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_INVERSE)))
+    return rc;
+  if ((rc = gemm(h, gemm_plain(w.t, true, P, n * n, w.Sh, S, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+                 LT_PROF_INVERSE)))
+    return rc;
+  return gemm(h, gemm_plain(w.t, true, P, s.I2 * n, w.Vh, V, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+              LT_PROF_INVERSE);
+}
+
+// Multirank under Fourier modes: the complex Jacobi's norms of each
+// representative count for both slices of its pair.
+int multirank_fourier(lt_handle* h, const lt_desc* a, const Shape& s, const float* A, double rtol, int32_t* rank,
+                      double* avg, int32_t* tubal, double tol, int max_sweeps, int prec, void* ws,
+                      size_t ws_bytes) {
+  int rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdDftWs w;
+  carve_lsvd_dft(c, s, prec, &w);
+  if ((rc = lsvd_fourier_core(h, s, A, tol, max_sweeps, prec, w, nullptr, false))) return rc;
+  const int n = (int)(s.I1 < s.I2 ? s.I1 : s.I2);
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_expand_pairs(w.sigma, w.rep, w.partner, w.npairs, n, w.sigP, h->stream));
+    HIP_TRY(h, lt::launch_multirank(w.sigP, (int)s.P, n, rtol, rank, w.mr, h->stream));
+  }
+  if (avg || tubal) {
+    HIP_TRY(h, hipMemcpyAsync(h->pinned, w.mr, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (avg) *avg = h->pinned[0];
+    if (tubal) *tubal = (int32_t)h->pinned[1];
+  }
+  return LT_OK;
+}
+
+// Rank-k truncation under Fourier modes: A_k's complex slice in working
+// orientation is U_k U_k^H W (U_k: the first k sorted, orthonormal left
+// singular vectors from the finalisation), formed by the real rebuild over the
+// interleaved rows from each column and its product by i, then the results back
+// to the planes (partners conjugated) and the inverse transform.
+int truncate_fourier(lt_handle* h, const lt_desc* a, const Shape& s, const float* A, int32_t k, float* Ak,
+                     double tol, int max_sweeps, int prec, void* ws, size_t ws_bytes) {
+  int rc;
+  if ((rc = check_dft(h, s, prec, true))) return rc;
+  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_TRUNCATE, prec);
+  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
+  Carver c(ws);
+  LsvdDftWs w;
+  carve_lsvd_dft(c, s, prec, &w, true);
+  if ((rc = lsvd_fourier_core(h, s, A, tol, max_sweeps, prec, w, nullptr, true))) return rc;
+  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
+  const int kk = k <= 0 ? 0 : (k < n ? (int)k : n);
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_twin_columns(w.scratch, 2LL * m * n + 2LL * n * n, 2 * m, kk, w.Bk, 4 * s.N, w.npairs,
+                                       h->stream));
+    HIP_TRY(h, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(w.kept), 2 * kk, (size_t)w.npairs, h->stream));
+  }
+  lt::RebuildArgs r{};
+  r.W = w.E;
+  r.D = w.E;
+  r.bk = w.Bk;
+  r.rank = w.kept;
+  r.slice_stride = 2 * s.N;
+  r.bk_stride = 4 * s.N;
+  r.kmax = 2 * n;
+  r.I1 = 2 * m;
+  r.I2 = n;
+  r.nslices = w.npairs;
+  r.flip = 0;
+  {
+    ProfScope ps(h, LT_PROF_REBUILD);
+    HIP_TRY(h, lt::launch_rebuild(r, h->stream));
+  }
+  {
+    ProfScope ps(h, LT_PROF_OTHER);
+    HIP_TRY(h, lt::launch_dft_unstack(w.E, w.rep, w.partner, w.npairs, (int)s.I1, (int)s.I2, w.Ah, w.Ah + s.nel,
+                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, h->stream));
+  }
+  return gemm(h, gemm_plain(w.t, true, (int)s.P, s.N, w.Ah, Ak, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
+              LT_PROF_INVERSE);
+}
+
 }  // namespace
 
 struct lt_batch {
@@ -1550,8 +1729,8 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
   Shape s;
   if (parse(nullptr, a, &s) != LT_OK) return 0;
   if (precision != LT_PREC_F32 && precision != LT_PREC_BF16X3) return 0;
-  if (s.any_dft && (precision != LT_PREC_F32 ||
-                    (op != LT_OP_SVT && op != LT_OP_PGA && op != LT_OP_LPRODUCT && op != LT_OP_LSVD)))
+  if (s.any_dft && (precision != LT_PREC_F32 || (op != LT_OP_SVT && op != LT_OP_PGA && op != LT_OP_LPRODUCT &&
+                                                 op != LT_OP_LSVD && op != LT_OP_TRUNCATE)))
     return 0;
   Carver c(nullptr);
   switch (op) {
@@ -1592,6 +1771,11 @@ size_t lt_workspace_bytes(const lt_desc* a, const lt_desc* b, int op, int precis
       break;
     }
     case LT_OP_TRUNCATE: {
+      if (s.any_dft) {
+        LsvdDftWs w;
+        carve_lsvd_dft(c, s, precision, &w, true);
+        break;
+      }
       LsvdWs w;
       carve_lsvd(c, s, precision, &w);
       (void)c.take<int32_t>((size_t)s.P);   // kept count per slice
@@ -1768,7 +1952,8 @@ int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, in
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  if ((rc = check_dft(h, s, prec, false))) return rc;
+  if (s.any_dft)
+    return multirank_fourier(h, a, s, A, rtol, rank, avg, tubal, tol, max_sweeps, prec, ws, ws_bytes);
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;
   const long long mrows = s.I1 < s.I2 ? s.I2 : s.I1;
   if (n > 256 || mrows > 2048)
@@ -1790,90 +1975,6 @@ int lt_multirank(lt_handle* h, const lt_desc* a, const float* A, double rtol, in
     if (tubal) *tubal = (int32_t)h->pinned[1];
   }
   return LT_OK;
-}
-
-// lt_lsvd under Fourier modes (Section 2's t-SVD): one complex SVD per
-// conjugate pair by the complex Jacobi in its all-columns mode, the economy
-// factors completed on the device (k_lsvd_finalize_cx: the representative's
-// and, conjugated, its partner's, in two planes), then the inverse transform.
-int lsvd_fourier(lt_handle* h, const lt_desc* a, const Shape& s, const float* A, float* U, float* S, float* V,
-                 float* sigma, int economy, int transform_domain, double tol, int max_sweeps, int prec, void* ws,
-                 size_t ws_bytes) {
-  int rc;
-  if ((rc = check_dft(h, s, prec, true))) return rc;
-  if (!economy || transform_domain)
-    return fail(h, LT_ERR_UNSUPPORTED, "Fourier modes: lt_lsvd returns economy factors in the spatial domain only");
-  const int m = (int)(s.I1 > s.I2 ? s.I1 : s.I2), n = (int)(s.I1 > s.I2 ? s.I2 : s.I1);
-  lt::JacobiConfig cc;
-  if (n > 256 || 2 * m > 2048 || lt::jacobi_cx_config(2 * m, n, h->max_lds, &cc) != 0)
-    return fail(h, LT_ERR_SHAPE, "slice %lld x %lld exceeds the complex Jacobi kernel", s.I1, s.I2);
-  const size_t need = lt_workspace_bytes(a, nullptr, LT_OP_LSVD, prec);
-  if ((rc = check_ws(h, ws, ws_bytes, need))) return rc;
-  Carver c(ws);
-  LsvdDftWs w;
-  carve_lsvd_dft(c, s, prec, &w);
-  if ((rc = build_transform(h, s, prec, w.t))) return rc;
-  const int P = (int)s.P;
-  if ((rc = gemm(h, gemm_plain(w.t, false, P, s.N, A, w.Ah, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
-                 LT_PROF_FORWARD)))
-    return rc;
-  std::vector<int> rep, partner;
-  dft_pairs(s, &rep, &partner);
-  HIP_TRY(h, hipMemcpyAsync(w.rep, rep.data(), rep.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(w.partner, partner.data(), partner.size() * sizeof(int), hipMemcpyHostToDevice,
-                            h->stream));
-  HIP_TRY(h, hipStreamSynchronize(h->stream));   // the host vectors go out of scope
-  {
-    ProfScope ps(h, LT_PROF_OTHER);
-    HIP_TRY(h, lt::launch_dft_stack(w.Ah, w.Ah + s.nel, w.rep, w.npairs, (int)s.I1, (int)s.I2, w.E, h->stream));
-  }
-  lt::JacobiArgs j{};
-  j.src = w.E;
-  j.slice_stride = 2 * s.N;
-  j.I1 = 2 * m;
-  j.I2 = n;
-  j.nslices = w.npairs;
-  j.tau = 0.0;
-  j.tol = fabs(tol);
-  j.max_sweeps = max_sweeps;
-  j.mode = 1;
-  j.bk = w.cols;
-  j.bk_stride = 2 * s.N;
-  j.sweeps = w.sweeps;
-  j.sigma = w.sigma;
-  {
-    ProfScope ps(h, LT_PROF_JACOBI);
-    HIP_TRY(h, lt::launch_jacobi_cx(j, cc, h->stream));
-  }
-  lt::LsvdCxArgs f{};
-  f.W = w.E;
-  f.cols = w.cols;
-  f.sigma = w.sigma;
-  f.w_stride = 2 * s.N;
-  f.rep = w.rep;
-  f.partner = w.partner;
-  f.npairs = w.npairs;
-  f.P = P;
-  f.I1 = (int)s.I1;
-  f.I2 = (int)s.I2;
-  f.U = w.Uh;
-  f.S = w.Sh;
-  f.V = w.Vh;
-  f.sig_out = sigma;
-  f.scratch = w.scratch;
-  f.scratch_stride = 2LL * m * n + 2LL * n * n;
-  {
-    ProfScope ps(h, LT_PROF_OTHER);
-    HIP_TRY(h, lt::launch_lsvd_finalize_cx(f, h->stream));
-  }
-  if ((rc = gemm(h, gemm_plain(w.t, true, P, s.I1 * n, w.Uh, U, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
-                 LT_PROF_INVERSE)))
-    return rc;
-  if ((rc = gemm(h, gemm_plain(w.t, true, P, (long long)n * n, w.Sh, S, true), prec, lt::PRO_PLAIN,
-                 lt::EPI_PLAIN, LT_PROF_INVERSE)))
-    return rc;
-  return gemm(h, gemm_plain(w.t, true, P, s.I2 * n, w.Vh, V, true), prec, lt::PRO_PLAIN, lt::EPI_PLAIN,
-              LT_PROF_INVERSE);
 }
 
 int lt_lsvd(lt_handle* h, const lt_desc* a, const float* A, float* U, float* S, float* V,
@@ -1975,7 +2076,7 @@ int lt_ltruncate(lt_handle* h, const lt_desc* a, const float* A, int32_t k, floa
   int max_sweeps, prec;
   resolve_opts(opts, &tol, &max_sweeps, &prec);
   if ((rc = check_prec(h, prec))) return rc;
-  if ((rc = check_dft(h, s, prec, false))) return rc;
+  if (s.any_dft) return truncate_fourier(h, a, s, A, k, Ak, tol, max_sweeps, prec, ws, ws_bytes);
   lt::JacobiConfig cfg;
   if ((rc = jacobi_config(h, s, &cfg))) return rc;
   const long long n = s.I1 < s.I2 ? s.I1 : s.I2;

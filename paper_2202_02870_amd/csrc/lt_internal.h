@@ -97,6 +97,13 @@ hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner
 // floats apart) into contiguous rows x ncols ones (dst_stride apart).
 hipError_t launch_even_columns(const float* src, long long src_stride, float* dst, long long dst_stride, int rows,
                                int ncols, int nslices, hipStream_t s);
+// Columns j < k of complex matrices (2 m interleaved rows) and their products
+// by i as columns 2j, 2j + 1 of Bk; per-representative values to both slices
+// of each conjugate pair (P x n).
+hipError_t launch_twin_columns(const float* U, long long u_stride, int rows2, int k, float* Bk, long long bk_stride,
+                               int nslices, hipStream_t s);
+hipError_t launch_expand_pairs(const double* v, const int* rep, const int* partner, int npairs, int n, double* out,
+                               hipStream_t s);
 // out[0] = scale * (v[0] + ... + v[n-1]) in a fixed summation order (one workgroup).
 hipError_t launch_sum_scaled(const double* v, int n, double scale, double* out, hipStream_t s);
 

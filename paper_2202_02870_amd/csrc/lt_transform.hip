@@ -485,6 +485,34 @@ __global__ __launch_bounds__(256) void k_dft_stack(const float* __restrict__ Re,
   }
 }
 
+// Columns j < k of per-slice complex matrices (rows2 = 2 m interleaved rows,
+// u_stride floats apart) written with their products by i ((Re, Im) ->
+// (-Im, Re)) as columns 2j and 2j + 1 of Bk (bk_stride apart): the real
+// rebuild over the interleaved rows then forms U_k U_k^H W.
+__global__ __launch_bounds__(256) void k_twin_columns(const float* __restrict__ U, long long u_stride, int rows2,
+                                                      int k, float* __restrict__ Bk, long long bk_stride) {
+  const int t = blockIdx.y;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)rows2 * k) return;
+  const int j = (int)(e / rows2), r = (int)(e - (long long)j * rows2);
+  const float* u = U + t * u_stride + (long long)j * rows2;
+  float* b = Bk + t * bk_stride + (long long)(2 * j) * rows2;
+  b[r] = u[r];
+  b[rows2 + r] = (r & 1) ? u[r - 1] : -u[r + 1];
+}
+
+// Per-representative values (n each) copied to the representative's slice and
+// its partner's (P x n).
+__global__ __launch_bounds__(256) void k_expand_pairs(const double* __restrict__ v, const int* rep,
+                                                      const int* partner, int n, double* __restrict__ out) {
+  const int t = blockIdx.x;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const double x = v[(long long)t * n + k];
+    out[(long long)rep[t] * n + k] = x;
+    out[(long long)partner[t] * n + k] = x;
+  }
+}
+
 // Columns 0, 2, 4, ... of per-slice column-major rows x (2 ncols) matrices
 // (leading dimension rows, src_stride floats apart) into rows x ncols ones
 // (dst_stride floats apart): the complex Cholesky factor out of the real
@@ -792,6 +820,22 @@ hipError_t launch_dft_unstack(const float* W, const int* rep, const int* partner
   hipLaunchKernelGGL(k_dft_unstack, dim3((unsigned)tiles, (unsigned)npairs), dim3(256), 0, s, W, rep, partner, I1,
                      I2, (long long)I1 * I2, Re, Im, rankE, rank, sweepsE, sweeps, nuc ? nucE : nullptr, nuc,
                      twin ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_twin_columns(const float* U, long long u_stride, int rows2, int k, float* Bk, long long bk_stride,
+                               int nslices, hipStream_t s) {
+  if (nslices <= 0 || k <= 0) return hipSuccess;
+  const long long e = (long long)rows2 * k;
+  hipLaunchKernelGGL(k_twin_columns, dim3((unsigned)((e + 255) / 256), (unsigned)nslices), dim3(256), 0, s, U,
+                     u_stride, rows2, k, Bk, bk_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_pairs(const double* v, const int* rep, const int* partner, int npairs, int n, double* out,
+                               hipStream_t s) {
+  if (npairs <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_pairs, dim3((unsigned)npairs), dim3(256), 0, s, v, rep, partner, n, out);
   return hipGetLastError();
 }
 

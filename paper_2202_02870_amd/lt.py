@@ -261,7 +261,8 @@ def ltruncate(A, k, kinds=None, jacobi_tol=0.0, max_sweeps=0, precision="f32", o
 def multirank(A, kinds=None, rtol=1e-5, jacobi_tol=0.0, max_sweeps=0, precision="f32", ws=None):
     """lt_multirank: the rank of every slice of L(A) (singular values above rtol
     times the largest of the tensor) as an int32 CUDA tensor, the average rank
-    and the tubal rank (slices up to 256 columns, real transforms)."""
+    and the tubal rank (slices up to 256 columns; Fourier modes through the
+    complex Jacobi)."""
     shape = tuple(A.shape)
     _check_tensor(A, shape, name="A")
     d = make_desc(shape, kinds)

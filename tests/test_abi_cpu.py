@@ -71,7 +71,8 @@ def test_workspace_sizes_host_only():
     # matrices and columns (P = 4: 3 representatives), factors in two planes
     assert lt.workspace_bytes((8, 6, 4), ("dft",), "lsvd") >= 4 * (2 * 8 * 6 * 4 + 2 * 3 * 2 * 8 * 6
                                                                     + 2 * 4 * (8 * 6 + 6 * 6 + 6 * 6))
-    for op, prec in (("svt", "bf16x3"), ("lsvd", "bf16x3"), ("lsvd_full", "f32"), ("truncate", "f32")):
+    assert lt.workspace_bytes((8, 6, 4), ("dft",), "truncate") > lt.workspace_bytes((8, 6, 4), ("dft",), "lsvd")
+    for op, prec in (("svt", "bf16x3"), ("lsvd", "bf16x3"), ("lsvd_full", "f32"), ("truncate", "bf16x3")):
         with pytest.raises(ValueError):      # other operations and BF16 transforms: rejected
             lt.workspace_bytes((8, 8, 4), ("dft",), op, prec)
     # the product under the DFT: real and imaginary planes of A, B and C

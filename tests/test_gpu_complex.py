@@ -163,15 +163,57 @@ def test_lsvd_fourier_invariants(lt, shape, kinds):
         assert np.abs(sh - np.diag(sg)).max() < 2e-5 * sv.max()
 
 
+@pytest.mark.parametrize("shape,kinds", [((12, 9, 5), ("dft",)), ((9, 14, 4), ("dft",)),
+                                         ((20, 14, 4, 3), ("dft", "dct")), ((64, 48, 3), ("dft",))])
+def test_ltruncate_fourier_matches_oracle(lt, shape, kinds):
+    """Eckart-Young under the DFT: A_k against the oracle on a rank-3 signal
+    plus small noise, for k = 0, 3 and min(I1, I2); the error norm equals the
+    tail of the transform-domain singular values over sqrt(alpha), alpha = P
+    for the unnormalised Fourier matrix (Section 3.2)."""
+    rng = np.random.default_rng(sum(shape) + 11)
+    mats = o.mats_for(shape, list(kinds))
+    A = o.lproduct(rng.standard_normal((shape[0], 3) + shape[2:]),
+                   rng.standard_normal((3, shape[1]) + shape[2:]), mats).real
+    A = A + 0.01 * rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    alpha = o.transform_alpha(mats)
+    n = min(shape[0], shape[1])
+    for k in (0, 3, n):
+        Ak = lt.to_host(lt.ltruncate(lt.to_device(A), k, kinds)).astype(np.float64)
+        if k == 0:
+            assert np.abs(Ak).max() == 0.0
+            continue
+        parity.check(Ak, o.truncate(A, k, mats), 2e-5, label="%s k %d" % (shape, k))
+        tail = float(np.sqrt((s[:, k:] ** 2).sum() / alpha))
+        resid = float(np.linalg.norm(A - Ak))
+        say("  truncate dft", shape, "k", k, "residual", resid, "tail", tail)
+        assert abs(resid - tail) <= 1e-4 * np.linalg.norm(A) + 1e-3 * tail
+
+
+@pytest.mark.parametrize("shape,kinds", [((20, 16, 5), ("dft",)), ((12, 30, 4, 3), ("dft", "dct"))])
+def test_multirank_fourier_low_rank_product(lt, shape, kinds):
+    """The multirank of a rank-4 product under the DFT: 4 on every slice (the
+    partners of each conjugate pair included), as the oracle counts it."""
+    rng = np.random.default_rng(sum(shape) + 13)
+    mats = o.mats_for(shape, list(kinds))
+    A = o.lproduct(rng.standard_normal((shape[0], 4) + shape[2:]),
+                   rng.standard_normal((4, shape[1]) + shape[2:]), mats).real
+    rho, avg, tubal = lt.multirank(lt.to_device(A), kinds)
+    rho = lt.to_host(rho)
+    assert np.all(rho == 4) and avg == 4.0 and tubal == 4
+    assert np.array_equal(rho, o.multirank(A, mats, rtol=1e-5)[0])
+
+
 def test_pga_video_dft(lt):
     """Completion of the 144 x 176 x 3 x 50 video tensor under the DFT (the
-    t-product's TNN-PGA-F) through the complex path, 10 iterations of the
-    default schedule, against the oracle."""
+    t-product's TNN-PGA-F) through the preconditioned complex path, 30
+    iterations of the default schedule (the iterate's rank builds up from 0),
+    against the oracle."""
     import torch
     p = wl.make_problem((144, 176, 3, 50), 10, 0.3, seed=5, kinds=("dft", "dft"))
     assert lt.svt_path(p.shape, p.kinds) == "precond+complex"
     s = wl.pga_schedule_params(p.M, p.mask)
-    iters = 10
+    iters = 30
     params = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], max_iter=iters)
     X, rep, st = lt.complete_pga(lt.to_device(p.M), lt.to_device(p.mask, torch.uint8), params, p.kinds)
     Xo, _ = o.complete_pga(p.M, p.mask, o.mats_for(p.shape, list(p.kinds)), mu0=s["mu0"], nu=s["nu"],

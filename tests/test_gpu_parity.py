@@ -487,8 +487,8 @@ def test_error_paths(lt):
     A = lt.to_device(np.ones((8, 8, 4)))
     with pytest.raises(ValueError):                   # Fourier modes: economy factors only
         lt.lsvd(A, ("dft",), economy=False)
-    with pytest.raises(ValueError):                   # and no truncation
-        lt.ltruncate(A, 2, ("dft",))
+    with pytest.raises(lt.LtError):                   # in the spatial domain
+        lt.lsvd(A, ("dft",), transform_domain=True)
     with pytest.raises(ValueError):                   # and FP32 transforms only
         lt.lproduct(A, A, ("dft",), precision="bf16x3")
     with pytest.raises(ValueError):
