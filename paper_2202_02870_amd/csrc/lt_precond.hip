@@ -728,36 +728,39 @@ __global__ __launch_bounds__(256) void k_cholb_thr(const double* C, long long c_
     thr[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (64.0 * n * DBL_EPSILON);
 }
 
-// Diagonal block K..K+kb-1 of each slice factored in place (one wave per slice).
+// Diagonal block K..K+kb-1 of each slice factored in place, one wave per
+// slice with the block in registers: lane i holds row i (columns 0..i), so in
+// step k the pivot and the entries L(j, k) of the scaled column reach every lane
+// by readlane at indices fixed by the unrolled loops, and each lane updates its
+// own row (pivots as above).
 __global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride, int n, int K,
                                                   const double* thr) {
-  __shared__ double Dg[CG][CG + 1];
   double* Cs = C + (long long)blockIdx.x * c_stride;
   const int kb = min(CG, n - K);
   const int lane = threadIdx.x;
-  for (int e = lane; e < kb * kb; e += 64) {
-    const int i = e % kb, j = e / kb;
-    Dg[i][j] = i >= j ? Cs[(K + i) + (long long)(K + j) * n] : 0.0;
-  }
-  wave_sync();
+  double v[CG];
+#pragma unroll
+  for (int j = 0; j < CG; ++j)
+    v[j] = (lane < kb && j <= lane) ? Cs[(K + lane) + (long long)(K + j) * n] : 0.0;
   const double t = thr[blockIdx.x];
-  for (int k = 0; k < kb; ++k) {
-    const double piv = Dg[k][k];
-    const double inv = piv > t ? rsq64(piv) : 0.0;
-    if (lane > k && lane < kb) Dg[lane][k] *= inv;
-    wave_sync();
-    const int r = kb - 1 - k;
-    for (int e = lane; e < r * r; e += 64) {
-      const int ii = k + 1 + e / r, jj = k + 1 + e % r;
-      if (jj <= ii) Dg[ii][jj] = fma(-Dg[ii][k], Dg[jj][k], Dg[ii][jj]);
+#pragma unroll
+  for (int k = 0; k < CG; ++k) {
+    if (k < kb) {   // uniform
+      const double piv = readlane_d(v[k], k);
+      const double inv = piv > t ? rsq64(piv) : 0.0;
+      v[k] = lane == k ? piv * inv : v[k] * inv;   // rows above k hold 0 in column k
+#pragma unroll
+      for (int j = k + 1; j < CG; ++j) {
+        if (j < kb) {
+          const double ljk = readlane_d(v[k], j);
+          if (lane >= j) v[j] = fma(-v[k], ljk, v[j]);
+        }
+      }
     }
-    if (lane == 0) Dg[k][k] = piv * inv;
-    wave_sync();
   }
-  for (int e = lane; e < kb * kb; e += 64) {
-    const int i = e % kb, j = e / kb;
-    if (i >= j) Cs[(K + i) + (long long)(K + j) * n] = Dg[i][j];
-  }
+#pragma unroll
+  for (int j = 0; j < CG; ++j)
+    if (lane < kb && j <= lane) Cs[(K + lane) + (long long)(K + j) * n] = v[j];
 }
 
 // Panel rows K+kb .. n-1: x L11^T = C(row, K..K+kb-1), solved in place, one
