@@ -384,12 +384,13 @@ __host__ __device__ inline size_t slice_lds_bytes(int npairs, int ldw, int nbuf)
 constexpr size_t kWgCtlBytes = 16;   // workgroup-wide rotation counters
 
 // A lane's rotation count holds two counts: rotations in the low 16 bits and
-// large rotations (the pair's |a_i . a_j| / (|a_i| |a_j|) above sqrt(tol) / 2)
-// in the high 16.  Cyclic Jacobi converges quadratically, so after a sweep
-// whose rotations were all small the next sweep's would fall near tol: a slice
-// stops after such a sweep instead of running a last sweep that only checks.
+// large rotations (the pair's |a_i . a_j| / (|a_i| |a_j|) above sqrt(tol)) in
+// the high 16.  Cyclic Jacobi converges quadratically, so after a sweep whose
+// rotations all had cosines below sqrt(tol) the next sweep's would fall near
+// tol: a slice stops after such a sweep instead of running a last sweep that
+// only checks.
 constexpr unsigned kBigOne = 1u << 16;
-__device__ inline double big_rotation2(double tol) { return tol * 0.25; }
+__device__ inline double big_rotation2(double tol) { return tol; }
 
 // One workgroup's work: nsub slices of identical shape (I1 x I2), slice q at
 // src + q * stride; outputs likewise.
