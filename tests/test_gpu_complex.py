@@ -78,6 +78,48 @@ def test_svt_complex_matches_oracle(lt, shape, kinds, precondition):
         assert np.all(np.abs(rk - ref_rk) <= near)
 
 
+@pytest.mark.parametrize("shape,kinds", [((7, 1, 4), ("dft",)), ((1, 9, 3), ("dft",)), ((10, 8, 1), ("dft",)),
+                                         ((6, 5, 2, 1), ("dft", "dft"))])
+def test_svt_complex_degenerate_shapes(lt, shape, kinds):
+    """One-column slices (n = 1: nothing to precondition), a single row, and
+    trailing modes of size 1 (every slice its own conjugate) against the
+    oracle."""
+    rng = np.random.default_rng(sum(shape) + 3)
+    mats = o.mats_for(shape, list(kinds))
+    A = rng.standard_normal(shape)
+    s = o.singular_values(A, mats)
+    assert "complex" in lt.svt_path(shape, kinds)
+    for tau in (0.0, float(np.median(s))):
+        D, rank, _ = lt.svt_prox(lt.to_device(A), tau, kinds)
+        ref = o.svt(A, tau, mats)
+        say("degenerate complex", shape, "tau", tau, "ranks", lt.to_host(rank))
+        if np.linalg.norm(ref) > 0:
+            parity.check(lt.to_host(D), ref, 2e-5, label="%s tau %.3g" % (shape, tau))
+        near = (np.abs(s - tau) < 1e-4 * max(s.max(), 1e-30)).sum(axis=1)
+        assert np.all(np.abs(lt.to_host(rank) - np.asarray(o.svt_ranks(A, tau, mats))) <= near)
+
+
+def test_noalloc_fourier_equals_workspace_entry_point(lt):
+    """The entry point that allocates nothing runs the same complex kernels on
+    its static scratch: the same bits as lt_svt_prox, twice in a row (the
+    second call smaller)."""
+    import torch
+    rng = np.random.default_rng(510)
+    for shape, kinds in (((144, 176, 3, 6), ("dft", "dft")), ((40, 30, 5), ("dft",))):
+        assert lt.workspace_bytes(shape, kinds, "svt") <= lt.NOALLOC_SCRATCH_BYTES
+        A = rng.standard_normal(shape)
+        tau = float(np.median(o.singular_values(A, o.mats_for(shape, list(kinds)))))
+        Ad = lt.to_device(A)
+        D1, r1, _ = lt.svt_prox(Ad, tau, kinds)
+        D2 = lt.fortran_empty(shape)
+        P = int(np.prod(shape[2:]))
+        r2 = torch.empty(P, dtype=torch.int32, device="cuda")
+        assert lt.svt_prox_noalloc(Ad, tau, D2, r2, None, kinds) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(lt.to_host(D1), lt.to_host(D2))
+        assert np.array_equal(lt.to_host(r1), lt.to_host(r2))
+
+
 @pytest.mark.parametrize("shape,r", [((40, 30, 5), 7), ((20, 64, 4), 5), ((144, 176, 3, 2), 10)])
 def test_svt_complex_precond_rank_deficient(lt, shape, r):
     """Slices of exact rank r < n: singular Gram matrices in the complex
