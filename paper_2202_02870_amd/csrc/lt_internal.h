@@ -275,6 +275,12 @@ struct GramArgs {
   int I1, I2, nslices;
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
+// The Gram matrix (2n x 2n lower triangle, FP64, c_stride doubles per slice) of
+// the real form [w_1, i w_1, w_2, i w_2, ...] of complex m x n slices whose
+// columns w_a are interleaved (Re, Im) rows col_stride floats apart (slices
+// w_stride floats apart): the real form of W^H W.
+hipError_t launch_gram_cx(const float* W, long long w_stride, long long col_stride, int m, int n, double* C,
+                          long long c_stride, int nslices, hipStream_t s);
 
 struct CholArgs {
   double* C;               // in: Gram lower triangles; out: L (FP32 n x n) over each slice's region

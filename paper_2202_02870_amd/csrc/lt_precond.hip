@@ -88,6 +88,64 @@ __device__ __attribute__((always_inline)) void gram_tile(const float* W, int I1,
     }
 }
 
+// The Gram matrix of a complex slice's real form T = [w_1, i w_1, w_2, ...]
+// (complex columns w_a of m entries held as interleaved (Re, Im) rows,
+// col_stride floats apart): its 2 x 2 blocks are [[Re g, -Im g], [Im g, Re g]]
+// with g = w_a^H w_b, so one complex product per block (half the multiply-adds
+// of the real Gram of T).  One 16 x 16 tile of complex products (lower, ti >=
+// tj, index t) per workgroup, one product per lane, FP64 from the exact FP32
+// products; C is the 2n x 2n lower triangle.
+constexpr int GTC = 16;
+__device__ __attribute__((always_inline)) void gram_tile_cx(const float* W, long long col_stride, int m, int n,
+                                                             double* C, int t) {
+  __shared__ double Ar[GT][GTC + 1], Ai[GT][GTC + 1], Br[GT][GTC + 1], Bi[GT][GTC + 1];
+  int ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double re = 0.0, im = 0.0;
+  for (int k0 = 0; k0 < m; k0 += GT) {
+    for (int idx = tid; idx < GT * GTC; idx += 256) {   // row kk of columns c: both parts contiguous
+      const int kk = idx % GT, c = idx / GT;
+      const int row = k0 + kk, ca = ti * GTC + c, cb = tj * GTC + c;
+      const bool ina = row < m && ca < n, inb = row < m && cb < n;
+      const float2 va = ina ? *reinterpret_cast<const float2*>(W + ca * col_stride + 2LL * row) : make_float2(0.f, 0.f);
+      const float2 vb = inb ? *reinterpret_cast<const float2*>(W + cb * col_stride + 2LL * row) : make_float2(0.f, 0.f);
+      Ar[kk][c] = va.x;
+      Ai[kk][c] = va.y;
+      Br[kk][c] = vb.x;
+      Bi[kk][c] = vb.y;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GT; ++kk) {
+      const double ar = Ar[kk][tx], ai = Ai[kk][tx], br = Br[kk][ty], bi = Bi[kk][ty];
+      re = fma(ar, br, re);
+      im = fma(ai, br, im);
+      re = fma(ai, bi, re);
+      im = fma(-ar, bi, im);
+    }
+    __syncthreads();
+  }
+  // g = w_b^H w_a for row a, column b of the complex Gram: Re = re, Im = -im
+  // (im sums Im a Re b - Re a Im b); real form rows 2a, 2a + 1, columns 2b, 2b + 1
+  const int a = ti * GTC + tx, b = tj * GTC + ty;
+  if (a < n && b < n && a >= b) {
+    const long long n2 = 2LL * n;
+    const double gi = -im;   // Im of the (a, b) entry of W^H W: sum conj(w_a) w_b
+    C[(2 * a) + (2 * b) * n2] = re;
+    C[(2 * a + 1) + (2 * b) * n2] = gi;
+    C[(2 * a + 1) + (2 * b + 1) * n2] = re;
+    if (a > b) C[(2 * a) + (2 * b + 1) * n2] = -gi;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gram_cx(const float* W, long long w_stride, long long col_stride, int m,
+                                                 int n, double* C, long long c_stride) {
+  const int s = blockIdx.y;
+  gram_tile_cx(W + (long long)s * w_stride, col_stride, m, n, C + (long long)s * c_stride, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
   const int s = blockIdx.y;
   gram_tile(a.W + (long long)s * a.slice_stride, a.I1, a.I2, a.C + (long long)s * a.c_stride, blockIdx.x);
@@ -893,6 +951,16 @@ hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, fl
 // kernel's up to CT_NMAX, the packed triangle's beyond.
 size_t chol_lds_bytes(int n) {
   return n <= CT_NMAX ? ct_lds_bytes(n) : (size_t)n * (n + 1) / 2 * sizeof(double);
+}
+
+hipError_t launch_gram_cx(const float* W, long long w_stride, long long col_stride, int m, int n, double* C,
+                          long long c_stride, int nslices, hipStream_t s) {
+  if (nslices <= 0) return hipSuccess;
+  if (m < 1 || n < 1 || c_stride < 4LL * n * n) return hipErrorInvalidValue;
+  const int nt = (n + GTC - 1) / GTC;
+  hipLaunchKernelGGL(k_gram_cx, dim3(nt * (nt + 1) / 2, nslices), dim3(256), 0, s, W, w_stride, col_stride, m, n, C,
+                     c_stride);
+  return hipGetLastError();
 }
 
 hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
