@@ -517,7 +517,7 @@ def leg_mix(args, torch, lt, wl):
     a.steps, a.warmup, a.precision, a.per_request_iters, a.lanes = 30, 5, "bf16x3", 3, "auto"
     r = bench_mix(a, torch, lt, wl)
     keep = ("value", "unit", "slice_svt_per_s", "per_request_f32_slice_svt_per_s", "batched_over_per_request",
-            "mean_sweeps", "jacobi_lanes", "config")
+            "batched_f32_slice_svt_per_s", "batched_over_batched_f32", "mean_sweeps", "jacobi_lanes", "config")
     return {k: r[k] for k in keep}
 
 
@@ -574,6 +574,25 @@ def bench_mix(args, torch, lt, wl):
     prof, _ = lt.profile_end()
     b2.close()
     del gps2
+    # the same batch with FP32 transforms: what the BF16x3 split itself buys
+    batched_f32 = None
+    if args.precision != "f32":
+        gps3 = []
+        for (p, M, mask, params) in dev:
+            s = p.schedule
+            pf = lt.pga_params(mu0=s["mu0"], nu=s["nu"], mu_bar=s["mu_bar"], tol=0.0,
+                               max_iter=args.steps + args.warmup, precision="f32")
+            gps3.append(lt.Problem(M, mask, pf, p.kinds))
+        b3 = lt.Batch(gps3, use_graph=True, jacobi_lanes=lanes)
+        if args.warmup > 0:
+            b3.step(args.warmup)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        b3.step(args.steps)
+        torch.cuda.synchronize()
+        batched_f32 = args.steps * total_slices / (time.perf_counter() - f0)
+        b3.close()
+        del gps3
     # plain FP32 per-request form: one problem after another, the same first iterations
     k = args.per_request_iters
     torch.cuda.synchronize()
@@ -604,6 +623,8 @@ def bench_mix(args, torch, lt, wl):
         "slice_svt_per_s": round(value * total_slices, 1),
         "per_request_f32_slice_svt_per_s": round(per_req_slices, 1),
         "batched_over_per_request": round(value * total_slices / per_req_slices, 3),
+        "batched_f32_slice_svt_per_s": round(batched_f32, 1) if batched_f32 else None,
+        "batched_over_batched_f32": round(value * total_slices / batched_f32, 3) if batched_f32 else None,
         "mean_sweeps": round(sum(r["total_sweeps"] for r in reps) / max(sum(r["total_slices"] for r in reps), 1), 3),
         "kernel_ms_20_eager_ticks": {k2: round(v[1], 3) for k2, v in prof.items()},
         "jacobi_lanes": lanes if lanes else "built-in",
