@@ -979,11 +979,12 @@ bool dft_complex(const Shape& s, bool precond_req, int max_lds, lt::JacobiConfig
   return lt::jacobi_cx_config(2 * (int)m, (int)n, max_lds, cc) == 0;
 }
 
-// The complex path: the representatives' working matrices (2 N floats each)
-// into the embedding buffer, the Hermitian Jacobi (each kept column written
-// with its product by i: up to 2 n columns, 4 N floats per representative in
-// the embedding's Bk), the real rebuild over the interleaved rows in place, and
-// the results back to the planes.
+// The complex path: the representatives' working matrices (2 N floats each,
+// or their twinned real forms, 4 N, when preconditioned) into the embedding
+// buffer, the preconditioner (above), the Hermitian Jacobi (each kept column
+// written with its product by i: up to 2 n columns, 4 N floats per
+// representative in the embedding's Bk), the real rebuild over the interleaved
+// rows in place, and the results back to the planes.
 int run_cx_svt(lt_handle* h, const Shape& s, const SvtWs& w, const lt::JacobiConfig& cc, bool pc, double tau,
                double tol, int max_sweeps, int32_t* rank, int32_t* sweeps, unsigned long long* sweep_total,
                unsigned long long* rot_total, unsigned int* hits) {
