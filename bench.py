@@ -46,6 +46,7 @@ PEAK_HBM = 8.0e12
 
 JACOBI_SRC = os.path.join(ROOT, "paper_2202_02870_amd", "csrc", "lt_jacobi.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_jacobi_warm_video_144x176x3x50.md")
+TRAFFIC_PROFILE_DFT = os.path.join(ROOT, "profiles", "k_jacobi_cx_video_dft_144x176x3x50.md")
 
 
 def svt_time_at_peak(m, n, sweeps_total):
@@ -117,12 +118,13 @@ def cpu_model():
     return "unknown"
 
 
-def measured_traffic():
-    """HBM bytes per k_jacobi_warm launch on the default video workload from the
-    committed FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
-    kernel source (its SHA-256 is recorded there), else None."""
+def measured_traffic(profile=TRAFFIC_PROFILE):
+    """HBM bytes per Jacobi launch on the video workload (k_jacobi_warm; with the
+    DFT, the complex k_jacobi) from the committed FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken on the current kernel source (its SHA-256 is
+    recorded there), else None."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(profile).read()
         src = hashlib.sha256(open(JACOBI_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -336,11 +338,14 @@ def bench_completion(args, torch, lt, wl):
     slowest = rep["slowest_sweeps"] / max(rep["iters"], 1)
     default_cfg = (args.workload == "video" and args.transform == "dct" and args.precision == "f32" and precond
                    and warm and not args.fp32_dots)
+    dft_cfg = (args.workload == "video" and args.transform == "dft" and args.precision == "f32" and precond
+               and cx and not args.fp32_dots)
     roofline = {"bound": "alu", "kernel": "k_jacobi_warm" if warm else "k_jacobi",
                 "achieved": round(flops / t_launch / 1e12, 3) if t_launch > 0 else None,
                 "peak": round(flops / t_peak / 1e12, 2) if t_peak > 0 else None, "unit": "TFLOP/s",
                 "frac": round(t_peak / t_launch, 4) if t_launch > 0 else None,
-                "traffic": measured_traffic() if default_cfg else None,
+                "traffic": (measured_traffic() if default_cfg else
+                            measured_traffic(TRAFFIC_PROFILE_DFT) if dft_cfg else None),
                 "count": ("per sweep of a complex m x n slice: n(n-1)/2 pairs x (16m FP64 + 18(m+n) FP32) flops"
                           if cx else
                           "per sweep of an m x n slice: n(n-1)/2 pairs x (6m FP64 + 6m+6n FP32) flops")
@@ -500,6 +505,8 @@ def leg_dft(args, torch, lt, wl, dct_ms=None):
                         "svt_path": lt.svt_path(p.shape, p.kinds),
                         "mean_sweeps": round(rep["total_sweeps"] / max(rep["total_slices"], 1), 3),
                         "jacobi_ms_per_iter": round(prof["jacobi"][1] / max(prof["jacobi"][0], 1), 4)}
+            if not embed:   # HBM bytes per complex Jacobi launch, from the committed counters
+                out[key]["jacobi_traffic"] = measured_traffic(TRAFFIC_PROFILE_DFT)
         finally:
             if embed:
                 del os.environ["LT_DFT_EMBED"]
