@@ -790,35 +790,47 @@ __global__ __launch_bounds__(256) void k_cholb_thr(const double* C, long long c_
 // slice with the block in registers: lane i holds row i (columns 0..i), so in
 // step k the pivot and the entries L(j, k) of the scaled column reach every lane
 // by readlane at indices fixed by the unrolled loops, and each lane updates its
-// own row (pivots as above).
+// own row (pivots as above).  A short last block is padded to CG columns with a
+// diagonal above the threshold and zero coupling, and each step masks column k
+// to the rows below the pivot once, so the steps run without branches: every
+// lane applies every update, which changes only entries above the diagonal
+// (never read, never stored); the entries of the factor see the same operations
+// in the same order as with per-entry guards.
 __global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride, int n, int K,
                                                   const double* thr) {
   double* Cs = C + (long long)blockIdx.x * c_stride;
   const int kb = min(CG, n - K);
   const int lane = threadIdx.x;
+  const double t = thr[blockIdx.x];
+  const double pad = 1.0 + 2.0 * t;   // > t (t >= 0): padded pivots keep their column
+  const int lr = min(lane, kb - 1);   // clamped: every lane loads in bounds
   double v[CG];
 #pragma unroll
-  for (int j = 0; j < CG; ++j)
-    v[j] = (lane < kb && j <= lane) ? Cs[(K + lane) + (long long)(K + j) * n] : 0.0;
-  const double t = thr[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < CG; ++k) {
-    if (k < kb) {   // uniform
-      const double piv = readlane_d(v[k], k);
-      const double inv = piv > t ? rsq64(piv) : 0.0;
-      v[k] = lane == k ? piv * inv : v[k] * inv;   // rows above k hold 0 in column k
-#pragma unroll
-      for (int j = k + 1; j < CG; ++j) {
-        if (j < kb) {
-          const double ljk = readlane_d(v[k], j);
-          if (lane >= j) v[j] = fma(-v[k], ljk, v[j]);
-        }
-      }
-    }
+  for (int j = 0; j < CG; ++j) {
+    const double x = Cs[(K + lr) + (long long)(K + min(j, kb - 1)) * n];
+    v[j] = (lane < kb && j <= lane) ? x : (lane == j ? pad : 0.0);
   }
 #pragma unroll
+  for (int k = 0; k < CG; ++k) {
+    const double piv = readlane_d(v[k], k);
+    const double inv = piv > t ? rsq64(piv) : 0.0;
+    v[k] = lane == k ? piv * inv : v[k] * inv;
+    const double vk = lane > k ? v[k] : 0.0;   // L(lane, k) below the pivot
+#pragma unroll
+    for (int j = k + 1; j < CG; ++j) {
+      v[j] = fma(-vk, readlane_d(v[k], j), v[j]);
+      // keeps the broadcast L(j, k) values from being hoisted en masse (they
+      // would spill out of the scalar registers)
+      if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // fresh copies of n and K: the stores' column offsets are recomputed here
+  // rather than kept in scalar registers from the loads through the steps
+  int ns = n, Ks = K;
+  asm volatile("" : "+s"(ns), "+s"(Ks));
+#pragma unroll
   for (int j = 0; j < CG; ++j)
-    if (lane < kb && j <= lane) Cs[(K + lane) + (long long)(K + j) * n] = v[j];
+    if (lane < kb && j <= lane) Cs[(Ks + lane) + (long long)(Ks + j) * ns] = v[j];
 }
 
 // Panel rows K+kb .. n-1: x L11^T = C(row, K..K+kb-1), solved in place, one
