@@ -89,61 +89,75 @@ __device__ __attribute__((always_inline)) void gram_tile(const float* W, int I1,
 }
 
 // The Gram matrix of a complex slice's real form T = [w_1, i w_1, w_2, ...]
-// (complex columns w_a of m entries held as interleaved (Re, Im) rows,
+// (complex columns w_a of m entries held as 2m interleaved (Re, Im) rows,
 // col_stride floats apart): its 2 x 2 blocks are [[Re g, -Im g], [Im g, Re g]]
 // with g = w_a^H w_b, so one complex product per block (half the multiply-adds
-// of the real Gram of T).  One 16 x 16 tile of complex products (lower, ti >=
-// tj, index t) per workgroup, one product per lane, FP64 from the exact FP32
-// products; C is the 2n x 2n lower triangle.
-constexpr int GTC = 16;
-__device__ __attribute__((always_inline)) void gram_tile_cx(const float* W, long long col_stride, int m, int n,
-                                                             double* C, int t) {
-  __shared__ double Ar[GT][GTC + 1], Ai[GT][GTC + 1], Br[GT][GTC + 1], Bi[GT][GTC + 1];
-  int ti = 0;
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  const int tj = t - ti * (ti + 1) / 2;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double re = 0.0, im = 0.0;
-  for (int k0 = 0; k0 < m; k0 += GT) {
-    for (int idx = tid; idx < GT * GTC; idx += 256) {   // row kk of columns c: both parts contiguous
-      const int kk = idx % GT, c = idx / GT;
-      const int row = k0 + kk, ca = ti * GTC + c, cb = tj * GTC + c;
-      const bool ina = row < m && ca < n, inb = row < m && cb < n;
-      const float2 va = ina ? *reinterpret_cast<const float2*>(W + ca * col_stride + 2LL * row) : make_float2(0.f, 0.f);
-      const float2 vb = inb ? *reinterpret_cast<const float2*>(W + cb * col_stride + 2LL * row) : make_float2(0.f, 0.f);
-      Ar[kk][c] = va.x;
-      Ai[kk][c] = va.y;
-      Br[kk][c] = vb.x;
-      Bi[kk][c] = vb.y;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < GT; ++kk) {
-      const double ar = Ar[kk][tx], ai = Ai[kk][tx], br = Br[kk][ty], bi = Bi[kk][ty];
-      re = fma(ar, br, re);
-      im = fma(ai, br, im);
-      re = fma(ai, bi, re);
-      im = fma(-ar, bi, im);
-    }
-    __syncthreads();
-  }
-  // g = w_b^H w_a for row a, column b of the complex Gram: Re = re, Im = -im
-  // (im sums Im a Re b - Re a Im b); real form rows 2a, 2a + 1, columns 2b, 2b + 1
-  const int a = ti * GTC + tx, b = tj * GTC + ty;
-  if (a < n && b < n && a >= b) {
-    const long long n2 = 2LL * n;
-    const double gi = -im;   // Im of the (a, b) entry of W^H W: sum conj(w_a) w_b
-    C[(2 * a) + (2 * b) * n2] = re;
-    C[(2 * a + 1) + (2 * b) * n2] = gi;
-    C[(2 * a + 1) + (2 * b + 1) * n2] = re;
-    if (a > b) C[(2 * a) + (2 * b + 1) * n2] = -gi;
-  }
-}
+// of the real Gram of T).  Over the interleaved rows Re g is the real dot of
+// the two columns and Im g the real dot of w_a with J w_b, where J maps each
+// (Re, Im) pair (x, y) to (y, -x).  One 32 x 32 tile of complex products
+// (lower, ta >= tb, index blockIdx.x) per workgroup of four waves, each wave a
+// 16 x 16 quarter on FP64 MFMA with two accumulators (Re g, Im g), the columns
+// staged through LDS 64 interleaved rows at a time; the FP32 entries are exact
+// in FP64, the products and sums are FP64.  C is the 2n x 2n lower triangle.
+typedef double ct_v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GCX = 32;     // complex columns per tile side
+constexpr int GCX_K = 64;   // interleaved rows per LDS chunk (even: pairs stay whole)
 
 __global__ __launch_bounds__(256) void k_gram_cx(const float* W, long long w_stride, long long col_stride, int m,
                                                  int n, double* C, long long c_stride) {
-  const int s = blockIdx.y;
-  gram_tile_cx(W + (long long)s * w_stride, col_stride, m, n, C + (long long)s * c_stride, blockIdx.x);
+  __shared__ float As[GCX_K][GCX + 1], Bs[GCX_K][GCX + 1];
+  const float* Ws = W + (long long)blockIdx.y * w_stride;
+  double* Cs = C + (long long)blockIdx.y * c_stride;
+  const int t = blockIdx.x;
+  int ta = 0;
+  while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+  const int tb = t - ta * (ta + 1) / 2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int wa = wave & 1, wb = wave >> 1;
+  const int a0 = GCX * ta, b0 = GCX * tb;
+  const bool live = !(ta == tb && wa < wb);   // a quarter wholly above the diagonal skips the products
+  const int rows = 2 * m;
+  // MFMA 16x16x4: lane l gives A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+  // D[l / 16 + 4 q][l % 16]; A from the b columns (w_b, or J w_b: the row's
+  // pair partner, negated on odd rows), B from the a columns, so lane l holds
+  // the products of column a = a0 + 16 wa + l % 16 with b = b0 + 16 wb + l / 16 + 4 q
+  const double sgn = (lq & 1) ? -1.0 : 1.0;
+  ct_v4d re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < rows; k0 += GCX_K) {
+    for (int e = tid; e < GCX_K * GCX; e += 256) {   // consecutive lanes: consecutive rows of a column
+      const int r = e % GCX_K, c = e / GCX_K;
+      const int row = k0 + r, ca = a0 + c, cb = b0 + c;
+      As[r][c] = (row < rows && ca < n) ? Ws[ca * col_stride + row] : 0.f;
+      Bs[r][c] = (row < rows && cb < n) ? Ws[cb * col_stride + row] : 0.f;
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < GCX_K; kk += 4) {
+        const double x = Bs[kk + lq][16 * wb + lr];
+        const double xj = sgn * (double)Bs[kk + (lq ^ 1)][16 * wb + lr];
+        const double y = As[kk + lq][16 * wa + lr];
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(xj, y, im, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  const long long n2 = 2LL * n;
+  const int a = a0 + 16 * wa + lr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = b0 + 16 * wb + lq + 4 * q;
+    if (a < n && b < n && a >= b) {   // real form rows 2a, 2a + 1, columns 2b, 2b + 1 (lower part)
+      Cs[(2 * a) + (2 * b) * n2] = re[q];
+      Cs[(2 * a + 1) + (2 * b) * n2] = im[q];
+      Cs[(2 * a + 1) + (2 * b + 1) * n2] = re[q];
+      if (a > b) Cs[(2 * a) + (2 * b + 1) * n2] = -im[q];
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
@@ -336,7 +350,6 @@ __device__ inline double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-typedef double ct_v4d __attribute__((ext_vector_type(4)));
 
 // Lane k of each 16-lane row to the whole row (DPP row_newbcast), FP64.
 template <int K>
@@ -969,7 +982,7 @@ hipError_t launch_gram_cx(const float* W, long long w_stride, long long col_stri
                           long long c_stride, int nslices, hipStream_t s) {
   if (nslices <= 0) return hipSuccess;
   if (m < 1 || n < 1 || c_stride < 4LL * n * n) return hipErrorInvalidValue;
-  const int nt = (n + GTC - 1) / GTC;
+  const int nt = (n + GCX - 1) / GCX;
   hipLaunchKernelGGL(k_gram_cx, dim3(nt * (nt + 1) / 2, nslices), dim3(256), 0, s, W, w_stride, col_stride, m, n, C,
                      c_stride);
   return hipGetLastError();

@@ -9,6 +9,9 @@ each column w with i w.  Pinned here:
   * with B' = [b_1, i b_1, ...] (columns twinned), B' B'^T applied to the
     interleaved W gives the interleaved B B^H W, and (T B') B'^T has the
     interleaved (W B) B^H as its even columns;
+  * over the interleaved rows, Re(w_a^H w_b) is the real dot of the columns
+    and Im(w_a^H w_b) the real dot of w_a with J w_b, J mapping each (Re, Im)
+    pair (x, y) to (y, -x): the row's pair partner, negated on odd rows;
   * the Hermitian rotation (phase of a^H b, then the real rotation with
     zeta = (|b|^2 - |a|^2) / (2 |a^H b|)) leaves the pair orthogonal.
 """
@@ -72,6 +75,21 @@ def test_twinned_gram_is_the_real_form_of_the_complex_gram():
     g = W[:, a].conj() @ W[:, b]
     blk = (T.T @ T)[2 * a:2 * a + 2, 2 * b:2 * b + 2]
     assert np.allclose(blk, [[g.real, -g.imag], [g.imag, g.real]])
+
+
+def test_complex_gram_from_two_real_dots():
+    rng = np.random.default_rng(5)
+    W = _rand(rng, 23, 9)
+    Wi = interleave(W)
+    JW = np.empty_like(Wi)
+    k = np.arange(Wi.shape[0])
+    sign = np.where(k % 2 == 1, -1.0, 1.0)
+    JW[:] = sign[:, None] * Wi[k ^ 1]                 # partner row, odd rows negated
+    G = W.conj().T @ W                                # G[a, b] = w_a^H w_b
+    assert np.allclose(Wi.T @ Wi, G.real)
+    assert np.allclose(Wi.T @ JW, G.imag)
+    # with G[a, b] in rows 2a, 2a + 1 and columns 2b, 2b + 1 of the real form
+    assert np.allclose(real_form(G), twin(Wi).T @ twin(Wi))
 
 
 def test_real_cholesky_of_the_twinned_gram_is_the_real_form_of_the_complex_factor():
