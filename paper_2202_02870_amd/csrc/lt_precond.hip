@@ -799,22 +799,21 @@ __global__ __launch_bounds__(256) void k_cholb_thr(const double* C, long long c_
     thr[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * (64.0 * n * DBL_EPSILON);
 }
 
-// Diagonal block K..K+kb-1 of each slice factored in place, one wave per
-// slice with the block in registers: lane i holds row i (columns 0..i), so in
-// step k the pivot and the entries L(j, k) of the scaled column reach every lane
-// by readlane at indices fixed by the unrolled loops, and each lane updates its
-// own row (pivots as above).  A short last block is padded to CG columns with a
+// Diagonal block K..K+kb-1 of one slice factored in place by one wave, the
+// block in registers: lane i holds row i (columns 0..i), so in step k the pivot
+// and the entries L(j, k) of the scaled column reach every lane by readlane at
+// indices fixed by the unrolled loops, and each lane updates its own row
+// (pivots as above).  A short last block is padded to CG columns with a
 // diagonal above the threshold and zero coupling, and each step masks column k
 // to the rows below the pivot once, so the steps run without branches: every
 // lane applies every update, which changes only entries above the diagonal
 // (never read, never stored); the entries of the factor see the same operations
-// in the same order as with per-entry guards.
-__global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride, int n, int K,
-                                                  const double* thr) {
-  double* Cs = C + (long long)blockIdx.x * c_stride;
+// in the same order as with per-entry guards.  With Dg, the factored block
+// (zero above the diagonal) is also left in LDS for a panel solve.
+__device__ __attribute__((always_inline)) void cholb_diag_wave(double* Cs, int n, int K, double t,
+                                                               double (*Dg)[CG + 1]) {
   const int kb = min(CG, n - K);
-  const int lane = threadIdx.x;
-  const double t = thr[blockIdx.x];
+  const int lane = threadIdx.x & 63;
   const double pad = 1.0 + 2.0 * t;   // > t (t >= 0): padded pivots keep their column
   const int lr = min(lane, kb - 1);   // clamped: every lane loads in bounds
   double v[CG];
@@ -844,10 +843,47 @@ __global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride
 #pragma unroll
   for (int j = 0; j < CG; ++j)
     if (lane < kb && j <= lane) Cs[(Ks + lane) + (long long)(Ks + j) * ns] = v[j];
+  if (Dg && lane < kb) {
+#pragma unroll
+    for (int j = 0; j < CG; ++j)
+      if (j < kb) Dg[lane][j] = j <= lane ? v[j] : 0.0;
+  }
 }
 
-// Panel rows K+kb .. n-1: x L11^T = C(row, K..K+kb-1), solved in place, one
-// lane per row.
+// Row i of the panel below the diagonal block: x L11^T = C(i, K..K+kb-1),
+// solved in place against the factored block Dg and its reciprocal pivots
+// (loaded first, solved and stored second).
+__device__ __attribute__((always_inline)) void cholb_panel_load(const double* Cs, int n, int K, int kb, int i,
+                                                                double (&x)[CG]) {
+#pragma unroll
+  for (int q = 0; q < CG; ++q) x[q] = q < kb ? Cs[i + (long long)(K + q) * n] : 0.0;
+}
+
+__device__ __attribute__((always_inline)) void cholb_panel_solve(double* Cs, int n, int K, int kb, int i,
+                                                                 const double (*Dg)[CG + 1], const double* dinv,
+                                                                 double (&x)[CG]) {
+#pragma unroll
+  for (int q = 0; q < CG; ++q) {
+    if (q < kb) {
+      double acc = x[q];
+#pragma unroll
+      for (int p2 = 0; p2 < CG; ++p2)
+        if (p2 < q) acc = fma(-x[p2], Dg[q][p2], acc);
+      x[q] = acc * dinv[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CG; ++q)
+    if (q < kb) Cs[i + (long long)(K + q) * n] = x[q];
+}
+
+__global__ __launch_bounds__(64) void k_cholb_diag(double* C, long long c_stride, int n, int K,
+                                                  const double* thr) {
+  cholb_diag_wave(C + (long long)blockIdx.x * c_stride, n, K, thr[blockIdx.x], nullptr);
+}
+
+// Panel rows K+kb .. n-1, one lane per row, against the block factored by
+// k_cholb_diag (read back from C).
 __global__ __launch_bounds__(256) void k_cholb_panel(double* C, long long c_stride, int n, int K) {
   __shared__ double Dg[CG][CG + 1];
   __shared__ double dinv[CG];
@@ -864,23 +900,39 @@ __global__ __launch_bounds__(256) void k_cholb_panel(double* C, long long c_stri
   }
   __syncthreads();
   const int i = K + kb + blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double x[CG];
-#pragma unroll
-  for (int q = 0; q < CG; ++q) x[q] = q < kb ? Cs[i + (long long)(K + q) * n] : 0.0;
-#pragma unroll
-  for (int q = 0; q < CG; ++q) {
-    if (q < kb) {
-      double acc = x[q];
-#pragma unroll
-      for (int p2 = 0; p2 < CG; ++p2)
-        if (p2 < q) acc = fma(-x[p2], Dg[q][p2], acc);
-      x[q] = acc * dinv[q];
-    }
+  if (i < n) {
+    double x[CG];
+    cholb_panel_load(Cs, n, K, kb, i, x);
+    cholb_panel_solve(Cs, n, K, kb, i, Dg, dinv, x);
   }
-#pragma unroll
-  for (int q = 0; q < CG; ++q)
-    if (q < kb) Cs[i + (long long)(K + q) * n] = x[q];
+}
+
+// Both in one launch when the panel is short: wave 0 factors the block into C
+// and LDS while the other waves, one panel row per lane, load their rows; then
+// they solve them.  This saves a launch and a read of the block per step and
+// overlaps the row loads with the factorization; the same arithmetic as the
+// two kernels above.
+constexpr int CHOLB_FUSED_ROWS = 256;   // panel rows up to which the step is fused
+
+__global__ __launch_bounds__(64 + CHOLB_FUSED_ROWS) void k_cholb_diag_panel(double* C, long long c_stride, int n,
+                                                                            int K, const double* thr) {
+  __shared__ double Dg[CG][CG + 1];
+  __shared__ double dinv[CG];
+  double* Cs = C + (long long)blockIdx.x * c_stride;
+  const int kb = min(CG, n - K);
+  const int tid = threadIdx.x;
+  const int i = K + kb + tid - 64;
+  const bool prow = tid >= 64 && i < n;
+  double x[CG];
+  if (tid < 64) cholb_diag_wave(Cs, n, K, thr[blockIdx.x], Dg);
+  else if (prow) cholb_panel_load(Cs, n, K, kb, i, x);
+  __syncthreads();
+  if (tid < kb) {
+    const double d = Dg[tid][tid];
+    dinv[tid] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+  __syncthreads();
+  if (prow) cholb_panel_solve(Cs, n, K, kb, i, Dg, dinv, x);
 }
 
 // Trailing update C(i, j) -= sum_q P(i, q) P(j, q) over the trailing lower
@@ -955,11 +1007,17 @@ hipError_t launch_chol_big(double* C, long long c_stride, int n, int nslices, fl
   for (int K = 0; K < n && e == hipSuccess; K += CG) {
     const int kb = n - K < CG ? n - K : CG;
     const int t = n - K - kb;
-    hipLaunchKernelGGL(k_cholb_diag, dim3(nslices), dim3(64), 0, s, C, c_stride, n, K, thr);
-    if ((e = hipGetLastError()) != hipSuccess) break;
-    if (t <= 0) break;
-    hipLaunchKernelGGL(k_cholb_panel, dim3((t + 255) / 256, nslices), dim3(256), 0, s, C, c_stride, n, K);
-    if ((e = hipGetLastError()) != hipSuccess) break;
+    if (t <= CHOLB_FUSED_ROWS) {
+      hipLaunchKernelGGL(k_cholb_diag_panel, dim3(nslices), dim3(64 + CHOLB_FUSED_ROWS), 0, s, C, c_stride, n, K,
+                         thr);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      if (t <= 0) break;
+    } else {
+      hipLaunchKernelGGL(k_cholb_diag, dim3(nslices), dim3(64), 0, s, C, c_stride, n, K, thr);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+      hipLaunchKernelGGL(k_cholb_panel, dim3((t + 255) / 256, nslices), dim3(256), 0, s, C, c_stride, n, K);
+      if ((e = hipGetLastError()) != hipSuccess) break;
+    }
     const int T64 = (t + 63) / 64;
     hipLaunchKernelGGL(k_cholb_update, dim3(T64 * (T64 + 1) / 2, nslices), dim3(256), 0, s, C, c_stride, n, K);
     e = hipGetLastError();
