@@ -35,57 +35,63 @@ __device__ inline float w_elem(const float* W, bool trans, int I1, int row, int 
   return trans ? W[(long long)row * I1 + col] : W[(long long)col * I1 + row];
 }
 
-constexpr int GT = 32;   // Gram output tile (GT x GT), rows of W per LDS chunk
+constexpr int GT = 32;   // Gram output tile (GT x GT)
+
+typedef double ct_v4d __attribute__((ext_vector_type(4)));
 
 // C (lower triangle, n x n column-major FP64) = W^T W for one slice: one
-// lower-triangle tile pair (ti >= tj, index t) per workgroup; 256 lanes, 2 x 2
-// outputs each.
+// lower-triangle GT x GT tile (ti >= tj, index t) per workgroup of four waves,
+// each wave a 16 x 16 quarter on FP64 MFMA (the FP32 entries of W are exact in
+// FP64, the products and sums are FP64), W staged through LDS GK rows at a
+// time, coalesced along whichever dimension W keeps contiguous.
+constexpr int GK = 64;   // rows of W per LDS chunk
 __device__ __attribute__((always_inline)) void gram_tile(const float* W, int I1, int I2, double* C, int t) {
-  __shared__ double Ai[GT][GT + 1];
-  __shared__ double Aj[GT][GT + 1];
+  __shared__ float Ai[GK][GT + 1];
+  __shared__ float Aj[GK][GT + 1];
   int ti = 0;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int tj = t - ti * (ti + 1) / 2;
   const bool trans = I1 < I2;
   const int m = trans ? I2 : I1;
   const int n = trans ? I1 : I2;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
-  for (int k0 = 0; k0 < m; k0 += GT) {
-    for (int idx = tid; idx < GT * GT; idx += 256) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int wa = wave & 1, wb = wave >> 1;
+  const bool live = !(ti == tj && wa < wb);   // a quarter wholly above the diagonal skips the products
+  // MFMA 16x16x4: lane l gives A[l % 16][l / 16] (from the tj columns) and
+  // B[l / 16][l % 16] (from the ti columns) and holds D[l / 16 + 4 q][l % 16]:
+  // C(i, j) with i = GT ti + 16 wa + l % 16, j = GT tj + 16 wb + l / 16 + 4 q
+  ct_v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < m; k0 += GK) {
+    for (int idx = tid; idx < GK * GT; idx += 256) {
       int kk, c;
       if (trans) {   // W(row, col) = A[row * I1 + col]: columns contiguous
         c = idx % GT;
         kk = idx / GT;
       } else {       // W(row, col) = A[col * I1 + row]: rows contiguous
-        kk = idx % GT;
-        c = idx / GT;
+        kk = idx % GK;
+        c = idx / GK;
       }
       const int row = k0 + kk, ci = ti * GT + c, cj = tj * GT + c;
-      Ai[kk][c] = (row < m && ci < n) ? (double)w_elem(W, trans, I1, row, ci) : 0.0;
-      Aj[kk][c] = (row < m && cj < n) ? (double)w_elem(W, trans, I1, row, cj) : 0.0;
+      Ai[kk][c] = (row < m && ci < n) ? w_elem(W, trans, I1, row, ci) : 0.f;
+      Aj[kk][c] = (row < m && cj < n) ? w_elem(W, trans, I1, row, cj) : 0.f;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < GT; ++kk) {
-      const double a0 = Ai[kk][2 * tx], a1 = Ai[kk][2 * tx + 1];
-      const double b0 = Aj[kk][2 * ty], b1 = Aj[kk][2 * ty + 1];
-      c00 = fma(a0, b0, c00);
-      c01 = fma(a0, b1, c01);
-      c10 = fma(a1, b0, c10);
-      c11 = fma(a1, b1, c11);
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < GK; kk += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Aj[kk + lq][16 * wb + lr], (double)Ai[kk + lq][16 * wa + lr],
+                                                   acc, 0, 0, 0);
     }
     __syncthreads();
   }
-  const int i0 = ti * GT + 2 * tx, j0 = tj * GT + 2 * ty;
-  const double v[2][2] = {{c00, c01}, {c10, c11}};
+  if (!live) return;
+  const int i = ti * GT + 16 * wa + lr;
 #pragma unroll
-  for (int di = 0; di < 2; ++di)
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj) {
-      const int i = i0 + di, j = j0 + dj;
-      if (i < n && j < n && i >= j) C[i + (long long)j * n] = v[di][dj];
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int j = tj * GT + 16 * wb + lq + 4 * q;
+    if (i < n && j < n && i >= j) C[i + (long long)j * n] = acc[q];
+  }
 }
 
 // The Gram matrix of a complex slice's real form T = [w_1, i w_1, w_2, ...]
@@ -99,8 +105,6 @@ __device__ __attribute__((always_inline)) void gram_tile(const float* W, int I1,
 // 16 x 16 quarter on FP64 MFMA with two accumulators (Re g, Im g), the columns
 // staged through LDS 64 interleaved rows at a time; the FP32 entries are exact
 // in FP64, the products and sums are FP64.  C is the 2n x 2n lower triangle.
-typedef double ct_v4d __attribute__((ext_vector_type(4)));
-
 constexpr int GCX = 32;     // complex columns per tile side
 constexpr int GCX_K = 64;   // interleaved rows per LDS chunk (even: pairs stay whole)
 
